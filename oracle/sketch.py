@@ -1,0 +1,89 @@
+"""Row sampling, sketch rows and the randomized Hadamard map (oracle; test
+infrastructure only).  Random numbers are inputs: every function takes its
+uniform draws in [0, 1) as an array, so the GPU path and the oracle can be fed
+the same draws.
+
+uniform_rows: Algorithm 1's i.i.d. uniform trials; row i = floor(u m), and the
+  sampled row is rescaled by sqrt(m / c).
+leverage_sample: Algorithm 2 / eq. (ldist): pi_i = l_i / sum_k l_k, c draws
+  with replacement, each sampled row rescaled by 1 / sqrt(c pi_i) (the
+  sampling-and-rescaling rule of Section 2.1.2).  A draw u picks the first row
+  whose running score total exceeds u * total (inverse CDF, the running total
+  accumulated in row order).
+sketch_rows: the sampled, rescaled rows of [X | b] (eq. (OLSc) with S applied).
+hadamard: Definition 2.4, H_0 = 1 and H_m = [[H, H], [H, -H]] / sqrt(2),
+  of size 2^m (the paper's size label is garbled; H_m is 2^m x 2^m here).
+srht_map: a k x p subsampled randomized Hadamard map sqrt(P/k) S H D on the
+  p-vector zero-padded to P = 2^ceil(log2 p) (Algorithm 1's construction with
+  random signs D and k uniform row trials S), restricted to its first p columns.
+jl_omega: Omega = R^{-1} Pi^T, the k columns whose row products give the
+  approximate generalised leverage scores of eq. (glev).
+
+Parity pins (tests/test_oracle_sketch.py): a hand-worked inverse-CDF example;
+E[S^T S] = I for the rescaled sampling matrix (Monte Carlo); H_m orthonormal
+and H_1 written out; E||Pi x||^2 = ||x||^2 for the SRHT map.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+from .toeplitz import lag_matrix
+
+
+def uniform_rows(u, m: int, c: int | None = None):
+    """Row indices floor(u m) (clamped to m-1) and the common scale sqrt(m/c)."""
+    u = np.asarray(u, np.float64)
+    c = u.size if c is None else c
+    idx = np.minimum(np.floor(u * m).astype(np.int64), m - 1)
+    scale = np.full(idx.size, np.sqrt(m / c))
+    return idx, scale
+
+
+def leverage_sample(scores, u, c: int | None = None):
+    """Inverse-CDF draws from pi = scores / sum(scores) and scales 1/sqrt(c pi)."""
+    s = np.asarray(scores, np.float64)
+    u = np.asarray(u, np.float64)
+    c = u.size if c is None else c
+    running = np.cumsum(s)
+    total = running[-1]
+    idx = np.searchsorted(running, u * total, side="right")
+    idx = np.minimum(idx, s.size - 1)
+    pi = s[idx] / total
+    scale = 1.0 / np.sqrt(c * pi)
+    return idx.astype(np.int64), scale
+
+
+def sketch_rows(y, p: int, idx, scale) -> np.ndarray:
+    """[S X | S b]: row t is scale_t * [X(idx_t, :), b(idx_t)]; shape (c, p+1)."""
+    X, b = lag_matrix(y, p)
+    idx = np.asarray(idx, np.int64)
+    scale = np.asarray(scale, np.float64)
+    return np.column_stack([X[idx, :], b[idx]]) * scale[:, None]
+
+
+def hadamard(mexp: int) -> np.ndarray:
+    """Normalised Hadamard matrix H_mexp of size 2^mexp (Definition 2.4)."""
+    H = np.array([[1.0]])
+    for _ in range(mexp):
+        H = np.block([[H, H], [H, -H]]) / np.sqrt(2.0)
+    return H
+
+
+def srht_map(p: int, k: int, u_signs, u_rows) -> np.ndarray:
+    """k x p map sqrt(P/k) S H_P D (first p columns); D_jj = +1 if u_signs[j] < 0.5
+    else -1 (j < P); S picks rows floor(u_rows[t] * P)."""
+    P = 1
+    while P < p:
+        P *= 2
+    H = hadamard(int(np.log2(P)))
+    d = np.where(np.asarray(u_signs, np.float64)[:P] < 0.5, 1.0, -1.0)
+    rows = np.minimum(np.floor(np.asarray(u_rows, np.float64)[:k] * P).astype(np.int64), P - 1)
+    Pi = np.sqrt(P / k) * H[rows, :] * d[None, :]
+    return Pi[:, :p]
+
+
+def jl_omega(R, Pi) -> np.ndarray:
+    """Omega = R^{-1} Pi^T (p x k) for upper-triangular R."""
+    return sla.solve_triangular(np.asarray(R, np.float64), np.asarray(Pi, np.float64).T,
+                                lower=False)

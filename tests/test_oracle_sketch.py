@@ -1,0 +1,107 @@
+"""Pins for oracle.sketch and oracle.philox: hand-worked sampling example,
+unbiasedness of the rescaled sampling matrix, Definition 2.4 written out,
+SRHT norm preservation in expectation, and the published Philox vectors."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.conftest import read_golden
+
+
+def test_inverse_cdf_hand_example():
+    scores_s, rows = read_golden("inverse_cdf_example.txt")
+    scores = np.array(scores_s[0], float)
+    u = np.array([float(r[0]) for r in rows])
+    expect = np.array([int(r[1]) for r in rows])
+    idx, scale = oracle.leverage_sample(scores, u)
+    assert np.array_equal(idx, expect)
+    pi = scores[expect] / scores.sum()
+    assert np.allclose(scale, 1.0 / np.sqrt(u.size * pi))
+
+
+def test_uniform_rows_alg1():
+    idx, scale = oracle.uniform_rows([0.0, 0.5, 0.999999], 10, c=3)
+    assert list(idx) == [0, 5, 9]
+    assert np.allclose(scale, np.sqrt(10 / 3))
+
+
+def test_sampling_matrix_unbiased(rng):
+    """E[S^T S] = I for leverage-score sampling with 1/sqrt(c pi) rescaling
+    (Section 2.1.2): so E[(SA)^T (SA)] = A^T A.  Monte Carlo, 5 sigma."""
+    scores = rng.uniform(0.1, 2.0, 12)
+    c, trials = 20, 20000
+    diag = np.zeros(12)
+    for _ in range(trials):
+        idx, scale = oracle.leverage_sample(scores, rng.random(c))
+        np.add.at(diag, idx, scale ** 2)
+    est = diag / trials
+    pi = scores / scores.sum()
+    sd = np.sqrt((1 - pi) / (c * pi) / trials)
+    assert np.all(np.abs(est - 1.0) <= 5 * sd)
+
+
+def test_sketch_rows_rescale(rng):
+    y = rng.standard_normal(50)
+    X, b = oracle.lag_matrix(y, 4)
+    idx = np.array([3, 0, 45, 3])
+    sc = np.array([1.0, 2.0, 0.5, -1.0])
+    S = oracle.sketch_rows(y, 4, idx, sc)
+    for t in range(4):
+        assert np.array_equal(S[t, :4], X[idx[t]] * sc[t])
+        assert S[t, 4] == b[idx[t]] * sc[t]
+
+
+def test_hadamard_definition():
+    H2 = np.array(read_golden("hadamard_h2.txt")[0], float) / 2.0
+    assert np.allclose(oracle.hadamard(2), H2, atol=0)
+    assert np.allclose(oracle.hadamard(1), np.array([[1, 1], [1, -1]]) / np.sqrt(2))
+    for m in range(0, 7):
+        H = oracle.hadamard(m)
+        assert np.allclose(H.T @ H, np.eye(2 ** m), atol=1e-13)
+
+
+def test_srht_map_preserves_norm_in_expectation(rng):
+    p, k = 11, 4
+    x = rng.standard_normal(p)
+    acc, trials = 0.0, 20000
+    vals = []
+    for _ in range(trials):
+        Pi = oracle.srht_map(p, k, rng.random(16), rng.random(k))
+        vals.append(np.sum((Pi @ x) ** 2))
+    vals = np.array(vals)
+    assert abs(vals.mean() - x @ x) <= 5 * vals.std() / np.sqrt(trials)
+
+
+def test_srht_columns_exact():
+    """With all signs + and k = P rows picking each row once, the map is
+    sqrt(P/k) H = H restricted to the first p columns."""
+    p, P = 3, 4
+    u_rows = (np.arange(P) + 0.5) / P
+    Pi = oracle.srht_map(p, P, np.zeros(P), u_rows)
+    assert np.allclose(Pi, oracle.hadamard(2)[:, :p])
+
+
+def test_philox_known_answers():
+    for row in read_golden("philox4x32_10_kat.txt")[0]:
+        vals = [int(x, 16) for x in row]
+        assert oracle.philox4x32_10(vals[0:4], vals[4:6]) == tuple(vals[6:10])
+
+
+def test_philox_uniform_stream_layout():
+    """philox_uniform draw j equals the scalar block at counter (j,0,s,f)."""
+    seed, s, f = 0x1234_5678_9ABC, 3, 17
+    u = oracle.philox_uniform(5, s, f, seed, start=7)
+    for t in range(5):
+        x0, x1, _, _ = oracle.philox4x32_10((7 + t, 0, s, f), (seed & 0xFFFFFFFF, seed >> 32))
+        bits = ((x0 << 32) | x1) >> 12
+        assert u[t] == (bits + 0.5) * 2.0 ** -52
+    assert np.all((u > 0) & (u < 1))
+
+
+def test_philox_uniform_moments():
+    u = oracle.philox_uniform(200000, 1, 0, 42)
+    assert abs(u.mean() - 0.5) < 5 * np.sqrt(1 / 12 / u.size)
+    z = oracle.philox_normal(100000, 2, 0, 42)
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1) < 5 * np.sqrt(2 / z.size)
