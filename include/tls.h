@@ -1,0 +1,220 @@
+/* tls.h - Toeplitz least squares for AR(p) fitting on AMD MI355X (gfx950).
+ *
+ * The problem (Section 3, eq. (xphi); Definition 2.1): given a series
+ * y_1..y_n and an order p, find phi minimising ||X phi - b||_2, where row t of
+ * X holds the p lags (y_{t-1}, ..., y_{t-p}) and b_t = y_t, t = p+1..n.  X is
+ * (n-p) x p and Toeplitz (constant descending diagonals), so only the series
+ * is ever stored.  By Theorem 2.2 the minimiser solves the normal equations
+ * and is unique when X has full column rank.
+ *
+ * Method: a randomized sketch of [X | b] (uniform row trials, then
+ * approximate generalised leverage scores (Definition 3.6, eq. (glev)) and
+ * leverage-score row sampling (Algorithm 2, eq. (ldist))) is QR-factored to
+ * give R; LSQR preconditioned by R^{-1} then converges to the exact
+ * least-squares solution, applying X and X^T by blocked FFT convolution.
+ *
+ * Conventions for every entry point:
+ *  - Coefficients are returned in lag order phi_1..phi_p (eq. (xphi)).
+ *  - The caller owns every buffer.  Host pointers are read or written only
+ *    during the call.  Device pointers (the *_device and tls_op_* calls) must
+ *    be device memory of the context's device and stay valid until the work
+ *    queued on `stream` has finished; the library never frees them.
+ *  - A stream argument is a hipStream_t passed as void*; NULL means the
+ *    context's own stream.  tls_op_* calls only enqueue work; tls_fit* calls
+ *    return after the fit is complete.
+ *  - Every call returns a tls_status; no exception crosses the ABI.  On any
+ *    status other than TLS_OK, TLS_ENOCONV and TLS_ERANK, outputs are left
+ *    unwritten.
+ *  - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef TLS_H_
+#define TLS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tls_status;
+#define TLS_OK 0          /* success */
+#define TLS_EINVAL 1      /* invalid argument: NULL pointer, p < 1, n < 2p + 1, tol not in (0,1), non-finite data */
+#define TLS_ERANK 2       /* X numerically rank deficient (Theorem 2.2's singular case); outputs hold LSQR's iterate */
+#define TLS_ENOCONV 3     /* iteration limit reached; outputs hold the last iterate */
+#define TLS_ENOMEM 4      /* device allocation failed */
+#define TLS_EDEVICE 5     /* HIP runtime error */
+#define TLS_EUNSUPPORTED 6 /* size outside the supported range (p > 1024 or FFT block limits) */
+
+/* Static description of a status code. */
+const char* tls_status_string(tls_status s);
+
+#define TLS_PREC_F64 0    /* every step in FP64 */
+#define TLS_PREC_MIXED 1  /* FP32 FFT matvecs and sketch scores; FP64 QR, recurrences and residual */
+
+#define TLS_SKETCH_LEVERAGE 0 /* uniform trials -> generalised leverage scores -> leverage sampling */
+#define TLS_SKETCH_UNIFORM 1  /* uniform trials only (Algorithm 1's sampling without the transform) */
+
+#define TLS_JL_SRHT 0     /* k x p subsampled randomized Hadamard map (Definition 2.4, Algorithm 1) */
+#define TLS_JL_GAUSS 1    /* k x p Gaussian map, entries N(0, 1/k) (eq. (glev)) */
+
+typedef struct tls_options {
+  int32_t precision;   /* TLS_PREC_* (default F64) */
+  int32_t sketch;      /* TLS_SKETCH_* (default LEVERAGE) */
+  int32_t jl_kind;     /* TLS_JL_* (default SRHT) */
+  int32_t gamma;       /* sketch rows c = gamma * p (default 8); all rows when c >= n - p */
+  int32_t jl_k;        /* columns of the JL map (default 8) */
+  int32_t max_iter;    /* LSQR / inner iteration limit (default 1000) */
+  int32_t block_lg;    /* log2 of the FFT block length B, 7..14; 0 = automatic */
+  int32_t warm_start;  /* 1: start from the compressed problem's solution (default 1) */
+  int32_t max_refine;  /* mixed precision: outer FP64 refinement steps (default 8) */
+  int32_t profile;     /* 1: time every Toeplitz pass with HIP events (tls_result.pass_ms) */
+  uint64_t seed;       /* random seed (default 0) */
+  uint64_t request_id; /* selects the random streams of one fit (default 0) */
+  int64_t reserved[4];
+} tls_options;
+
+typedef struct tls_result {
+  double resid_norm;   /* FP64 ||b - X phi||_2 of the returned phi */
+  double kappa_est;    /* max|R_ii| / min|R_ii| of the sketch factor (cheap condition estimate) */
+  double lsqr_rnorm;   /* LSQR's own residual estimate */
+  double lsqr_arnorm;  /* LSQR's ||A^T r|| estimate */
+  int32_t iters;       /* total inner iterations */
+  int32_t istop;       /* LSQR stop reason: 1, 2 converged; 3 exact; 7 limit */
+  int32_t refine_steps;/* outer refinement steps (mixed precision), else 0 */
+  int32_t sketch_rows; /* c */
+  int32_t block_len;   /* FFT block length B used */
+  int32_t n_blocks;    /* FFT blocks per pass */
+  double t_total_ms;   /* wall time of the call */
+  double pass_ms;      /* profile = 1: summed device time of the Toeplitz passes that did work */
+  int32_t pass_count;  /* profile = 1: number of those passes */
+  int32_t reserved1;
+} tls_result;
+
+typedef struct tls_ctx tls_ctx;
+
+/* Fill `opt` with the defaults listed above. */
+void tls_options_default(tls_options* opt);
+
+/* Create a context on HIP device `device` (its own stream, FFT twiddle
+ * tables, a reusable device workspace).  opt may be NULL (defaults).
+ * Errors: TLS_EINVAL (ctx NULL), TLS_EDEVICE, TLS_ENOMEM. */
+tls_status tls_create(tls_ctx** ctx, int device, const tls_options* opt);
+
+/* Release a context and everything it allocated.  NULL is ignored. */
+void tls_destroy(tls_ctx* ctx);
+
+/* Fit AR(p) to the host series y[0..n-1] (Section 3, eq. (xphi)) with the
+ * default context (device 0, default options, created on first use).
+ * coef: host, p doubles out.  resid_norm: host, 1 double out (FP64
+ * ||b - X phi||).  iters: host, 1 int out (LSQR iterations).  tol: LSQR
+ * stopping tolerance in (0, 1).  Not thread-safe. */
+tls_status tls_fit(const double* series, int64_t n, int32_t p, double tol, double* coef,
+                   double* resid_norm, int32_t* iters);
+
+/* Same with an explicit context and options (opt NULL = the context's).
+ * series is host memory; coef host, p doubles; out may be NULL. */
+tls_status tls_fit_ex(tls_ctx* ctx, const double* series, int64_t n, int32_t p, double tol,
+                      const tls_options* opt, double* coef, tls_result* out);
+
+/* Same, with the series already in device memory (d_series, n doubles),
+ * work queued on `stream`; coef and out are host memory. */
+tls_status tls_fit_device(tls_ctx* ctx, const double* d_series, int64_t n, int32_t p, double tol,
+                          const tls_options* opt, void* stream, double* coef, tls_result* out);
+
+/* Batched fits of `count` independent host series: series[i] has n[i]
+ * samples and order p[i]; coefficients of fit i go to
+ * coef_packed[coef_offset[i] .. + p[i]).  resid_norm, iters, per_fit_status:
+ * host arrays of count entries (any may be NULL).  Each fit gives the same
+ * result as tls_fit_ex with the same options and request_id = opt.request_id + i.
+ * Returns TLS_OK when every fit's status is TLS_OK, else the first failing
+ * status; per-fit statuses say which. */
+tls_status tls_fit_batch(tls_ctx* ctx, int32_t count, const double* const* series, const int64_t* n,
+                         const int32_t* p, double tol, const tls_options* opt, double* coef_packed,
+                         const int64_t* coef_offset, double* resid_norm, int32_t* iters,
+                         tls_status* per_fit_status);
+
+/* ---- step-level entry points (device pointers; work enqueued on stream) ----
+ * These run one step of the path on its own so that each step can be checked
+ * against the CPU oracle.  prec: TLS_PREC_F64 or TLS_PREC_MIXED (FP32 data).
+ * B: FFT block length (power of two, 128..16384, B >= 2p).  Block layout:
+ * block k covers rows [kL, kL + L), L = B - p + 1, nblocks = ceil((n-p)/L). */
+
+/* Number of FFT blocks for (n, p, B), or -1 if B is invalid. */
+int64_t tls_num_blocks(int64_t n, int32_t p, int32_t B);
+
+/* Packed block spectra of the series (the length-B real DFT of each window
+ * y[kL .. kL+B), zero past the end): d_spec receives nblocks * B/2 complex
+ * values (FP64 pairs for F64, FP32 pairs for MIXED); word 0 of a block holds
+ * (X[0], X[B/2]), word j the bin X[j]. */
+tls_status tls_op_spectra(tls_ctx* ctx, int32_t prec, const double* d_y, int64_t n, int32_t p,
+                          int32_t B, void* d_spec, void* stream);
+
+/* One pass of the lag matrix over a vector (eq. (xphi)):
+ *   e = s1 * X v + s2 * w     (v: host, p doubles; w: device, n-p values or NULL)
+ *   d_e (device, n-p values, may alias d_w; NULL = not stored)
+ *   d_out (device, p+1 doubles): X^T e in [0, p) when want_rmv, ||e||^2 in [p].
+ * If v is NULL, e = d_u_in (device, n-p values) and only X^T e, ||e||^2 are
+ * formed.  Vectors of n-p values are FP64 (F64) or FP32 (MIXED). */
+tls_status tls_op_toeplitz(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n, int32_t p,
+                           int32_t B, const double* v, double s1, double s2, const void* d_w,
+                           void* d_e, const void* d_u_in, int32_t want_rmv, double* d_out,
+                           void* stream);
+
+/* Approximate generalised leverage scores in product form (eq. (glev)):
+ * d_scores[i] = sum_q ((X omega_q)[i])^2 for the p x k matrix d_omega
+ * (device FP64, column-major, columns contiguous).  d_scores: n-p values,
+ * FP64 or FP32 by prec. */
+tls_status tls_op_scores(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n, int32_t p,
+                         int32_t B, const double* d_omega, int32_t k, void* d_scores, void* stream);
+
+/* Leverage-score sampling (Algorithm 2, eq. (ldist)): c draws with
+ * replacement from pi_i = s_i / sum s, by the inverse CDF of the running
+ * total in row order; row i is rescaled by 1/sqrt(c pi_i).  d_u: device, c
+ * uniforms in [0,1) (NULL: Philox stream 3 of (seed, fit)).  d_idx: c int64;
+ * d_scale: c doubles.  d_scores FP64 or FP32 by prec. */
+tls_status tls_op_sample(tls_ctx* ctx, int32_t prec, const void* d_scores, int64_t m,
+                         const double* d_u, int32_t c, uint64_t seed, uint32_t fit,
+                         int64_t* d_idx, double* d_scale, void* stream);
+
+/* Sketch rows scale_t * [X(idx_t, :), b(idx_t)] into d_A (device FP64,
+ * row-major, crows x ldq; rows >= c and columns >= p+1 zeroed).
+ * mode 0: d_idx/d_scale given; 1: uniform trials from Philox stream 0 of
+ * (seed, fit) with scale sqrt(m/c) (Algorithm 1), idx/scale written out if
+ * non-NULL; 2: every row (c = n - p, scale 1). */
+tls_status tls_op_gather(tls_ctx* ctx, const double* d_y, int64_t n, int32_t p, int32_t mode,
+                         int64_t* d_idx, double* d_scale, int32_t c, int32_t crows, int32_t ldq,
+                         double* d_A, uint64_t seed, uint32_t fit, void* stream);
+
+/* QR of the sketch (Section 2.1: QR of the compressed matrix): upper
+ * triangular d_R (q x q, row-major, non-negative diagonal) with
+ * A^T A = R^T R for the crows x ldq row-major d_A (crows % 4 == 0,
+ * ldq % 16 == 0, q <= ldq; d_A is overwritten).  *status_out (host) gets the
+ * breakdown bits: 1 = the shifted first sweep broke down, 2 = a later sweep
+ * broke down, 4 = min|R_ii| <= q u max|R_ii|; 2 or 4 mean numerically rank
+ * deficient.  Synchronises the stream. */
+tls_status tls_op_qr(tls_ctx* ctx, double* d_A, int32_t crows, int32_t q, int32_t ldq,
+                     double* d_R, int32_t* status_out, void* stream);
+
+/* d_M = R[:p,:p]^{-1} (row-major, upper) and d_phi0 = R[:p,:p]^{-1} R[:p,p]
+ * (the compressed problem's solution) from the q x q row-major d_R (q = p+1,
+ * or q = p with d_phi0 NULL). */
+tls_status tls_op_triinv(tls_ctx* ctx, const double* d_R, int32_t q, int32_t p, double* d_M,
+                         double* d_phi0, void* stream);
+
+/* The k x p JL map Pi (kind TLS_JL_*) from Philox streams of (seed, fit) and
+ * Omega = M Pi^T (p x k column-major) for upper-triangular d_M (p x p
+ * row-major).  d_Pi may be NULL. */
+tls_status tls_op_jl(tls_ctx* ctx, const double* d_M, int32_t p, int32_t k, int32_t kind,
+                     uint64_t seed, uint32_t fit, double* d_Pi, double* d_omega, void* stream);
+
+/* count Philox4x32-10 uniforms of stream `rng_stream`, fit `fit`, seed
+ * `seed`, draws start .. start+count-1, into d_out (device FP64). */
+tls_status tls_op_philox(tls_ctx* ctx, uint64_t seed, uint32_t rng_stream, uint32_t fit,
+                         uint64_t start, int64_t count, double* d_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLS_H_ */

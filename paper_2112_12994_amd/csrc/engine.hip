@@ -1,0 +1,781 @@
+// Host engine and C-ABI of the Toeplitz least-squares library: contexts,
+// device workspace, the per-fit plan (FFT block length, sketch size) and the
+// orchestration of the kernels for one fit.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "../../include/tls.h"
+
+using namespace tls;
+
+struct tls_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  tls_options opt{};
+  void* tw64 = nullptr;
+  void* tw32 = nullptr;
+  Twiddles tw;
+  double* consts = nullptr;  // {-1, 1, 1, 0}
+  void* ws = nullptr;        // workspace
+  size_t ws_bytes = 0;
+  void* pinned = nullptr;    // host staging
+  size_t pinned_bytes = 0;
+  std::vector<hipEvent_t> events;  // profile = 1: pairs around each Toeplitz pass
+};
+
+namespace {
+
+constexpr int P_MAX = 1024;
+constexpr int CHUNK_ITERS = 8;
+
+#define TLS_CHECK(call)                          \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_status(e_); \
+  } while (0)
+
+tls_status hip_status(hipError_t e) {
+  if (e == hipErrorOutOfMemory) return TLS_ENOMEM;
+  if (e == hipErrorInvalidValue) return TLS_EUNSUPPORTED;
+  return TLS_EDEVICE;
+}
+
+int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t{1} << l) < x) ++l;
+  return l;
+}
+
+hipError_t build_twiddles(tls_ctx* c) {
+  std::vector<cx<double>> t64(NMAX);
+  std::vector<cx<float>> t32(NMAX);
+  for (int k = 0; k < NMAX; ++k) {
+    const long double a = -2.0L * 3.141592653589793238462643383279502884L * k / BMAX;
+    t64[k] = {static_cast<double>(cosl(a)), static_cast<double>(sinl(a))};
+    t32[k] = {static_cast<float>(cosl(a)), static_cast<float>(sinl(a))};
+  }
+  hipError_t e = hipMalloc(&c->tw64, NMAX * sizeof(cx<double>));
+  if (e != hipSuccess) return e;
+  e = hipMalloc(&c->tw32, NMAX * sizeof(cx<float>));
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(c->tw64, t64.data(), NMAX * sizeof(cx<double>), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(c->tw32, t32.data(), NMAX * sizeof(cx<float>), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  c->tw.d64 = c->tw64;
+  c->tw.d32 = c->tw32;
+  const double k4[4] = {-1.0, 1.0, 1.0, 0.0};
+  e = hipMalloc(&c->consts, sizeof(k4));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(c->consts, k4, sizeof(k4), hipMemcpyHostToDevice);
+}
+
+// Bump allocator over the context workspace (256-byte aligned slices).
+struct Arena {
+  size_t need = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t off = (need + 255) & ~size_t{255};
+    need = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+hipError_t ensure_ws(tls_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return hipSuccess;
+  if (c->ws) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  const size_t grow = bytes + bytes / 8;
+  hipError_t e = hipMalloc(&c->ws, grow);
+  if (e != hipSuccess) return e;
+  c->ws_bytes = grow;
+  return hipSuccess;
+}
+
+hipError_t ensure_pinned(tls_ctx* c, size_t bytes) {
+  if (bytes <= c->pinned_bytes) return hipSuccess;
+  if (c->pinned) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+  }
+  hipError_t e = hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  c->pinned_bytes = bytes;
+  return hipSuccess;
+}
+
+// Event pair `i` (created on first use; kept for the context's lifetime).
+hipError_t pass_events(tls_ctx* c, size_t i, hipEvent_t* a, hipEvent_t* b) {
+  while (c->events.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    c->events.push_back(e);
+  }
+  *a = c->events[2 * i];
+  *b = c->events[2 * i + 1];
+  return hipSuccess;
+}
+
+hipStream_t pick_stream(tls_ctx* c, void* s) {
+  return s ? static_cast<hipStream_t>(s) : c->stream;
+}
+
+// ---------------------------------------------------------------------------
+struct Plan {
+  int prec, B, lgn, L, nblocks, p, q, ldq, c, crows, k, all_rows;
+  int64_t n, m;
+};
+
+int auto_block(int p, int64_t m) {
+  // Smallest power of two >= 16 p (>= 2p always), between 256 and 16384, and
+  // no longer than the data needs.
+  int lg = ilog2(16 * static_cast<int64_t>(p));
+  if (lg < 8) lg = 8;
+  const int lgdata = ilog2(m + p);
+  if (lg > lgdata) lg = lgdata < 8 ? 8 : lgdata;
+  if (lg > LG_BMAX) lg = LG_BMAX;
+  while ((1 << lg) < 2 * p) ++lg;
+  return lg;
+}
+
+tls_status make_plan(int64_t n, int p, const tls_options& o, Plan* pl) {
+  pl->n = n;
+  pl->p = p;
+  pl->m = n - p;
+  pl->prec = o.precision;
+  int lg = o.block_lg > 0 ? o.block_lg : auto_block(p, pl->m);
+  if (lg < 7 || lg > LG_BMAX) return TLS_EUNSUPPORTED;
+  pl->B = 1 << lg;
+  if (pl->B < 2 * p) return TLS_EUNSUPPORTED;
+  pl->lgn = lg - 1;
+  pl->L = pl->B - p + 1;
+  pl->nblocks = static_cast<int>((pl->m + pl->L - 1) / pl->L);
+  pl->q = p + 1;
+  pl->ldq = (pl->q + 15) / 16 * 16;
+  const int64_t c = static_cast<int64_t>(o.gamma > 0 ? o.gamma : 8) * p;
+  pl->all_rows = c >= pl->m ? 1 : 0;
+  pl->c = static_cast<int>(pl->all_rows ? pl->m : c);
+  pl->crows = (pl->c + 3) / 4 * 4;
+  pl->k = o.jl_k > 0 ? o.jl_k : 8;
+  return TLS_OK;
+}
+
+tls_status validate(int64_t n, int p, double tol, const tls_options& o) {
+  if (p < 1 || n < 2 * static_cast<int64_t>(p) + 1) return TLS_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0)) return TLS_EINVAL;
+  if (o.precision != TLS_PREC_F64 && o.precision != TLS_PREC_MIXED) return TLS_EINVAL;
+  if (o.sketch != TLS_SKETCH_LEVERAGE && o.sketch != TLS_SKETCH_UNIFORM) return TLS_EINVAL;
+  if (o.jl_kind != TLS_JL_SRHT && o.jl_kind != TLS_JL_GAUSS) return TLS_EINVAL;
+  if (p > P_MAX) return TLS_EUNSUPPORTED;
+  if (n > (int64_t{1} << 40)) return TLS_EUNSUPPORTED;
+  return TLS_OK;
+}
+
+// Device buffers of one fit, carved from the workspace.
+struct FitBufs {
+  double* y;        // series copy (host input) or nullptr
+  float* y32;       // FP32 series (mixed)
+  void* Yhat;       // spectra in compute precision
+  void* Yhat64;     // FP64 spectra (mixed: residual passes)
+  void* u;          // m-vector (also sketch scores)
+  double* partial;  // (p+1) x nblocks
+  double* g;        // p+1
+  double* A;        // crows x ldq
+  double* G;        // ldq^2 + 2 q^2
+  double *R1, *R2, *R;
+  double *M, *Mt, *M0, *Mt0;
+  double *Pi, *Om;
+  void* Omhat;
+  void* Vhat;
+  double *v, *w, *z, *phi0, *phi;
+  int64_t* idx;
+  double* scale;
+  double* swork;
+  LsqrState* st;
+  int* status;      // [0] QR bits, [1] triinv bits
+  double* dminmax;  // scratch
+  double* rr;       // residual norm^2
+  double* rpart;    // direct residual partials
+};
+
+size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
+  Arena a;
+  a.base = base;
+  const size_t es = pl.prec == TLS_PREC_F64 ? sizeof(double) : sizeof(float);
+  const size_t N = static_cast<size_t>(pl.B / 2);
+  b->y = copy_y ? a.take<double>(pl.n) : nullptr;
+  b->y32 = pl.prec == TLS_PREC_MIXED ? a.take<float>(pl.n) : nullptr;
+  b->Yhat = a.take<char>(static_cast<size_t>(pl.nblocks) * N * 2 * es);
+  b->Yhat64 = pl.prec == TLS_PREC_MIXED ? a.take<char>(static_cast<size_t>(pl.nblocks) * N * 16)
+                                        : b->Yhat;
+  b->u = a.take<char>(static_cast<size_t>(pl.m) * (pl.prec == TLS_PREC_F64 ? 8 : 8));
+  b->partial = a.take<double>(static_cast<size_t>(pl.p + 1) * pl.nblocks);
+  b->g = a.take<double>(pl.p + 1);
+  b->A = a.take<double>(static_cast<size_t>(pl.crows) * pl.ldq);
+  b->G = a.take<double>(static_cast<size_t>(pl.ldq) * pl.ldq + 2 * static_cast<size_t>(pl.q) * pl.q);
+  b->R1 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
+  b->R2 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
+  b->R = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
+  b->M = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->Mt = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->M0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->Mt0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->Pi = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
+  b->Om = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
+  b->Omhat = a.take<char>(static_cast<size_t>(pl.k) * N * 2 * es);
+  b->Vhat = a.take<char>(N * 16);
+  b->v = a.take<double>(pl.p);
+  b->w = a.take<double>(pl.p);
+  b->z = a.take<double>(pl.p);
+  b->phi0 = a.take<double>(pl.p);
+  b->phi = a.take<double>(pl.p);
+  b->idx = a.take<int64_t>(pl.c);
+  b->scale = a.take<double>(pl.c);
+  b->swork = a.take<double>(sample_work_doubles(pl.m));
+  b->st = a.take<LsqrState>(1);
+  b->status = a.take<int>(4);
+  b->dminmax = a.take<double>(4);
+  b->rr = a.take<double>(4);
+  b->rpart = a.take<double>(resid_direct_blocks(pl.m));
+  return a.need + 256;
+}
+
+__global__ void fill_state_kernel(LsqrState* st, double tol, int max_iter, int* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    LsqrState s{};
+    s.tol = tol;
+    s.max_iter = max_iter;
+    s.coef[0] = -1.0;
+    s.coef[1] = 1.0;
+    *st = s;
+    status[0] = status[1] = status[2] = status[3] = 0;
+  }
+}
+
+__global__ void diag_minmax_kernel(const double* R, int q, int p, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double a = 0.0, b = INFINITY;
+    for (int i = 0; i < p; ++i) {
+      const double d = fabs(R[static_cast<size_t>(i) * q + i]);
+      a = fmax(a, d);
+      b = fmin(b, d);
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+__global__ void zero_kernel(double* x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+__global__ void to_f32_kernel(const double* x, int64_t n, float* y) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = static_cast<float>(x[i]);
+}
+
+struct HostOut {
+  LsqrState st;
+  double dminmax[4];
+  double rr[4];
+  int status[4];
+};
+
+// The fit of one series already in device memory (d_y), on stream s.
+tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const double* d_y_in,
+                   const double* host_y, double tol, hipStream_t s, double* coef, tls_result* res) {
+  const auto t0 = std::chrono::steady_clock::now();
+  FitBufs b{};
+  const size_t need = carve(pl, host_y != nullptr, &b, nullptr);
+  TLS_CHECK(ensure_ws(ctx, need));
+  carve(pl, host_y != nullptr, &b, static_cast<char*>(ctx->ws));
+  TLS_CHECK(ensure_pinned(ctx, sizeof(HostOut) + pl.p * sizeof(double) + 64));
+  HostOut* ho = static_cast<HostOut*>(ctx->pinned);
+  double* hphi = reinterpret_cast<double*>(ho + 1);
+
+  const double* d_y = d_y_in;
+  if (host_y) {
+    TLS_CHECK(hipMemcpyAsync(b.y, host_y, pl.n * sizeof(double), hipMemcpyHostToDevice, s));
+    d_y = b.y;
+  }
+  const int prec = pl.prec;
+  const int p = pl.p, q = pl.q;
+  const double invB = 1.0 / pl.B;
+  const uint64_t seed = o.seed;
+  const uint32_t fit = static_cast<uint32_t>(o.request_id);
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
+
+  hipLaunchKernelGGL(fill_state_kernel, dim3(1), dim3(64), 0, s, b.st, tol, max_iter, b.status);
+  TLS_CHECK(hipGetLastError());
+
+  // Spectra of the series blocks.
+  if (prec == TLS_PREC_MIXED) {
+    const unsigned nb = static_cast<unsigned>((pl.n + 255) / 256);
+    hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(256), 0, s, d_y, pl.n, b.y32);
+    TLS_CHECK(launch_spectra(PREC_F32, pl.lgn, d_y, pl.n, pl.L, pl.nblocks, b.Yhat, ctx->tw, s));
+    TLS_CHECK(launch_spectra(PREC_F64, pl.lgn, d_y, pl.n, pl.L, pl.nblocks, b.Yhat64, ctx->tw, s));
+  } else {
+    TLS_CHECK(launch_spectra(PREC_F64, pl.lgn, d_y, pl.n, pl.L, pl.nblocks, b.Yhat, ctx->tw, s));
+  }
+
+  // Sketch -> R.
+  if (pl.all_rows) {
+    TLS_CHECK(launch_gather(d_y, pl.m, p, 2, nullptr, nullptr, pl.c, pl.crows, pl.ldq, b.A,
+                            nullptr, nullptr, seed, fit, s));
+  } else {
+    TLS_CHECK(launch_gather(d_y, pl.m, p, 1, nullptr, nullptr, pl.c, pl.crows, pl.ldq, b.A, b.idx,
+                            b.scale, seed, fit, s));
+    if (o.sketch == TLS_SKETCH_LEVERAGE) {
+      TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, b.R, b.G, b.R1, b.R2, b.status + 2, s));
+      TLS_CHECK(launch_triinv(b.R, q, p, b.M0, b.Mt0, nullptr, b.status + 3, s));
+      TLS_CHECK(launch_jl_omega(b.M0, p, pl.k, o.jl_kind, b.Pi, b.Om, seed, fit, s));
+      TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.Om, p, p, pl.k, invB, b.Omhat, ctx->tw, nullptr, s));
+      TLS_CHECK(launch_scores(prec, pl.lgn, b.Yhat, b.Omhat, pl.k, b.u, ctx->tw, pl.m, p, pl.L,
+                              pl.nblocks, s));
+      TLS_CHECK(launch_sample(prec, b.u, pl.m, nullptr, pl.c, b.idx, b.scale, b.swork, seed, fit, s));
+      TLS_CHECK(launch_gather(d_y, pl.m, p, 0, b.idx, b.scale, pl.c, pl.crows, pl.ldq, b.A,
+                              nullptr, nullptr, seed, fit, s));
+    }
+  }
+  TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, b.R, b.G, b.R1, b.R2, b.status, s));
+  TLS_CHECK(launch_triinv(b.R, q, p, b.M, b.Mt, b.phi0, b.status + 1, s));
+  hipLaunchKernelGGL(diag_minmax_kernel, dim3(1), dim3(64), 0, s, b.R, q, p, b.dminmax);
+  if (!o.warm_start) {
+    hipLaunchKernelGGL(zero_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phi0, p);
+  }
+  TLS_CHECK(hipGetLastError());
+
+  int total_iters = 0, istop = 0, refine = 0, pass_count = 0;
+  double pass_ms = 0.0;
+  if (prec == TLS_PREC_F64) {
+    // LSQR on A = X M from the warm start.
+    const int* flag = &b.st->done;
+    size_t npass = 0;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.phi0, p, p, 1, invB, b.Vhat, ctx->tw, nullptr, s));
+    if (o.profile) {
+      TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
+      TLS_CHECK(hipEventRecord(ea, s));
+    }
+    TLS_CHECK(launch_toep(prec, pl.lgn, MODE_FUSED, b.Yhat, b.Vhat, d_y + p, b.u, nullptr,
+                          b.partial, b.st->coef, flag, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
+    if (o.profile) {
+      TLS_CHECK(hipEventRecord(eb, s));
+      ++npass;
+    }
+    TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, flag, s));
+    TLS_CHECK(launch_lsqr_step(prec, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0, b.phi,
+                               b.Vhat, ctx->tw, s));
+    int launched = 0;
+    for (;;) {
+      for (int it = 0; it < CHUNK_ITERS; ++it) {
+        if (o.profile) {
+          TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
+          TLS_CHECK(hipEventRecord(ea, s));
+        }
+        TLS_CHECK(launch_toep(prec, pl.lgn, MODE_FUSED, b.Yhat, b.Vhat, b.u, b.u, nullptr,
+                              b.partial, b.st->coef, flag, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
+        if (o.profile) {
+          TLS_CHECK(hipEventRecord(eb, s));
+          ++npass;
+        }
+        TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, flag, s));
+        TLS_CHECK(launch_lsqr_step(prec, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
+                                   b.phi, b.Vhat, ctx->tw, s));
+      }
+      launched += CHUNK_ITERS;
+      TLS_CHECK(hipMemcpyAsync(&ho->st, b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+      TLS_CHECK(hipStreamSynchronize(s));
+      if (ho->st.done || launched > max_iter + CHUNK_ITERS) break;
+    }
+    total_iters = ho->st.iter;
+    istop = ho->st.istop;
+    if (o.profile) {
+      // passes 0 .. iter did work; later launches in the last chunk exit at once
+      const size_t worked = std::min(npass, static_cast<size_t>(total_iters) + 1);
+      double ms = 0.0;
+      for (size_t i = 0; i < worked; ++i) {
+        float t = 0.f;
+        TLS_CHECK(hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]));
+        ms += t;
+      }
+      pass_ms = ms;
+      pass_count = static_cast<int>(worked);
+    }
+  } else {
+    return TLS_EUNSUPPORTED;  // mixed precision path below
+  }
+
+  // FP64 residual of the returned coefficients, row by row.
+  TLS_CHECK(launch_resid_direct(d_y, pl.m, p, b.phi, b.rpart, s));
+  TLS_CHECK(launch_colsum(b.rpart, resid_direct_blocks(pl.m), 1, b.rr, nullptr, s));
+  TLS_CHECK(hipMemcpyAsync(hphi, b.phi, p * sizeof(double), hipMemcpyDeviceToHost, s));
+  TLS_CHECK(hipMemcpyAsync(ho->rr, b.rr, sizeof(double), hipMemcpyDeviceToHost, s));
+  TLS_CHECK(hipMemcpyAsync(ho->dminmax, b.dminmax, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  TLS_CHECK(hipMemcpyAsync(ho->status, b.status, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  TLS_CHECK(hipStreamSynchronize(s));
+
+  memcpy(coef, hphi, p * sizeof(double));
+  const auto t1 = std::chrono::steady_clock::now();
+  if (res) {
+    memset(res, 0, sizeof(*res));
+    res->resid_norm = sqrt(ho->rr[0]);
+    res->kappa_est = ho->dminmax[1] > 0 ? ho->dminmax[0] / ho->dminmax[1] : INFINITY;
+    res->lsqr_rnorm = ho->st.rnorm;
+    res->lsqr_arnorm = ho->st.arnorm;
+    res->iters = total_iters;
+    res->istop = istop;
+    res->refine_steps = refine;
+    res->sketch_rows = pl.c;
+    res->block_len = pl.B;
+    res->n_blocks = pl.nblocks;
+    res->pass_ms = pass_ms;
+    res->pass_count = pass_count;
+    res->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  for (int i = 0; i < p; ++i)
+    if (!isfinite(coef[i])) return TLS_EINVAL;
+  if ((ho->status[0] & 6) || (ho->status[1] & 4)) return TLS_ERANK;
+  if (istop == 7) return TLS_ENOCONV;
+  return TLS_OK;
+}
+
+tls_ctx* g_default = nullptr;
+std::mutex g_default_mu;
+
+const tls_options& eff_opt(tls_ctx* c, const tls_options* o) { return o ? *o : c->opt; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* tls_status_string(tls_status s) {
+  switch (s) {
+    case TLS_OK: return "ok";
+    case TLS_EINVAL: return "invalid argument";
+    case TLS_ERANK: return "numerically rank-deficient lag matrix";
+    case TLS_ENOCONV: return "iteration limit reached";
+    case TLS_ENOMEM: return "device allocation failed";
+    case TLS_EDEVICE: return "HIP runtime error";
+    case TLS_EUNSUPPORTED: return "size outside the supported range";
+    default: return "unknown status";
+  }
+}
+
+void tls_options_default(tls_options* o) {
+  if (!o) return;
+  memset(o, 0, sizeof(*o));
+  o->precision = TLS_PREC_F64;
+  o->sketch = TLS_SKETCH_LEVERAGE;
+  o->jl_kind = TLS_JL_SRHT;
+  o->gamma = 8;
+  o->jl_k = 8;
+  o->max_iter = 1000;
+  o->block_lg = 0;
+  o->warm_start = 1;
+  o->max_refine = 8;
+  o->seed = 0;
+  o->request_id = 0;
+}
+
+tls_status tls_create(tls_ctx** out, int device, const tls_options* opt) {
+  if (!out) return TLS_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TLS_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TLS_EDEVICE;
+  tls_ctx* c = new tls_ctx();
+  c->device = device;
+  if (opt)
+    c->opt = *opt;
+  else
+    tls_options_default(&c->opt);
+  hipError_t e = hipStreamCreate(&c->stream);
+  if (e == hipSuccess) e = build_twiddles(c);
+  if (e != hipSuccess) {
+    tls_destroy(c);
+    return hip_status(e);
+  }
+  *out = c;
+  return TLS_OK;
+}
+
+void tls_destroy(tls_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  if (c->ws) hipFree(c->ws);
+  if (c->pinned) hipHostFree(c->pinned);
+  if (c->tw64) hipFree(c->tw64);
+  if (c->tw32) hipFree(c->tw32);
+  if (c->consts) hipFree(c->consts);
+  for (hipEvent_t e : c->events) hipEventDestroy(e);
+  if (c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+tls_status tls_fit_ex(tls_ctx* ctx, const double* series, int64_t n, int32_t p, double tol,
+                      const tls_options* opt, double* coef, tls_result* out) {
+  if (!ctx || !series || !coef) return TLS_EINVAL;
+  const tls_options& o = eff_opt(ctx, opt);
+  tls_status st = validate(n, p, tol, o);
+  if (st != TLS_OK) return st;
+  for (int64_t i = 0; i < n; ++i)
+    if (!isfinite(series[i])) return TLS_EINVAL;
+  Plan pl;
+  st = make_plan(n, p, o, &pl);
+  if (st != TLS_OK) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return TLS_EDEVICE;
+  return run_fit(ctx, pl, o, nullptr, series, tol, ctx->stream, coef, out);
+}
+
+tls_status tls_fit_device(tls_ctx* ctx, const double* d_series, int64_t n, int32_t p, double tol,
+                          const tls_options* opt, void* stream, double* coef, tls_result* out) {
+  if (!ctx || !d_series || !coef) return TLS_EINVAL;
+  const tls_options& o = eff_opt(ctx, opt);
+  tls_status st = validate(n, p, tol, o);
+  if (st != TLS_OK) return st;
+  Plan pl;
+  st = make_plan(n, p, o, &pl);
+  if (st != TLS_OK) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return TLS_EDEVICE;
+  return run_fit(ctx, pl, o, d_series, nullptr, tol, pick_stream(ctx, stream), coef, out);
+}
+
+tls_status tls_fit(const double* series, int64_t n, int32_t p, double tol, double* coef,
+                   double* resid_norm, int32_t* iters) {
+  if (!series || !coef) return TLS_EINVAL;
+  {
+    tls_options d;
+    tls_options_default(&d);
+    const tls_status v = validate(n, p, tol, d);
+    if (v != TLS_OK) return v;
+    for (int64_t i = 0; i < n; ++i)
+      if (!isfinite(series[i])) return TLS_EINVAL;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_default_mu);
+    if (!g_default) {
+      tls_status st = tls_create(&g_default, 0, nullptr);
+      if (st != TLS_OK) return st;
+    }
+  }
+  tls_result r;
+  tls_status st = tls_fit_ex(g_default, series, n, p, tol, nullptr, coef, &r);
+  if (st == TLS_OK || st == TLS_ENOCONV || st == TLS_ERANK) {
+    if (resid_norm) *resid_norm = r.resid_norm;
+    if (iters) *iters = r.iters;
+  }
+  return st;
+}
+
+tls_status tls_fit_batch(tls_ctx* ctx, int32_t count, const double* const* series, const int64_t* n,
+                         const int32_t* p, double tol, const tls_options* opt, double* coef_packed,
+                         const int64_t* coef_offset, double* resid_norm, int32_t* iters,
+                         tls_status* per_fit_status) {
+  if (!ctx || count < 0 || (count > 0 && (!series || !n || !p || !coef_packed || !coef_offset)))
+    return TLS_EINVAL;
+  tls_options o = eff_opt(ctx, opt);
+  const uint64_t rid0 = o.request_id;
+  tls_status first = TLS_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    o.request_id = rid0 + static_cast<uint64_t>(i);
+    tls_result r;
+    tls_status st = tls_fit_ex(ctx, series[i], n[i], p[i], tol, &o, coef_packed + coef_offset[i], &r);
+    if (per_fit_status) per_fit_status[i] = st;
+    if (st == TLS_OK || st == TLS_ENOCONV || st == TLS_ERANK) {
+      if (resid_norm) resid_norm[i] = r.resid_norm;
+      if (iters) iters[i] = r.iters;
+    }
+    if (st != TLS_OK && first == TLS_OK) first = st;
+  }
+  return first;
+}
+
+// ---- step-level entry points -----------------------------------------------
+
+int64_t tls_num_blocks(int64_t n, int32_t p, int32_t B) {
+  if (p < 1 || B < 128 || B > BMAX || (B & (B - 1)) || B < 2 * p || n <= p) return -1;
+  const int64_t L = B - p + 1;
+  return (n - p + L - 1) / L;
+}
+
+tls_status tls_op_spectra(tls_ctx* ctx, int32_t prec, const double* d_y, int64_t n, int32_t p,
+                          int32_t B, void* d_spec, void* stream) {
+  if (!ctx || !d_y || !d_spec) return TLS_EINVAL;
+  const int64_t nb = tls_num_blocks(n, p, B);
+  if (nb < 1) return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  TLS_CHECK(launch_spectra(prec == TLS_PREC_F64 ? PREC_F64 : PREC_F32, ilog2(B) - 1, d_y, n,
+                           B - p + 1, static_cast<int>(nb), d_spec, ctx->tw, pick_stream(ctx, stream)));
+  return TLS_OK;
+}
+
+tls_status tls_op_toeplitz(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n, int32_t p,
+                           int32_t B, const double* v, double s1, double s2, const void* d_w,
+                           void* d_e, const void* d_u_in, int32_t want_rmv, double* d_out,
+                           void* stream) {
+  if (!ctx || !d_spec || !d_out) return TLS_EINVAL;
+  if (!v && (!d_u_in || !want_rmv)) return TLS_EINVAL;
+  const int64_t nb64 = tls_num_blocks(n, p, B);
+  if (nb64 < 1) return TLS_EINVAL;
+  const int nb = static_cast<int>(nb64);
+  hipSetDevice(ctx->device);
+  hipStream_t s = pick_stream(ctx, stream);
+  const int pr = prec == TLS_PREC_F64 ? PREC_F64 : PREC_F32;
+  const int lgn = ilog2(B) - 1;
+  Arena a;
+  a.take<double>(p);
+  a.take<double>(2);
+  a.take<char>(static_cast<size_t>(B / 2) * 16);
+  a.take<double>(static_cast<size_t>(p + 1) * nb);
+  TLS_CHECK(ensure_ws(ctx, a.need + 256));
+  a.need = 0;
+  a.base = static_cast<char*>(ctx->ws);
+  double* dv = a.take<double>(p);
+  double* dcoef = a.take<double>(2);
+  void* Vh = a.take<char>(static_cast<size_t>(B / 2) * 16);
+  double* part = a.take<double>(static_cast<size_t>(p + 1) * nb);
+  int mode = MODE_RMV;
+  if (v) {
+    const double cf[2] = {s1, s2};
+    TLS_CHECK(hipMemcpyAsync(dv, v, p * sizeof(double), hipMemcpyHostToDevice, s));
+    TLS_CHECK(hipMemcpyAsync(dcoef, cf, sizeof(cf), hipMemcpyHostToDevice, s));
+    TLS_CHECK(launch_small_rfft(pr, lgn, dv, p, p, 1, 1.0 / B, Vh, ctx->tw, nullptr, s));
+    mode = want_rmv ? MODE_FUSED : MODE_MV;
+  }
+  TLS_CHECK(launch_toep(pr, lgn, mode, d_spec, Vh, d_w, d_e, d_u_in, part, dcoef, nullptr, ctx->tw,
+                        n - p, p, B - p + 1, nb, s));
+  if (mode & PM_RMV) {
+    TLS_CHECK(launch_colsum(part, nb, p + 1, d_out, nullptr, s));
+  } else {
+    TLS_CHECK(launch_colsum(part + static_cast<size_t>(p) * nb, nb, 1, d_out + p, nullptr, s));
+  }
+  // the host copies above read pageable memory; finish before returning
+  TLS_CHECK(hipStreamSynchronize(s));
+  return TLS_OK;
+}
+
+tls_status tls_op_scores(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n, int32_t p,
+                         int32_t B, const double* d_omega, int32_t k, void* d_scores, void* stream) {
+  if (!ctx || !d_spec || !d_omega || !d_scores || k < 1) return TLS_EINVAL;
+  const int64_t nb = tls_num_blocks(n, p, B);
+  if (nb < 1) return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  hipStream_t s = pick_stream(ctx, stream);
+  const int pr = prec == TLS_PREC_F64 ? PREC_F64 : PREC_F32;
+  const int lgn = ilog2(B) - 1;
+  const size_t bytes = static_cast<size_t>(k) * (B / 2) * 16 + 256;
+  TLS_CHECK(ensure_ws(ctx, bytes));
+  TLS_CHECK(launch_small_rfft(pr, lgn, d_omega, p, p, k, 1.0 / B, ctx->ws, ctx->tw, nullptr, s));
+  TLS_CHECK(launch_scores(pr, lgn, d_spec, ctx->ws, k, d_scores, ctx->tw, n - p, p, B - p + 1,
+                          static_cast<int>(nb), s));
+  return TLS_OK;
+}
+
+tls_status tls_op_sample(tls_ctx* ctx, int32_t prec, const void* d_scores, int64_t m,
+                         const double* d_u, int32_t c, uint64_t seed, uint32_t fit,
+                         int64_t* d_idx, double* d_scale, void* stream) {
+  if (!ctx || !d_scores || !d_idx || !d_scale || m < 1 || c < 1) return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  TLS_CHECK(ensure_ws(ctx, sample_work_doubles(m) * sizeof(double) + 256));
+  TLS_CHECK(launch_sample(prec == TLS_PREC_F64 ? PREC_F64 : PREC_F32, d_scores, m, d_u, c, d_idx,
+                          d_scale, static_cast<double*>(ctx->ws), seed, fit,
+                          pick_stream(ctx, stream)));
+  return TLS_OK;
+}
+
+tls_status tls_op_gather(tls_ctx* ctx, const double* d_y, int64_t n, int32_t p, int32_t mode,
+                         int64_t* d_idx, double* d_scale, int32_t c, int32_t crows, int32_t ldq,
+                         double* d_A, uint64_t seed, uint32_t fit, void* stream) {
+  if (!ctx || !d_y || !d_A || p < 1 || n < 2 * static_cast<int64_t>(p) + 1) return TLS_EINVAL;
+  if (mode < 0 || mode > 2 || c < 1 || crows < c || ldq < p + 1) return TLS_EINVAL;
+  if (mode == 0 && (!d_idx || !d_scale)) return TLS_EINVAL;
+  if (mode == 2 && c != n - p) return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  TLS_CHECK(launch_gather(d_y, n - p, p, mode, d_idx, d_scale, c, crows, ldq, d_A,
+                          mode == 1 ? d_idx : nullptr, mode == 1 ? d_scale : nullptr, seed, fit,
+                          pick_stream(ctx, stream)));
+  return TLS_OK;
+}
+
+tls_status tls_op_qr(tls_ctx* ctx, double* d_A, int32_t crows, int32_t q, int32_t ldq, double* d_R,
+                     int32_t* status_out, void* stream) {
+  if (!ctx || !d_A || !d_R || q < 1 || crows % 4 || ldq % 16 || q > ldq || crows < 4)
+    return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  hipStream_t s = pick_stream(ctx, stream);
+  Arena a;
+  a.take<double>(static_cast<size_t>(ldq) * ldq + 2 * static_cast<size_t>(q) * q);
+  a.take<double>(static_cast<size_t>(q) * q);
+  a.take<double>(static_cast<size_t>(q) * q);
+  a.take<int>(4);
+  TLS_CHECK(ensure_ws(ctx, a.need + 256));
+  a.need = 0;
+  a.base = static_cast<char*>(ctx->ws);
+  double* G = a.take<double>(static_cast<size_t>(ldq) * ldq + 2 * static_cast<size_t>(q) * q);
+  double* R1 = a.take<double>(static_cast<size_t>(q) * q);
+  double* R2 = a.take<double>(static_cast<size_t>(q) * q);
+  int* dst = a.take<int>(4);
+  TLS_CHECK(hipMemsetAsync(dst, 0, 4 * sizeof(int), s));
+  TLS_CHECK(launch_qr(d_A, crows, q, ldq, q, d_R, G, R1, R2, dst, s));
+  int hst[4];
+  TLS_CHECK(hipMemcpyAsync(hst, dst, sizeof(hst), hipMemcpyDeviceToHost, s));
+  TLS_CHECK(hipStreamSynchronize(s));
+  if (status_out) *status_out = hst[0];
+  return TLS_OK;
+}
+
+tls_status tls_op_triinv(tls_ctx* ctx, const double* d_R, int32_t q, int32_t p, double* d_M,
+                         double* d_phi0, void* stream) {
+  if (!ctx || !d_R || !d_M || p < 1 || q < p || (d_phi0 && q < p + 1)) return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  hipStream_t s = pick_stream(ctx, stream);
+  TLS_CHECK(ensure_ws(ctx, static_cast<size_t>(p) * p * sizeof(double) + 512));
+  double* Mt = static_cast<double*>(ctx->ws);
+  int* dst = reinterpret_cast<int*>(Mt + static_cast<size_t>(p) * p);
+  TLS_CHECK(hipMemsetAsync(dst, 0, sizeof(int), s));
+  TLS_CHECK(launch_triinv(d_R, q, p, d_M, Mt, d_phi0, dst, s));
+  return TLS_OK;
+}
+
+tls_status tls_op_jl(tls_ctx* ctx, const double* d_M, int32_t p, int32_t k, int32_t kind,
+                     uint64_t seed, uint32_t fit, double* d_Pi, double* d_omega, void* stream) {
+  if (!ctx || !d_M || !d_omega || p < 1 || k < 1 || (kind != 0 && kind != 1)) return TLS_EINVAL;
+  if (p > P_MAX) return TLS_EUNSUPPORTED;
+  hipSetDevice(ctx->device);
+  TLS_CHECK(launch_jl_omega(d_M, p, k, kind, d_Pi, d_omega, seed, fit, pick_stream(ctx, stream)));
+  return TLS_OK;
+}
+
+tls_status tls_op_philox(tls_ctx* ctx, uint64_t seed, uint32_t rng_stream, uint32_t fit,
+                         uint64_t start, int64_t count, double* d_out, void* stream) {
+  if (!ctx || !d_out || count < 0) return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  TLS_CHECK(launch_philox_uniform(d_out, count, rng_stream, fit, seed, start,
+                                  pick_stream(ctx, stream)));
+  return TLS_OK;
+}
+
+}  // extern "C"

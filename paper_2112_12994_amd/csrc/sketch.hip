@@ -1,0 +1,274 @@
+// Randomized sketch kernels: Philox draws, row gathers of [X | b], leverage
+// score sampling (Algorithm 2, eq. (ldist)) and the k-column JL map
+// Omega = M Pi^T of eq. (glev) with a subsampled randomized Hadamard map
+// (Definition 2.4, Algorithm 1) or a Gaussian map.
+#include <math.h>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace tls {
+
+namespace {
+
+__global__ void philox_uniform_kernel(double* __restrict__ out, int64_t count, uint32_t stream,
+                                      uint32_t fit, uint64_t seed, uint64_t start) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = philox_u01(start + static_cast<uint64_t>(i), stream, fit, seed);
+}
+
+// Row t of the sketch: scale * [X(idx,:), b(idx)], zero-padded to ldq columns;
+// rows t >= c are zero.  mode 0: given idx/scale; 1: uniform trials (Algorithm
+// 1: idx = floor(u m), scale sqrt(m/c)); 2: every row (c == m, scale 1).
+__global__ __launch_bounds__(64) void gather_kernel(const double* __restrict__ y, int64_t m, int p,
+                                                    int mode, const int64_t* __restrict__ idx,
+                                                    const double* __restrict__ scale, int c,
+                                                    int ldq, double* __restrict__ A,
+                                                    int64_t* __restrict__ idx_out,
+                                                    double* __restrict__ scale_out, uint64_t seed,
+                                                    uint32_t fit) {
+  const int t = blockIdx.x;
+  double* row = A + static_cast<size_t>(t) * ldq;
+  if (t >= c) {
+    for (int j = threadIdx.x; j < ldq; j += 64) row[j] = 0.0;
+    return;
+  }
+  int64_t ii;
+  double sc;
+  if (mode == 0) {
+    ii = idx[t];
+    sc = scale[t];
+  } else if (mode == 1) {
+    const double u = philox_u01(static_cast<uint64_t>(t), RNG_UNIFORM_ROWS, fit, seed);
+    ii = static_cast<int64_t>(floor(u * static_cast<double>(m)));
+    if (ii > m - 1) ii = m - 1;
+    sc = sqrt(static_cast<double>(m) / static_cast<double>(c));
+  } else {
+    ii = t;
+    sc = 1.0;
+  }
+  for (int j = threadIdx.x; j < ldq; j += 64) {
+    double v = 0.0;
+    if (j < p)
+      v = sc * y[p - 1 + ii - j];
+    else if (j == p)
+      v = sc * y[p + ii];
+    row[j] = v;
+  }
+  if (threadIdx.x == 0) {
+    if (idx_out) idx_out[t] = ii;
+    if (scale_out) scale_out[t] = sc;
+  }
+}
+
+constexpr int CHUNK = 4096;
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void chunk_sum_kernel(const T* __restrict__ s, int64_t m,
+                                                       double* __restrict__ out) {
+  __shared__ double red[NT / 64];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < CHUNK; i += NT) {
+    const int64_t g = base + i;
+    if (g < m) acc += static_cast<double>(s[g]);
+  }
+  const double tot = block_sum<NT>(acc, red);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
+// Exclusive prefix of the chunk sums in chunk order: pre[0] = 0, pre[k+1] =
+// pre[k] + sums[k]; pre[nch] is the total.  One workgroup.
+template <int NT>
+__global__ __launch_bounds__(NT) void chunk_prefix_kernel(const double* __restrict__ sums,
+                                                          int nch, double* __restrict__ pre) {
+  __shared__ double buf[NT];
+  __shared__ double carry;
+  if (threadIdx.x == 0) {
+    carry = 0.0;
+    pre[0] = 0.0;
+  }
+  __syncthreads();
+  for (int base = 0; base < nch; base += NT) {
+    const int i = base + threadIdx.x;
+    buf[threadIdx.x] = i < nch ? sums[i] : 0.0;
+    __syncthreads();
+    // inclusive Hillis-Steele scan over NT entries
+    for (int off = 1; off < NT; off <<= 1) {
+      const double v = threadIdx.x >= off ? buf[threadIdx.x - off] : 0.0;
+      __syncthreads();
+      buf[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (i < nch) pre[i + 1] = carry + buf[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) carry += buf[NT - 1];
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double wave_incl_scan(double v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const double t = __shfl_up(v, off, 64);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
+// One wavefront per draw: target = u * total; find the chunk by binary search
+// on the prefix, then the first row in the chunk whose running total exceeds
+// the target.  scale = 1 / sqrt(c * s_i / total).
+template <typename T>
+__global__ __launch_bounds__(64) void draw_kernel(const T* __restrict__ s, int64_t m,
+                                                  const double* __restrict__ pre, int nch,
+                                                  const double* __restrict__ u, int c,
+                                                  int64_t* __restrict__ idx,
+                                                  double* __restrict__ scale, uint64_t seed,
+                                                  uint32_t fit) {
+  const int t = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double total = pre[nch];
+  const double ut = u ? u[t] : philox_u01(static_cast<uint64_t>(t), RNG_LEVERAGE, fit, seed);
+  const double target = ut * total;
+  int lo = 0, hi = nch - 1;  // last chunk with pre[k] <= target
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= target)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int64_t base = static_cast<int64_t>(lo) * CHUNK;
+  double running = pre[lo];
+  int64_t found = -1, lastpos = -1;
+  for (int off = 0; off < CHUNK && base + off < m; off += 64) {
+    const int64_t g = base + off + lane;
+    const double v = g < m ? static_cast<double>(s[g]) : 0.0;
+    const double incl = wave_incl_scan(v);
+    const uint64_t hit = __ballot(running + incl > target && v > 0.0);
+    const uint64_t pos = __ballot(v > 0.0);
+    if (pos) lastpos = base + off + 63 - __builtin_clzll(pos);
+    if (hit) {
+      found = base + off + __builtin_ctzll(hit);
+      break;
+    }
+    running += __shfl(incl, 63, 64);
+  }
+  if (found < 0) found = lastpos;  // target within rounding of the chunk end
+  if (found < 0) found = base;     // all-zero chunk cannot be reached by a positive total
+  if (lane == 0) {
+    idx[t] = found;
+    const double sv = static_cast<double>(s[found]);
+    scale[t] = 1.0 / sqrt(static_cast<double>(c) * sv / total);
+  }
+}
+
+// Pi (k x p) and Omega = M Pi^T (p x k, column-major).  kind 0: subsampled
+// randomized Hadamard map: Pi[q][j] = d_j (-1)^popcount(r_q & j) / sqrt(k)
+// with d_j = +-1 from the sign stream and r_q uniform in [0, P); kind 1:
+// Gaussian N(0, 1/k) entries (Box-Muller).  M is upper triangular, row-major (p x p).
+template <int NT>
+__global__ __launch_bounds__(NT) void jl_omega_kernel(const double* __restrict__ M, int p, int k,
+                                                      int kind, double* __restrict__ Pi,
+                                                      double* __restrict__ Om, uint64_t seed,
+                                                      uint32_t fit) {
+  extern __shared__ double prow[];
+  const int q = blockIdx.x;
+  int P = 1;
+  while (P < p) P <<= 1;
+  const double invsk = 1.0 / sqrt(static_cast<double>(k));
+  uint32_t rq = 0;
+  if (kind == 0) {
+    const double ur = philox_u01(static_cast<uint64_t>(q), RNG_SRHT_ROWS, fit, seed);
+    int64_t r = static_cast<int64_t>(floor(ur * static_cast<double>(P)));
+    if (r > P - 1) r = P - 1;
+    rq = static_cast<uint32_t>(r);
+  }
+  for (int j = threadIdx.x; j < p; j += NT) {
+    double val;
+    if (kind == 0) {
+      const double us = philox_u01(static_cast<uint64_t>(j), RNG_SRHT_SIGNS, fit, seed);
+      const double d = us < 0.5 ? 1.0 : -1.0;
+      const double h = (__popc(rq & static_cast<uint32_t>(j)) & 1) ? -1.0 : 1.0;
+      val = d * h * invsk;
+    } else {
+      const uint64_t e = static_cast<uint64_t>(q) * p + j;
+      const double u1 = philox_u01(2 * e, RNG_GAUSS, fit, seed);
+      const double u2 = philox_u01(2 * e + 1, RNG_GAUSS, fit, seed);
+      val = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2) * invsk;
+    }
+    prow[j] = val;
+    if (Pi) Pi[static_cast<size_t>(q) * p + j] = val;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < p; i += NT) {
+    double acc = 0.0;
+    const double* mi = M + static_cast<size_t>(i) * p;
+    for (int j = i; j < p; ++j) acc += mi[j] * prow[j];
+    Om[static_cast<size_t>(q) * p + i] = acc;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_philox_uniform(double* out, int64_t count, uint32_t stream, uint32_t fit,
+                                 uint64_t seed, uint64_t start, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const int64_t nb = (count + 255) / 256;
+  hipLaunchKernelGGL(philox_uniform_kernel, dim3(static_cast<unsigned>(nb)), dim3(256), 0, st,
+                     out, count, stream, fit, seed, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const double* y, int64_t m, int p, int mode, const int64_t* idx,
+                         const double* scale, int c, int crows, int ldq, double* A, int64_t* idx_out,
+                         double* scale_out, uint64_t seed, uint32_t fit, hipStream_t st) {
+  if (crows < c || ldq < p + 1 || crows < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gather_kernel, dim3(crows), dim3(64), 0, st, y, m, p, mode, idx, scale, c,
+                     ldq, A, idx_out, scale_out, seed, fit);
+  return hipGetLastError();
+}
+
+size_t sample_work_doubles(int64_t m) {
+  const int64_t nch = (m + CHUNK - 1) / CHUNK;
+  return static_cast<size_t>(2 * nch + 1);
+}
+
+hipError_t launch_sample(int prec, const void* scores, int64_t m, const double* u, int c,
+                         int64_t* idx, double* scale, double* work, uint64_t seed, uint32_t fit,
+                         hipStream_t st) {
+  if (m < 1 || c < 1) return hipErrorInvalidValue;
+  const int nch = static_cast<int>((m + CHUNK - 1) / CHUNK);
+  double* sums = work;
+  double* pre = work + nch;
+  if (prec == PREC_F64) {
+    hipLaunchKernelGGL((chunk_sum_kernel<double, 256>), dim3(nch), dim3(256), 0, st,
+                       static_cast<const double*>(scores), m, sums);
+  } else {
+    hipLaunchKernelGGL((chunk_sum_kernel<float, 256>), dim3(nch), dim3(256), 0, st,
+                       static_cast<const float*>(scores), m, sums);
+  }
+  hipLaunchKernelGGL((chunk_prefix_kernel<256>), dim3(1), dim3(256), 0, st, sums, nch, pre);
+  if (prec == PREC_F64) {
+    hipLaunchKernelGGL((draw_kernel<double>), dim3(c), dim3(64), 0, st,
+                       static_cast<const double*>(scores), m, pre, nch, u, c, idx, scale, seed,
+                       fit);
+  } else {
+    hipLaunchKernelGGL((draw_kernel<float>), dim3(c), dim3(64), 0, st,
+                       static_cast<const float*>(scores), m, pre, nch, u, c, idx, scale, seed,
+                       fit);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, double* Om,
+                           uint64_t seed, uint32_t fit, hipStream_t st) {
+  if (p < 1 || k < 1 || p > 8192) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((jl_omega_kernel<256>), dim3(k), dim3(256), p * sizeof(double), st, M, p, k,
+                     kind, Pi, Om, seed, fit);
+  return hipGetLastError();
+}
+
+}  // namespace tls

@@ -1,0 +1,271 @@
+// Blocked circulant-embedding kernels for the lag matrix of eq. (xphi).
+//
+// Layout (0-based): X[i, j] = y[p-1+i-j], b[i] = y[p+i], m = n - p rows.
+// Block k covers rows [kL, kL+L), L = B - p + 1, and owns the window
+// y[kL .. kL+B) (zero past the end of y).  Inside the window, row i sits at
+// position tau = i - kL + p - 1 in [p-1, B): the circular convolution of the
+// window with v (zero-padded to B) at tau is exactly (X v)[i], and the
+// circular correlation of the window with the block's rows placed at
+// tau in [p-1, B) gives that block's share of (X^T u)[j] at j < p (no
+// wrap-around in either, since every index difference stays in [0, B)).
+//
+// Spectra are stored packed: N = B/2 complex words per block, word 0 holding
+// (X[0], X[N]) (both real) and word k the bin X[k] for 0 < k < N.
+#pragma once
+
+#include "fft.h"
+#include "kernels.h"
+
+namespace tls {
+
+template <typename T>
+__device__ __forceinline__ void load_pair(const cx<T>* __restrict__ P, int k, int N, cx<T>& a,
+                                          cx<T>& b) {
+  if (k == 0) {
+    const cx<T> w0 = P[0];
+    a = {w0.x, T(0)};
+    b = {w0.y, T(0)};
+  } else {
+    a = P[k];
+    b = P[N - k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block spectra of the series (computed in FP64, stored as TS).
+template <int LGN, int NT, typename TS>
+__global__ __launch_bounds__(NT) void spectra_kernel(const double* __restrict__ y, int64_t n, int L,
+                                                     cx<TS>* __restrict__ Yhat,
+                                                     const cx<double>* __restrict__ tab) {
+  constexpr int N = 1 << LGN;
+  __shared__ cx<double> s[N];
+  const int blk = blockIdx.x;
+  const int64_t start = static_cast<int64_t>(blk) * L;
+  for (int t = threadIdx.x; t < N; t += NT) {
+    const int64_t i0 = start + 2 * t;
+    s[t] = {i0 < n ? y[i0] : 0.0, i0 + 1 < n ? y[i0 + 1] : 0.0};
+  }
+  __syncthreads();
+  fft_dif<double, false, LGN, NT>(s, tab);
+  cx<TS>* out = Yhat + static_cast<size_t>(blk) * N;
+  for (int k = threadIdx.x; k <= N / 2; k += NT) {
+    const cx<double> w = twiddle<double, false>(tab, k, LGN + 1);
+    cx<double> Xk, Xnk;
+    rfft_post(s[bitrev(k, LGN)], s[bitrev((N - k) & (N - 1), LGN)], w, Xk, Xnk);
+    if (k == 0) {
+      out[0] = {static_cast<TS>(Xk.x), static_cast<TS>(Xnk.x)};
+    } else {
+      out[k] = {static_cast<TS>(Xk.x), static_cast<TS>(Xk.y)};
+      if (2 * k != N) out[N - k] = {static_cast<TS>(Xnk.x), static_cast<TS>(Xnk.y)};
+    }
+  }
+}
+
+// Packed spectra (times `scale`) of short real columns zero-padded to B.
+template <int LGN, int NT, typename TS>
+__global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict__ cols, int len,
+                                                        int ld, double scale,
+                                                        cx<TS>* __restrict__ out,
+                                                        const cx<double>* __restrict__ tab,
+                                                        const int* __restrict__ flag) {
+  constexpr int N = 1 << LGN;
+  __shared__ cx<double> s[N];
+  if (flag && *flag) return;
+  const double* col = cols + static_cast<size_t>(blockIdx.x) * ld;
+  for (int t = threadIdx.x; t < N; t += NT) {
+    const int i0 = 2 * t;
+    s[t] = {i0 < len ? col[i0] : 0.0, i0 + 1 < len ? col[i0 + 1] : 0.0};
+  }
+  __syncthreads();
+  fft_dif<double, false, LGN, NT>(s, tab);
+  cx<TS>* o = out + static_cast<size_t>(blockIdx.x) * N;
+  for (int k = threadIdx.x; k <= N / 2; k += NT) {
+    const cx<double> w = twiddle<double, false>(tab, k, LGN + 1);
+    cx<double> Xk, Xnk;
+    rfft_post(s[bitrev(k, LGN)], s[bitrev((N - k) & (N - 1), LGN)], w, Xk, Xnk);
+    Xk = cscale(Xk, scale);
+    Xnk = cscale(Xnk, scale);
+    if (k == 0) {
+      o[0] = {static_cast<TS>(Xk.x), static_cast<TS>(Xnk.x)};
+    } else {
+      o[k] = {static_cast<TS>(Xk.x), static_cast<TS>(Xk.y)};
+      if (2 * k != N) o[N - k] = {static_cast<TS>(Xnk.x), static_cast<TS>(Xnk.y)};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One pass over all blocks.  With v's packed spectrum pre-scaled by 1/B:
+//   e = s1 * (X v) + s2 * w          (PM_MV; the w term when w_in != NULL)
+//   u_out = e                        (when u_out != NULL; may alias w_in)
+//   partial[j*nb + blk] = block share of (X^T e)[j], j < p     (PM_RMV)
+//   partial[p*nb + blk] = block share of ||e||^2
+// Without PM_MV the pass vector is u_in.  (s1, s2) = coef[0..1].
+template <typename T, int LGN, int NT, int MODE>
+__global__ __launch_bounds__(NT) void toep_pass_kernel(
+    const cx<T>* __restrict__ Yhat, const cx<T>* __restrict__ Vhat, const T* w_in, T* u_out,
+    const T* __restrict__ u_in, double* __restrict__ partial, const double* __restrict__ coef,
+    const int* __restrict__ flag, const cx<T>* __restrict__ tab, int64_t m, int p, int L,
+    int nblocks) {
+  constexpr int N = 1 << LGN;
+  constexpr int NPAIR = (N / 2 + 1 + NT - 1) / NT;
+  constexpr int NEL = N / NT;
+  static_assert(N % NT == 0, "block transform must cover the workgroup");
+  __shared__ cx<T> s[N];
+  __shared__ double red[NT / 64];
+  if (flag && *flag) return;
+  const int blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  const cx<T>* Y = Yhat + static_cast<size_t>(blk) * N;
+  const int64_t row0 = static_cast<int64_t>(blk) * L - (p - 1);  // row at tau = 0
+
+  cx<T> yk[NPAIR], ynk[NPAIR];
+#pragma unroll
+  for (int ip = 0; ip < NPAIR; ++ip) {
+    const int k = tid + ip * NT;
+    if (k <= N / 2) load_pair(Y, k, N, yk[ip], ynk[ip]);
+  }
+
+  double nrm = 0.0;
+  if constexpr ((MODE & PM_MV) != 0) {
+    const T s1 = static_cast<T>(coef[0]);
+    const T s2 = static_cast<T>(coef[1]);
+#pragma unroll
+    for (int ip = 0; ip < NPAIR; ++ip) {
+      const int k = tid + ip * NT;
+      if (k <= N / 2) {
+        cx<T> vk, vnk;
+        load_pair(Vhat, k, N, vk, vnk);
+        const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
+        cx<T> Zk, Znk;
+        irfft_pre(cmul(yk[ip], vk), cmul(ynk[ip], vnk), w, Zk, Znk);
+        s[bitrev(k, LGN)] = Zk;
+        if (k != 0 && 2 * k != N) s[bitrev(N - k, LGN)] = Znk;
+      }
+    }
+    __syncthreads();
+    fft_dit<T, true, LGN, NT>(s, tab);
+#pragma unroll
+    for (int e = 0; e < NEL; ++e) {
+      const int t = tid + e * NT;
+      const cx<T> z = s[t];
+      T o0 = T(0), o1 = T(0);
+      const int64_t i0 = row0 + 2 * t;
+      if (2 * t >= p - 1 && i0 < m) {
+        o0 = s1 * z.x;
+        if (w_in) o0 += s2 * w_in[i0];
+        if (u_out) u_out[i0] = o0;
+      }
+      if (2 * t + 1 >= p - 1 && i0 + 1 < m) {
+        o1 = s1 * z.y;
+        if (w_in) o1 += s2 * w_in[i0 + 1];
+        if (u_out) u_out[i0 + 1] = o1;
+      }
+      nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
+      if constexpr ((MODE & PM_RMV) != 0) s[t] = {o0, o1};
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < NEL; ++e) {
+      const int t = tid + e * NT;
+      const int64_t i0 = row0 + 2 * t;
+      const T o0 = (2 * t >= p - 1 && i0 < m) ? u_in[i0] : T(0);
+      const T o1 = (2 * t + 1 >= p - 1 && i0 + 1 < m) ? u_in[i0 + 1] : T(0);
+      nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
+      s[t] = {o0, o1};
+    }
+  }
+
+  if constexpr ((MODE & PM_RMV) != 0) {
+    __syncthreads();
+    fft_dif<T, false, LGN, NT>(s, tab);
+#pragma unroll
+    for (int ip = 0; ip < NPAIR; ++ip) {
+      const int k = tid + ip * NT;
+      if (k <= N / 2) {
+        const int bk = bitrev(k, LGN);
+        const int bnk = bitrev((N - k) & (N - 1), LGN);
+        const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
+        cx<T> Xk, Xnk;
+        rfft_post(s[bk], s[bnk], w, Xk, Xnk);
+        cx<T> Zk, Znk;
+        irfft_pre(cmulconj(yk[ip], Xk), cmulconj(ynk[ip], Xnk), w, Zk, Znk);
+        s[bk] = Zk;
+        if (k != 0 && 2 * k != N) s[bnk] = Znk;
+      }
+    }
+    __syncthreads();
+    fft_dit<T, true, LGN, NT>(s, tab);
+    const double invB = 1.0 / static_cast<double>(2 * N);
+    for (int t = tid; 2 * t < p; t += NT) {
+      const cx<T> z = s[t];
+      partial[static_cast<size_t>(2 * t) * nblocks + blk] = static_cast<double>(z.x) * invB;
+      if (2 * t + 1 < p)
+        partial[static_cast<size_t>(2 * t + 1) * nblocks + blk] = static_cast<double>(z.y) * invB;
+    }
+  }
+  const double tot = block_sum<NT>(nrm, red);
+  if (tid == 0) partial[static_cast<size_t>(p) * nblocks + blk] = tot;
+}
+
+// ---------------------------------------------------------------------------
+// Approximate generalised leverage scores (eq. (glev) in product form):
+// scores[i] = sum_q ((X omega_q)[i])^2 for k packed column spectra (scaled 1/B).
+template <typename T, int LGN, int NT>
+__global__ __launch_bounds__(NT) void scores_kernel(const cx<T>* __restrict__ Yhat,
+                                                    const cx<T>* __restrict__ Om, int kcols,
+                                                    T* __restrict__ scores,
+                                                    const cx<T>* __restrict__ tab, int64_t m,
+                                                    int p, int L) {
+  constexpr int N = 1 << LGN;
+  constexpr int NPAIR = (N / 2 + 1 + NT - 1) / NT;
+  constexpr int NEL = N / NT;
+  __shared__ cx<T> s[N];
+  const int blk = blockIdx.x;
+  const int tid = threadIdx.x;
+  const cx<T>* Y = Yhat + static_cast<size_t>(blk) * N;
+  const int64_t row0 = static_cast<int64_t>(blk) * L - (p - 1);
+  cx<T> yk[NPAIR], ynk[NPAIR];
+#pragma unroll
+  for (int ip = 0; ip < NPAIR; ++ip) {
+    const int k = tid + ip * NT;
+    if (k <= N / 2) load_pair(Y, k, N, yk[ip], ynk[ip]);
+  }
+  T acc0[NEL], acc1[NEL];
+#pragma unroll
+  for (int e = 0; e < NEL; ++e) acc0[e] = acc1[e] = T(0);
+  for (int q = 0; q < kcols; ++q) {
+    const cx<T>* V = Om + static_cast<size_t>(q) * N;
+#pragma unroll
+    for (int ip = 0; ip < NPAIR; ++ip) {
+      const int k = tid + ip * NT;
+      if (k <= N / 2) {
+        cx<T> vk, vnk;
+        load_pair(V, k, N, vk, vnk);
+        const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
+        cx<T> Zk, Znk;
+        irfft_pre(cmul(yk[ip], vk), cmul(ynk[ip], vnk), w, Zk, Znk);
+        s[bitrev(k, LGN)] = Zk;
+        if (k != 0 && 2 * k != N) s[bitrev(N - k, LGN)] = Znk;
+      }
+    }
+    __syncthreads();
+    fft_dit<T, true, LGN, NT>(s, tab);
+#pragma unroll
+    for (int e = 0; e < NEL; ++e) {
+      const cx<T> z = s[tid + e * NT];
+      acc0[e] += z.x * z.x;
+      acc1[e] += z.y * z.y;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < NEL; ++e) {
+    const int t = tid + e * NT;
+    const int64_t i0 = row0 + 2 * t;
+    if (2 * t >= p - 1 && i0 < m) scores[i0] = acc0[e];
+    if (2 * t + 1 >= p - 1 && i0 + 1 < m) scores[i0 + 1] = acc1[e];
+  }
+}
+
+}  // namespace tls

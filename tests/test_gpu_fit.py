@@ -1,0 +1,205 @@
+"""End-to-end parity: tls_fit* (HIP path through the C-ABI) against the FP64
+QR oracle.  Coefficient gate 1e-6 relative for the FP64 path, asserted where
+the attainable accuracy allows it (kappa(X) * 1e-12 below the gate)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import (attainable, capi, chunked_matvec_norms, resid_tol, say, to_dev,
+                              torch_dev)
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = capi()
+    with c.Context(0) as cx:
+        yield cx
+
+
+def _check_fit(out, y, p, gate=1e-6, tol=1e-10):
+    """Status OK; coefficients within the 1e-6 gate wherever the attainable
+    accuracy (gpu_common.attainable) is below it; fitted values and the FP64
+    residual norm within their derived bounds at any conditioning."""
+    c = capi()
+    ref = oracle.fit_qr(y, p)
+    phi = ref["phi"]
+    smax = float(np.linalg.svd(ref["R"], compute_uv=False)[0])
+    xd, xphi = chunked_matvec_norms(y, p, out["coef"] - phi, phi)
+    bnorm = float(np.linalg.norm(y[p:]))
+    coef_b, fit_b = attainable(phi, ref["rnorm"], ref["kappa"], smax, xphi, bnorm, p,
+                               out["block_len"], tol)
+    err = oracle.rel_error(out["coef"], phi)
+    say("   kappa=%.3g err=%.3g (bound %.2g) fit=%.3g (bound %.2g) iters=%d istop=%d"
+        % (ref["kappa"], err, coef_b, xd / xphi, fit_b, out["iters"], out["istop"]))
+    assert out["status"] == c.TLS_OK, c.status_string(out["status"])
+    if coef_b < gate:
+        assert err <= gate
+    assert xd / xphi <= max(10 * fit_b, 1e-14)
+    rt = resid_tol(phi, ref["rnorm"], smax, np.abs(y).max(), p, xd)
+    assert abs(out["resid_norm"] - ref["rnorm"]) <= rt
+    return err, ref
+
+
+def test_ar3_config(ctx):
+    """AR(3), phi = (0.5, -0.3, 0.1), n = 10,000, sketch 20p, tol 1e-10."""
+    say("fit ar3")
+    f = synth.workload_ar3(seed=0)
+    out = ctx.fit(f.y, 3, 1e-10, gamma=20)
+    err, _ = _check_fit(out, f.y, 3)
+    assert err <= 1e-10
+    assert out["iters"] <= 10
+
+
+@pytest.mark.parametrize("p,n,seed", [(1, 5000, 0), (2, 777, 1), (8, 20000, 2), (40, 65536, 3),
+                                      (100, 65536, 0), (64, 262144, 4), (200, 100000, 5)])
+def test_fit_f64_matches_oracle(ctx, p, n, seed):
+    say("fit f64", p, n, seed)
+    rng = np.random.default_rng(seed)
+    y = synth.ar_series(n, p, rng, 0.3, 0.9)
+    out = ctx.fit(y, p, 1e-10)
+    _check_fit(out, y, p)
+
+
+@pytest.mark.parametrize("sketch,jl", [(1, 0), (0, 1), (0, 0)])
+def test_sketch_variants_converge_to_same_solution(ctx, sketch, jl):
+    say("fit sketch variant", sketch, jl)
+    rng = np.random.default_rng(21)
+    y = synth.ar_series(50000, 30, rng, 0.3, 0.9)
+    out = ctx.fit(y, 30, 1e-10, sketch=sketch, jl_kind=jl)
+    _check_fit(out, y, 30)
+
+
+def test_all_rows_when_sketch_exceeds_data(ctx):
+    """c >= n - p: the sketch is all of [X | b], R is exact, LSQR stops at once."""
+    say("fit all rows")
+    rng = np.random.default_rng(22)
+    y = synth.ar_series(300, 20, rng, 0.3, 0.9)
+    out = ctx.fit(y, 20, 1e-10, gamma=50)
+    _check_fit(out, y, 20)
+    assert out["sketch_rows"] == 280
+    assert out["iters"] <= 3
+
+
+def test_minimal_length(ctx):
+    say("fit minimal length")
+    rng = np.random.default_rng(23)
+    p = 6
+    y = rng.standard_normal(2 * p + 1)
+    out = ctx.fit(y, p, 1e-10)
+    _check_fit(out, y, p)
+
+
+def test_no_warm_start(ctx):
+    say("fit cold start")
+    rng = np.random.default_rng(24)
+    y = synth.ar_series(30000, 12, rng, 0.3, 0.9)
+    out = ctx.fit(y, 12, 1e-10, warm_start=0)
+    _check_fit(out, y, 12)
+
+
+def test_outlier_stress(ctx):
+    """Outlier recipe of Section 4.2 scaled to n (1000 per 2e6 points)."""
+    say("fit outliers")
+    rng = np.random.default_rng(25)
+    y = synth.ar_series(200000, 20, rng, 0.5, 0.95)
+    y = synth.add_outliers(y, rng, 100)
+    out = ctx.fit(y, 20, 1e-10)
+    _check_fit(out, y, 20)
+
+
+def test_student_t(ctx):
+    say("fit t5")
+    rng = np.random.default_rng(26)
+    y = synth.ar_series(100000, 16, rng, 0.3, 0.95, innovations="t5")
+    out = ctx.fit(y, 16, 1e-10)
+    _check_fit(out, y, 16)
+
+
+def test_deterministic(ctx):
+    say("fit determinism")
+    rng = np.random.default_rng(27)
+    y = synth.ar_series(40000, 25, rng, 0.3, 0.9)
+    a = ctx.fit(y, 25, 1e-10, seed=5)
+    b = ctx.fit(y, 25, 1e-10, seed=5)
+    assert a["coef"].tobytes() == b["coef"].tobytes()
+    assert a["iters"] == b["iters"]
+
+
+def test_device_input_same_as_host(ctx):
+    say("fit device input")
+    rng = np.random.default_rng(28)
+    y = synth.ar_series(40000, 25, rng, 0.3, 0.9)
+    a = ctx.fit(y, 25, 1e-10)
+    b = ctx.fit_device(to_dev(y), 25, 1e-10)
+    assert a["coef"].tobytes() == b["coef"].tobytes()
+
+
+def test_invalid_arguments(ctx):
+    c = capi()
+    say("fit invalid")
+    y = np.ones(100)
+    assert ctx.fit(y, 0, 1e-10)["status"] == c.TLS_EINVAL
+    assert ctx.fit(y, 50, 1e-10)["status"] == c.TLS_EINVAL
+    assert ctx.fit(y, 3, 0.0)["status"] == c.TLS_EINVAL
+    yb = np.random.default_rng(0).standard_normal(100)
+    yb[7] = np.nan
+    assert ctx.fit(yb, 3, 1e-10)["status"] == c.TLS_EINVAL
+
+
+def test_rank_deficient_flagged(ctx):
+    """A constant series makes X rank one (Theorem 2.2's singular case)."""
+    c = capi()
+    say("fit rank deficient")
+    y = np.full(5000, 2.0)
+    out = ctx.fit(y, 3, 1e-10)
+    assert out["status"] == c.TLS_ERANK
+
+
+def test_iteration_limit(ctx):
+    c = capi()
+    say("fit iteration limit")
+    rng = np.random.default_rng(29)
+    y = synth.ar_series(30000, 30, rng, 0.5, 0.95)
+    out = ctx.fit(y, 30, 1e-14, max_iter=1, warm_start=0)
+    assert out["status"] == c.TLS_ENOCONV
+    assert out["iters"] == 1
+    assert np.all(np.isfinite(out["coef"]))
+
+
+def test_batch_equals_single(ctx):
+    c = capi()
+    say("fit batch")
+    fits = synth.workload_batch(seed=3, count=6, lo_exp=12, hi_exp=14)
+    s, outs = ctx.fit_batch([f.y for f in fits], [f.p for f in fits], 1e-10, request_id=100)
+    assert s == c.TLS_OK
+    for i, (f, o) in enumerate(zip(fits, outs)):
+        single = ctx.fit(f.y, f.p, 1e-10, request_id=100 + i)
+        assert o["coef"].tobytes() == single["coef"].tobytes()
+
+
+def test_ar100_full_size_against_stored_oracle(ctx):
+    """The AR(100), n = 2^22 workload at full size, in the configuration the
+    bench times, against the oracle's stored solution (tests/golden)."""
+    say("fit ar100 full size")
+    data = np.loadtxt(os.path.join(GOLDEN, "ar100_seed0_oracle.txt"))
+    phi, rnorm, kappa, smax = data[:-3], data[-3], data[-2], data[-1]
+    f = synth.workload_ar100(seed=0)
+    out = ctx.fit(f.y, 100, f.tol, gamma=f.gamma)
+    assert out["status"] == capi().TLS_OK
+    xd, xphi = chunked_matvec_norms(f.y, 100, out["coef"] - phi, phi)
+    coef_b, fit_b = attainable(phi, rnorm, kappa, smax, xphi, float(np.linalg.norm(f.y[100:])), 100,
+                               out["block_len"], f.tol)
+    err = oracle.rel_error(out["coef"], phi)
+    say("   kappa=%.3g err=%.3g (bound %.2g) fit=%.3g (bound %.2g) iters=%d"
+        % (kappa, err, coef_b, xd / xphi, fit_b, out["iters"]))
+    if coef_b < 1e-6:
+        assert err <= 1e-6
+    assert xd / xphi <= max(10 * fit_b, 1e-14)
+    assert abs(out["resid_norm"] - rnorm) <= resid_tol(phi, rnorm, smax, np.abs(f.y).max(), 100, xd)
