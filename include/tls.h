@@ -40,7 +40,8 @@ extern "C" {
 typedef int32_t tls_status;
 #define TLS_OK 0          /* success */
 #define TLS_EINVAL 1      /* invalid argument: NULL pointer, p < 1, n < 2p + 1, tol not in (0,1), non-finite data */
-#define TLS_ERANK 2       /* X numerically rank deficient (Theorem 2.2's singular case); outputs hold LSQR's iterate */
+#define TLS_ERANK 2       /* X numerically rank deficient (Theorem 2.2's singular case), or the preconditioned
+                             iteration broke down numerically; outputs hold the last finite iterate */
 #define TLS_ENOCONV 3     /* iteration limit reached; outputs hold the last iterate */
 #define TLS_ENOMEM 4      /* device allocation failed */
 #define TLS_EDEVICE 5     /* HIP runtime error */
@@ -80,7 +81,7 @@ typedef struct tls_result {
   double lsqr_rnorm;   /* LSQR's own residual estimate */
   double lsqr_arnorm;  /* LSQR's ||A^T r|| estimate */
   int32_t iters;       /* total inner iterations */
-  int32_t istop;       /* LSQR stop reason: 1, 2 converged; 3 exact; 7 limit */
+  int32_t istop;       /* LSQR stop reason: 1, 2 converged; 3 exact; 4 breakdown; 7 limit */
   int32_t refine_steps;/* outer refinement steps (mixed precision), else 0 */
   int32_t sketch_rows; /* c */
   int32_t block_len;   /* FFT block length B used */
@@ -188,7 +189,7 @@ tls_status tls_op_gather(tls_ctx* ctx, const double* d_y, int64_t n, int32_t p, 
 
 /* QR of the sketch (Section 2.1: QR of the compressed matrix): upper
  * triangular d_R (q x q, row-major, non-negative diagonal) with
- * A^T A = R^T R for the crows x ldq row-major d_A (crows % 4 == 0,
+ * A^T A = R^T R for the crows x ldq row-major d_A (crows % 16 == 0,
  * ldq % 16 == 0, q <= ldq; d_A is overwritten).  *status_out (host) gets the
  * breakdown bits: 1 = the shifted first sweep broke down, 2 = a later sweep
  * broke down, 4 = min|R_ii| <= q u max|R_ii|; 2 or 4 mean numerically rank

@@ -174,7 +174,7 @@ tls_status make_plan(int64_t n, int p, const tls_options& o, Plan* pl) {
   const int64_t c = static_cast<int64_t>(o.gamma > 0 ? o.gamma : 8) * p;
   pl->all_rows = c >= pl->m ? 1 : 0;
   pl->c = static_cast<int>(pl->all_rows ? pl->m : c);
-  pl->crows = (pl->c + 3) / 4 * 4;
+  pl->crows = (pl->c + 15) / 16 * 16;
   pl->k = o.jl_k > 0 ? o.jl_k : 8;
   return TLS_OK;
 }
@@ -231,7 +231,7 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->partial = a.take<double>(static_cast<size_t>(pl.p + 1) * pl.nblocks);
   b->g = a.take<double>(pl.p + 1);
   b->A = a.take<double>(static_cast<size_t>(pl.crows) * pl.ldq);
-  b->G = a.take<double>(static_cast<size_t>(pl.ldq) * pl.ldq + 2 * static_cast<size_t>(pl.q) * pl.q);
+  b->G = a.take<double>(qr_scratch_doubles(pl.crows, pl.q, pl.ldq));
   b->R1 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
   b->R2 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
   b->R = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
@@ -346,7 +346,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     TLS_CHECK(launch_gather(d_y, pl.m, p, 1, nullptr, nullptr, pl.c, pl.crows, pl.ldq, b.A, b.idx,
                             b.scale, seed, fit, s));
     if (o.sketch == TLS_SKETCH_LEVERAGE) {
-      TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, b.R, b.G, b.R1, b.R2, b.status + 2, s));
+      TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 1, b.R, b.G, b.R1, b.R2, b.status + 2, s));
       TLS_CHECK(launch_triinv(b.R, q, p, b.M0, b.Mt0, nullptr, b.status + 3, s));
       TLS_CHECK(launch_jl_omega(b.M0, p, pl.k, o.jl_kind, b.Pi, b.Om, seed, fit, s));
       TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.Om, p, p, pl.k, invB, b.Omhat, ctx->tw, nullptr, s));
@@ -357,7 +357,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
                               nullptr, nullptr, seed, fit, s));
     }
   }
-  TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, b.R, b.G, b.R1, b.R2, b.status, s));
+  TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 3, b.R, b.G, b.R1, b.R2, b.status, s));
   TLS_CHECK(launch_triinv(b.R, q, p, b.M, b.Mt, b.phi0, b.status + 1, s));
   hipLaunchKernelGGL(diag_minmax_kernel, dim3(1), dim3(64), 0, s, b.R, q, p, b.dminmax);
   if (!o.warm_start) {
@@ -455,7 +455,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   }
   for (int i = 0; i < p; ++i)
     if (!isfinite(coef[i])) return TLS_EINVAL;
-  if ((ho->status[0] & 6) || (ho->status[1] & 4)) return TLS_ERANK;
+  if ((ho->status[0] & 6) || (ho->status[1] & 4) || istop == 4) return TLS_ERANK;
   if (istop == 7) return TLS_ENOCONV;
   return TLS_OK;
 }
@@ -722,24 +722,24 @@ tls_status tls_op_gather(tls_ctx* ctx, const double* d_y, int64_t n, int32_t p, 
 
 tls_status tls_op_qr(tls_ctx* ctx, double* d_A, int32_t crows, int32_t q, int32_t ldq, double* d_R,
                      int32_t* status_out, void* stream) {
-  if (!ctx || !d_A || !d_R || q < 1 || crows % 4 || ldq % 16 || q > ldq || crows < 4)
+  if (!ctx || !d_A || !d_R || q < 1 || crows % 16 || ldq % 16 || q > ldq || crows < 16)
     return TLS_EINVAL;
   hipSetDevice(ctx->device);
   hipStream_t s = pick_stream(ctx, stream);
   Arena a;
-  a.take<double>(static_cast<size_t>(ldq) * ldq + 2 * static_cast<size_t>(q) * q);
+  a.take<double>(qr_scratch_doubles(crows, q, ldq));
   a.take<double>(static_cast<size_t>(q) * q);
   a.take<double>(static_cast<size_t>(q) * q);
   a.take<int>(4);
   TLS_CHECK(ensure_ws(ctx, a.need + 256));
   a.need = 0;
   a.base = static_cast<char*>(ctx->ws);
-  double* G = a.take<double>(static_cast<size_t>(ldq) * ldq + 2 * static_cast<size_t>(q) * q);
+  double* G = a.take<double>(qr_scratch_doubles(crows, q, ldq));
   double* R1 = a.take<double>(static_cast<size_t>(q) * q);
   double* R2 = a.take<double>(static_cast<size_t>(q) * q);
   int* dst = a.take<int>(4);
   TLS_CHECK(hipMemsetAsync(dst, 0, 4 * sizeof(int), s));
-  TLS_CHECK(launch_qr(d_A, crows, q, ldq, q, d_R, G, R1, R2, dst, s));
+  TLS_CHECK(launch_qr(d_A, crows, q, ldq, q, 3, d_R, G, R1, R2, dst, s));
   int hst[4];
   TLS_CHECK(hipMemcpyAsync(hst, dst, sizeof(hst), hipMemcpyDeviceToHost, s));
   TLS_CHECK(hipStreamSynchronize(s));

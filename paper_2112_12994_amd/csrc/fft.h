@@ -19,6 +19,16 @@
 
 namespace tls {
 
+// LDS index swizzle: one 256-byte LDS row holds 16 complex doubles (32
+// complex floats); XOR-ing the column with the row number spreads both
+// power-of-two strides (small-span passes) and bit-reversed scatters across
+// all banks.  A bijection on [0, N) for N >= one row.
+template <typename T>
+__device__ __forceinline__ int swz(int i) {
+  constexpr int LG = sizeof(cx<T>) == 16 ? 4 : 5;
+  return i ^ ((i >> LG) & ((1 << LG) - 1));
+}
+
 template <typename T, bool INV>
 __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tab, int e, int lgL) {
   cx<T> w = tab[e << (LG_BMAX - lgL)];
@@ -35,7 +45,7 @@ __device__ __forceinline__ void dit_pass3(cx<T>* s, const cx<T>* __restrict__ ta
     const int base = ((q >> lgh) << (lgh + 3)) + r;
     cx<T> a[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = s[base + k * h];
+    for (int k = 0; k < 8; ++k) a[k] = s[swz<T>(base + k * h)];
     const cx<T> w1 = twiddle<T, INV>(tab, r, lgh + 1);
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
@@ -66,7 +76,7 @@ __device__ __forceinline__ void dit_pass3(cx<T>* s, const cx<T>* __restrict__ ta
       a[k] = cadd(a[k], b);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s[base + k * h] = a[k];
+    for (int k = 0; k < 8; ++k) s[swz<T>(base + k * h)] = a[k];
   }
 }
 
@@ -78,7 +88,7 @@ __device__ __forceinline__ void dit_pass2(cx<T>* s, const cx<T>* __restrict__ ta
     const int base = ((q >> lgh) << (lgh + 2)) + r;
     cx<T> a[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a[k] = s[base + k * h];
+    for (int k = 0; k < 4; ++k) a[k] = s[swz<T>(base + k * h)];
     const cx<T> w1 = twiddle<T, INV>(tab, r, lgh + 1);
 #pragma unroll
     for (int k = 0; k < 4; k += 2) {
@@ -95,7 +105,7 @@ __device__ __forceinline__ void dit_pass2(cx<T>* s, const cx<T>* __restrict__ ta
     a[3] = csub(a[1], b);
     a[1] = cadd(a[1], b);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s[base + k * h] = a[k];
+    for (int k = 0; k < 4; ++k) s[swz<T>(base + k * h)] = a[k];
   }
 }
 
@@ -105,10 +115,10 @@ __device__ __forceinline__ void dit_pass1(cx<T>* s, const cx<T>* __restrict__ ta
   for (int q = threadIdx.x; q < N / 2; q += NT) {
     const int r = q & (h - 1);
     const int base = ((q >> lgh) << (lgh + 1)) + r;
-    const cx<T> a0 = s[base];
-    const cx<T> b = cmul(s[base + h], twiddle<T, INV>(tab, r, lgh + 1));
-    s[base] = cadd(a0, b);
-    s[base + h] = csub(a0, b);
+    const cx<T> a0 = s[swz<T>(base)];
+    const cx<T> b = cmul(s[swz<T>(base + h)], twiddle<T, INV>(tab, r, lgh + 1));
+    s[swz<T>(base)] = cadd(a0, b);
+    s[swz<T>(base + h)] = csub(a0, b);
   }
 }
 
@@ -121,7 +131,7 @@ __device__ __forceinline__ void dif_pass3(cx<T>* s, const cx<T>* __restrict__ ta
     const int base = ((q >> lgh) << (lgh + 3)) + r;
     cx<T> a[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = s[base + k * h];
+    for (int k = 0; k < 8; ++k) a[k] = s[swz<T>(base + k * h)];
     cx<T> w3[4];
     w3[0] = twiddle<T, INV>(tab, r, lgh + 3);
     w3[1] = twiddle<T, INV>(tab, r + h, lgh + 3);
@@ -152,7 +162,7 @@ __device__ __forceinline__ void dif_pass3(cx<T>* s, const cx<T>* __restrict__ ta
       a[k + 1] = cmul(t, w1);
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s[base + k * h] = a[k];
+    for (int k = 0; k < 8; ++k) s[swz<T>(base + k * h)] = a[k];
   }
 }
 
@@ -164,7 +174,7 @@ __device__ __forceinline__ void dif_pass2(cx<T>* s, const cx<T>* __restrict__ ta
     const int base = ((q >> lgh) << (lgh + 2)) + r;
     cx<T> a[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a[k] = s[base + k * h];
+    for (int k = 0; k < 4; ++k) a[k] = s[swz<T>(base + k * h)];
     const cx<T> w2 = twiddle<T, INV>(tab, r, lgh + 2);
     const cx<T> w2b = rot90<T, INV>(w2);
     cx<T> t = csub(a[0], a[2]);
@@ -181,7 +191,7 @@ __device__ __forceinline__ void dif_pass2(cx<T>* s, const cx<T>* __restrict__ ta
       a[k + 1] = cmul(t, w1);
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s[base + k * h] = a[k];
+    for (int k = 0; k < 4; ++k) s[swz<T>(base + k * h)] = a[k];
   }
 }
 
@@ -191,14 +201,15 @@ __device__ __forceinline__ void dif_pass1(cx<T>* s, const cx<T>* __restrict__ ta
   for (int q = threadIdx.x; q < N / 2; q += NT) {
     const int r = q & (h - 1);
     const int base = ((q >> lgh) << (lgh + 1)) + r;
-    const cx<T> a0 = s[base], a1 = s[base + h];
-    s[base] = cadd(a0, a1);
-    s[base + h] = cmul(csub(a0, a1), twiddle<T, INV>(tab, r, lgh + 1));
+    const cx<T> a0 = s[swz<T>(base)], a1 = s[swz<T>(base + h)];
+    s[swz<T>(base)] = cadd(a0, a1);
+    s[swz<T>(base + h)] = cmul(csub(a0, a1), twiddle<T, INV>(tab, r, lgh + 1));
   }
 }
 
-// Full transforms.  Callers synchronise before (input written by other
-// threads); the transforms end with a barrier so results are visible.
+// Full transforms on an LDS array addressed through swz<T>().  Callers
+// synchronise before (input written by other threads) and index the array
+// through swz<T>() too; the transforms end with a barrier.
 template <typename T, bool INV, int LGN, int NT>
 __device__ __forceinline__ void fft_dit(cx<T>* s, const cx<T>* __restrict__ tab) {
   constexpr int N = 1 << LGN;

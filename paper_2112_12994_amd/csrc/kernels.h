@@ -63,8 +63,13 @@ hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, 
 // QR of the sketch and triangular helpers
 // rank_cols: leading columns whose breakdown or tiny pivot means rank
 // deficiency (the sketch [S X | S b] passes p: b may lie in the range of X).
-hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, double* R, double* G,
-                     double* R1, double* R2, int* status, hipStream_t st);
+// A: crows x ldq row-major, crows % 16 == 0.  G: qr_scratch_doubles() doubles.
+size_t qr_scratch_doubles(int crows, int q, int ldq);
+// sweeps: 3 = shifted Cholesky QR then two refining sweeps (R accurate to
+// O(u) orthogonality); 1 = the shifted sweep alone (a rougher R, enough for
+// approximate leverage scores).
+hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sweeps, double* R,
+                     double* G, double* R1, double* R2, int* status, hipStream_t st);
 hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, double* phi0,
                          int* status, hipStream_t st);
 

@@ -13,7 +13,8 @@
 //
 // Stopping (atol = btol = tol): ||A^T r|| <= tol ||A|| ||r|| (istop 2) or
 // ||r|| <= tol ||r0|| + tol ||A|| ||z|| (istop 1); alpha or beta = 0 (istop 3,
-// exact); iteration limit (istop 7).
+// exact); a non-finite alpha or beta (istop 4, the last finite iterate is
+// kept); iteration limit (istop 7).
 #include <math.h>
 
 #include "fft.h"
@@ -23,7 +24,39 @@ namespace tls {
 
 namespace {
 
-template <int LGN, int NT, typename TS>
+// out[r] = sum_{c in [lo(r), p)} Mrow[r][c] x[c] for the rows r of an upper
+// (lo(r) = r) or lower (lo = 0, hi(r) = r + 1) triangular p x p row-major
+// matrix; one wavefront per row, four rows in flight, lanes over columns.
+// Results go to out[r] (lane 0 of the owning wave) via the callback.
+template <int NT, bool UPPER, typename F>
+__device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, int p,
+                                              const double* __restrict__ x, F&& emit) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  for (int r0 = wid * 4; r0 < p; r0 += NW * 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + u;
+      if (r < p) {
+        const double* row = Mrow + static_cast<size_t>(r) * p;
+        const int lo = UPPER ? r : 0, hi = UPPER ? p : r + 1;
+        for (int c = lo + lane; c < hi; c += 64) acc[u] += row[c] * x[c];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = wave_sum(acc[u]);
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (r0 + u < p) emit(r0 + u, acc[u]);
+    }
+  }
+}
+
+// MLDS: M (p <= 128) is staged once into LDS (rows padded to an odd length)
+// and every product with M or M^T reads it there.
+template <int LGN, int NT, typename TS, bool MLDS>
 __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restrict__ st,
                                                        const double* __restrict__ g,
                                                        const double* __restrict__ M,
@@ -40,25 +73,44 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
   extern __shared__ double smem[];
   double* sg = smem;
   double* sv = sg + p;
+  double* sM = sv + p;  // MLDS: p x ldm
+  const int ldm = p | 1;
   __shared__ double red[NT / 64];
   if (st->done) return;
   const int tid = threadIdx.x;
   const bool init = st->phase == 0;
   const double tol = st->tol;
+  if constexpr (MLDS) {
+    for (int e = tid; e < p * p; e += NT) sM[(e / p) * ldm + e % p] = M[e];
+  }
 
   const double beta = sqrt(g[p]);
   const double invbeta = beta > 0.0 ? 1.0 / beta : 0.0;
   for (int i = tid; i < p; i += NT) sg[i] = g[i] * invbeta;
   __syncthreads();
 
-  // v~ = M^T (X^T u) - beta v   (M row-major upper: column j holds M[i][j], i <= j)
+  // v~ = M^T (X^T u) - beta v: row j of M^T (= column j of M) is Mt[j][0..j]
   double hsq = 0.0;
-  for (int j = tid; j < p; j += NT) {
-    double acc = 0.0;
-    for (int i = 0; i <= j; ++i) acc += M[static_cast<size_t>(i) * p + j] * sg[i];
-    const double h = init ? acc : acc - beta * v[j];
-    sv[j] = h;
-    hsq += h * h;
+  if constexpr (MLDS) {
+    for (int j = tid; j < p; j += NT) {
+      double a0 = 0.0, a1 = 0.0;
+      int i = 0;
+      for (; i + 1 <= j; i += 2) {
+        a0 += sM[i * ldm + j] * sg[i];
+        a1 += sM[(i + 1) * ldm + j] * sg[i + 1];
+      }
+      if (i <= j) a0 += sM[i * ldm + j] * sg[i];
+      const double acc = a0 + a1;
+      const double h = init ? acc : acc - beta * v[j];
+      sv[j] = h;
+      hsq += h * h;
+    }
+  } else {
+    tri_gemv_rows<NT, false>(Mt, p, sg, [&](int j, double acc) {
+      const double h = init ? acc : acc - beta * v[j];
+      sv[j] = h;
+      hsq += h * h;
+    });
   }
   const double alpha = sqrt(block_sum<NT>(hsq, red));
   const double invalpha = alpha > 0.0 ? 1.0 / alpha : 0.0;
@@ -88,6 +140,13 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
       done = true;
       istop = 0;
     }
+  } else if (!isfinite(alpha) || !isfinite(beta)) {
+    // numerical breakdown: keep the last finite iterate
+    done = true;
+    istop = 4;
+    iter += 1;
+    rnorm = st->rnorm;
+    arnorm = st->arnorm;
   } else {
     anorm2 += alpha_prev * alpha_prev + beta * beta;
     const double rho = hypot(rhobar, beta);
@@ -128,15 +187,24 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
 
   if (!done) {
     // q = M v_new into sg, then its packed spectrum scaled by 1/B.
-    for (int i = tid; i < p; i += NT) {
-      double acc = 0.0;
-      for (int j = i; j < p; ++j) acc += Mt[static_cast<size_t>(j) * p + i] * sv[j];
-      sg[i] = acc;
+    if constexpr (MLDS) {
+      for (int i = tid; i < p; i += NT) {
+        double a0 = 0.0, a1 = 0.0;
+        int j = i;
+        for (; j + 1 < p; j += 2) {
+          a0 += sM[i * ldm + j] * sv[j];
+          a1 += sM[i * ldm + j + 1] * sv[j + 1];
+        }
+        if (j < p) a0 += sM[i * ldm + j] * sv[j];
+        sg[i] = a0 + a1;
+      }
+    } else {
+      tri_gemv_rows<NT, true>(M, p, sv, [&](int i, double acc) { sg[i] = acc; });
     }
     __syncthreads();
     for (int t = tid; t < N; t += NT) {
       const int i0 = 2 * t;
-      s[t] = {i0 < p ? sg[i0] : 0.0, i0 + 1 < p ? sg[i0 + 1] : 0.0};
+      s[swz<double>(t)] = {i0 < p ? sg[i0] : 0.0, i0 + 1 < p ? sg[i0 + 1] : 0.0};
     }
     __syncthreads();
     fft_dif<double, false, LGN, NT>(s, tab);
@@ -144,7 +212,7 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
     for (int k = tid; k <= N / 2; k += NT) {
       const cx<double> wk = twiddle<double, false>(tab, k, LGN + 1);
       cx<double> Xk, Xnk;
-      rfft_post(s[bitrev(k, LGN)], s[bitrev((N - k) & (N - 1), LGN)], wk, Xk, Xnk);
+      rfft_post(s[swz<double>(bitrev(k, LGN))], s[swz<double>(bitrev((N - k) & (N - 1), LGN))], wk, Xk, Xnk);
       Xk = cscale(Xk, invB);
       Xnk = cscale(Xnk, invB);
       if (k == 0) {
@@ -156,10 +224,15 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
     }
   } else {
     // phi = phi0 + M z
-    for (int i = tid; i < p; i += NT) {
-      double acc = 0.0;
-      for (int j = i; j < p; ++j) acc += Mt[static_cast<size_t>(j) * p + i] * z[j];
-      phi[i] = phi0[i] + acc;
+    __syncthreads();
+    if constexpr (MLDS) {
+      for (int i = tid; i < p; i += NT) {
+        double acc = 0.0;
+        for (int j = i; j < p; ++j) acc += sM[i * ldm + j] * z[j];
+        phi[i] = phi0[i] + acc;
+      }
+    } else {
+      tri_gemv_rows<NT, true>(M, p, z, [&](int i, double acc) { phi[i] = phi0[i] + acc; });
     }
   }
   if (tid == 0) {
@@ -186,10 +259,18 @@ hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, cons
                     double* v, double* w, double* z, const double* phi0, double* phi, void* Vhat,
                     const Twiddles& tw, hipStream_t stream) {
   constexpr int NT = 256;
-  const size_t shm = 2 * static_cast<size_t>(p) * sizeof(double);
-  hipLaunchKernelGGL((lsqr_step_kernel<LGN, NT, TS>), dim3(1), dim3(NT), shm, stream, p, st, g, M,
-                     Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
-                     static_cast<const cx<double>*>(tw.d64));
+  const size_t small = 2 * static_cast<size_t>(p) * sizeof(double);
+  const size_t with_m = small + static_cast<size_t>(p) * (p | 1) * sizeof(double);
+  const size_t lds_static = static_cast<size_t>(1 << LGN) * 16 + 64;
+  if (p <= 128 && with_m + lds_static <= 160 * 1024) {
+    hipLaunchKernelGGL((lsqr_step_kernel<LGN, NT, TS, true>), dim3(1), dim3(NT), with_m, stream, p,
+                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
+                       static_cast<const cx<double>*>(tw.d64));
+  } else {
+    hipLaunchKernelGGL((lsqr_step_kernel<LGN, NT, TS, false>), dim3(1), dim3(NT), small, stream, p,
+                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
+                       static_cast<const cx<double>*>(tw.d64));
+  }
   return hipGetLastError();
 }
 

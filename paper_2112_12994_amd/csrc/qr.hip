@@ -5,6 +5,9 @@
 // A <- A R2^{-1}; G = A^T A -> R3; R = R3 R2 R1.  The shift
 // s = 11 (c q + q (q + 1)) u trace(A^T A) keeps the first Cholesky factorable
 // up to condition numbers near 1/u; the later sweeps restore orthogonality.
+// Near that limit the first sweep can leave kappa(A R1^{-1}) ~ 1e8, where the
+// unshifted Gram matrix is on the edge of breakdown; a later sweep whose
+// Cholesky breaks down is therefore redone with the shift (status bit 8).
 // Every Gram matrix is a dense contraction over the c rows, computed on the
 // FP64 matrix cores (V_MFMA_F64_16X16X4_F64).
 //
@@ -66,20 +69,20 @@ __global__ __launch_bounds__(NT) void chol_kernel(const double* __restrict__ G, 
   for (int i = threadIdx.x; i < q; i += NT) tr += G[static_cast<size_t>(i) * ldq + i];
   tr = block_sum<NT>(tr, red);
   if (threadIdx.x == 0) {
-    s_shift = shift ? 11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) *
-                          0x1p-53 * tr
-                    : 0.0;
+    s_shift = 11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) * 0x1p-53 * tr;
     s_floor = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
   }
+  bool failed = false;
+  for (int attempt = (shift == 1 ? 1 : 0); attempt < 2; ++attempt) {
+  failed = false;
   for (int e = threadIdx.x; e < q * q; e += NT) {
     const int i = e / q, k = e % q;
     R[e] = (k >= i) ? G[static_cast<size_t>(i) * ldq + k] : 0.0;
   }
   __syncthreads();
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0 && attempt)
     for (int i = 0; i < q; ++i) R[static_cast<size_t>(i) * q + i] += s_shift;
   __syncthreads();
-  bool failed = false;
   for (int j = 0; j < q; ++j) {
     double d = R[static_cast<size_t>(j) * q + j];
     if (!(d > s_floor)) {
@@ -99,6 +102,12 @@ __global__ __launch_bounds__(NT) void chol_kernel(const double* __restrict__ G, 
       if (kk >= ii) R[static_cast<size_t>(ii) * q + kk] -= rj[ii] * rj[kk];
     }
     __syncthreads();
+  }
+  if (!failed || shift != 2 || attempt == 1) {
+    if (attempt == 1 && shift == 2 && threadIdx.x == 0) atomicOr(status, 8);
+    break;
+  }
+  __syncthreads();
   }
   if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
 }
@@ -202,45 +211,460 @@ __global__ __launch_bounds__(NT) void triinv_kernel(const double* __restrict__ R
   }
 }
 
+// ---- LDS-resident variants for q <= 128 (the whole q x q matrix in LDS) ----
+
+// Cholesky of G[:q,:q] (+ shift) with the trailing matrix kept symmetric in
+// LDS: step j subtracts S[i][j] S[j][k] / S[j][j] from the trailing square
+// (one barrier per column); row j is scaled by 1/sqrt(S[j][j]) at the end.
+// shift_mode: 0 never shift, 1 always shift, 2 shift only when the unshifted
+// factorisation breaks down (then status |= 8; a breakdown of the shifted
+// retry sets fail_bit).
+template <int NT>
+__global__ __launch_bounds__(NT) void chol_lds_kernel(const double* __restrict__ G, int ldq, int q,
+                                                      int crows, int shift_mode,
+                                                      double* __restrict__ R,
+                                                      int* __restrict__ status, int fail_bit,
+                                                      int rank_cols) {
+  extern __shared__ double S[];
+  __shared__ double red[NT / 64];
+  __shared__ int s_fail;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < q; i += NT) tr += G[static_cast<size_t>(i) * ldq + i];
+  tr = block_sum<NT>(tr, red);
+  const double shift_amount =
+      11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) * 0x1p-53 * tr;
+  const double floor_ = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  constexpr int TY = NT / 16;
+  for (int attempt = (shift_mode == 1 ? 1 : 0); attempt < 2; ++attempt) {
+    const double sh = attempt ? shift_amount : 0.0;
+    for (int e = threadIdx.x; e < q * q; e += NT) {
+      const int i = e / q, k = e % q;
+      S[e] = G[static_cast<size_t>(i) * ldq + k] + (i == k ? sh : 0.0);
+    }
+    if (threadIdx.x == 0) s_fail = 0;
+    __syncthreads();
+    for (int j = 0; j < q; ++j) {
+      double d = S[j * q + j];
+      if (!(d > floor_)) {
+        if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
+        d = floor_;
+      }
+      const double invd = 1.0 / d;
+      const double* rowj = S + j * q;
+      for (int i = j + 1 + ty; i < q; i += TY) {
+        const double f = rowj[i] * invd;
+        double* rowi = S + i * q;
+        for (int k = j + 1 + tx; k < q; k += 16) rowi[k] -= f * rowj[k];
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) S[j * q + j] = d;  // the floored pivot, read again only below
+    }
+    __syncthreads();
+    const int failed = s_fail;
+    if (!failed || shift_mode != 2 || attempt == 1) {
+      if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
+      if (attempt == 1 && shift_mode == 2 && threadIdx.x == 0) atomicOr(status, 8);
+      break;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < q * q; e += NT) {
+    const int i = e / q, k = e % q;
+    const double di = sqrt(S[i * q + i]);
+    R[e] = k < i ? 0.0 : (k == i ? di : S[e] / di);
+  }
+}
+
+// ---- register-tiled variants for q <= 16 QT (QT <= 8) ---------------------
+// Thread (tx, ty) of 256 owns the elements (ty + 16 a, tx + 16 b) of the q x q
+// matrix in registers; the row a step needs is published through a
+// double-buffered LDS row, so a step costs one barrier and register FMAs.
+
+// Cholesky G[:q,:q] (+ shift) = R^T R; shift_mode as in chol_lds_kernel.
+template <int QT>
+__global__ __launch_bounds__(256) void chol_reg_kernel(const double* __restrict__ G, int ldq, int q,
+                                                       int crows, int shift_mode,
+                                                       double* __restrict__ R,
+                                                       int* __restrict__ status, int fail_bit,
+                                                       int rank_cols) {
+  __shared__ double pub[2][16 * QT];
+  __shared__ double red[4];
+  __shared__ int s_fail;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < q; i += 256) tr += G[static_cast<size_t>(i) * ldq + i];
+  tr = block_sum<256>(tr, red);
+  const double shift_amount =
+      11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) * 0x1p-53 * tr;
+  const double floor_ = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
+  double reg[QT][QT];
+  for (int attempt = (shift_mode == 1 ? 1 : 0); attempt < 2; ++attempt) {
+    const double sh = attempt ? shift_amount : 0.0;
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int b = 0; b < QT; ++b) {
+        const int i = ty + 16 * a, k = tx + 16 * b;
+        reg[a][b] = (i < q && k < q) ? G[static_cast<size_t>(i) * ldq + k] + (i == k ? sh : 0.0) : 0.0;
+      }
+    if (threadIdx.x == 0) s_fail = 0;
+    __syncthreads();
+    for (int j = 0; j < q; ++j) {
+      double* pj = pub[j & 1];
+      if (ty == (j & 15)) {
+#pragma unroll
+        for (int a = 0; a < QT; ++a)
+          if (a == (j >> 4))
+#pragma unroll
+            for (int b = 0; b < QT; ++b) pj[tx + 16 * b] = reg[a][b];
+      }
+      __syncthreads();
+      double d = pj[j];
+      if (!(d > floor_)) {
+        if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
+        d = floor_;
+      }
+      const double invd = 1.0 / d;
+      const double isd = 1.0 / sqrt(d);
+      for (int k = threadIdx.x; k < q; k += 256)
+        R[static_cast<size_t>(j) * q + k] = k < j ? 0.0 : (k == j ? sqrt(d) : pj[k] * isd);
+      double fi[QT], fk[QT];
+#pragma unroll
+      for (int a = 0; a < QT; ++a) {
+        const int i = ty + 16 * a;
+        fi[a] = (i > j && i < q) ? pj[i] * invd : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < QT; ++b) {
+        const int k = tx + 16 * b;
+        fk[b] = (k > j && k < q) ? pj[k] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+#pragma unroll
+        for (int b = 0; b < QT; ++b) reg[a][b] -= fi[a] * fk[b];
+    }
+    __syncthreads();
+    const int failed = s_fail;
+    if (!failed || shift_mode != 2 || attempt == 1) {
+      if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
+      if (attempt == 1 && shift_mode == 2 && threadIdx.x == 0) atomicOr(status, 8);
+      break;
+    }
+    __syncthreads();
+  }
+}
+
+// M = R[:n,:n]^{-1} (upper; row-major, leading dimension ldm, zero elsewhere
+// in the ldm x ldm block): M = I, then for i = n-1 .. 0, row i of M is
+// divided by R_ii and R[r][i] times it is subtracted from every row r < i.
+template <int QT>
+__global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restrict__ R, int ldr, int n,
+                                                         double* __restrict__ M, int ldm) {
+  extern __shared__ double Rs[];  // n x (n + 1)
+  __shared__ double pub[2][16 * QT];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int ld = n + 1;
+  for (int e = threadIdx.x; e < n * n; e += 256) Rs[(e / n) * ld + e % n] = R[static_cast<size_t>(e / n) * ldr + e % n];
+  double reg[QT][QT];
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < QT; ++b) reg[a][b] = (ty + 16 * a == tx + 16 * b && ty + 16 * a < n) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    double* pi = pub[i & 1];
+    const double inv = 1.0 / Rs[i * ld + i];
+    if (ty == (i & 15)) {
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+        if (a == (i >> 4))
+#pragma unroll
+          for (int b = 0; b < QT; ++b) {
+            reg[a][b] *= inv;
+            pi[tx + 16 * b] = reg[a][b];
+          }
+    }
+    __syncthreads();
+    double ri[QT], mc[QT];
+#pragma unroll
+    for (int a = 0; a < QT; ++a) {
+      const int r = ty + 16 * a;
+      ri[a] = r < i ? Rs[r * ld + i] : 0.0;
+    }
+#pragma unroll
+    for (int b = 0; b < QT; ++b) {
+      const int c = tx + 16 * b;
+      mc[b] = c < n ? pi[c] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int b = 0; b < QT; ++b) reg[a][b] -= ri[a] * mc[b];
+  }
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < QT; ++b) {
+      const int r = ty + 16 * a, c = tx + 16 * b;
+      if (r < ldm && c < ldm) M[static_cast<size_t>(r) * ldm + c] = (r < n && c < n) ? reg[a][b] : 0.0;
+    }
+  // rows / columns of the ldm block beyond 16 QT (only when ldm > 16 QT)
+  for (int e = threadIdx.x; e < ldm * ldm; e += 256) {
+    const int r = e / ldm, c = e % ldm;
+    if (r >= 16 * QT || c >= 16 * QT) M[e] = 0.0;
+  }
+}
+
+// M = R[:n,:n]^{-1} (upper, row-major with leading dimension ldm, zero
+// elsewhere in the ldm x ldm block), rows computed bottom-up in LDS.
+template <int NT>
+__global__ __launch_bounds__(NT) void triinv_lds_kernel(const double* __restrict__ R, int ldr, int n,
+                                                        double* __restrict__ M, int ldm) {
+  extern __shared__ double S[];  // n x n, then one staged row of R
+  double* ri = S + n * n;
+  for (int e = threadIdx.x; e < n * n; e += NT) S[e] = 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    for (int k = i + threadIdx.x; k < n; k += NT) ri[k] = R[static_cast<size_t>(i) * ldr + k];
+    __syncthreads();
+    const double inv = 1.0 / ri[i];
+    for (int j = i + threadIdx.x; j < n; j += NT) {
+      double a0 = (j == i) ? 1.0 : 0.0, a1 = 0.0;
+      int k = i + 1;
+      for (; k + 1 <= j; k += 2) {
+        a0 -= ri[k] * S[k * n + j];
+        a1 -= ri[k + 1] * S[(k + 1) * n + j];
+      }
+      if (k <= j) a0 -= ri[k] * S[k * n + j];
+      S[i * n + j] = (a0 + a1) * inv;
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < ldm * ldm; e += NT) {
+    const int i = e / ldm, j = e % ldm;
+    M[e] = (i < n && j < n) ? S[i * n + j] : 0.0;
+  }
+}
+
+// A <- A R^{-1} on the first q columns, 16 rows per wavefront (rows are
+// independent).  Blocked by 16 columns as in LAPACK's triangular solve: the
+// 16 x 16 diagonal block by forward substitution (one lane per row), then the
+// trailing columns A[:, K] -= X[:, J] R[J, K] on the FP64 matrix cores.
+// Backward stable, unlike a product with an explicitly inverted R.
+__global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, int ldq, int q,
+                                                       const double* __restrict__ R) {
+  extern __shared__ double T[];  // 16 x (ldq + 1) rows of A, then 16 x ldq rows of R
+  const int ld = ldq + 1;
+  double* Rp = T + 16 * ld;
+  const int lane = threadIdx.x;
+  const size_t r0 = static_cast<size_t>(blockIdx.x) * 16;
+  for (int e = lane; e < 16 * ldq; e += 64) T[(e / ldq) * ld + e % ldq] = A[(r0 + e / ldq) * ldq + e % ldq];
+  const int nt = (q + 15) / 16;
+  for (int J = 0; J < nt; ++J) {
+    const int j0 = J * 16;
+    // rows j0 .. j0+15 of R (zero outside q x q)
+    for (int e = lane; e < 16 * ldq; e += 64) {
+      const int rr = j0 + e / ldq, cc = e % ldq;
+      Rp[e] = (rr < q && cc < q) ? R[static_cast<size_t>(rr) * q + cc] : 0.0;
+    }
+    __syncthreads();
+    if (lane < 16) {
+      double* row = T + lane * ld;
+      for (int jj = 0; jj < 16 && j0 + jj < q; ++jj) {
+        const double* rj = Rp + jj * ldq;
+        const double x = row[j0 + jj] / rj[j0 + jj];
+        row[j0 + jj] = x;
+        for (int kk = jj + 1; kk < 16 && j0 + kk < q; ++kk) row[j0 + kk] -= x * rj[j0 + kk];
+      }
+    }
+    __syncthreads();
+    for (int K = J + 1; K < nt; ++K) {
+      const int k0 = K * 16;
+      d4 acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = T[(4 * v + (lane >> 4)) * ld + k0 + (lane & 15)];
+#pragma unroll
+      for (int k4 = 0; k4 < 16; k4 += 4) {
+        const double xa = -T[(lane & 15) * ld + j0 + k4 + (lane >> 4)];
+        const double rb = Rp[(k4 + (lane >> 4)) * ldq + k0 + (lane & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, rb, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[(4 * v + (lane >> 4)) * ld + k0 + (lane & 15)] = acc[v];
+    }
+    __syncthreads();
+  }
+  for (int e = lane; e < 16 * ldq; e += 64) A[(r0 + e / ldq) * ldq + e % ldq] = T[(e / ldq) * ld + e % ldq];
+}
+
+// Aout = Ain * M on the first ldq columns (M upper triangular, ldq x ldq,
+// zero-padded): one 16x16 output tile per wavefront on the FP64 matrix cores.
+__global__ __launch_bounds__(64) void gemm_upper_kernel(const double* __restrict__ Ain, int ldq,
+                                                        const double* __restrict__ M,
+                                                        double* __restrict__ Aout) {
+  const int tiles_n = ldq / 16;
+  const int tr = blockIdx.x / tiles_n, tc = blockIdx.x % tiles_n;
+  const int lane = threadIdx.x;
+  const int r0 = tr * 16, c0 = tc * 16;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const double* arow = Ain + static_cast<size_t>(r0 + (lane & 15)) * ldq;
+  const int kend = c0 + 16;  // M[i][j] = 0 for i > j
+  for (int k0 = 0; k0 < kend; k0 += 4) {
+    const double a = arow[k0 + (lane >> 4)];
+    const double b = M[static_cast<size_t>(k0 + (lane >> 4)) * ldq + c0 + (lane & 15)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+    Aout[static_cast<size_t>(r0 + 4 * v + (lane >> 4)) * ldq + c0 + (lane & 15)] = acc[v];
+}
+
 // status |= 4 when min|R_ii| <= k u max|R_ii| over the first k = rank_cols
 // diagonal entries (numerical rank of the leading columns below k).
-__global__ void rank_test_kernel(const double* __restrict__ R, int q, int rank_cols,
-                                 int* __restrict__ status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(64) void rank_test_kernel(const double* __restrict__ R, int q,
+                                                       int rank_cols, int* __restrict__ status) {
   double a = 0.0, b = INFINITY;
-  for (int i = 0; i < rank_cols; ++i) {
+  for (int i = threadIdx.x; i < rank_cols; i += 64) {
     const double d = fabs(R[static_cast<size_t>(i) * q + i]);
     a = fmax(a, d);
     b = fmin(b, d);
   }
-  if (!(b > static_cast<double>(rank_cols) * 0x1p-53 * a)) atomicOr(status, 4);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a = fmax(a, __shfl_xor(a, off, 64));
+    b = fmin(b, __shfl_xor(b, off, 64));
+  }
+  if (threadIdx.x == 0 && !(b > static_cast<double>(rank_cols) * 0x1p-53 * a)) atomicOr(status, 4);
+}
+
+// Tail of the preconditioner set-up once M = R[:p,:p]^{-1} exists: Mt = M^T,
+// phi0 = M R[:p, p], rank test on R[:p,:p] (status |= 4).
+template <int NT>
+__global__ __launch_bounds__(NT) void triinv_finish_kernel(const double* __restrict__ R, int q,
+                                                           int p, const double* __restrict__ M,
+                                                           double* __restrict__ Mt,
+                                                           double* __restrict__ phi0,
+                                                           int* __restrict__ status) {
+  for (int e = threadIdx.x; e < p * p; e += NT) {
+    const int i = e / p, j = e % p;
+    Mt[static_cast<size_t>(j) * p + i] = M[e];
+  }
+  if (phi0 && q > p) {
+    for (int i = threadIdx.x; i < p; i += NT) {
+      double acc = 0.0;
+      for (int j = i; j < p; ++j)
+        acc += M[static_cast<size_t>(i) * p + j] * R[static_cast<size_t>(j) * q + p];
+      phi0[i] = acc;
+    }
+  }
+  if (threadIdx.x < 64) {
+    double a = 0.0, b = INFINITY;
+    for (int i = threadIdx.x; i < p; i += 64) {
+      const double d = fabs(R[static_cast<size_t>(i) * q + i]);
+      a = fmax(a, d);
+      b = fmin(b, d);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a = fmax(a, __shfl_xor(a, off, 64));
+      b = fmin(b, __shfl_xor(b, off, 64));
+    }
+    if (threadIdx.x == 0 && status && !(b > static_cast<double>(p) * 0x1p-53 * a))
+      atomicOr(status, 4);
+  }
 }
 
 }  // namespace
 
-// G must hold ldq*ldq + 2*q*q doubles (Gram matrix, then R3 and R3 R2).
-hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, double* R, double* G,
-                     double* R1, double* R2, int* status, hipStream_t st) {
-  if (crows % 4 != 0 || ldq % 16 != 0 || q > ldq || q < 1) return hipErrorInvalidValue;
+// Scratch: G must hold ldq*ldq + 2*q*q doubles (Gram matrix, then R3 and
+// R3 R2); for q <= 128 also ldq*ldq (inverse) + crows*ldq (second copy of A)
+// beyond that, i.e. qr_scratch_doubles(crows, q, ldq) in total.
+size_t qr_scratch_doubles(int crows, int q, int ldq) {
+  return static_cast<size_t>(ldq) * ldq * 2 + 2 * static_cast<size_t>(q) * q +
+         static_cast<size_t>(crows) * ldq;
+}
+
+namespace {
+
+template <int QT>
+void chol_reg_launch(const double* G, int ldq, int q, int crows, int shift_mode, double* R,
+                     int* status, int fail_bit, int rank_cols, hipStream_t st) {
+  hipLaunchKernelGGL((chol_reg_kernel<QT>), dim3(1), dim3(256), 0, st, G, ldq, q, crows, shift_mode,
+                     R, status, fail_bit, rank_cols);
+}
+
+void chol_launch(const double* G, int ldq, int q, int crows, int shift_mode, double* R, int* status,
+                 int fail_bit, int rank_cols, hipStream_t st) {
+  const int qt = (q + 15) / 16;
+  switch (qt) {
+    case 1: chol_reg_launch<1>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    case 2: chol_reg_launch<2>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    case 3: chol_reg_launch<3>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    case 4: chol_reg_launch<4>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    case 5: chol_reg_launch<5>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    case 6: chol_reg_launch<6>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    case 7: chol_reg_launch<7>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    case 8: chol_reg_launch<8>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+    default:
+      hipLaunchKernelGGL((chol_kernel<256>), dim3(1), dim3(256), 0, st, G, ldq, q, crows, shift_mode,
+                         R, status, fail_bit, rank_cols);
+  }
+}
+
+template <int QT>
+void triinv_reg_launch(const double* R, int ldr, int n, double* M, int ldm, hipStream_t st) {
+  hipLaunchKernelGGL((triinv_reg_kernel<QT>), dim3(1), dim3(256),
+                     static_cast<size_t>(n) * (n + 1) * sizeof(double), st, R, ldr, n, M, ldm);
+}
+
+}  // namespace
+
+// Triangular inverse of R[:n,:n] into M (n <= 128: register tiles; else the
+// global-memory kernel) with leading dimension ldm >= n, zero-padded.
+hipError_t tri_inverse(const double* R, int ldr, int n, double* M, int ldm, hipStream_t st) {
+  switch ((n + 15) / 16) {
+    case 1: triinv_reg_launch<1>(R, ldr, n, M, ldm, st); break;
+    case 2: triinv_reg_launch<2>(R, ldr, n, M, ldm, st); break;
+    case 3: triinv_reg_launch<3>(R, ldr, n, M, ldm, st); break;
+    case 4: triinv_reg_launch<4>(R, ldr, n, M, ldm, st); break;
+    case 5: triinv_reg_launch<5>(R, ldr, n, M, ldm, st); break;
+    case 6: triinv_reg_launch<6>(R, ldr, n, M, ldm, st); break;
+    case 7: triinv_reg_launch<7>(R, ldr, n, M, ldm, st); break;
+    case 8: triinv_reg_launch<8>(R, ldr, n, M, ldm, st); break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sweeps, double* R,
+                     double* G, double* R1, double* R2, int* status, hipStream_t st) {
+  if (crows % 16 != 0 || ldq % 16 != 0 || q > ldq || q < 1 || sweeps < 1 || sweeps > 3)
+    return hipErrorInvalidValue;
   const int nt = ldq / 16;
   double* R3 = G + static_cast<size_t>(ldq) * ldq;
   double* T = R3 + static_cast<size_t>(q) * q;
-  double* Rs[3] = {R1, R2, R3};
-  for (int sweep = 0; sweep < 3; ++sweep) {
+  double* Rs[3] = {sweeps == 1 ? R : R1, R2, R3};
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
     hipLaunchKernelGGL(gram_kernel, dim3(nt * nt), dim3(256), 0, st, A, crows, ldq, G);
-    hipLaunchKernelGGL((chol_kernel<256>), dim3(1), dim3(256), 0, st, G, ldq, q, crows,
-                       sweep == 0 ? 1 : 0, Rs[sweep], status, sweep == 0 ? 1 : 2, rank_cols);
-    if (sweep == 2) break;
-    if (q <= 128) {
-      hipLaunchKernelGGL((trsm_kernel<64, 128>), dim3((crows + 63) / 64), dim3(64), 0, st, A,
-                         crows, ldq, q, Rs[sweep]);
+    chol_launch(G, ldq, q, crows, sweep == 0 ? 1 : 2, Rs[sweep], status, sweep == 0 ? 1 : 2,
+                rank_cols, st);
+    if (sweep == sweeps - 1) break;
+    if (ldq <= 1024) {
+      hipLaunchKernelGGL(trsm_tile_kernel, dim3(crows / 16), dim3(64),
+                         (16 * (ldq + 1) + 16 * ldq) * sizeof(double), st, A, ldq, q, Rs[sweep]);
     } else {
       hipLaunchKernelGGL(trsm_global_kernel, dim3((crows + 63) / 64), dim3(64), 0, st, A, crows,
                          ldq, q, Rs[sweep]);
     }
   }
-  hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, R3, R2, q, T);
-  hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, T, R1, q, R);
+  if (sweeps == 3) {
+    hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, R3, R2, q, T);
+    hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, T, R1, q, R);
+  } else if (sweeps == 2) {
+    hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, R2, R1, q, R);
+  }
   hipLaunchKernelGGL(rank_test_kernel, dim3(1), dim3(64), 0, st, R, q, rank_cols, status);
   return hipGetLastError();
 }
@@ -248,8 +672,15 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, double
 hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, double* phi0,
                          int* status, hipStream_t st) {
   if (p < 1 || q < p) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((triinv_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, Mt, phi0,
-                     status);
+  if (p <= 128) {
+    hipError_t e = tri_inverse(R, q, p, M, p, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((triinv_finish_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, Mt, phi0,
+                       status);
+  } else {
+    hipLaunchKernelGGL((triinv_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, Mt, phi0,
+                       status);
+  }
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(NT) void spectra_kernel(const double* __restrict__ 
   const int64_t start = static_cast<int64_t>(blk) * L;
   for (int t = threadIdx.x; t < N; t += NT) {
     const int64_t i0 = start + 2 * t;
-    s[t] = {i0 < n ? y[i0] : 0.0, i0 + 1 < n ? y[i0 + 1] : 0.0};
+    s[swz<double>(t)] = {i0 < n ? y[i0] : 0.0, i0 + 1 < n ? y[i0 + 1] : 0.0};
   }
   __syncthreads();
   fft_dif<double, false, LGN, NT>(s, tab);
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(NT) void spectra_kernel(const double* __restrict__ 
   for (int k = threadIdx.x; k <= N / 2; k += NT) {
     const cx<double> w = twiddle<double, false>(tab, k, LGN + 1);
     cx<double> Xk, Xnk;
-    rfft_post(s[bitrev(k, LGN)], s[bitrev((N - k) & (N - 1), LGN)], w, Xk, Xnk);
+    rfft_post(s[swz<double>(bitrev(k, LGN))], s[swz<double>(bitrev((N - k) & (N - 1), LGN))], w, Xk, Xnk);
     if (k == 0) {
       out[0] = {static_cast<TS>(Xk.x), static_cast<TS>(Xnk.x)};
     } else {
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict
   const double* col = cols + static_cast<size_t>(blockIdx.x) * ld;
   for (int t = threadIdx.x; t < N; t += NT) {
     const int i0 = 2 * t;
-    s[t] = {i0 < len ? col[i0] : 0.0, i0 + 1 < len ? col[i0 + 1] : 0.0};
+    s[swz<double>(t)] = {i0 < len ? col[i0] : 0.0, i0 + 1 < len ? col[i0 + 1] : 0.0};
   }
   __syncthreads();
   fft_dif<double, false, LGN, NT>(s, tab);
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict
   for (int k = threadIdx.x; k <= N / 2; k += NT) {
     const cx<double> w = twiddle<double, false>(tab, k, LGN + 1);
     cx<double> Xk, Xnk;
-    rfft_post(s[bitrev(k, LGN)], s[bitrev((N - k) & (N - 1), LGN)], w, Xk, Xnk);
+    rfft_post(s[swz<double>(bitrev(k, LGN))], s[swz<double>(bitrev((N - k) & (N - 1), LGN))], w, Xk, Xnk);
     Xk = cscale(Xk, scale);
     Xnk = cscale(Xnk, scale);
     if (k == 0) {
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
         const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
         cx<T> Zk, Znk;
         irfft_pre(cmul(yk[ip], vk), cmul(ynk[ip], vnk), w, Zk, Znk);
-        s[bitrev(k, LGN)] = Zk;
-        if (k != 0 && 2 * k != N) s[bitrev(N - k, LGN)] = Znk;
+        s[swz<T>(bitrev(k, LGN))] = Zk;
+        if (k != 0 && 2 * k != N) s[swz<T>(bitrev(N - k, LGN))] = Znk;
       }
     }
     __syncthreads();
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
 #pragma unroll
     for (int e = 0; e < NEL; ++e) {
       const int t = tid + e * NT;
-      const cx<T> z = s[t];
+      const cx<T> z = s[swz<T>(t)];
       T o0 = T(0), o1 = T(0);
       const int64_t i0 = row0 + 2 * t;
       if (2 * t >= p - 1 && i0 < m) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
         if (u_out) u_out[i0 + 1] = o1;
       }
       nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
-      if constexpr ((MODE & PM_RMV) != 0) s[t] = {o0, o1};
+      if constexpr ((MODE & PM_RMV) != 0) s[swz<T>(t)] = {o0, o1};
     }
   } else {
 #pragma unroll
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
       const T o0 = (2 * t >= p - 1 && i0 < m) ? u_in[i0] : T(0);
       const T o1 = (2 * t + 1 >= p - 1 && i0 + 1 < m) ? u_in[i0 + 1] : T(0);
       nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
-      s[t] = {o0, o1};
+      s[swz<T>(t)] = {o0, o1};
     }
   }
 
@@ -187,18 +187,18 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
         const int bnk = bitrev((N - k) & (N - 1), LGN);
         const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
         cx<T> Xk, Xnk;
-        rfft_post(s[bk], s[bnk], w, Xk, Xnk);
+        rfft_post(s[swz<T>(bk)], s[swz<T>(bnk)], w, Xk, Xnk);
         cx<T> Zk, Znk;
         irfft_pre(cmulconj(yk[ip], Xk), cmulconj(ynk[ip], Xnk), w, Zk, Znk);
-        s[bk] = Zk;
-        if (k != 0 && 2 * k != N) s[bnk] = Znk;
+        s[swz<T>(bk)] = Zk;
+        if (k != 0 && 2 * k != N) s[swz<T>(bnk)] = Znk;
       }
     }
     __syncthreads();
     fft_dit<T, true, LGN, NT>(s, tab);
     const double invB = 1.0 / static_cast<double>(2 * N);
     for (int t = tid; 2 * t < p; t += NT) {
-      const cx<T> z = s[t];
+      const cx<T> z = s[swz<T>(t)];
       partial[static_cast<size_t>(2 * t) * nblocks + blk] = static_cast<double>(z.x) * invB;
       if (2 * t + 1 < p)
         partial[static_cast<size_t>(2 * t + 1) * nblocks + blk] = static_cast<double>(z.y) * invB;
@@ -245,15 +245,15 @@ __global__ __launch_bounds__(NT) void scores_kernel(const cx<T>* __restrict__ Yh
         const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
         cx<T> Zk, Znk;
         irfft_pre(cmul(yk[ip], vk), cmul(ynk[ip], vnk), w, Zk, Znk);
-        s[bitrev(k, LGN)] = Zk;
-        if (k != 0 && 2 * k != N) s[bitrev(N - k, LGN)] = Znk;
+        s[swz<T>(bitrev(k, LGN))] = Zk;
+        if (k != 0 && 2 * k != N) s[swz<T>(bitrev(N - k, LGN))] = Znk;
       }
     }
     __syncthreads();
     fft_dit<T, true, LGN, NT>(s, tab);
 #pragma unroll
     for (int e = 0; e < NEL; ++e) {
-      const cx<T> z = s[tid + e * NT];
+      const cx<T> z = s[swz<T>(tid + e * NT)];
       acc0[e] += z.x * z.x;
       acc1[e] += z.y * z.y;
     }

@@ -239,7 +239,7 @@ def test_gather(ctx, mode):
         cc = m
     else:
         cc = 101
-    crows = (cc + 3) // 4 * 4
+    crows = (cc + 15) // 16 * 16
     A = torch.full((crows * ldq,), 7.0, dtype=torch.float64, device=dev)
     seed, fit = 1234, 2
     if mode == 0:
@@ -269,7 +269,7 @@ def test_qr_matches_lapack(ctx, c_rows, q):
     say("qr", c_rows, q)
     rng = np.random.default_rng(12)
     ldq = (q + 15) // 16 * 16
-    crows = (c_rows + 3) // 4 * 4
+    crows = (c_rows + 15) // 16 * 16
     A = np.zeros((crows, ldq))
     # moderately conditioned columns
     A[:c_rows, :q] = rng.standard_normal((c_rows, q)) @ np.diag(np.logspace(0, 3, q))
