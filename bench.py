@@ -38,6 +38,8 @@ WORKLOAD_TEXT = {
              "U(0,pi), N(0,1) innovations, seed 0; sketch 8p rows, LSQR tol 1e-10, FP64",
     "ar3": "AR(3), phi=(0.5,-0.3,0.1), n=10000, N(0,1), burn-in 500, seed 0; sketch 20p, "
            "LSQR tol 1e-10, FP64",
+    "ar500": "AR(500) series, n=2^25, 250 pole pairs with moduli U[0.5,0.95] and angles U(0,pi), "
+             "N(0,1) innovations, seed 0; sketch 8p rows, tol 1e-10",
 }
 
 
@@ -102,6 +104,26 @@ def accuracy(y, p, coef, resid, workload):
             if kappa * 1e-16 > 1e-6 else "coefficient gate attainable"}
 
 
+def gpu_fp64_agreement(y, p, out, ref):
+    """Full-size comparison of a fit against the GPU FP64 fit of the same
+    series (the dense oracle does not fit in host memory at this size)."""
+    import oracle
+    d = out["coef"] - ref["coef"]
+    num = den = 0.0
+    step = 1 << 18
+    m = y.size - p
+    for a in range(0, m, step):
+        rows = min(step, m - a)
+        seg = y[a: a + rows + p]
+        num += float(np.sum(oracle.matvec(seg, p, d) ** 2))
+        den += float(np.sum(oracle.matvec(seg, p, ref["coef"]) ** 2))
+    return {"reference": "GPU FP64 fit at full size", "kappa_est_R": ref["kappa_est"],
+            "rel_err_vs_f64": float(np.linalg.norm(d) / np.linalg.norm(ref["coef"])),
+            "fitted_rel_err": float(np.sqrt(num / den)),
+            "resid_rel_diff": abs(out["resid_norm"] - ref["resid_norm"]) / ref["resid_norm"],
+            "f64_status": ref["status"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +131,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ar100", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--precision", default="f64", choices=["f64", "mixed"])
+    ap.add_argument("--block-lg", type=int, default=0, help="log2 FFT block length (0 = automatic)")
+    ap.add_argument("--n", type=int, default=0, help="override the series length")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters against a known size) and exit")
@@ -136,12 +161,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
-    f = synth.WORKLOADS[args.workload](seed=0)
+    f = synth.WORKLOADS[args.workload](seed=0, **({"n": args.n} if args.n else {}))
+    prec = 1 if args.precision == "mixed" else 0
     y, p = f.y, f.p
     print(f"[bench] workload {args.workload}: n={y.size} p={p}", file=sys.stderr, flush=True)
     dy = torch.from_numpy(y).to("cuda:0")
     torch.cuda.synchronize()
-    ctx = capi.Context(0, gamma=f.gamma)
+    ctx = capi.Context(0, gamma=f.gamma, precision=prec, block_lg=args.block_lg)
     stream = torch.cuda.current_stream()
 
     out = None
@@ -165,10 +191,20 @@ def main():
     print(f"[bench] timed {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
 
     B, nb = out["block_len"], out["n_blocks"]
-    bytes_pass = fused_pass_bytes(y.size, p, B, nb, 8)
+    if prec == 0:
+        bytes_pass = fused_pass_bytes(y.size, p, B, nb, 8)
+        kernel_name = "toep_pass_kernel<double, fused>: e = X v - a u, X^T e, ||e||^2"
+    else:
+        # the CG pass reads only the FP32 spectra and writes the block partials
+        bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * nb * 8
+        kernel_name = "toep_pass_kernel<float, fused>: X^T X v (CG normal-equation product)"
     avg_pass_s = pass_ms / max(pass_count, 1) / 1e3
     achieved = bytes_pass / avg_pass_s / 1e9 if pass_count else 0.0
-    acc = accuracy(y, p, out["coef"], out["resid_norm"], args.workload)
+    if args.workload == "ar500":
+        ref = ctx.fit_device(dy, p, f.tol, stream=stream, precision=0)
+        acc = gpu_fp64_agreement(y, p, out, ref)
+    else:
+        acc = accuracy(y, p, out["coef"], out["resid_norm"], args.workload)
 
     line = {
         "metric": METRIC,
@@ -181,14 +217,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == 0 else "f32 products, f64 recurrences",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "n": int(y.size), "p": p,
                    "sketch_rows": out["sketch_rows"], "fft_block": B, "fft_blocks": nb,
-                   "lsqr_iters": int(np.median(iters)), "status": capi.status_string(out["status"])},
+                   "precision": args.precision, "iters": int(np.median(iters)),
+                   "refine_steps": out["refine_steps"], "kappa_est_R": out["kappa_est"],
+                   "status": capi.status_string(out["status"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "toep_pass_kernel<double, fused>",
+                     "kernel": kernel_name,
                      "bytes_per_launch": bytes_pass, "avg_launch_us": avg_pass_s * 1e6,
                      "launches_timed": pass_count},
         "accuracy": acc,

@@ -68,7 +68,7 @@ typedef struct tls_options {
   int32_t max_iter;    /* LSQR / inner iteration limit (default 1000) */
   int32_t block_lg;    /* log2 of the FFT block length B, 7..14; 0 = automatic */
   int32_t warm_start;  /* 1: start from the compressed problem's solution (default 1) */
-  int32_t max_refine;  /* mixed precision: outer FP64 refinement steps (default 8) */
+  int32_t max_refine;  /* mixed precision: outer FP64 refinement steps (default 10) */
   int32_t profile;     /* 1: time every Toeplitz pass with HIP events (tls_result.pass_ms) */
   uint64_t seed;       /* random seed (default 0) */
   uint64_t request_id; /* selects the random streams of one fit (default 0) */
@@ -81,7 +81,9 @@ typedef struct tls_result {
   double lsqr_rnorm;   /* LSQR's own residual estimate */
   double lsqr_arnorm;  /* LSQR's ||A^T r|| estimate */
   int32_t iters;       /* total inner iterations */
-  int32_t istop;       /* LSQR stop reason: 1, 2 converged; 3 exact; 4 breakdown; 7 limit */
+  int32_t istop;       /* stop reason: 1, 2 converged; 3 exact; 4 breakdown; 5 (mixed) no
+                          further contraction: the FP32 products reached their resolution
+                          (returned as TLS_OK); 7 iteration / refinement limit */
   int32_t refine_steps;/* outer refinement steps (mixed precision), else 0 */
   int32_t sketch_rows; /* c */
   int32_t block_len;   /* FFT block length B used */

@@ -146,9 +146,10 @@ struct Plan {
 };
 
 int auto_block(int p, int64_t m) {
-  // Smallest power of two >= 16 p (>= 2p always), between 256 and 16384, and
-  // no longer than the data needs.
-  int lg = ilog2(16 * static_cast<int64_t>(p));
+  // Smallest power of two >= 8 p (>= 2p always), between 256 and 16384, and
+  // no longer than the data needs: shorter blocks cost fewer FFT flops per
+  // sample, longer ones re-read fewer overlapping samples.
+  int lg = ilog2(8 * static_cast<int64_t>(p));
   if (lg < 8) lg = 8;
   const int lgdata = ilog2(m + p);
   if (lg > lgdata) lg = lgdata < 8 ? 8 : lgdata;
@@ -215,6 +216,9 @@ struct FitBufs {
   double* dminmax;  // scratch
   double* rr;       // residual norm^2
   double* rpart;    // direct residual partials
+  void* Vhat32;     // mixed: FP32 spectrum of the CG direction
+  RefineState* rst; // mixed: refinement state
+  double *cw, *cres, *cd;  // mixed: CG vectors
 };
 
 size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
@@ -256,6 +260,11 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->dminmax = a.take<double>(4);
   b->rr = a.take<double>(4);
   b->rpart = a.take<double>(resid_direct_blocks(pl.m));
+  b->Vhat32 = a.take<char>(N * 8);
+  b->rst = a.take<RefineState>(1);
+  b->cw = a.take<double>(pl.p);
+  b->cres = a.take<double>(pl.p);
+  b->cd = a.take<double>(pl.p);
   return a.need + 256;
 }
 
@@ -269,6 +278,23 @@ __global__ void fill_state_kernel(LsqrState* st, double tol, int max_iter, int* 
     *st = s;
     status[0] = status[1] = status[2] = status[3] = 0;
   }
+}
+
+__global__ void fill_refine_kernel(RefineState* st, double tol, int max_refine, int inner_max,
+                                   double inner_tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    RefineState s{};
+    s.tol = tol;
+    s.max_refine = max_refine;
+    s.inner_max = inner_max;
+    s.inner_tol = inner_tol;
+    *st = s;
+  }
+}
+
+__global__ void copy_vec_kernel(const double* a, int n, double* b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
 }
 
 __global__ void diag_minmax_kernel(const double* R, int q, int p, double* out) {
@@ -295,7 +321,10 @@ __global__ void to_f32_kernel(const double* x, int64_t n, float* y) {
 }
 
 struct HostOut {
-  LsqrState st;
+  union {
+    LsqrState st;
+    RefineState rs;
+  };
   double dminmax[4];
   double rr[4];
   int status[4];
@@ -423,7 +452,71 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       pass_count = static_cast<int>(worked);
     }
   } else {
-    return TLS_EUNSUPPORTED;  // mixed precision path below
+    // Mixed precision: FP64 residual and gradient of the current phi, then a
+    // CG solve of the preconditioned normal equations for the correction,
+    // whose X^T X products are single FP32 passes over the FP32 spectra.
+    const int max_refine = o.max_refine > 0 ? o.max_refine : 8;
+    const int inner_max = std::min(max_iter, 25);
+    constexpr int INNER_CHUNK = 6;
+    hipLaunchKernelGGL(fill_refine_kernel, dim3(1), dim3(64), 0, s, b.rst, tol, max_refine,
+                       inner_max, 1e-5);
+    hipLaunchKernelGGL(copy_vec_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phi0, p, b.phi);
+    TLS_CHECK(hipGetLastError());
+    size_t npass = 0;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    RefineState* hr = &ho->rs;
+    double worked_ms = 0.0;
+    int worked_passes = 0;
+    for (int outer = 0; outer <= max_refine; ++outer) {
+      const size_t first_pass = npass;
+      TLS_CHECK(launch_small_rfft(PREC_F64, pl.lgn, b.phi, p, p, 1, invB, b.Vhat, ctx->tw, nullptr, s));
+      TLS_CHECK(launch_toep(PREC_F64, pl.lgn, MODE_FUSED, b.Yhat64, b.Vhat, d_y + p, nullptr, nullptr,
+                            b.partial, ctx->consts, &b.rst->done, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
+      TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, &b.rst->done, s));
+      TLS_CHECK(launch_refine_outer(pl.lgn, p, b.rst, b.g, b.M, b.Mt, b.cw, b.cres, b.cd, b.Vhat32,
+                                    ctx->tw, s));
+      for (int it = 0; it < inner_max; it += INNER_CHUNK) {
+        for (int k = it; k < std::min(inner_max, it + INNER_CHUNK); ++k) {
+          if (o.profile) {
+            TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
+            TLS_CHECK(hipEventRecord(ea, s));
+          }
+          TLS_CHECK(launch_toep(PREC_F32, pl.lgn, MODE_FUSED, b.Yhat, b.Vhat32, nullptr, nullptr,
+                                nullptr, b.partial, ctx->consts + 2, &b.rst->inner_done, ctx->tw,
+                                pl.m, p, pl.L, pl.nblocks, s));
+          if (o.profile) {
+            TLS_CHECK(hipEventRecord(eb, s));
+            ++npass;
+          }
+          TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, &b.rst->inner_done, s));
+          TLS_CHECK(launch_refine_cg(pl.lgn, p, b.rst, b.g, b.M, b.Mt, b.cw, b.cres, b.cd, b.phi,
+                                     b.Vhat32, ctx->tw, s));
+        }
+        TLS_CHECK(hipMemcpyAsync(hr, b.rst, sizeof(RefineState), hipMemcpyDeviceToHost, s));
+        TLS_CHECK(hipStreamSynchronize(s));
+        if (hr->inner_done) break;
+      }
+      if (o.profile) {
+        // the first `inner` passes of this outer step did work; later ones exited at once
+        const size_t worked = std::min(npass - first_pass, static_cast<size_t>(hr->inner));
+        for (size_t i = first_pass; i < first_pass + worked; ++i) {
+          float t = 0.f;
+          TLS_CHECK(hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]));
+          worked_ms += t;
+        }
+        worked_passes += static_cast<int>(worked);
+      }
+      if (hr->done) break;
+    }
+    TLS_CHECK(hipMemcpyAsync(hr, b.rst, sizeof(RefineState), hipMemcpyDeviceToHost, s));
+    TLS_CHECK(hipStreamSynchronize(s));
+    total_iters = hr->total_inner;
+    refine = hr->outer;
+    istop = hr->stop == 1 ? 2 : (hr->stop == 7 ? 7 : (hr->stop == 5 ? 5 : 0));
+    if (o.profile) {
+      pass_ms = worked_ms;
+      pass_count = worked_passes;
+    }
   }
 
   // FP64 residual of the returned coefficients, row by row.
@@ -494,7 +587,7 @@ void tls_options_default(tls_options* o) {
   o->max_iter = 1000;
   o->block_lg = 0;
   o->warm_start = 1;
-  o->max_refine = 8;
+  o->max_refine = 10;
   o->seed = 0;
   o->request_id = 0;
 }

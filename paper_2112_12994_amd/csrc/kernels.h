@@ -83,6 +83,24 @@ hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const doubl
                             const double* M, const double* Mt, double* v, double* w, double* z,
                             const double* phi0, double* phi, void* Vhat, const Twiddles& tw,
                             hipStream_t stream);
+// Mixed-precision refinement (FP64 outer residual, FP32 inner CG on the
+// preconditioned normal equations).
+struct RefineState {
+  double rho, rho0, tol, inner_tol, rnorm, hnorm, hprev;
+  int outer, inner, max_refine, inner_max, done, inner_done, total_inner, stop;
+};
+// g64: X^T r (p) and ||r||^2 ([p]) for r = b - X phi.  Checks convergence
+// (||M^T g|| <= tol ||r||), else starts CG: w = 0, res = d = M^T g, and
+// writes the packed FP32 spectrum of M d (scaled 1/B) to Vhat32.
+hipError_t launch_refine_outer(int lgn, int p, RefineState* st, const double* g64, const double* M,
+                               const double* Mt, double* w, double* res, double* d,
+                               void* Vhat32, const Twiddles& tw, hipStream_t s);
+// g: X^T X (M d) (p) from the FP32 Gram pass.  One CG step; when the inner
+// solve ends, phi += M w.
+hipError_t launch_refine_cg(int lgn, int p, RefineState* st, const double* g, const double* M,
+                            const double* Mt, double* w, double* res, double* d, double* phi,
+                            void* Vhat32, const Twiddles& tw, hipStream_t s);
+
 hipError_t launch_vec_axpy_small(const double* M, const double* x, const double* y0, int p,
                                  double* out, hipStream_t st);
 

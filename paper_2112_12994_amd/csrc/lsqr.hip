@@ -274,6 +274,224 @@ hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, cons
   return hipGetLastError();
 }
 
+// ---- mixed-precision refinement p-side kernels ---------------------------
+// Both stage M into LDS when p <= 128 (padded rows), else read it from global.
+
+// Packed spectrum (scaled 1/B) of the real p-vector q into Vhat (TS words).
+template <int LGN, int NT, typename TS>
+__device__ void spectrum_of(const double* __restrict__ q, int p, cx<double>* s,
+                            cx<TS>* __restrict__ Vhat, const cx<double>* __restrict__ tab) {
+  constexpr int N = 1 << LGN;
+  for (int t = threadIdx.x; t < N; t += NT) {
+    const int i0 = 2 * t;
+    s[swz<double>(t)] = {i0 < p ? q[i0] : 0.0, i0 + 1 < p ? q[i0 + 1] : 0.0};
+  }
+  __syncthreads();
+  fft_dif<double, false, LGN, NT>(s, tab);
+  const double invB = 1.0 / static_cast<double>(2 * N);
+  for (int k = threadIdx.x; k <= N / 2; k += NT) {
+    const cx<double> wk = twiddle<double, false>(tab, k, LGN + 1);
+    cx<double> Xk, Xnk;
+    rfft_post(s[swz<double>(bitrev(k, LGN))], s[swz<double>(bitrev((N - k) & (N - 1), LGN))], wk,
+              Xk, Xnk);
+    Xk = cscale(Xk, invB);
+    Xnk = cscale(Xnk, invB);
+    if (k == 0) {
+      Vhat[0] = {static_cast<TS>(Xk.x), static_cast<TS>(Xnk.x)};
+    } else {
+      Vhat[k] = {static_cast<TS>(Xk.x), static_cast<TS>(Xk.y)};
+      if (2 * k != N) Vhat[N - k] = {static_cast<TS>(Xnk.x), static_cast<TS>(Xnk.y)};
+    }
+  }
+}
+
+// out = M^T x (M upper; out[j] = sum_{i <= j} M[i][j] x[i]) or M x.
+template <int NT, bool TRANS>
+__device__ void gemv_m(const double* __restrict__ M, const double* __restrict__ Mt, const double* sM,
+                       int ldm, bool lds, int p, const double* x, double* out) {
+  if (lds) {
+    for (int r = threadIdx.x; r < p; r += NT) {
+      double a0 = 0.0, a1 = 0.0;
+      if (TRANS) {
+        int i = 0;
+        for (; i + 1 <= r; i += 2) {
+          a0 += sM[i * ldm + r] * x[i];
+          a1 += sM[(i + 1) * ldm + r] * x[i + 1];
+        }
+        if (i <= r) a0 += sM[i * ldm + r] * x[i];
+      } else {
+        int j = r;
+        for (; j + 1 < p; j += 2) {
+          a0 += sM[r * ldm + j] * x[j];
+          a1 += sM[r * ldm + j + 1] * x[j + 1];
+        }
+        if (j < p) a0 += sM[r * ldm + j] * x[j];
+      }
+      out[r] = a0 + a1;
+    }
+  } else if (TRANS) {
+    tri_gemv_rows<NT, false>(Mt, p, x, [&](int j, double acc) { out[j] = acc; });
+  } else {
+    tri_gemv_rows<NT, true>(M, p, x, [&](int i, double acc) { out[i] = acc; });
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ double dot_block(const double* a, const double* b, int p, double* red) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < p; i += NT) acc += a[i] * b[i];
+  return block_sum<NT>(acc, red);
+}
+
+template <int LGN, int NT>
+__global__ __launch_bounds__(NT) void refine_outer_kernel(int p, RefineState* __restrict__ st,
+                                                          const double* __restrict__ g64,
+                                                          const double* __restrict__ M,
+                                                          const double* __restrict__ Mt,
+                                                          double* __restrict__ w,
+                                                          double* __restrict__ res,
+                                                          double* __restrict__ d,
+                                                          cx<float>* __restrict__ Vhat32,
+                                                          const cx<double>* __restrict__ tab) {
+  constexpr int N = 1 << LGN;
+  __shared__ cx<double> s[N];
+  __shared__ double red[NT / 64];
+  extern __shared__ double smem[];
+  double* sx = smem;      // p
+  double* sh = sx + p;    // p
+  double* sq = sh + p;    // p
+  double* sM = sq + p;    // p x ldm when lds
+  const int ldm = p | 1;
+  const bool lds = p <= 128;
+  if (st->done) return;
+  if (lds)
+    for (int e = threadIdx.x; e < p * p; e += NT) sM[(e / p) * ldm + e % p] = M[e];
+  for (int i = threadIdx.x; i < p; i += NT) sx[i] = g64[i];
+  __syncthreads();
+  gemv_m<NT, true>(M, Mt, sM, ldm, lds, p, sx, sh);  // h = M^T X^T r
+  const double hh = dot_block<NT>(sh, sh, p, red);
+  const double hn = sqrt(hh), rn = sqrt(g64[p]);
+  const int outer = st->outer;
+  bool done = false;
+  int stop = 0;
+  if (hn <= st->tol * rn) {
+    done = true;
+    stop = 1;
+  } else if (outer >= st->max_refine) {
+    done = true;
+    stop = 7;
+  } else if (outer > 0 && !(hn < 0.5 * st->hprev)) {
+    done = true;  // no further contraction (FP32 products at their resolution)
+    stop = 5;
+  }
+  if (!done) {
+    for (int i = threadIdx.x; i < p; i += NT) {
+      w[i] = 0.0;
+      res[i] = sh[i];
+      d[i] = sh[i];
+    }
+    gemv_m<NT, false>(M, Mt, sM, ldm, lds, p, sh, sq);  // M d
+    spectrum_of<LGN, NT, float>(sq, p, s, Vhat32, tab);
+  }
+  if (threadIdx.x == 0) {
+    st->rnorm = rn;
+    st->hprev = st->hnorm > 0.0 ? fmin(st->hnorm, hn) : hn;
+    st->hnorm = hn;
+    st->rho = hh;
+    st->rho0 = hh;
+    st->inner = 0;
+    st->inner_done = done ? 1 : 0;
+    st->outer = outer + 1;
+    st->stop = stop;
+    if (done) st->done = 1;
+  }
+}
+
+template <int LGN, int NT>
+__global__ __launch_bounds__(NT) void refine_cg_kernel(int p, RefineState* __restrict__ st,
+                                                       const double* __restrict__ g,
+                                                       const double* __restrict__ M,
+                                                       const double* __restrict__ Mt,
+                                                       double* __restrict__ w,
+                                                       double* __restrict__ res,
+                                                       double* __restrict__ d,
+                                                       double* __restrict__ phi,
+                                                       cx<float>* __restrict__ Vhat32,
+                                                       const cx<double>* __restrict__ tab) {
+  constexpr int N = 1 << LGN;
+  __shared__ cx<double> s[N];
+  __shared__ double red[NT / 64];
+  extern __shared__ double smem[];
+  double* sx = smem;    // p
+  double* st_ = sx + p; // p: t = M^T g
+  double* sq = st_ + p; // p
+  double* sM = sq + p;
+  const int ldm = p | 1;
+  const bool lds = p <= 128;
+  if (st->inner_done) return;
+  if (lds)
+    for (int e = threadIdx.x; e < p * p; e += NT) sM[(e / p) * ldm + e % p] = M[e];
+  for (int i = threadIdx.x; i < p; i += NT) sx[i] = g[i];
+  __syncthreads();
+  gemv_m<NT, true>(M, Mt, sM, ldm, lds, p, sx, st_);  // t = A^T A d
+  const double dt = dot_block<NT>(d, st_, p, red);
+  const double rho = st->rho;
+  const double alpha = dt > 0.0 ? rho / dt : 0.0;
+  double rr = 0.0;
+  for (int i = threadIdx.x; i < p; i += NT) {
+    w[i] += alpha * d[i];
+    const double ri = res[i] - alpha * st_[i];
+    res[i] = ri;
+    rr += ri * ri;
+  }
+  const double rho_new = block_sum<NT>(rr, red);
+  const int inner = st->inner + 1;
+  const bool finish = !(dt > 0.0) || !isfinite(rho_new) || rho_new <= st->inner_tol * st->inner_tol * st->rho0 ||
+                      inner >= st->inner_max;
+  if (!finish) {
+    const double beta = rho_new / rho;
+    for (int i = threadIdx.x; i < p; i += NT) d[i] = res[i] + beta * d[i];
+    __syncthreads();
+    gemv_m<NT, false>(M, Mt, sM, ldm, lds, p, d, sq);
+    spectrum_of<LGN, NT, float>(sq, p, s, Vhat32, tab);
+  } else {
+    __syncthreads();
+    gemv_m<NT, false>(M, Mt, sM, ldm, lds, p, w, sq);  // phi += M w
+    for (int i = threadIdx.x; i < p; i += NT) phi[i] += sq[i];
+  }
+  if (threadIdx.x == 0) {
+    st->rho = rho_new;
+    st->inner = inner;
+    st->total_inner += 1;
+    if (finish) st->inner_done = 1;
+  }
+}
+
+template <int LGN>
+hipError_t refine_outer_one(int p, RefineState* st, const double* g64, const double* M,
+                            const double* Mt, double* w, double* res, double* d, void* Vhat32,
+                            const Twiddles& tw, hipStream_t s) {
+  const size_t shm = (3 * static_cast<size_t>(p) + (p <= 128 ? static_cast<size_t>(p) * (p | 1) : 0)) *
+                     sizeof(double);
+  hipLaunchKernelGGL((refine_outer_kernel<LGN, 256>), dim3(1), dim3(256), shm, s, p, st, g64, M, Mt,
+                     w, res, d, static_cast<cx<float>*>(Vhat32),
+                     static_cast<const cx<double>*>(tw.d64));
+  return hipGetLastError();
+}
+
+template <int LGN>
+hipError_t refine_cg_one(int p, RefineState* st, const double* g, const double* M, const double* Mt,
+                         double* w, double* res, double* d, double* phi, void* Vhat32,
+                         const Twiddles& tw, hipStream_t s) {
+  const size_t shm = (3 * static_cast<size_t>(p) + (p <= 128 ? static_cast<size_t>(p) * (p | 1) : 0)) *
+                     sizeof(double);
+  hipLaunchKernelGGL((refine_cg_kernel<LGN, 256>), dim3(1), dim3(256), shm, s, p, st, g, M, Mt, w,
+                     res, d, phi, static_cast<cx<float>*>(Vhat32),
+                     static_cast<const cx<double>*>(tw.d64));
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void gemv_upper_kernel(const double* __restrict__ Mt,
                                                          const double* __restrict__ x,
                                                          const double* __restrict__ y0, int p,
@@ -311,6 +529,35 @@ hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const doubl
       return hipErrorInvalidValue;
   }
 #undef TLS_STEP_CASE
+}
+
+#define TLS_LG_SWITCH(CALL)                   \
+  switch (lgn) {                              \
+    case 6: return CALL(6);                   \
+    case 7: return CALL(7);                   \
+    case 8: return CALL(8);                   \
+    case 9: return CALL(9);                   \
+    case 10: return CALL(10);                 \
+    case 11: return CALL(11);                 \
+    case 12: return CALL(12);                 \
+    case 13: return CALL(13);                 \
+    default: return hipErrorInvalidValue;     \
+  }
+
+hipError_t launch_refine_outer(int lgn, int p, RefineState* st, const double* g64, const double* M,
+                               const double* Mt, double* w, double* res, double* d, void* Vhat32,
+                               const Twiddles& tw, hipStream_t s) {
+#define TLS_OUTER(LG) refine_outer_one<LG>(p, st, g64, M, Mt, w, res, d, Vhat32, tw, s)
+  TLS_LG_SWITCH(TLS_OUTER)
+#undef TLS_OUTER
+}
+
+hipError_t launch_refine_cg(int lgn, int p, RefineState* st, const double* g, const double* M,
+                            const double* Mt, double* w, double* res, double* d, double* phi,
+                            void* Vhat32, const Twiddles& tw, hipStream_t s) {
+#define TLS_CG(LG) refine_cg_one<LG>(p, st, g, M, Mt, w, res, d, phi, Vhat32, tw, s)
+  TLS_LG_SWITCH(TLS_CG)
+#undef TLS_CG
 }
 
 // out = y0 + M x for upper-triangular M given as Mt = M^T (row-major).

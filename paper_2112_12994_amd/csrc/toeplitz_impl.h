@@ -119,13 +119,6 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
   const cx<T>* Y = Yhat + static_cast<size_t>(blk) * N;
   const int64_t row0 = static_cast<int64_t>(blk) * L - (p - 1);  // row at tau = 0
 
-  cx<T> yk[NPAIR], ynk[NPAIR];
-#pragma unroll
-  for (int ip = 0; ip < NPAIR; ++ip) {
-    const int k = tid + ip * NT;
-    if (k <= N / 2) load_pair(Y, k, N, yk[ip], ynk[ip]);
-  }
-
   double nrm = 0.0;
   if constexpr ((MODE & PM_MV) != 0) {
     const T s1 = static_cast<T>(coef[0]);
@@ -134,11 +127,12 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
     for (int ip = 0; ip < NPAIR; ++ip) {
       const int k = tid + ip * NT;
       if (k <= N / 2) {
-        cx<T> vk, vnk;
+        cx<T> yk, ynk, vk, vnk;
+        load_pair(Y, k, N, yk, ynk);
         load_pair(Vhat, k, N, vk, vnk);
         const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
         cx<T> Zk, Znk;
-        irfft_pre(cmul(yk[ip], vk), cmul(ynk[ip], vnk), w, Zk, Znk);
+        irfft_pre(cmul(yk, vk), cmul(ynk, vnk), w, Zk, Znk);
         s[swz<T>(bitrev(k, LGN))] = Zk;
         if (k != 0 && 2 * k != N) s[swz<T>(bitrev(N - k, LGN))] = Znk;
       }
@@ -188,8 +182,10 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
         const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
         cx<T> Xk, Xnk;
         rfft_post(s[swz<T>(bk)], s[swz<T>(bnk)], w, Xk, Xnk);
+        cx<T> yk2, ynk2;  // reloaded (cache hit) rather than kept live across the transforms
+        load_pair(Y, k, N, yk2, ynk2);
         cx<T> Zk, Znk;
-        irfft_pre(cmulconj(yk[ip], Xk), cmulconj(ynk[ip], Xnk), w, Zk, Znk);
+        irfft_pre(cmulconj(yk2, Xk), cmulconj(ynk2, Xnk), w, Zk, Znk);
         s[swz<T>(bk)] = Zk;
         if (k != 0 && 2 * k != N) s[swz<T>(bnk)] = Znk;
       }

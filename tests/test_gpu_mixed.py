@@ -1,0 +1,109 @@
+"""Mixed-precision path (FP32 FFT products and sketch scores; FP64 QR,
+recurrences and residual) against the FP64 QR oracle.  Coefficient gate
+1e-4 relative wherever the attainable accuracy allows it; the FP64 outer
+refinement is expected to reach FP64-level agreement on moderately
+conditioned problems."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import attainable, capi, chunked_matvec_norms, resid_tol, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MIXED = 1
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = capi()
+    with c.Context(0) as cx:
+        yield cx
+
+
+def _check_mixed(out, y, p, gate=1e-4, tol=1e-10):
+    c = capi()
+    ref = oracle.fit_qr(y, p)
+    phi = ref["phi"]
+    smax = float(np.linalg.svd(ref["R"], compute_uv=False)[0])
+    xd, xphi = chunked_matvec_norms(y, p, out["coef"] - phi, phi)
+    coef_b, fit_b = attainable(phi, ref["rnorm"], ref["kappa"], smax, xphi,
+                               float(np.linalg.norm(y[p:])), p, out["block_len"], tol)
+    err = oracle.rel_error(out["coef"], phi)
+    say("   kappa=%.3g err=%.3g (bound %.2g) fit=%.3g refine=%d inner=%d istop=%d"
+        % (ref["kappa"], err, coef_b, xd / xphi, out["refine_steps"], out["iters"], out["istop"]))
+    rt = resid_tol(phi, ref["rnorm"], smax, np.abs(y).max(), p, xd)
+    if ref["kappa"] * 2.0 ** -24 < 0.1:
+        # FP32 products accurate enough for the FP64 refinement to contract
+        assert out["status"] == c.TLS_OK, c.status_string(out["status"])
+        assert err <= gate
+        assert err <= max(100 * coef_b, 1e-12)
+    else:
+        # beyond FP32 resolution the refinement may stop early (istop 5) or at
+        # its limit (TLS_ENOCONV); the fit can then only be worse than optimal
+        assert out["status"] in (c.TLS_OK, c.TLS_ENOCONV), c.status_string(out["status"])
+        assert out["resid_norm"] >= ref["rnorm"] - rt
+    # the reported residual is the row-wise FP64 norm of the returned phi
+    assert abs(out["resid_norm"] - ref["rnorm"]) <= rt or ref["kappa"] * 2.0 ** -24 >= 0.1
+    return err
+
+
+@pytest.mark.parametrize("p,n,seed,rlo,rhi", [(3, 10000, 0, 0.3, 0.9), (10, 65536, 1, 0.3, 0.9),
+                                              (64, 131072, 2, 0.3, 0.9), (100, 65536, 3, 0.3, 0.85),
+                                              (200, 100000, 4, 0.3, 0.8)])
+def test_mixed_matches_oracle(ctx, p, n, seed, rlo, rhi):
+    say("mixed", p, n, seed)
+    rng = np.random.default_rng(seed)
+    y = synth.ar_series(n, p, rng, rlo, rhi)
+    out = ctx.fit(y, p, 1e-10, precision=MIXED)
+    _check_mixed(out, y, p)
+
+
+def test_mixed_ar500_shape(ctx):
+    """AR(500) from the pole generator (moduli U[0.3, 0.8] to stay within
+    FP32-resolvable conditioning), n = 2^16: exercises the p > 128 kernels."""
+    say("mixed ar500")
+    rng = np.random.default_rng(5)
+    y = synth.ar_series(1 << 16, 500, rng, 0.3, 0.8)
+    out = ctx.fit(y, 500, 1e-10, precision=MIXED)
+    _check_mixed(out, y, 500)
+
+
+def test_mixed_equals_f64_fitted_values(ctx):
+    """Mixed and FP64 paths agree on a moderately conditioned AR(100) series."""
+    say("mixed vs f64")
+    rng = np.random.default_rng(7)
+    y = synth.ar_series(1 << 18, 100, rng, 0.3, 0.85)
+    a = ctx.fit(y, 100, 1e-10)
+    b = ctx.fit(y, 100, 1e-10, precision=MIXED)
+    xd, xphi = chunked_matvec_norms(y, 100, a["coef"] - b["coef"], a["coef"])
+    say("   fitted diff %.3g, resid %.12g vs %.12g" % (xd / xphi, a["resid_norm"], b["resid_norm"]))
+    assert a["status"] == capi().TLS_OK and b["status"] == capi().TLS_OK
+    assert xd / xphi <= 1e-9
+    assert abs(a["resid_norm"] - b["resid_norm"]) <= 1e-9 * a["resid_norm"]
+
+
+def test_mixed_beyond_fp32_resolution_is_flagged(ctx):
+    """kappa(X) ~ 1e12 (the AR(100) pole workload) is beyond what FP32
+    products resolve: the refinement stops on stagnation or at its limit and
+    its residual is no smaller than the FP64 least-squares optimum."""
+    c = capi()
+    say("mixed beyond resolution")
+    f = synth.workload_ar100(seed=0, n=1 << 18)
+    a = ctx.fit(f.y, 100, 1e-10)
+    b = ctx.fit(f.y, 100, 1e-10, precision=MIXED)
+    say("   istop=%d refine=%d resid %.12g vs %.12g" % (b["istop"], b["refine_steps"],
+                                                         b["resid_norm"], a["resid_norm"]))
+    assert b["status"] in (c.TLS_OK, c.TLS_ENOCONV)
+    assert b["istop"] in (5, 7)
+    assert b["resid_norm"] >= a["resid_norm"] * (1 - 1e-12)
+
+
+def test_mixed_device_input_deterministic(ctx):
+    say("mixed determinism")
+    rng = np.random.default_rng(6)
+    y = synth.ar_series(50000, 20, rng, 0.3, 0.9)
+    a = ctx.fit_device(to_dev(y), 20, 1e-10, precision=MIXED)
+    b = ctx.fit(y, 20, 1e-10, precision=MIXED)
+    assert a["coef"].tobytes() == b["coef"].tobytes()
