@@ -137,6 +137,22 @@ tls_status tls_fit_batch(tls_ctx* ctx, int32_t count, const double* const* serie
                          const int64_t* coef_offset, double* resid_norm, int32_t* iters,
                          tls_status* per_fit_status);
 
+/* Batched fits of `count` series already in device memory: d_series is a
+ * host array of device pointers (series i: n[i] doubles, order p[i]), work
+ * queued on `stream` (NULL = the context's stream; the call returns after it
+ * has finished).  coef_packed, coef_offset, out (count tls_result entries,
+ * may be NULL) and per_fit_status (may be NULL) are host memory.  The fits
+ * are grouped by FFT block length and order class and each group runs its
+ * kernels as single launches over all of its fits; fit i gives the same
+ * result, bit for bit, as tls_fit_device with request_id = opt.request_id + i.
+ * The series must stay valid and unmodified until the call returns.
+ * Returns TLS_OK when every fit is TLS_OK, else the first failing status. */
+tls_status tls_fit_batch_device(tls_ctx* ctx, int32_t count, const double* const* d_series,
+                                const int64_t* n, const int32_t* p, double tol,
+                                const tls_options* opt, void* stream, double* coef_packed,
+                                const int64_t* coef_offset, tls_result* out,
+                                tls_status* per_fit_status);
+
 /* ---- step-level entry points (device pointers; work enqueued on stream) ----
  * These run one step of the path on its own so that each step can be checked
  * against the CPU oracle.  prec: TLS_PREC_F64 or TLS_PREC_MIXED (FP32 data).

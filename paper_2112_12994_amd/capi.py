@@ -121,6 +121,10 @@ _SIGS = {
     "tls_fit_batch": (_i32, [_ctxp, _i32, _c.POINTER(_dp), _c.POINTER(_i64), _c.POINTER(_i32),
                              _c.c_double, _c.POINTER(TlsOptions), _dp, _c.POINTER(_i64), _dp,
                              _c.POINTER(_i32), _c.POINTER(_i32)]),
+    "tls_fit_batch_device": (_i32, [_ctxp, _i32, _c.POINTER(_vp), _c.POINTER(_i64),
+                                    _c.POINTER(_i32), _c.c_double, _c.POINTER(TlsOptions), _vp,
+                                    _dp, _c.POINTER(_i64), _c.POINTER(TlsResult),
+                                    _c.POINTER(_i32)]),
     "tls_num_blocks": (_i64, [_i64, _i32, _i32]),
     "tls_op_spectra": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _vp, _vp]),
     "tls_op_toeplitz": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _dp, _c.c_double, _c.c_double,
@@ -281,6 +285,32 @@ class Context:
                               sts.ctypes.data_as(_c.POINTER(_i32)))
         outs = [{"status": int(sts[i]), "coef": coef[off[i]: off[i] + ps[i]].copy(),
                  "resid_norm": float(rn[i]), "iters": int(its[i])} for i in range(count)]
+        return s, outs
+
+    def fit_batch_device(self, d_series_list, p_list, tol: float = 1e-10, stream=None, **opts):
+        """tls_fit_batch_device on torch float64 device tensors: (status,
+        list of dicts with status, coef and the result fields)."""
+        count = len(d_series_list)
+        ptrs = (_vp * count)(*[_ptr(t) for t in d_series_list])
+        ns = np.array([t.numel() for t in d_series_list], dtype=np.int64)
+        ps = np.array(p_list, dtype=np.int32)
+        off = np.zeros(count, dtype=np.int64)
+        if count:
+            off[1:] = np.cumsum(ps[:-1])
+        coef = np.zeros(int(ps.sum()) if count else 0)
+        res = (TlsResult * max(count, 1))()
+        sts = np.zeros(count, dtype=np.int32)
+        o = self._opt(opts)
+        s = lib.tls_fit_batch_device(self._h, count, ptrs, ns.ctypes.data_as(_c.POINTER(_i64)),
+                                     ps.ctypes.data_as(_c.POINTER(_i32)), tol, ctypes.byref(o),
+                                     _stream(stream), _dptr(coef),
+                                     off.ctypes.data_as(_c.POINTER(_i64)), res,
+                                     sts.ctypes.data_as(_c.POINTER(_i32)))
+        outs = []
+        for i in range(count):
+            d = res[i].as_dict()
+            d.update(status=int(sts[i]), coef=coef[off[i]: off[i] + ps[i]].copy())
+            outs.append(d)
         return s, outs
 
     # ---- step-level calls (torch device tensors) ----------------------------

@@ -1,0 +1,469 @@
+// Batched driver: many independent AR(p) fits of different lengths and orders
+// in one pass over the device.
+//
+// Every kernel of the single-fit path has a batched twin that maps its
+// workgroup index through a table of work items {fit, local index} to a
+// per-fit descriptor (FitDesc), so one launch serves the blocks, rows, tiles
+// or columns of all fits of a launch class.  A launch class groups the fits
+// that share every compile-time choice the single-fit path makes for them:
+// the FFT half-length, the register-tile counts of the Cholesky (q = p + 1)
+// and of the triangular inverse (p), and whether the LSQR step stages M in
+// LDS.  Within a class each fit runs exactly the arithmetic of its single
+// fit, so the result of fit i equals tls_fit_ex with request_id + i bit for
+// bit.  Fits that finish early leave their later workgroups with nothing to
+// do (each checks its fit's done flag first); device counters tell the host
+// when a whole class has finished.
+#include "engine.h"
+
+#include <map>
+#include <tuple>
+
+namespace {
+
+constexpr int B_CHUNK_ITERS = 8;
+constexpr int B_INNER_CHUNK = 6;
+
+struct FitRec {
+  double rr, dmax, dmin, rnorm, arnorm;
+  int status[4];
+  int iters, istop, refine, pad;
+};
+
+struct List {
+  int off = 0, n = 0;
+};
+
+struct Cls {
+  int lgn = 0, qt = 0, pt = 0;
+  bool mlds = false;
+  int first = 0, count = 0, pmax = 0, ldqmax = 0;
+  List blocks, blocks1, rows1, rows2, tiles1, tiles2, rowtiles2, trmm2, fits, fits1, jl, chunks, draws, cols,
+      rblocks;
+};
+
+__global__ void init_b_kernel(FitDesc* D, int nfits, double tol, int max_iter, int max_refine,
+                              int inner_max, double inner_tol) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nfits) return;
+  const FitDesc& d = D[f];
+  LsqrState s{};
+  s.tol = tol;
+  s.max_iter = max_iter;
+  s.coef[0] = -1.0;
+  s.coef[1] = 1.0;
+  *d.st = s;
+  RefineState r{};
+  r.tol = tol;
+  r.max_refine = max_refine;
+  r.inner_max = inner_max;
+  r.inner_tol = inner_tol;
+  *d.rst = r;
+  d.status[0] = d.status[1] = d.status[2] = d.status[3] = 0;
+}
+
+// After the final QR: zero phi0 for a cold start; the mixed refinement starts
+// from phi = phi0.
+__global__ void post_qr_b_kernel(const FitDesc* D, int warm, int mixed) {
+  const FitDesc& d = D[blockIdx.x];
+  for (int i = threadIdx.x; i < d.p; i += blockDim.x) {
+    const double v = warm ? d.phi0[i] : 0.0;
+    if (!warm) d.phi0[i] = 0.0;
+    if (mixed) d.phi[i] = v;
+  }
+}
+
+__global__ void zero_ints_kernel(int* x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+// Item idx = offset of the fit's coefficients in the packed output.
+__global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* __restrict__ D,
+                                 int mixed, double* __restrict__ coef, FitRec* __restrict__ rec) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  for (int i = threadIdx.x; i < d.p; i += blockDim.x) coef[it.idx + i] = d.phi[i];
+  if (threadIdx.x == 0) {
+    FitRec r{};
+    r.rr = d.rr[0];
+    r.dmax = d.dminmax[0];
+    r.dmin = d.dminmax[1];
+    for (int k = 0; k < 4; ++k) r.status[k] = d.status[k];
+    if (mixed) {
+      const RefineState& s = *d.rst;
+      r.rnorm = s.rnorm;
+      r.arnorm = s.hnorm;
+      r.iters = s.total_inner;
+      r.refine = s.outer;
+      r.istop = s.stop == 1 ? 2 : (s.stop == 7 ? 7 : (s.stop == 5 ? 5 : 0));
+    } else {
+      const LsqrState& s = *d.st;
+      r.rnorm = s.rnorm;
+      r.arnorm = s.arnorm;
+      r.iters = s.iter;
+      r.istop = s.istop;
+    }
+    rec[it.fit] = r;
+  }
+}
+
+void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, FitDesc* d) {
+  *d = FitDesc{};
+  d->y = y;
+  d->n = pl.n;
+  d->m = pl.m;
+  d->p = pl.p;
+  d->q = pl.q;
+  d->ldq = pl.ldq;
+  d->c = pl.c;
+  d->crows = pl.crows;
+  d->k = pl.k;
+  d->L = pl.L;
+  d->nblocks = pl.nblocks;
+  d->nchunks = static_cast<int>((sample_work_doubles(pl.m) - 1) / 2);
+  d->all_rows = pl.all_rows;
+  d->fit = fit;
+  d->Yhat = b.Yhat;
+  d->Yhat64 = b.Yhat64;
+  d->u = b.u;
+  d->partial = b.partial;
+  d->g = b.g;
+  d->A = b.A;
+  d->G = b.G;
+  d->R1 = b.R1;
+  d->R2 = b.R2;
+  d->R = b.R;
+  d->M = b.M;
+  d->Mt = b.Mt;
+  d->M0 = b.M0;
+  d->Mt0 = b.Mt0;
+  d->Pi = b.Pi;
+  d->Om = b.Om;
+  d->Omhat = b.Omhat;
+  d->Vhat = b.Vhat;
+  d->Vhat32 = b.Vhat32;
+  d->v = b.v;
+  d->w = b.w;
+  d->z = b.z;
+  d->phi0 = b.phi0;
+  d->phi = b.phi;
+  d->idx = b.idx;
+  d->scale = b.scale;
+  d->swork = b.swork;
+  d->st = b.st;
+  d->rst = b.rst;
+  d->status = b.status;
+  d->rpart = b.rpart;
+  d->rr = b.rr;
+  d->dminmax = b.dminmax;
+  d->cw = b.cw;
+  d->cres = b.cres;
+  d->cd = b.cd;
+}
+
+template <typename F>
+List add_items(std::vector<Item>& all, const Cls& c, const std::vector<Plan>& plans,
+               const std::vector<int>& order, F&& per_fit) {
+  List l;
+  l.off = static_cast<int>(all.size());
+  for (int j = c.first; j < c.first + c.count; ++j) {
+    const int cnt = per_fit(plans[order[j]]);
+    for (int i = 0; i < cnt; ++i) all.push_back({j, i});
+  }
+  l.n = static_cast<int>(all.size()) - l.off;
+  return l;
+}
+
+}  // namespace
+
+tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
+                     const double* const* dev_series, const int64_t* n, const int32_t* p,
+                     double tol, const tls_options& o, hipStream_t s, double* coef_packed,
+                     const int64_t* coef_offset, tls_result* res, tls_status* fit_status) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int prec = o.precision;
+  const bool mixed = prec == TLS_PREC_MIXED;
+  const bool leverage = o.sketch == TLS_SKETCH_LEVERAGE;
+  const bool copy_y = host_series != nullptr;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
+  const int max_refine = o.max_refine > 0 ? o.max_refine : 8;
+  const int inner_max = std::min(max_iter, 25);
+
+  std::vector<Plan> plans(count);
+  std::vector<tls_status> st(count, TLS_OK);
+  std::vector<int> singles;  // fits outside the batched kernels' limits
+  using Key = std::tuple<int, int, int, int>;
+  std::map<Key, std::vector<int>> groups;
+  for (int i = 0; i < count; ++i) {
+    if (copy_y ? !host_series[i] : !dev_series[i]) {
+      st[i] = TLS_EINVAL;
+      continue;
+    }
+    st[i] = validate(n[i], p[i], tol, o);
+    if (st[i] == TLS_OK && copy_y)
+      for (int64_t t = 0; t < n[i]; ++t)
+        if (!isfinite(host_series[i][t])) {
+          st[i] = TLS_EINVAL;
+          break;
+        }
+    if (st[i] == TLS_OK) st[i] = make_plan(n[i], p[i], o, &plans[i]);
+    if (st[i] != TLS_OK) continue;
+    const Plan& pl = plans[i];
+    if (pl.ldq > 1024) {
+      singles.push_back(i);
+      continue;
+    }
+    const int qt = (pl.q + 15) / 16 <= 8 ? (pl.q + 15) / 16 : 0;
+    const int pt = pl.p <= 128 ? (pl.p + 15) / 16 : 0;
+    groups[Key(pl.lgn, qt, pt, lsqr_step_lds(pl.lgn, pl.p) ? 1 : 0)].push_back(i);
+  }
+
+  // Order the batched fits by class; build the classes and their item lists.
+  std::vector<int> order;
+  std::vector<Cls> classes;
+  for (auto& kv : groups) {
+    Cls c;
+    c.lgn = std::get<0>(kv.first);
+    c.qt = std::get<1>(kv.first);
+    c.pt = std::get<2>(kv.first);
+    c.mlds = std::get<3>(kv.first) != 0;
+    c.first = static_cast<int>(order.size());
+    c.count = static_cast<int>(kv.second.size());
+    for (int i : kv.second) {
+      order.push_back(i);
+      c.pmax = std::max(c.pmax, plans[i].p);
+      c.ldqmax = std::max(c.ldqmax, plans[i].ldq);
+    }
+    classes.push_back(c);
+  }
+  const int nb = static_cast<int>(order.size());
+  std::vector<Item> items;
+  for (Cls& c : classes) {
+    const bool lev = leverage;
+    c.blocks = add_items(items, c, plans, order, [](const Plan& q) { return q.nblocks; });
+    c.blocks1 = add_items(items, c, plans, order,
+                          [lev](const Plan& q) { return lev && !q.all_rows ? q.nblocks : 0; });
+    c.rows1 = add_items(items, c, plans, order, [](const Plan& q) { return q.crows; });
+    c.rows2 = add_items(items, c, plans, order,
+                        [lev](const Plan& q) { return lev && !q.all_rows ? q.crows : 0; });
+    c.tiles1 = add_items(items, c, plans, order, [lev](const Plan& q) {
+      return lev && !q.all_rows ? (q.ldq / 16) * (q.ldq / 16) : 0;
+    });
+    c.tiles2 = add_items(items, c, plans, order,
+                         [](const Plan& q) { return (q.ldq / 16) * (q.ldq / 16); });
+    c.rowtiles2 = add_items(items, c, plans, order, [](const Plan& q) { return q.crows / 16; });
+    c.trmm2 = add_items(items, c, plans, order, [](const Plan& q) { return q.q; });
+    c.fits = add_items(items, c, plans, order, [](const Plan&) { return 1; });
+    c.fits1 = add_items(items, c, plans, order,
+                        [lev](const Plan& q) { return lev && !q.all_rows ? 1 : 0; });
+    c.jl = add_items(items, c, plans, order,
+                     [lev](const Plan& q) { return lev && !q.all_rows ? q.k : 0; });
+    c.chunks = add_items(items, c, plans, order, [lev](const Plan& q) {
+      return lev && !q.all_rows ? static_cast<int>((sample_work_doubles(q.m) - 1) / 2) : 0;
+    });
+    c.draws = add_items(items, c, plans, order,
+                        [lev](const Plan& q) { return lev && !q.all_rows ? q.c : 0; });
+    c.cols = add_items(items, c, plans, order, [](const Plan& q) { return q.p + 1; });
+    c.rblocks = add_items(items, c, plans, order,
+                          [](const Plan& q) { return resid_direct_blocks(q.m); });
+  }
+  // collect list: every batched fit, idx = offset of its packed coefficients
+  const int collect_off = static_cast<int>(items.size());
+  int64_t coef_total = 0;
+  for (int j = 0; j < nb; ++j) {
+    items.push_back({j, static_cast<int>(coef_total)});
+    coef_total += plans[order[j]].p;
+  }
+  if (coef_total > (int64_t{1} << 30)) return TLS_EUNSUPPORTED;
+
+  // Workspace: per-fit buffers, then the descriptors, items, counters and outputs.
+  size_t total = 0;
+  auto reserve = [&total](size_t bytes) {
+    const size_t at = (total + 255) & ~size_t{255};
+    total = at + bytes;
+    return at;
+  };
+  std::vector<size_t> fit_off(nb);
+  for (int j = 0; j < nb; ++j) {
+    FitBufs tmp{};
+    fit_off[j] = reserve(carve(plans[order[j]], copy_y, &tmp, nullptr));
+  }
+  const size_t ncounts = 2 * std::max<size_t>(classes.size(), 1);
+  const size_t off_D = reserve(sizeof(FitDesc) * std::max(nb, 1));
+  const size_t off_items = reserve(sizeof(Item) * std::max<size_t>(items.size(), 1));
+  const size_t off_counts = reserve(sizeof(int) * ncounts);
+  const size_t off_coef = reserve(sizeof(double) * std::max<int64_t>(coef_total, 1));
+  const size_t off_rec = reserve(sizeof(FitRec) * std::max(nb, 1));
+  if (nb > 0) TLS_CHECK(ensure_ws(ctx, total + 256));
+  char* base = static_cast<char*>(ctx->ws);
+
+  std::vector<FitDesc> desc(nb);
+  std::vector<FitBufs> bufs(nb);
+  for (int j = 0; j < nb; ++j) {
+    const int i = order[j];
+    carve(plans[i], copy_y, &bufs[j], base + fit_off[j]);
+    const double* y = copy_y ? bufs[j].y : dev_series[i];
+    if (copy_y)
+      TLS_CHECK(hipMemcpyAsync(bufs[j].y, host_series[i], plans[i].n * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+    fill_desc(plans[i], bufs[j], y, static_cast<uint32_t>(o.request_id + static_cast<uint64_t>(i)),
+              &desc[j]);
+  }
+  FitDesc* D = reinterpret_cast<FitDesc*>(base + off_D);
+  const Item* I = reinterpret_cast<const Item*>(base + off_items);
+  int* counts = reinterpret_cast<int*>(base + off_counts);
+  double* dcoef = reinterpret_cast<double*>(base + off_coef);
+  FitRec* drec = reinterpret_cast<FitRec*>(base + off_rec);
+  // pinned: two counters, the fit records, the packed coefficients
+  const size_t host_bytes = 256 + sizeof(FitRec) * std::max(nb, 1) +
+                            sizeof(double) * std::max<int64_t>(coef_total, 1);
+  TLS_CHECK(ensure_pinned(ctx, host_bytes));
+  int* hcounts = static_cast<int*>(ctx->pinned);
+  FitRec* hrec = reinterpret_cast<FitRec*>(static_cast<char*>(ctx->pinned) + 256);
+  double* hcoef = reinterpret_cast<double*>(hrec + std::max(nb, 1));
+
+  if (nb > 0) {
+    TLS_CHECK(hipMemcpyAsync(D, desc.data(), sizeof(FitDesc) * nb, hipMemcpyHostToDevice, s));
+    TLS_CHECK(hipMemcpyAsync(base + off_items, items.data(), sizeof(Item) * items.size(),
+                             hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(init_b_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, D, nb, tol, max_iter,
+                       max_refine, inner_max, 1e-5);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, counts, static_cast<int>(ncounts));
+    TLS_CHECK(hipGetLastError());
+  }
+  const uint64_t seed = o.seed;
+  const int cprec = mixed ? PREC_F32 : PREC_F64;
+#define L_(lst) I + c.lst.off, c.lst.n
+  for (const Cls& c : classes) {
+    int* cnt = counts + 2 * (&c - classes.data());
+    // spectra of the series blocks (mixed: FP32 for the products, FP64 for the residuals)
+    TLS_CHECK(launch_spectra_b(cprec, c.lgn, L_(blocks), D, 0, ctx->tw, s));
+    if (mixed) TLS_CHECK(launch_spectra_b(PREC_F64, c.lgn, L_(blocks), D, 1, ctx->tw, s));
+    // sketch -> R
+    TLS_CHECK(launch_gather_b(1, L_(rows1), D, seed, s));
+    if (c.fits1.n > 0) {
+      TLS_CHECK(launch_qr_b(1, c.qt, L_(tiles1), nullptr, 0, nullptr, 0, L_(fits1), c.ldqmax, D, s));
+      TLS_CHECK(launch_triinv_b(1, c.pt, L_(fits1), c.pmax, D, s));
+      TLS_CHECK(launch_jl_b(L_(jl), D, o.jl_kind, c.pmax, seed, s));
+      TLS_CHECK(launch_small_rfft_b(cprec, c.lgn, 0, L_(jl), D, ctx->tw, s));
+      TLS_CHECK(launch_scores_b(cprec, c.lgn, L_(blocks1), D, ctx->tw, s));
+      TLS_CHECK(launch_sample_b(cprec, L_(chunks), L_(draws), L_(fits1), D, seed, s));
+      TLS_CHECK(launch_gather_b(2, L_(rows2), D, seed, s));
+    }
+    TLS_CHECK(launch_qr_b(2, c.qt, L_(tiles2), L_(rowtiles2), L_(trmm2), L_(fits), c.ldqmax, D, s));
+    TLS_CHECK(launch_triinv_b(2, c.pt, L_(fits), c.pmax, D, s));
+    hipLaunchKernelGGL(post_qr_b_kernel, dim3(c.count), dim3(64), 0, s, D + c.first,
+                       o.warm_start ? 1 : 0, mixed ? 1 : 0);
+    TLS_CHECK(hipGetLastError());
+
+    if (!mixed) {
+      TLS_CHECK(launch_small_rfft_b(PREC_F64, c.lgn, 1, L_(fits), D, ctx->tw, s));
+      TLS_CHECK(launch_toep_b(PREC_F64, c.lgn, BP_LSQR_FIRST, L_(blocks), D, ctx->consts, ctx->tw, s));
+      TLS_CHECK(launch_colsum_b(0, L_(cols), D, s));
+      TLS_CHECK(launch_lsqr_step_b(PREC_F64, c.lgn, c.count, c.pmax, c.mlds, D + c.first, cnt,
+                                   ctx->tw, s));
+      int launched = 0;
+      for (;;) {
+        for (int it = 0; it < B_CHUNK_ITERS; ++it) {
+          TLS_CHECK(launch_toep_b(PREC_F64, c.lgn, BP_LSQR, L_(blocks), D, ctx->consts, ctx->tw, s));
+          TLS_CHECK(launch_colsum_b(0, L_(cols), D, s));
+          TLS_CHECK(launch_lsqr_step_b(PREC_F64, c.lgn, c.count, c.pmax, c.mlds, D + c.first, cnt,
+                                       ctx->tw, s));
+        }
+        launched += B_CHUNK_ITERS;
+        TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        TLS_CHECK(hipStreamSynchronize(s));
+        if (hcounts[0] >= c.count || launched > max_iter + B_CHUNK_ITERS) break;
+      }
+    } else {
+      for (int outer = 0; outer <= max_refine; ++outer) {
+        hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, cnt, 2);
+        TLS_CHECK(launch_small_rfft_b(PREC_F64, c.lgn, 2, L_(fits), D, ctx->tw, s));
+        TLS_CHECK(launch_toep_b(PREC_F64, c.lgn, BP_OUTER64, L_(blocks), D, ctx->consts, ctx->tw, s));
+        TLS_CHECK(launch_colsum_b(1, L_(cols), D, s));
+        TLS_CHECK(launch_refine_outer_b(c.lgn, c.count, c.pmax, D + c.first, cnt, ctx->tw, s));
+        for (int it = 0; it < inner_max; it += B_INNER_CHUNK) {
+          for (int k = it; k < std::min(inner_max, it + B_INNER_CHUNK); ++k) {
+            TLS_CHECK(launch_toep_b(PREC_F32, c.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
+                                    ctx->tw, s));
+            TLS_CHECK(launch_colsum_b(2, L_(cols), D, s));
+            TLS_CHECK(launch_refine_cg_b(c.lgn, c.count, c.pmax, D + c.first, cnt, ctx->tw, s));
+          }
+          TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+          TLS_CHECK(hipStreamSynchronize(s));
+          if (hcounts[1] >= c.count) break;
+        }
+        if (hcounts[0] >= c.count) break;
+      }
+    }
+    // FP64 residual of the returned coefficients, row by row
+    TLS_CHECK(launch_resid_b(L_(rblocks), D, c.pmax, s));
+    TLS_CHECK(launch_colsum_b(3, L_(fits), D, s));
+  }
+#undef L_
+  if (nb > 0) {
+    hipLaunchKernelGGL(collect_b_kernel, dim3(nb), dim3(64), 0, s, I + collect_off, D, mixed ? 1 : 0,
+                       dcoef, drec);
+    TLS_CHECK(hipGetLastError());
+    TLS_CHECK(hipMemcpyAsync(hrec, drec, sizeof(FitRec) * nb, hipMemcpyDeviceToHost, s));
+    TLS_CHECK(hipMemcpyAsync(hcoef, dcoef, sizeof(double) * coef_total, hipMemcpyDeviceToHost, s));
+    TLS_CHECK(hipStreamSynchronize(s));
+  }
+  const auto t1 = std::chrono::steady_clock::now();
+  const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+
+  int64_t off = 0;
+  for (int j = 0; j < nb; ++j) {
+    const int i = order[j];
+    const Plan& pl = plans[i];
+    const FitRec& r = hrec[j];
+    double* coef = coef_packed + coef_offset[i];
+    memcpy(coef, hcoef + off, pl.p * sizeof(double));
+    off += pl.p;
+    if (res) {
+      tls_result& o_ = res[i];
+      memset(&o_, 0, sizeof(o_));
+      o_.resid_norm = sqrt(r.rr);
+      o_.kappa_est = r.dmin > 0 ? r.dmax / r.dmin : INFINITY;
+      o_.lsqr_rnorm = r.rnorm;
+      o_.lsqr_arnorm = r.arnorm;
+      o_.iters = r.iters;
+      o_.istop = r.istop;
+      o_.refine_steps = r.refine;
+      o_.sketch_rows = pl.c;
+      o_.block_len = pl.B;
+      o_.n_blocks = pl.nblocks;
+      o_.t_total_ms = ms;
+    }
+    tls_status fs = TLS_OK;
+    for (int k = 0; k < pl.p; ++k)
+      if (!isfinite(coef[k])) fs = TLS_EINVAL;
+    if (fs == TLS_OK) {
+      if ((r.status[0] & 6) || (r.status[1] & 4) || r.istop == 4)
+        fs = TLS_ERANK;
+      else if (r.istop == 7)
+        fs = TLS_ENOCONV;
+    }
+    st[i] = fs;
+  }
+  // Fits beyond the batched kernels' limits run one at a time.
+  for (int i : singles) {
+    tls_options oi = o;
+    oi.request_id = o.request_id + static_cast<uint64_t>(i);
+    tls_result r{};
+    if (copy_y) {
+      st[i] = run_fit(ctx, plans[i], oi, nullptr, host_series[i], tol, s,
+                      coef_packed + coef_offset[i], &r);
+    } else {
+      st[i] = run_fit(ctx, plans[i], oi, dev_series[i], nullptr, tol, s,
+                      coef_packed + coef_offset[i], &r);
+    }
+    if (res) res[i] = r;
+  }
+  tls_status first = TLS_OK;
+  for (int i = 0; i < count; ++i) {
+    if (fit_status) fit_status[i] = st[i];
+    if (st[i] != TLS_OK && first == TLS_OK) first = st[i];
+  }
+  return first;
+}

@@ -1,0 +1,343 @@
+// Shared host-side pieces of the Toeplitz least-squares engine: the context,
+// the device workspace arena, the per-fit plan and buffer carving, and the
+// small set-up kernels used by the single-fit and the batched drivers.
+#pragma once
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+#include "../../include/tls.h"
+
+using namespace tls;
+
+struct tls_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  tls_options opt{};
+  void* tw64 = nullptr;
+  void* tw32 = nullptr;
+  Twiddles tw;
+  double* consts = nullptr;  // {-1, 1, 1, 0}
+  void* ws = nullptr;        // workspace
+  size_t ws_bytes = 0;
+  void* pinned = nullptr;    // host staging
+  size_t pinned_bytes = 0;
+  std::vector<hipEvent_t> events;  // profile = 1: pairs around each Toeplitz pass
+};
+
+struct Plan {
+  int prec, B, lgn, L, nblocks, p, q, ldq, c, crows, k, all_rows;
+  int64_t n, m;
+};
+
+// Device buffers of one fit, carved from the workspace.
+struct FitBufs {
+  double* y;        // series copy (host input) or nullptr
+  void* Yhat;       // spectra in compute precision
+  void* Yhat64;     // FP64 spectra (mixed: residual passes)
+  void* u;          // m-vector (also sketch scores)
+  double* partial;  // (p+1) x nblocks
+  double* g;        // p+1
+  double* A;        // crows x ldq
+  double* G;        // ldq^2 + 2 q^2
+  double *R1, *R2, *R;
+  double *M, *Mt, *M0, *Mt0;
+  double *Pi, *Om;
+  void* Omhat;
+  void* Vhat;
+  double *v, *w, *z, *phi0, *phi;
+  int64_t* idx;
+  double* scale;
+  double* swork;
+  LsqrState* st;
+  int* status;      // [0] QR bits, [1] triinv bits
+  double* dminmax;  // scratch
+  double* rr;       // residual norm^2
+  double* rpart;    // direct residual partials
+  void* Vhat32;     // mixed: FP32 spectrum of the CG direction
+  RefineState* rst; // mixed: refinement state
+  double *cw, *cres, *cd;  // mixed: CG vectors
+};
+
+namespace {
+
+
+constexpr int P_MAX = 1024;
+constexpr int CHUNK_ITERS = 8;
+
+#define TLS_CHECK(call)                          \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_status(e_); \
+  } while (0)
+
+tls_status hip_status(hipError_t e) {
+  if (e == hipErrorOutOfMemory) return TLS_ENOMEM;
+  if (e == hipErrorInvalidValue) return TLS_EUNSUPPORTED;
+  return TLS_EDEVICE;
+}
+
+int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t{1} << l) < x) ++l;
+  return l;
+}
+
+hipError_t build_twiddles(tls_ctx* c) {
+  std::vector<cx<double>> t64(NMAX);
+  std::vector<cx<float>> t32(NMAX);
+  for (int k = 0; k < NMAX; ++k) {
+    const long double a = -2.0L * 3.141592653589793238462643383279502884L * k / BMAX;
+    t64[k] = {static_cast<double>(cosl(a)), static_cast<double>(sinl(a))};
+    t32[k] = {static_cast<float>(cosl(a)), static_cast<float>(sinl(a))};
+  }
+  hipError_t e = hipMalloc(&c->tw64, NMAX * sizeof(cx<double>));
+  if (e != hipSuccess) return e;
+  e = hipMalloc(&c->tw32, NMAX * sizeof(cx<float>));
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(c->tw64, t64.data(), NMAX * sizeof(cx<double>), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(c->tw32, t32.data(), NMAX * sizeof(cx<float>), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  c->tw.d64 = c->tw64;
+  c->tw.d32 = c->tw32;
+  const double k4[4] = {-1.0, 1.0, 1.0, 0.0};
+  e = hipMalloc(&c->consts, sizeof(k4));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(c->consts, k4, sizeof(k4), hipMemcpyHostToDevice);
+}
+
+// Bump allocator over the context workspace (256-byte aligned slices).
+struct Arena {
+  size_t need = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t off = (need + 255) & ~size_t{255};
+    need = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+};
+
+hipError_t ensure_ws(tls_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return hipSuccess;
+  if (c->ws) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  const size_t grow = bytes + bytes / 8;
+  hipError_t e = hipMalloc(&c->ws, grow);
+  if (e != hipSuccess) return e;
+  c->ws_bytes = grow;
+  return hipSuccess;
+}
+
+hipError_t ensure_pinned(tls_ctx* c, size_t bytes) {
+  if (bytes <= c->pinned_bytes) return hipSuccess;
+  if (c->pinned) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_bytes = 0;
+  }
+  hipError_t e = hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  c->pinned_bytes = bytes;
+  return hipSuccess;
+}
+
+// Event pair `i` (created on first use; kept for the context's lifetime).
+hipError_t pass_events(tls_ctx* c, size_t i, hipEvent_t* a, hipEvent_t* b) {
+  while (c->events.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    c->events.push_back(e);
+  }
+  *a = c->events[2 * i];
+  *b = c->events[2 * i + 1];
+  return hipSuccess;
+}
+
+hipStream_t pick_stream(tls_ctx* c, void* s) {
+  return s ? static_cast<hipStream_t>(s) : c->stream;
+}
+
+// ---------------------------------------------------------------------------
+
+int auto_block(int p, int64_t m) {
+  // Smallest power of two >= 8 p (>= 2p always), between 256 and 16384, and
+  // no longer than the data needs: shorter blocks cost fewer FFT flops per
+  // sample, longer ones re-read fewer overlapping samples.
+  int lg = ilog2(8 * static_cast<int64_t>(p));
+  if (lg < 8) lg = 8;
+  const int lgdata = ilog2(m + p);
+  if (lg > lgdata) lg = lgdata < 8 ? 8 : lgdata;
+  if (lg > LG_BMAX) lg = LG_BMAX;
+  while ((1 << lg) < 2 * p) ++lg;
+  return lg;
+}
+
+tls_status make_plan(int64_t n, int p, const tls_options& o, Plan* pl) {
+  pl->n = n;
+  pl->p = p;
+  pl->m = n - p;
+  pl->prec = o.precision;
+  int lg = o.block_lg > 0 ? o.block_lg : auto_block(p, pl->m);
+  if (lg < 7 || lg > LG_BMAX) return TLS_EUNSUPPORTED;
+  pl->B = 1 << lg;
+  if (pl->B < 2 * p) return TLS_EUNSUPPORTED;
+  pl->lgn = lg - 1;
+  pl->L = pl->B - p + 1;
+  pl->nblocks = static_cast<int>((pl->m + pl->L - 1) / pl->L);
+  pl->q = p + 1;
+  pl->ldq = (pl->q + 15) / 16 * 16;
+  const int64_t c = static_cast<int64_t>(o.gamma > 0 ? o.gamma : 8) * p;
+  pl->all_rows = c >= pl->m ? 1 : 0;
+  pl->c = static_cast<int>(pl->all_rows ? pl->m : c);
+  pl->crows = (pl->c + 15) / 16 * 16;
+  pl->k = o.jl_k > 0 ? o.jl_k : 8;
+  return TLS_OK;
+}
+
+tls_status validate(int64_t n, int p, double tol, const tls_options& o) {
+  if (p < 1 || n < 2 * static_cast<int64_t>(p) + 1) return TLS_EINVAL;
+  if (!(tol > 0.0 && tol < 1.0)) return TLS_EINVAL;
+  if (o.precision != TLS_PREC_F64 && o.precision != TLS_PREC_MIXED) return TLS_EINVAL;
+  if (o.sketch != TLS_SKETCH_LEVERAGE && o.sketch != TLS_SKETCH_UNIFORM) return TLS_EINVAL;
+  if (o.jl_kind != TLS_JL_SRHT && o.jl_kind != TLS_JL_GAUSS) return TLS_EINVAL;
+  if (p > P_MAX) return TLS_EUNSUPPORTED;
+  if (n > (int64_t{1} << 40)) return TLS_EUNSUPPORTED;
+  return TLS_OK;
+}
+
+
+size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
+  Arena a;
+  a.base = base;
+  const size_t es = pl.prec == TLS_PREC_F64 ? sizeof(double) : sizeof(float);
+  const size_t N = static_cast<size_t>(pl.B / 2);
+  b->y = copy_y ? a.take<double>(pl.n) : nullptr;
+  b->Yhat = a.take<char>(static_cast<size_t>(pl.nblocks) * N * 2 * es);
+  b->Yhat64 = pl.prec == TLS_PREC_MIXED ? a.take<char>(static_cast<size_t>(pl.nblocks) * N * 16)
+                                        : b->Yhat;
+  b->u = a.take<char>(static_cast<size_t>(pl.m) * (pl.prec == TLS_PREC_F64 ? 8 : 8));
+  b->partial = a.take<double>(static_cast<size_t>(pl.p + 1) * pl.nblocks);
+  b->g = a.take<double>(pl.p + 1);
+  b->A = a.take<double>(static_cast<size_t>(pl.crows) * pl.ldq);
+  b->G = a.take<double>(qr_scratch_doubles(pl.crows, pl.q, pl.ldq));
+  b->R1 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
+  b->R2 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
+  b->R = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
+  b->M = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->Mt = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->M0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->Mt0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
+  b->Pi = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
+  b->Om = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
+  b->Omhat = a.take<char>(static_cast<size_t>(pl.k) * N * 2 * es);
+  b->Vhat = a.take<char>(N * 16);
+  b->v = a.take<double>(pl.p);
+  b->w = a.take<double>(pl.p);
+  b->z = a.take<double>(pl.p);
+  b->phi0 = a.take<double>(pl.p);
+  b->phi = a.take<double>(pl.p);
+  b->idx = a.take<int64_t>(pl.c);
+  b->scale = a.take<double>(pl.c);
+  b->swork = a.take<double>(sample_work_doubles(pl.m));
+  b->st = a.take<LsqrState>(1);
+  b->status = a.take<int>(4);
+  b->dminmax = a.take<double>(4);
+  b->rr = a.take<double>(4);
+  b->rpart = a.take<double>(resid_direct_blocks(pl.m));
+  b->Vhat32 = a.take<char>(N * 8);
+  b->rst = a.take<RefineState>(1);
+  b->cw = a.take<double>(pl.p);
+  b->cres = a.take<double>(pl.p);
+  b->cd = a.take<double>(pl.p);
+  return a.need + 256;
+}
+
+__global__ void fill_state_kernel(LsqrState* st, double tol, int max_iter, int* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    LsqrState s{};
+    s.tol = tol;
+    s.max_iter = max_iter;
+    s.coef[0] = -1.0;
+    s.coef[1] = 1.0;
+    *st = s;
+    status[0] = status[1] = status[2] = status[3] = 0;
+  }
+}
+
+__global__ void fill_refine_kernel(RefineState* st, double tol, int max_refine, int inner_max,
+                                   double inner_tol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    RefineState s{};
+    s.tol = tol;
+    s.max_refine = max_refine;
+    s.inner_max = inner_max;
+    s.inner_tol = inner_tol;
+    *st = s;
+  }
+}
+
+__global__ void copy_vec_kernel(const double* a, int n, double* b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+__global__ void diag_minmax_kernel(const double* R, int q, int p, double* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double a = 0.0, b = INFINITY;
+    for (int i = 0; i < p; ++i) {
+      const double d = fabs(R[static_cast<size_t>(i) * q + i]);
+      a = fmax(a, d);
+      b = fmin(b, d);
+    }
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+__global__ void zero_kernel(double* x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+struct HostOut {
+  union {
+    LsqrState st;
+    RefineState rs;
+  };
+  double dminmax[4];
+  double rr[4];
+  int status[4];
+};
+}  // namespace
+
+// The fit of one series (device series d_y, or host series host_y copied in)
+// on stream s; coef host, p doubles.
+tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const double* d_y_in,
+                   const double* host_y, double tol, hipStream_t s, double* coef, tls_result* res);
+
+// Batched driver: fits of `count` series (host series when host_series is
+// non-null, else device series) grouped into launch classes; per-fit
+// coefficients, results and statuses.
+tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
+                     const double* const* dev_series, const int64_t* n, const int32_t* p,
+                     double tol, const tls_options& o, hipStream_t s, double* coef_packed,
+                     const int64_t* coef_offset, tls_result* res, tls_status* fit_status);

@@ -1,336 +1,8 @@
 // Host engine and C-ABI of the Toeplitz least-squares library: contexts,
 // device workspace, the per-fit plan (FFT block length, sketch size) and the
 // orchestration of the kernels for one fit.
-#include <math.h>
-#include <stdio.h>
-#include <stdlib.h>
-#include <string.h>
+#include "engine.h"
 
-#include <algorithm>
-#include <chrono>
-#include <mutex>
-#include <vector>
-
-#include "common.h"
-#include "kernels.h"
-#include "../../include/tls.h"
-
-using namespace tls;
-
-struct tls_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  tls_options opt{};
-  void* tw64 = nullptr;
-  void* tw32 = nullptr;
-  Twiddles tw;
-  double* consts = nullptr;  // {-1, 1, 1, 0}
-  void* ws = nullptr;        // workspace
-  size_t ws_bytes = 0;
-  void* pinned = nullptr;    // host staging
-  size_t pinned_bytes = 0;
-  std::vector<hipEvent_t> events;  // profile = 1: pairs around each Toeplitz pass
-};
-
-namespace {
-
-constexpr int P_MAX = 1024;
-constexpr int CHUNK_ITERS = 8;
-
-#define TLS_CHECK(call)                          \
-  do {                                           \
-    hipError_t e_ = (call);                      \
-    if (e_ != hipSuccess) return hip_status(e_); \
-  } while (0)
-
-tls_status hip_status(hipError_t e) {
-  if (e == hipErrorOutOfMemory) return TLS_ENOMEM;
-  if (e == hipErrorInvalidValue) return TLS_EUNSUPPORTED;
-  return TLS_EDEVICE;
-}
-
-int ilog2(int64_t x) {
-  int l = 0;
-  while ((int64_t{1} << l) < x) ++l;
-  return l;
-}
-
-hipError_t build_twiddles(tls_ctx* c) {
-  std::vector<cx<double>> t64(NMAX);
-  std::vector<cx<float>> t32(NMAX);
-  for (int k = 0; k < NMAX; ++k) {
-    const long double a = -2.0L * 3.141592653589793238462643383279502884L * k / BMAX;
-    t64[k] = {static_cast<double>(cosl(a)), static_cast<double>(sinl(a))};
-    t32[k] = {static_cast<float>(cosl(a)), static_cast<float>(sinl(a))};
-  }
-  hipError_t e = hipMalloc(&c->tw64, NMAX * sizeof(cx<double>));
-  if (e != hipSuccess) return e;
-  e = hipMalloc(&c->tw32, NMAX * sizeof(cx<float>));
-  if (e != hipSuccess) return e;
-  e = hipMemcpy(c->tw64, t64.data(), NMAX * sizeof(cx<double>), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return e;
-  e = hipMemcpy(c->tw32, t32.data(), NMAX * sizeof(cx<float>), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return e;
-  c->tw.d64 = c->tw64;
-  c->tw.d32 = c->tw32;
-  const double k4[4] = {-1.0, 1.0, 1.0, 0.0};
-  e = hipMalloc(&c->consts, sizeof(k4));
-  if (e != hipSuccess) return e;
-  return hipMemcpy(c->consts, k4, sizeof(k4), hipMemcpyHostToDevice);
-}
-
-// Bump allocator over the context workspace (256-byte aligned slices).
-struct Arena {
-  size_t need = 0;
-  char* base = nullptr;
-  template <typename T>
-  T* take(size_t count) {
-    const size_t off = (need + 255) & ~size_t{255};
-    need = off + count * sizeof(T);
-    return base ? reinterpret_cast<T*>(base + off) : nullptr;
-  }
-};
-
-hipError_t ensure_ws(tls_ctx* c, size_t bytes) {
-  if (bytes <= c->ws_bytes) return hipSuccess;
-  if (c->ws) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return e;
-    hipFree(c->ws);
-    c->ws = nullptr;
-    c->ws_bytes = 0;
-  }
-  const size_t grow = bytes + bytes / 8;
-  hipError_t e = hipMalloc(&c->ws, grow);
-  if (e != hipSuccess) return e;
-  c->ws_bytes = grow;
-  return hipSuccess;
-}
-
-hipError_t ensure_pinned(tls_ctx* c, size_t bytes) {
-  if (bytes <= c->pinned_bytes) return hipSuccess;
-  if (c->pinned) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return e;
-    hipHostFree(c->pinned);
-    c->pinned = nullptr;
-    c->pinned_bytes = 0;
-  }
-  hipError_t e = hipHostMalloc(&c->pinned, bytes, hipHostMallocDefault);
-  if (e != hipSuccess) return e;
-  c->pinned_bytes = bytes;
-  return hipSuccess;
-}
-
-// Event pair `i` (created on first use; kept for the context's lifetime).
-hipError_t pass_events(tls_ctx* c, size_t i, hipEvent_t* a, hipEvent_t* b) {
-  while (c->events.size() < 2 * (i + 1)) {
-    hipEvent_t e;
-    hipError_t r = hipEventCreate(&e);
-    if (r != hipSuccess) return r;
-    c->events.push_back(e);
-  }
-  *a = c->events[2 * i];
-  *b = c->events[2 * i + 1];
-  return hipSuccess;
-}
-
-hipStream_t pick_stream(tls_ctx* c, void* s) {
-  return s ? static_cast<hipStream_t>(s) : c->stream;
-}
-
-// ---------------------------------------------------------------------------
-struct Plan {
-  int prec, B, lgn, L, nblocks, p, q, ldq, c, crows, k, all_rows;
-  int64_t n, m;
-};
-
-int auto_block(int p, int64_t m) {
-  // Smallest power of two >= 8 p (>= 2p always), between 256 and 16384, and
-  // no longer than the data needs: shorter blocks cost fewer FFT flops per
-  // sample, longer ones re-read fewer overlapping samples.
-  int lg = ilog2(8 * static_cast<int64_t>(p));
-  if (lg < 8) lg = 8;
-  const int lgdata = ilog2(m + p);
-  if (lg > lgdata) lg = lgdata < 8 ? 8 : lgdata;
-  if (lg > LG_BMAX) lg = LG_BMAX;
-  while ((1 << lg) < 2 * p) ++lg;
-  return lg;
-}
-
-tls_status make_plan(int64_t n, int p, const tls_options& o, Plan* pl) {
-  pl->n = n;
-  pl->p = p;
-  pl->m = n - p;
-  pl->prec = o.precision;
-  int lg = o.block_lg > 0 ? o.block_lg : auto_block(p, pl->m);
-  if (lg < 7 || lg > LG_BMAX) return TLS_EUNSUPPORTED;
-  pl->B = 1 << lg;
-  if (pl->B < 2 * p) return TLS_EUNSUPPORTED;
-  pl->lgn = lg - 1;
-  pl->L = pl->B - p + 1;
-  pl->nblocks = static_cast<int>((pl->m + pl->L - 1) / pl->L);
-  pl->q = p + 1;
-  pl->ldq = (pl->q + 15) / 16 * 16;
-  const int64_t c = static_cast<int64_t>(o.gamma > 0 ? o.gamma : 8) * p;
-  pl->all_rows = c >= pl->m ? 1 : 0;
-  pl->c = static_cast<int>(pl->all_rows ? pl->m : c);
-  pl->crows = (pl->c + 15) / 16 * 16;
-  pl->k = o.jl_k > 0 ? o.jl_k : 8;
-  return TLS_OK;
-}
-
-tls_status validate(int64_t n, int p, double tol, const tls_options& o) {
-  if (p < 1 || n < 2 * static_cast<int64_t>(p) + 1) return TLS_EINVAL;
-  if (!(tol > 0.0 && tol < 1.0)) return TLS_EINVAL;
-  if (o.precision != TLS_PREC_F64 && o.precision != TLS_PREC_MIXED) return TLS_EINVAL;
-  if (o.sketch != TLS_SKETCH_LEVERAGE && o.sketch != TLS_SKETCH_UNIFORM) return TLS_EINVAL;
-  if (o.jl_kind != TLS_JL_SRHT && o.jl_kind != TLS_JL_GAUSS) return TLS_EINVAL;
-  if (p > P_MAX) return TLS_EUNSUPPORTED;
-  if (n > (int64_t{1} << 40)) return TLS_EUNSUPPORTED;
-  return TLS_OK;
-}
-
-// Device buffers of one fit, carved from the workspace.
-struct FitBufs {
-  double* y;        // series copy (host input) or nullptr
-  float* y32;       // FP32 series (mixed)
-  void* Yhat;       // spectra in compute precision
-  void* Yhat64;     // FP64 spectra (mixed: residual passes)
-  void* u;          // m-vector (also sketch scores)
-  double* partial;  // (p+1) x nblocks
-  double* g;        // p+1
-  double* A;        // crows x ldq
-  double* G;        // ldq^2 + 2 q^2
-  double *R1, *R2, *R;
-  double *M, *Mt, *M0, *Mt0;
-  double *Pi, *Om;
-  void* Omhat;
-  void* Vhat;
-  double *v, *w, *z, *phi0, *phi;
-  int64_t* idx;
-  double* scale;
-  double* swork;
-  LsqrState* st;
-  int* status;      // [0] QR bits, [1] triinv bits
-  double* dminmax;  // scratch
-  double* rr;       // residual norm^2
-  double* rpart;    // direct residual partials
-  void* Vhat32;     // mixed: FP32 spectrum of the CG direction
-  RefineState* rst; // mixed: refinement state
-  double *cw, *cres, *cd;  // mixed: CG vectors
-};
-
-size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
-  Arena a;
-  a.base = base;
-  const size_t es = pl.prec == TLS_PREC_F64 ? sizeof(double) : sizeof(float);
-  const size_t N = static_cast<size_t>(pl.B / 2);
-  b->y = copy_y ? a.take<double>(pl.n) : nullptr;
-  b->y32 = pl.prec == TLS_PREC_MIXED ? a.take<float>(pl.n) : nullptr;
-  b->Yhat = a.take<char>(static_cast<size_t>(pl.nblocks) * N * 2 * es);
-  b->Yhat64 = pl.prec == TLS_PREC_MIXED ? a.take<char>(static_cast<size_t>(pl.nblocks) * N * 16)
-                                        : b->Yhat;
-  b->u = a.take<char>(static_cast<size_t>(pl.m) * (pl.prec == TLS_PREC_F64 ? 8 : 8));
-  b->partial = a.take<double>(static_cast<size_t>(pl.p + 1) * pl.nblocks);
-  b->g = a.take<double>(pl.p + 1);
-  b->A = a.take<double>(static_cast<size_t>(pl.crows) * pl.ldq);
-  b->G = a.take<double>(qr_scratch_doubles(pl.crows, pl.q, pl.ldq));
-  b->R1 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
-  b->R2 = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
-  b->R = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
-  b->M = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
-  b->Mt = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
-  b->M0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
-  b->Mt0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
-  b->Pi = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
-  b->Om = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
-  b->Omhat = a.take<char>(static_cast<size_t>(pl.k) * N * 2 * es);
-  b->Vhat = a.take<char>(N * 16);
-  b->v = a.take<double>(pl.p);
-  b->w = a.take<double>(pl.p);
-  b->z = a.take<double>(pl.p);
-  b->phi0 = a.take<double>(pl.p);
-  b->phi = a.take<double>(pl.p);
-  b->idx = a.take<int64_t>(pl.c);
-  b->scale = a.take<double>(pl.c);
-  b->swork = a.take<double>(sample_work_doubles(pl.m));
-  b->st = a.take<LsqrState>(1);
-  b->status = a.take<int>(4);
-  b->dminmax = a.take<double>(4);
-  b->rr = a.take<double>(4);
-  b->rpart = a.take<double>(resid_direct_blocks(pl.m));
-  b->Vhat32 = a.take<char>(N * 8);
-  b->rst = a.take<RefineState>(1);
-  b->cw = a.take<double>(pl.p);
-  b->cres = a.take<double>(pl.p);
-  b->cd = a.take<double>(pl.p);
-  return a.need + 256;
-}
-
-__global__ void fill_state_kernel(LsqrState* st, double tol, int max_iter, int* status) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    LsqrState s{};
-    s.tol = tol;
-    s.max_iter = max_iter;
-    s.coef[0] = -1.0;
-    s.coef[1] = 1.0;
-    *st = s;
-    status[0] = status[1] = status[2] = status[3] = 0;
-  }
-}
-
-__global__ void fill_refine_kernel(RefineState* st, double tol, int max_refine, int inner_max,
-                                   double inner_tol) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    RefineState s{};
-    s.tol = tol;
-    s.max_refine = max_refine;
-    s.inner_max = inner_max;
-    s.inner_tol = inner_tol;
-    *st = s;
-  }
-}
-
-__global__ void copy_vec_kernel(const double* a, int n, double* b) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = a[i];
-}
-
-__global__ void diag_minmax_kernel(const double* R, int q, int p, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double a = 0.0, b = INFINITY;
-    for (int i = 0; i < p; ++i) {
-      const double d = fabs(R[static_cast<size_t>(i) * q + i]);
-      a = fmax(a, d);
-      b = fmin(b, d);
-    }
-    out[0] = a;
-    out[1] = b;
-  }
-}
-
-__global__ void zero_kernel(double* x, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = 0.0;
-}
-
-__global__ void to_f32_kernel(const double* x, int64_t n, float* y) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = static_cast<float>(x[i]);
-}
-
-struct HostOut {
-  union {
-    LsqrState st;
-    RefineState rs;
-  };
-  double dminmax[4];
-  double rr[4];
-  int status[4];
-};
-
-// The fit of one series already in device memory (d_y), on stream s.
 tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const double* d_y_in,
                    const double* host_y, double tol, hipStream_t s, double* coef, tls_result* res) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -359,8 +31,6 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
 
   // Spectra of the series blocks.
   if (prec == TLS_PREC_MIXED) {
-    const unsigned nb = static_cast<unsigned>((pl.n + 255) / 256);
-    hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(256), 0, s, d_y, pl.n, b.y32);
     TLS_CHECK(launch_spectra(PREC_F32, pl.lgn, d_y, pl.n, pl.L, pl.nblocks, b.Yhat, ctx->tw, s));
     TLS_CHECK(launch_spectra(PREC_F64, pl.lgn, d_y, pl.n, pl.L, pl.nblocks, b.Yhat64, ctx->tw, s));
   } else {
@@ -395,7 +65,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   TLS_CHECK(hipGetLastError());
 
   int total_iters = 0, istop = 0, refine = 0, pass_count = 0;
-  double pass_ms = 0.0;
+  double pass_ms = 0.0, lsqr_rnorm = 0.0, lsqr_arnorm = 0.0;
   if (prec == TLS_PREC_F64) {
     // LSQR on A = X M from the warm start.
     const int* flag = &b.st->done;
@@ -439,6 +109,8 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     }
     total_iters = ho->st.iter;
     istop = ho->st.istop;
+    lsqr_rnorm = ho->st.rnorm;
+    lsqr_arnorm = ho->st.arnorm;
     if (o.profile) {
       // passes 0 .. iter did work; later launches in the last chunk exit at once
       const size_t worked = std::min(npass, static_cast<size_t>(total_iters) + 1);
@@ -512,6 +184,8 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     TLS_CHECK(hipStreamSynchronize(s));
     total_iters = hr->total_inner;
     refine = hr->outer;
+    lsqr_rnorm = hr->rnorm;
+    lsqr_arnorm = hr->hnorm;
     istop = hr->stop == 1 ? 2 : (hr->stop == 7 ? 7 : (hr->stop == 5 ? 5 : 0));
     if (o.profile) {
       pass_ms = worked_ms;
@@ -534,8 +208,8 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     memset(res, 0, sizeof(*res));
     res->resid_norm = sqrt(ho->rr[0]);
     res->kappa_est = ho->dminmax[1] > 0 ? ho->dminmax[0] / ho->dminmax[1] : INFINITY;
-    res->lsqr_rnorm = ho->st.rnorm;
-    res->lsqr_arnorm = ho->st.arnorm;
+    res->lsqr_rnorm = lsqr_rnorm;
+    res->lsqr_arnorm = lsqr_arnorm;
     res->iters = total_iters;
     res->istop = istop;
     res->refine_steps = refine;
@@ -552,6 +226,8 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   if (istop == 7) return TLS_ENOCONV;
   return TLS_OK;
 }
+
+namespace {
 
 tls_ctx* g_default = nullptr;
 std::mutex g_default_mu;
@@ -689,20 +365,35 @@ tls_status tls_fit_batch(tls_ctx* ctx, int32_t count, const double* const* serie
                          tls_status* per_fit_status) {
   if (!ctx || count < 0 || (count > 0 && (!series || !n || !p || !coef_packed || !coef_offset)))
     return TLS_EINVAL;
-  tls_options o = eff_opt(ctx, opt);
-  const uint64_t rid0 = o.request_id;
-  tls_status first = TLS_OK;
+  hipSetDevice(ctx->device);
+  std::vector<tls_result> r(static_cast<size_t>(count));
+  std::vector<tls_status> fs(static_cast<size_t>(count), TLS_OK);
+  const tls_status first = run_batch(ctx, count, series, nullptr, n, p, tol, eff_opt(ctx, opt),
+                                     ctx->stream, coef_packed, coef_offset, r.data(), fs.data());
   for (int32_t i = 0; i < count; ++i) {
-    o.request_id = rid0 + static_cast<uint64_t>(i);
-    tls_result r;
-    tls_status st = tls_fit_ex(ctx, series[i], n[i], p[i], tol, &o, coef_packed + coef_offset[i], &r);
-    if (per_fit_status) per_fit_status[i] = st;
-    if (st == TLS_OK || st == TLS_ENOCONV || st == TLS_ERANK) {
-      if (resid_norm) resid_norm[i] = r.resid_norm;
-      if (iters) iters[i] = r.iters;
+    if (per_fit_status) per_fit_status[i] = fs[i];
+    if (fs[i] == TLS_OK || fs[i] == TLS_ENOCONV || fs[i] == TLS_ERANK) {
+      if (resid_norm) resid_norm[i] = r[i].resid_norm;
+      if (iters) iters[i] = r[i].iters;
     }
-    if (st != TLS_OK && first == TLS_OK) first = st;
   }
+  return first;
+}
+
+tls_status tls_fit_batch_device(tls_ctx* ctx, int32_t count, const double* const* d_series,
+                                const int64_t* n, const int32_t* p, double tol,
+                                const tls_options* opt, void* stream, double* coef_packed,
+                                const int64_t* coef_offset, tls_result* out,
+                                tls_status* per_fit_status) {
+  if (!ctx || count < 0 || (count > 0 && (!d_series || !n || !p || !coef_packed || !coef_offset)))
+    return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  std::vector<tls_status> fs(static_cast<size_t>(count), TLS_OK);
+  const tls_status first = run_batch(ctx, count, nullptr, d_series, n, p, tol, eff_opt(ctx, opt),
+                                     pick_stream(ctx, stream), coef_packed, coef_offset, out,
+                                     fs.data());
+  if (per_fit_status)
+    for (int32_t i = 0; i < count; ++i) per_fit_status[i] = fs[i];
   return first;
 }
 

@@ -101,6 +101,88 @@ hipError_t launch_refine_cg(int lgn, int p, RefineState* st, const double* g, co
                             const double* Mt, double* w, double* res, double* d, double* phi,
                             void* Vhat32, const Twiddles& tw, hipStream_t s);
 
+// ---- batched fits -----------------------------------------------------------
+// Device descriptor of one fit of a batch: its sizes and its slice of the
+// batch workspace.  Every fit of one batched run shares the FFT block length,
+// the precision and the options.
+struct FitDesc {
+  const double* y;
+  int64_t n, m;
+  int p, q, ldq, c, crows, k, L, nblocks, nchunks, all_rows;
+  uint32_t fit;
+  void* Yhat;
+  void* Yhat64;
+  void* u;
+  double *partial, *g, *A, *G, *R1, *R2, *R, *M, *Mt, *M0, *Mt0, *Pi, *Om;
+  void* Omhat;
+  void* Vhat;
+  void* Vhat32;
+  double *v, *w, *z, *phi0, *phi;
+  int64_t* idx;
+  double *scale, *swork;
+  LsqrState* st;
+  RefineState* rst;
+  int* status;
+  double *rpart, *rr, *dminmax, *cw, *cres, *cd;
+};
+
+// Work items {fit, local index} of a batched launch (one workgroup each).
+struct Item {
+  int fit, idx;
+};
+
+// Variants of the batched Toeplitz pass.
+enum BatchPass : int {
+  BP_LSQR_FIRST = 0,  // e = b - X phi0 into u, X^T e   (FP64 / compute precision)
+  BP_LSQR = 1,        // e = X (M v) - (alpha/beta) u in place, X^T e
+  BP_OUTER64 = 2,     // FP64: r = b - X phi, X^T r (nothing stored)
+  BP_INNER32 = 3,     // FP32: X^T X (M d) (nothing stored)
+};
+
+hipError_t launch_spectra_b(int prec, int lgn, const Item* items, int nitems, const FitDesc* D,
+                            int to64, const Twiddles& tw, hipStream_t st);
+hipError_t launch_toep_b(int prec, int lgn, int variant, const Item* items, int nitems,
+                         const FitDesc* D, const double* consts, const Twiddles& tw,
+                         hipStream_t st);
+hipError_t launch_small_rfft_b(int prec, int lgn, int variant, const Item* items, int nitems,
+                               const FitDesc* D, const Twiddles& tw, hipStream_t st);
+hipError_t launch_scores_b(int prec, int lgn, const Item* items, int nitems, const FitDesc* D,
+                           const Twiddles& tw, hipStream_t st);
+// variant 0: LSQR partials -> g (flag st->done); 1: outer64 (flag rst->done);
+// 2: inner32 (flag rst->inner_done); 3: residual partials -> rr
+hipError_t launch_colsum_b(int variant, const Item* items, int nitems, const FitDesc* D,
+                           hipStream_t st);
+hipError_t launch_resid_b(const Item* items, int nitems, const FitDesc* D, int pmax,
+                          hipStream_t st);
+hipError_t launch_gather_b(int stage, const Item* items, int nitems, const FitDesc* D,
+                           uint64_t seed, hipStream_t st);
+hipError_t launch_sample_b(int prec, const Item* chunk_items, int nchunk_items,
+                           const Item* draw_items, int ndraw_items, const Item* fit_items,
+                           int nfit_items, const FitDesc* D, uint64_t seed, hipStream_t st);
+hipError_t launch_jl_b(const Item* items, int nitems, const FitDesc* D, int kind, int pmax,
+                       uint64_t seed, hipStream_t st);
+// stage 1: one shifted sweep into R (rank bits to status[2]); stage 2: three
+// sweeps into R (status[0]).  Item lists: Gram tiles (fit, tile of the
+// ldq/16 x ldq/16 grid), 16-row tiles (fit, tile), rows of R (fit, row), and
+// one item per fit.  qt = ceil(qmax/16) <= 8, or 0 for the global-memory kernels.
+hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const Item* rowtiles,
+                       int nrowtiles, const Item* rows, int nrows, const Item* fits, int nfits,
+                       int ldqmax, const FitDesc* D, hipStream_t st);
+// stage 1: M0, Mt0 (status[3]); stage 2: M, Mt, phi0 (status[1]), |R_ii| range.
+hipError_t launch_triinv_b(int stage, int pt, const Item* fits, int nfits, int pmax,
+                           const FitDesc* D, hipStream_t st);
+// One workgroup per fit of D[0 .. nfits).  counts[0] += 1 for each fit that
+// finishes (LSQR) or is finished (refinement outer step); counts[1] += 1 for
+// each fit whose inner CG solve is finished.  mlds must equal
+// lsqr_step_lds(lgn, p) for every fit (the single-fit kernel's choice).
+bool lsqr_step_lds(int lgn, int p);
+hipError_t launch_lsqr_step_b(int prec, int lgn, int nfits, int pmax, bool mlds, const FitDesc* D,
+                              int* counts, const Twiddles& tw, hipStream_t st);
+hipError_t launch_refine_outer_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
+                                 const Twiddles& tw, hipStream_t st);
+hipError_t launch_refine_cg_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
+                              const Twiddles& tw, hipStream_t st);
+
 hipError_t launch_vec_axpy_small(const double* M, const double* x, const double* y0, int p,
                                  double* out, hipStream_t st);
 

@@ -22,6 +22,14 @@
 
 namespace tls {
 
+// The step kernel stages M in LDS when p <= 128 and it fits beside the
+// 2^LGN-point transform buffer.
+bool lsqr_step_lds(int lgn, int p) {
+  const size_t with_m = (2 * static_cast<size_t>(p) + static_cast<size_t>(p) * (p | 1)) * sizeof(double);
+  const size_t lds_static = static_cast<size_t>(1 << lgn) * 16 + 64;
+  return p <= 128 && with_m + lds_static <= 160 * 1024;
+}
+
 namespace {
 
 // out[r] = sum_{c in [lo(r), p)} Mrow[r][c] x[c] for the rows r of an upper
@@ -57,7 +65,7 @@ __device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, i
 // MLDS: M (p <= 128) is staged once into LDS (rows padded to an odd length)
 // and every product with M or M^T reads it there.
 template <int LGN, int NT, typename TS, bool MLDS>
-__global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restrict__ st,
+__device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st,
                                                        const double* __restrict__ g,
                                                        const double* __restrict__ M,
                                                        const double* __restrict__ Mt,
@@ -254,6 +262,21 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
   }
 }
 
+template <int LGN, int NT, typename TS, bool MLDS>
+__global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restrict__ st,
+                                                       const double* __restrict__ g,
+                                                       const double* __restrict__ M,
+                                                       const double* __restrict__ Mt,
+                                                       double* __restrict__ v,
+                                                       double* __restrict__ w,
+                                                       double* __restrict__ z,
+                                                       const double* __restrict__ phi0,
+                                                       double* __restrict__ phi,
+                                                       cx<TS>* __restrict__ Vhat,
+                                                       const cx<double>* __restrict__ tab) {
+  lsqr_step_body<LGN, NT, TS, MLDS>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, tab);
+}
+
 template <int LGN, typename TS>
 hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, const double* Mt,
                     double* v, double* w, double* z, const double* phi0, double* phi, void* Vhat,
@@ -261,8 +284,7 @@ hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, cons
   constexpr int NT = 256;
   const size_t small = 2 * static_cast<size_t>(p) * sizeof(double);
   const size_t with_m = small + static_cast<size_t>(p) * (p | 1) * sizeof(double);
-  const size_t lds_static = static_cast<size_t>(1 << LGN) * 16 + 64;
-  if (p <= 128 && with_m + lds_static <= 160 * 1024) {
+  if (lsqr_step_lds(LGN, p)) {
     hipLaunchKernelGGL((lsqr_step_kernel<LGN, NT, TS, true>), dim3(1), dim3(NT), with_m, stream, p,
                        st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
                        static_cast<const cx<double>*>(tw.d64));
@@ -345,7 +367,7 @@ __device__ double dot_block(const double* a, const double* b, int p, double* red
 }
 
 template <int LGN, int NT>
-__global__ __launch_bounds__(NT) void refine_outer_kernel(int p, RefineState* __restrict__ st,
+__device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict__ st,
                                                           const double* __restrict__ g64,
                                                           const double* __restrict__ M,
                                                           const double* __restrict__ Mt,
@@ -409,7 +431,20 @@ __global__ __launch_bounds__(NT) void refine_outer_kernel(int p, RefineState* __
 }
 
 template <int LGN, int NT>
-__global__ __launch_bounds__(NT) void refine_cg_kernel(int p, RefineState* __restrict__ st,
+__global__ __launch_bounds__(NT) void refine_outer_kernel(int p, RefineState* __restrict__ st,
+                                                          const double* __restrict__ g64,
+                                                          const double* __restrict__ M,
+                                                          const double* __restrict__ Mt,
+                                                          double* __restrict__ w,
+                                                          double* __restrict__ res,
+                                                          double* __restrict__ d,
+                                                          cx<float>* __restrict__ Vhat32,
+                                                          const cx<double>* __restrict__ tab) {
+  refine_outer_body<LGN, NT>(p, st, g64, M, Mt, w, res, d, Vhat32, tab);
+}
+
+template <int LGN, int NT>
+__device__ __forceinline__ void refine_cg_body(int p, RefineState* __restrict__ st,
                                                        const double* __restrict__ g,
                                                        const double* __restrict__ M,
                                                        const double* __restrict__ Mt,
@@ -466,6 +501,20 @@ __global__ __launch_bounds__(NT) void refine_cg_kernel(int p, RefineState* __res
     st->total_inner += 1;
     if (finish) st->inner_done = 1;
   }
+}
+
+template <int LGN, int NT>
+__global__ __launch_bounds__(NT) void refine_cg_kernel(int p, RefineState* __restrict__ st,
+                                                       const double* __restrict__ g,
+                                                       const double* __restrict__ M,
+                                                       const double* __restrict__ Mt,
+                                                       double* __restrict__ w,
+                                                       double* __restrict__ res,
+                                                       double* __restrict__ d,
+                                                       double* __restrict__ phi,
+                                                       cx<float>* __restrict__ Vhat32,
+                                                       const cx<double>* __restrict__ tab) {
+  refine_cg_body<LGN, NT>(p, st, g, M, Mt, w, res, d, phi, Vhat32, tab);
 }
 
 template <int LGN>
@@ -565,6 +614,112 @@ hipError_t launch_vec_axpy_small(const double* Mt, const double* x, const double
                                  double* out, hipStream_t st) {
   hipLaunchKernelGGL(gemv_upper_kernel, dim3(1), dim3(256), 0, st, Mt, x, y0, p, out);
   return hipGetLastError();
+}
+
+// ---- batched launches: one workgroup per fit (blockIdx.x indexes D) ----------
+namespace {
+
+// counts[0]: fits whose LSQR (or refinement) has finished; counts[1]: fits
+// whose inner CG solve of the current refinement step has finished.
+template <int LGN, int NT, typename TS, bool MLDS>
+__global__ __launch_bounds__(NT) void lsqr_step_b_kernel(const FitDesc* __restrict__ D,
+                                                         int* __restrict__ counts,
+                                                         const cx<double>* __restrict__ tab) {
+  const FitDesc& d = D[blockIdx.x];
+  if (d.st->done) return;
+  lsqr_step_body<LGN, NT, TS, MLDS>(d.p, d.st, d.g, d.M, d.Mt, d.v, d.w, d.z, d.phi0, d.phi,
+                                    static_cast<cx<TS>*>(d.Vhat), tab);
+  if (threadIdx.x == 0 && d.st->done) atomicAdd(counts, 1);
+}
+
+template <int LGN, int NT>
+__global__ __launch_bounds__(NT) void refine_outer_b_kernel(const FitDesc* __restrict__ D,
+                                                            int* __restrict__ counts,
+                                                            const cx<double>* __restrict__ tab) {
+  const FitDesc& d = D[blockIdx.x];
+  if (!d.rst->done)
+    refine_outer_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.cw, d.cres, d.cd,
+                               static_cast<cx<float>*>(d.Vhat32), tab);
+  if (threadIdx.x == 0) {
+    if (d.rst->done) atomicAdd(counts, 1);
+    if (d.rst->inner_done) atomicAdd(counts + 1, 1);
+  }
+}
+
+template <int LGN, int NT>
+__global__ __launch_bounds__(NT) void refine_cg_b_kernel(const FitDesc* __restrict__ D,
+                                                         int* __restrict__ counts,
+                                                         const cx<double>* __restrict__ tab) {
+  const FitDesc& d = D[blockIdx.x];
+  if (d.rst->inner_done) return;
+  refine_cg_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.cw, d.cres, d.cd, d.phi,
+                          static_cast<cx<float>*>(d.Vhat32), tab);
+  if (threadIdx.x == 0 && d.rst->inner_done) atomicAdd(counts + 1, 1);
+}
+
+template <int LGN, typename TS>
+hipError_t step_b(int nfits, int pmax, bool mlds, const FitDesc* D, int* counts,
+                  const Twiddles& tw, hipStream_t s) {
+  constexpr int NT = 256;
+  const size_t small = 2 * static_cast<size_t>(pmax) * sizeof(double);
+  const size_t with_m = small + static_cast<size_t>(pmax) * (pmax | 1) * sizeof(double);
+  const cx<double>* tab = static_cast<const cx<double>*>(tw.d64);
+  if (mlds)
+    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, true>), dim3(nfits), dim3(NT), with_m, s, D,
+                       counts, tab);
+  else
+    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, false>), dim3(nfits), dim3(NT), small, s, D,
+                       counts, tab);
+  return hipGetLastError();
+}
+
+size_t refine_shm(int pmax) {
+  return (3 * static_cast<size_t>(pmax) +
+          (pmax <= 128 ? static_cast<size_t>(pmax) * (pmax | 1) : 0)) * sizeof(double);
+}
+
+template <int LGN>
+hipError_t outer_b(int nfits, int pmax, const FitDesc* D, int* counts, const Twiddles& tw,
+                   hipStream_t s) {
+  hipLaunchKernelGGL((refine_outer_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax), s,
+                     D, counts, static_cast<const cx<double>*>(tw.d64));
+  return hipGetLastError();
+}
+
+template <int LGN>
+hipError_t cg_b(int nfits, int pmax, const FitDesc* D, int* counts, const Twiddles& tw,
+                hipStream_t s) {
+  hipLaunchKernelGGL((refine_cg_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax), s, D,
+                     counts, static_cast<const cx<double>*>(tw.d64));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_lsqr_step_b(int prec, int lgn, int nfits, int pmax, bool mlds, const FitDesc* D,
+                              int* counts, const Twiddles& tw, hipStream_t s) {
+  if (nfits < 1) return hipSuccess;
+#define TLS_STEP_B(LG)                                                        \
+  (prec == PREC_F64 ? step_b<LG, double>(nfits, pmax, mlds, D, counts, tw, s) \
+                    : step_b<LG, float>(nfits, pmax, mlds, D, counts, tw, s))
+  TLS_LG_SWITCH(TLS_STEP_B)
+#undef TLS_STEP_B
+}
+
+hipError_t launch_refine_outer_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
+                                 const Twiddles& tw, hipStream_t s) {
+  if (nfits < 1) return hipSuccess;
+#define TLS_OUTER_B(LG) outer_b<LG>(nfits, pmax, D, counts, tw, s)
+  TLS_LG_SWITCH(TLS_OUTER_B)
+#undef TLS_OUTER_B
+}
+
+hipError_t launch_refine_cg_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
+                              const Twiddles& tw, hipStream_t s) {
+  if (nfits < 1) return hipSuccess;
+#define TLS_CG_B(LG) cg_b<LG>(nfits, pmax, D, counts, tw, s)
+  TLS_LG_SWITCH(TLS_CG_B)
+#undef TLS_CG_B
 }
 
 }  // namespace tls

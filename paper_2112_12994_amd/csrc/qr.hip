@@ -29,10 +29,10 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 // One 16x16 tile (ti <= tj) of G = A^T A per workgroup of 4 wavefronts; the
 // waves take interleaved 4-row steps and their tiles are summed in a fixed order.
-__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ A, int crows, int ldq,
-                                                   double* __restrict__ G) {
+__device__ __forceinline__ void gram_body(const double* __restrict__ A, int crows, int ldq,
+                                                   double* __restrict__ G, int tile) {
   const int nt = ldq / 16;
-  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  const int ti = tile / nt, tj = tile % nt;
   if (ti > tj) return;
   __shared__ double part[4][16][17];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -55,11 +55,16 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ A,
   G[static_cast<size_t>(gj) * ldq + gi] = s;
 }
 
+__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ A, int crows, int ldq,
+                                                   double* __restrict__ G) {
+  gram_body(A, crows, ldq, G, blockIdx.x);
+}
+
 // Right-looking Cholesky of G[:q,:q] (+ shift on the diagonal) into the upper
 // factor R (row-major q x q, zero below the diagonal).  One workgroup; the
 // working copy lives in R.
 template <int NT>
-__global__ __launch_bounds__(NT) void chol_kernel(const double* __restrict__ G, int ldq, int q,
+__device__ __forceinline__ void chol_body(const double* __restrict__ G, int ldq, int q,
                                                   int crows, int shift, double* __restrict__ R,
                                                   int* __restrict__ status, int fail_bit,
                                                   int rank_cols) {
@@ -112,6 +117,14 @@ __global__ __launch_bounds__(NT) void chol_kernel(const double* __restrict__ G, 
   if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void chol_kernel(const double* __restrict__ G, int ldq, int q,
+                                                  int crows, int shift, double* __restrict__ R,
+                                                  int* __restrict__ status, int fail_bit,
+                                                  int rank_cols) {
+  chol_body<NT>(G, ldq, q, crows, shift, R, status, fail_bit, rank_cols);
+}
+
 // A <- A R^{-1} on the first q columns (each thread owns one row).
 template <int ROWS, int QMAX>
 __global__ __launch_bounds__(ROWS) void trsm_kernel(double* __restrict__ A, int crows, int ldq,
@@ -132,9 +145,9 @@ __global__ __launch_bounds__(ROWS) void trsm_kernel(double* __restrict__ A, int 
 }
 
 // Same, rows kept in place in global memory (large q).
-__global__ __launch_bounds__(64) void trsm_global_kernel(double* __restrict__ A, int crows, int ldq,
-                                                         int q, const double* __restrict__ R) {
-  const int t = blockIdx.x * 64 + threadIdx.x;
+__device__ __forceinline__ void trsm_global_body(double* __restrict__ A, int crows, int ldq,
+                                                         int q, const double* __restrict__ R, int blk) {
+  const int t = blk * 64 + threadIdx.x;
   if (t >= crows) return;
   double* row = A + static_cast<size_t>(t) * ldq;
   for (int j = 0; j < q; ++j) {
@@ -145,12 +158,16 @@ __global__ __launch_bounds__(64) void trsm_global_kernel(double* __restrict__ A,
   }
 }
 
+__global__ __launch_bounds__(64) void trsm_global_kernel(double* __restrict__ A, int crows, int ldq,
+                                                         int q, const double* __restrict__ R) {
+  trsm_global_body(A, crows, ldq, q, R, blockIdx.x);
+}
+
 // C = Ra Rb for upper-triangular q x q (row-major); one workgroup per row.
 template <int NT>
-__global__ __launch_bounds__(NT) void trmm_kernel(const double* __restrict__ Ra,
+__device__ __forceinline__ void trmm_body(const double* __restrict__ Ra,
                                                   const double* __restrict__ Rb, int q,
-                                                  double* __restrict__ C) {
-  const int i = blockIdx.x;
+                                                  double* __restrict__ C, int i) {
   const double* ra = Ra + static_cast<size_t>(i) * q;
   for (int j = threadIdx.x; j < q; j += NT) {
     double acc = 0.0;
@@ -159,10 +176,17 @@ __global__ __launch_bounds__(NT) void trmm_kernel(const double* __restrict__ Ra,
   }
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void trmm_kernel(const double* __restrict__ Ra,
+                                                  const double* __restrict__ Rb, int q,
+                                                  double* __restrict__ C) {
+  trmm_body<NT>(Ra, Rb, q, C, blockIdx.x);
+}
+
 // M = R[:p,:p]^{-1} (row-major, upper), Mt = M^T, phi0 = M R[:p, p] (the
 // compressed problem's solution), and the rank test min|R_ii| <= p u max|R_ii|.
 template <int NT>
-__global__ __launch_bounds__(NT) void triinv_kernel(const double* __restrict__ R, int q, int p,
+__device__ __forceinline__ void triinv_body(const double* __restrict__ R, int q, int p,
                                                     double* __restrict__ M, double* __restrict__ Mt,
                                                     double* __restrict__ phi0,
                                                     int* __restrict__ status) {
@@ -209,6 +233,14 @@ __global__ __launch_bounds__(NT) void triinv_kernel(const double* __restrict__ R
     }
     if (!(b > static_cast<double>(p) * 0x1p-53 * a)) atomicOr(status, 4);
   }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void triinv_kernel(const double* __restrict__ R, int q, int p,
+                                                    double* __restrict__ M, double* __restrict__ Mt,
+                                                    double* __restrict__ phi0,
+                                                    int* __restrict__ status) {
+  triinv_body<NT>(R, q, p, M, Mt, phi0, status);
 }
 
 // ---- LDS-resident variants for q <= 128 (the whole q x q matrix in LDS) ----
@@ -283,7 +315,7 @@ __global__ __launch_bounds__(NT) void chol_lds_kernel(const double* __restrict__
 
 // Cholesky G[:q,:q] (+ shift) = R^T R; shift_mode as in chol_lds_kernel.
 template <int QT>
-__global__ __launch_bounds__(256) void chol_reg_kernel(const double* __restrict__ G, int ldq, int q,
+__device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int ldq, int q,
                                                        int crows, int shift_mode,
                                                        double* __restrict__ R,
                                                        int* __restrict__ status, int fail_bit,
@@ -356,11 +388,20 @@ __global__ __launch_bounds__(256) void chol_reg_kernel(const double* __restrict_
   }
 }
 
+template <int QT>
+__global__ __launch_bounds__(256) void chol_reg_kernel(const double* __restrict__ G, int ldq, int q,
+                                                       int crows, int shift_mode,
+                                                       double* __restrict__ R,
+                                                       int* __restrict__ status, int fail_bit,
+                                                       int rank_cols) {
+  chol_reg_body<QT>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols);
+}
+
 // M = R[:n,:n]^{-1} (upper; row-major, leading dimension ldm, zero elsewhere
 // in the ldm x ldm block): M = I, then for i = n-1 .. 0, row i of M is
 // divided by R_ii and R[r][i] times it is subtracted from every row r < i.
 template <int QT>
-__global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restrict__ R, int ldr, int n,
+__device__ __forceinline__ void triinv_reg_body(const double* __restrict__ R, int ldr, int n,
                                                          double* __restrict__ M, int ldm) {
   extern __shared__ double Rs[];  // n x (n + 1)
   __shared__ double pub[2][16 * QT];
@@ -417,6 +458,12 @@ __global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restric
   }
 }
 
+template <int QT>
+__global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restrict__ R, int ldr, int n,
+                                                         double* __restrict__ M, int ldm) {
+  triinv_reg_body<QT>(R, ldr, n, M, ldm);
+}
+
 // M = R[:n,:n]^{-1} (upper, row-major with leading dimension ldm, zero
 // elsewhere in the ldm x ldm block), rows computed bottom-up in LDS.
 template <int NT>
@@ -452,13 +499,13 @@ __global__ __launch_bounds__(NT) void triinv_lds_kernel(const double* __restrict
 // 16 x 16 diagonal block by forward substitution (one lane per row), then the
 // trailing columns A[:, K] -= X[:, J] R[J, K] on the FP64 matrix cores.
 // Backward stable, unlike a product with an explicitly inverted R.
-__global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, int ldq, int q,
-                                                       const double* __restrict__ R) {
+__device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, int q,
+                                                       const double* __restrict__ R, int rt) {
   extern __shared__ double T[];  // 16 x (ldq + 1) rows of A, then 16 x ldq rows of R
   const int ld = ldq + 1;
   double* Rp = T + 16 * ld;
   const int lane = threadIdx.x;
-  const size_t r0 = static_cast<size_t>(blockIdx.x) * 16;
+  const size_t r0 = static_cast<size_t>(rt) * 16;
   for (int e = lane; e < 16 * ldq; e += 64) T[(e / ldq) * ld + e % ldq] = A[(r0 + e / ldq) * ldq + e % ldq];
   const int nt = (q + 15) / 16;
   for (int J = 0; J < nt; ++J) {
@@ -498,6 +545,11 @@ __global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, i
   for (int e = lane; e < 16 * ldq; e += 64) A[(r0 + e / ldq) * ldq + e % ldq] = T[(e / ldq) * ld + e % ldq];
 }
 
+__global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, int ldq, int q,
+                                                       const double* __restrict__ R) {
+  trsm_tile_body(A, ldq, q, R, blockIdx.x);
+}
+
 // Aout = Ain * M on the first ldq columns (M upper triangular, ldq x ldq,
 // zero-padded): one 16x16 output tile per wavefront on the FP64 matrix cores.
 __global__ __launch_bounds__(64) void gemm_upper_kernel(const double* __restrict__ Ain, int ldq,
@@ -522,7 +574,7 @@ __global__ __launch_bounds__(64) void gemm_upper_kernel(const double* __restrict
 
 // status |= 4 when min|R_ii| <= k u max|R_ii| over the first k = rank_cols
 // diagonal entries (numerical rank of the leading columns below k).
-__global__ __launch_bounds__(64) void rank_test_kernel(const double* __restrict__ R, int q,
+__device__ __forceinline__ void rank_test_body(const double* __restrict__ R, int q,
                                                        int rank_cols, int* __restrict__ status) {
   double a = 0.0, b = INFINITY;
   for (int i = threadIdx.x; i < rank_cols; i += 64) {
@@ -538,10 +590,15 @@ __global__ __launch_bounds__(64) void rank_test_kernel(const double* __restrict_
   if (threadIdx.x == 0 && !(b > static_cast<double>(rank_cols) * 0x1p-53 * a)) atomicOr(status, 4);
 }
 
+__global__ __launch_bounds__(64) void rank_test_kernel(const double* __restrict__ R, int q,
+                                                       int rank_cols, int* __restrict__ status) {
+  rank_test_body(R, q, rank_cols, status);
+}
+
 // Tail of the preconditioner set-up once M = R[:p,:p]^{-1} exists: Mt = M^T,
 // phi0 = M R[:p, p], rank test on R[:p,:p] (status |= 4).
 template <int NT>
-__global__ __launch_bounds__(NT) void triinv_finish_kernel(const double* __restrict__ R, int q,
+__device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R, int q,
                                                            int p, const double* __restrict__ M,
                                                            double* __restrict__ Mt,
                                                            double* __restrict__ phi0,
@@ -573,6 +630,15 @@ __global__ __launch_bounds__(NT) void triinv_finish_kernel(const double* __restr
     if (threadIdx.x == 0 && status && !(b > static_cast<double>(p) * 0x1p-53 * a))
       atomicOr(status, 4);
   }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void triinv_finish_kernel(const double* __restrict__ R, int q,
+                                                           int p, const double* __restrict__ M,
+                                                           double* __restrict__ Mt,
+                                                           double* __restrict__ phi0,
+                                                           int* __restrict__ status) {
+  triinv_finish_body<NT>(R, q, p, M, Mt, phi0, status);
 }
 
 }  // namespace
@@ -682,6 +748,172 @@ hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, d
                        status);
   }
   return hipGetLastError();
+}
+
+}  // namespace tls
+
+// ---- batched launches ---------------------------------------------------------
+namespace tls {
+namespace {
+
+__global__ __launch_bounds__(256) void gram_b_kernel(const Item* __restrict__ items,
+                                                     const FitDesc* __restrict__ D) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  gram_body(d.A, d.crows, d.ldq, d.G, it.idx);
+}
+
+// sweep 0..2 of the three-sweep factorisation, or sweep -1: the single shifted
+// sweep of the stage-1 sketch (into R, rank bits to status[2]).
+__device__ __forceinline__ void chol_target(const FitDesc& d, int sweep, double** R, int** status,
+                                            int* shift_mode, int* fail_bit) {
+  double* R3 = d.G + static_cast<size_t>(d.ldq) * d.ldq;
+  *R = sweep < 0 ? d.R : (sweep == 0 ? d.R1 : (sweep == 1 ? d.R2 : R3));
+  *status = sweep < 0 ? d.status + 2 : d.status;
+  *shift_mode = sweep <= 0 ? 1 : 2;
+  *fail_bit = sweep <= 0 ? 1 : 2;
+}
+
+template <int QT>
+__global__ __launch_bounds__(256) void chol_b_kernel(const Item* __restrict__ items,
+                                                     const FitDesc* __restrict__ D, int sweep) {
+  const FitDesc& d = D[items[blockIdx.x].fit];
+  double* R;
+  int* status;
+  int shift_mode, fail_bit;
+  chol_target(d, sweep, &R, &status, &shift_mode, &fail_bit);
+  if (QT > 0)
+    chol_reg_body<(QT > 0 ? QT : 1)>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
+  else
+    chol_body<256>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
+}
+
+__global__ __launch_bounds__(64) void trsm_b_kernel(const Item* __restrict__ items,
+                                                    const FitDesc* __restrict__ D, int which) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  trsm_tile_body(d.A, d.ldq, d.q, which == 0 ? d.R1 : d.R2, it.idx);
+}
+
+__global__ __launch_bounds__(256) void trmm_b_kernel(const Item* __restrict__ items,
+                                                     const FitDesc* __restrict__ D, int variant) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  double* R3 = d.G + static_cast<size_t>(d.ldq) * d.ldq;
+  double* T = R3 + static_cast<size_t>(d.q) * d.q;
+  if (variant == 0)
+    trmm_body<256>(R3, d.R2, d.q, T, it.idx);
+  else
+    trmm_body<256>(T, d.R1, d.q, d.R, it.idx);
+}
+
+__global__ __launch_bounds__(64) void rank_test_b_kernel(const Item* __restrict__ items,
+                                                         const FitDesc* __restrict__ D, int stage) {
+  const FitDesc& d = D[items[blockIdx.x].fit];
+  rank_test_body(d.R, d.q, d.p, stage == 1 ? d.status + 2 : d.status);
+}
+
+template <int QT>
+__global__ __launch_bounds__(256) void triinv_b_kernel(const Item* __restrict__ items,
+                                                       const FitDesc* __restrict__ D, int stage) {
+  const FitDesc& d = D[items[blockIdx.x].fit];
+  double* M = stage == 1 ? d.M0 : d.M;
+  double* Mt = stage == 1 ? d.Mt0 : d.Mt;
+  if (QT > 0)
+    triinv_reg_body<(QT > 0 ? QT : 1)>(d.R, d.q, d.p, M, d.p);
+  else
+    triinv_body<256>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
+                     stage == 1 ? d.status + 3 : d.status + 1);
+  __syncthreads();
+  if (QT > 0)
+    triinv_finish_body<256>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
+                            stage == 1 ? d.status + 3 : d.status + 1);
+  if (stage == 2 && threadIdx.x < 64) {
+    double a = 0.0, b = INFINITY;
+    for (int i = threadIdx.x; i < d.p; i += 64) {
+      const double v = fabs(d.R[static_cast<size_t>(i) * d.q + i]);
+      a = fmax(a, v);
+      b = fmin(b, v);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a = fmax(a, __shfl_xor(a, off, 64));
+      b = fmin(b, __shfl_xor(b, off, 64));
+    }
+    if (threadIdx.x == 0) {
+      d.dminmax[0] = a;
+      d.dminmax[1] = b;
+    }
+  }
+}
+
+template <int QT>
+hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtiles, int nrowtiles,
+                   const Item* rows, int nrows, const Item* fits, int nfits, int ldqmax,
+                   const FitDesc* D, hipStream_t st) {
+  const size_t trsm_shm = (16 * static_cast<size_t>(ldqmax + 1) + 16 * static_cast<size_t>(ldqmax)) *
+                          sizeof(double);
+  const int sweeps = stage == 1 ? 1 : 3;
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
+    hipLaunchKernelGGL(gram_b_kernel, dim3(ntiles), dim3(256), 0, st, tiles, D);
+    hipLaunchKernelGGL((chol_b_kernel<QT>), dim3(nfits), dim3(256), 0, st, fits, D,
+                       stage == 1 ? -1 : sweep);
+    if (sweep < sweeps - 1)
+      hipLaunchKernelGGL(trsm_b_kernel, dim3(nrowtiles), dim3(64), trsm_shm, st, rowtiles, D, sweep);
+  }
+  if (stage == 2) {
+    hipLaunchKernelGGL(trmm_b_kernel, dim3(nrows), dim3(256), 0, st, rows, D, 0);
+    hipLaunchKernelGGL(trmm_b_kernel, dim3(nrows), dim3(256), 0, st, rows, D, 1);
+  }
+  hipLaunchKernelGGL(rank_test_b_kernel, dim3(nfits), dim3(64), 0, st, fits, D, stage);
+  return hipGetLastError();
+}
+
+template <int QT>
+hipError_t triinv_b_qt(int stage, const Item* fits, int nfits, int pmax, const FitDesc* D,
+                       hipStream_t st) {
+  const size_t shm = QT > 0 ? static_cast<size_t>(pmax) * (pmax + 1) * sizeof(double) : 0;
+  hipLaunchKernelGGL((triinv_b_kernel<QT>), dim3(nfits), dim3(256), shm, st, fits, D, stage);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// qt = ceil(qmax / 16) (register tiles, <= 8) or 0 (global-memory kernels).
+hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const Item* rowtiles,
+                       int nrowtiles, const Item* rows, int nrows, const Item* fits, int nfits,
+                       int ldqmax, const FitDesc* D, hipStream_t st) {
+  if (nfits < 1) return hipSuccess;
+  switch (qt) {
+    case 0: return qr_b_qt<0>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 1: return qr_b_qt<1>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 2: return qr_b_qt<2>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 3: return qr_b_qt<3>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 4: return qr_b_qt<4>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 5: return qr_b_qt<5>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 6: return qr_b_qt<6>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 7: return qr_b_qt<7>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 8: return qr_b_qt<8>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// pt = ceil(pmax / 16) (register tiles, <= 8) or 0 (global-memory kernel).
+hipError_t launch_triinv_b(int stage, int pt, const Item* fits, int nfits, int pmax,
+                           const FitDesc* D, hipStream_t st) {
+  if (nfits < 1) return hipSuccess;
+  switch (pt) {
+    case 0: return triinv_b_qt<0>(stage, fits, nfits, pmax, D, st);
+    case 1: return triinv_b_qt<1>(stage, fits, nfits, pmax, D, st);
+    case 2: return triinv_b_qt<2>(stage, fits, nfits, pmax, D, st);
+    case 3: return triinv_b_qt<3>(stage, fits, nfits, pmax, D, st);
+    case 4: return triinv_b_qt<4>(stage, fits, nfits, pmax, D, st);
+    case 5: return triinv_b_qt<5>(stage, fits, nfits, pmax, D, st);
+    case 6: return triinv_b_qt<6>(stage, fits, nfits, pmax, D, st);
+    case 7: return triinv_b_qt<7>(stage, fits, nfits, pmax, D, st);
+    case 8: return triinv_b_qt<8>(stage, fits, nfits, pmax, D, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace tls

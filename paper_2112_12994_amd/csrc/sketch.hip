@@ -20,14 +20,13 @@ __global__ void philox_uniform_kernel(double* __restrict__ out, int64_t count, u
 // Row t of the sketch: scale * [X(idx,:), b(idx)], zero-padded to ldq columns;
 // rows t >= c are zero.  mode 0: given idx/scale; 1: uniform trials (Algorithm
 // 1: idx = floor(u m), scale sqrt(m/c)); 2: every row (c == m, scale 1).
-__global__ __launch_bounds__(64) void gather_kernel(const double* __restrict__ y, int64_t m, int p,
+__device__ __forceinline__ void gather_body(const double* __restrict__ y, int64_t m, int p,
                                                     int mode, const int64_t* __restrict__ idx,
                                                     const double* __restrict__ scale, int c,
                                                     int ldq, double* __restrict__ A,
                                                     int64_t* __restrict__ idx_out,
                                                     double* __restrict__ scale_out, uint64_t seed,
-                                                    uint32_t fit) {
-  const int t = blockIdx.x;
+                                                    uint32_t fit, int t) {
   double* row = A + static_cast<size_t>(t) * ldq;
   if (t >= c) {
     for (int j = threadIdx.x; j < ldq; j += 64) row[j] = 0.0;
@@ -61,26 +60,42 @@ __global__ __launch_bounds__(64) void gather_kernel(const double* __restrict__ y
   }
 }
 
+__global__ __launch_bounds__(64) void gather_kernel(const double* __restrict__ y, int64_t m, int p,
+                                                    int mode, const int64_t* __restrict__ idx,
+                                                    const double* __restrict__ scale, int c,
+                                                    int ldq, double* __restrict__ A,
+                                                    int64_t* __restrict__ idx_out,
+                                                    double* __restrict__ scale_out, uint64_t seed,
+                                                    uint32_t fit) {
+  gather_body(y, m, p, mode, idx, scale, c, ldq, A, idx_out, scale_out, seed, fit, blockIdx.x);
+}
+
 constexpr int CHUNK = 4096;
 
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void chunk_sum_kernel(const T* __restrict__ s, int64_t m,
-                                                       double* __restrict__ out) {
+__device__ __forceinline__ void chunk_sum_body(const T* __restrict__ s, int64_t m,
+                                                       double* __restrict__ out, int chunk) {
   __shared__ double red[NT / 64];
-  const int64_t base = static_cast<int64_t>(blockIdx.x) * CHUNK;
+  const int64_t base = static_cast<int64_t>(chunk) * CHUNK;
   double acc = 0.0;
   for (int i = threadIdx.x; i < CHUNK; i += NT) {
     const int64_t g = base + i;
     if (g < m) acc += static_cast<double>(s[g]);
   }
   const double tot = block_sum<NT>(acc, red);
-  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+  if (threadIdx.x == 0) out[chunk] = tot;
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void chunk_sum_kernel(const T* __restrict__ s, int64_t m,
+                                                       double* __restrict__ out) {
+  chunk_sum_body<T, NT>(s, m, out, blockIdx.x);
 }
 
 // Exclusive prefix of the chunk sums in chunk order: pre[0] = 0, pre[k+1] =
 // pre[k] + sums[k]; pre[nch] is the total.  One workgroup.
 template <int NT>
-__global__ __launch_bounds__(NT) void chunk_prefix_kernel(const double* __restrict__ sums,
+__device__ __forceinline__ void chunk_prefix_body(const double* __restrict__ sums,
                                                           int nch, double* __restrict__ pre) {
   __shared__ double buf[NT];
   __shared__ double carry;
@@ -107,6 +122,12 @@ __global__ __launch_bounds__(NT) void chunk_prefix_kernel(const double* __restri
   }
 }
 
+template <int NT>
+__global__ __launch_bounds__(NT) void chunk_prefix_kernel(const double* __restrict__ sums,
+                                                          int nch, double* __restrict__ pre) {
+  chunk_prefix_body<NT>(sums, nch, pre);
+}
+
 __device__ __forceinline__ double wave_incl_scan(double v) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -121,13 +142,12 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
 // on the prefix, then the first row in the chunk whose running total exceeds
 // the target.  scale = 1 / sqrt(c * s_i / total).
 template <typename T>
-__global__ __launch_bounds__(64) void draw_kernel(const T* __restrict__ s, int64_t m,
+__device__ __forceinline__ void draw_body(const T* __restrict__ s, int64_t m,
                                                   const double* __restrict__ pre, int nch,
                                                   const double* __restrict__ u, int c,
                                                   int64_t* __restrict__ idx,
                                                   double* __restrict__ scale, uint64_t seed,
-                                                  uint32_t fit) {
-  const int t = blockIdx.x;
+                                                  uint32_t fit, int t) {
   const int lane = threadIdx.x;
   const double total = pre[nch];
   const double ut = u ? u[t] : philox_u01(static_cast<uint64_t>(t), RNG_LEVERAGE, fit, seed);
@@ -165,17 +185,26 @@ __global__ __launch_bounds__(64) void draw_kernel(const T* __restrict__ s, int64
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(64) void draw_kernel(const T* __restrict__ s, int64_t m,
+                                                  const double* __restrict__ pre, int nch,
+                                                  const double* __restrict__ u, int c,
+                                                  int64_t* __restrict__ idx,
+                                                  double* __restrict__ scale, uint64_t seed,
+                                                  uint32_t fit) {
+  draw_body<T>(s, m, pre, nch, u, c, idx, scale, seed, fit, blockIdx.x);
+}
+
 // Pi (k x p) and Omega = M Pi^T (p x k, column-major).  kind 0: subsampled
 // randomized Hadamard map: Pi[q][j] = d_j (-1)^popcount(r_q & j) / sqrt(k)
 // with d_j = +-1 from the sign stream and r_q uniform in [0, P); kind 1:
 // Gaussian N(0, 1/k) entries (Box-Muller).  M is upper triangular, row-major (p x p).
 template <int NT>
-__global__ __launch_bounds__(NT) void jl_omega_kernel(const double* __restrict__ M, int p, int k,
+__device__ __forceinline__ void jl_omega_body(const double* __restrict__ M, int p, int k,
                                                       int kind, double* __restrict__ Pi,
                                                       double* __restrict__ Om, uint64_t seed,
-                                                      uint32_t fit) {
+                                                      uint32_t fit, int q) {
   extern __shared__ double prow[];
-  const int q = blockIdx.x;
   int P = 1;
   while (P < p) P <<= 1;
   const double invsk = 1.0 / sqrt(static_cast<double>(k));
@@ -209,6 +238,14 @@ __global__ __launch_bounds__(NT) void jl_omega_kernel(const double* __restrict__
     for (int j = i; j < p; ++j) acc += mi[j] * prow[j];
     Om[static_cast<size_t>(q) * p + i] = acc;
   }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void jl_omega_kernel(const double* __restrict__ M, int p, int k,
+                                                      int kind, double* __restrict__ Pi,
+                                                      double* __restrict__ Om, uint64_t seed,
+                                                      uint32_t fit) {
+  jl_omega_body<NT>(M, p, k, kind, Pi, Om, seed, fit, blockIdx.x);
 }
 
 }  // namespace
@@ -268,6 +305,93 @@ hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, 
   if (p < 1 || k < 1 || p > 8192) return hipErrorInvalidValue;
   hipLaunchKernelGGL((jl_omega_kernel<256>), dim3(k), dim3(256), p * sizeof(double), st, M, p, k,
                      kind, Pi, Om, seed, fit);
+  return hipGetLastError();
+}
+
+}  // namespace tls
+
+// ---- batched launches ---------------------------------------------------------
+namespace tls {
+namespace {
+
+// stage 1: uniform trials (every row when the sketch covers all rows);
+// stage 2: the sampled rows and scales of the leverage stage.
+__global__ __launch_bounds__(64) void gather_b_kernel(const Item* __restrict__ items,
+                                                      const FitDesc* __restrict__ D, int stage,
+                                                      uint64_t seed) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  const int mode = d.all_rows ? 2 : (stage == 1 ? 1 : 0);
+  gather_body(d.y, d.m, d.p, mode, d.idx, d.scale, d.c, d.ldq, d.A, mode == 1 ? d.idx : nullptr,
+              mode == 1 ? d.scale : nullptr, seed, d.fit, it.idx);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void chunk_sum_b_kernel(const Item* __restrict__ items,
+                                                          const FitDesc* __restrict__ D) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  chunk_sum_body<T, 256>(static_cast<const T*>(d.u), d.m, d.swork, it.idx);
+}
+
+__global__ __launch_bounds__(256) void chunk_prefix_b_kernel(const Item* __restrict__ items,
+                                                             const FitDesc* __restrict__ D) {
+  const FitDesc& d = D[items[blockIdx.x].fit];
+  chunk_prefix_body<256>(d.swork, d.nchunks, d.swork + d.nchunks);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void draw_b_kernel(const Item* __restrict__ items,
+                                                    const FitDesc* __restrict__ D, uint64_t seed) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  draw_body<T>(static_cast<const T*>(d.u), d.m, d.swork + d.nchunks, d.nchunks, nullptr, d.c, d.idx,
+               d.scale, seed, d.fit, it.idx);
+}
+
+__global__ __launch_bounds__(256) void jl_b_kernel(const Item* __restrict__ items,
+                                                   const FitDesc* __restrict__ D, int kind,
+                                                   uint64_t seed) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  jl_omega_body<256>(d.M0, d.p, d.k, kind, d.Pi, d.Om, seed, d.fit, it.idx);
+}
+
+}  // namespace
+
+hipError_t launch_gather_b(int stage, const Item* items, int nitems, const FitDesc* D,
+                           uint64_t seed, hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+  hipLaunchKernelGGL(gather_b_kernel, dim3(nitems), dim3(64), 0, st, items, D, stage, seed);
+  return hipGetLastError();
+}
+
+// fit_items: one item per fit that samples (idx unused).
+hipError_t launch_sample_b(int prec, const Item* chunk_items, int nchunk_items,
+                           const Item* draw_items, int ndraw_items, const Item* fit_items,
+                           int nfit_items, const FitDesc* D, uint64_t seed, hipStream_t st) {
+  if (nfit_items < 1) return hipSuccess;
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((chunk_sum_b_kernel<double>), dim3(nchunk_items), dim3(256), 0, st,
+                       chunk_items, D);
+  else
+    hipLaunchKernelGGL((chunk_sum_b_kernel<float>), dim3(nchunk_items), dim3(256), 0, st,
+                       chunk_items, D);
+  hipLaunchKernelGGL(chunk_prefix_b_kernel, dim3(nfit_items), dim3(256), 0, st, fit_items, D);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((draw_b_kernel<double>), dim3(ndraw_items), dim3(64), 0, st, draw_items, D,
+                       seed);
+  else
+    hipLaunchKernelGGL((draw_b_kernel<float>), dim3(ndraw_items), dim3(64), 0, st, draw_items, D,
+                       seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_jl_b(const Item* items, int nitems, const FitDesc* D, int kind, int pmax,
+                       uint64_t seed, hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+  hipLaunchKernelGGL(jl_b_kernel, dim3(nitems), dim3(256), pmax * sizeof(double), st, items, D, kind,
+                     seed);
   return hipGetLastError();
 }
 

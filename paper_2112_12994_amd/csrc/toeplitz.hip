@@ -108,16 +108,23 @@ hipError_t scores_one(const void* Yhat, const void* Om, int k, void* scores, con
 }
 
 template <int NT>
+__device__ __forceinline__ void colsum_body(const double* __restrict__ partial,
+                                                    int nblocks, double* __restrict__ out,
+                                                    const int* __restrict__ flag, int j) {
+  __shared__ double red[NT / 64];
+  if (flag && *flag) return;
+  const double* colp = partial + static_cast<size_t>(j) * nblocks;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += NT) s += colp[b];
+  const double tot = block_sum<NT>(s, red);
+  if (threadIdx.x == 0) out[j] = tot;
+}
+
+template <int NT>
 __global__ __launch_bounds__(NT) void colsum_kernel(const double* __restrict__ partial,
                                                     int nblocks, double* __restrict__ out,
                                                     const int* __restrict__ flag) {
-  __shared__ double red[NT / 64];
-  if (flag && *flag) return;
-  const double* col = partial + static_cast<size_t>(blockIdx.x) * nblocks;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += NT) s += col[b];
-  const double tot = block_sum<NT>(s, red);
-  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+  colsum_body<NT>(partial, nblocks, out, flag, blockIdx.x);
 }
 
 // Direct FP64 residual r_i = b_i - sum_j phi_j X[i, j] = y[p+i] - sum_j phi_j y[p-1+i-j],
@@ -126,15 +133,15 @@ __global__ __launch_bounds__(NT) void colsum_kernel(const double* __restrict__ p
 // products).  Each workgroup stages its rows' samples and phi in LDS and
 // writes one partial of ||r||^2.
 template <int NT, int RPT>
-__global__ __launch_bounds__(NT) void resid_direct_kernel(const double* __restrict__ y, int64_t m,
+__device__ __forceinline__ void resid_direct_body(const double* __restrict__ y, int64_t m,
                                                           int p, const double* __restrict__ phi,
-                                                          double* __restrict__ partial) {
+                                                          double* __restrict__ partial, int tile) {
   extern __shared__ double sh[];
   double* sphi = sh;
   double* sy = sh + p;
   __shared__ double red[NT / 64];
   constexpr int TILE = NT * RPT;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * TILE;
+  const int64_t row0 = static_cast<int64_t>(tile) * TILE;
   for (int j = threadIdx.x; j < p; j += NT) sphi[j] = phi[j];
   // samples y[row0 .. row0 + TILE + p) (rows use y[i .. i + p])
   for (int t = threadIdx.x; t < TILE + p; t += NT) {
@@ -153,7 +160,14 @@ __global__ __launch_bounds__(NT) void resid_direct_kernel(const double* __restri
     }
   }
   const double tot = block_sum<NT>(acc, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+  if (threadIdx.x == 0) partial[tile] = tot;
+}
+
+template <int NT, int RPT>
+__global__ __launch_bounds__(NT) void resid_direct_kernel(const double* __restrict__ y, int64_t m,
+                                                          int p, const double* __restrict__ phi,
+                                                          double* __restrict__ partial) {
+  resid_direct_body<NT, RPT>(y, m, p, phi, partial, blockIdx.x);
 }
 
 }  // namespace
@@ -233,6 +247,227 @@ hipError_t launch_colsum(const double* partial, int nblocks, int ncols, double* 
   if (ncols < 1 || nblocks < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL((colsum_kernel<256>), dim3(ncols), dim3(256), 0, st, partial, nblocks, out,
                      flag);
+  return hipGetLastError();
+}
+
+}  // namespace tls
+
+// ---- batched launches: one workgroup per work item {fit, local index} -------
+namespace tls {
+namespace {
+
+template <int LGN, int NT, typename TS>
+__global__ __launch_bounds__(NT) void spectra_b_kernel(const Item* __restrict__ items,
+                                                       const FitDesc* __restrict__ D, int to64,
+                                                       const cx<double>* __restrict__ tab) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  spectra_body<LGN, NT, TS>(d.y, d.n, d.L, static_cast<cx<TS>*>(to64 ? d.Yhat64 : d.Yhat), tab,
+                            it.idx);
+}
+
+template <typename T, int LGN, int NT, int VARIANT>
+__global__ __launch_bounds__(NT) void toep_b_kernel(const Item* __restrict__ items,
+                                                    const FitDesc* __restrict__ D,
+                                                    const double* __restrict__ consts,
+                                                    const cx<T>* __restrict__ tab) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  if constexpr (VARIANT == BP_LSQR_FIRST || VARIANT == BP_LSQR) {
+    const T* w = VARIANT == BP_LSQR_FIRST ? reinterpret_cast<const T*>(d.y + d.p)
+                                          : static_cast<const T*>(d.u);
+    toep_pass_body<T, LGN, NT, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat),
+                                           static_cast<const cx<T>*>(d.Vhat), w,
+                                           static_cast<T*>(d.u), nullptr, d.partial, d.st->coef,
+                                           &d.st->done, tab, d.m, d.p, d.L, d.nblocks, it.idx);
+  } else if constexpr (VARIANT == BP_OUTER64) {
+    toep_pass_body<T, LGN, NT, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat64),
+                                           static_cast<const cx<T>*>(d.Vhat),
+                                           reinterpret_cast<const T*>(d.y + d.p), nullptr, nullptr,
+                                           d.partial, consts, &d.rst->done, tab, d.m, d.p, d.L,
+                                           d.nblocks, it.idx);
+  } else {
+    toep_pass_body<T, LGN, NT, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat),
+                                           static_cast<const cx<T>*>(d.Vhat32), nullptr, nullptr,
+                                           nullptr, d.partial, consts + 2, &d.rst->inner_done,
+                                           tab, d.m, d.p, d.L, d.nblocks, it.idx);
+  }
+}
+
+template <int LGN, int NT, typename TS>
+__global__ __launch_bounds__(NT) void small_rfft_b_kernel(const Item* __restrict__ items,
+                                                          const FitDesc* __restrict__ D,
+                                                          int variant,
+                                                          const cx<double>* __restrict__ tab) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  const double scale = 1.0 / static_cast<double>(2 << LGN);
+  if (variant == 0)
+    small_rfft_body<LGN, NT, TS>(d.Om, d.p, d.p, scale, static_cast<cx<TS>*>(d.Omhat), tab,
+                                 nullptr, it.idx);
+  else
+    small_rfft_body<LGN, NT, TS>(variant == 1 ? d.phi0 : d.phi, d.p, d.p, scale,
+                                 static_cast<cx<TS>*>(d.Vhat), tab, nullptr, 0);
+}
+
+template <typename T, int LGN, int NT>
+__global__ __launch_bounds__(NT) void scores_b_kernel(const Item* __restrict__ items,
+                                                      const FitDesc* __restrict__ D,
+                                                      const cx<T>* __restrict__ tab) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  scores_body<T, LGN, NT>(static_cast<const cx<T>*>(d.Yhat), static_cast<const cx<T>*>(d.Omhat),
+                          d.k, static_cast<T*>(d.u), tab, d.m, d.p, d.L, it.idx);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void colsum_b_kernel(const Item* __restrict__ items,
+                                                      const FitDesc* __restrict__ D, int variant) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  if (variant == 3) {
+    colsum_body<NT>(d.rpart, static_cast<int>((d.m + 1023) / 1024), d.rr, nullptr, it.idx);
+    return;
+  }
+  const int* flag = variant == 0 ? &d.st->done : (variant == 1 ? &d.rst->done : &d.rst->inner_done);
+  colsum_body<NT>(d.partial, d.nblocks, d.g, flag, it.idx);
+}
+
+template <int NT, int RPT>
+__global__ __launch_bounds__(NT) void resid_b_kernel(const Item* __restrict__ items,
+                                                     const FitDesc* __restrict__ D) {
+  const Item it = items[blockIdx.x];
+  const FitDesc& d = D[it.fit];
+  resid_direct_body<NT, RPT>(d.y, d.m, d.p, d.phi, d.rpart, it.idx);
+}
+
+template <int LGN>
+hipError_t toep_b_sel(int prec, int variant, const Item* items, int nitems, const FitDesc* D,
+                      const double* consts, const Twiddles& tw, hipStream_t st) {
+  constexpr int NT = nt_for(LGN);
+  switch (variant) {
+    case BP_LSQR_FIRST:
+      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_LSQR_FIRST>), dim3(nitems), dim3(NT), 0,
+                         st, items, D, consts, tab_of<double>(tw));
+      break;
+    case BP_LSQR:
+      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_LSQR>), dim3(nitems), dim3(NT), 0, st,
+                         items, D, consts, tab_of<double>(tw));
+      break;
+    case BP_OUTER64:
+      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_OUTER64>), dim3(nitems), dim3(NT), 0,
+                         st, items, D, consts, tab_of<double>(tw));
+      break;
+    case BP_INNER32:
+      hipLaunchKernelGGL((toep_b_kernel<float, LGN, NT, BP_INNER32>), dim3(nitems), dim3(NT), 0,
+                         st, items, D, consts, tab_of<float>(tw));
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  (void)prec;
+  return hipGetLastError();
+}
+
+template <int LGN>
+hipError_t spectra_b_sel(int prec, const Item* items, int nitems, const FitDesc* D, int to64,
+                         const Twiddles& tw, hipStream_t st) {
+  constexpr int NT = nt_for(LGN);
+  if (prec == PREC_F64 || to64)
+    hipLaunchKernelGGL((spectra_b_kernel<LGN, NT, double>), dim3(nitems), dim3(NT), 0, st, items, D,
+                       to64, static_cast<const cx<double>*>(tw.d64));
+  else
+    hipLaunchKernelGGL((spectra_b_kernel<LGN, NT, float>), dim3(nitems), dim3(NT), 0, st, items, D,
+                       to64, static_cast<const cx<double>*>(tw.d64));
+  return hipGetLastError();
+}
+
+template <int LGN>
+hipError_t small_rfft_b_sel(int prec, int variant, const Item* items, int nitems, const FitDesc* D,
+                            const Twiddles& tw, hipStream_t st) {
+  constexpr int NT = nt_for(LGN);
+  if (prec == PREC_F64 || variant == 2)
+    hipLaunchKernelGGL((small_rfft_b_kernel<LGN, NT, double>), dim3(nitems), dim3(NT), 0, st, items,
+                       D, variant, static_cast<const cx<double>*>(tw.d64));
+  else
+    hipLaunchKernelGGL((small_rfft_b_kernel<LGN, NT, float>), dim3(nitems), dim3(NT), 0, st, items,
+                       D, variant, static_cast<const cx<double>*>(tw.d64));
+  return hipGetLastError();
+}
+
+template <int LGN>
+hipError_t scores_b_sel(int prec, const Item* items, int nitems, const FitDesc* D,
+                        const Twiddles& tw, hipStream_t st) {
+  constexpr int NT = nt_for(LGN);
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((scores_b_kernel<double, LGN, NT>), dim3(nitems), dim3(NT), 0, st, items, D,
+                       tab_of<double>(tw));
+  else
+    hipLaunchKernelGGL((scores_b_kernel<float, LGN, NT>), dim3(nitems), dim3(NT), 0, st, items, D,
+                       tab_of<float>(tw));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+#define TLS_B_SWITCH(CALL)                    \
+  switch (lgn) {                              \
+    case 6: return CALL(6);                   \
+    case 7: return CALL(7);                   \
+    case 8: return CALL(8);                   \
+    case 9: return CALL(9);                   \
+    case 10: return CALL(10);                 \
+    case 11: return CALL(11);                 \
+    case 12: return CALL(12);                 \
+    case 13: return CALL(13);                 \
+    default: return hipErrorInvalidValue;     \
+  }
+
+hipError_t launch_spectra_b(int prec, int lgn, const Item* items, int nitems, const FitDesc* D,
+                            int to64, const Twiddles& tw, hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+#define TLS_C(LG) spectra_b_sel<LG>(prec, items, nitems, D, to64, tw, st)
+  TLS_B_SWITCH(TLS_C)
+#undef TLS_C
+}
+
+hipError_t launch_toep_b(int prec, int lgn, int variant, const Item* items, int nitems,
+                         const FitDesc* D, const double* consts, const Twiddles& tw,
+                         hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+#define TLS_C(LG) toep_b_sel<LG>(prec, variant, items, nitems, D, consts, tw, st)
+  TLS_B_SWITCH(TLS_C)
+#undef TLS_C
+}
+
+hipError_t launch_small_rfft_b(int prec, int lgn, int variant, const Item* items, int nitems,
+                               const FitDesc* D, const Twiddles& tw, hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+#define TLS_C(LG) small_rfft_b_sel<LG>(prec, variant, items, nitems, D, tw, st)
+  TLS_B_SWITCH(TLS_C)
+#undef TLS_C
+}
+
+hipError_t launch_scores_b(int prec, int lgn, const Item* items, int nitems, const FitDesc* D,
+                           const Twiddles& tw, hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+#define TLS_C(LG) scores_b_sel<LG>(prec, items, nitems, D, tw, st)
+  TLS_B_SWITCH(TLS_C)
+#undef TLS_C
+}
+
+hipError_t launch_colsum_b(int variant, const Item* items, int nitems, const FitDesc* D,
+                           hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+  hipLaunchKernelGGL((colsum_b_kernel<256>), dim3(nitems), dim3(256), 0, st, items, D, variant);
+  return hipGetLastError();
+}
+
+hipError_t launch_resid_b(const Item* items, int nitems, const FitDesc* D, int pmax,
+                          hipStream_t st) {
+  if (nitems < 1) return hipSuccess;
+  const size_t shm = (static_cast<size_t>(pmax) + 1024 + pmax) * sizeof(double);
+  hipLaunchKernelGGL((resid_b_kernel<256, 4>), dim3(nitems), dim3(256), shm, st, items, D);
   return hipGetLastError();
 }
 

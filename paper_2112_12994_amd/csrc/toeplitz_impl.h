@@ -34,12 +34,11 @@ __device__ __forceinline__ void load_pair(const cx<T>* __restrict__ P, int k, in
 // ---------------------------------------------------------------------------
 // Block spectra of the series (computed in FP64, stored as TS).
 template <int LGN, int NT, typename TS>
-__global__ __launch_bounds__(NT) void spectra_kernel(const double* __restrict__ y, int64_t n, int L,
+__device__ __forceinline__ void spectra_body(const double* __restrict__ y, int64_t n, int L,
                                                      cx<TS>* __restrict__ Yhat,
-                                                     const cx<double>* __restrict__ tab) {
+                                                     const cx<double>* __restrict__ tab, int blk) {
   constexpr int N = 1 << LGN;
   __shared__ cx<double> s[N];
-  const int blk = blockIdx.x;
   const int64_t start = static_cast<int64_t>(blk) * L;
   for (int t = threadIdx.x; t < N; t += NT) {
     const int64_t i0 = start + 2 * t;
@@ -61,24 +60,31 @@ __global__ __launch_bounds__(NT) void spectra_kernel(const double* __restrict__ 
   }
 }
 
+template <int LGN, int NT, typename TS>
+__global__ __launch_bounds__(NT) void spectra_kernel(const double* __restrict__ y, int64_t n, int L,
+                                                     cx<TS>* __restrict__ Yhat,
+                                                     const cx<double>* __restrict__ tab) {
+  spectra_body<LGN, NT, TS>(y, n, L, Yhat, tab, blockIdx.x);
+}
+
 // Packed spectra (times `scale`) of short real columns zero-padded to B.
 template <int LGN, int NT, typename TS>
-__global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict__ cols, int len,
+__device__ __forceinline__ void small_rfft_body(const double* __restrict__ cols, int len,
                                                         int ld, double scale,
                                                         cx<TS>* __restrict__ out,
                                                         const cx<double>* __restrict__ tab,
-                                                        const int* __restrict__ flag) {
+                                                        const int* __restrict__ flag, int col_idx) {
   constexpr int N = 1 << LGN;
   __shared__ cx<double> s[N];
   if (flag && *flag) return;
-  const double* col = cols + static_cast<size_t>(blockIdx.x) * ld;
+  const double* col = cols + static_cast<size_t>(col_idx) * ld;
   for (int t = threadIdx.x; t < N; t += NT) {
     const int i0 = 2 * t;
     s[swz<double>(t)] = {i0 < len ? col[i0] : 0.0, i0 + 1 < len ? col[i0 + 1] : 0.0};
   }
   __syncthreads();
   fft_dif<double, false, LGN, NT>(s, tab);
-  cx<TS>* o = out + static_cast<size_t>(blockIdx.x) * N;
+  cx<TS>* o = out + static_cast<size_t>(col_idx) * N;
   for (int k = threadIdx.x; k <= N / 2; k += NT) {
     const cx<double> w = twiddle<double, false>(tab, k, LGN + 1);
     cx<double> Xk, Xnk;
@@ -94,6 +100,15 @@ __global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict
   }
 }
 
+template <int LGN, int NT, typename TS>
+__global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict__ cols, int len,
+                                                        int ld, double scale,
+                                                        cx<TS>* __restrict__ out,
+                                                        const cx<double>* __restrict__ tab,
+                                                        const int* __restrict__ flag) {
+  small_rfft_body<LGN, NT, TS>(cols, len, ld, scale, out, tab, flag, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // One pass over all blocks.  With v's packed spectrum pre-scaled by 1/B:
 //   e = s1 * (X v) + s2 * w          (PM_MV; the w term when w_in != NULL)
@@ -102,11 +117,11 @@ __global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict
 //   partial[p*nb + blk] = block share of ||e||^2
 // Without PM_MV the pass vector is u_in.  (s1, s2) = coef[0..1].
 template <typename T, int LGN, int NT, int MODE>
-__global__ __launch_bounds__(NT) void toep_pass_kernel(
+__device__ __forceinline__ void toep_pass_body(
     const cx<T>* __restrict__ Yhat, const cx<T>* __restrict__ Vhat, const T* w_in, T* u_out,
     const T* __restrict__ u_in, double* __restrict__ partial, const double* __restrict__ coef,
     const int* __restrict__ flag, const cx<T>* __restrict__ tab, int64_t m, int p, int L,
-    int nblocks) {
+    int nblocks, int blk) {
   constexpr int N = 1 << LGN;
   constexpr int NPAIR = (N / 2 + 1 + NT - 1) / NT;
   constexpr int NEL = N / NT;
@@ -114,7 +129,6 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
   __shared__ cx<T> s[N];
   __shared__ double red[NT / 64];
   if (flag && *flag) return;
-  const int blk = blockIdx.x;
   const int tid = threadIdx.x;
   const cx<T>* Y = Yhat + static_cast<size_t>(blk) * N;
   const int64_t row0 = static_cast<int64_t>(blk) * L - (p - 1);  // row at tau = 0
@@ -204,20 +218,28 @@ __global__ __launch_bounds__(NT) void toep_pass_kernel(
   if (tid == 0) partial[static_cast<size_t>(p) * nblocks + blk] = tot;
 }
 
+template <typename T, int LGN, int NT, int MODE>
+__global__ __launch_bounds__(NT) void toep_pass_kernel(
+    const cx<T>* __restrict__ Yhat, const cx<T>* __restrict__ Vhat, const T* w_in, T* u_out,
+    const T* __restrict__ u_in, double* __restrict__ partial, const double* __restrict__ coef,
+    const int* __restrict__ flag, const cx<T>* __restrict__ tab, int64_t m, int p, int L,
+    int nblocks) {
+  toep_pass_body<T, LGN, NT, MODE>(Yhat, Vhat, w_in, u_out, u_in, partial, coef, flag, tab, m, p, L, nblocks, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Approximate generalised leverage scores (eq. (glev) in product form):
 // scores[i] = sum_q ((X omega_q)[i])^2 for k packed column spectra (scaled 1/B).
 template <typename T, int LGN, int NT>
-__global__ __launch_bounds__(NT) void scores_kernel(const cx<T>* __restrict__ Yhat,
+__device__ __forceinline__ void scores_body(const cx<T>* __restrict__ Yhat,
                                                     const cx<T>* __restrict__ Om, int kcols,
                                                     T* __restrict__ scores,
                                                     const cx<T>* __restrict__ tab, int64_t m,
-                                                    int p, int L) {
+                                                    int p, int L, int blk) {
   constexpr int N = 1 << LGN;
   constexpr int NPAIR = (N / 2 + 1 + NT - 1) / NT;
   constexpr int NEL = N / NT;
   __shared__ cx<T> s[N];
-  const int blk = blockIdx.x;
   const int tid = threadIdx.x;
   const cx<T>* Y = Yhat + static_cast<size_t>(blk) * N;
   const int64_t row0 = static_cast<int64_t>(blk) * L - (p - 1);
@@ -262,6 +284,15 @@ __global__ __launch_bounds__(NT) void scores_kernel(const cx<T>* __restrict__ Yh
     if (2 * t >= p - 1 && i0 < m) scores[i0] = acc0[e];
     if (2 * t + 1 >= p - 1 && i0 + 1 < m) scores[i0 + 1] = acc1[e];
   }
+}
+
+template <typename T, int LGN, int NT>
+__global__ __launch_bounds__(NT) void scores_kernel(const cx<T>* __restrict__ Yhat,
+                                                    const cx<T>* __restrict__ Om, int kcols,
+                                                    T* __restrict__ scores,
+                                                    const cx<T>* __restrict__ tab, int64_t m,
+                                                    int p, int L) {
+  scores_body<T, LGN, NT>(Yhat, Om, kcols, scores, tab, m, p, L, blockIdx.x);
 }
 
 }  // namespace tls

@@ -1,0 +1,133 @@
+"""Batched fits (tls_fit_batch, tls_fit_batch_device): every fit of a batch
+equals the single fit with the same options and request id bit for bit, over
+mixed lengths and orders that span several launch classes (FFT block length,
+Cholesky and inverse tile counts, LDS staging of the step), with invalid and
+degenerate fits mixed in; spot checks against the FP64 QR oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import capi, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = capi()
+    with c.Context(0) as cx:
+        yield cx
+
+
+def _same_as_single(ctx, ys, ps, outs, rid0, device=False, **opts):
+    for i, (y, p, o) in enumerate(zip(ys, ps, outs)):
+        if device:
+            single = ctx.fit_device(to_dev(y), p, 1e-10, request_id=rid0 + i, **opts)
+        else:
+            single = ctx.fit(y, p, 1e-10, request_id=rid0 + i, **opts)
+        assert o["status"] == single["status"], (i, p, y.size)
+        assert o["coef"].tobytes() == single["coef"].tobytes(), (i, p, y.size)
+        if "iters" in o:
+            assert o["iters"] == single["iters"], (i, p, y.size)
+        if "resid_norm" in o:
+            assert o["resid_norm"] == single["resid_norm"], (i, p, y.size)
+
+
+def test_batch_host_equals_single(ctx):
+    say("batch host")
+    fits = synth.workload_batch(seed=11, count=24, lo_exp=12, hi_exp=15)
+    ys, ps = [f.y for f in fits], [f.p for f in fits]
+    s, outs = ctx.fit_batch(ys, ps, 1e-10, request_id=500)
+    assert s == capi().TLS_OK
+    _same_as_single(ctx, ys, ps, outs, 500)
+
+
+def test_batch_device_equals_single(ctx):
+    say("batch device")
+    fits = synth.workload_batch(seed=12, count=32, lo_exp=12, hi_exp=16)
+    ys, ps = [f.y for f in fits], [f.p for f in fits]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=7)
+    assert s == capi().TLS_OK
+    say("   classes span B =", sorted({o["block_len"] for o in outs}))
+    _same_as_single(ctx, ys, ps, outs, 7, device=True)
+
+
+def test_batch_orders_across_kernel_limits(ctx):
+    """p = 127, 128 (q = 129: the global-memory Cholesky), 150 and 200 (no LDS
+    staging of M), with small orders in the same batch."""
+    say("batch wide orders")
+    rng = np.random.default_rng(13)
+    ps = [3, 127, 128, 150, 200, 16, 128]
+    ys = [synth.ar_series(int(n), p, rng, 0.3, 0.85)
+          for n, p in zip([5000, 40000, 30000, 50000, 60000, 9000, 20000], ps)]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=40)
+    assert s == capi().TLS_OK
+    _same_as_single(ctx, ys, ps, outs, 40, device=True)
+
+
+def test_batch_mixed_precision_equals_single(ctx):
+    say("batch mixed")
+    rng = np.random.default_rng(14)
+    ps = [4, 20, 60, 33, 100]
+    ys = [synth.ar_series(int(n), p, rng, 0.3, 0.85)
+          for n, p in zip([8000, 30000, 70000, 20000, 50000], ps)]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=3, precision=1)
+    assert s in (capi().TLS_OK, capi().TLS_ENOCONV)
+    _same_as_single(ctx, ys, ps, outs, 3, device=True, precision=1)
+
+
+def test_batch_uniform_sketch_and_all_rows(ctx):
+    """Uniform sketch, and short series whose sketch covers every row."""
+    say("batch uniform / all rows")
+    rng = np.random.default_rng(15)
+    ps = [20, 6, 30, 10]
+    ys = [synth.ar_series(int(n), p, rng, 0.3, 0.9) for n, p in zip([300, 40, 20000, 5000], ps)]
+    for sketch in (0, 1):
+        s, outs = ctx.fit_batch(ys, ps, 1e-10, request_id=90, sketch=sketch)
+        assert s == capi().TLS_OK
+        _same_as_single(ctx, ys, ps, outs, 90, sketch=sketch)
+
+
+def test_batch_invalid_fits_reported_per_fit(ctx):
+    c = capi()
+    say("batch invalid")
+    rng = np.random.default_rng(16)
+    good = synth.ar_series(5000, 5, rng, 0.3, 0.9)
+    bad = good.copy()
+    bad[17] = np.inf
+    const = np.full(3000, 1.5)
+    ys = [good, bad, good[:8], const, good]
+    ps = [5, 5, 5, 3, 5]
+    s, outs = ctx.fit_batch(ys, ps, 1e-10, request_id=0)
+    sts = [o["status"] for o in outs]
+    say("   statuses", sts)
+    assert sts[0] == c.TLS_OK and sts[4] == c.TLS_OK
+    assert sts[1] == c.TLS_EINVAL
+    assert sts[2] == c.TLS_EINVAL  # n < 2p + 1
+    assert sts[3] == c.TLS_ERANK
+    assert s == c.TLS_EINVAL
+    single = ctx.fit(good, 5, 1e-10, request_id=4)
+    assert outs[4]["coef"].tobytes() == single["coef"].tobytes()
+
+
+def test_batch_empty(ctx):
+    s, outs = ctx.fit_batch_device([], [], 1e-10)
+    assert s == capi().TLS_OK and outs == []
+
+
+def test_batch_against_oracle(ctx):
+    """A few fits of a batch against the FP64 QR oracle (coefficient gate 1e-6
+    on moderately conditioned series)."""
+    say("batch vs oracle")
+    rng = np.random.default_rng(17)
+    ps = [2, 9, 31, 64]
+    ys = [synth.ar_series(int(n), p, rng, 0.3, 0.8) for n, p in zip([3000, 12000, 40000, 90000], ps)]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10)
+    assert s == capi().TLS_OK
+    for y, p, o in zip(ys, ps, outs):
+        ref = oracle.fit_qr(y, p)
+        err = oracle.rel_error(o["coef"], ref["phi"])
+        say("   p=%d kappa=%.3g err=%.3g" % (p, ref["kappa"], err))
+        assert err <= 1e-6
+        assert abs(o["resid_norm"] - ref["rnorm"]) <= 1e-9 * ref["rnorm"]
