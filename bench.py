@@ -20,6 +20,9 @@ Besides the JSON fields of the bench contract, the line carries:
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +44,104 @@ WORKLOAD_TEXT = {
     "ar500": "AR(500) series, n=2^25, 250 pole pairs with moduli U[0.5,0.95] and angles U(0,pi), "
              "N(0,1) innovations, seed 0; sketch 8p rows, tol 1e-10",
 }
+
+
+# Sources that define the fused Toeplitz pass: HBM counters taken from a
+# profile are used only while these are unchanged.
+PASS_SOURCES = ["paper_2112_12994_amd/csrc/toeplitz_impl.h", "paper_2112_12994_amd/csrc/fft.h",
+                "paper_2112_12994_amd/csrc/common.h", "paper_2112_12994_amd/csrc/toeplitz.hip"]
+
+
+def pass_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in PASS_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def hbm_profile_name(workload: str, precision: str) -> str:
+    return os.path.join(ROOT, "profiles", f"toep_pass_{precision}_{workload}_hbm_counters.txt")
+
+
+def read_hbm_profile(workload: str, precision: str):
+    """HBM bytes per launch of the dominant pass from the committed counter
+    summary, or None when there is none or the pass sources changed since."""
+    path = hbm_profile_name(workload, precision)
+    if not os.path.exists(path):
+        return None, "no counter profile"
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != pass_source_hash():
+        return None, "pass sources changed since the counters were taken"
+    return float(kv["hbm_bytes_per_dispatch"]), os.path.relpath(path, ROOT)
+
+
+def _rows(pattern_dir: str, suffix: str):
+    files = sorted(glob.glob(os.path.join(pattern_dir, "**", f"*{suffix}"), recursive=True))
+    rows = []
+    for f in files:
+        with open(f, newline="") as fh:
+            rows.extend({k.lower(): v for k, v in r.items()} for r in csv.DictReader(fh))
+    return rows
+
+
+def _short(name: str) -> str:
+    s = name.replace("(anonymous namespace)::", "").replace("tls::", "")
+    if s.startswith("void "):
+        s = s[5:]
+    return s.split("(")[0] if "(" in s and not s.startswith("(") else s
+
+
+def prof_summary(kind: str, dirs: list, out: str, cmd: str, title: str):
+    """Compact text summaries of rocprofv3 CSV output (kernel statistics, or
+    per-dispatch HBM counters with the copy-kernel calibration)."""
+    lines = [f"# {title}", f"# command: {cmd}", f"source_hash: {pass_source_hash()}"]
+    if kind == "stats":
+        rows = _rows(dirs[0], "kernel_stats.csv")
+        tot = sum(float(r["totaldurationns"]) for r in rows) or 1.0
+        lines.append(f"{'kernel':90s} {'calls':>7s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s}")
+        for r in sorted(rows, key=lambda r: -float(r["totaldurationns"])):
+            lines.append(f"{_short(r['name'])[:90]:90s} {int(r['calls']):7d} "
+                         f"{float(r['totaldurationns']) / 1e3:11.1f} {float(r['averagens']) / 1e3:9.2f} "
+                         f"{100 * float(r['totaldurationns']) / tot:6.2f}")
+    else:
+        # dirs: FETCH run, WRITE run, copy FETCH run, copy WRITE run; kernel filter
+        kern, copy_bytes = kind.split("=", 1)[1].rsplit("@", 1)
+        copy_bytes = float(copy_bytes)
+
+        def mean_for(d, counter, match):
+            vals = {}
+            for r in _rows(d, "counter_collection.csv"):
+                if r.get("counter_name") != counter:
+                    continue
+                vals.setdefault(_short(r["kernel_name"]), []).append(float(r["counter_value"]))
+            if match is None:  # the copy run: the kernel that moved the most
+                name = max(vals, key=lambda k: max(vals[k]))
+            else:
+                name = next(k for k in vals if k.startswith(match))
+            v = vals[name]
+            return name, sum(v) / len(v), len(v)
+
+        kname, fetch, nf = mean_for(dirs[0], "FETCH_SIZE", kern)
+        _, write, nw = mean_for(dirs[1], "WRITE_SIZE", kern)
+        cname, cfetch, _ = mean_for(dirs[2], "FETCH_SIZE", None)
+        _, cwrite, _ = mean_for(dirs[3], "WRITE_SIZE", None)
+        fs, ws = copy_bytes / (cfetch * 1024), copy_bytes / (cwrite * 1024)
+        lines += [f"kernel: {kname}", f"dispatches_fetch: {nf}", f"dispatches_write: {nw}",
+                  f"fetch_kib_per_dispatch: {fetch:.1f}", f"write_kib_per_dispatch: {write:.1f}",
+                  f"copy_kernel: {cname}", f"copy_bytes_each_way: {copy_bytes:.0f}",
+                  f"copy_fetch_kib_per_dispatch: {cfetch:.1f}",
+                  f"copy_write_kib_per_dispatch: {cwrite:.1f}",
+                  f"fetch_scale: {fs:.4f}", f"write_scale: {ws:.4f}",
+                  f"hbm_bytes_per_dispatch: {fetch * 1024 * fs + write * 1024 * ws:.0f}"]
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def fused_pass_bytes(n: int, p: int, B: int, nblocks: int, elem: int) -> int:
@@ -137,7 +238,15 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters against a known size) and exit")
+    ap.add_argument("--prof-summary", nargs="+", metavar="ARG",
+                    help="KIND OUT TITLE CMD DIR...: summarise rocprofv3 CSV output and exit "
+                         "(KIND 'stats', or 'hbm=<kernel prefix>@<copy bytes>' with the FETCH, "
+                         "WRITE, copy-FETCH and copy-WRITE run directories)")
     args = ap.parse_args()
+    if args.prof_summary:
+        kind, out, title, cmd, *dirs = args.prof_summary
+        prof_summary(kind, dirs, out, cmd, title)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 8
@@ -178,6 +287,7 @@ def main():
 
     pass_ms = 0.0
     pass_count = 0
+    pass_worked = 0
     iters = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -185,6 +295,7 @@ def main():
         out = ctx.fit_device(dy, p, f.tol, stream=stream, profile=1)
         pass_ms += out["pass_ms"]
         pass_count += out["pass_count"]
+        pass_worked += out["pass_worked"]
         iters.append(out["iters"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -198,8 +309,15 @@ def main():
         # the CG pass reads only the FP32 spectra and writes the block partials
         bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * nb * 8
         kernel_name = "toep_pass_kernel<float, fused>: X^T X v (CG normal-equation product)"
+    # Every launch of the pass is timed, including the few queued after a fit
+    # converged (they exit at once): bytes per launch is the algorithmic bytes
+    # of a working pass times the fraction of launches that worked.
     avg_pass_s = pass_ms / max(pass_count, 1) / 1e3
-    achieved = bytes_pass / avg_pass_s / 1e9 if pass_count else 0.0
+    bytes_launch = bytes_pass * pass_worked / max(pass_count, 1)
+    achieved = bytes_launch / avg_pass_s / 1e9 if pass_count else 0.0
+    traffic, traffic_src = None, "non-default configuration"
+    if not args.block_lg and not args.n:
+        traffic, traffic_src = read_hbm_profile(args.workload, args.precision)
     if args.workload == "ar500":
         ref = ctx.fit_device(dy, p, f.tol, stream=stream, precision=0)
         acc = gpu_fp64_agreement(y, p, out, ref)
@@ -225,10 +343,12 @@ def main():
                    "refine_steps": out["refine_steps"], "kappa_est_R": out["kappa_est"],
                    "status": capi.status_string(out["status"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "kernel": kernel_name,
-                     "bytes_per_launch": bytes_pass, "avg_launch_us": avg_pass_s * 1e6,
-                     "launches_timed": pass_count},
+                     "bytes_per_launch": bytes_launch, "bytes_per_working_launch": bytes_pass,
+                     "avg_launch_us": avg_pass_s * 1e6,
+                     "launches_timed": pass_count, "launches_worked": pass_worked},
         "accuracy": acc,
     }
     if not args.no_cpu:

@@ -89,9 +89,12 @@ typedef struct tls_result {
   int32_t block_len;   /* FFT block length B used */
   int32_t n_blocks;    /* FFT blocks per pass */
   double t_total_ms;   /* wall time of the call */
-  double pass_ms;      /* profile = 1: summed device time of the Toeplitz passes that did work */
-  int32_t pass_count;  /* profile = 1: number of those passes */
-  int32_t reserved1;
+  double pass_ms;      /* profile = 1: summed device time of every launch of the dominant
+                          Toeplitz pass (FP64: the fused LSQR pass; mixed: the FP32
+                          normal-equation pass), including launches queued after the fit
+                          had converged, which exit at once */
+  int32_t pass_count;  /* profile = 1: number of those launches */
+  int32_t pass_worked; /* profile = 1: how many of them did work */
 } tls_result;
 
 typedef struct tls_ctx tls_ctx;

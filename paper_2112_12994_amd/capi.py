@@ -57,7 +57,7 @@ class TlsResult(ctypes.Structure):
         ("t_total_ms", ctypes.c_double),
         ("pass_ms", ctypes.c_double),
         ("pass_count", ctypes.c_int32),
-        ("reserved1", ctypes.c_int32),
+        ("pass_worked", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -64,7 +64,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   }
   TLS_CHECK(hipGetLastError());
 
-  int total_iters = 0, istop = 0, refine = 0, pass_count = 0;
+  int total_iters = 0, istop = 0, refine = 0, pass_count = 0, pass_worked = 0;
   double pass_ms = 0.0, lsqr_rnorm = 0.0, lsqr_arnorm = 0.0;
   if (prec == TLS_PREC_F64) {
     // LSQR on A = X M from the warm start.
@@ -113,15 +113,15 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     lsqr_arnorm = ho->st.arnorm;
     if (o.profile) {
       // passes 0 .. iter did work; later launches in the last chunk exit at once
-      const size_t worked = std::min(npass, static_cast<size_t>(total_iters) + 1);
       double ms = 0.0;
-      for (size_t i = 0; i < worked; ++i) {
+      for (size_t i = 0; i < npass; ++i) {
         float t = 0.f;
         TLS_CHECK(hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]));
         ms += t;
       }
       pass_ms = ms;
-      pass_count = static_cast<int>(worked);
+      pass_count = static_cast<int>(npass);
+      pass_worked = static_cast<int>(std::min(npass, static_cast<size_t>(total_iters) + 1));
     }
   } else {
     // Mixed precision: FP64 residual and gradient of the current phi, then a
@@ -137,7 +137,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     size_t npass = 0;
     hipEvent_t ea = nullptr, eb = nullptr;
     RefineState* hr = &ho->rs;
-    double worked_ms = 0.0;
+    double all_ms = 0.0;
     int worked_passes = 0;
     for (int outer = 0; outer <= max_refine; ++outer) {
       const size_t first_pass = npass;
@@ -170,13 +170,12 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       }
       if (o.profile) {
         // the first `inner` passes of this outer step did work; later ones exited at once
-        const size_t worked = std::min(npass - first_pass, static_cast<size_t>(hr->inner));
-        for (size_t i = first_pass; i < first_pass + worked; ++i) {
+        for (size_t i = first_pass; i < npass; ++i) {
           float t = 0.f;
           TLS_CHECK(hipEventElapsedTime(&t, ctx->events[2 * i], ctx->events[2 * i + 1]));
-          worked_ms += t;
+          all_ms += t;
         }
-        worked_passes += static_cast<int>(worked);
+        worked_passes += static_cast<int>(std::min(npass - first_pass, static_cast<size_t>(hr->inner)));
       }
       if (hr->done) break;
     }
@@ -188,8 +187,9 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     lsqr_arnorm = hr->hnorm;
     istop = hr->stop == 1 ? 2 : (hr->stop == 7 ? 7 : (hr->stop == 5 ? 5 : 0));
     if (o.profile) {
-      pass_ms = worked_ms;
-      pass_count = worked_passes;
+      pass_ms = all_ms;
+      pass_count = static_cast<int>(npass);
+      pass_worked = worked_passes;
     }
   }
 
@@ -218,6 +218,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     res->n_blocks = pl.nblocks;
     res->pass_ms = pass_ms;
     res->pass_count = pass_count;
+    res->pass_worked = pass_worked;
     res->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   }
   for (int i = 0; i < p; ++i)
