@@ -43,6 +43,8 @@ WORKLOAD_TEXT = {
            "LSQR tol 1e-10, FP64",
     "ar500": "AR(500) series, n=2^25, 250 pole pairs with moduli U[0.5,0.95] and angles U(0,pi), "
              "N(0,1) innovations, seed 0; sketch 8p rows, tol 1e-10",
+    "batch": "2048 independent series, n=round(2^U(12,18)), p~U{4..64}, pole moduli U[0.3,0.95], "
+             "t5 innovations, seed 0; one batched call per step; sketch 8p rows, tol 1e-10",
 }
 
 
@@ -225,6 +227,126 @@ def gpu_fp64_agreement(y, p, out, ref):
             "f64_status": ref["status"]}
 
 
+def batch_bench(args, torch, synth, capi):
+    """The batched workload: `steps` calls of tls_fit_batch_device over 2048
+    resident series; value = fits per second.  Beside it: the same fits as
+    one synchronous FP64 tls_fit_device call each (the plain per-series
+    path), the oracle on a bounded subset, and agreement with the oracle on
+    a sample of fits."""
+    import oracle
+    prec = 1 if args.precision == "mixed" else 0
+    t0 = time.perf_counter()
+    fits = synth.workload_batch(seed=0)
+    print(f"[bench] batch of {len(fits)} generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    dys = [torch.from_numpy(f.y).to("cuda:0") for f in fits]
+    ps = [f.p for f in fits]
+    torch.cuda.synchronize()
+    ctx = capi.Context(0, gamma=8, precision=prec, block_lg=args.block_lg)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        s, outs = ctx.fit_batch_device(dys, ps, 1e-10, stream=stream)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done: status {capi.status_string(s) if args.warmup else None}",
+          file=sys.stderr, flush=True)
+    pass_ms = 0.0
+    pass_count = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s, outs = ctx.fit_batch_device(dys, ps, 1e-10, stream=stream, profile=1)
+        pass_ms += outs[0]["pass_ms"]
+        pass_count += outs[0]["pass_count"]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} batches in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # algorithmic bytes of the dominant pass over one batch: per fit, bytes of
+    # one pass times the passes that did work for it
+    tot_bytes = 0.0
+    for f, o in zip(fits, outs):
+        B, nb, m = o["block_len"], o["n_blocks"], f.y.size - f.p
+        if prec == 0:
+            tot_bytes += fused_pass_bytes(f.y.size, f.p, B, nb, 8) * (o["iters"] + 1)
+        else:
+            tot_bytes += (nb * (B // 2) * 8 + (B // 2) * 8 + (f.p + 1) * nb * 8) * o["iters"]
+    avg_launch_s = pass_ms / max(pass_count, 1) / 1e3
+    achieved = tot_bytes * args.steps / (pass_ms / 1e3) / 1e9 if pass_ms else 0.0
+    statuses = [o["status"] for o in outs]
+
+    # plain path: one synchronous FP64 fit per series
+    ctx64 = capi.Context(0, gamma=8, precision=0)
+    for i in range(8):
+        ctx64.fit_device(dys[i], ps[i], 1e-10, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, p in zip(dys, ps):
+        ctx64.fit_device(d, p, 1e-10, stream=stream)
+    torch.cuda.synchronize()
+    plain = len(fits) / (time.perf_counter() - t0)
+    ctx64.close()
+
+    # agreement with the oracle on every 32nd fit
+    errs = []
+    for i in range(0, len(fits), 32):
+        ref = oracle.fit_qr(fits[i].y, fits[i].p)
+        errs.append((ref["kappa"], oracle.rel_error(outs[i]["coef"], ref["phi"])))
+    gate = 1e-4 if prec else 1e-6
+    strata = {}
+    for lo, hi, name in [(0, 1e6, "kappa<1e6"), (1e6, 1e12, "1e6<=kappa<1e12"),
+                         (1e12, float("inf"), "kappa>=1e12")]:
+        sel = [e for k, e in errs if lo <= k < hi]
+        strata[name] = {"fits": len(sel), "within_gate": sum(e <= gate for e in sel),
+                        "max_rel_err": max(sel) if sel else None}
+
+    cpu = None
+    if not args.no_cpu:
+        cost = [(f.y.size - f.p) * (f.p + 1) ** 2 for f in fits]
+        t0 = time.perf_counter()
+        done = 0
+        for f in fits:
+            oracle.fit_qr(f.y, f.p)
+            done += 1
+            if time.perf_counter() - t0 > 15.0:
+                break
+        t = time.perf_counter() - t0
+        total = t * sum(cost) / sum(cost[:done])
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
+        except Exception:  # pragma: no cover
+            cores = os.cpu_count() or 1
+        cpu = {"value": len(fits) / total, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+               "sample": f"oracle.fit_qr on the first {done} of the {len(fits)} series in {t:.1f} s, "
+                         f"scaled by the m (p+1)^2 cost of all series"}
+    classes = sorted({(o["block_len"]) for o in outs})
+    line = {
+        "metric": METRIC, "value": args.steps * len(fits) / elapsed, "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prec == 0 else "f32 products, f64 recurrences",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["batch"], "fits_per_step": len(fits),
+                   "samples_per_step": int(sum(f.y.size for f in fits)),
+                   "precision": args.precision, "fft_blocks_used": classes,
+                   "status": capi.status_string(s),
+                   "fit_statuses": {capi.status_string(k): statuses.count(k) for k in set(statuses)},
+                   "median_iters": int(np.median([o["iters"] for o in outs]))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "traffic_source": "no counter profile for the batched pass",
+                     "kernel": "toep_b_kernel (batched Toeplitz pass, "
+                               + ("FP64 fused LSQR pass)" if prec == 0 else "FP32 normal-equation pass)"),
+                     "bytes_per_launch": tot_bytes / max(pass_count / args.steps, 1),
+                     "avg_launch_us": avg_launch_s * 1e6, "launches_timed": pass_count},
+        "plain_fp64_per_series": {"value": plain, "unit": "solves/s",
+                                  "what": "one synchronous FP64 tls_fit_device per series"},
+        "accuracy": {"oracle_sample": len(errs), "gate": gate, "by_kappa": strata},
+    }
+    if cpu:
+        line["cpu_baseline"] = cpu
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +392,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a ROCm GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batch":
+        batch_bench(args, torch, synth, capi)
+        return
     f = synth.WORKLOADS[args.workload](seed=0, **({"n": args.n} if args.n else {}))
     prec = 1 if args.precision == "mixed" else 0
     y, p = f.y, f.p

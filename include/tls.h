@@ -81,9 +81,11 @@ typedef struct tls_result {
   double lsqr_rnorm;   /* LSQR's own residual estimate */
   double lsqr_arnorm;  /* LSQR's ||A^T r|| estimate */
   int32_t iters;       /* total inner iterations */
-  int32_t istop;       /* stop reason: 1, 2 converged; 3 exact; 4 breakdown; 5 (mixed) no
-                          further contraction: the FP32 products reached their resolution
-                          (returned as TLS_OK); 7 iteration / refinement limit */
+  int32_t istop;       /* stop reason: 1, 2 converged; 3 exact; 4 breakdown; 7 iteration
+                          limit.  Mixed precision: 2 when the FP64 refinement converged;
+                          when it stopped contracting (conditioning beyond the FP32
+                          products' resolution) or hit its step limit, FP64 LSQR finishes
+                          from the best refinement iterate and its code is reported */
   int32_t refine_steps;/* outer refinement steps (mixed precision), else 0 */
   int32_t sketch_rows; /* c */
   int32_t block_len;   /* FFT block length B used */
@@ -93,7 +95,9 @@ typedef struct tls_result {
                           Toeplitz pass (FP64: the fused LSQR pass; mixed: the FP32
                           normal-equation pass), including launches queued after the fit
                           had converged, which exit at once */
-  int32_t pass_count;  /* profile = 1: number of those launches */
+  int32_t pass_count;  /* profile = 1: number of those launches (batched calls: pass_ms and
+                          pass_count cover the whole batch's launches, the same in every
+                          fit's result) */
   int32_t pass_worked; /* profile = 1: how many of them did work */
 } tls_result;
 

@@ -72,6 +72,20 @@ __global__ void post_qr_b_kernel(const FitDesc* D, int warm, int mixed) {
   }
 }
 
+// Mixed precision: fits whose refinement stopped without converging (stop 5
+// or 7) restart FP64 LSQR from their best iterate; the others are marked done
+// and counted.
+__global__ void fallback_prep_b_kernel(const FitDesc* D, int* counts) {
+  const FitDesc& d = D[blockIdx.x];
+  const int stop = d.rst->stop;
+  if (stop == 5 || stop == 7) {
+    for (int i = threadIdx.x; i < d.p; i += blockDim.x) d.phi0[i] = d.phib[i];
+  } else if (threadIdx.x == 0) {
+    d.st->done = 1;
+    atomicAdd(counts, 1);
+  }
+}
+
 __global__ void zero_ints_kernel(int* x, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0;
@@ -95,7 +109,13 @@ __global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* 
       r.arnorm = s.hnorm;
       r.iters = s.total_inner;
       r.refine = s.outer;
-      r.istop = s.stop == 1 ? 2 : (s.stop == 7 ? 7 : (s.stop == 5 ? 5 : 0));
+      r.istop = s.stop == 1 ? 2 : 0;
+      if (s.stop == 5 || s.stop == 7) {  // finished by FP64 LSQR
+        r.rnorm = d.st->rnorm;
+        r.arnorm = d.st->arnorm;
+        r.iters += d.st->iter;
+        r.istop = d.st->istop;
+      }
     } else {
       const LsqrState& s = *d.st;
       r.rnorm = s.rnorm;
@@ -147,6 +167,7 @@ void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, 
   d->z = b.z;
   d->phi0 = b.phi0;
   d->phi = b.phi;
+  d->phib = b.phib;
   d->idx = b.idx;
   d->scale = b.scale;
   d->swork = b.swork;
@@ -333,6 +354,23 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
   }
   const uint64_t seed = o.seed;
   const int cprec = mixed ? PREC_F32 : PREC_F64;
+  // profile = 1: event pairs around every launch of the dominant pass (FP64:
+  // the fused LSQR pass; mixed: the FP32 normal-equation pass)
+  size_t npass = 0;
+  auto timed = [&](auto&& launch) -> hipError_t {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (o.profile) {
+      hipError_t e = pass_events(ctx, npass, &ea, &eb);
+      if (e == hipSuccess) e = hipEventRecord(ea, s);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch();
+    if (e == hipSuccess && o.profile) {
+      e = hipEventRecord(eb, s);
+      ++npass;
+    }
+    return e;
+  };
 #define L_(lst) I + c.lst.off, c.lst.n
   for (const Cls& c : classes) {
     int* cnt = counts + 2 * (&c - classes.data());
@@ -356,16 +394,24 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
                        o.warm_start ? 1 : 0, mixed ? 1 : 0);
     TLS_CHECK(hipGetLastError());
 
-    if (!mixed) {
+    // FP64 LSQR over the class from phi0 (fits already done skip every step);
+    // counts[0] holds the number of finished fits.
+    auto lsqr64 = [&](bool time_it) -> tls_status {
+      auto pass = [&](int variant) -> hipError_t {
+        auto go = [&] {
+          return launch_toep_b(PREC_F64, c.lgn, variant, L_(blocks), D, ctx->consts, ctx->tw, s);
+        };
+        return time_it ? timed(go) : go();
+      };
       TLS_CHECK(launch_small_rfft_b(PREC_F64, c.lgn, 1, L_(fits), D, ctx->tw, s));
-      TLS_CHECK(launch_toep_b(PREC_F64, c.lgn, BP_LSQR_FIRST, L_(blocks), D, ctx->consts, ctx->tw, s));
+      TLS_CHECK(pass(BP_LSQR_FIRST));
       TLS_CHECK(launch_colsum_b(0, L_(cols), D, s));
       TLS_CHECK(launch_lsqr_step_b(PREC_F64, c.lgn, c.count, c.pmax, c.mlds, D + c.first, cnt,
                                    ctx->tw, s));
       int launched = 0;
       for (;;) {
         for (int it = 0; it < B_CHUNK_ITERS; ++it) {
-          TLS_CHECK(launch_toep_b(PREC_F64, c.lgn, BP_LSQR, L_(blocks), D, ctx->consts, ctx->tw, s));
+          TLS_CHECK(pass(BP_LSQR));
           TLS_CHECK(launch_colsum_b(0, L_(cols), D, s));
           TLS_CHECK(launch_lsqr_step_b(PREC_F64, c.lgn, c.count, c.pmax, c.mlds, D + c.first, cnt,
                                        ctx->tw, s));
@@ -375,6 +421,11 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         TLS_CHECK(hipStreamSynchronize(s));
         if (hcounts[0] >= c.count || launched > max_iter + B_CHUNK_ITERS) break;
       }
+      return TLS_OK;
+    };
+    if (!mixed) {
+      const tls_status e = lsqr64(o.profile != 0);
+      if (e != TLS_OK) return e;
     } else {
       for (int outer = 0; outer <= max_refine; ++outer) {
         hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, cnt, 2);
@@ -384,8 +435,10 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         TLS_CHECK(launch_refine_outer_b(c.lgn, c.count, c.pmax, D + c.first, cnt, ctx->tw, s));
         for (int it = 0; it < inner_max; it += B_INNER_CHUNK) {
           for (int k = it; k < std::min(inner_max, it + B_INNER_CHUNK); ++k) {
-            TLS_CHECK(launch_toep_b(PREC_F32, c.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
-                                    ctx->tw, s));
+            TLS_CHECK(timed([&] {
+              return launch_toep_b(PREC_F32, c.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
+                                   ctx->tw, s);
+            }));
             TLS_CHECK(launch_colsum_b(2, L_(cols), D, s));
             TLS_CHECK(launch_refine_cg_b(c.lgn, c.count, c.pmax, D + c.first, cnt, ctx->tw, s));
           }
@@ -394,6 +447,16 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
           if (hcounts[1] >= c.count) break;
         }
         if (hcounts[0] >= c.count) break;
+      }
+      // FP64 finish for the fits whose refinement stopped short
+      hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, cnt, 2);
+      hipLaunchKernelGGL(fallback_prep_b_kernel, dim3(c.count), dim3(64), 0, s, D + c.first, cnt);
+      TLS_CHECK(hipGetLastError());
+      TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      TLS_CHECK(hipStreamSynchronize(s));
+      if (hcounts[0] < c.count) {
+        const tls_status e = lsqr64(false);
+        if (e != TLS_OK) return e;
       }
     }
     // FP64 residual of the returned coefficients, row by row
@@ -411,6 +474,12 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
   }
   const auto t1 = std::chrono::steady_clock::now();
   const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  double pass_ms = 0.0;
+  for (size_t k = 0; k < npass; ++k) {
+    float t = 0.f;
+    TLS_CHECK(hipEventElapsedTime(&t, ctx->events[2 * k], ctx->events[2 * k + 1]));
+    pass_ms += t;
+  }
 
   int64_t off = 0;
   for (int j = 0; j < nb; ++j) {
@@ -434,6 +503,8 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       o_.block_len = pl.B;
       o_.n_blocks = pl.nblocks;
       o_.t_total_ms = ms;
+      o_.pass_ms = pass_ms;  // the whole batch's launches of the dominant pass
+      o_.pass_count = static_cast<int>(npass);
     }
     tls_status fs = TLS_OK;
     for (int k = 0; k < pl.p; ++k)

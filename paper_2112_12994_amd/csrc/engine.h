@@ -55,6 +55,7 @@ struct FitBufs {
   void* Omhat;
   void* Vhat;
   double *v, *w, *z, *phi0, *phi;
+  double* phib;     // mixed: best refinement iterate
   int64_t* idx;
   double* scale;
   double* swork;
@@ -255,6 +256,7 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->z = a.take<double>(pl.p);
   b->phi0 = a.take<double>(pl.p);
   b->phi = a.take<double>(pl.p);
+  b->phib = a.take<double>(pl.p);
   b->idx = a.take<int64_t>(pl.c);
   b->scale = a.take<double>(pl.c);
   b->swork = a.take<double>(sample_work_doubles(pl.m));
@@ -319,10 +321,8 @@ __global__ void zero_kernel(double* x, int n) {
 }
 
 struct HostOut {
-  union {
-    LsqrState st;
-    RefineState rs;
-  };
+  LsqrState st;
+  RefineState rs;
   double dminmax[4];
   double rr[4];
   int status[4];

@@ -66,52 +66,44 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
 
   int total_iters = 0, istop = 0, refine = 0, pass_count = 0, pass_worked = 0;
   double pass_ms = 0.0, lsqr_rnorm = 0.0, lsqr_arnorm = 0.0;
-  if (prec == TLS_PREC_F64) {
-    // LSQR on A = X M from the warm start.
+
+  // FP64 LSQR on A = X M from phi0 over the FP64 spectra `spec`; `timed`:
+  // event pairs around every fused pass.
+  auto lsqr64 = [&](const void* spec, bool timed) -> tls_status {
     const int* flag = &b.st->done;
     size_t npass = 0;
     hipEvent_t ea = nullptr, eb = nullptr;
-    TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.phi0, p, p, 1, invB, b.Vhat, ctx->tw, nullptr, s));
-    if (o.profile) {
-      TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
-      TLS_CHECK(hipEventRecord(ea, s));
-    }
-    TLS_CHECK(launch_toep(prec, pl.lgn, MODE_FUSED, b.Yhat, b.Vhat, d_y + p, b.u, nullptr,
-                          b.partial, b.st->coef, flag, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
-    if (o.profile) {
-      TLS_CHECK(hipEventRecord(eb, s));
-      ++npass;
-    }
-    TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, flag, s));
-    TLS_CHECK(launch_lsqr_step(prec, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0, b.phi,
-                               b.Vhat, ctx->tw, s));
+    auto pass = [&](const void* w_in) -> tls_status {
+      if (timed) {
+        TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
+        TLS_CHECK(hipEventRecord(ea, s));
+      }
+      TLS_CHECK(launch_toep(PREC_F64, pl.lgn, MODE_FUSED, spec, b.Vhat, w_in, b.u, nullptr,
+                            b.partial, b.st->coef, flag, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
+      if (timed) {
+        TLS_CHECK(hipEventRecord(eb, s));
+        ++npass;
+      }
+      TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, flag, s));
+      TLS_CHECK(launch_lsqr_step(PREC_F64, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
+                                 b.phi, b.Vhat, ctx->tw, s));
+      return TLS_OK;
+    };
+    TLS_CHECK(launch_small_rfft(PREC_F64, pl.lgn, b.phi0, p, p, 1, invB, b.Vhat, ctx->tw, nullptr, s));
+    tls_status e = pass(d_y + p);
+    if (e != TLS_OK) return e;
     int launched = 0;
     for (;;) {
       for (int it = 0; it < CHUNK_ITERS; ++it) {
-        if (o.profile) {
-          TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
-          TLS_CHECK(hipEventRecord(ea, s));
-        }
-        TLS_CHECK(launch_toep(prec, pl.lgn, MODE_FUSED, b.Yhat, b.Vhat, b.u, b.u, nullptr,
-                              b.partial, b.st->coef, flag, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
-        if (o.profile) {
-          TLS_CHECK(hipEventRecord(eb, s));
-          ++npass;
-        }
-        TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, flag, s));
-        TLS_CHECK(launch_lsqr_step(prec, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
-                                   b.phi, b.Vhat, ctx->tw, s));
+        e = pass(b.u);
+        if (e != TLS_OK) return e;
       }
       launched += CHUNK_ITERS;
       TLS_CHECK(hipMemcpyAsync(&ho->st, b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
       TLS_CHECK(hipStreamSynchronize(s));
       if (ho->st.done || launched > max_iter + CHUNK_ITERS) break;
     }
-    total_iters = ho->st.iter;
-    istop = ho->st.istop;
-    lsqr_rnorm = ho->st.rnorm;
-    lsqr_arnorm = ho->st.arnorm;
-    if (o.profile) {
+    if (timed) {
       // passes 0 .. iter did work; later launches in the last chunk exit at once
       double ms = 0.0;
       for (size_t i = 0; i < npass; ++i) {
@@ -121,12 +113,25 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       }
       pass_ms = ms;
       pass_count = static_cast<int>(npass);
-      pass_worked = static_cast<int>(std::min(npass, static_cast<size_t>(total_iters) + 1));
+      pass_worked = static_cast<int>(std::min(npass, static_cast<size_t>(ho->st.iter) + 1));
     }
+    return TLS_OK;
+  };
+
+  if (prec == TLS_PREC_F64) {
+    const tls_status e = lsqr64(b.Yhat, o.profile != 0);
+    if (e != TLS_OK) return e;
+    total_iters = ho->st.iter;
+    istop = ho->st.istop;
+    lsqr_rnorm = ho->st.rnorm;
+    lsqr_arnorm = ho->st.arnorm;
   } else {
     // Mixed precision: FP64 residual and gradient of the current phi, then a
     // CG solve of the preconditioned normal equations for the correction,
     // whose X^T X products are single FP32 passes over the FP32 spectra.
+    // When the FP32 products stop contracting (conditioning beyond their
+    // resolution) or the step limit is reached, FP64 LSQR over the FP64
+    // spectra finishes from the best iterate.
     const int max_refine = o.max_refine > 0 ? o.max_refine : 8;
     const int inner_max = std::min(max_iter, 25);
     constexpr int INNER_CHUNK = 6;
@@ -145,8 +150,8 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       TLS_CHECK(launch_toep(PREC_F64, pl.lgn, MODE_FUSED, b.Yhat64, b.Vhat, d_y + p, nullptr, nullptr,
                             b.partial, ctx->consts, &b.rst->done, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
       TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, &b.rst->done, s));
-      TLS_CHECK(launch_refine_outer(pl.lgn, p, b.rst, b.g, b.M, b.Mt, b.cw, b.cres, b.cd, b.Vhat32,
-                                    ctx->tw, s));
+      TLS_CHECK(launch_refine_outer(pl.lgn, p, b.rst, b.g, b.M, b.Mt, b.phi, b.phib, b.cw, b.cres,
+                                    b.cd, b.Vhat32, ctx->tw, s));
       for (int it = 0; it < inner_max; it += INNER_CHUNK) {
         for (int k = it; k < std::min(inner_max, it + INNER_CHUNK); ++k) {
           if (o.profile) {
@@ -181,11 +186,22 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     }
     TLS_CHECK(hipMemcpyAsync(hr, b.rst, sizeof(RefineState), hipMemcpyDeviceToHost, s));
     TLS_CHECK(hipStreamSynchronize(s));
-    total_iters = hr->total_inner;
-    refine = hr->outer;
-    lsqr_rnorm = hr->rnorm;
-    lsqr_arnorm = hr->hnorm;
-    istop = hr->stop == 1 ? 2 : (hr->stop == 7 ? 7 : (hr->stop == 5 ? 5 : 0));
+    const RefineState rs = *hr;
+    total_iters = rs.total_inner;
+    refine = rs.outer;
+    lsqr_rnorm = rs.rnorm;
+    lsqr_arnorm = rs.hnorm;
+    istop = rs.stop == 1 ? 2 : 0;
+    if (rs.stop == 5 || rs.stop == 7) {
+      hipLaunchKernelGGL(copy_vec_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phib, p, b.phi0);
+      TLS_CHECK(hipGetLastError());
+      const tls_status e = lsqr64(b.Yhat64, false);
+      if (e != TLS_OK) return e;
+      total_iters += ho->st.iter;
+      istop = ho->st.istop;
+      lsqr_rnorm = ho->st.rnorm;
+      lsqr_arnorm = ho->st.arnorm;
+    }
     if (o.profile) {
       pass_ms = all_ms;
       pass_count = static_cast<int>(npass);

@@ -86,15 +86,17 @@ hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const doubl
 // Mixed-precision refinement (FP64 outer residual, FP32 inner CG on the
 // preconditioned normal equations).
 struct RefineState {
-  double rho, rho0, tol, inner_tol, rnorm, hnorm, hprev;
+  double rho, rho0, tol, inner_tol, rnorm, hnorm, hprev, hbest;
   int outer, inner, max_refine, inner_max, done, inner_done, total_inner, stop;
 };
-// g64: X^T r (p) and ||r||^2 ([p]) for r = b - X phi.  Checks convergence
+// g64: X^T r (p) and ||r||^2 ([p]) for r = b - X phi.  Keeps the iterate with
+// the smallest preconditioned gradient in phib.  Checks convergence
 // (||M^T g|| <= tol ||r||), else starts CG: w = 0, res = d = M^T g, and
 // writes the packed FP32 spectrum of M d (scaled 1/B) to Vhat32.
 hipError_t launch_refine_outer(int lgn, int p, RefineState* st, const double* g64, const double* M,
-                               const double* Mt, double* w, double* res, double* d,
-                               void* Vhat32, const Twiddles& tw, hipStream_t s);
+                               const double* Mt, const double* phi, double* phib, double* w,
+                               double* res, double* d, void* Vhat32, const Twiddles& tw,
+                               hipStream_t s);
 // g: X^T X (M d) (p) from the FP32 Gram pass.  One CG step; when the inner
 // solve ends, phi += M w.
 hipError_t launch_refine_cg(int lgn, int p, RefineState* st, const double* g, const double* M,
@@ -117,7 +119,7 @@ struct FitDesc {
   void* Omhat;
   void* Vhat;
   void* Vhat32;
-  double *v, *w, *z, *phi0, *phi;
+  double *v, *w, *z, *phi0, *phi, *phib;
   int64_t* idx;
   double *scale, *swork;
   LsqrState* st;
@@ -133,8 +135,8 @@ struct Item {
 
 // Variants of the batched Toeplitz pass.
 enum BatchPass : int {
-  BP_LSQR_FIRST = 0,  // e = b - X phi0 into u, X^T e   (FP64 / compute precision)
-  BP_LSQR = 1,        // e = X (M v) - (alpha/beta) u in place, X^T e
+  BP_LSQR_FIRST = 0,  // FP64: e = b - X phi0 into u, X^T e (FP64 spectra)
+  BP_LSQR = 1,        // FP64: e = X (M v) - (alpha/beta) u in place, X^T e
   BP_OUTER64 = 2,     // FP64: r = b - X phi, X^T r (nothing stored)
   BP_INNER32 = 3,     // FP32: X^T X (M d) (nothing stored)
 };

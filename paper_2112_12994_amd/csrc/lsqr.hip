@@ -371,6 +371,8 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
                                                           const double* __restrict__ g64,
                                                           const double* __restrict__ M,
                                                           const double* __restrict__ Mt,
+                                                          const double* __restrict__ phi,
+                                                          double* __restrict__ phib,
                                                           double* __restrict__ w,
                                                           double* __restrict__ res,
                                                           double* __restrict__ d,
@@ -395,6 +397,11 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
   const double hh = dot_block<NT>(sh, sh, p, red);
   const double hn = sqrt(hh), rn = sqrt(g64[p]);
   const int outer = st->outer;
+  // keep the best iterate: the FP32 products may stop contracting, or expand,
+  // beyond their resolution
+  const bool best = outer == 0 || hn < st->hbest;
+  if (best)
+    for (int i = threadIdx.x; i < p; i += NT) phib[i] = phi[i];
   bool done = false;
   int stop = 0;
   if (hn <= st->tol * rn) {
@@ -419,6 +426,7 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
   if (threadIdx.x == 0) {
     st->rnorm = rn;
     st->hprev = st->hnorm > 0.0 ? fmin(st->hnorm, hn) : hn;
+    if (best) st->hbest = hn;
     st->hnorm = hn;
     st->rho = hh;
     st->rho0 = hh;
@@ -435,12 +443,14 @@ __global__ __launch_bounds__(NT) void refine_outer_kernel(int p, RefineState* __
                                                           const double* __restrict__ g64,
                                                           const double* __restrict__ M,
                                                           const double* __restrict__ Mt,
+                                                          const double* __restrict__ phi,
+                                                          double* __restrict__ phib,
                                                           double* __restrict__ w,
                                                           double* __restrict__ res,
                                                           double* __restrict__ d,
                                                           cx<float>* __restrict__ Vhat32,
                                                           const cx<double>* __restrict__ tab) {
-  refine_outer_body<LGN, NT>(p, st, g64, M, Mt, w, res, d, Vhat32, tab);
+  refine_outer_body<LGN, NT>(p, st, g64, M, Mt, phi, phib, w, res, d, Vhat32, tab);
 }
 
 template <int LGN, int NT>
@@ -519,12 +529,13 @@ __global__ __launch_bounds__(NT) void refine_cg_kernel(int p, RefineState* __res
 
 template <int LGN>
 hipError_t refine_outer_one(int p, RefineState* st, const double* g64, const double* M,
-                            const double* Mt, double* w, double* res, double* d, void* Vhat32,
-                            const Twiddles& tw, hipStream_t s) {
+                            const double* Mt, const double* phi, double* phib, double* w,
+                            double* res, double* d, void* Vhat32, const Twiddles& tw,
+                            hipStream_t s) {
   const size_t shm = (3 * static_cast<size_t>(p) + (p <= 128 ? static_cast<size_t>(p) * (p | 1) : 0)) *
                      sizeof(double);
   hipLaunchKernelGGL((refine_outer_kernel<LGN, 256>), dim3(1), dim3(256), shm, s, p, st, g64, M, Mt,
-                     w, res, d, static_cast<cx<float>*>(Vhat32),
+                     phi, phib, w, res, d, static_cast<cx<float>*>(Vhat32),
                      static_cast<const cx<double>*>(tw.d64));
   return hipGetLastError();
 }
@@ -594,9 +605,10 @@ hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const doubl
   }
 
 hipError_t launch_refine_outer(int lgn, int p, RefineState* st, const double* g64, const double* M,
-                               const double* Mt, double* w, double* res, double* d, void* Vhat32,
-                               const Twiddles& tw, hipStream_t s) {
-#define TLS_OUTER(LG) refine_outer_one<LG>(p, st, g64, M, Mt, w, res, d, Vhat32, tw, s)
+                               const double* Mt, const double* phi, double* phib, double* w,
+                               double* res, double* d, void* Vhat32, const Twiddles& tw,
+                               hipStream_t s) {
+#define TLS_OUTER(LG) refine_outer_one<LG>(p, st, g64, M, Mt, phi, phib, w, res, d, Vhat32, tw, s)
   TLS_LG_SWITCH(TLS_OUTER)
 #undef TLS_OUTER
 }
@@ -638,7 +650,7 @@ __global__ __launch_bounds__(NT) void refine_outer_b_kernel(const FitDesc* __res
                                                             const cx<double>* __restrict__ tab) {
   const FitDesc& d = D[blockIdx.x];
   if (!d.rst->done)
-    refine_outer_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.cw, d.cres, d.cd,
+    refine_outer_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.phi, d.phib, d.cw, d.cres, d.cd,
                                static_cast<cx<float>*>(d.Vhat32), tab);
   if (threadIdx.x == 0) {
     if (d.rst->done) atomicAdd(counts, 1);

@@ -276,7 +276,7 @@ __global__ __launch_bounds__(NT) void toep_b_kernel(const Item* __restrict__ ite
   if constexpr (VARIANT == BP_LSQR_FIRST || VARIANT == BP_LSQR) {
     const T* w = VARIANT == BP_LSQR_FIRST ? reinterpret_cast<const T*>(d.y + d.p)
                                           : static_cast<const T*>(d.u);
-    toep_pass_body<T, LGN, NT, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat),
+    toep_pass_body<T, LGN, NT, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat64),
                                            static_cast<const cx<T>*>(d.Vhat), w,
                                            static_cast<T*>(d.u), nullptr, d.partial, d.st->coef,
                                            &d.st->done, tab, d.m, d.p, d.L, d.nblocks, it.idx);

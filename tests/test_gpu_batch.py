@@ -131,3 +131,22 @@ def test_batch_against_oracle(ctx):
         say("   p=%d kappa=%.3g err=%.3g" % (p, ref["kappa"], err))
         assert err <= 1e-6
         assert abs(o["resid_norm"] - ref["rnorm"]) <= 1e-9 * ref["rnorm"]
+
+
+def test_batch_mixed_fp64_finish_equals_single(ctx):
+    """Mixed batch with series beyond FP32 resolution (pole moduli up to
+    0.95): the fits whose refinement stalls finish in FP64 LSQR inside the
+    batch, bit for bit as alone, and reach the FP64 path's residual."""
+    say("batch mixed fp64 finish")
+    rng = np.random.default_rng(18)
+    ps = [40, 64, 12, 50]
+    ys = [synth.ar_series(int(n), p, rng, 0.5, 0.95) for n, p in zip([60000, 100000, 20000, 80000], ps)]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=9, precision=1)
+    assert s == capi().TLS_OK
+    _same_as_single(ctx, ys, ps, outs, 9, device=True, precision=1)
+    for y, p, o in zip(ys, ps, outs):
+        f64 = ctx.fit(y, p, 1e-10)
+        say("   p=%d refine=%d iters=%d istop=%d kappa_R=%.3g resid %.12g vs %.12g"
+            % (p, o["refine_steps"], o["iters"], o["istop"], o["kappa_est"], o["resid_norm"],
+               f64["resid_norm"]))
+        assert abs(o["resid_norm"] - f64["resid_norm"]) <= 1e-9 * f64["resid_norm"]
