@@ -46,6 +46,7 @@ typedef int32_t tls_status;
 #define TLS_ENOMEM 4      /* device allocation failed */
 #define TLS_EDEVICE 5     /* HIP runtime error */
 #define TLS_EUNSUPPORTED 6 /* size outside the supported range (p > 1024 or FFT block limits) */
+#define TLS_EAGAIN 7      /* served request not finished yet (tls_poll) */
 
 /* Static description of a status code. */
 const char* tls_status_string(tls_status s);
@@ -159,6 +160,68 @@ tls_status tls_fit_batch_device(tls_ctx* ctx, int32_t count, const double* const
                                 const tls_options* opt, void* stream, double* coef_packed,
                                 const int64_t* coef_offset, tls_result* out,
                                 tls_status* per_fit_status);
+
+/* ---- served continuous batching ----------------------------------------------
+ * A server admits fit requests as they arrive and runs them to completion on
+ * one device: each tick of its worker thread sets up the newly admitted fits
+ * and runs one LSQR step for every fit in flight, all as batched launches, so
+ * short and long, small-p and large-p requests share the device.  A request is
+ * admitted first come, first served once its device footprint (series copy,
+ * block spectra, sketch, factors, LSQR state: about 25 bytes per sample plus
+ * O(c p + p^2) for the FP64 path) fits in the server's HBM budget and a slot is
+ * free.  Each request gives the same result, bit for bit, as tls_fit_device
+ * with the server's options and request_id, whatever else is in flight.
+ * Submit, poll and wait are thread-safe; the context must outlive the server
+ * (the server uses only its read-only tables, not its workspace or stream). */
+typedef struct tls_server tls_server;
+typedef uint64_t tls_ticket;
+
+typedef struct tls_server_stats {
+  uint64_t ticks;             /* worker ticks so far */
+  uint64_t admitted;          /* requests admitted to the device */
+  uint64_t completed;         /* requests finished */
+  uint64_t queued;            /* waiting for admission */
+  uint64_t in_flight;         /* admitted, not finished */
+  uint64_t arena_bytes_in_use;
+  uint64_t arena_bytes;       /* the HBM budget */
+  tls_status status;          /* TLS_OK, or the device error that stopped the worker */
+  int32_t reserved;
+} tls_server_stats;
+
+/* Create a server on ctx's device with `hbm_budget` bytes of device memory
+ * (allocated now, at least 1 MiB) and at most `max_slots` fits in flight.
+ * opt NULL = the context's options; only TLS_PREC_F64 is served
+ * (TLS_EUNSUPPORTED otherwise).  TLS_ENOMEM if the budget cannot be allocated. */
+tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
+                             const tls_options* opt, tls_server** out);
+
+/* Queue a fit of the host series (copied before return) of length n, order p,
+ * LSQR tolerance tol; request_id selects its random streams (Philox fit id).
+ * Validation as tls_fit_ex: TLS_EINVAL, TLS_EUNSUPPORTED (p = 1024), TLS_ENOMEM
+ * (footprint above the whole budget).  *ticket identifies the request. */
+tls_status tls_submit(tls_server* server, const double* series, int64_t n, int32_t p, double tol,
+                      uint64_t request_id, tls_ticket* ticket);
+
+/* Same with the series in device memory on the server's device, borrowed (not
+ * copied): it must stay valid and unmodified until the request is finished. */
+tls_status tls_submit_device(tls_server* server, const double* d_series, int64_t n, int32_t p,
+                             double tol, uint64_t request_id, tls_ticket* ticket);
+
+/* Result of a finished request: coef (host, p doubles), out and fit_status
+ * (the status tls_fit_device would return) may each be NULL; out->t_total_ms
+ * is the request's latency from submission to completion.  Returns TLS_OK and
+ * forgets the ticket, TLS_EAGAIN while the request is in flight (tls_poll),
+ * or TLS_EINVAL for an unknown ticket.  tls_wait blocks until finished. */
+tls_status tls_poll(tls_server* server, tls_ticket ticket, double* coef, tls_result* out,
+                    tls_status* fit_status);
+tls_status tls_wait(tls_server* server, tls_ticket ticket, double* coef, tls_result* out,
+                    tls_status* fit_status);
+
+tls_status tls_server_get_stats(tls_server* server, tls_server_stats* out);
+
+/* Runs every queued and in-flight request to completion, then frees the
+ * server; results not yet taken are discarded. */
+void tls_server_destroy(tls_server* server);
 
 /* ---- step-level entry points (device pointers; work enqueued on stream) ----
  * These run one step of the path on its own so that each step can be checked

@@ -15,7 +15,8 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtls.so")
 
-TLS_OK, TLS_EINVAL, TLS_ERANK, TLS_ENOCONV, TLS_ENOMEM, TLS_EDEVICE, TLS_EUNSUPPORTED = range(7)
+(TLS_OK, TLS_EINVAL, TLS_ERANK, TLS_ENOCONV, TLS_ENOMEM, TLS_EDEVICE, TLS_EUNSUPPORTED,
+ TLS_EAGAIN) = range(8)
 PREC_F64, PREC_MIXED = 0, 1
 SKETCH_LEVERAGE, SKETCH_UNIFORM = 0, 1
 JL_SRHT, JL_GAUSS = 0, 1
@@ -39,6 +40,20 @@ class TlsOptions(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("request_id", ctypes.c_uint64),
         ("reserved", ctypes.c_int64 * 4),
+    ]
+
+
+class TlsServerStats(ctypes.Structure):
+    _fields_ = [
+        ("ticks", ctypes.c_uint64),
+        ("admitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("queued", ctypes.c_uint64),
+        ("in_flight", ctypes.c_uint64),
+        ("arena_bytes_in_use", ctypes.c_uint64),
+        ("arena_bytes", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -125,6 +140,14 @@ _SIGS = {
                                     _c.POINTER(_i32), _c.c_double, _c.POINTER(TlsOptions), _vp,
                                     _dp, _c.POINTER(_i64), _c.POINTER(TlsResult),
                                     _c.POINTER(_i32)]),
+    "tls_server_create": (_i32, [_ctxp, _c.c_size_t, _i32, _c.POINTER(TlsOptions),
+                                 _c.POINTER(_vp)]),
+    "tls_submit": (_i32, [_vp, _dp, _i64, _i32, _c.c_double, _u64, _c.POINTER(_u64)]),
+    "tls_submit_device": (_i32, [_vp, _vp, _i64, _i32, _c.c_double, _u64, _c.POINTER(_u64)]),
+    "tls_poll": (_i32, [_vp, _u64, _dp, _c.POINTER(TlsResult), _c.POINTER(_i32)]),
+    "tls_wait": (_i32, [_vp, _u64, _dp, _c.POINTER(TlsResult), _c.POINTER(_i32)]),
+    "tls_server_get_stats": (_i32, [_vp, _c.POINTER(TlsServerStats)]),
+    "tls_server_destroy": (None, [_vp]),
     "tls_num_blocks": (_i64, [_i64, _i32, _i32]),
     "tls_op_spectra": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _vp, _vp]),
     "tls_op_toeplitz": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _dp, _c.c_double, _c.c_double,
@@ -355,6 +378,84 @@ class Context:
     def op_philox(self, seed, rng_stream, fit, start, count, d_out, stream=None):
         return lib.tls_op_philox(self._h, seed, rng_stream, fit, start, count, _ptr(d_out),
                                  _stream(stream))
+
+
+class Server:
+    """A tls_server on a Context: submit fits at any time, take results by
+    ticket.  Device series are borrowed: the tensor is kept referenced here
+    until its result is taken."""
+
+    def __init__(self, ctx: "Context", hbm_budget: int, max_slots: int = 4096, **opts):
+        self._h = ctypes.c_void_p()
+        self.ctx = ctx
+        o = ctx._opt(opts)
+        _check(lib.tls_server_create(ctx.handle, hbm_budget, max_slots, ctypes.byref(o),
+                                     ctypes.byref(self._h)), "tls_server_create")
+        self._p = {}
+        self._keep = {}
+
+    def submit(self, series, p: int, tol: float = 1e-10, request_id: int = 0) -> int:
+        """Host series (copied); returns the ticket, raises TlsError on rejection."""
+        y = np.ascontiguousarray(series, dtype=np.float64)
+        t = _u64(0)
+        _check(lib.tls_submit(self._h, _dptr(y), y.size, p, tol, request_id, ctypes.byref(t)),
+               "tls_submit")
+        self._p[t.value] = p
+        return t.value
+
+    def submit_device(self, d_series, p: int, tol: float = 1e-10, request_id: int = 0) -> int:
+        """torch float64 device tensor (borrowed until the result is taken)."""
+        t = _u64(0)
+        _check(lib.tls_submit_device(self._h, _ptr(d_series), d_series.numel(), p, tol, request_id,
+                                     ctypes.byref(t)), "tls_submit_device")
+        self._p[t.value] = p
+        self._keep[t.value] = d_series
+        return t.value
+
+    def _take(self, fn, ticket: int):
+        p = self._p.get(ticket, 0)
+        coef = np.zeros(max(p, 1))
+        res = TlsResult()
+        st = _i32(0)
+        s = fn(self._h, ticket, _dptr(coef), ctypes.byref(res), ctypes.byref(st))
+        if s == TLS_EAGAIN:
+            return None
+        _check(s, "tls_wait/poll")
+        self._p.pop(ticket, None)
+        self._keep.pop(ticket, None)
+        out = res.as_dict()
+        out.update(status=st.value, coef=coef[:p])
+        return out
+
+    def poll(self, ticket: int):
+        """Result dict, or None while in flight."""
+        return self._take(lib.tls_poll, ticket)
+
+    def wait(self, ticket: int):
+        return self._take(lib.tls_wait, ticket)
+
+    def stats(self) -> dict:
+        s = TlsServerStats()
+        _check(lib.tls_server_get_stats(self._h, ctypes.byref(s)), "tls_server_get_stats")
+        return {f: getattr(s, f) for f, _ in s._fields_ if f != "reserved"}
+
+    def close(self):
+        if self._h:
+            lib.tls_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def num_blocks(n: int, p: int, B: int) -> int:

@@ -1,59 +1,41 @@
-// Batched driver: many independent AR(p) fits of different lengths and orders
-// in one pass over the device.
+// Batched execution: many independent AR(p) fits of different lengths and
+// orders in one pass over the device.
 //
 // Every kernel of the single-fit path has a batched twin that maps its
 // workgroup index through a table of work items {fit, local index} to a
 // per-fit descriptor (FitDesc), so one launch serves the blocks, rows, tiles
 // or columns of all fits of a launch class.  A launch class groups the fits
-// that share every compile-time choice the single-fit path makes for them:
-// the FFT half-length, the register-tile counts of the Cholesky (q = p + 1)
-// and of the triangular inverse (p), and whether the LSQR step stages M in
-// LDS.  Within a class each fit runs exactly the arithmetic of its single
-// fit, so the result of fit i equals tls_fit_ex with request_id + i bit for
-// bit.  Fits that finish early leave their later workgroups with nothing to
-// do (each checks its fit's done flag first); device counters tell the host
-// when a whole class has finished.
+// that share every compile-time choice the single-fit path makes for them
+// (ClassKey); within a class each fit runs exactly the arithmetic of its
+// single fit, so the result of fit i equals tls_fit_ex with request_id + i
+// bit for bit.  Fits that finish early leave their later workgroups with
+// nothing to do (each checks its fit's done flag first); device counters tell
+// the host when a whole class has finished.
+//
+// The first part is the execution core shared with the server (server.hip);
+// the second the batched driver behind tls_fit_batch*.
 #include "engine.h"
 
 #include <map>
-#include <tuple>
 
 namespace {
 
 constexpr int B_CHUNK_ITERS = 8;
 constexpr int B_INNER_CHUNK = 6;
 
-struct FitRec {
-  double rr, dmax, dmin, rnorm, arnorm;
-  int status[4];
-  int iters, istop, refine, pad;
-};
-
-struct List {
-  int off = 0, n = 0;
-};
-
-struct Cls {
-  int lgn = 0, qt = 0, pt = 0;
-  bool mlds = false;
-  int first = 0, count = 0, pmax = 0, ldqmax = 0;
-  List blocks, blocks1, rows1, rows2, tiles1, tiles2, rowtiles2, trmm2, fits, fits1, jl, chunks, draws, cols,
-      rblocks;
-};
-
-__global__ void init_b_kernel(FitDesc* D, int nfits, double tol, int max_iter, int max_refine,
-                              int inner_max, double inner_tol) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nfits) return;
-  const FitDesc& d = D[f];
+__global__ void init_b_kernel(const Item* fits, int nfits, FitDesc* D, int max_iter,
+                              int max_refine, int inner_max, double inner_tol) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nfits) return;
+  const FitDesc& d = D[fits[k].fit];
   LsqrState s{};
-  s.tol = tol;
+  s.tol = d.tol;
   s.max_iter = max_iter;
   s.coef[0] = -1.0;
   s.coef[1] = 1.0;
   *d.st = s;
   RefineState r{};
-  r.tol = tol;
+  r.tol = d.tol;
   r.max_refine = max_refine;
   r.inner_max = inner_max;
   r.inner_tol = inner_tol;
@@ -63,8 +45,8 @@ __global__ void init_b_kernel(FitDesc* D, int nfits, double tol, int max_iter, i
 
 // After the final QR: zero phi0 for a cold start; the mixed refinement starts
 // from phi = phi0.
-__global__ void post_qr_b_kernel(const FitDesc* D, int warm, int mixed) {
-  const FitDesc& d = D[blockIdx.x];
+__global__ void post_qr_b_kernel(const Item* fits, const FitDesc* D, int warm, int mixed) {
+  const FitDesc& d = D[fits[blockIdx.x].fit];
   for (int i = threadIdx.x; i < d.p; i += blockDim.x) {
     const double v = warm ? d.phi0[i] : 0.0;
     if (!warm) d.phi0[i] = 0.0;
@@ -75,8 +57,8 @@ __global__ void post_qr_b_kernel(const FitDesc* D, int warm, int mixed) {
 // Mixed precision: fits whose refinement stopped without converging (stop 5
 // or 7) restart FP64 LSQR from their best iterate; the others are marked done
 // and counted.
-__global__ void fallback_prep_b_kernel(const FitDesc* D, int* counts) {
-  const FitDesc& d = D[blockIdx.x];
+__global__ void fallback_prep_b_kernel(const Item* fits, const FitDesc* D, int* counts) {
+  const FitDesc& d = D[fits[blockIdx.x].fit];
   const int stop = d.rst->stop;
   if (stop == 5 || stop == 7) {
     for (int i = threadIdx.x; i < d.p; i += blockDim.x) d.phi0[i] = d.phib[i];
@@ -91,7 +73,6 @@ __global__ void zero_ints_kernel(int* x, int n) {
   if (i < n) x[i] = 0;
 }
 
-// Item idx = offset of the fit's coefficients in the packed output.
 __global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* __restrict__ D,
                                  int mixed, double* __restrict__ coef, FitRec* __restrict__ rec) {
   const Item it = items[blockIdx.x];
@@ -123,15 +104,69 @@ __global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* 
       r.iters = s.iter;
       r.istop = s.istop;
     }
-    rec[it.fit] = r;
+    rec[blockIdx.x] = r;
   }
 }
 
-void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, FitDesc* d) {
+template <typename F>
+List add_items(std::vector<Item>& all, const std::vector<int>& desc,
+               const std::vector<const Plan*>& plans, F&& per_fit) {
+  List l;
+  l.off = static_cast<int>(all.size());
+  for (size_t j = 0; j < desc.size(); ++j) {
+    const int cnt = per_fit(*plans[j]);
+    for (int i = 0; i < cnt; ++i) all.push_back({desc[j], i});
+  }
+  l.n = static_cast<int>(all.size()) - l.off;
+  return l;
+}
+
+}  // namespace
+
+// ---- execution core -----------------------------------------------------------
+
+ClassKey class_key(const Plan& pl) {
+  ClassKey k;
+  k.lgn = pl.lgn;
+  k.qt = (pl.q + 15) / 16 <= 8 ? (pl.q + 15) / 16 : 0;
+  k.pt = pl.p <= 128 ? (pl.p + 15) / 16 : 0;
+  k.mlds = lsqr_step_lds(pl.lgn, pl.p) ? 1 : 0;
+  return k;
+}
+
+ClassLists build_lists(std::vector<Item>& items, const std::vector<int>& desc,
+                       const std::vector<const Plan*>& plans, bool lev) {
+  ClassLists c;
+  auto sampled = [lev](const Plan& q) { return lev && !q.all_rows; };
+  c.blocks = add_items(items, desc, plans, [](const Plan& q) { return q.nblocks; });
+  c.blocks1 = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? q.nblocks : 0; });
+  c.rows1 = add_items(items, desc, plans, [](const Plan& q) { return q.crows; });
+  c.rows2 = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? q.crows : 0; });
+  c.tiles1 = add_items(items, desc, plans, [&](const Plan& q) {
+    return sampled(q) ? (q.ldq / 16) * (q.ldq / 16) : 0;
+  });
+  c.tiles2 = add_items(items, desc, plans, [](const Plan& q) { return (q.ldq / 16) * (q.ldq / 16); });
+  c.rowtiles2 = add_items(items, desc, plans, [](const Plan& q) { return q.crows / 16; });
+  c.trmm2 = add_items(items, desc, plans, [](const Plan& q) { return q.q; });
+  c.fits = add_items(items, desc, plans, [](const Plan&) { return 1; });
+  c.fits1 = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? 1 : 0; });
+  c.jl = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? q.k : 0; });
+  c.chunks = add_items(items, desc, plans, [&](const Plan& q) {
+    return sampled(q) ? static_cast<int>((sample_work_doubles(q.m) - 1) / 2) : 0;
+  });
+  c.draws = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? q.c : 0; });
+  c.cols = add_items(items, desc, plans, [](const Plan& q) { return q.p + 1; });
+  c.rblocks = add_items(items, desc, plans, [](const Plan& q) { return resid_direct_blocks(q.m); });
+  return c;
+}
+
+void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, double tol,
+               FitDesc* d) {
   *d = FitDesc{};
   d->y = y;
   d->n = pl.n;
   d->m = pl.m;
+  d->tol = tol;
   d->p = pl.p;
   d->q = pl.q;
   d->ldq = pl.ldq;
@@ -182,29 +217,134 @@ void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, 
   d->cd = b.cd;
 }
 
-template <typename F>
-List add_items(std::vector<Item>& all, const Cls& c, const std::vector<Plan>& plans,
-               const std::vector<int>& order, F&& per_fit) {
-  List l;
-  l.off = static_cast<int>(all.size());
-  for (int j = c.first; j < c.first + c.count; ++j) {
-    const int cnt = per_fit(plans[order[j]]);
-    for (int i = 0; i < cnt; ++i) all.push_back({j, i});
-  }
-  l.n = static_cast<int>(all.size()) - l.off;
-  return l;
+hipError_t batch_init(const Item* fits, int nfits, FitDesc* D, int max_iter, int max_refine,
+                      int inner_max, double inner_tol, hipStream_t s) {
+  if (nfits < 1) return hipSuccess;
+  hipLaunchKernelGGL(init_b_kernel, dim3((nfits + 63) / 64), dim3(64), 0, s, fits, nfits, D,
+                     max_iter, max_refine, inner_max, inner_tol);
+  return hipGetLastError();
 }
 
-}  // namespace
+hipError_t batch_zero_ints(int* x, int n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((n + 63) / 64), dim3(64), 0, s, x, n);
+  return hipGetLastError();
+}
+
+hipError_t PassTimer::begin(hipStream_t s) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = pass_events(ctx, n, &a, &b);
+  return e == hipSuccess ? hipEventRecord(a, s) : e;
+}
+
+hipError_t PassTimer::end(hipStream_t s) {
+  hipEvent_t b = ctx->events[2 * n + 1];
+  ++n;
+  return hipEventRecord(b, s);
+}
+
+hipError_t PassTimer::total_ms(double* ms) const {
+  double t = 0.0;
+  for (size_t k = 0; k < n; ++k) {
+    float x = 0.f;
+    hipError_t e = hipEventElapsedTime(&x, ctx->events[2 * k], ctx->events[2 * k + 1]);
+    if (e != hipSuccess) return e;
+    t += x;
+  }
+  *ms = t;
+  return hipSuccess;
+}
+
+#define L_(lst) I + l.lst.off, l.lst.n
+
+tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, const Item* I,
+                       const ClassLists& l, FitDesc* D, const tls_options& o, hipStream_t s) {
+  const bool mixed = o.precision == TLS_PREC_MIXED;
+  const int cprec = mixed ? PREC_F32 : PREC_F64;
+  const uint64_t seed = o.seed;
+  // spectra of the series blocks (mixed: FP32 for the products, FP64 for the residuals)
+  TLS_CHECK(launch_spectra_b(cprec, k.lgn, L_(blocks), D, 0, ctx->tw, s));
+  if (mixed) TLS_CHECK(launch_spectra_b(PREC_F64, k.lgn, L_(blocks), D, 1, ctx->tw, s));
+  // sketch -> R
+  TLS_CHECK(launch_gather_b(1, L_(rows1), D, seed, s));
+  if (l.fits1.n > 0) {
+    TLS_CHECK(launch_qr_b(1, k.qt, L_(tiles1), nullptr, 0, nullptr, 0, L_(fits1), ldqmax, D, s));
+    TLS_CHECK(launch_triinv_b(1, k.pt, L_(fits1), pmax, D, s));
+    TLS_CHECK(launch_jl_b(L_(jl), D, o.jl_kind, pmax, seed, s));
+    TLS_CHECK(launch_small_rfft_b(cprec, k.lgn, 0, L_(jl), D, ctx->tw, s));
+    TLS_CHECK(launch_scores_b(cprec, k.lgn, L_(blocks1), D, ctx->tw, s));
+    TLS_CHECK(launch_sample_b(cprec, L_(chunks), L_(draws), L_(fits1), D, seed, s));
+    TLS_CHECK(launch_gather_b(2, L_(rows2), D, seed, s));
+  }
+  TLS_CHECK(launch_qr_b(2, k.qt, L_(tiles2), L_(rowtiles2), L_(trmm2), L_(fits), ldqmax, D, s));
+  TLS_CHECK(launch_triinv_b(2, k.pt, L_(fits), pmax, D, s));
+  if (l.fits.n > 0) {
+    hipLaunchKernelGGL(post_qr_b_kernel, dim3(l.fits.n), dim3(64), 0, s, I + l.fits.off, D,
+                       o.warm_start ? 1 : 0, mixed ? 1 : 0);
+    TLS_CHECK(hipGetLastError());
+  }
+  return TLS_OK;
+}
+
+tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
+                           const Item* blocks, int nblocks, const Item* cols, int ncols,
+                           const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
+                           PassTimer* tm, hipStream_t s) {
+  if (first) TLS_CHECK(launch_small_rfft_b(PREC_F64, lgn, 1, fits, nfits, D, ctx->tw, s));
+  if (tm) TLS_CHECK(tm->begin(s));
+  TLS_CHECK(launch_toep_b(PREC_F64, lgn, first ? BP_LSQR_FIRST : BP_LSQR, blocks, nblocks, D,
+                          ctx->consts, ctx->tw, s));
+  if (tm) TLS_CHECK(tm->end(s));
+  TLS_CHECK(launch_colsum_b(0, cols, ncols, D, s));
+  TLS_CHECK(launch_lsqr_step_b(PREC_F64, lgn, fits, nfits, pmax, mlds, D, counts, done_list,
+                               ctx->tw, s));
+  return TLS_OK;
+}
+
+tls_status residual_class(const Item* rblocks, int nrblocks, const Item* fits, int nfits, int pmax,
+                          FitDesc* D, hipStream_t s) {
+  TLS_CHECK(launch_resid_b(rblocks, nrblocks, D, pmax, s));
+  TLS_CHECK(launch_colsum_b(3, fits, nfits, D, s));
+  return TLS_OK;
+}
+
+hipError_t collect_b(const Item* fits, int nfits, const FitDesc* D, int mixed, double* coef,
+                     FitRec* rec, hipStream_t s) {
+  if (nfits < 1) return hipSuccess;
+  hipLaunchKernelGGL(collect_b_kernel, dim3(nfits), dim3(64), 0, s, fits, D, mixed, coef, rec);
+  return hipGetLastError();
+}
+
+tls_status record_status(const FitRec& r, const double* coef, int p) {
+  for (int k = 0; k < p; ++k)
+    if (!isfinite(coef[k])) return TLS_EINVAL;
+  if ((r.status[0] & 6) || (r.status[1] & 4) || r.istop == 4) return TLS_ERANK;
+  if (r.istop == 7) return TLS_ENOCONV;
+  return TLS_OK;
+}
+
+void record_result(const FitRec& r, const Plan& pl, double ms, tls_result* o) {
+  memset(o, 0, sizeof(*o));
+  o->resid_norm = sqrt(r.rr);
+  o->kappa_est = r.dmin > 0 ? r.dmax / r.dmin : INFINITY;
+  o->lsqr_rnorm = r.rnorm;
+  o->lsqr_arnorm = r.arnorm;
+  o->iters = r.iters;
+  o->istop = r.istop;
+  o->refine_steps = r.refine;
+  o->sketch_rows = pl.c;
+  o->block_len = pl.B;
+  o->n_blocks = pl.nblocks;
+  o->t_total_ms = ms;
+}
+
+// ---- batched driver -------------------------------------------------------------
 
 tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
                      const double* const* dev_series, const int64_t* n, const int32_t* p,
                      double tol, const tls_options& o, hipStream_t s, double* coef_packed,
                      const int64_t* coef_offset, tls_result* res, tls_status* fit_status) {
   const auto t0 = std::chrono::steady_clock::now();
-  const int prec = o.precision;
-  const bool mixed = prec == TLS_PREC_MIXED;
-  const bool leverage = o.sketch == TLS_SKETCH_LEVERAGE;
+  const bool mixed = o.precision == TLS_PREC_MIXED;
   const bool copy_y = host_series != nullptr;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
   const int max_refine = o.max_refine > 0 ? o.max_refine : 8;
@@ -213,8 +353,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
   std::vector<Plan> plans(count);
   std::vector<tls_status> st(count, TLS_OK);
   std::vector<int> singles;  // fits outside the batched kernels' limits
-  using Key = std::tuple<int, int, int, int>;
-  std::map<Key, std::vector<int>> groups;
+  std::map<ClassKey, std::vector<int>> groups;
   for (int i = 0; i < count; ++i) {
     if (copy_y ? !host_series[i] : !dev_series[i]) {
       st[i] = TLS_EINVAL;
@@ -229,65 +368,38 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         }
     if (st[i] == TLS_OK) st[i] = make_plan(n[i], p[i], o, &plans[i]);
     if (st[i] != TLS_OK) continue;
-    const Plan& pl = plans[i];
-    if (pl.ldq > 1024) {
+    if (plans[i].ldq > BATCH_LDQ_MAX) {
       singles.push_back(i);
       continue;
     }
-    const int qt = (pl.q + 15) / 16 <= 8 ? (pl.q + 15) / 16 : 0;
-    const int pt = pl.p <= 128 ? (pl.p + 15) / 16 : 0;
-    groups[Key(pl.lgn, qt, pt, lsqr_step_lds(pl.lgn, pl.p) ? 1 : 0)].push_back(i);
+    groups[class_key(plans[i])].push_back(i);
   }
 
-  // Order the batched fits by class; build the classes and their item lists.
+  // Order the batched fits by class (descriptor j = position in `order`) and
+  // build each class's item lists.
+  struct Cls {
+    ClassKey key;
+    int first, count, pmax, ldqmax;
+    ClassLists l;
+  };
   std::vector<int> order;
   std::vector<Cls> classes;
+  std::vector<Item> items;
   for (auto& kv : groups) {
-    Cls c;
-    c.lgn = std::get<0>(kv.first);
-    c.qt = std::get<1>(kv.first);
-    c.pt = std::get<2>(kv.first);
-    c.mlds = std::get<3>(kv.first) != 0;
-    c.first = static_cast<int>(order.size());
-    c.count = static_cast<int>(kv.second.size());
+    Cls c{kv.first, static_cast<int>(order.size()), static_cast<int>(kv.second.size()), 0, 0, {}};
+    std::vector<int> desc;
+    std::vector<const Plan*> pls;
     for (int i : kv.second) {
+      desc.push_back(static_cast<int>(order.size()));
+      pls.push_back(&plans[i]);
       order.push_back(i);
       c.pmax = std::max(c.pmax, plans[i].p);
       c.ldqmax = std::max(c.ldqmax, plans[i].ldq);
     }
+    c.l = build_lists(items, desc, pls, o.sketch == TLS_SKETCH_LEVERAGE);
     classes.push_back(c);
   }
   const int nb = static_cast<int>(order.size());
-  std::vector<Item> items;
-  for (Cls& c : classes) {
-    const bool lev = leverage;
-    c.blocks = add_items(items, c, plans, order, [](const Plan& q) { return q.nblocks; });
-    c.blocks1 = add_items(items, c, plans, order,
-                          [lev](const Plan& q) { return lev && !q.all_rows ? q.nblocks : 0; });
-    c.rows1 = add_items(items, c, plans, order, [](const Plan& q) { return q.crows; });
-    c.rows2 = add_items(items, c, plans, order,
-                        [lev](const Plan& q) { return lev && !q.all_rows ? q.crows : 0; });
-    c.tiles1 = add_items(items, c, plans, order, [lev](const Plan& q) {
-      return lev && !q.all_rows ? (q.ldq / 16) * (q.ldq / 16) : 0;
-    });
-    c.tiles2 = add_items(items, c, plans, order,
-                         [](const Plan& q) { return (q.ldq / 16) * (q.ldq / 16); });
-    c.rowtiles2 = add_items(items, c, plans, order, [](const Plan& q) { return q.crows / 16; });
-    c.trmm2 = add_items(items, c, plans, order, [](const Plan& q) { return q.q; });
-    c.fits = add_items(items, c, plans, order, [](const Plan&) { return 1; });
-    c.fits1 = add_items(items, c, plans, order,
-                        [lev](const Plan& q) { return lev && !q.all_rows ? 1 : 0; });
-    c.jl = add_items(items, c, plans, order,
-                     [lev](const Plan& q) { return lev && !q.all_rows ? q.k : 0; });
-    c.chunks = add_items(items, c, plans, order, [lev](const Plan& q) {
-      return lev && !q.all_rows ? static_cast<int>((sample_work_doubles(q.m) - 1) / 2) : 0;
-    });
-    c.draws = add_items(items, c, plans, order,
-                        [lev](const Plan& q) { return lev && !q.all_rows ? q.c : 0; });
-    c.cols = add_items(items, c, plans, order, [](const Plan& q) { return q.p + 1; });
-    c.rblocks = add_items(items, c, plans, order,
-                          [](const Plan& q) { return resid_direct_blocks(q.m); });
-  }
   // collect list: every batched fit, idx = offset of its packed coefficients
   const int collect_off = static_cast<int>(items.size());
   int64_t coef_total = 0;
@@ -309,7 +421,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     FitBufs tmp{};
     fit_off[j] = reserve(carve(plans[order[j]], copy_y, &tmp, nullptr));
   }
-  const size_t ncounts = 2 * std::max<size_t>(classes.size(), 1);
+  const size_t ncounts = 4 * std::max<size_t>(classes.size(), 1);
   const size_t off_D = reserve(sizeof(FitDesc) * std::max(nb, 1));
   const size_t off_items = reserve(sizeof(Item) * std::max<size_t>(items.size(), 1));
   const size_t off_counts = reserve(sizeof(int) * ncounts);
@@ -328,14 +440,14 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       TLS_CHECK(hipMemcpyAsync(bufs[j].y, host_series[i], plans[i].n * sizeof(double),
                                hipMemcpyHostToDevice, s));
     fill_desc(plans[i], bufs[j], y, static_cast<uint32_t>(o.request_id + static_cast<uint64_t>(i)),
-              &desc[j]);
+              tol, &desc[j]);
   }
   FitDesc* D = reinterpret_cast<FitDesc*>(base + off_D);
   const Item* I = reinterpret_cast<const Item*>(base + off_items);
   int* counts = reinterpret_cast<int*>(base + off_counts);
   double* dcoef = reinterpret_cast<double*>(base + off_coef);
   FitRec* drec = reinterpret_cast<FitRec*>(base + off_rec);
-  // pinned: two counters, the fit records, the packed coefficients
+  // pinned: counters, the fit records, the packed coefficients
   const size_t host_bytes = 256 + sizeof(FitRec) * std::max(nb, 1) +
                             sizeof(double) * std::max<int64_t>(coef_total, 1);
   TLS_CHECK(ensure_pinned(ctx, host_bytes));
@@ -347,127 +459,78 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     TLS_CHECK(hipMemcpyAsync(D, desc.data(), sizeof(FitDesc) * nb, hipMemcpyHostToDevice, s));
     TLS_CHECK(hipMemcpyAsync(base + off_items, items.data(), sizeof(Item) * items.size(),
                              hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(init_b_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, D, nb, tol, max_iter,
-                       max_refine, inner_max, 1e-5);
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, counts, static_cast<int>(ncounts));
-    TLS_CHECK(hipGetLastError());
+    TLS_CHECK(batch_init(I + collect_off, nb, D, max_iter, max_refine, inner_max, 1e-5, s));
+    TLS_CHECK(batch_zero_ints(counts, static_cast<int>(ncounts), s));
   }
-  const uint64_t seed = o.seed;
-  const int cprec = mixed ? PREC_F32 : PREC_F64;
   // profile = 1: event pairs around every launch of the dominant pass (FP64:
   // the fused LSQR pass; mixed: the FP32 normal-equation pass)
-  size_t npass = 0;
-  auto timed = [&](auto&& launch) -> hipError_t {
-    hipEvent_t ea = nullptr, eb = nullptr;
-    if (o.profile) {
-      hipError_t e = pass_events(ctx, npass, &ea, &eb);
-      if (e == hipSuccess) e = hipEventRecord(ea, s);
-      if (e != hipSuccess) return e;
-    }
-    hipError_t e = launch();
-    if (e == hipSuccess && o.profile) {
-      e = hipEventRecord(eb, s);
-      ++npass;
-    }
-    return e;
-  };
-#define L_(lst) I + c.lst.off, c.lst.n
+  PassTimer timer{ctx, 0};
+  PassTimer* tm = o.profile ? &timer : nullptr;
   for (const Cls& c : classes) {
-    int* cnt = counts + 2 * (&c - classes.data());
-    // spectra of the series blocks (mixed: FP32 for the products, FP64 for the residuals)
-    TLS_CHECK(launch_spectra_b(cprec, c.lgn, L_(blocks), D, 0, ctx->tw, s));
-    if (mixed) TLS_CHECK(launch_spectra_b(PREC_F64, c.lgn, L_(blocks), D, 1, ctx->tw, s));
-    // sketch -> R
-    TLS_CHECK(launch_gather_b(1, L_(rows1), D, seed, s));
-    if (c.fits1.n > 0) {
-      TLS_CHECK(launch_qr_b(1, c.qt, L_(tiles1), nullptr, 0, nullptr, 0, L_(fits1), c.ldqmax, D, s));
-      TLS_CHECK(launch_triinv_b(1, c.pt, L_(fits1), c.pmax, D, s));
-      TLS_CHECK(launch_jl_b(L_(jl), D, o.jl_kind, c.pmax, seed, s));
-      TLS_CHECK(launch_small_rfft_b(cprec, c.lgn, 0, L_(jl), D, ctx->tw, s));
-      TLS_CHECK(launch_scores_b(cprec, c.lgn, L_(blocks1), D, ctx->tw, s));
-      TLS_CHECK(launch_sample_b(cprec, L_(chunks), L_(draws), L_(fits1), D, seed, s));
-      TLS_CHECK(launch_gather_b(2, L_(rows2), D, seed, s));
-    }
-    TLS_CHECK(launch_qr_b(2, c.qt, L_(tiles2), L_(rowtiles2), L_(trmm2), L_(fits), c.ldqmax, D, s));
-    TLS_CHECK(launch_triinv_b(2, c.pt, L_(fits), c.pmax, D, s));
-    hipLaunchKernelGGL(post_qr_b_kernel, dim3(c.count), dim3(64), 0, s, D + c.first,
-                       o.warm_start ? 1 : 0, mixed ? 1 : 0);
-    TLS_CHECK(hipGetLastError());
+    const ClassLists& l = c.l;
+    int* cnt = counts + 4 * (&c - classes.data());
+    const tls_status e0 = setup_class(ctx, c.key, c.pmax, c.ldqmax, I, l, D, o, s);
+    if (e0 != TLS_OK) return e0;
 
-    // FP64 LSQR over the class from phi0 (fits already done skip every step);
-    // counts[0] holds the number of finished fits.
-    auto lsqr64 = [&](bool time_it) -> tls_status {
-      auto pass = [&](int variant) -> hipError_t {
-        auto go = [&] {
-          return launch_toep_b(PREC_F64, c.lgn, variant, L_(blocks), D, ctx->consts, ctx->tw, s);
-        };
-        return time_it ? timed(go) : go();
-      };
-      TLS_CHECK(launch_small_rfft_b(PREC_F64, c.lgn, 1, L_(fits), D, ctx->tw, s));
-      TLS_CHECK(pass(BP_LSQR_FIRST));
-      TLS_CHECK(launch_colsum_b(0, L_(cols), D, s));
-      TLS_CHECK(launch_lsqr_step_b(PREC_F64, c.lgn, c.count, c.pmax, c.mlds, D + c.first, cnt,
-                                   ctx->tw, s));
-      int launched = 0;
-      for (;;) {
+    // FP64 LSQR over the class from phi0 (fits already done skip every
+    // step); cnt[0] holds the number of finished fits.
+    auto lsqr64 = [&](PassTimer* t) -> tls_status {
+      for (int launched = 0;; launched += B_CHUNK_ITERS) {
         for (int it = 0; it < B_CHUNK_ITERS; ++it) {
-          TLS_CHECK(pass(BP_LSQR));
-          TLS_CHECK(launch_colsum_b(0, L_(cols), D, s));
-          TLS_CHECK(launch_lsqr_step_b(PREC_F64, c.lgn, c.count, c.pmax, c.mlds, D + c.first, cnt,
-                                       ctx->tw, s));
+          const tls_status e = lsqr_step_class(ctx, c.key.lgn, c.pmax, c.key.mlds != 0,
+                                               launched == 0 && it == 0, L_(blocks), L_(cols),
+                                               L_(fits), D, cnt, nullptr, t, s);
+          if (e != TLS_OK) return e;
         }
-        launched += B_CHUNK_ITERS;
-        TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         TLS_CHECK(hipStreamSynchronize(s));
-        if (hcounts[0] >= c.count || launched > max_iter + B_CHUNK_ITERS) break;
+        if (hcounts[0] >= c.count || launched > max_iter) break;
       }
       return TLS_OK;
     };
     if (!mixed) {
-      const tls_status e = lsqr64(o.profile != 0);
+      const tls_status e = lsqr64(tm);
       if (e != TLS_OK) return e;
     } else {
       for (int outer = 0; outer <= max_refine; ++outer) {
-        hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, cnt, 2);
-        TLS_CHECK(launch_small_rfft_b(PREC_F64, c.lgn, 2, L_(fits), D, ctx->tw, s));
-        TLS_CHECK(launch_toep_b(PREC_F64, c.lgn, BP_OUTER64, L_(blocks), D, ctx->consts, ctx->tw, s));
+        TLS_CHECK(batch_zero_ints(cnt, 2, s));
+        TLS_CHECK(launch_small_rfft_b(PREC_F64, c.key.lgn, 2, L_(fits), D, ctx->tw, s));
+        TLS_CHECK(launch_toep_b(PREC_F64, c.key.lgn, BP_OUTER64, L_(blocks), D, ctx->consts,
+                                ctx->tw, s));
         TLS_CHECK(launch_colsum_b(1, L_(cols), D, s));
-        TLS_CHECK(launch_refine_outer_b(c.lgn, c.count, c.pmax, D + c.first, cnt, ctx->tw, s));
+        TLS_CHECK(launch_refine_outer_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s));
         for (int it = 0; it < inner_max; it += B_INNER_CHUNK) {
           for (int k = it; k < std::min(inner_max, it + B_INNER_CHUNK); ++k) {
-            TLS_CHECK(timed([&] {
-              return launch_toep_b(PREC_F32, c.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
-                                   ctx->tw, s);
-            }));
+            if (tm) TLS_CHECK(tm->begin(s));
+            TLS_CHECK(launch_toep_b(PREC_F32, c.key.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
+                                    ctx->tw, s));
+            if (tm) TLS_CHECK(tm->end(s));
             TLS_CHECK(launch_colsum_b(2, L_(cols), D, s));
-            TLS_CHECK(launch_refine_cg_b(c.lgn, c.count, c.pmax, D + c.first, cnt, ctx->tw, s));
+            TLS_CHECK(launch_refine_cg_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s));
           }
-          TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+          TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
           TLS_CHECK(hipStreamSynchronize(s));
           if (hcounts[1] >= c.count) break;
         }
         if (hcounts[0] >= c.count) break;
       }
       // FP64 finish for the fits whose refinement stopped short
-      hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, cnt, 2);
-      hipLaunchKernelGGL(fallback_prep_b_kernel, dim3(c.count), dim3(64), 0, s, D + c.first, cnt);
+      TLS_CHECK(batch_zero_ints(cnt, 4, s));
+      hipLaunchKernelGGL(fallback_prep_b_kernel, dim3(l.fits.n), dim3(64), 0, s, I + l.fits.off,
+                         D, cnt);
       TLS_CHECK(hipGetLastError());
-      TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
       TLS_CHECK(hipStreamSynchronize(s));
       if (hcounts[0] < c.count) {
-        const tls_status e = lsqr64(false);
+        const tls_status e = lsqr64(nullptr);
         if (e != TLS_OK) return e;
       }
     }
-    // FP64 residual of the returned coefficients, row by row
-    TLS_CHECK(launch_resid_b(L_(rblocks), D, c.pmax, s));
-    TLS_CHECK(launch_colsum_b(3, L_(fits), D, s));
+    const tls_status e1 = residual_class(L_(rblocks), L_(fits), c.pmax, D, s);
+    if (e1 != TLS_OK) return e1;
   }
-#undef L_
   if (nb > 0) {
-    hipLaunchKernelGGL(collect_b_kernel, dim3(nb), dim3(64), 0, s, I + collect_off, D, mixed ? 1 : 0,
-                       dcoef, drec);
-    TLS_CHECK(hipGetLastError());
+    TLS_CHECK(collect_b(I + collect_off, nb, D, mixed ? 1 : 0, dcoef, drec, s));
     TLS_CHECK(hipMemcpyAsync(hrec, drec, sizeof(FitRec) * nb, hipMemcpyDeviceToHost, s));
     TLS_CHECK(hipMemcpyAsync(hcoef, dcoef, sizeof(double) * coef_total, hipMemcpyDeviceToHost, s));
     TLS_CHECK(hipStreamSynchronize(s));
@@ -475,60 +538,29 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
   const auto t1 = std::chrono::steady_clock::now();
   const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   double pass_ms = 0.0;
-  for (size_t k = 0; k < npass; ++k) {
-    float t = 0.f;
-    TLS_CHECK(hipEventElapsedTime(&t, ctx->events[2 * k], ctx->events[2 * k + 1]));
-    pass_ms += t;
-  }
+  TLS_CHECK(timer.total_ms(&pass_ms));
 
   int64_t off = 0;
   for (int j = 0; j < nb; ++j) {
     const int i = order[j];
     const Plan& pl = plans[i];
-    const FitRec& r = hrec[j];
     double* coef = coef_packed + coef_offset[i];
     memcpy(coef, hcoef + off, pl.p * sizeof(double));
     off += pl.p;
     if (res) {
-      tls_result& o_ = res[i];
-      memset(&o_, 0, sizeof(o_));
-      o_.resid_norm = sqrt(r.rr);
-      o_.kappa_est = r.dmin > 0 ? r.dmax / r.dmin : INFINITY;
-      o_.lsqr_rnorm = r.rnorm;
-      o_.lsqr_arnorm = r.arnorm;
-      o_.iters = r.iters;
-      o_.istop = r.istop;
-      o_.refine_steps = r.refine;
-      o_.sketch_rows = pl.c;
-      o_.block_len = pl.B;
-      o_.n_blocks = pl.nblocks;
-      o_.t_total_ms = ms;
-      o_.pass_ms = pass_ms;  // the whole batch's launches of the dominant pass
-      o_.pass_count = static_cast<int>(npass);
+      record_result(hrec[j], pl, ms, &res[i]);
+      res[i].pass_ms = pass_ms;  // the whole batch's launches of the dominant pass
+      res[i].pass_count = static_cast<int>(timer.n);
     }
-    tls_status fs = TLS_OK;
-    for (int k = 0; k < pl.p; ++k)
-      if (!isfinite(coef[k])) fs = TLS_EINVAL;
-    if (fs == TLS_OK) {
-      if ((r.status[0] & 6) || (r.status[1] & 4) || r.istop == 4)
-        fs = TLS_ERANK;
-      else if (r.istop == 7)
-        fs = TLS_ENOCONV;
-    }
-    st[i] = fs;
+    st[i] = record_status(hrec[j], coef, pl.p);
   }
   // Fits beyond the batched kernels' limits run one at a time.
   for (int i : singles) {
     tls_options oi = o;
     oi.request_id = o.request_id + static_cast<uint64_t>(i);
     tls_result r{};
-    if (copy_y) {
-      st[i] = run_fit(ctx, plans[i], oi, nullptr, host_series[i], tol, s,
-                      coef_packed + coef_offset[i], &r);
-    } else {
-      st[i] = run_fit(ctx, plans[i], oi, dev_series[i], nullptr, tol, s,
-                      coef_packed + coef_offset[i], &r);
-    }
+    st[i] = run_fit(ctx, plans[i], oi, copy_y ? nullptr : dev_series[i],
+                    copy_y ? host_series[i] : nullptr, tol, s, coef_packed + coef_offset[i], &r);
     if (res) res[i] = r;
   }
   tls_status first = TLS_OK;

@@ -334,6 +334,84 @@ struct HostOut {
 tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const double* d_y_in,
                    const double* host_y, double tol, hipStream_t s, double* coef, tls_result* res);
 
+// ---- batched execution core (batch.hip), shared by the batched driver and
+// the server -------------------------------------------------------------------
+
+// A range of a device work-item table.
+struct List {
+  int off = 0, n = 0;
+};
+
+// The compile-time choices the single-fit path makes for a fit: FFT
+// half-length, Cholesky register tiles (q = p + 1; 0 = global kernels),
+// inverse register tiles (p; 0 = global kernel), LDS staging of M in the
+// LSQR step.  Fits with equal keys share every launch of a batched run.
+struct ClassKey {
+  int lgn, qt, pt, mlds;
+  bool operator<(const ClassKey& o) const {
+    if (lgn != o.lgn) return lgn < o.lgn;
+    if (qt != o.qt) return qt < o.qt;
+    if (pt != o.pt) return pt < o.pt;
+    return mlds < o.mlds;
+  }
+};
+ClassKey class_key(const Plan& pl);
+// The batched sketch kernels stage 16-row panels of width ldq in LDS.
+constexpr int BATCH_LDQ_MAX = 1024;
+
+// Work-item lists of one class (offsets into one device item table).
+struct ClassLists {
+  List blocks, blocks1, rows1, rows2, tiles1, tiles2, rowtiles2, trmm2, fits, fits1, jl, chunks,
+      draws, cols, rblocks;
+};
+// Appends the lists of the fits with descriptor indices desc[i] and plans
+// plans[i] to `items`.
+ClassLists build_lists(std::vector<Item>& items, const std::vector<int>& desc,
+                       const std::vector<const Plan*>& plans, bool leverage);
+
+// Per-fit result record written on the device by collect_b.
+struct FitRec {
+  double rr, dmax, dmin, rnorm, arnorm;
+  int status[4];
+  int iters, istop, refine, pad;
+};
+
+void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, double tol,
+               FitDesc* d);
+// LSQR and refinement state, status words (one item per fit).
+hipError_t batch_init(const Item* fits, int nfits, FitDesc* D, int max_iter, int max_refine,
+                      int inner_max, double inner_tol, hipStream_t s);
+hipError_t batch_zero_ints(int* x, int n, hipStream_t s);
+
+// Event pairs around launches of the dominant pass (profile = 1).
+struct PassTimer {
+  tls_ctx* ctx = nullptr;
+  size_t n = 0;
+  hipError_t begin(hipStream_t s);
+  hipError_t end(hipStream_t s);
+  hipError_t total_ms(double* ms) const;
+};
+
+// Spectra, two-stage sketch, final QR, inverse and warm start for the fits
+// of one class.
+tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, const Item* I,
+                       const ClassLists& l, FitDesc* D, const tls_options& o, hipStream_t s);
+// One FP64 LSQR step for the listed fits: the fused pass (first: from b and
+// phi0, after the spectrum of phi0), the column sums and the p-side step.
+tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
+                           const Item* blocks, int nblocks, const Item* cols, int ncols,
+                           const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
+                           PassTimer* tm, hipStream_t s);
+// FP64 residual of phi (row-wise) for the listed fits.
+tls_status residual_class(const Item* rblocks, int nrblocks, const Item* fits, int nfits, int pmax,
+                          FitDesc* D, hipStream_t s);
+// Coefficients (packed at item.idx) and result records (rec[k] for the k-th item).
+hipError_t collect_b(const Item* fits, int nfits, const FitDesc* D, int mixed, double* coef,
+                     FitRec* rec, hipStream_t s);
+// Per-fit status from a record and the returned coefficients.
+tls_status record_status(const FitRec& r, const double* coef, int p);
+void record_result(const FitRec& r, const Plan& pl, double ms, tls_result* out);
+
 // Batched driver: fits of `count` series (host series when host_series is
 // non-null, else device series) grouped into launch classes; per-fit
 // coefficients, results and statuses.

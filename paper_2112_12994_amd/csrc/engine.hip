@@ -265,6 +265,7 @@ const char* tls_status_string(tls_status s) {
     case TLS_ENOMEM: return "device allocation failed";
     case TLS_EDEVICE: return "HIP runtime error";
     case TLS_EUNSUPPORTED: return "size outside the supported range";
+    case TLS_EAGAIN: return "request not finished yet";
     default: return "unknown status";
   }
 }

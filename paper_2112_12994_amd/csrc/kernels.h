@@ -110,6 +110,7 @@ hipError_t launch_refine_cg(int lgn, int p, RefineState* st, const double* g, co
 struct FitDesc {
   const double* y;
   int64_t n, m;
+  double tol;
   int p, q, ldq, c, crows, k, L, nblocks, nchunks, all_rows;
   uint32_t fit;
   void* Yhat;
@@ -173,17 +174,20 @@ hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const I
 // stage 1: M0, Mt0 (status[3]); stage 2: M, Mt, phi0 (status[1]), |R_ii| range.
 hipError_t launch_triinv_b(int stage, int pt, const Item* fits, int nfits, int pmax,
                            const FitDesc* D, hipStream_t st);
-// One workgroup per fit of D[0 .. nfits).  counts[0] += 1 for each fit that
-// finishes (LSQR) or is finished (refinement outer step); counts[1] += 1 for
-// each fit whose inner CG solve is finished.  mlds must equal
-// lsqr_step_lds(lgn, p) for every fit (the single-fit kernel's choice).
+// One workgroup per item of `fits` (item.fit indexes D).  counts[0] += 1 for
+// each fit that finishes (LSQR) or is finished (refinement outer step);
+// counts[1] += 1 for each fit whose inner CG solve is finished; the LSQR step
+// appends each fit it finishes to done_list (when non-null; length in
+// counts[2]).  mlds must equal lsqr_step_lds(lgn, p) for every fit (the
+// single-fit kernel's choice).
 bool lsqr_step_lds(int lgn, int p);
-hipError_t launch_lsqr_step_b(int prec, int lgn, int nfits, int pmax, bool mlds, const FitDesc* D,
+hipError_t launch_lsqr_step_b(int prec, int lgn, const Item* fits, int nfits, int pmax, bool mlds,
+                              const FitDesc* D, int* counts, int* done_list, const Twiddles& tw,
+                              hipStream_t st);
+hipError_t launch_refine_outer_b(int lgn, const Item* fits, int nfits, int pmax, const FitDesc* D,
+                                 int* counts, const Twiddles& tw, hipStream_t st);
+hipError_t launch_refine_cg_b(int lgn, const Item* fits, int nfits, int pmax, const FitDesc* D,
                               int* counts, const Twiddles& tw, hipStream_t st);
-hipError_t launch_refine_outer_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
-                                 const Twiddles& tw, hipStream_t st);
-hipError_t launch_refine_cg_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
-                              const Twiddles& tw, hipStream_t st);
 
 hipError_t launch_vec_axpy_small(const double* M, const double* x, const double* y0, int p,
                                  double* out, hipStream_t st);

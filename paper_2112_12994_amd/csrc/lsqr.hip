@@ -628,27 +628,36 @@ hipError_t launch_vec_axpy_small(const double* Mt, const double* x, const double
   return hipGetLastError();
 }
 
-// ---- batched launches: one workgroup per fit (blockIdx.x indexes D) ----------
+// ---- batched launches: one workgroup per fit (items[blockIdx.x].fit) ---------
 namespace {
 
 // counts[0]: fits whose LSQR (or refinement) has finished; counts[1]: fits
-// whose inner CG solve of the current refinement step has finished.
+// whose inner CG solve of the current refinement step has finished.  When
+// done_list is given, every fit that finishes in this launch appends its
+// descriptor index there (length in counts[2]).
 template <int LGN, int NT, typename TS, bool MLDS>
-__global__ __launch_bounds__(NT) void lsqr_step_b_kernel(const FitDesc* __restrict__ D,
+__global__ __launch_bounds__(NT) void lsqr_step_b_kernel(const Item* __restrict__ fits,
+                                                         const FitDesc* __restrict__ D,
                                                          int* __restrict__ counts,
+                                                         int* __restrict__ done_list,
                                                          const cx<double>* __restrict__ tab) {
-  const FitDesc& d = D[blockIdx.x];
+  const int f = fits[blockIdx.x].fit;
+  const FitDesc& d = D[f];
   if (d.st->done) return;
   lsqr_step_body<LGN, NT, TS, MLDS>(d.p, d.st, d.g, d.M, d.Mt, d.v, d.w, d.z, d.phi0, d.phi,
                                     static_cast<cx<TS>*>(d.Vhat), tab);
-  if (threadIdx.x == 0 && d.st->done) atomicAdd(counts, 1);
+  if (threadIdx.x == 0 && d.st->done) {
+    atomicAdd(counts, 1);
+    if (done_list) done_list[atomicAdd(counts + 2, 1)] = f;
+  }
 }
 
 template <int LGN, int NT>
-__global__ __launch_bounds__(NT) void refine_outer_b_kernel(const FitDesc* __restrict__ D,
+__global__ __launch_bounds__(NT) void refine_outer_b_kernel(const Item* __restrict__ fits,
+                                                            const FitDesc* __restrict__ D,
                                                             int* __restrict__ counts,
                                                             const cx<double>* __restrict__ tab) {
-  const FitDesc& d = D[blockIdx.x];
+  const FitDesc& d = D[fits[blockIdx.x].fit];
   if (!d.rst->done)
     refine_outer_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.phi, d.phib, d.cw, d.cres, d.cd,
                                static_cast<cx<float>*>(d.Vhat32), tab);
@@ -659,10 +668,11 @@ __global__ __launch_bounds__(NT) void refine_outer_b_kernel(const FitDesc* __res
 }
 
 template <int LGN, int NT>
-__global__ __launch_bounds__(NT) void refine_cg_b_kernel(const FitDesc* __restrict__ D,
+__global__ __launch_bounds__(NT) void refine_cg_b_kernel(const Item* __restrict__ fits,
+                                                         const FitDesc* __restrict__ D,
                                                          int* __restrict__ counts,
                                                          const cx<double>* __restrict__ tab) {
-  const FitDesc& d = D[blockIdx.x];
+  const FitDesc& d = D[fits[blockIdx.x].fit];
   if (d.rst->inner_done) return;
   refine_cg_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.cw, d.cres, d.cd, d.phi,
                           static_cast<cx<float>*>(d.Vhat32), tab);
@@ -670,18 +680,18 @@ __global__ __launch_bounds__(NT) void refine_cg_b_kernel(const FitDesc* __restri
 }
 
 template <int LGN, typename TS>
-hipError_t step_b(int nfits, int pmax, bool mlds, const FitDesc* D, int* counts,
-                  const Twiddles& tw, hipStream_t s) {
+hipError_t step_b(const Item* fits, int nfits, int pmax, bool mlds, const FitDesc* D, int* counts,
+                  int* done_list, const Twiddles& tw, hipStream_t s) {
   constexpr int NT = 256;
   const size_t small = 2 * static_cast<size_t>(pmax) * sizeof(double);
   const size_t with_m = small + static_cast<size_t>(pmax) * (pmax | 1) * sizeof(double);
   const cx<double>* tab = static_cast<const cx<double>*>(tw.d64);
   if (mlds)
-    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, true>), dim3(nfits), dim3(NT), with_m, s, D,
-                       counts, tab);
+    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, true>), dim3(nfits), dim3(NT), with_m, s,
+                       fits, D, counts, done_list, tab);
   else
-    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, false>), dim3(nfits), dim3(NT), small, s, D,
-                       counts, tab);
+    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, false>), dim3(nfits), dim3(NT), small, s,
+                       fits, D, counts, done_list, tab);
   return hipGetLastError();
 }
 
@@ -691,45 +701,46 @@ size_t refine_shm(int pmax) {
 }
 
 template <int LGN>
-hipError_t outer_b(int nfits, int pmax, const FitDesc* D, int* counts, const Twiddles& tw,
-                   hipStream_t s) {
+hipError_t outer_b(const Item* fits, int nfits, int pmax, const FitDesc* D, int* counts,
+                   const Twiddles& tw, hipStream_t s) {
   hipLaunchKernelGGL((refine_outer_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax), s,
-                     D, counts, static_cast<const cx<double>*>(tw.d64));
+                     fits, D, counts, static_cast<const cx<double>*>(tw.d64));
   return hipGetLastError();
 }
 
 template <int LGN>
-hipError_t cg_b(int nfits, int pmax, const FitDesc* D, int* counts, const Twiddles& tw,
-                hipStream_t s) {
-  hipLaunchKernelGGL((refine_cg_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax), s, D,
-                     counts, static_cast<const cx<double>*>(tw.d64));
+hipError_t cg_b(const Item* fits, int nfits, int pmax, const FitDesc* D, int* counts,
+                const Twiddles& tw, hipStream_t s) {
+  hipLaunchKernelGGL((refine_cg_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax), s,
+                     fits, D, counts, static_cast<const cx<double>*>(tw.d64));
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_lsqr_step_b(int prec, int lgn, int nfits, int pmax, bool mlds, const FitDesc* D,
-                              int* counts, const Twiddles& tw, hipStream_t s) {
+hipError_t launch_lsqr_step_b(int prec, int lgn, const Item* fits, int nfits, int pmax, bool mlds,
+                              const FitDesc* D, int* counts, int* done_list, const Twiddles& tw,
+                              hipStream_t s) {
   if (nfits < 1) return hipSuccess;
-#define TLS_STEP_B(LG)                                                        \
-  (prec == PREC_F64 ? step_b<LG, double>(nfits, pmax, mlds, D, counts, tw, s) \
-                    : step_b<LG, float>(nfits, pmax, mlds, D, counts, tw, s))
+#define TLS_STEP_B(LG)                                                                         \
+  (prec == PREC_F64 ? step_b<LG, double>(fits, nfits, pmax, mlds, D, counts, done_list, tw, s) \
+                    : step_b<LG, float>(fits, nfits, pmax, mlds, D, counts, done_list, tw, s))
   TLS_LG_SWITCH(TLS_STEP_B)
 #undef TLS_STEP_B
 }
 
-hipError_t launch_refine_outer_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
-                                 const Twiddles& tw, hipStream_t s) {
+hipError_t launch_refine_outer_b(int lgn, const Item* fits, int nfits, int pmax, const FitDesc* D,
+                                 int* counts, const Twiddles& tw, hipStream_t s) {
   if (nfits < 1) return hipSuccess;
-#define TLS_OUTER_B(LG) outer_b<LG>(nfits, pmax, D, counts, tw, s)
+#define TLS_OUTER_B(LG) outer_b<LG>(fits, nfits, pmax, D, counts, tw, s)
   TLS_LG_SWITCH(TLS_OUTER_B)
 #undef TLS_OUTER_B
 }
 
-hipError_t launch_refine_cg_b(int lgn, int nfits, int pmax, const FitDesc* D, int* counts,
-                              const Twiddles& tw, hipStream_t s) {
+hipError_t launch_refine_cg_b(int lgn, const Item* fits, int nfits, int pmax, const FitDesc* D,
+                              int* counts, const Twiddles& tw, hipStream_t s) {
   if (nfits < 1) return hipSuccess;
-#define TLS_CG_B(LG) cg_b<LG>(nfits, pmax, D, counts, tw, s)
+#define TLS_CG_B(LG) cg_b<LG>(fits, nfits, pmax, D, counts, tw, s)
   TLS_LG_SWITCH(TLS_CG_B)
 #undef TLS_CG_B
 }
