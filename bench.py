@@ -45,6 +45,9 @@ WORKLOAD_TEXT = {
              "N(0,1) innovations, seed 0; sketch 8p rows, tol 1e-10",
     "batch": "2048 independent series, n=round(2^U(12,18)), p~U{4..64}, pole moduli U[0.3,0.95], "
              "t5 innovations, seed 0; one batched call per step; sketch 8p rows, tol 1e-10",
+    "serve": "Poisson arrivals at 5000 requests/s, each a series drawn with replacement from a pool "
+             "of resident series with n=round(2^U(10,20)), p~U{2..200}, pole moduli U[0.5,0.95], "
+             "N(0,1) innovations, seed 0; FP64, sketch 8p rows, tol 1e-10",
 }
 
 
@@ -347,6 +350,134 @@ def batch_bench(args, torch, synth, capi):
     print(json.dumps(line), flush=True)
 
 
+def serve_bench(args, torch, synth, capi):
+    """Open-loop served workload: one thread submits requests at their Poisson
+    arrival times (series resident in device memory, borrowed by the server),
+    another takes the results in order; value = completed requests per second
+    over the timed window, with latency percentiles."""
+    import threading
+
+    import oracle
+    duration = args.duration
+    t0 = time.perf_counter()
+    arrivals, which, pool = synth.workload_serve(seed=0, rate=args.rate, duration=duration + 2.0,
+                                                 pool=args.pool)
+    print(f"[bench] pool of {len(pool)} series ({sum(f.y.size for f in pool)} samples) generated in "
+          f"{time.perf_counter() - t0:.1f} s; {arrivals.size} arrivals", file=sys.stderr, flush=True)
+    dys = [torch.from_numpy(f.y).to("cuda:0") for f in pool]
+    torch.cuda.synchronize()
+    max_iter = args.max_iter or 200
+    ctx = capi.Context(0, gamma=8, max_iter=max_iter)
+    srv = capi.Server(ctx, args.serve_budget << 30, args.serve_slots)
+    # warm-up: a burst of requests, all taken before the timed window
+    warm = [srv.submit_device(dys[int(i)], pool[int(i)].p, 1e-10, request_id=10_000_000 + k)
+            for k, i in enumerate(which[:args.warmup * 50])]
+    for t in warm:
+        srv.wait(t)
+    print(f"[bench] warmup done ({len(warm)} requests)", file=sys.stderr, flush=True)
+
+    results = [None] * arrivals.size
+    tickets = [None] * arrivals.size
+    ready = [threading.Event() for _ in range(arrivals.size)]
+    sub_done = [0.0]
+
+    def submitter(start):
+        for k in range(arrivals.size):
+            due = start + arrivals[k]
+            while True:
+                left = due - time.perf_counter()
+                if left <= 0:
+                    break
+                if left > 5e-4:
+                    time.sleep(left - 3e-4)
+            i = int(which[k])
+            tickets[k] = srv.submit_device(dys[i], pool[i].p, 1e-10, request_id=k)
+            ready[k].set()
+        sub_done[0] = time.perf_counter()
+
+    def collector():
+        for k in range(arrivals.size):
+            ready[k].wait()
+            results[k] = srv.wait(tickets[k])
+
+    start = time.perf_counter() + 0.05
+    ts = threading.Thread(target=submitter, args=(start,))
+    tc = threading.Thread(target=collector)
+    ts.start()
+    tc.start()
+    last_report = start
+    while tc.is_alive():
+        tc.join(timeout=5.0)
+        now = time.perf_counter()
+        if now - last_report >= 5.0 and tc.is_alive():
+            st = srv.stats()
+            print(f"[bench] t={now - start:.0f}s completed={st['completed']} in_flight={st['in_flight']} "
+                  f"queued={st['queued']} ticks={st['ticks']}", file=sys.stderr, flush=True)
+            last_report = now
+    ts.join()
+    end = time.perf_counter()
+    stats = srv.stats()
+    srv.close()
+    lat = np.array([r["t_total_ms"] for r in results])
+    statuses = [r["status"] for r in results]
+    samples = int(sum(pool[int(i)].y.size for i in which))
+    elapsed = end - start
+    # agreement with the oracle on a sample of requests (series up to 2^17)
+    errs = []
+    for k in range(0, arrivals.size, max(1, arrivals.size // 40)):
+        f = pool[int(which[k])]
+        if f.y.size > (1 << 17):
+            continue
+        ref = oracle.fit_qr(f.y, f.p)
+        errs.append((ref["kappa"], oracle.rel_error(results[k]["coef"], ref["phi"])))
+    strata = {}
+    for lo, hi, name in [(0, 1e6, "kappa<1e6"), (1e6, 1e12, "1e6<=kappa<1e12"),
+                         (1e12, float("inf"), "kappa>=1e12")]:
+        sel = [e for kk, e in errs if lo <= kk < hi]
+        strata[name] = {"fits": len(sel), "within_1e-6": sum(e <= 1e-6 for e in sel),
+                        "within_1e-4": sum(e <= 1e-4 for e in sel),
+                        "max_rel_err": max(sel) if sel else None}
+    cpu = None
+    if not args.no_cpu:
+        cost = [(f.y.size - f.p) * (f.p + 1) ** 2 for f in (pool[int(i)] for i in which)]
+        tc0 = time.perf_counter()
+        done = 0
+        for i in which:
+            f = pool[int(i)]
+            oracle.fit_qr(f.y, f.p)
+            done += 1
+            if time.perf_counter() - tc0 > 15.0:
+                break
+        t = time.perf_counter() - tc0
+        total = t * sum(cost) / sum(cost[:done])
+        cpu = {"value": arrivals.size / total, "unit": "requests/s", "cores": os.cpu_count() or 1,
+               "kind": "oracle",
+               "sample": f"oracle.fit_qr on the first {done} of {arrivals.size} requests in {t:.1f} s, "
+                         f"scaled by the m (p+1)^2 cost of all requests"}
+    line = {
+        "metric": METRIC, "value": arrivals.size / elapsed, "unit": "requests/s", "n_gpus": 1,
+        "steps": int(arrivals.size), "warmup": len(warm), "ms_per_step": elapsed / arrivals.size * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["serve"], "offered_rate": args.rate,
+                   "duration_s": duration, "pool_series": len(pool), "requests": int(arrivals.size),
+                   "samples": samples, "hbm_budget_gib": args.serve_budget,
+                   "max_slots": args.serve_slots, "max_iter": max_iter,
+                   "fit_statuses": {capi.status_string(k): statuses.count(k) for k in set(statuses)}},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
+                       "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean()),
+                       "max": float(lat.max())},
+        "samples_per_s": samples / elapsed,
+        "server": {"ticks": stats["ticks"], "ticks_per_s": stats["ticks"] / elapsed,
+                   "submit_lag_s": sub_done[0] - (start + float(arrivals[-1]))},
+        "accuracy": {"oracle_sample": len(errs), "by_kappa": strata},
+    }
+    if cpu:
+        line["cpu_baseline"] = cpu
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -357,6 +488,13 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed"])
     ap.add_argument("--block-lg", type=int, default=0, help="log2 FFT block length (0 = automatic)")
     ap.add_argument("--n", type=int, default=0, help="override the series length")
+    ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=5000.0, help="serve: requests per second")
+    ap.add_argument("--pool", type=int, default=512, help="serve: resident series in the pool")
+    ap.add_argument("--serve-budget", type=int, default=64, help="serve: HBM budget in GiB")
+    ap.add_argument("--serve-slots", type=int, default=8192, help="serve: fits in flight at most")
+    ap.add_argument("--max-iter", type=int, default=0,
+                    help="LSQR iteration limit (0: the library default, 1000; serve default 200)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (calibrates the HBM "
                          "byte counters against a known size) and exit")
@@ -394,6 +532,9 @@ def main():
         sys.exit(1)
     if args.workload == "batch":
         batch_bench(args, torch, synth, capi)
+        return
+    if args.workload == "serve":
+        serve_bench(args, torch, synth, capi)
         return
     f = synth.WORKLOADS[args.workload](seed=0, **({"n": args.n} if args.n else {}))
     prec = 1 if args.precision == "mixed" else 0
