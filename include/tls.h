@@ -281,7 +281,8 @@ tls_status tls_op_gather(tls_ctx* ctx, const double* d_y, int64_t n, int32_t p, 
  * ldq % 16 == 0, q <= ldq; d_A is overwritten).  *status_out (host) gets the
  * breakdown bits: 1 = the shifted first sweep broke down, 2 = a later sweep
  * broke down, 4 = min|R_ii| <= q u max|R_ii|; 2 or 4 mean numerically rank
- * deficient.  Synchronises the stream. */
+ * deficient; 8 (informational) = the third refining sweep ran.  Synchronises
+ * the stream. */
 tls_status tls_op_qr(tls_ctx* ctx, double* d_A, int32_t crows, int32_t q, int32_t ldq,
                      double* d_R, int32_t* status_out, void* stream);
 

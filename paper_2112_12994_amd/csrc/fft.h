@@ -36,174 +36,219 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tab, int e, i
   return w;
 }
 
-// ---- decimation-in-time passes (levels of span h, 2h, 4h) -----------------
-template <typename T, bool INV, int N, int NT>
-__device__ __forceinline__ void dit_pass3(cx<T>* s, const cx<T>* __restrict__ tab, int lgh) {
-  const int h = 1 << lgh;
-  for (int q = threadIdx.x; q < N / 8; q += NT) {
-    const int r = q & (h - 1);
-    const int base = ((q >> lgh) << (lgh + 3)) + r;
-    cx<T> a[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = s[swz<T>(base + k * h)];
-    const cx<T> w1 = twiddle<T, INV>(tab, r, lgh + 1);
-#pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      const cx<T> b = cmul(a[k + 1], w1);
-      a[k + 1] = csub(a[k], b);
-      a[k] = cadd(a[k], b);
+// Forward twiddles of one radix-R stage for the offset r within its span h:
+// w1 = w_{2h}^r, w2 = w_{4h}^r (R >= 4), w3a = w_{8h}^r and
+// w3b = w_{8h}^{r+h} (R = 8).  At h = 1 (r = 0) they are constants.  The
+// inverse stages use the conjugates, so one set serves both directions.
+template <typename T, int R, int LGH>
+struct Tw {
+  cx<T> w1, w2, w3a, w3b;
+  __device__ __forceinline__ Tw(const cx<T>* __restrict__ tab, int r) {
+    if constexpr (R == 8 && LGH == 0) {
+      constexpr T c = T(0.70710678118654752440084436210484903928);
+      w1 = {T(1), T(0)};
+      w2 = {T(1), T(0)};
+      w3a = {T(1), T(0)};
+      w3b = {c, -c};
+    } else {
+      w1 = twiddle<T, false>(tab, r, LGH + 1);
+      if constexpr (R >= 4) w2 = twiddle<T, false>(tab, r, LGH + 2);
+      if constexpr (R == 8) {
+        w3a = twiddle<T, false>(tab, r, LGH + 3);
+        w3b = twiddle<T, false>(tab, r + (1 << LGH), LGH + 3);
+      }
     }
-    const cx<T> w2 = twiddle<T, INV>(tab, r, lgh + 2);
-    const cx<T> w2b = rot90<T, INV>(w2);
+  }
+};
+
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> cj(cx<T> w) {
+  return INV ? cx<T>{w.x, -w.y} : w;
+}
+
+// a * w, skipping the product when w is the constant 1 (exact either way).
+template <typename T, bool ONE>
+__device__ __forceinline__ cx<T> tmul(cx<T> a, cx<T> w) {
+  if constexpr (ONE) return a;
+  else return cmul(a, w);
+}
+
+// ---- butterflies on registers: points base + k*h, h = 2^LGH -----------------
+// Decimation in time: levels of span h, 2h, 4h (radix 8), h, 2h (radix 4), h.
+template <typename T, bool INV, int LGH>
+__device__ __forceinline__ void bfly_dit8(cx<T> (&a)[8], const Tw<T, 8, LGH>& tw) {
+  constexpr bool C = LGH == 0;
+  const cx<T> w1 = cj<T, INV>(tw.w1), w2 = cj<T, INV>(tw.w2);
 #pragma unroll
-    for (int k0 = 0; k0 < 8; k0 += 4) {
-      cx<T> b = cmul(a[k0 + 2], w2);
-      a[k0 + 2] = csub(a[k0], b);
-      a[k0] = cadd(a[k0], b);
-      b = cmul(a[k0 + 3], w2b);
-      a[k0 + 3] = csub(a[k0 + 1], b);
-      a[k0 + 1] = cadd(a[k0 + 1], b);
-    }
-    cx<T> w3[4];
-    w3[0] = twiddle<T, INV>(tab, r, lgh + 3);
-    w3[1] = twiddle<T, INV>(tab, r + h, lgh + 3);
-    w3[2] = rot90<T, INV>(w3[0]);
-    w3[3] = rot90<T, INV>(w3[1]);
+  for (int k = 0; k < 8; k += 2) {
+    const cx<T> b = tmul<T, C>(a[k + 1], w1);
+    a[k + 1] = csub(a[k], b);
+    a[k] = cadd(a[k], b);
+  }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const cx<T> b = cmul(a[k + 4], w3[k]);
-      a[k + 4] = csub(a[k], b);
-      a[k] = cadd(a[k], b);
-    }
+  for (int k0 = 0; k0 < 8; k0 += 4) {
+    cx<T> b = tmul<T, C>(a[k0 + 2], w2);
+    a[k0 + 2] = csub(a[k0], b);
+    a[k0] = cadd(a[k0], b);
+    b = C ? rot90<T, INV>(a[k0 + 3]) : cmul(a[k0 + 3], rot90<T, INV>(w2));
+    a[k0 + 3] = csub(a[k0 + 1], b);
+    a[k0 + 1] = cadd(a[k0 + 1], b);
+  }
+  const cx<T> w3a = cj<T, INV>(tw.w3a), w3b = cj<T, INV>(tw.w3b);
+  const cx<T> w3[4] = {w3a, w3b, rot90<T, INV>(w3a), rot90<T, INV>(w3b)};
 #pragma unroll
-    for (int k = 0; k < 8; ++k) s[swz<T>(base + k * h)] = a[k];
+  for (int k = 0; k < 4; ++k) {
+    const cx<T> b = (C && k == 0) ? a[k + 4] : (C && k == 2) ? rot90<T, INV>(a[k + 4])
+                                                             : cmul(a[k + 4], w3[k]);
+    a[k + 4] = csub(a[k], b);
+    a[k] = cadd(a[k], b);
   }
 }
 
-template <typename T, bool INV, int N, int NT>
-__device__ __forceinline__ void dit_pass2(cx<T>* s, const cx<T>* __restrict__ tab, int lgh) {
-  const int h = 1 << lgh;
-  for (int q = threadIdx.x; q < N / 4; q += NT) {
-    const int r = q & (h - 1);
-    const int base = ((q >> lgh) << (lgh + 2)) + r;
-    cx<T> a[4];
+template <typename T, bool INV, int LGH>
+__device__ __forceinline__ void bfly_dit4(cx<T> (&a)[4], const Tw<T, 4, LGH>& tw) {
+  const cx<T> w1 = cj<T, INV>(tw.w1), w2 = cj<T, INV>(tw.w2);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a[k] = s[swz<T>(base + k * h)];
-    const cx<T> w1 = twiddle<T, INV>(tab, r, lgh + 1);
+  for (int k = 0; k < 4; k += 2) {
+    const cx<T> b = cmul(a[k + 1], w1);
+    a[k + 1] = csub(a[k], b);
+    a[k] = cadd(a[k], b);
+  }
+  cx<T> b = cmul(a[2], w2);
+  a[2] = csub(a[0], b);
+  a[0] = cadd(a[0], b);
+  b = cmul(a[3], rot90<T, INV>(w2));
+  a[3] = csub(a[1], b);
+  a[1] = cadd(a[1], b);
+}
+
+template <typename T, bool INV, int LGH>
+__device__ __forceinline__ void bfly_dit2(cx<T> (&a)[2], const Tw<T, 2, LGH>& tw) {
+  const cx<T> b = cmul(a[1], cj<T, INV>(tw.w1));
+  a[1] = csub(a[0], b);
+  a[0] = cadd(a[0], b);
+}
+
+// Decimation in frequency: levels of span 4h, 2h, h (radix 8), 2h, h, h.
+template <typename T, bool INV, int LGH>
+__device__ __forceinline__ void bfly_dif8(cx<T> (&a)[8], const Tw<T, 8, LGH>& tw) {
+  constexpr bool C = LGH == 0;
+  const cx<T> w3a = cj<T, INV>(tw.w3a), w3b = cj<T, INV>(tw.w3b);
+  const cx<T> w3[4] = {w3a, w3b, rot90<T, INV>(w3a), rot90<T, INV>(w3b)};
 #pragma unroll
-    for (int k = 0; k < 4; k += 2) {
-      const cx<T> b = cmul(a[k + 1], w1);
-      a[k + 1] = csub(a[k], b);
-      a[k] = cadd(a[k], b);
-    }
-    const cx<T> w2 = twiddle<T, INV>(tab, r, lgh + 2);
-    const cx<T> w2b = rot90<T, INV>(w2);
-    cx<T> b = cmul(a[2], w2);
-    a[2] = csub(a[0], b);
-    a[0] = cadd(a[0], b);
-    b = cmul(a[3], w2b);
-    a[3] = csub(a[1], b);
-    a[1] = cadd(a[1], b);
+  for (int k = 0; k < 4; ++k) {
+    const cx<T> t = csub(a[k], a[k + 4]);
+    a[k] = cadd(a[k], a[k + 4]);
+    a[k + 4] = (C && k == 0) ? t : (C && k == 2) ? rot90<T, INV>(t) : cmul(t, w3[k]);
+  }
+  const cx<T> w1 = cj<T, INV>(tw.w1), w2 = cj<T, INV>(tw.w2);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) s[swz<T>(base + k * h)] = a[k];
+  for (int k0 = 0; k0 < 8; k0 += 4) {
+    cx<T> t = csub(a[k0], a[k0 + 2]);
+    a[k0] = cadd(a[k0], a[k0 + 2]);
+    a[k0 + 2] = tmul<T, C>(t, w2);
+    t = csub(a[k0 + 1], a[k0 + 3]);
+    a[k0 + 1] = cadd(a[k0 + 1], a[k0 + 3]);
+    a[k0 + 3] = C ? rot90<T, INV>(t) : cmul(t, rot90<T, INV>(w2));
+  }
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    const cx<T> t = csub(a[k], a[k + 1]);
+    a[k] = cadd(a[k], a[k + 1]);
+    a[k + 1] = tmul<T, C>(t, w1);
   }
 }
 
-template <typename T, bool INV, int N, int NT>
-__device__ __forceinline__ void dit_pass1(cx<T>* s, const cx<T>* __restrict__ tab, int lgh) {
-  const int h = 1 << lgh;
-  for (int q = threadIdx.x; q < N / 2; q += NT) {
-    const int r = q & (h - 1);
-    const int base = ((q >> lgh) << (lgh + 1)) + r;
-    const cx<T> a0 = s[swz<T>(base)];
-    const cx<T> b = cmul(s[swz<T>(base + h)], twiddle<T, INV>(tab, r, lgh + 1));
-    s[swz<T>(base)] = cadd(a0, b);
-    s[swz<T>(base + h)] = csub(a0, b);
+template <typename T, bool INV, int LGH>
+__device__ __forceinline__ void bfly_dif4(cx<T> (&a)[4], const Tw<T, 4, LGH>& tw) {
+  const cx<T> w1 = cj<T, INV>(tw.w1), w2 = cj<T, INV>(tw.w2);
+  cx<T> t = csub(a[0], a[2]);
+  a[0] = cadd(a[0], a[2]);
+  a[2] = cmul(t, w2);
+  t = csub(a[1], a[3]);
+  a[1] = cadd(a[1], a[3]);
+  a[3] = cmul(t, rot90<T, INV>(w2));
+#pragma unroll
+  for (int k = 0; k < 4; k += 2) {
+    t = csub(a[k], a[k + 1]);
+    a[k] = cadd(a[k], a[k + 1]);
+    a[k + 1] = cmul(t, w1);
   }
 }
 
-// ---- decimation-in-frequency passes (levels of span 4h, 2h, h) -----------
-template <typename T, bool INV, int N, int NT>
-__device__ __forceinline__ void dif_pass3(cx<T>* s, const cx<T>* __restrict__ tab, int lgh) {
-  const int h = 1 << lgh;
-  for (int q = threadIdx.x; q < N / 8; q += NT) {
-    const int r = q & (h - 1);
-    const int base = ((q >> lgh) << (lgh + 3)) + r;
-    cx<T> a[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) a[k] = s[swz<T>(base + k * h)];
-    cx<T> w3[4];
-    w3[0] = twiddle<T, INV>(tab, r, lgh + 3);
-    w3[1] = twiddle<T, INV>(tab, r + h, lgh + 3);
-    w3[2] = rot90<T, INV>(w3[0]);
-    w3[3] = rot90<T, INV>(w3[1]);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const cx<T> t = csub(a[k], a[k + 4]);
-      a[k] = cadd(a[k], a[k + 4]);
-      a[k + 4] = cmul(t, w3[k]);
-    }
-    const cx<T> w2 = twiddle<T, INV>(tab, r, lgh + 2);
-    const cx<T> w2b = rot90<T, INV>(w2);
-#pragma unroll
-    for (int k0 = 0; k0 < 8; k0 += 4) {
-      cx<T> t = csub(a[k0], a[k0 + 2]);
-      a[k0] = cadd(a[k0], a[k0 + 2]);
-      a[k0 + 2] = cmul(t, w2);
-      t = csub(a[k0 + 1], a[k0 + 3]);
-      a[k0 + 1] = cadd(a[k0 + 1], a[k0 + 3]);
-      a[k0 + 3] = cmul(t, w2b);
-    }
-    const cx<T> w1 = twiddle<T, INV>(tab, r, lgh + 1);
-#pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      const cx<T> t = csub(a[k], a[k + 1]);
-      a[k] = cadd(a[k], a[k + 1]);
-      a[k + 1] = cmul(t, w1);
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) s[swz<T>(base + k * h)] = a[k];
+template <typename T, bool INV, int LGH>
+__device__ __forceinline__ void bfly_dif2(cx<T> (&a)[2], const Tw<T, 2, LGH>& tw) {
+  const cx<T> t = csub(a[0], a[1]);
+  a[0] = cadd(a[0], a[1]);
+  a[1] = cmul(t, cj<T, INV>(tw.w1));
+}
+
+template <typename T, bool DIT, bool INV, int R, int LGH>
+__device__ __forceinline__ void bfly(cx<T> (&a)[R], const Tw<T, R, LGH>& tw) {
+  if constexpr (R == 8) {
+    if constexpr (DIT) bfly_dit8<T, INV, LGH>(a, tw);
+    else bfly_dif8<T, INV, LGH>(a, tw);
+  } else if constexpr (R == 4) {
+    if constexpr (DIT) bfly_dit4<T, INV, LGH>(a, tw);
+    else bfly_dif4<T, INV, LGH>(a, tw);
+  } else {
+    if constexpr (DIT) bfly_dit2<T, INV, LGH>(a, tw);
+    else bfly_dif2<T, INV, LGH>(a, tw);
   }
 }
 
-template <typename T, bool INV, int N, int NT>
-__device__ __forceinline__ void dif_pass2(cx<T>* s, const cx<T>* __restrict__ tab, int lgh) {
-  const int h = 1 << lgh;
-  for (int q = threadIdx.x; q < N / 4; q += NT) {
+// One radix-R stage over the LDS array: thread loop over the N/R point groups.
+template <typename T, bool DIT, bool INV, int N, int NT, int R, int LGH>
+__device__ __forceinline__ void stage(cx<T>* s, const cx<T>* __restrict__ tab) {
+  constexpr int h = 1 << LGH;
+  constexpr int LGR = R == 8 ? 3 : (R == 4 ? 2 : 1);
+  for (int q = threadIdx.x; q < N / R; q += NT) {
     const int r = q & (h - 1);
-    const int base = ((q >> lgh) << (lgh + 2)) + r;
-    cx<T> a[4];
+    const int base = ((q >> LGH) << (LGH + LGR)) + r;
+    cx<T> a[R];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) a[k] = s[swz<T>(base + k * h)];
-    const cx<T> w2 = twiddle<T, INV>(tab, r, lgh + 2);
-    const cx<T> w2b = rot90<T, INV>(w2);
-    cx<T> t = csub(a[0], a[2]);
-    a[0] = cadd(a[0], a[2]);
-    a[2] = cmul(t, w2);
-    t = csub(a[1], a[3]);
-    a[1] = cadd(a[1], a[3]);
-    a[3] = cmul(t, w2b);
-    const cx<T> w1 = twiddle<T, INV>(tab, r, lgh + 1);
+    for (int k = 0; k < R; ++k) a[k] = s[swz<T>(base + k * h)];
+    const Tw<T, R, LGH> tw(tab, r);
+    bfly<T, DIT, INV, R, LGH>(a, tw);
 #pragma unroll
-    for (int k = 0; k < 4; k += 2) {
-      t = csub(a[k], a[k + 1]);
-      a[k] = cadd(a[k], a[k + 1]);
-      a[k + 1] = cmul(t, w1);
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) s[swz<T>(base + k * h)] = a[k];
+    for (int k = 0; k < R; ++k) s[swz<T>(base + k * h)] = a[k];
   }
 }
 
-template <typename T, bool INV, int N, int NT>
-__device__ __forceinline__ void dif_pass1(cx<T>* s, const cx<T>* __restrict__ tab, int lgh) {
-  const int h = 1 << lgh;
-  for (int q = threadIdx.x; q < N / 2; q += NT) {
-    const int r = q & (h - 1);
-    const int base = ((q >> lgh) << (lgh + 1)) + r;
-    const cx<T> a0 = s[swz<T>(base)], a1 = s[swz<T>(base + h)];
-    s[swz<T>(base)] = cadd(a0, a1);
-    s[swz<T>(base + h)] = cmul(csub(a0, a1), twiddle<T, INV>(tab, r, lgh + 1));
+// Stage plans.  DIT: radix-8 stages from span 1 upward, then one radix-4 or
+// radix-2 stage for the remaining levels; DIF: the mirror image.
+template <int LGN>
+struct Plan8 {
+  static constexpr int REM = LGN % 3;
+  static constexpr int RLAST = REM == 0 ? 8 : (REM == 2 ? 4 : 2);  // radix of the outer stage
+  static constexpr int LGLAST = LGN - (REM == 0 ? 3 : REM);         // its span exponent
+};
+
+template <typename T, bool INV, int LGN, int NT, int LGH, bool SKIP_LAST>
+__device__ __forceinline__ void dit_from(cx<T>* s, const cx<T>* __restrict__ tab) {
+  constexpr int N = 1 << LGN;
+  if constexpr (LGH + 3 <= LGN) {
+    if constexpr (!(SKIP_LAST && LGH + 3 == LGN)) {
+      stage<T, true, INV, N, NT, 8, LGH>(s, tab);
+      __syncthreads();
+    }
+    dit_from<T, INV, LGN, NT, LGH + 3, SKIP_LAST>(s, tab);
+  } else if constexpr (LGN - LGH == 2 && !SKIP_LAST) {
+    stage<T, true, INV, N, NT, 4, LGH>(s, tab);
+    __syncthreads();
+  } else if constexpr (LGN - LGH == 1 && !SKIP_LAST) {
+    stage<T, true, INV, N, NT, 2, LGH>(s, tab);
+    __syncthreads();
+  }
+}
+
+template <typename T, bool INV, int LGN, int NT, int LGH>
+__device__ __forceinline__ void dif_down(cx<T>* s, const cx<T>* __restrict__ tab) {
+  constexpr int N = 1 << LGN;
+  if constexpr (LGH >= 0) {
+    stage<T, false, INV, N, NT, 8, LGH>(s, tab);
+    __syncthreads();
+    dif_down<T, INV, LGN, NT, LGH - 3>(s, tab);
   }
 }
 
@@ -212,41 +257,18 @@ __device__ __forceinline__ void dif_pass1(cx<T>* s, const cx<T>* __restrict__ ta
 // through swz<T>() too; the transforms end with a barrier.
 template <typename T, bool INV, int LGN, int NT>
 __device__ __forceinline__ void fft_dit(cx<T>* s, const cx<T>* __restrict__ tab) {
-  constexpr int N = 1 << LGN;
-  int lgh = 0;
-#pragma unroll
-  for (int it = 0; it < LGN / 3; ++it, lgh += 3) {
-    dit_pass3<T, INV, N, NT>(s, tab, lgh);
-    __syncthreads();
-  }
-  if constexpr (LGN % 3 == 2) {
-    dit_pass2<T, INV, N, NT>(s, tab, lgh);
-    __syncthreads();
-  } else if constexpr (LGN % 3 == 1) {
-    dit_pass1<T, INV, N, NT>(s, tab, lgh);
-    __syncthreads();
-  }
+  dit_from<T, INV, LGN, NT, 0, false>(s, tab);
 }
 
 template <typename T, bool INV, int LGN, int NT>
 __device__ __forceinline__ void fft_dif(cx<T>* s, const cx<T>* __restrict__ tab) {
   constexpr int N = 1 << LGN;
-  int lgh = LGN;
-  if constexpr (LGN % 3 == 2) {
-    lgh -= 2;
-    dif_pass2<T, INV, N, NT>(s, tab, lgh);
-    __syncthreads();
-  } else if constexpr (LGN % 3 == 1) {
-    lgh -= 1;
-    dif_pass1<T, INV, N, NT>(s, tab, lgh);
+  using P = Plan8<LGN>;
+  if constexpr (P::RLAST != 8) {
+    stage<T, false, INV, N, NT, P::RLAST, P::LGLAST>(s, tab);
     __syncthreads();
   }
-#pragma unroll
-  for (int it = 0; it < LGN / 3; ++it) {
-    lgh -= 3;
-    dif_pass3<T, INV, N, NT>(s, tab, lgh);
-    __syncthreads();
-  }
+  dif_down<T, INV, LGN, NT, P::RLAST == 8 ? P::LGLAST : P::LGLAST - 3>(s, tab);
 }
 
 // Forward real-FFT post-step for the bin pair (k, N-k): from Z[k], Z[N-k]

@@ -65,9 +65,10 @@ hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, 
 // deficiency (the sketch [S X | S b] passes p: b may lie in the range of X).
 // A: crows x ldq row-major, crows % 16 == 0.  G: qr_scratch_doubles() doubles.
 size_t qr_scratch_doubles(int crows, int q, int ldq);
-// sweeps: 3 = shifted Cholesky QR then two refining sweeps (R accurate to
-// O(u) orthogonality); 1 = the shifted sweep alone (a rougher R, enough for
-// approximate leverage scores).
+// sweeps: 3 = shifted Cholesky QR then one refining sweep, and a second one
+// only when the first refining Cholesky needed the shift (A R^{-1}
+// orthonormal to about 1e-6 or better); 1 = the shifted sweep alone (a
+// rougher R, enough for approximate leverage scores).
 hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sweeps, double* R,
                      double* G, double* R1, double* R2, int* status, hipStream_t st);
 hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, double* phi0,

@@ -32,6 +32,27 @@ bool lsqr_step_lds(int lgn, int p) {
 
 namespace {
 
+// Stages the p x p row-major matrix M into LDS rows of odd length ldm: one
+// wavefront per row, 8 rows' loads in flight per wavefront before any store.
+template <int NT>
+__device__ __forceinline__ void stage_m(const double* __restrict__ M, int p, int ldm,
+                                        double* __restrict__ sM) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int r0 = wid * 8; r0 < p; r0 += NW * 8) {
+    for (int c0 = 0; c0 < p; c0 += 64) {
+      const int c = c0 + lane;
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        v[u] = (r0 + u < p && c < p) ? M[static_cast<size_t>(r0 + u) * p + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (r0 + u < p && c < p) sM[(r0 + u) * ldm + c] = v[u];
+    }
+  }
+}
+
 // out[r] = sum_{c in [lo(r), p)} Mrow[r][c] x[c] for the rows r of an upper
 // (lo(r) = r) or lower (lo = 0, hi(r) = r + 1) triangular p x p row-major
 // matrix; one wavefront per row, four rows in flight, lanes over columns.
@@ -89,7 +110,7 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
   const bool init = st->phase == 0;
   const double tol = st->tol;
   if constexpr (MLDS) {
-    for (int e = tid; e < p * p; e += NT) sM[(e / p) * ldm + e % p] = M[e];
+    stage_m<NT>(M, p, ldm, sM);
   }
 
   const double beta = sqrt(g[p]);
@@ -390,7 +411,7 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
   const bool lds = p <= 128;
   if (st->done) return;
   if (lds)
-    for (int e = threadIdx.x; e < p * p; e += NT) sM[(e / p) * ldm + e % p] = M[e];
+    stage_m<NT>(M, p, ldm, sM);
   for (int i = threadIdx.x; i < p; i += NT) sx[i] = g64[i];
   __syncthreads();
   gemv_m<NT, true>(M, Mt, sM, ldm, lds, p, sx, sh);  // h = M^T X^T r
@@ -476,7 +497,7 @@ __device__ __forceinline__ void refine_cg_body(int p, RefineState* __restrict__ 
   const bool lds = p <= 128;
   if (st->inner_done) return;
   if (lds)
-    for (int e = threadIdx.x; e < p * p; e += NT) sM[(e / p) * ldm + e % p] = M[e];
+    stage_m<NT>(M, p, ldm, sM);
   for (int i = threadIdx.x; i < p; i += NT) sx[i] = g[i];
   __syncthreads();
   gemv_m<NT, true>(M, Mt, sM, ldm, lds, p, sx, st_);  // t = A^T A d

@@ -7,7 +7,10 @@
 // up to condition numbers near 1/u; the later sweeps restore orthogonality.
 // Near that limit the first sweep can leave kappa(A R1^{-1}) ~ 1e8, where the
 // unshifted Gram matrix is on the edge of breakdown; a later sweep whose
-// Cholesky breaks down is therefore redone with the shift (status bit 8).
+// Cholesky breaks down is therefore redone with the shift.  After the second
+// sweep, A R1^{-1} R2^{-1} is orthonormal to O(u kappa(A R1^{-1})^2); the
+// third sweep runs only when the second Cholesky needed the shift or its
+// pivots spanned more than 1e4 (status bit 8), otherwise R = R2 R1.
 // Every Gram matrix is a dense contraction over the c rows, computed on the
 // FP64 matrix cores (V_MFMA_F64_16X16X4_F64).
 //
@@ -63,6 +66,15 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ A,
 // Right-looking Cholesky of G[:q,:q] (+ shift on the diagonal) into the upper
 // factor R (row-major q x q, zero below the diagonal).  One workgroup; the
 // working copy lives in R.
+// After a refining sweep, A R^{-1} is orthonormal to about u kappa^2, kappa
+// the condition number of that sweep's input.  Its pivots (R_jj^2) give only
+// a lower bound on kappa^2 (by about 1e6 on ill-conditioned lag sketches), so
+// the next sweep is enabled (status bit 8) as soon as they span more than 1e4:
+// well-conditioned inputs (R near the identity) skip it.
+__device__ __forceinline__ bool needs_third_sweep(double dmin, double dmax) {
+  return !(dmax <= 1e4 * dmin);
+}
+
 template <int NT>
 __device__ __forceinline__ void chol_body(const double* __restrict__ G, int ldq, int q,
                                                   int crows, int shift, double* __restrict__ R,
@@ -78,8 +90,11 @@ __device__ __forceinline__ void chol_body(const double* __restrict__ G, int ldq,
     s_floor = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
   }
   bool failed = false;
+  double dmin = INFINITY, dmax = 0.0;
   for (int attempt = (shift == 1 ? 1 : 0); attempt < 2; ++attempt) {
   failed = false;
+  dmin = INFINITY;
+  dmax = 0.0;
   for (int e = threadIdx.x; e < q * q; e += NT) {
     const int i = e / q, k = e % q;
     R[e] = (k >= i) ? G[static_cast<size_t>(i) * ldq + k] : 0.0;
@@ -93,6 +108,10 @@ __device__ __forceinline__ void chol_body(const double* __restrict__ G, int ldq,
     if (!(d > s_floor)) {
       if (j < rank_cols) failed = true;  // later columns may be exactly dependent (b in range)
       d = s_floor;
+    }
+    if (j < rank_cols) {
+      dmin = fmin(dmin, d);
+      dmax = fmax(dmax, d);
     }
     const double rjj = sqrt(d);
     const double inv = 1.0 / rjj;
@@ -109,7 +128,8 @@ __device__ __forceinline__ void chol_body(const double* __restrict__ G, int ldq,
     __syncthreads();
   }
   if (!failed || shift != 2 || attempt == 1) {
-    if (attempt == 1 && shift == 2 && threadIdx.x == 0) atomicOr(status, 8);
+    if (shift == 2 && threadIdx.x == 0 && (attempt == 1 || needs_third_sweep(dmin, dmax)))
+      atomicOr(status, 8);
     break;
   }
   __syncthreads();
@@ -121,7 +141,8 @@ template <int NT>
 __global__ __launch_bounds__(NT) void chol_kernel(const double* __restrict__ G, int ldq, int q,
                                                   int crows, int shift, double* __restrict__ R,
                                                   int* __restrict__ status, int fail_bit,
-                                                  int rank_cols) {
+                                                  int rank_cols, const int* __restrict__ gate) {
+  if (gate && !(*gate & 8)) return;
   chol_body<NT>(G, ldq, q, crows, shift, R, status, fail_bit, rank_cols);
 }
 
@@ -203,9 +224,11 @@ __device__ __forceinline__ void triinv_body(const double* __restrict__ R, int q,
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < p * p; e += NT) {
-    const int i = e / p, j = e % p;
-    Mt[static_cast<size_t>(j) * p + i] = M[e];
+  {
+    // Mt = M^T: one wavefront per row of M, lanes over its columns
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = wid; i < p; i += NT / 64)
+      for (int j = lane; j < p; j += 64) Mt[static_cast<size_t>(j) * p + i] = M[static_cast<size_t>(i) * p + j];
   }
   if (phi0 && q > p) {
     for (int i = threadIdx.x; i < p; i += NT) {
@@ -245,75 +268,13 @@ __global__ __launch_bounds__(NT) void triinv_kernel(const double* __restrict__ R
 
 // ---- LDS-resident variants for q <= 128 (the whole q x q matrix in LDS) ----
 
-// Cholesky of G[:q,:q] (+ shift) with the trailing matrix kept symmetric in
-// LDS: step j subtracts S[i][j] S[j][k] / S[j][j] from the trailing square
-// (one barrier per column); row j is scaled by 1/sqrt(S[j][j]) at the end.
-// shift_mode: 0 never shift, 1 always shift, 2 shift only when the unshifted
-// factorisation breaks down (then status |= 8; a breakdown of the shifted
-// retry sets fail_bit).
-template <int NT>
-__global__ __launch_bounds__(NT) void chol_lds_kernel(const double* __restrict__ G, int ldq, int q,
-                                                      int crows, int shift_mode,
-                                                      double* __restrict__ R,
-                                                      int* __restrict__ status, int fail_bit,
-                                                      int rank_cols) {
-  extern __shared__ double S[];
-  __shared__ double red[NT / 64];
-  __shared__ int s_fail;
-  double tr = 0.0;
-  for (int i = threadIdx.x; i < q; i += NT) tr += G[static_cast<size_t>(i) * ldq + i];
-  tr = block_sum<NT>(tr, red);
-  const double shift_amount =
-      11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) * 0x1p-53 * tr;
-  const double floor_ = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  constexpr int TY = NT / 16;
-  for (int attempt = (shift_mode == 1 ? 1 : 0); attempt < 2; ++attempt) {
-    const double sh = attempt ? shift_amount : 0.0;
-    for (int e = threadIdx.x; e < q * q; e += NT) {
-      const int i = e / q, k = e % q;
-      S[e] = G[static_cast<size_t>(i) * ldq + k] + (i == k ? sh : 0.0);
-    }
-    if (threadIdx.x == 0) s_fail = 0;
-    __syncthreads();
-    for (int j = 0; j < q; ++j) {
-      double d = S[j * q + j];
-      if (!(d > floor_)) {
-        if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
-        d = floor_;
-      }
-      const double invd = 1.0 / d;
-      const double* rowj = S + j * q;
-      for (int i = j + 1 + ty; i < q; i += TY) {
-        const double f = rowj[i] * invd;
-        double* rowi = S + i * q;
-        for (int k = j + 1 + tx; k < q; k += 16) rowi[k] -= f * rowj[k];
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) S[j * q + j] = d;  // the floored pivot, read again only below
-    }
-    __syncthreads();
-    const int failed = s_fail;
-    if (!failed || shift_mode != 2 || attempt == 1) {
-      if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
-      if (attempt == 1 && shift_mode == 2 && threadIdx.x == 0) atomicOr(status, 8);
-      break;
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < q * q; e += NT) {
-    const int i = e / q, k = e % q;
-    const double di = sqrt(S[i * q + i]);
-    R[e] = k < i ? 0.0 : (k == i ? di : S[e] / di);
-  }
-}
-
 // ---- register-tiled variants for q <= 16 QT (QT <= 8) ---------------------
 // Thread (tx, ty) of 256 owns the elements (ty + 16 a, tx + 16 b) of the q x q
 // matrix in registers; the row a step needs is published through a
 // double-buffered LDS row, so a step costs one barrier and register FMAs.
 
-// Cholesky G[:q,:q] (+ shift) = R^T R; shift_mode as in chol_lds_kernel.
+// Cholesky G[:q,:q] (+ shift) = R^T R.  shift_mode 1: always shifted; 2: unshifted, redone
+// with the shift on breakdown.
 template <int QT>
 __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int ldq, int q,
                                                        int crows, int shift_mode,
@@ -342,6 +303,7 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
       }
     if (threadIdx.x == 0) s_fail = 0;
     __syncthreads();
+    double dmin = INFINITY, dmax = 0.0;
     for (int j = 0; j < q; ++j) {
       double* pj = pub[j & 1];
       if (ty == (j & 15)) {
@@ -357,10 +319,27 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
         if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
         d = floor_;
       }
+      if (j < rank_cols) {
+        dmin = fmin(dmin, d);
+        dmax = fmax(dmax, d);
+      }
+      // independent operations (shortest dependent chain per column)
       const double invd = 1.0 / d;
       const double isd = 1.0 / sqrt(d);
-      for (int k = threadIdx.x; k < q; k += 256)
-        R[static_cast<size_t>(j) * q + k] = k < j ? 0.0 : (k == j ? sqrt(d) : pj[k] * isd);
+      const double sd = sqrt(d);
+      // row j of R stays in the registers of its owner (rows above j are not
+      // updated again); R is written once after the last column, so no
+      // barrier waits on global stores
+      if (ty == (j & 15)) {
+#pragma unroll
+        for (int a = 0; a < QT; ++a)
+          if (a == (j >> 4))
+#pragma unroll
+            for (int b = 0; b < QT; ++b) {
+              const int k = tx + 16 * b;
+              reg[a][b] = k < j ? 0.0 : (k == j ? sd : reg[a][b] * isd);
+            }
+      }
       double fi[QT], fk[QT];
 #pragma unroll
       for (int a = 0; a < QT; ++a) {
@@ -379,9 +358,18 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
     }
     __syncthreads();
     const int failed = s_fail;
+    // R (q x q, row-major): the finished rows from the register tiles
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int b = 0; b < QT; ++b) {
+        const int i = ty + 16 * a, k = tx + 16 * b;
+        if (i < q && k < q) R[static_cast<size_t>(i) * q + k] = reg[a][b];
+      }
     if (!failed || shift_mode != 2 || attempt == 1) {
       if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
-      if (attempt == 1 && shift_mode == 2 && threadIdx.x == 0) atomicOr(status, 8);
+      if (shift_mode == 2 && threadIdx.x == 0 && (attempt == 1 || needs_third_sweep(dmin, dmax)))
+        atomicOr(status, 8);
       break;
     }
     __syncthreads();
@@ -393,7 +381,8 @@ __global__ __launch_bounds__(256) void chol_reg_kernel(const double* __restrict_
                                                        int crows, int shift_mode,
                                                        double* __restrict__ R,
                                                        int* __restrict__ status, int fail_bit,
-                                                       int rank_cols) {
+                                                       int rank_cols, const int* __restrict__ gate) {
+  if (gate && !(*gate & 8)) return;
   chol_reg_body<QT>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols);
 }
 
@@ -407,7 +396,19 @@ __device__ __forceinline__ void triinv_reg_body(const double* __restrict__ R, in
   __shared__ double pub[2][16 * QT];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int ld = n + 1;
-  for (int e = threadIdx.x; e < n * n; e += 256) Rs[(e / n) * ld + e % n] = R[static_cast<size_t>(e / n) * ldr + e % n];
+  {
+    // one wavefront per 8 rows, lanes over columns, 8 loads in flight
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int r0 = wid * 8; r0 < n; r0 += 32)
+      for (int c = lane; c < n; c += 64) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = r0 + u < n ? R[static_cast<size_t>(r0 + u) * ldr + c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (r0 + u < n) Rs[(r0 + u) * ld + c] = v[u];
+      }
+  }
   double reg[QT][QT];
 #pragma unroll
   for (int a = 0; a < QT; ++a)
@@ -452,46 +453,17 @@ __device__ __forceinline__ void triinv_reg_body(const double* __restrict__ R, in
       if (r < ldm && c < ldm) M[static_cast<size_t>(r) * ldm + c] = (r < n && c < n) ? reg[a][b] : 0.0;
     }
   // rows / columns of the ldm block beyond 16 QT (only when ldm > 16 QT)
-  for (int e = threadIdx.x; e < ldm * ldm; e += 256) {
-    const int r = e / ldm, c = e % ldm;
-    if (r >= 16 * QT || c >= 16 * QT) M[e] = 0.0;
-  }
+  if (ldm > 16 * QT)
+    for (int e = threadIdx.x; e < ldm * ldm; e += 256) {
+      const int r = e / ldm, c = e % ldm;
+      if (r >= 16 * QT || c >= 16 * QT) M[e] = 0.0;
+    }
 }
 
 template <int QT>
 __global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restrict__ R, int ldr, int n,
                                                          double* __restrict__ M, int ldm) {
   triinv_reg_body<QT>(R, ldr, n, M, ldm);
-}
-
-// M = R[:n,:n]^{-1} (upper, row-major with leading dimension ldm, zero
-// elsewhere in the ldm x ldm block), rows computed bottom-up in LDS.
-template <int NT>
-__global__ __launch_bounds__(NT) void triinv_lds_kernel(const double* __restrict__ R, int ldr, int n,
-                                                        double* __restrict__ M, int ldm) {
-  extern __shared__ double S[];  // n x n, then one staged row of R
-  double* ri = S + n * n;
-  for (int e = threadIdx.x; e < n * n; e += NT) S[e] = 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    for (int k = i + threadIdx.x; k < n; k += NT) ri[k] = R[static_cast<size_t>(i) * ldr + k];
-    __syncthreads();
-    const double inv = 1.0 / ri[i];
-    for (int j = i + threadIdx.x; j < n; j += NT) {
-      double a0 = (j == i) ? 1.0 : 0.0, a1 = 0.0;
-      int k = i + 1;
-      for (; k + 1 <= j; k += 2) {
-        a0 -= ri[k] * S[k * n + j];
-        a1 -= ri[k + 1] * S[(k + 1) * n + j];
-      }
-      if (k <= j) a0 -= ri[k] * S[k * n + j];
-      S[i * n + j] = (a0 + a1) * inv;
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < ldm * ldm; e += NT) {
-    const int i = e / ldm, j = e % ldm;
-    M[e] = (i < n && j < n) ? S[i * n + j] : 0.0;
-  }
 }
 
 // A <- A R^{-1} on the first q columns, 16 rows per wavefront (rows are
@@ -506,14 +478,26 @@ __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, 
   double* Rp = T + 16 * ld;
   const int lane = threadIdx.x;
   const size_t r0 = static_cast<size_t>(rt) * 16;
-  for (int e = lane; e < 16 * ldq; e += 64) T[(e / ldq) * ld + e % ldq] = A[(r0 + e / ldq) * ldq + e % ldq];
+  // the 16 rows of A: lanes over columns, 16 rows' loads in flight
+  for (int c = lane; c < ldq; c += 64) {
+    double v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = A[(r0 + r) * ldq + c];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) T[r * ld + c] = v[r];
+  }
   const int nt = (q + 15) / 16;
   for (int J = 0; J < nt; ++J) {
     const int j0 = J * 16;
-    // rows j0 .. j0+15 of R (zero outside q x q)
-    for (int e = lane; e < 16 * ldq; e += 64) {
-      const int rr = j0 + e / ldq, cc = e % ldq;
-      Rp[e] = (rr < q && cc < q) ? R[static_cast<size_t>(rr) * q + cc] : 0.0;
+    // rows j0 .. j0+15 of R from column j0 on (zero outside q x q; R is
+    // upper triangular, so nothing left of j0 is read)
+    for (int cc = j0 + lane; cc < ldq; cc += 64) {
+      double v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        v[r] = (j0 + r < q && cc < q) ? R[static_cast<size_t>(j0 + r) * q + cc] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Rp[r * ldq + cc] = v[r];
     }
     __syncthreads();
     if (lane < 16) {
@@ -542,34 +526,15 @@ __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, 
     }
     __syncthreads();
   }
-  for (int e = lane; e < 16 * ldq; e += 64) A[(r0 + e / ldq) * ldq + e % ldq] = T[(e / ldq) * ld + e % ldq];
+  for (int c = lane; c < ldq; c += 64) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) A[(r0 + r) * ldq + c] = T[r * ld + c];
+  }
 }
 
 __global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, int ldq, int q,
                                                        const double* __restrict__ R) {
   trsm_tile_body(A, ldq, q, R, blockIdx.x);
-}
-
-// Aout = Ain * M on the first ldq columns (M upper triangular, ldq x ldq,
-// zero-padded): one 16x16 output tile per wavefront on the FP64 matrix cores.
-__global__ __launch_bounds__(64) void gemm_upper_kernel(const double* __restrict__ Ain, int ldq,
-                                                        const double* __restrict__ M,
-                                                        double* __restrict__ Aout) {
-  const int tiles_n = ldq / 16;
-  const int tr = blockIdx.x / tiles_n, tc = blockIdx.x % tiles_n;
-  const int lane = threadIdx.x;
-  const int r0 = tr * 16, c0 = tc * 16;
-  d4 acc = {0.0, 0.0, 0.0, 0.0};
-  const double* arow = Ain + static_cast<size_t>(r0 + (lane & 15)) * ldq;
-  const int kend = c0 + 16;  // M[i][j] = 0 for i > j
-  for (int k0 = 0; k0 < kend; k0 += 4) {
-    const double a = arow[k0 + (lane >> 4)];
-    const double b = M[static_cast<size_t>(k0 + (lane >> 4)) * ldq + c0 + (lane & 15)];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int v = 0; v < 4; ++v)
-    Aout[static_cast<size_t>(r0 + 4 * v + (lane >> 4)) * ldq + c0 + (lane & 15)] = acc[v];
 }
 
 // status |= 4 when min|R_ii| <= k u max|R_ii| over the first k = rank_cols
@@ -603,9 +568,11 @@ __device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R,
                                                            double* __restrict__ Mt,
                                                            double* __restrict__ phi0,
                                                            int* __restrict__ status) {
-  for (int e = threadIdx.x; e < p * p; e += NT) {
-    const int i = e / p, j = e % p;
-    Mt[static_cast<size_t>(j) * p + i] = M[e];
+  {
+    // Mt = M^T: one wavefront per row of M, lanes over its columns
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int i = wid; i < p; i += NT / 64)
+      for (int j = lane; j < p; j += 64) Mt[static_cast<size_t>(j) * p + i] = M[static_cast<size_t>(i) * p + j];
   }
   if (phi0 && q > p) {
     for (int i = threadIdx.x; i < p; i += NT) {
@@ -655,26 +622,24 @@ namespace {
 
 template <int QT>
 void chol_reg_launch(const double* G, int ldq, int q, int crows, int shift_mode, double* R,
-                     int* status, int fail_bit, int rank_cols, hipStream_t st) {
+                     int* status, int fail_bit, int rank_cols, const int* gate, hipStream_t st) {
   hipLaunchKernelGGL((chol_reg_kernel<QT>), dim3(1), dim3(256), 0, st, G, ldq, q, crows, shift_mode,
-                     R, status, fail_bit, rank_cols);
+                     R, status, fail_bit, rank_cols, gate);
 }
 
+// gate: NULL, or run only when bit 8 of *gate is set (the third sweep).
 void chol_launch(const double* G, int ldq, int q, int crows, int shift_mode, double* R, int* status,
-                 int fail_bit, int rank_cols, hipStream_t st) {
+                 int fail_bit, int rank_cols, const int* gate, hipStream_t st) {
   const int qt = (q + 15) / 16;
   switch (qt) {
-    case 1: chol_reg_launch<1>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
-    case 2: chol_reg_launch<2>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
-    case 3: chol_reg_launch<3>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
-    case 4: chol_reg_launch<4>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
-    case 5: chol_reg_launch<5>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
-    case 6: chol_reg_launch<6>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
-    case 7: chol_reg_launch<7>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
-    case 8: chol_reg_launch<8>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, st); return;
+#define TLS_CHOL_QT(K) \
+    case K: chol_reg_launch<K>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, gate, st); return;
+    TLS_CHOL_QT(1) TLS_CHOL_QT(2) TLS_CHOL_QT(3) TLS_CHOL_QT(4)
+    TLS_CHOL_QT(5) TLS_CHOL_QT(6) TLS_CHOL_QT(7) TLS_CHOL_QT(8)
+#undef TLS_CHOL_QT
     default:
       hipLaunchKernelGGL((chol_kernel<256>), dim3(1), dim3(256), 0, st, G, ldq, q, crows, shift_mode,
-                         R, status, fail_bit, rank_cols);
+                         R, status, fail_bit, rank_cols, gate);
   }
 }
 
@@ -704,6 +669,40 @@ hipError_t tri_inverse(const double* R, int ldr, int n, double* M, int ldm, hipS
   return hipGetLastError();
 }
 
+namespace {
+
+// Third-sweep kernels: they run only when bit 8 of *gate is set by the
+// second Cholesky (see needs_third_sweep); otherwise R = R2 R1.
+__global__ __launch_bounds__(256) void gram_gated_kernel(const int* __restrict__ gate,
+                                                         const double* __restrict__ A, int crows,
+                                                         int ldq, double* __restrict__ G) {
+  if (!(*gate & 8)) return;
+  gram_body(A, crows, ldq, G, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void trsm_tile_gated_kernel(const int* __restrict__ gate,
+                                                             double* __restrict__ A, int ldq, int q,
+                                                             const double* __restrict__ R) {
+  if (!(*gate & 8)) return;
+  trsm_tile_body(A, ldq, q, R, blockIdx.x);
+}
+
+// Row i of T = R3 R2 when the third sweep ran, else of T = R2.
+template <int NT>
+__global__ __launch_bounds__(NT) void trmm_gated_kernel(const int* __restrict__ gate,
+                                                        const double* __restrict__ R3,
+                                                        const double* __restrict__ R2, int q,
+                                                        double* __restrict__ T) {
+  if (*gate & 8) {
+    trmm_body<NT>(R3, R2, q, T, blockIdx.x);
+    return;
+  }
+  const size_t row = static_cast<size_t>(blockIdx.x) * q;
+  for (int k = threadIdx.x; k < q; k += NT) T[row + k] = R2[row + k];
+}
+
+}  // namespace
+
 hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sweeps, double* R,
                      double* G, double* R1, double* R2, int* status, hipStream_t st) {
   if (crows % 16 != 0 || ldq % 16 != 0 || q > ldq || q < 1 || sweeps < 1 || sweeps > 3)
@@ -712,21 +711,35 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sw
   double* R3 = G + static_cast<size_t>(ldq) * ldq;
   double* T = R3 + static_cast<size_t>(q) * q;
   double* Rs[3] = {sweeps == 1 ? R : R1, R2, R3};
+  // the third sweep is gated on status bit 8 from the second Cholesky
+  const bool gate3 = sweeps == 3 && ldq <= 1024;
+  const size_t trsm_shm = (16 * (ldq + 1) + 16 * ldq) * sizeof(double);
   for (int sweep = 0; sweep < sweeps; ++sweep) {
-    hipLaunchKernelGGL(gram_kernel, dim3(nt * nt), dim3(256), 0, st, A, crows, ldq, G);
+    const bool gated = gate3 && sweep == 2;
+    if (gated)
+      hipLaunchKernelGGL(gram_gated_kernel, dim3(nt * nt), dim3(256), 0, st, status, A, crows, ldq, G);
+    else
+      hipLaunchKernelGGL(gram_kernel, dim3(nt * nt), dim3(256), 0, st, A, crows, ldq, G);
     chol_launch(G, ldq, q, crows, sweep == 0 ? 1 : 2, Rs[sweep], status, sweep == 0 ? 1 : 2,
-                rank_cols, st);
+                rank_cols, gated ? status : nullptr, st);
     if (sweep == sweeps - 1) break;
     if (ldq <= 1024) {
-      hipLaunchKernelGGL(trsm_tile_kernel, dim3(crows / 16), dim3(64),
-                         (16 * (ldq + 1) + 16 * ldq) * sizeof(double), st, A, ldq, q, Rs[sweep]);
+      if (gate3 && sweep == 1)
+        hipLaunchKernelGGL(trsm_tile_gated_kernel, dim3(crows / 16), dim3(64), trsm_shm, st, status,
+                           A, ldq, q, Rs[sweep]);
+      else
+        hipLaunchKernelGGL(trsm_tile_kernel, dim3(crows / 16), dim3(64), trsm_shm, st, A, ldq, q,
+                           Rs[sweep]);
     } else {
       hipLaunchKernelGGL(trsm_global_kernel, dim3((crows + 63) / 64), dim3(64), 0, st, A, crows,
                          ldq, q, Rs[sweep]);
     }
   }
   if (sweeps == 3) {
-    hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, R3, R2, q, T);
+    if (gate3)
+      hipLaunchKernelGGL((trmm_gated_kernel<256>), dim3(q), dim3(256), 0, st, status, R3, R2, q, T);
+    else
+      hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, R3, R2, q, T);
     hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, T, R1, q, R);
   } else if (sweeps == 2) {
     hipLaunchKernelGGL((trmm_kernel<256>), dim3(q), dim3(256), 0, st, R2, R1, q, R);
@@ -756,10 +769,13 @@ hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, d
 namespace tls {
 namespace {
 
+// gated: the third sweep of the final factorisation, run only for fits whose
+// second Cholesky set status bit 8.
 __global__ __launch_bounds__(256) void gram_b_kernel(const Item* __restrict__ items,
-                                                     const FitDesc* __restrict__ D) {
+                                                     const FitDesc* __restrict__ D, int gated) {
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
+  if (gated && !(d.status[0] & 8)) return;
   gram_body(d.A, d.crows, d.ldq, d.G, it.idx);
 }
 
@@ -778,6 +794,7 @@ template <int QT>
 __global__ __launch_bounds__(256) void chol_b_kernel(const Item* __restrict__ items,
                                                      const FitDesc* __restrict__ D, int sweep) {
   const FitDesc& d = D[items[blockIdx.x].fit];
+  if (sweep == 2 && !(d.status[0] & 8)) return;
   double* R;
   int* status;
   int shift_mode, fail_bit;
@@ -792,6 +809,7 @@ __global__ __launch_bounds__(64) void trsm_b_kernel(const Item* __restrict__ ite
                                                     const FitDesc* __restrict__ D, int which) {
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
+  if (which == 1 && !(d.status[0] & 8)) return;  // only feeds the third sweep
   trsm_tile_body(d.A, d.ldq, d.q, which == 0 ? d.R1 : d.R2, it.idx);
 }
 
@@ -801,9 +819,14 @@ __global__ __launch_bounds__(256) void trmm_b_kernel(const Item* __restrict__ it
   const FitDesc& d = D[it.fit];
   double* R3 = d.G + static_cast<size_t>(d.ldq) * d.ldq;
   double* T = R3 + static_cast<size_t>(d.q) * d.q;
-  if (variant == 0)
-    trmm_body<256>(R3, d.R2, d.q, T, it.idx);
-  else
+  if (variant == 0) {
+    if (d.status[0] & 8) {
+      trmm_body<256>(R3, d.R2, d.q, T, it.idx);
+    } else {
+      const size_t row = static_cast<size_t>(it.idx) * d.q;
+      for (int k = threadIdx.x; k < d.q; k += 256) T[row + k] = d.R2[row + k];
+    }
+  } else
     trmm_body<256>(T, d.R1, d.q, d.R, it.idx);
 }
 
@@ -855,7 +878,8 @@ hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtile
                           sizeof(double);
   const int sweeps = stage == 1 ? 1 : 3;
   for (int sweep = 0; sweep < sweeps; ++sweep) {
-    hipLaunchKernelGGL(gram_b_kernel, dim3(ntiles), dim3(256), 0, st, tiles, D);
+    hipLaunchKernelGGL(gram_b_kernel, dim3(ntiles), dim3(256), 0, st, tiles, D,
+                       stage == 2 && sweep == 2 ? 1 : 0);
     hipLaunchKernelGGL((chol_b_kernel<QT>), dim3(nfits), dim3(256), 0, st, fits, D,
                        stage == 1 ? -1 : sweep);
     if (sweep < sweeps - 1)

@@ -176,7 +176,6 @@ struct tls_server {
   bool stopping = false;
   tls_status failed = TLS_OK;  // a device error stops the worker
   uint64_t ticks = 0, admitted = 0, completed = 0;
-  size_t active = 0;
   std::thread worker;
 };
 
@@ -436,10 +435,6 @@ void worker_main(tls_server* S) {
       if (!r->lsqr_done) next_active.push_back(r);
     active.swap(next_active);
     finishing.swap(newly_done);
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->active = active.size() + finishing.size();
-    }
   }
 }
 
@@ -572,7 +567,7 @@ tls_status tls_server_get_stats(tls_server* S, tls_server_stats* out) {
   out->admitted = S->admitted;
   out->completed = S->completed;
   out->queued = S->queue.size();
-  out->in_flight = S->active;
+  out->in_flight = S->admitted - S->completed;
   out->arena_bytes_in_use = S->alloc.in_use();
   out->arena_bytes = S->budget;
   out->status = S->failed;

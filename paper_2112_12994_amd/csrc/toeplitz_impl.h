@@ -135,8 +135,8 @@ __device__ __forceinline__ void toep_pass_body(
 
   double nrm = 0.0;
   if constexpr ((MODE & PM_MV) != 0) {
-    const T s1 = static_cast<T>(coef[0]);
-    const T s2 = static_cast<T>(coef[1]);
+    // spectrum of X v on this block: Y * V (V pre-scaled by 1/B), in the
+    // half-length complex form, bit-reversed for the inverse transform
 #pragma unroll
     for (int ip = 0; ip < NPAIR; ++ip) {
       const int k = tid + ip * NT;
@@ -152,25 +152,48 @@ __device__ __forceinline__ void toep_pass_body(
       }
     }
     __syncthreads();
+  }
+  // e at the rows of this block (zero outside them) from the inverse
+  // transform value z = ((X v)[2t], (X v)[2t+1]) at packed position t
+  auto emap = [&](int t, cx<T> z, T wa, T wb) -> cx<T> {
+    const T s1 = static_cast<T>(coef[0]);
+    const T s2 = static_cast<T>(coef[1]);
+    T o0 = T(0), o1 = T(0);
+    const int64_t i0 = row0 + 2 * t;
+    if (2 * t >= p - 1 && i0 < m) {
+      o0 = s1 * z.x;
+      if (w_in) o0 += s2 * wa;
+      if (u_out) u_out[i0] = o0;
+    }
+    if (2 * t + 1 >= p - 1 && i0 + 1 < m) {
+      o1 = s1 * z.y;
+      if (w_in) o1 += s2 * wb;
+      if (u_out) u_out[i0 + 1] = o1;
+    }
+    nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
+    return cx<T>{o0, o1};
+  };
+
+  if constexpr ((MODE & PM_MV) != 0) {
     fft_dit<T, true, LGN, NT>(s, tab);
+    // the w terms of all this thread's rows are loaded before any is used
+    // (one memory round trip rather than one per element)
+    T w0[NEL], w1[NEL];
+#pragma unroll
+    for (int e = 0; e < NEL; ++e) {
+      const int64_t i0 = row0 + 2 * (tid + e * NT);
+      w0[e] = (w_in && i0 >= 0 && i0 < m) ? w_in[i0] : T(0);
+      w1[e] = (w_in && i0 + 1 >= 0 && i0 + 1 < m) ? w_in[i0 + 1] : T(0);
+    }
 #pragma unroll
     for (int e = 0; e < NEL; ++e) {
       const int t = tid + e * NT;
-      const cx<T> z = s[swz<T>(t)];
-      T o0 = T(0), o1 = T(0);
-      const int64_t i0 = row0 + 2 * t;
-      if (2 * t >= p - 1 && i0 < m) {
-        o0 = s1 * z.x;
-        if (w_in) o0 += s2 * w_in[i0];
-        if (u_out) u_out[i0] = o0;
-      }
-      if (2 * t + 1 >= p - 1 && i0 + 1 < m) {
-        o1 = s1 * z.y;
-        if (w_in) o1 += s2 * w_in[i0 + 1];
-        if (u_out) u_out[i0 + 1] = o1;
-      }
-      nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
-      if constexpr ((MODE & PM_RMV) != 0) s[swz<T>(t)] = {o0, o1};
+      const cx<T> o = emap(t, s[swz<T>(t)], w0[e], w1[e]);
+      if constexpr ((MODE & PM_RMV) != 0) s[swz<T>(t)] = o;
+    }
+    if constexpr ((MODE & PM_RMV) != 0) {
+      __syncthreads();
+      fft_dif<T, false, LGN, NT>(s, tab);
     }
   } else {
 #pragma unroll
@@ -182,11 +205,13 @@ __device__ __forceinline__ void toep_pass_body(
       nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
       s[swz<T>(t)] = {o0, o1};
     }
+    __syncthreads();
+    fft_dif<T, false, LGN, NT>(s, tab);
   }
 
   if constexpr ((MODE & PM_RMV) != 0) {
-    __syncthreads();
-    fft_dif<T, false, LGN, NT>(s, tab);
+    // block share of X^T e: correlation of the window with e, via
+    // conj(E) * Y per bin pair, then the inverse transform's first p outputs
 #pragma unroll
     for (int ip = 0; ip < NPAIR; ++ip) {
       const int k = tid + ip * NT;
