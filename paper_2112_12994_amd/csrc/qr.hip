@@ -304,67 +304,69 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
     if (threadIdx.x == 0) s_fail = 0;
     __syncthreads();
     double dmin = INFINITY, dmax = 0.0;
-    for (int j = 0; j < q; ++j) {
-      double* pj = pub[j & 1];
-      if (ty == (j & 15)) {
+    // column j = 16 a0 + jj: tiles left of / above tile a0 are final (row j's
+    // multipliers vanish there), so the register tile indices are static
 #pragma unroll
-        for (int a = 0; a < QT; ++a)
-          if (a == (j >> 4))
+    for (int a0 = 0; a0 < QT; ++a0) {
+      for (int jj = 0; jj < 16; ++jj) {
+        const int j = 16 * a0 + jj;
+        if (j >= q) break;
+        double* pj = pub[j & 1];
+        if (ty == jj) {
 #pragma unroll
-            for (int b = 0; b < QT; ++b) pj[tx + 16 * b] = reg[a][b];
+          for (int b = a0; b < QT; ++b) pj[tx + 16 * b] = reg[a0][b];
+        }
+        __syncthreads();
+        double d = pj[j];
+        if (!(d > floor_)) {
+          if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
+          d = floor_;
+        }
+        if (j < rank_cols) {
+          dmin = fmin(dmin, d);
+          dmax = fmax(dmax, d);
+        }
+        // independent operations (shortest dependent chain per column)
+        const double invd = 1.0 / d;
+        const double isd = 1.0 / sqrt(d);
+        const double sd = sqrt(d);
+        // row j of R stays in the registers of its owner (not updated again);
+        // R is written once after the last column
+        if (ty == jj) {
+#pragma unroll
+          for (int b = a0; b < QT; ++b) {
+            const int k = tx + 16 * b;
+            reg[a0][b] = k < j ? 0.0 : (k == j ? sd : reg[a0][b] * isd);
+          }
+        }
+        // rank-one update of the trailing rows and columns (index > j); pub
+        // entries beyond q are zero
+        double fi[QT], fk[QT];
+#pragma unroll
+        for (int a = a0; a < QT; ++a) {
+          const double v = pj[ty + 16 * a] * invd;
+          fi[a] = (a > a0 || ty > jj) ? v : 0.0;
+        }
+#pragma unroll
+        for (int b = a0; b < QT; ++b) {
+          const double v = pj[tx + 16 * b];
+          fk[b] = (b > a0 || tx > jj) ? v : 0.0;
+        }
+#pragma unroll
+        for (int a = a0; a < QT; ++a)
+#pragma unroll
+          for (int b = a0; b < QT; ++b) reg[a][b] -= fi[a] * fk[b];
       }
-      __syncthreads();
-      double d = pj[j];
-      if (!(d > floor_)) {
-        if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
-        d = floor_;
-      }
-      if (j < rank_cols) {
-        dmin = fmin(dmin, d);
-        dmax = fmax(dmax, d);
-      }
-      // independent operations (shortest dependent chain per column)
-      const double invd = 1.0 / d;
-      const double isd = 1.0 / sqrt(d);
-      const double sd = sqrt(d);
-      // row j of R stays in the registers of its owner (rows above j are not
-      // updated again); R is written once after the last column, so no
-      // barrier waits on global stores
-      if (ty == (j & 15)) {
-#pragma unroll
-        for (int a = 0; a < QT; ++a)
-          if (a == (j >> 4))
-#pragma unroll
-            for (int b = 0; b < QT; ++b) {
-              const int k = tx + 16 * b;
-              reg[a][b] = k < j ? 0.0 : (k == j ? sd : reg[a][b] * isd);
-            }
-      }
-      double fi[QT], fk[QT];
-#pragma unroll
-      for (int a = 0; a < QT; ++a) {
-        const int i = ty + 16 * a;
-        fi[a] = (i > j && i < q) ? pj[i] * invd : 0.0;
-      }
-#pragma unroll
-      for (int b = 0; b < QT; ++b) {
-        const int k = tx + 16 * b;
-        fk[b] = (k > j && k < q) ? pj[k] : 0.0;
-      }
-#pragma unroll
-      for (int a = 0; a < QT; ++a)
-#pragma unroll
-        for (int b = 0; b < QT; ++b) reg[a][b] -= fi[a] * fk[b];
     }
     __syncthreads();
     const int failed = s_fail;
-    // R (q x q, row-major): the finished rows from the register tiles
+    // R (q x q, row-major, zero below the diagonal) from the register tiles
 #pragma unroll
     for (int a = 0; a < QT; ++a)
 #pragma unroll
       for (int b = 0; b < QT; ++b) {
         const int i = ty + 16 * a, k = tx + 16 * b;
-        if (i < q && k < q) R[static_cast<size_t>(i) * q + k] = reg[a][b];
+        if (i < q && k < q) R[static_cast<size_t>(i) * q + k] = k < i ? 0.0 : reg[a][b];
       }
     if (!failed || shift_mode != 2 || attempt == 1) {
       if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
@@ -415,35 +417,40 @@ __device__ __forceinline__ void triinv_reg_body(const double* __restrict__ R, in
 #pragma unroll
     for (int b = 0; b < QT; ++b) reg[a][b] = (ty + 16 * a == tx + 16 * b && ty + 16 * a < n) ? 1.0 : 0.0;
   __syncthreads();
-  for (int i = n - 1; i >= 0; --i) {
-    double* pi = pub[i & 1];
-    const double inv = 1.0 / Rs[i * ld + i];
-    if (ty == (i & 15)) {
+  // row i = 16 a0 + ii, from the last: row i of M (nonzero from column i on)
+  // is final once divided by R_ii, then subtracted from the rows above it;
+  // the register tile indices are static
 #pragma unroll
-      for (int a = 0; a < QT; ++a)
-        if (a == (i >> 4))
+  for (int a0 = QT - 1; a0 >= 0; --a0) {
+    for (int ii = 15; ii >= 0; --ii) {
+      const int i = 16 * a0 + ii;
+      if (i >= n) continue;
+      double* pi = pub[i & 1];
+      const double inv = 1.0 / Rs[i * ld + i];
+      if (ty == ii) {
 #pragma unroll
-          for (int b = 0; b < QT; ++b) {
-            reg[a][b] *= inv;
-            pi[tx + 16 * b] = reg[a][b];
-          }
+        for (int b = a0; b < QT; ++b) {
+          reg[a0][b] *= inv;
+          pi[tx + 16 * b] = reg[a0][b];
+        }
+      }
+      __syncthreads();
+      double ri[QT], mc[QT];
+#pragma unroll
+      for (int a = 0; a <= a0; ++a) {
+        const int r = ty + 16 * a;
+        ri[a] = (a < a0 || ty < ii) ? Rs[r * ld + i] : 0.0;
+      }
+#pragma unroll
+      for (int b = a0; b < QT; ++b) {
+        const int c = tx + 16 * b;
+        mc[b] = c < n ? pi[c] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a <= a0; ++a)
+#pragma unroll
+        for (int b = a0; b < QT; ++b) reg[a][b] -= ri[a] * mc[b];
     }
-    __syncthreads();
-    double ri[QT], mc[QT];
-#pragma unroll
-    for (int a = 0; a < QT; ++a) {
-      const int r = ty + 16 * a;
-      ri[a] = r < i ? Rs[r * ld + i] : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b < QT; ++b) {
-      const int c = tx + 16 * b;
-      mc[b] = c < n ? pi[c] : 0.0;
-    }
-#pragma unroll
-    for (int a = 0; a < QT; ++a)
-#pragma unroll
-      for (int b = 0; b < QT; ++b) reg[a][b] -= ri[a] * mc[b];
   }
 #pragma unroll
   for (int a = 0; a < QT; ++a)
