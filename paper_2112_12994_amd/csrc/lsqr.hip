@@ -32,23 +32,33 @@ bool lsqr_step_lds(int lgn, int p) {
 
 namespace {
 
-// Stages the p x p row-major matrix M into LDS rows of odd length ldm: one
-// wavefront per row, 8 rows' loads in flight per wavefront before any store.
+// Stages the p x p (p <= 128) row-major upper triangular matrix M into LDS
+// rows of odd length ldm: wavefront w takes rows w, w + NW, ..., lanes the
+// columns; every load of a thread is issued before its first store (one
+// memory round trip).  Entries below the diagonal are not read.
 template <int NT>
 __device__ __forceinline__ void stage_m(const double* __restrict__ M, int p, int ldm,
                                         double* __restrict__ sM) {
   constexpr int NW = NT / 64;
+  constexpr int RW = (128 + NW - 1) / NW;  // rows per wavefront at p = 128
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int r0 = wid * 8; r0 < p; r0 += NW * 8) {
-    for (int c0 = 0; c0 < p; c0 += 64) {
-      const int c = c0 + lane;
-      double v[8];
+  double v[RW][2];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        v[u] = (r0 + u < p && c < p) ? M[static_cast<size_t>(r0 + u) * p + c] : 0.0;
+  for (int u = 0; u < RW; ++u) {
+    const int r = wid + NW * u;
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        if (r0 + u < p && c < p) sM[(r0 + u) * ldm + c] = v[u];
+    for (int h = 0; h < 2; ++h) {
+      const int c = lane + 64 * h;
+      v[u][h] = (r < p && c < p && c >= r) ? M[static_cast<size_t>(r) * p + c] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RW; ++u) {
+    const int r = wid + NW * u;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int c = lane + 64 * h;
+      if (r < p && c < p) sM[r * ldm + c] = v[u][h];
     }
   }
 }
@@ -105,17 +115,22 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
   double* sM = sv + p;  // MLDS: p x ldm
   const int ldm = p | 1;
   __shared__ double red[NT / 64];
-  if (st->done) return;
+  // the state, g and M are requested together (one memory round trip)
+  const int done_in = st->done;
+  const double gp = g[p];
   const int tid = threadIdx.x;
-  const bool init = st->phase == 0;
-  const double tol = st->tol;
+  const double gt = tid < p ? g[tid] : 0.0;
   if constexpr (MLDS) {
     stage_m<NT>(M, p, ldm, sM);
   }
+  if (done_in) return;
+  const bool init = st->phase == 0;
+  const double tol = st->tol;
 
-  const double beta = sqrt(g[p]);
+  const double beta = sqrt(gp);
   const double invbeta = beta > 0.0 ? 1.0 / beta : 0.0;
-  for (int i = tid; i < p; i += NT) sg[i] = g[i] * invbeta;
+  if (tid < p) sg[tid] = gt * invbeta;
+  for (int i = tid + NT; i < p; i += NT) sg[i] = g[i] * invbeta;
   __syncthreads();
 
   // v~ = M^T (X^T u) - beta v: row j of M^T (= column j of M) is Mt[j][0..j]
