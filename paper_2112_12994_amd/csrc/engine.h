@@ -32,6 +32,7 @@ struct tls_ctx {
   void* pinned = nullptr;    // host staging
   size_t pinned_bytes = 0;
   std::vector<hipEvent_t> events;  // profile = 1: pairs around each Toeplitz pass
+  hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // ends of the LSQR chunks in flight
 };
 
 struct Plan {
@@ -322,6 +323,7 @@ __global__ void zero_kernel(double* x, int n) {
 
 struct HostOut {
   LsqrState st;
+  LsqrState ring[2];  // state snapshots at the ends of the chunks in flight
   RefineState rs;
   double dminmax[4];
   double rr[4];

@@ -92,17 +92,32 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     TLS_CHECK(launch_small_rfft(PREC_F64, pl.lgn, b.phi0, p, p, 1, invB, b.Vhat, ctx->tw, nullptr, s));
     tls_status e = pass(d_y + p);
     if (e != TLS_OK) return e;
+    // Chunks of iterations with one chunk always queued behind the one the
+    // host waits for, so the device never idles on the host's convergence
+    // check; iterations queued after convergence exit at once.
     int launched = 0;
-    for (;;) {
-      for (int it = 0; it < CHUNK_ITERS; ++it) {
-        e = pass(b.u);
-        if (e != TLS_OK) return e;
+    auto chunk = [&](int iters, int slot) -> tls_status {
+      for (int it = 0; it < iters; ++it) {
+        const tls_status ec = pass(b.u);
+        if (ec != TLS_OK) return ec;
       }
-      launched += CHUNK_ITERS;
-      TLS_CHECK(hipMemcpyAsync(&ho->st, b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
-      TLS_CHECK(hipStreamSynchronize(s));
-      if (ho->st.done || launched > max_iter + CHUNK_ITERS) break;
+      launched += iters;
+      TLS_CHECK(hipMemcpyAsync(&ho->ring[slot], b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+      TLS_CHECK(hipEventRecord(ctx->chunk_ev[slot], s));
+      return TLS_OK;
+    };
+    e = chunk(CHUNK_ITERS, 0);
+    if (e == TLS_OK) e = chunk(CHUNK_ITERS, 1);
+    if (e != TLS_OK) return e;
+    for (int k = 0;; ++k) {
+      const int slot = k & 1;
+      TLS_CHECK(hipEventSynchronize(ctx->chunk_ev[slot]));
+      if (ho->ring[slot].done || launched > max_iter + 2 * CHUNK_ITERS) break;
+      e = chunk(2, slot);
+      if (e != TLS_OK) return e;
     }
+    TLS_CHECK(hipMemcpyAsync(&ho->st, b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    TLS_CHECK(hipStreamSynchronize(s));
     if (timed) {
       // passes 0 .. iter did work; later launches in the last chunk exit at once
       double ms = 0.0;
@@ -299,6 +314,8 @@ tls_status tls_create(tls_ctx** out, int device, const tls_options* opt) {
   else
     tls_options_default(&c->opt);
   hipError_t e = hipStreamCreate(&c->stream);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&c->chunk_ev[k], hipEventDisableTiming);
   if (e == hipSuccess) e = build_twiddles(c);
   if (e != hipSuccess) {
     tls_destroy(c);
@@ -318,6 +335,8 @@ void tls_destroy(tls_ctx* c) {
   if (c->tw32) hipFree(c->tw32);
   if (c->consts) hipFree(c->consts);
   for (hipEvent_t e : c->events) hipEventDestroy(e);
+  for (hipEvent_t e : c->chunk_ev)
+    if (e) hipEventDestroy(e);
   if (c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
