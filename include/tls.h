@@ -82,7 +82,10 @@ typedef struct tls_result {
   double lsqr_rnorm;   /* LSQR's own residual estimate */
   double lsqr_arnorm;  /* LSQR's ||A^T r|| estimate */
   int32_t iters;       /* total inner iterations */
-  int32_t istop;       /* stop reason: 1, 2 converged; 3 exact; 4 breakdown; 7 iteration
+  int32_t istop;       /* stop reason: 1, 2 converged; 3 exact; 4 breakdown; 5 the
+                          ||A^T r|| estimate stopped decreasing (30 iterations without
+                          halving: the rounding of the FFT products was reached before
+                          tol; the iterate is returned with TLS_OK); 7 iteration
                           limit.  Mixed precision: 2 when the FP64 refinement converged;
                           when it stopped contracting (conditioning beyond the FP32
                           products' resolution) or hit its step limit, FP64 LSQR finishes

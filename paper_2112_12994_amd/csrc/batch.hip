@@ -128,8 +128,8 @@ List add_items(std::vector<Item>& all, const std::vector<int>& desc,
 ClassKey class_key(const Plan& pl) {
   ClassKey k;
   k.lgn = pl.lgn;
-  k.qt = (pl.q + 15) / 16 <= 8 ? (pl.q + 15) / 16 : 0;
-  k.pt = pl.p <= 128 ? (pl.p + 15) / 16 : 0;
+  k.qt = reg_tiles(pl.q);
+  k.pt = reg_tiles(pl.p);
   k.mlds = lsqr_step_lds(pl.lgn, pl.p) ? 1 : 0;
   return k;
 }

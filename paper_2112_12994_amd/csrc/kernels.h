@@ -69,6 +69,14 @@ size_t qr_scratch_doubles(int crows, int q, int ldq);
 // only when the first refining Cholesky needed the shift (A R^{-1}
 // orthonormal to about 1e-6 or better); 1 = the shifted sweep alone (a
 // rougher R, enough for approximate leverage scores).
+// Register-tile class of the Cholesky (order q) and triangular inverse
+// (order p) kernels: ceil(n/16) for n <= 128 (16 x 16 threads), 100 +
+// ceil(n/32) for 128 < n <= 224 (32 x 32 threads), 0 above (global memory).
+inline int reg_tiles(int n) {
+  if (n <= 128) return (n + 15) / 16;
+  if (n <= 224) return 100 + (n + 31) / 32;
+  return 0;
+}
 hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sweeps, double* R,
                      double* G, double* R1, double* R2, int* status, hipStream_t st);
 hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, double* phi0,
@@ -78,7 +86,8 @@ hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, d
 struct LsqrState {
   double alpha, beta, rhobar, phibar, anorm2, bnorm, rnorm, arnorm, znorm, tol;
   double coef[2];
-  int iter, istop, done, max_iter, phase, pad_;
+  double best_ratio;  // smallest ||A^T r|| / (||A|| ||r||) estimate so far (2x steps)
+  int iter, istop, done, max_iter, phase, best_iter;
 };
 hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const double* g,
                             const double* M, const double* Mt, double* v, double* w, double* z,

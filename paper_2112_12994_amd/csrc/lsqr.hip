@@ -14,13 +14,19 @@
 // Stopping (atol = btol = tol): ||A^T r|| <= tol ||A|| ||r|| (istop 2) or
 // ||r|| <= tol ||r0|| + tol ||A|| ||z|| (istop 1); alpha or beta = 0 (istop 3,
 // exact); a non-finite alpha or beta (istop 4, the last finite iterate is
-// kept); iteration limit (istop 7).
+// kept); no halving of the ||A^T r|| / (||A|| ||r||) estimate in
+// LSQR_STALL consecutive iterations (istop 5: with A = X R^{-1} well
+// conditioned each iteration gains a constant factor in exact arithmetic,
+// so a stall means the rounding of the products has been reached);
+// iteration limit (istop 7).
 #include <math.h>
 
 #include "fft.h"
 #include "kernels.h"
 
 namespace tls {
+
+constexpr int LSQR_STALL = 30;
 
 // The step kernel stages M in LDS when p <= 128 and it fits beside the
 // 2^LGN-point transform buffer.
@@ -63,31 +69,45 @@ __device__ __forceinline__ void stage_m(const double* __restrict__ M, int p, int
   }
 }
 
-// out[r] = sum_{c in [lo(r), p)} Mrow[r][c] x[c] for the rows r of an upper
-// (lo(r) = r) or lower (lo = 0, hi(r) = r + 1) triangular p x p row-major
-// matrix; one wavefront per row, four rows in flight, lanes over columns.
-// Results go to out[r] (lane 0 of the owning wave) via the callback.
+// out[r] = sum_{c in [lo(r), hi(r))} Mrow[r][c] x[c] for the rows r of an
+// upper (lo(r) = r, hi = p) or lower (lo = 0, hi(r) = r + 1) triangular p x p
+// row-major matrix; 8 rows per wavefront, lanes over columns, 8 rows x 2
+// column chunks of loads in flight.  Results go to out[r] (lane 0 of the
+// owning wave) via the callback.
 template <int NT, bool UPPER, typename F>
 __device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, int p,
                                               const double* __restrict__ x, F&& emit) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  constexpr int NW = NT / 64;
-  for (int r0 = wid * 4; r0 < p; r0 += NW * 4) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  constexpr int NW = NT / 64, RU = 8, CU = 2;
+  for (int r0 = wid * RU; r0 < p; r0 += NW * RU) {
+    double acc[RU];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + u;
-      if (r < p) {
-        const double* row = Mrow + static_cast<size_t>(r) * p;
+    for (int u = 0; u < RU; ++u) acc[u] = 0.0;
+    for (int c0 = 0; c0 < p; c0 += 64 * CU) {
+      double mv[RU][CU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int r = r0 + u;
         const int lo = UPPER ? r : 0, hi = UPPER ? p : r + 1;
-        for (int c = lo + lane; c < hi; c += 64) acc[u] += row[c] * x[c];
+#pragma unroll
+        for (int k = 0; k < CU; ++k) {
+          const int c = c0 + 64 * k + lane;
+          mv[u][k] = (r < p && c >= lo && c < hi) ? Mrow[static_cast<size_t>(r) * p + c] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < CU; ++k) {
+        const int c = c0 + 64 * k + lane;
+        const double xc = c < p ? x[c] : 0.0;
+#pragma unroll
+        for (int u = 0; u < RU; ++u) acc[u] += mv[u][k] * xc;
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = wave_sum(acc[u]);
+    for (int u = 0; u < RU; ++u) acc[u] = wave_sum(acc[u]);
     if (lane == 0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < RU; ++u)
         if (r0 + u < p) emit(r0 + u, acc[u]);
     }
   }
@@ -167,6 +187,8 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
   double rhobar = st->rhobar, phibar = st->phibar, anorm2 = st->anorm2, bnorm = st->bnorm;
   double rnorm, arnorm, znorm = st->znorm;
   int iter = st->iter, istop = 0;
+  double best_ratio = st->best_ratio;
+  int best_iter = st->best_iter;
   bool done = false;
   if (init) {
     bnorm = beta;
@@ -180,6 +202,8 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
     rnorm = beta;
     arnorm = alpha * beta;
     znorm = 0.0;
+    best_ratio = INFINITY;
+    best_iter = 0;
     if (arnorm == 0.0) {
       done = true;
       istop = 0;
@@ -213,6 +237,11 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
     arnorm = phibar * alpha * fabs(c);
     const double anorm = sqrt(anorm2);
     iter += 1;
+    const double ratio = arnorm / (anorm * rnorm);
+    if (ratio < 0.5 * best_ratio) {
+      best_ratio = ratio;
+      best_iter = iter;
+    }
     if (arnorm <= tol * anorm * rnorm) {
       done = true;
       istop = 2;
@@ -222,6 +251,9 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
     } else if (alpha == 0.0 || beta == 0.0) {
       done = true;
       istop = 3;
+    } else if (iter - best_iter >= LSQR_STALL) {
+      done = true;
+      istop = 5;
     } else if (iter >= st->max_iter) {
       done = true;
       istop = 7;
@@ -289,6 +321,8 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
     st->rnorm = rnorm;
     st->arnorm = arnorm;
     st->znorm = znorm;
+    st->best_ratio = best_ratio;
+    st->best_iter = best_iter;
     st->iter = iter;
     st->istop = istop;
     st->phase = 1;
@@ -325,7 +359,9 @@ hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, cons
                        st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
                        static_cast<const cx<double>*>(tw.d64));
   } else {
-    hipLaunchKernelGGL((lsqr_step_kernel<LGN, NT, TS, false>), dim3(1), dim3(NT), small, stream, p,
+    // M read from global memory: 16 wavefronts keep more of its rows in flight
+    constexpr int NTG = 1024;
+    hipLaunchKernelGGL((lsqr_step_kernel<LGN, NTG, TS, false>), dim3(1), dim3(NTG), small, stream, p,
                        st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
                        static_cast<const cx<double>*>(tw.d64));
   }
@@ -726,8 +762,8 @@ hipError_t step_b(const Item* fits, int nfits, int pmax, bool mlds, const FitDes
     hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, true>), dim3(nfits), dim3(NT), with_m, s,
                        fits, D, counts, done_list, tab);
   else
-    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, NT, TS, false>), dim3(nfits), dim3(NT), small, s,
-                       fits, D, counts, done_list, tab);
+    hipLaunchKernelGGL((lsqr_step_b_kernel<LGN, 1024, TS, false>), dim3(nfits), dim3(1024), small,
+                       s, fits, D, counts, done_list, tab);
   return hipGetLastError();
 }
 

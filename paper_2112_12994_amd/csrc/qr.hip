@@ -275,19 +275,20 @@ __global__ __launch_bounds__(NT) void triinv_kernel(const double* __restrict__ R
 
 // Cholesky G[:q,:q] (+ shift) = R^T R.  shift_mode 1: always shifted; 2: unshifted, redone
 // with the shift on breakdown.
-template <int QT>
+template <int QT, int TD = 16>
 __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int ldq, int q,
                                                        int crows, int shift_mode,
                                                        double* __restrict__ R,
                                                        int* __restrict__ status, int fail_bit,
                                                        int rank_cols) {
-  __shared__ double pub[2][16 * QT];
-  __shared__ double red[4];
+  constexpr int NT = TD * TD;
+  __shared__ double pub[2][TD * QT];
+  __shared__ double red[NT / 64];
   __shared__ int s_fail;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int tx = threadIdx.x % TD, ty = threadIdx.x / TD;
   double tr = 0.0;
-  for (int i = threadIdx.x; i < q; i += 256) tr += G[static_cast<size_t>(i) * ldq + i];
-  tr = block_sum<256>(tr, red);
+  for (int i = threadIdx.x; i < q; i += NT) tr += G[static_cast<size_t>(i) * ldq + i];
+  tr = block_sum<NT>(tr, red);
   const double shift_amount =
       11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) * 0x1p-53 * tr;
   const double floor_ = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
@@ -298,23 +299,23 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
     for (int a = 0; a < QT; ++a)
 #pragma unroll
       for (int b = 0; b < QT; ++b) {
-        const int i = ty + 16 * a, k = tx + 16 * b;
+        const int i = ty + TD * a, k = tx + TD * b;
         reg[a][b] = (i < q && k < q) ? G[static_cast<size_t>(i) * ldq + k] + (i == k ? sh : 0.0) : 0.0;
       }
     if (threadIdx.x == 0) s_fail = 0;
     __syncthreads();
     double dmin = INFINITY, dmax = 0.0;
-    // column j = 16 a0 + jj: tiles left of / above tile a0 are final (row j's
+    // column j = TD a0 + jj: tiles left of / above tile a0 are final (row j's
     // multipliers vanish there), so the register tile indices are static
 #pragma unroll
     for (int a0 = 0; a0 < QT; ++a0) {
-      for (int jj = 0; jj < 16; ++jj) {
-        const int j = 16 * a0 + jj;
+      for (int jj = 0; jj < TD; ++jj) {
+        const int j = TD * a0 + jj;
         if (j >= q) break;
         double* pj = pub[j & 1];
         if (ty == jj) {
 #pragma unroll
-          for (int b = a0; b < QT; ++b) pj[tx + 16 * b] = reg[a0][b];
+          for (int b = a0; b < QT; ++b) pj[tx + TD * b] = reg[a0][b];
         }
         __syncthreads();
         double d = pj[j];
@@ -335,7 +336,7 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
         if (ty == jj) {
 #pragma unroll
           for (int b = a0; b < QT; ++b) {
-            const int k = tx + 16 * b;
+            const int k = tx + TD * b;
             reg[a0][b] = k < j ? 0.0 : (k == j ? sd : reg[a0][b] * isd);
           }
         }
@@ -344,12 +345,12 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
         double fi[QT], fk[QT];
 #pragma unroll
         for (int a = a0; a < QT; ++a) {
-          const double v = pj[ty + 16 * a] * invd;
+          const double v = pj[ty + TD * a] * invd;
           fi[a] = (a > a0 || ty > jj) ? v : 0.0;
         }
 #pragma unroll
         for (int b = a0; b < QT; ++b) {
-          const double v = pj[tx + 16 * b];
+          const double v = pj[tx + TD * b];
           fk[b] = (b > a0 || tx > jj) ? v : 0.0;
         }
 #pragma unroll
@@ -365,7 +366,7 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
     for (int a = 0; a < QT; ++a)
 #pragma unroll
       for (int b = 0; b < QT; ++b) {
-        const int i = ty + 16 * a, k = tx + 16 * b;
+        const int i = ty + TD * a, k = tx + TD * b;
         if (i < q && k < q) R[static_cast<size_t>(i) * q + k] = k < i ? 0.0 : reg[a][b];
       }
     if (!failed || shift_mode != 2 || attempt == 1) {
@@ -386,6 +387,18 @@ __global__ __launch_bounds__(256) void chol_reg_kernel(const double* __restrict_
                                                        int rank_cols, const int* __restrict__ gate) {
   if (gate && !(*gate & 8)) return;
   chol_reg_body<QT>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols);
+}
+
+// 128 < q <= 224: a 32 x 32 thread grid, QT = ceil(q / 32) register tiles.
+template <int QT>
+__global__ __launch_bounds__(1024) void chol_reg32_kernel(const double* __restrict__ G, int ldq,
+                                                          int q, int crows, int shift_mode,
+                                                          double* __restrict__ R,
+                                                          int* __restrict__ status, int fail_bit,
+                                                          int rank_cols,
+                                                          const int* __restrict__ gate) {
+  if (gate && !(*gate & 8)) return;
+  chol_reg_body<QT, 32>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols);
 }
 
 // M = R[:n,:n]^{-1} (upper; row-major, leading dimension ldm, zero elsewhere
@@ -569,6 +582,75 @@ __global__ __launch_bounds__(64) void rank_test_kernel(const double* __restrict_
 
 // Tail of the preconditioner set-up once M = R[:p,:p]^{-1} exists: Mt = M^T,
 // phi0 = M R[:p, p], rank test on R[:p,:p] (status |= 4).
+// M = R[:n,:n]^{-1} for 128 < n <= 224 on a 32 x 32 thread grid with QT =
+// ceil(n / 32) register tiles; the algorithm of triinv_reg_body, with the
+// columns of R staged in LDS 32 at a time (n x 33 doubles) instead of all of R.
+template <int QT>
+__device__ __forceinline__ void triinv_reg32_body(const double* __restrict__ R, int ldr, int n,
+                                                  double* __restrict__ M, int ldm) {
+  constexpr int TD = 32;
+  extern __shared__ double Rc[];  // rows x 33: columns 32 a0 .. 32 a0 + 31 of R
+  __shared__ double pub[2][TD * QT];
+  const int tx = threadIdx.x % TD, ty = threadIdx.x / TD;
+  double reg[QT][QT];
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < QT; ++b) reg[a][b] = (ty + TD * a == tx + TD * b && ty + TD * a < n) ? 1.0 : 0.0;
+#pragma unroll
+  for (int a0 = QT - 1; a0 >= 0; --a0) {
+    const int rows = min(n, TD * a0 + TD);
+    __syncthreads();  // the previous chunk is no longer read
+    for (int r = ty; r < rows; r += TD) {
+      const int c = TD * a0 + tx;
+      Rc[r * (TD + 1) + tx] = c < n ? R[static_cast<size_t>(r) * ldr + c] : 0.0;
+    }
+    __syncthreads();
+    for (int ii = TD - 1; ii >= 0; --ii) {
+      const int i = TD * a0 + ii;
+      if (i >= n) continue;
+      double* pi = pub[i & 1];
+      const double inv = 1.0 / Rc[i * (TD + 1) + ii];
+      if (ty == ii) {
+#pragma unroll
+        for (int b = a0; b < QT; ++b) {
+          reg[a0][b] *= inv;
+          pi[tx + TD * b] = reg[a0][b];
+        }
+      }
+      __syncthreads();
+      double ri[QT], mc[QT];
+#pragma unroll
+      for (int a = 0; a <= a0; ++a) {
+        const int r = ty + TD * a;
+        ri[a] = ((a < a0 || ty < ii) && r < n) ? Rc[r * (TD + 1) + ii] : 0.0;
+      }
+#pragma unroll
+      for (int b = a0; b < QT; ++b) {
+        const int c = tx + TD * b;
+        mc[b] = c < n ? pi[c] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a <= a0; ++a)
+#pragma unroll
+        for (int b = a0; b < QT; ++b) reg[a][b] -= ri[a] * mc[b];
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < QT; ++b) {
+      const int r = ty + TD * a, c = tx + TD * b;
+      if (r < ldm && c < ldm) M[static_cast<size_t>(r) * ldm + c] = (r < n && c < n) ? reg[a][b] : 0.0;
+    }
+}
+
+template <int QT>
+__global__ __launch_bounds__(1024) void triinv_reg32_kernel(const double* __restrict__ R, int ldr,
+                                                            int n, double* __restrict__ M, int ldm) {
+  triinv_reg32_body<QT>(R, ldr, n, M, ldm);
+}
+
 template <int NT>
 __device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R, int q,
                                                            int p, const double* __restrict__ M,
@@ -637,13 +719,20 @@ void chol_reg_launch(const double* G, int ldq, int q, int crows, int shift_mode,
 // gate: NULL, or run only when bit 8 of *gate is set (the third sweep).
 void chol_launch(const double* G, int ldq, int q, int crows, int shift_mode, double* R, int* status,
                  int fail_bit, int rank_cols, const int* gate, hipStream_t st) {
-  const int qt = (q + 15) / 16;
+  const int qt = reg_tiles(q);
   switch (qt) {
 #define TLS_CHOL_QT(K) \
     case K: chol_reg_launch<K>(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, gate, st); return;
     TLS_CHOL_QT(1) TLS_CHOL_QT(2) TLS_CHOL_QT(3) TLS_CHOL_QT(4)
     TLS_CHOL_QT(5) TLS_CHOL_QT(6) TLS_CHOL_QT(7) TLS_CHOL_QT(8)
 #undef TLS_CHOL_QT
+#define TLS_CHOL_QT32(K)                                                                        \
+  case 100 + K:                                                                                 \
+    hipLaunchKernelGGL((chol_reg32_kernel<K>), dim3(1), dim3(1024), 0, st, G, ldq, q, crows,     \
+                       shift_mode, R, status, fail_bit, rank_cols, gate);                        \
+    return;
+    TLS_CHOL_QT32(5) TLS_CHOL_QT32(6) TLS_CHOL_QT32(7)
+#undef TLS_CHOL_QT32
     default:
       hipLaunchKernelGGL((chol_kernel<256>), dim3(1), dim3(256), 0, st, G, ldq, q, crows, shift_mode,
                          R, status, fail_bit, rank_cols, gate);
@@ -658,10 +747,19 @@ void triinv_reg_launch(const double* R, int ldr, int n, double* M, int ldm, hipS
 
 }  // namespace
 
-// Triangular inverse of R[:n,:n] into M (n <= 128: register tiles; else the
+// Triangular inverse of R[:n,:n] into M (n <= 224: register tiles on 16 x 16
+// or 32 x 32 thread grids; else the
 // global-memory kernel) with leading dimension ldm >= n, zero-padded.
 hipError_t tri_inverse(const double* R, int ldr, int n, double* M, int ldm, hipStream_t st) {
-  switch ((n + 15) / 16) {
+  const size_t shm32 = static_cast<size_t>(n) * 33 * sizeof(double);
+  switch (reg_tiles(n)) {
+#define TLS_TRI32(K)                                                                          \
+  case 100 + K:                                                                               \
+    hipLaunchKernelGGL((triinv_reg32_kernel<K>), dim3(1), dim3(1024), shm32, st, R, ldr, n, M, \
+                       ldm);                                                                  \
+    break;
+    TLS_TRI32(5) TLS_TRI32(6) TLS_TRI32(7)
+#undef TLS_TRI32
     case 1: triinv_reg_launch<1>(R, ldr, n, M, ldm, st); break;
     case 2: triinv_reg_launch<2>(R, ldr, n, M, ldm, st); break;
     case 3: triinv_reg_launch<3>(R, ldr, n, M, ldm, st); break;
@@ -758,7 +856,7 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sw
 hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, double* phi0,
                          int* status, hipStream_t st) {
   if (p < 1 || q < p) return hipErrorInvalidValue;
-  if (p <= 128) {
+  if (reg_tiles(p) != 0) {
     hipError_t e = tri_inverse(R, q, p, M, p, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((triinv_finish_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, Mt, phi0,
@@ -812,6 +910,19 @@ __global__ __launch_bounds__(256) void chol_b_kernel(const Item* __restrict__ it
     chol_body<256>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
 }
 
+// 128 < q <= 224: the 32 x 32 thread grid
+template <int QT>
+__global__ __launch_bounds__(1024) void chol_b32_kernel(const Item* __restrict__ items,
+                                                        const FitDesc* __restrict__ D, int sweep) {
+  const FitDesc& d = D[items[blockIdx.x].fit];
+  if (sweep == 2 && !(d.status[0] & 8)) return;
+  double* R;
+  int* status;
+  int shift_mode, fail_bit;
+  chol_target(d, sweep, &R, &status, &shift_mode, &fail_bit);
+  chol_reg_body<QT, 32>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
+}
+
 __global__ __launch_bounds__(64) void trsm_b_kernel(const Item* __restrict__ items,
                                                     const FitDesc* __restrict__ D, int which) {
   const Item it = items[blockIdx.x];
@@ -843,6 +954,26 @@ __global__ __launch_bounds__(64) void rank_test_b_kernel(const Item* __restrict_
   rank_test_body(d.R, d.q, d.p, stage == 1 ? d.status + 2 : d.status);
 }
 
+// max and min |R_ii| over the first p diagonal entries (one wavefront)
+__device__ __forceinline__ void diag_range(const FitDesc& d) {
+  if (threadIdx.x >= 64) return;
+  double a = 0.0, b = INFINITY;
+  for (int i = threadIdx.x; i < d.p; i += 64) {
+    const double v = fabs(d.R[static_cast<size_t>(i) * d.q + i]);
+    a = fmax(a, v);
+    b = fmin(b, v);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a = fmax(a, __shfl_xor(a, off, 64));
+    b = fmin(b, __shfl_xor(b, off, 64));
+  }
+  if (threadIdx.x == 0) {
+    d.dminmax[0] = a;
+    d.dminmax[1] = b;
+  }
+}
+
 template <int QT>
 __global__ __launch_bounds__(256) void triinv_b_kernel(const Item* __restrict__ items,
                                                        const FitDesc* __restrict__ D, int stage) {
@@ -858,23 +989,21 @@ __global__ __launch_bounds__(256) void triinv_b_kernel(const Item* __restrict__ 
   if (QT > 0)
     triinv_finish_body<256>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
                             stage == 1 ? d.status + 3 : d.status + 1);
-  if (stage == 2 && threadIdx.x < 64) {
-    double a = 0.0, b = INFINITY;
-    for (int i = threadIdx.x; i < d.p; i += 64) {
-      const double v = fabs(d.R[static_cast<size_t>(i) * d.q + i]);
-      a = fmax(a, v);
-      b = fmin(b, v);
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      a = fmax(a, __shfl_xor(a, off, 64));
-      b = fmin(b, __shfl_xor(b, off, 64));
-    }
-    if (threadIdx.x == 0) {
-      d.dminmax[0] = a;
-      d.dminmax[1] = b;
-    }
-  }
+  if (stage == 2) diag_range(d);
+}
+
+// 128 < p <= 224: the 32 x 32 thread grid
+template <int QT>
+__global__ __launch_bounds__(1024) void triinv_b32_kernel(const Item* __restrict__ items,
+                                                          const FitDesc* __restrict__ D, int stage) {
+  const FitDesc& d = D[items[blockIdx.x].fit];
+  double* M = stage == 1 ? d.M0 : d.M;
+  double* Mt = stage == 1 ? d.Mt0 : d.Mt;
+  triinv_reg32_body<QT>(d.R, d.q, d.p, M, d.p);
+  __syncthreads();
+  triinv_finish_body<1024>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
+                           stage == 1 ? d.status + 3 : d.status + 1);
+  if (stage == 2) diag_range(d);
 }
 
 template <int QT>
@@ -887,8 +1016,12 @@ hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtile
   for (int sweep = 0; sweep < sweeps; ++sweep) {
     hipLaunchKernelGGL(gram_b_kernel, dim3(ntiles), dim3(256), 0, st, tiles, D,
                        stage == 2 && sweep == 2 ? 1 : 0);
-    hipLaunchKernelGGL((chol_b_kernel<QT>), dim3(nfits), dim3(256), 0, st, fits, D,
-                       stage == 1 ? -1 : sweep);
+    if constexpr (QT > 100)
+      hipLaunchKernelGGL((chol_b32_kernel<(QT > 100 ? QT - 100 : 1)>), dim3(nfits), dim3(1024), 0, st,
+                         fits, D, stage == 1 ? -1 : sweep);
+    else
+      hipLaunchKernelGGL((chol_b_kernel<QT>), dim3(nfits), dim3(256), 0, st, fits, D,
+                         stage == 1 ? -1 : sweep);
     if (sweep < sweeps - 1)
       hipLaunchKernelGGL(trsm_b_kernel, dim3(nrowtiles), dim3(64), trsm_shm, st, rowtiles, D, sweep);
   }
@@ -903,14 +1036,20 @@ hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtile
 template <int QT>
 hipError_t triinv_b_qt(int stage, const Item* fits, int nfits, int pmax, const FitDesc* D,
                        hipStream_t st) {
-  const size_t shm = QT > 0 ? static_cast<size_t>(pmax) * (pmax + 1) * sizeof(double) : 0;
-  hipLaunchKernelGGL((triinv_b_kernel<QT>), dim3(nfits), dim3(256), shm, st, fits, D, stage);
+  if constexpr (QT > 100) {
+    const size_t shm = static_cast<size_t>(pmax) * 33 * sizeof(double);
+    hipLaunchKernelGGL((triinv_b32_kernel<(QT > 100 ? QT - 100 : 1)>), dim3(nfits), dim3(1024), shm, st,
+                       fits, D, stage);
+  } else {
+    const size_t shm = QT > 0 ? static_cast<size_t>(pmax) * (pmax + 1) * sizeof(double) : 0;
+    hipLaunchKernelGGL((triinv_b_kernel<QT>), dim3(nfits), dim3(256), shm, st, fits, D, stage);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-// qt = ceil(qmax / 16) (register tiles, <= 8) or 0 (global-memory kernels).
+// qt = reg_tiles(q) of every fit of the launch.
 hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const Item* rowtiles,
                        int nrowtiles, const Item* rows, int nrows, const Item* fits, int nfits,
                        int ldqmax, const FitDesc* D, hipStream_t st) {
@@ -925,11 +1064,14 @@ hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const I
     case 6: return qr_b_qt<6>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
     case 7: return qr_b_qt<7>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
     case 8: return qr_b_qt<8>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 105: return qr_b_qt<105>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 106: return qr_b_qt<106>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
+    case 107: return qr_b_qt<107>(stage, tiles, ntiles, rowtiles, nrowtiles, rows, nrows, fits, nfits, ldqmax, D, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-// pt = ceil(pmax / 16) (register tiles, <= 8) or 0 (global-memory kernel).
+// pt = reg_tiles(p) of every fit of the launch.
 hipError_t launch_triinv_b(int stage, int pt, const Item* fits, int nfits, int pmax,
                            const FitDesc* D, hipStream_t st) {
   if (nfits < 1) return hipSuccess;
@@ -943,6 +1085,9 @@ hipError_t launch_triinv_b(int stage, int pt, const Item* fits, int nfits, int p
     case 6: return triinv_b_qt<6>(stage, fits, nfits, pmax, D, st);
     case 7: return triinv_b_qt<7>(stage, fits, nfits, pmax, D, st);
     case 8: return triinv_b_qt<8>(stage, fits, nfits, pmax, D, st);
+    case 105: return triinv_b_qt<105>(stage, fits, nfits, pmax, D, st);
+    case 106: return triinv_b_qt<106>(stage, fits, nfits, pmax, D, st);
+    case 107: return triinv_b_qt<107>(stage, fits, nfits, pmax, D, st);
     default: return hipErrorInvalidValue;
   }
 }

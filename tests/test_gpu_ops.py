@@ -262,7 +262,8 @@ def test_gather(ctx, mode):
         assert np.array_equal(to_np(di), ri)
 
 
-@pytest.mark.parametrize("c_rows,q", [(64, 4), (800, 101), (2000, 65), (400, 200), (4000, 129)])
+@pytest.mark.parametrize("c_rows,q", [(64, 4), (800, 101), (2000, 65), (400, 200), (4000, 129),
+                                        (1792, 224), (1808, 225)])
 def test_qr_matches_lapack(ctx, c_rows, q):
     c = capi()
     torch, dev = torch_dev()
@@ -302,7 +303,7 @@ def test_qr_flags_rank_deficiency(ctx):
     assert s == c.TLS_OK and (st & 6)
 
 
-@pytest.mark.parametrize("p", [1, 3, 37, 100, 300])
+@pytest.mark.parametrize("p", [1, 3, 37, 100, 128, 129, 150, 224, 225, 300])
 def test_triinv(ctx, p):
     c = capi()
     torch, dev = torch_dev()
