@@ -71,7 +71,8 @@ size_t qr_scratch_doubles(int crows, int q, int ldq);
 // rougher R, enough for approximate leverage scores).
 // Register-tile class of the Cholesky (order q) and triangular inverse
 // (order p) kernels: ceil(n/16) for n <= 128 (16 x 16 threads), 100 +
-// ceil(n/32) for 128 < n <= 224 (32 x 32 threads), 0 above (global memory).
+// ceil(n/32) for 128 < n <= 224 (32 x 32 threads), 0 above (blocked kernels on
+// 32 x 32 blocks, one launch per block column).
 inline int reg_tiles(int n) {
   if (n <= 128) return (n + 15) / 16;
   if (n <= 224) return 100 + (n + 31) / 32;
@@ -177,7 +178,7 @@ hipError_t launch_jl_b(const Item* items, int nitems, const FitDesc* D, int kind
 // stage 1: one shifted sweep into R (rank bits to status[2]); stage 2: three
 // sweeps into R (status[0]).  Item lists: Gram tiles (fit, tile of the
 // ldq/16 x ldq/16 grid), 16-row tiles (fit, tile), rows of R (fit, row), and
-// one item per fit.  qt = ceil(qmax/16) <= 8, or 0 for the global-memory kernels.
+// one item per fit.  qt = ceil(qmax/16) <= 8, or 0 for the blocked kernels.
 hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const Item* rowtiles,
                        int nrowtiles, const Item* rows, int nrows, const Item* fits, int nfits,
                        int ldqmax, const FitDesc* D, hipStream_t st);

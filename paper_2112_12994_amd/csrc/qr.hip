@@ -75,77 +75,6 @@ __device__ __forceinline__ bool needs_third_sweep(double dmin, double dmax) {
   return !(dmax <= 1e4 * dmin);
 }
 
-template <int NT>
-__device__ __forceinline__ void chol_body(const double* __restrict__ G, int ldq, int q,
-                                                  int crows, int shift, double* __restrict__ R,
-                                                  int* __restrict__ status, int fail_bit,
-                                                  int rank_cols) {
-  __shared__ double red[NT / 64];
-  __shared__ double s_shift, s_floor;
-  double tr = 0.0;
-  for (int i = threadIdx.x; i < q; i += NT) tr += G[static_cast<size_t>(i) * ldq + i];
-  tr = block_sum<NT>(tr, red);
-  if (threadIdx.x == 0) {
-    s_shift = 11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) * 0x1p-53 * tr;
-    s_floor = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
-  }
-  bool failed = false;
-  double dmin = INFINITY, dmax = 0.0;
-  for (int attempt = (shift == 1 ? 1 : 0); attempt < 2; ++attempt) {
-  failed = false;
-  dmin = INFINITY;
-  dmax = 0.0;
-  for (int e = threadIdx.x; e < q * q; e += NT) {
-    const int i = e / q, k = e % q;
-    R[e] = (k >= i) ? G[static_cast<size_t>(i) * ldq + k] : 0.0;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && attempt)
-    for (int i = 0; i < q; ++i) R[static_cast<size_t>(i) * q + i] += s_shift;
-  __syncthreads();
-  for (int j = 0; j < q; ++j) {
-    double d = R[static_cast<size_t>(j) * q + j];
-    if (!(d > s_floor)) {
-      if (j < rank_cols) failed = true;  // later columns may be exactly dependent (b in range)
-      d = s_floor;
-    }
-    if (j < rank_cols) {
-      dmin = fmin(dmin, d);
-      dmax = fmax(dmax, d);
-    }
-    const double rjj = sqrt(d);
-    const double inv = 1.0 / rjj;
-    __syncthreads();
-    for (int k = j + 1 + threadIdx.x; k < q; k += NT) R[static_cast<size_t>(j) * q + k] *= inv;
-    if (threadIdx.x == 0) R[static_cast<size_t>(j) * q + j] = rjj;
-    __syncthreads();
-    const int w = q - j - 1;
-    const double* rj = R + static_cast<size_t>(j) * q;
-    for (int e = threadIdx.x; e < w * w; e += NT) {
-      const int ii = j + 1 + e / w, kk = j + 1 + e % w;
-      if (kk >= ii) R[static_cast<size_t>(ii) * q + kk] -= rj[ii] * rj[kk];
-    }
-    __syncthreads();
-  }
-  if (!failed || shift != 2 || attempt == 1) {
-    if (shift == 2 && threadIdx.x == 0 && (attempt == 1 || needs_third_sweep(dmin, dmax)))
-      atomicOr(status, 8);
-    break;
-  }
-  __syncthreads();
-  }
-  if (failed && threadIdx.x == 0) atomicOr(status, fail_bit);
-}
-
-template <int NT>
-__global__ __launch_bounds__(NT) void chol_kernel(const double* __restrict__ G, int ldq, int q,
-                                                  int crows, int shift, double* __restrict__ R,
-                                                  int* __restrict__ status, int fail_bit,
-                                                  int rank_cols, const int* __restrict__ gate) {
-  if (gate && !(*gate & 8)) return;
-  chol_body<NT>(G, ldq, q, crows, shift, R, status, fail_bit, rank_cols);
-}
-
 // A <- A R^{-1} on the first q columns (each thread owns one row).
 template <int ROWS, int QMAX>
 __global__ __launch_bounds__(ROWS) void trsm_kernel(double* __restrict__ A, int crows, int ldq,
@@ -202,68 +131,6 @@ __global__ __launch_bounds__(NT) void trmm_kernel(const double* __restrict__ Ra,
                                                   const double* __restrict__ Rb, int q,
                                                   double* __restrict__ C) {
   trmm_body<NT>(Ra, Rb, q, C, blockIdx.x);
-}
-
-// M = R[:p,:p]^{-1} (row-major, upper), Mt = M^T, phi0 = M R[:p, p] (the
-// compressed problem's solution), and the rank test min|R_ii| <= p u max|R_ii|.
-template <int NT>
-__device__ __forceinline__ void triinv_body(const double* __restrict__ R, int q, int p,
-                                                    double* __restrict__ M, double* __restrict__ Mt,
-                                                    double* __restrict__ phi0,
-                                                    int* __restrict__ status) {
-  __shared__ double red[NT / 64];
-  for (int e = threadIdx.x; e < p * p; e += NT) M[e] = 0.0;
-  __syncthreads();
-  for (int i = p - 1; i >= 0; --i) {
-    const double* ri = R + static_cast<size_t>(i) * q;
-    const double inv = 1.0 / ri[i];
-    for (int j = i + threadIdx.x; j < p; j += NT) {
-      double acc = (j == i) ? 1.0 : 0.0;
-      for (int k = i + 1; k <= j; ++k) acc -= ri[k] * M[static_cast<size_t>(k) * p + j];
-      M[static_cast<size_t>(i) * p + j] = acc * inv;
-    }
-    __syncthreads();
-  }
-  {
-    // Mt = M^T: one wavefront per row of M, lanes over its columns
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = wid; i < p; i += NT / 64)
-      for (int j = lane; j < p; j += 64) Mt[static_cast<size_t>(j) * p + i] = M[static_cast<size_t>(i) * p + j];
-  }
-  if (phi0 && q > p) {
-    for (int i = threadIdx.x; i < p; i += NT) {
-      double acc = 0.0;
-      for (int j = i; j < p; ++j) acc += M[static_cast<size_t>(i) * p + j] * R[static_cast<size_t>(j) * q + p];
-      phi0[i] = acc;
-    }
-  }
-  double dmax = 0.0, dmin = INFINITY;
-  for (int i = threadIdx.x; i < p; i += NT) {
-    const double d = fabs(R[static_cast<size_t>(i) * q + i]);
-    dmax = fmax(dmax, d);
-    dmin = fmin(dmin, d);
-  }
-  // block max / min via two sums of one-hot contributions would lose order; use LDS.
-  __shared__ double smax[NT], smin[NT];
-  smax[threadIdx.x] = dmax;
-  smin[threadIdx.x] = dmin;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double a = 0.0, b = INFINITY;
-    for (int t = 0; t < NT; ++t) {
-      a = fmax(a, smax[t]);
-      b = fmin(b, smin[t]);
-    }
-    if (!(b > static_cast<double>(p) * 0x1p-53 * a)) atomicOr(status, 4);
-  }
-}
-
-template <int NT>
-__global__ __launch_bounds__(NT) void triinv_kernel(const double* __restrict__ R, int q, int p,
-                                                    double* __restrict__ M, double* __restrict__ Mt,
-                                                    double* __restrict__ phi0,
-                                                    int* __restrict__ status) {
-  triinv_body<NT>(R, q, p, M, Mt, phi0, status);
 }
 
 // ---- LDS-resident variants for q <= 128 (the whole q x q matrix in LDS) ----
@@ -697,14 +564,536 @@ __global__ __launch_bounds__(NT) void triinv_finish_kernel(const double* __restr
   triinv_finish_body<NT>(R, q, p, M, Mt, phi0, status);
 }
 
+
+// ---- blocked Cholesky and triangular inverse (order above 224) -------------
+// Right-looking Cholesky on 32 x 32 blocks, one launch per block column k:
+// every trailing block (i, j), k < i <= j, is updated by W_ij -= P_i^T P_j
+// with P_i = D_k^T W_ki = R_ki (D_k = R_kk^{-1}, inverted once when R_kk is
+// factored), and the workgroup of block (k+1, k+1) then factors that block
+// and inverts its factor for launch k+1.  Every workgroup recomputes the two
+// panel blocks it needs, so the panel solve needs no launch of its own.  The
+// working matrix W (G plus the shift, padded with the identity to whole
+// blocks), the block inverses and a control record (shift, pivot floor,
+// pivot range, breakdown flag, liveness, retry flag) live in the QR scratch
+// beyond R3 and T.  An unshifted factorisation (shift mode 2) that breaks
+// down sets the retry flag, which enables a second, shifted chain.
+constexpr int NBK = 32;
+
+struct BlkScratch {
+  double* W;
+  double* Dinv;
+  double* ctl;  // shift, floor, dmin, dmax, live, failed, retry
+  int ldw, nbk;
+};
+
+__host__ __device__ inline BlkScratch blk_scratch(double* G, int ldq, int q) {
+  BlkScratch s;
+  s.nbk = (q + NBK - 1) / NBK;
+  s.ldw = s.nbk * NBK;
+  s.W = G + static_cast<size_t>(ldq) * ldq + 2 * static_cast<size_t>(q) * q;
+  s.Dinv = s.W + static_cast<size_t>(s.ldw) * s.ldw;
+  s.ctl = s.Dinv + static_cast<size_t>(s.nbk) * NBK * NBK;
+  return s;
+}
+
+__host__ __device__ inline size_t blk_scratch_doubles(int q) {
+  const size_t nbk = (q + NBK - 1) / NBK;
+  return nbk * NBK * nbk * NBK + nbk * NBK * NBK + 8;
+}
+
+// t-th pair (a, b), 0 <= a <= b < m, in row order
+__device__ __forceinline__ void upper_pair(int t, int m, int* a, int* b) {
+  int r = 0;
+  while (t >= m - r) {
+    t -= m - r;
+    ++r;
+  }
+  *a = r;
+  *b = r + t;
+}
+
+// Lane src's value of x in every lane (src a compile-time constant: two
+// scalar reads, no LDS).
+__device__ __forceinline__ double lane_bcast(double x, int src) {
+  const long long bits = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(bits), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(bits >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Orders one wavefront's LDS writes before its later LDS reads of other
+// lanes' data (a wavefront executes its LDS instructions in program order;
+// this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// One wavefront (wavefront 0 of the workgroup) factors the 32 x 32 block B
+// (LDS, upper part), columns b*32 .. b*32+31 of the whole matrix, by
+// symmetric elimination of the augmented matrix [B | I], lane l holding
+// column l of it in registers: column jj's pivot (clamped to the floor; a
+// breakdown when the column is below rank_cols) gives row jj of the factor
+// U by scaling with its inverse square root, and every later row ii loses
+// U[jj][ii] times that row.  Lane l < 32 ends with column l of U, lane
+// 32 + r with row r of U^{-1} (the eliminated identity is U^{-T}).  R gets
+// the block (zero below the diagonal, clipped to q), Dinv[b] its inverse.
+__device__ __forceinline__ void wave_factor(const double (*B)[NBK + 1], double* pub, int b, int q,
+                                            double floor_, int rank_cols, double* dmin,
+                                            double* dmax, bool* failed, double* __restrict__ R,
+                                            double* __restrict__ Dinv) {
+  const int lane = threadIdx.x & 63;
+  double v[NBK];
+  double mn = *dmin, mx = *dmax;
+  bool fl = *failed;
+#pragma unroll
+  for (int r = 0; r < NBK; ++r) {
+    const double g = B[r][lane & (NBK - 1)];
+    v[r] = lane < NBK ? g : (r == lane - NBK ? 1.0 : 0.0);
+  }
+  // branch-free steps (divergent branches here make the compiler keep far
+  // more values live); row jj's diagonal entry goes to dg
+#pragma unroll
+  for (int jj = 0; jj < NBK; ++jj) {
+    const bool track = b * NBK + jj < rank_cols;
+    double d = lane_bcast(v[jj], jj);
+    const bool ok = d > floor_;
+    fl = fl || (track && !ok);
+    d = ok ? d : floor_;
+    mn = track ? fmin(mn, d) : mn;
+    mx = track ? fmax(mx, d) : mx;
+    const double rjj = sqrt(d);
+    const double inv = 1.0 / rjj;
+    v[jj] *= inv;
+    double* pb = pub + (jj & 1) * 64;
+    pb[lane] = v[jj];
+    pub[128 + jj] = rjj;
+    wave_lds_sync();
+#pragma unroll
+    for (int ii = jj + 1; ii < NBK; ++ii) v[ii] -= pb[ii] * v[jj];
+  }
+  *dmin = mn;
+  *dmax = mx;
+  *failed = fl;
+  if (lane < NBK) {
+    const int k = b * NBK + lane;
+#pragma unroll
+    for (int r = 0; r < NBK; ++r) {
+      const int i = b * NBK + r;
+      if (i < q && k < q)
+        R[static_cast<size_t>(i) * q + k] = r < lane ? v[r] : (r == lane ? pub[128 + r] : 0.0);
+    }
+  } else {
+    double* drow = Dinv + static_cast<size_t>(b) * NBK * NBK + (lane - NBK) * NBK;
+#pragma unroll
+    for (int c = 0; c < NBK; ++c) drow[c] = v[c];
+  }
+}
+
+// One wavefront: X = T^{-1} for the upper-triangular 32 x 32 block T (LDS),
+// lane c < 32 forming column c by right-looking back substitution (T's
+// entries are uniform LDS reads).  X goes to LDS.
+__device__ __forceinline__ void wave_tri_inv(const double (*T)[NBK + 1], double (*X)[NBK + 1]) {
+  const int c = threadIdx.x & (NBK - 1);
+  double acc[NBK];
+#pragma unroll
+  for (int r = 0; r < NBK; ++r) acc[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+  for (int i = NBK - 1; i >= 0; --i) {
+    const double xi = acc[i] / T[i][i];
+    acc[i] = xi;
+#pragma unroll
+    for (int r = 0; r < i; ++r) acc[r] -= T[r][i] * xi;
+  }
+  if ((threadIdx.x & 63) < NBK) {
+#pragma unroll
+    for (int r = 0; r < NBK; ++r) X[r][c] = acc[r];
+  }
+}
+
+// Launch before the panels of one attempt (0: unshifted, shift mode 2 only;
+// 1: shifted): workgroup t copies upper block pair t of G into W and zeroes
+// the mirrored block of R; workgroup 0 also factors block 0 and sets up the
+// control record.  gate: NULL, or run only when bit 8 of *gate is set.
+__device__ __forceinline__ void chol_blk_init_body(const double* __restrict__ G, int ldq, int q,
+                                                   int crows, int shift_mode, int attempt,
+                                                   const int* __restrict__ gate,
+                                                   double* __restrict__ R, int rank_cols,
+                                                   const BlkScratch& s, int t) {
+  __shared__ double red[4];
+  __shared__ double B[NBK][NBK + 1], pub[128 + NBK];
+  double* ctl = s.ctl;
+  if (t >= s.nbk * (s.nbk + 1) / 2) return;
+  const bool gate_on = !gate || (*gate & 8);
+  // attempt 1 after an unshifted attempt runs only on its breakdown
+  const bool live = (attempt == 1 && shift_mode == 2) ? ctl[6] != 0.0 : gate_on;
+  if (!live) {
+    if (t == 0 && threadIdx.x == 0) {
+      ctl[4] = 0.0;
+      if (attempt == 0) ctl[6] = 0.0;
+    }
+    return;
+  }
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < q; i += 256) tr += G[static_cast<size_t>(i) * ldq + i];
+  tr = block_sum<256>(tr, red);
+  const double shift =
+      attempt ? 11.0 * (static_cast<double>(crows) * q + static_cast<double>(q) * (q + 1)) * 0x1p-53 * tr
+              : 0.0;
+  const double floor_ = tr > 0.0 ? tr * 0x1p-104 : 1e-300;
+  int bi, bj;
+  upper_pair(t, s.nbk, &bi, &bj);
+  for (int e = threadIdx.x; e < NBK * NBK; e += 256) {
+    const int r = e / NBK, c = e % NBK;
+    const int i = bi * NBK + r, k = bj * NBK + c;
+    const double v = (i < q && k < q) ? G[static_cast<size_t>(i) * ldq + k] + (i == k ? shift : 0.0)
+                                      : (i == k ? 1.0 : 0.0);
+    s.W[static_cast<size_t>(i) * s.ldw + k] = v;
+    if (t == 0) B[r][c] = v;
+    // block (bj, bi) of R lies below the diagonal
+    const int i2 = bj * NBK + r, k2 = bi * NBK + c;
+    if (bi < bj && i2 < q && k2 < q) R[static_cast<size_t>(i2) * q + k2] = 0.0;
+  }
+  if (t != 0) return;
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  double dmin = INFINITY, dmax = 0.0;
+  bool failed = false;
+  wave_factor(B, pub, 0, q, floor_, rank_cols, &dmin, &dmax, &failed, R, s.Dinv);
+  if (threadIdx.x == 0) {
+    ctl[0] = shift;
+    ctl[1] = floor_;
+    ctl[2] = dmin;
+    ctl[3] = dmax;
+    ctl[4] = 1.0;
+    ctl[5] = failed ? 1.0 : 0.0;
+    if (attempt == 0) ctl[6] = 0.0;
+  }
+}
+
+// Launch k: workgroup t updates trailing block pair t (see above).
+__device__ __forceinline__ void chol_blk_panel_body(int q, double* __restrict__ R, int rank_cols,
+                                                    const BlkScratch& s, int k, int t) {
+  __shared__ double Pi[NBK][NBK + 1], Pj[NBK][NBK + 1];
+  __shared__ double B[NBK][NBK + 1], pub[128 + NBK];
+  const double* ctl = s.ctl;
+  const int m = s.nbk - 1 - k;
+  if (m <= 0 || t >= m * (m + 1) / 2) return;
+  if (ctl[4] == 0.0) return;
+  int a, b;
+  upper_pair(t, m, &a, &b);
+  const int bi = k + 1 + a, bj = k + 1 + b;
+  const bool diag_next = a == 0 && b == 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tr = wv >> 1, tc = wv & 1;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  const double* Dk = s.Dinv + static_cast<size_t>(k) * NBK * NBK;
+  const double* Wk = s.W + static_cast<size_t>(k) * NBK * s.ldw;
+  // P_i, P_j tiles (tr, tc): P[r][c] = sum_s D_k[s][r] W_k[s][c]
+  d4 pi = {0.0, 0.0, 0.0, 0.0}, pj = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s0 = 0; s0 < NBK; s0 += 4) {
+    const int sr = s0 + l4;
+    const double av = Dk[sr * NBK + tr * 16 + l16];
+    const double* wrow = Wk + static_cast<size_t>(sr) * s.ldw;
+    pi = __builtin_amdgcn_mfma_f64_16x16x4f64(av, wrow[bi * NBK + tc * 16 + l16], pi, 0, 0, 0);
+    pj = __builtin_amdgcn_mfma_f64_16x16x4f64(av, wrow[bj * NBK + tc * 16 + l16], pj, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    Pi[tr * 16 + 4 * v + l4][tc * 16 + l16] = pi[v];
+    Pj[tr * 16 + 4 * v + l4][tc * 16 + l16] = pj[v];
+  }
+  __syncthreads();
+  // W_ij -= P_i^T P_j
+  d4 u = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s0 = 0; s0 < NBK; s0 += 4) {
+    const int sr = s0 + l4;
+    u = __builtin_amdgcn_mfma_f64_16x16x4f64(Pi[sr][tr * 16 + l16], Pj[sr][tc * 16 + l16], u, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = tr * 16 + 4 * v + l4, c = tc * 16 + l16;
+    double* w = s.W + static_cast<size_t>(bi * NBK + r) * s.ldw + bj * NBK + c;
+    const double nv = *w - u[v];
+    *w = nv;
+    if (diag_next) B[r][c] = nv;
+  }
+  if (bi == bj) {
+    // R_{k, bi} = P_i
+    for (int e = threadIdx.x; e < NBK * NBK; e += 256) {
+      const int r = e / NBK, c = e % NBK;
+      const int i = k * NBK + r, kk = bi * NBK + c;
+      if (i < q && kk < q) R[static_cast<size_t>(i) * q + kk] = Pi[r][c];
+    }
+  }
+  if (!diag_next) return;
+  __syncthreads();
+  if (wv != 0) return;
+  double dmin = ctl[2], dmax = ctl[3];
+  bool failed = ctl[5] != 0.0;
+  wave_factor(B, pub, bi, q, ctl[1], rank_cols, &dmin, &dmax, &failed, R, s.Dinv);
+  if (lane == 0) {
+    s.ctl[2] = dmin;
+    s.ctl[3] = dmax;
+    s.ctl[5] = failed ? 1.0 : 0.0;
+  }
+}
+
+// After the panels of one attempt (one thread): status bits as the
+// single-workgroup Cholesky sets them, or the retry flag.
+__device__ __forceinline__ void chol_blk_finish_body(int shift_mode, int attempt,
+                                                     int* __restrict__ status, int fail_bit,
+                                                     const BlkScratch& s) {
+  double* ctl = s.ctl;
+  if (threadIdx.x != 0 || ctl[4] == 0.0) return;
+  const bool failed = ctl[5] != 0.0;
+  if (attempt == 0) {
+    if (failed) {
+      ctl[6] = 1.0;
+      return;
+    }
+    if (needs_third_sweep(ctl[2], ctl[3])) atomicOr(status, 8);
+    return;
+  }
+  if (failed) atomicOr(status, fail_bit);
+  if (shift_mode == 2) atomicOr(status, 8);
+}
+
+__global__ __launch_bounds__(256) void chol_blk_init_kernel(double* G, int ldq, int q, int crows,
+                                                            int shift_mode, int attempt,
+                                                            const int* __restrict__ gate,
+                                                            double* __restrict__ R, int rank_cols) {
+  chol_blk_init_body(G, ldq, q, crows, shift_mode, attempt, gate, R, rank_cols,
+                     blk_scratch(G, ldq, q), blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void chol_blk_panel_kernel(double* G, int ldq, int q,
+                                                             double* __restrict__ R, int rank_cols,
+                                                             int k) {
+  chol_blk_panel_body(q, R, rank_cols, blk_scratch(G, ldq, q), k, blockIdx.x);
+}
+
+__global__ __launch_bounds__(64) void chol_blk_finish_kernel(double* G, int ldq, int q,
+                                                             int shift_mode, int attempt,
+                                                             int* __restrict__ status,
+                                                             int fail_bit) {
+  chol_blk_finish_body(shift_mode, attempt, status, fail_bit, blk_scratch(G, ldq, q));
+}
+
+// M = R[:p,:p]^{-1} by 32 x 32 blocks: the diagonal blocks are inverted first
+// (one workgroup each, also kept in Dinv); launch d then forms every block at
+// distance d above the diagonal, M_ij = -D_i sum_{i<k<=j} R_ik M_kj, from
+// blocks of earlier launches.  Blocks beyond p are the identity.
+
+// Diagonal block b of M, and the strictly lower blocks of its block row (zero).
+__device__ __forceinline__ void inv_blk_diag_body(const double* __restrict__ R, int q, int p,
+                                                  double* __restrict__ M,
+                                                  double* __restrict__ Dinv, int b) {
+  __shared__ double B[NBK][NBK + 1], X[NBK][NBK + 1];
+  for (int e = threadIdx.x; e < NBK * NBK; e += 256) {
+    const int r = e / NBK, c = e % NBK;
+    const int i = b * NBK + r, k = b * NBK + c;
+    B[r][c] = (i < p && k < p) ? R[static_cast<size_t>(i) * q + k] : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) wave_tri_inv(B, X);
+  __syncthreads();
+  for (int e = threadIdx.x; e < NBK * NBK; e += 256) {
+    const int r = e / NBK, c = e % NBK;
+    const int i = b * NBK + r, k = b * NBK + c;
+    if (i < p && k < p) M[static_cast<size_t>(i) * p + k] = X[r][c];
+    Dinv[static_cast<size_t>(b) * NBK * NBK + e] = X[r][c];
+  }
+  const int w = b * NBK;
+  for (int e = threadIdx.x; e < NBK * w; e += 256) {
+    const int i = b * NBK + e / w, k = e % w;
+    if (i < p) M[static_cast<size_t>(i) * p + k] = 0.0;
+  }
+}
+
+// Block (i, i + d) of M: wavefront w sums the terms kb = i + 1 + w, i + 5 + w,
+// ... for all four 16 x 16 tiles, the partial sums meet in LDS in a fixed
+// order, and the four wavefronts then apply -D_i, one tile each.
+__device__ __forceinline__ void inv_blk_off_body(const double* __restrict__ R, int q, int p,
+                                                 double* __restrict__ M,
+                                                 const double* __restrict__ Dinv, int d, int i) {
+  __shared__ double S[4][NBK][NBK + 1];
+  const int j = i + d;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int kb = i + 1 + wv; kb <= j; kb += 4) {
+#pragma unroll
+    for (int s0 = 0; s0 < NBK; s0 += 4) {
+      const int col = kb * NBK + s0 + l4;
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int row = i * NBK + a * 16 + l16;
+        av[a] = (row < p && col < p) ? R[static_cast<size_t>(row) * q + col] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int mcol = j * NBK + b * 16 + l16;
+        bv[b] = (col < p && mcol < p) ? M[static_cast<size_t>(col) * p + mcol] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S[wv][a * 16 + 4 * v + l4][b * 16 + l16] = acc[a][b][v];
+  __syncthreads();
+  const int tr = wv >> 1, tc = wv & 1;
+  const double* Di = Dinv + static_cast<size_t>(i) * NBK * NBK;
+  d4 out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s0 = 0; s0 < NBK; s0 += 4) {
+    const int sr = s0 + l4, sc = tc * 16 + l16;
+    const double sv = ((S[0][sr][sc] + S[1][sr][sc]) + S[2][sr][sc]) + S[3][sr][sc];
+    out = __builtin_amdgcn_mfma_f64_16x16x4f64(Di[(tr * 16 + l16) * NBK + sr], sv, out, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int r = i * NBK + tr * 16 + 4 * v + l4;
+    const int mcol = j * NBK + tc * 16 + l16;
+    if (r < p && mcol < p) M[static_cast<size_t>(r) * p + mcol] = -out[v];
+  }
+}
+
+// Mt = M^T by 32 x 32 tiles (t < nbp^2), phi0 = M R[:p, p] by 32-row blocks
+// (nbp workgroups after the tiles), and on the first of those the rank test
+// min|R_ii| <= p u max|R_ii| (status bit 4) and the diagonal range.
+__device__ __forceinline__ void inv_blk_finish_body(const double* __restrict__ R, int q, int p,
+                                                    const double* __restrict__ M,
+                                                    double* __restrict__ Mt,
+                                                    double* __restrict__ phi0,
+                                                    int* __restrict__ status,
+                                                    double* __restrict__ dminmax, int t) {
+  __shared__ double T[NBK][NBK + 1];
+  const int nbp = (p + NBK - 1) / NBK;
+  if (t < nbp * nbp) {
+    const int bi = t / nbp, bj = t % nbp;
+    for (int e = threadIdx.x; e < NBK * NBK; e += 256) {
+      const int r = e / NBK, c = e % NBK;
+      const int i = bi * NBK + r, k = bj * NBK + c;
+      T[r][c] = (i < p && k < p) ? M[static_cast<size_t>(i) * p + k] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NBK * NBK; e += 256) {
+      const int r = e / NBK, c = e % NBK;
+      const int i = bj * NBK + r, k = bi * NBK + c;
+      if (i < p && k < p) Mt[static_cast<size_t>(i) * p + k] = T[c][r];
+    }
+    return;
+  }
+  const int rb = t - nbp * nbp;
+  if (rb >= nbp) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (phi0 && q > p) {
+    for (int rr = 0; rr < NBK / 4; ++rr) {
+      const int i = rb * NBK + wv * (NBK / 4) + rr;
+      if (i >= p) break;
+      double acc = 0.0;
+      for (int j = i + lane; j < p; j += 64)
+        acc += M[static_cast<size_t>(i) * p + j] * R[static_cast<size_t>(j) * q + p];
+      acc = wave_sum(acc);
+      if (lane == 0) phi0[i] = acc;
+    }
+  }
+  if (rb == 0 && wv == 0) {
+    double a = 0.0, b = INFINITY;
+    for (int i = lane; i < p; i += 64) {
+      const double d = fabs(R[static_cast<size_t>(i) * q + i]);
+      a = fmax(a, d);
+      b = fmin(b, d);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a = fmax(a, __shfl_xor(a, off, 64));
+      b = fmin(b, __shfl_xor(b, off, 64));
+    }
+    if (lane == 0) {
+      if (status && !(b > static_cast<double>(p) * 0x1p-53 * a)) atomicOr(status, 4);
+      if (dminmax) {
+        dminmax[0] = a;
+        dminmax[1] = b;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void inv_blk_diag_kernel(const double* __restrict__ R, int q,
+                                                           int p, double* __restrict__ M,
+                                                           double* __restrict__ Dinv) {
+  inv_blk_diag_body(R, q, p, M, Dinv, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void inv_blk_off_kernel(const double* __restrict__ R, int q,
+                                                          int p, double* __restrict__ M,
+                                                          const double* __restrict__ Dinv, int d) {
+  inv_blk_off_body(R, q, p, M, Dinv, d, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void inv_blk_finish_kernel(const double* __restrict__ R, int q,
+                                                             int p, const double* __restrict__ M,
+                                                             double* __restrict__ Mt,
+                                                             double* __restrict__ phi0,
+                                                             int* __restrict__ status) {
+  inv_blk_finish_body(R, q, p, M, Mt, phi0, status, nullptr, blockIdx.x);
+}
+
+void chol_blk_launch(double* G, int ldq, int q, int crows, int shift_mode, double* R, int* status,
+                     int fail_bit, int rank_cols, const int* gate, hipStream_t st) {
+  const int nbk = (q + NBK - 1) / NBK;
+  for (int attempt = shift_mode == 1 ? 1 : 0; attempt < 2; ++attempt) {
+    hipLaunchKernelGGL(chol_blk_init_kernel, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, st, G, ldq, q,
+                       crows, shift_mode, attempt, gate, R, rank_cols);
+    for (int k = 0; k + 1 < nbk; ++k) {
+      const int m = nbk - 1 - k;
+      hipLaunchKernelGGL(chol_blk_panel_kernel, dim3(m * (m + 1) / 2), dim3(256), 0, st, G, ldq, q,
+                         R, rank_cols, k);
+    }
+    hipLaunchKernelGGL(chol_blk_finish_kernel, dim3(1), dim3(64), 0, st, G, ldq, q, shift_mode,
+                       attempt, status, fail_bit);
+  }
+}
+
+// Mt doubles as the store of the diagonal block inverses until the finish.
+void inv_blk_launch(const double* R, int q, int p, double* M, double* Mt, double* phi0,
+                    int* status, hipStream_t st) {
+  const int nbp = (p + NBK - 1) / NBK;
+  hipLaunchKernelGGL(inv_blk_diag_kernel, dim3(nbp), dim3(256), 0, st, R, q, p, M, Mt);
+  for (int d = 1; d < nbp; ++d)
+    hipLaunchKernelGGL(inv_blk_off_kernel, dim3(nbp - d), dim3(256), 0, st, R, q, p, M, Mt, d);
+  hipLaunchKernelGGL(inv_blk_finish_kernel, dim3(nbp * nbp + nbp), dim3(256), 0, st, R, q, p, M, Mt,
+                     phi0, status);
+}
+
 }  // namespace
 
-// Scratch: G must hold ldq*ldq + 2*q*q doubles (Gram matrix, then R3 and
-// R3 R2); for q <= 128 also ldq*ldq (inverse) + crows*ldq (second copy of A)
-// beyond that, i.e. qr_scratch_doubles(crows, q, ldq) in total.
+// Scratch: G holds ldq*ldq + 2*q*q doubles (Gram matrix, then R3 and R3 R2)
+// and, for the blocked Cholesky (q above 224), its working matrix, block
+// inverses and control record beyond that.
 size_t qr_scratch_doubles(int crows, int q, int ldq) {
-  return static_cast<size_t>(ldq) * ldq * 2 + 2 * static_cast<size_t>(q) * q +
-         static_cast<size_t>(crows) * ldq;
+  (void)crows;
+  return static_cast<size_t>(ldq) * ldq + 2 * static_cast<size_t>(q) * q +
+         (reg_tiles(q) == 0 ? blk_scratch_doubles(q) : 0);
 }
 
 namespace {
@@ -717,7 +1106,7 @@ void chol_reg_launch(const double* G, int ldq, int q, int crows, int shift_mode,
 }
 
 // gate: NULL, or run only when bit 8 of *gate is set (the third sweep).
-void chol_launch(const double* G, int ldq, int q, int crows, int shift_mode, double* R, int* status,
+void chol_launch(double* G, int ldq, int q, int crows, int shift_mode, double* R, int* status,
                  int fail_bit, int rank_cols, const int* gate, hipStream_t st) {
   const int qt = reg_tiles(q);
   switch (qt) {
@@ -734,8 +1123,7 @@ void chol_launch(const double* G, int ldq, int q, int crows, int shift_mode, dou
     TLS_CHOL_QT32(5) TLS_CHOL_QT32(6) TLS_CHOL_QT32(7)
 #undef TLS_CHOL_QT32
     default:
-      hipLaunchKernelGGL((chol_kernel<256>), dim3(1), dim3(256), 0, st, G, ldq, q, crows, shift_mode,
-                         R, status, fail_bit, rank_cols, gate);
+      chol_blk_launch(G, ldq, q, crows, shift_mode, R, status, fail_bit, rank_cols, gate, st);
   }
 }
 
@@ -747,9 +1135,9 @@ void triinv_reg_launch(const double* R, int ldr, int n, double* M, int ldm, hipS
 
 }  // namespace
 
-// Triangular inverse of R[:n,:n] into M (n <= 224: register tiles on 16 x 16
-// or 32 x 32 thread grids; else the
-// global-memory kernel) with leading dimension ldm >= n, zero-padded.
+// Triangular inverse of R[:n,:n] into M with leading dimension ldm >= n,
+// zero-padded, for n <= 224 (register tiles on 16 x 16 or 32 x 32 thread
+// grids; larger orders take the blocked kernels through launch_triinv).
 hipError_t tri_inverse(const double* R, int ldr, int n, double* M, int ldm, hipStream_t st) {
   const size_t shm32 = static_cast<size_t>(n) * 33 * sizeof(double);
   switch (reg_tiles(n)) {
@@ -862,8 +1250,7 @@ hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, d
     hipLaunchKernelGGL((triinv_finish_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, Mt, phi0,
                        status);
   } else {
-    hipLaunchKernelGGL((triinv_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, Mt, phi0,
-                       status);
+    inv_blk_launch(R, q, p, M, Mt, phi0, status, st);
   }
   return hipGetLastError();
 }
@@ -904,10 +1291,7 @@ __global__ __launch_bounds__(256) void chol_b_kernel(const Item* __restrict__ it
   int* status;
   int shift_mode, fail_bit;
   chol_target(d, sweep, &R, &status, &shift_mode, &fail_bit);
-  if (QT > 0)
-    chol_reg_body<(QT > 0 ? QT : 1)>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
-  else
-    chol_body<256>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
+  chol_reg_body<QT>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
 }
 
 // 128 < q <= 224: the 32 x 32 thread grid
@@ -980,15 +1364,10 @@ __global__ __launch_bounds__(256) void triinv_b_kernel(const Item* __restrict__ 
   const FitDesc& d = D[items[blockIdx.x].fit];
   double* M = stage == 1 ? d.M0 : d.M;
   double* Mt = stage == 1 ? d.Mt0 : d.Mt;
-  if (QT > 0)
-    triinv_reg_body<(QT > 0 ? QT : 1)>(d.R, d.q, d.p, M, d.p);
-  else
-    triinv_body<256>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
-                     stage == 1 ? d.status + 3 : d.status + 1);
+  triinv_reg_body<QT>(d.R, d.q, d.p, M, d.p);
   __syncthreads();
-  if (QT > 0)
-    triinv_finish_body<256>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
-                            stage == 1 ? d.status + 3 : d.status + 1);
+  triinv_finish_body<256>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
+                          stage == 1 ? d.status + 3 : d.status + 1);
   if (stage == 2) diag_range(d);
 }
 
@@ -1006,6 +1385,116 @@ __global__ __launch_bounds__(1024) void triinv_b32_kernel(const Item* __restrict
   if (stage == 2) diag_range(d);
 }
 
+// Blocked Cholesky and inverse of the fits of a launch with q (or p) above
+// 224: workgroup w serves fit items[w / per] with index w % per; indices
+// beyond that fit's block count return at once.
+__global__ __launch_bounds__(256) void chol_blk_init_b_kernel(const Item* __restrict__ items,
+                                                              const FitDesc* __restrict__ D,
+                                                              int sweep, int attempt, int per) {
+  const FitDesc& d = D[items[blockIdx.x / per].fit];
+  double* R;
+  int* status;
+  int shift_mode, fail_bit;
+  chol_target(d, sweep, &R, &status, &shift_mode, &fail_bit);
+  chol_blk_init_body(d.G, d.ldq, d.q, d.crows, shift_mode, attempt, sweep == 2 ? d.status : nullptr,
+                     R, d.p, blk_scratch(d.G, d.ldq, d.q), blockIdx.x % per);
+}
+
+__global__ __launch_bounds__(256) void chol_blk_panel_b_kernel(const Item* __restrict__ items,
+                                                               const FitDesc* __restrict__ D,
+                                                               int sweep, int k, int per) {
+  const FitDesc& d = D[items[blockIdx.x / per].fit];
+  double* R;
+  int* status;
+  int shift_mode, fail_bit;
+  chol_target(d, sweep, &R, &status, &shift_mode, &fail_bit);
+  chol_blk_panel_body(d.q, R, d.p, blk_scratch(d.G, d.ldq, d.q), k, blockIdx.x % per);
+}
+
+__global__ __launch_bounds__(64) void chol_blk_finish_b_kernel(const Item* __restrict__ items,
+                                                               const FitDesc* __restrict__ D,
+                                                               int sweep, int attempt) {
+  const FitDesc& d = D[items[blockIdx.x].fit];
+  double* R;
+  int* status;
+  int shift_mode, fail_bit;
+  chol_target(d, sweep, &R, &status, &shift_mode, &fail_bit);
+  chol_blk_finish_body(shift_mode, attempt, status, fail_bit, blk_scratch(d.G, d.ldq, d.q));
+}
+
+void chol_blk_b(const Item* fits, int nfits, int ldqmax, int sweep, const FitDesc* D,
+                hipStream_t st) {
+  const int nbk = (ldqmax + NBK - 1) / NBK;
+  const int per0 = nbk * (nbk + 1) / 2;
+  for (int attempt = sweep <= 0 ? 1 : 0; attempt < 2; ++attempt) {
+    hipLaunchKernelGGL(chol_blk_init_b_kernel, dim3(nfits * per0), dim3(256), 0, st, fits, D, sweep,
+                       attempt, per0);
+    for (int k = 0; k + 1 < nbk; ++k) {
+      const int m = nbk - 1 - k;
+      const int per = m * (m + 1) / 2;
+      hipLaunchKernelGGL(chol_blk_panel_b_kernel, dim3(nfits * per), dim3(256), 0, st, fits, D,
+                         sweep, k, per);
+    }
+    hipLaunchKernelGGL(chol_blk_finish_b_kernel, dim3(nfits), dim3(64), 0, st, fits, D, sweep,
+                       attempt);
+  }
+}
+
+__device__ __forceinline__ void inv_target(const FitDesc& d, int stage, double** M, double** Mt,
+                                           double** phi0, int** status) {
+  *M = stage == 1 ? d.M0 : d.M;
+  *Mt = stage == 1 ? d.Mt0 : d.Mt;
+  *phi0 = stage == 1 ? nullptr : d.phi0;
+  *status = stage == 1 ? d.status + 3 : d.status + 1;
+}
+
+__global__ __launch_bounds__(256) void inv_blk_diag_b_kernel(const Item* __restrict__ items,
+                                                             const FitDesc* __restrict__ D,
+                                                             int stage, int per) {
+  const FitDesc& d = D[items[blockIdx.x / per].fit];
+  const int b = blockIdx.x % per;
+  if (b >= (d.p + NBK - 1) / NBK) return;
+  double *M, *Mt, *phi0;
+  int* status;
+  inv_target(d, stage, &M, &Mt, &phi0, &status);
+  inv_blk_diag_body(d.R, d.q, d.p, M, Mt, b);
+}
+
+__global__ __launch_bounds__(256) void inv_blk_off_b_kernel(const Item* __restrict__ items,
+                                                            const FitDesc* __restrict__ D,
+                                                            int stage, int dist, int per) {
+  const FitDesc& d = D[items[blockIdx.x / per].fit];
+  const int i = blockIdx.x % per;
+  if (i + dist >= (d.p + NBK - 1) / NBK) return;
+  double *M, *Mt, *phi0;
+  int* status;
+  inv_target(d, stage, &M, &Mt, &phi0, &status);
+  inv_blk_off_body(d.R, d.q, d.p, M, Mt, dist, i);
+}
+
+__global__ __launch_bounds__(256) void inv_blk_finish_b_kernel(const Item* __restrict__ items,
+                                                               const FitDesc* __restrict__ D,
+                                                               int stage, int per) {
+  const FitDesc& d = D[items[blockIdx.x / per].fit];
+  double *M, *Mt, *phi0;
+  int* status;
+  inv_target(d, stage, &M, &Mt, &phi0, &status);
+  inv_blk_finish_body(d.R, d.q, d.p, M, Mt, phi0, status, stage == 2 ? d.dminmax : nullptr,
+                      blockIdx.x % per);
+}
+
+void inv_blk_b(int stage, const Item* fits, int nfits, int pmax, const FitDesc* D,
+               hipStream_t st) {
+  const int nbp = (pmax + NBK - 1) / NBK;
+  hipLaunchKernelGGL(inv_blk_diag_b_kernel, dim3(nfits * nbp), dim3(256), 0, st, fits, D, stage, nbp);
+  for (int dist = 1; dist < nbp; ++dist)
+    hipLaunchKernelGGL(inv_blk_off_b_kernel, dim3(nfits * (nbp - dist)), dim3(256), 0, st, fits, D,
+                       stage, dist, nbp - dist);
+  const int per = nbp * nbp + nbp;
+  hipLaunchKernelGGL(inv_blk_finish_b_kernel, dim3(nfits * per), dim3(256), 0, st, fits, D, stage,
+                     per);
+}
+
 template <int QT>
 hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtiles, int nrowtiles,
                    const Item* rows, int nrows, const Item* fits, int nfits, int ldqmax,
@@ -1019,9 +1508,11 @@ hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtile
     if constexpr (QT > 100)
       hipLaunchKernelGGL((chol_b32_kernel<(QT > 100 ? QT - 100 : 1)>), dim3(nfits), dim3(1024), 0, st,
                          fits, D, stage == 1 ? -1 : sweep);
-    else
+    else if constexpr (QT > 0)
       hipLaunchKernelGGL((chol_b_kernel<QT>), dim3(nfits), dim3(256), 0, st, fits, D,
                          stage == 1 ? -1 : sweep);
+    else
+      chol_blk_b(fits, nfits, ldqmax, stage == 1 ? -1 : sweep, D, st);
     if (sweep < sweeps - 1)
       hipLaunchKernelGGL(trsm_b_kernel, dim3(nrowtiles), dim3(64), trsm_shm, st, rowtiles, D, sweep);
   }
@@ -1040,9 +1531,11 @@ hipError_t triinv_b_qt(int stage, const Item* fits, int nfits, int pmax, const F
     const size_t shm = static_cast<size_t>(pmax) * 33 * sizeof(double);
     hipLaunchKernelGGL((triinv_b32_kernel<(QT > 100 ? QT - 100 : 1)>), dim3(nfits), dim3(1024), shm, st,
                        fits, D, stage);
-  } else {
-    const size_t shm = QT > 0 ? static_cast<size_t>(pmax) * (pmax + 1) * sizeof(double) : 0;
+  } else if constexpr (QT > 0) {
+    const size_t shm = static_cast<size_t>(pmax) * (pmax + 1) * sizeof(double);
     hipLaunchKernelGGL((triinv_b_kernel<QT>), dim3(nfits), dim3(256), shm, st, fits, D, stage);
+  } else {
+    inv_blk_b(stage, fits, nfits, pmax, D, st);
   }
   return hipGetLastError();
 }

@@ -54,13 +54,14 @@ def test_batch_device_equals_single(ctx):
 
 
 def test_batch_orders_across_kernel_limits(ctx):
-    """p = 127, 128 (q = 129: the global-memory Cholesky), 150 and 200 (no LDS
-    staging of M), with small orders in the same batch."""
+    """p = 127, 128 (q = 129: the 32 x 32 register grid), 150 and 200 (no LDS
+    staging of M), 250 and 300 (blocked Cholesky and inverse with different
+    block counts), with small orders in the same batch."""
     say("batch wide orders")
     rng = np.random.default_rng(13)
-    ps = [3, 127, 128, 150, 200, 16, 128]
+    ps = [3, 127, 128, 150, 200, 16, 128, 250, 300, 260]
     ys = [synth.ar_series(int(n), p, rng, 0.3, 0.85)
-          for n, p in zip([5000, 40000, 30000, 50000, 60000, 9000, 20000], ps)]
+          for n, p in zip([5000, 40000, 30000, 50000, 60000, 9000, 20000, 60000, 70000, 50000], ps)]
     s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=40)
     assert s == capi().TLS_OK
     _same_as_single(ctx, ys, ps, outs, 40, device=True)

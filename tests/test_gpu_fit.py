@@ -58,7 +58,8 @@ def test_ar3_config(ctx):
 
 
 @pytest.mark.parametrize("p,n,seed", [(1, 5000, 0), (2, 777, 1), (8, 20000, 2), (40, 65536, 3),
-                                      (100, 65536, 0), (64, 262144, 4), (200, 100000, 5)])
+                                      (100, 65536, 0), (64, 262144, 4), (200, 100000, 5),
+                                      (300, 100000, 6), (500, 60000, 7)])
 def test_fit_f64_matches_oracle(ctx, p, n, seed):
     say("fit f64", p, n, seed)
     rng = np.random.default_rng(seed)

@@ -262,18 +262,21 @@ def test_gather(ctx, mode):
         assert np.array_equal(to_np(di), ri)
 
 
-@pytest.mark.parametrize("c_rows,q", [(64, 4), (800, 101), (2000, 65), (400, 200), (4000, 129),
-                                        (1792, 224), (1808, 225)])
-def test_qr_matches_lapack(ctx, c_rows, q):
+@pytest.mark.parametrize("c_rows,q,decades", [(64, 4, 3), (800, 101, 3), (2000, 65, 3), (400, 200, 3),
+                                                (4000, 129, 3), (1792, 224, 3), (1808, 225, 3),
+                                                (2400, 257, 3), (4008, 501, 3), (3000, 300, 7),
+                                                (8200, 1025, 3)])
+def test_qr_matches_lapack(ctx, c_rows, q, decades):
+    """Orders above 224 take the blocked Cholesky (32 x 32 blocks): whole and
+    ragged last blocks, and columns scaled over 7 decades."""
     c = capi()
     torch, dev = torch_dev()
-    say("qr", c_rows, q)
+    say("qr", c_rows, q, decades)
     rng = np.random.default_rng(12)
     ldq = (q + 15) // 16 * 16
     crows = (c_rows + 15) // 16 * 16
     A = np.zeros((crows, ldq))
-    # moderately conditioned columns
-    A[:c_rows, :q] = rng.standard_normal((c_rows, q)) @ np.diag(np.logspace(0, 3, q))
+    A[:c_rows, :q] = rng.standard_normal((c_rows, q)) @ np.diag(np.logspace(0, decades, q))
     dA = to_dev(A.ravel())
     dR = torch.zeros(q * q, dtype=torch.float64, device=dev)
     s, st = ctx.op_qr(dA, crows, q, ldq, dR)
@@ -303,7 +306,7 @@ def test_qr_flags_rank_deficiency(ctx):
     assert s == c.TLS_OK and (st & 6)
 
 
-@pytest.mark.parametrize("p", [1, 3, 37, 100, 128, 129, 150, 224, 225, 300])
+@pytest.mark.parametrize("p", [1, 3, 37, 100, 128, 129, 150, 224, 225, 256, 300, 500, 1024])
 def test_triinv(ctx, p):
     c = capi()
     torch, dev = torch_dev()
