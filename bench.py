@@ -257,21 +257,37 @@ def batch_bench(args, torch, synth, capi):
     torch.cuda.synchronize()
     ctx = capi.Context(0, gamma=8, precision=prec, block_lg=args.block_lg)
     stream = torch.cuda.current_stream()
+    tuned = {}
+    if args.block_lg == 0:
+        # block lengths from the autotuner (device measurements, before the timed region)
+        t0 = time.perf_counter()
+        pmin, pmax = min(ps), max(ps)
+        nmin, nmax = min(f.y.size for f in fits), max(f.y.size for f in fits)
+        ctx.autotune(prec, pmin, pmax, max(nmin, 2 * pmax + 1), nmax)
+        table = ctx.tuning()
+        for f in fits:
+            lg = int(table[capi.tune_index(prec, f.p, f.y.size - f.p)])
+            key = "p<=%d,m<=2^%d" % (1 << max(0, (f.p - 1).bit_length()),
+                                     max(0, (f.y.size - f.p - 1).bit_length()))
+            tuned[key] = 1 << lg if lg else None
+        print(f"[bench] autotuned in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         s, outs = ctx.fit_batch_device(dys, ps, 1e-10, stream=stream)
     torch.cuda.synchronize()
     print(f"[bench] warmup done: status {capi.status_string(s) if args.warmup else None}",
           file=sys.stderr, flush=True)
-    pass_ms = 0.0
-    pass_count = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s, outs = ctx.fit_batch_device(dys, ps, 1e-10, stream=stream, profile=1)
-        pass_ms += outs[0]["pass_ms"]
-        pass_count += outs[0]["pass_count"]
+        s, outs = ctx.fit_batch_device(dys, ps, 1e-10, stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     print(f"[bench] timed {args.steps} batches in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    # one more call with every launch of the dominant pass bracketed by HIP
+    # events (graphs off while profiling): the pass's average launch time
+    _, pouts = ctx.fit_batch_device(dys, ps, 1e-10, stream=stream, profile=1)
+    torch.cuda.synchronize()
+    pass_ms = pouts[0]["pass_ms"]
+    pass_count = pouts[0]["pass_count"]
     # algorithmic bytes of the dominant pass over one batch: per fit, bytes of
     # one pass times the passes that did work for it
     tot_bytes = 0.0
@@ -282,7 +298,7 @@ def batch_bench(args, torch, synth, capi):
         else:
             tot_bytes += (nb * (B // 2) * 8 + (B // 2) * 8 + (f.p + 1) * nb * 8) * o["iters"]
     avg_launch_s = pass_ms / max(pass_count, 1) / 1e3
-    achieved = tot_bytes * args.steps / (pass_ms / 1e3) / 1e9 if pass_ms else 0.0
+    achieved = tot_bytes / (pass_ms / 1e3) / 1e9 if pass_ms else 0.0
     statuses = [o["status"] for o in outs]
 
     # plain path: one synchronous FP64 fit per series
@@ -340,6 +356,9 @@ def batch_bench(args, torch, synth, capi):
         "config": {"workload": WORKLOAD_TEXT["batch"], "fits_per_step": len(fits),
                    "samples_per_step": int(sum(f.y.size for f in fits)),
                    "precision": args.precision, "fft_blocks_used": classes,
+                   "fft_block_source": "autotuner" if tuned else "block_lg=%d" % args.block_lg,
+                   "autotuned_blocks": tuned or None,
+                   "graphs": "each chunk of LSQR / inner steps of a class replayed as a HIP graph",
                    "status": capi.status_string(s),
                    "fit_statuses": {capi.status_string(k): statuses.count(k) for k in set(statuses)},
                    "median_iters": int(np.median([o["iters"] for o in outs]))},
@@ -348,8 +367,9 @@ def batch_bench(args, torch, synth, capi):
                      "traffic_source": "no counter profile for the batched pass",
                      "kernel": "toep_b_kernel (batched Toeplitz pass, "
                                + ("FP64 fused LSQR pass)" if prec == 0 else "FP32 normal-equation pass)"),
-                     "bytes_per_launch": tot_bytes / max(pass_count / args.steps, 1),
-                     "avg_launch_us": avg_launch_s * 1e6, "launches_timed": pass_count},
+                     "bytes_per_launch": tot_bytes / max(pass_count, 1),
+                     "avg_launch_us": avg_launch_s * 1e6, "launches_timed": pass_count,
+                     "timed_in": "one extra batched call with profile=1 after the timed steps"},
         "plain_fp64_per_series": {"value": plain, "unit": "solves/s",
                                   "what": "one synchronous FP64 tls_fit_device per series"},
         "accuracy": {"oracle_sample": len(errs), "gate": gate, "by_kappa": strata},

@@ -60,6 +60,13 @@ const char* tls_status_string(tls_status s);
 #define TLS_JL_SRHT 0     /* k x p subsampled randomized Hadamard map (Definition 2.4, Algorithm 1) */
 #define TLS_JL_GAUSS 1    /* k x p Gaussian map, entries N(0, 1/k) (eq. (glev)) */
 
+/* Autotuned block lengths: one log2 B per (precision, order bucket ceil(log2 p),
+ * length bucket ceil(log2 (n - p)), clamped to 40); 0 = not tuned. */
+#define TLS_TUNE_PRECS 2
+#define TLS_TUNE_PBUCKETS 11
+#define TLS_TUNE_MBUCKETS 41
+#define TLS_TUNE_ENTRIES (TLS_TUNE_PRECS * TLS_TUNE_PBUCKETS * TLS_TUNE_MBUCKETS)
+
 typedef struct tls_options {
   int32_t precision;   /* TLS_PREC_* (default F64) */
   int32_t sketch;      /* TLS_SKETCH_* (default LEVERAGE) */
@@ -73,7 +80,11 @@ typedef struct tls_options {
   int32_t profile;     /* 1: time every Toeplitz pass with HIP events (tls_result.pass_ms) */
   uint64_t seed;       /* random seed (default 0) */
   uint64_t request_id; /* selects the random streams of one fit (default 0) */
-  int64_t reserved[4];
+  int32_t no_graph;    /* batched calls: 1 launches every step directly; 0 (default) captures
+                          each chunk of LSQR (or inner refinement) steps of a launch class once
+                          as a HIP graph and replays it (not while profile = 1) */
+  int32_t reserved0;
+  int64_t reserved[3];
 } tls_options;
 
 typedef struct tls_result {
@@ -163,6 +174,33 @@ tls_status tls_fit_batch_device(tls_ctx* ctx, int32_t count, const double* const
                                 const tls_options* opt, void* stream, double* coef_packed,
                                 const int64_t* coef_offset, tls_result* out,
                                 tls_status* per_fit_status);
+
+/* ---- block-length autotuner ---------------------------------------------------
+ * The FFT block length B of the overlap-save products (eq. (xphi) through
+ * circulant embedding) trades FFT work per sample against the p - 1 samples
+ * each block re-reads.  tls_autotune measures, on the device and on synthetic
+ * data, the per-iteration pass of the given precision (FP64: the fused LSQR
+ * pass; mixed: the FP32 normal-equation pass; each with its column sums) at
+ * every admissible B (2p <= B <= 2^14, B no longer than needed for m) for the
+ * order buckets covering [p_min, p_max] (measured at p = 2^bucket) and the
+ * length buckets covering [n_min, n_max] (measured at m = 2^bucket, at most
+ * 2^26; longer buckets take the 2^26 result), and records the fastest in the
+ * context.  Fits on this context whose options leave block_lg = 0 then take
+ * B from the table (or the built-in rule where the table has no entry), so
+ * single, batched and served fits of one context agree bit for bit.  Uses the
+ * context's stream and workspace and synchronises; *entries (optional)
+ * receives the number of table entries written.  TLS_EINVAL for a bad
+ * precision or range (1 <= p_min <= p_max <= 1024, 2 p_max + 1 <= n_min <=
+ * n_max). */
+tls_status tls_autotune(tls_ctx* ctx, int32_t precision, int32_t p_min, int32_t p_max,
+                        int64_t n_min, int64_t n_max, int32_t* entries);
+/* Copy the table out (table: TLS_TUNE_ENTRIES bytes, index
+ * (prec * TLS_TUNE_PBUCKETS + pbucket) * TLS_TUNE_MBUCKETS + mbucket, prec 0 =
+ * F64, 1 = mixed), or replace it, so that a tuned choice can be stored and
+ * reused by another process with identical results.  tls_set_tuning rejects
+ * (TLS_EINVAL, table unchanged) entries other than 0 or 7..14. */
+tls_status tls_get_tuning(const tls_ctx* ctx, int8_t* table);
+tls_status tls_set_tuning(tls_ctx* ctx, const int8_t* table);
 
 /* ---- served continuous batching ----------------------------------------------
  * A server admits fit requests as they arrive and runs them to completion on

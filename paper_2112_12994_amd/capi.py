@@ -23,6 +23,15 @@ JL_SRHT, JL_GAUSS = 0, 1
 
 # Philox stream numbers of one fit (include/tls.h, tls_op_* documentation)
 RNG_UNIFORM_ROWS, RNG_SRHT_SIGNS, RNG_SRHT_ROWS, RNG_LEVERAGE, RNG_GAUSS = range(5)
+TUNE_PRECS, TUNE_PBUCKETS, TUNE_MBUCKETS = 2, 11, 41
+TUNE_ENTRIES = TUNE_PRECS * TUNE_PBUCKETS * TUNE_MBUCKETS
+
+
+def tune_index(precision: int, p: int, m: int) -> int:
+    """Index of the table entry that a fit of order p and m = n - p rows uses."""
+    pb = max(0, (int(p) - 1).bit_length())
+    mb = min(max(0, (int(m) - 1).bit_length()), TUNE_MBUCKETS - 1)
+    return ((1 if precision == PREC_MIXED else 0) * TUNE_PBUCKETS + pb) * TUNE_MBUCKETS + mb
 
 
 class TlsOptions(ctypes.Structure):
@@ -39,7 +48,9 @@ class TlsOptions(ctypes.Structure):
         ("profile", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("request_id", ctypes.c_uint64),
-        ("reserved", ctypes.c_int64 * 4),
+        ("no_graph", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("reserved", ctypes.c_int64 * 3),
     ]
 
 
@@ -148,6 +159,9 @@ _SIGS = {
     "tls_wait": (_i32, [_vp, _u64, _dp, _c.POINTER(TlsResult), _c.POINTER(_i32)]),
     "tls_server_get_stats": (_i32, [_vp, _c.POINTER(TlsServerStats)]),
     "tls_server_destroy": (None, [_vp]),
+    "tls_autotune": (_i32, [_ctxp, _i32, _i32, _i32, _i64, _i64, _c.POINTER(_i32)]),
+    "tls_get_tuning": (_i32, [_ctxp, _c.POINTER(_c.c_int8)]),
+    "tls_set_tuning": (_i32, [_ctxp, _c.POINTER(_c.c_int8)]),
     "tls_num_blocks": (_i64, [_i64, _i32, _i32]),
     "tls_op_spectra": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _vp, _vp]),
     "tls_op_toeplitz": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _dp, _c.c_double, _c.c_double,
@@ -361,6 +375,28 @@ class Context:
                   stream=None):
         return lib.tls_op_gather(self._h, _ptr(d_y), d_y.numel(), p, mode, _ptr(d_idx),
                                  _ptr(d_scale), c, crows, ldq, _ptr(d_A), seed, fit, _stream(stream))
+
+    def autotune(self, precision: int, p_min: int, p_max: int, n_min: int, n_max: int) -> int:
+        """Measure block lengths on the device; returns the table entries written."""
+        k = _i32(0)
+        _check(lib.tls_autotune(self._h, precision, p_min, p_max, n_min, n_max, ctypes.byref(k)),
+               "tls_autotune")
+        return k.value
+
+    def tuning(self):
+        """The autotuned table, int8[TLS_TUNE_ENTRIES] (0 = not tuned)."""
+        import numpy as np
+        t = np.zeros(TUNE_ENTRIES, dtype=np.int8)
+        _check(lib.tls_get_tuning(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))),
+               "tls_get_tuning")
+        return t
+
+    def set_tuning(self, table) -> int:
+        import numpy as np
+        t = np.ascontiguousarray(table, dtype=np.int8)
+        if t.size != TUNE_ENTRIES:
+            raise ValueError("tuning table must have %d entries" % TUNE_ENTRIES)
+        return lib.tls_set_tuning(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
 
     def op_qr(self, d_A, crows, q, ldq, d_R, stream=None):
         st = _i32(0)

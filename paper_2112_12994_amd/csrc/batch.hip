@@ -16,7 +16,10 @@
 // the second the batched driver behind tls_fit_batch*.
 #include "engine.h"
 
+#include <atomic>
+#include <functional>
 #include <map>
+#include <thread>
 
 namespace {
 
@@ -232,12 +235,12 @@ hipError_t batch_zero_ints(int* x, int n, hipStream_t s) {
 
 hipError_t PassTimer::begin(hipStream_t s) {
   hipEvent_t a = nullptr, b = nullptr;
-  hipError_t e = pass_events(ctx, n, &a, &b);
+  hipError_t e = pool_events(*pool, n, &a, &b);
   return e == hipSuccess ? hipEventRecord(a, s) : e;
 }
 
 hipError_t PassTimer::end(hipStream_t s) {
-  hipEvent_t b = ctx->events[2 * n + 1];
+  hipEvent_t b = (*pool)[2 * n + 1];
   ++n;
   return hipEventRecord(b, s);
 }
@@ -246,7 +249,7 @@ hipError_t PassTimer::total_ms(double* ms) const {
   double t = 0.0;
   for (size_t k = 0; k < n; ++k) {
     float x = 0.f;
-    hipError_t e = hipEventElapsedTime(&x, ctx->events[2 * k], ctx->events[2 * k + 1]);
+    hipError_t e = hipEventElapsedTime(&x, (*pool)[2 * k], (*pool)[2 * k + 1]);
     if (e != hipSuccess) return e;
     t += x;
   }
@@ -255,6 +258,40 @@ hipError_t PassTimer::total_ms(double* ms) const {
 }
 
 #define L_(lst) I + l.lst.off, l.lst.n
+
+namespace {
+
+// A fixed sequence of launches on one stream, captured as a HIP graph on
+// first use and replayed afterwards (or launched directly when use = false).
+// The sequences captured here hold kernel launches only.
+struct GraphSlot {
+  hipGraphExec_t exec = nullptr;
+};
+
+tls_status run_graph(GraphSlot& g, bool use, hipStream_t s,
+                     const std::function<tls_status()>& body) {
+  if (!use) return body();
+  if (!g.exec) {
+    TLS_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const tls_status e = body();
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &graph);
+    if (e != TLS_OK || ec != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return e != TLS_OK ? e : hip_status(ec);
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      g.exec = nullptr;
+      return hip_status(ei);
+    }
+  }
+  TLS_CHECK(hipGraphLaunch(g.exec, s));
+  return TLS_OK;
+}
+
+}  // namespace
 
 tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, const Item* I,
                        const ClassLists& l, FitDesc* D, const tls_options& o, hipStream_t s) {
@@ -366,7 +403,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
           st[i] = TLS_EINVAL;
           break;
         }
-    if (st[i] == TLS_OK) st[i] = make_plan(n[i], p[i], o, &plans[i]);
+    if (st[i] == TLS_OK) st[i] = make_plan(n[i], p[i], o, &plans[i], ctx);
     if (st[i] != TLS_OK) continue;
     if (plans[i].ldq > BATCH_LDQ_MAX) {
       singles.push_back(i);
@@ -463,71 +500,135 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     TLS_CHECK(batch_zero_ints(counts, static_cast<int>(ncounts), s));
   }
   // profile = 1: event pairs around every launch of the dominant pass (FP64:
-  // the fused LSQR pass; mixed: the FP32 normal-equation pass)
-  PassTimer timer{ctx, 0};
-  PassTimer* tm = o.profile ? &timer : nullptr;
-  for (const Cls& c : classes) {
+  // the fused LSQR pass; mixed: the FP32 normal-equation pass), one pool per
+  // class stream
+  const bool graphs = !o.no_graph && !o.profile;
+
+  // One class from setup to residual on stream cs; hc: 4 pinned ints.
+  auto run_class = [&](const Cls& c, hipStream_t cs, int* hc, PassTimer* tm) -> tls_status {
     const ClassLists& l = c.l;
     int* cnt = counts + 4 * (&c - classes.data());
+    const hipStream_t s = cs;
     const tls_status e0 = setup_class(ctx, c.key, c.pmax, c.ldqmax, I, l, D, o, s);
     if (e0 != TLS_OK) return e0;
+    GraphSlot g_lsqr, g_inner, g_inner_tail;
+    auto done = [&](tls_status e) {
+      // the graphs' last launches finished at the host's final check
+      for (GraphSlot* g : {&g_lsqr, &g_inner, &g_inner_tail})
+        if (g->exec) hipGraphExecDestroy(g->exec);
+      return e;
+    };
 
     // FP64 LSQR over the class from phi0 (fits already done skip every
-    // step); cnt[0] holds the number of finished fits.
+    // step); cnt[0] holds the number of finished fits.  Every chunk after
+    // the first is the same sequence of launches: a graph when enabled.
     auto lsqr64 = [&](PassTimer* t) -> tls_status {
       for (int launched = 0;; launched += B_CHUNK_ITERS) {
-        for (int it = 0; it < B_CHUNK_ITERS; ++it) {
-          const tls_status e = lsqr_step_class(ctx, c.key.lgn, c.pmax, c.key.mlds != 0,
-                                               launched == 0 && it == 0, L_(blocks), L_(cols),
-                                               L_(fits), D, cnt, nullptr, t, s);
-          if (e != TLS_OK) return e;
-        }
-        TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        auto chunk = [&, launched]() -> tls_status {
+          for (int it = 0; it < B_CHUNK_ITERS; ++it) {
+            const tls_status e = lsqr_step_class(ctx, c.key.lgn, c.pmax, c.key.mlds != 0,
+                                                 launched == 0 && it == 0, L_(blocks), L_(cols),
+                                                 L_(fits), D, cnt, nullptr, t, s);
+            if (e != TLS_OK) return e;
+          }
+          return TLS_OK;
+        };
+        const tls_status e = run_graph(g_lsqr, graphs && launched > 0, s, chunk);
+        if (e != TLS_OK) return e;
+        TLS_CHECK(hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         TLS_CHECK(hipStreamSynchronize(s));
-        if (hcounts[0] >= c.count || launched > max_iter) break;
+        if (hc[0] >= c.count || launched > max_iter) break;
       }
       return TLS_OK;
     };
     if (!mixed) {
       const tls_status e = lsqr64(tm);
-      if (e != TLS_OK) return e;
+      if (e != TLS_OK) return done(e);
     } else {
       for (int outer = 0; outer <= max_refine; ++outer) {
-        TLS_CHECK(batch_zero_ints(cnt, 2, s));
-        TLS_CHECK(launch_small_rfft_b(PREC_F64, c.key.lgn, 2, L_(fits), D, ctx->tw, s));
-        TLS_CHECK(launch_toep_b(PREC_F64, c.key.lgn, BP_OUTER64, L_(blocks), D, ctx->consts,
-                                ctx->tw, s));
-        TLS_CHECK(launch_colsum_b(1, L_(cols), D, s));
-        TLS_CHECK(launch_refine_outer_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s));
+        if (hipError_t he = batch_zero_ints(cnt, 2, s)) return done(hip_status(he));
+        auto outer_step = [&]() -> hipError_t {
+          hipError_t he = launch_small_rfft_b(PREC_F64, c.key.lgn, 2, L_(fits), D, ctx->tw, s);
+          if (!he) he = launch_toep_b(PREC_F64, c.key.lgn, BP_OUTER64, L_(blocks), D, ctx->consts,
+                                      ctx->tw, s);
+          if (!he) he = launch_colsum_b(1, L_(cols), D, s);
+          if (!he) he = launch_refine_outer_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s);
+          return he;
+        };
+        if (hipError_t he = outer_step()) return done(hip_status(he));
         for (int it = 0; it < inner_max; it += B_INNER_CHUNK) {
-          for (int k = it; k < std::min(inner_max, it + B_INNER_CHUNK); ++k) {
-            if (tm) TLS_CHECK(tm->begin(s));
-            TLS_CHECK(launch_toep_b(PREC_F32, c.key.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
-                                    ctx->tw, s));
-            if (tm) TLS_CHECK(tm->end(s));
-            TLS_CHECK(launch_colsum_b(2, L_(cols), D, s));
-            TLS_CHECK(launch_refine_cg_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s));
-          }
-          TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-          TLS_CHECK(hipStreamSynchronize(s));
-          if (hcounts[1] >= c.count) break;
+          const int kend = std::min(inner_max, it + B_INNER_CHUNK);
+          auto inner = [&, it, kend]() -> tls_status {
+            for (int k = it; k < kend; ++k) {
+              if (tm) TLS_CHECK(tm->begin(s));
+              TLS_CHECK(launch_toep_b(PREC_F32, c.key.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
+                                      ctx->tw, s));
+              if (tm) TLS_CHECK(tm->end(s));
+              TLS_CHECK(launch_colsum_b(2, L_(cols), D, s));
+              TLS_CHECK(launch_refine_cg_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s));
+            }
+            return TLS_OK;
+          };
+          const tls_status e = run_graph(kend - it == B_INNER_CHUNK ? g_inner : g_inner_tail,
+                                         graphs, s, inner);
+          if (e != TLS_OK) return done(e);
+          if (hipError_t he = hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s))
+            return done(hip_status(he));
+          if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
+          if (hc[1] >= c.count) break;
         }
-        if (hcounts[0] >= c.count) break;
+        if (hc[0] >= c.count) break;
       }
       // FP64 finish for the fits whose refinement stopped short
-      TLS_CHECK(batch_zero_ints(cnt, 4, s));
+      if (hipError_t he = batch_zero_ints(cnt, 4, s)) return done(hip_status(he));
       hipLaunchKernelGGL(fallback_prep_b_kernel, dim3(l.fits.n), dim3(64), 0, s, I + l.fits.off,
                          D, cnt);
-      TLS_CHECK(hipGetLastError());
-      TLS_CHECK(hipMemcpyAsync(hcounts, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-      TLS_CHECK(hipStreamSynchronize(s));
-      if (hcounts[0] < c.count) {
+      if (hipError_t he = hipGetLastError()) return done(hip_status(he));
+      if (hipError_t he = hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s))
+        return done(hip_status(he));
+      if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
+      if (hc[0] < c.count) {
         const tls_status e = lsqr64(nullptr);
-        if (e != TLS_OK) return e;
+        if (e != TLS_OK) return done(e);
       }
     }
-    const tls_status e1 = residual_class(L_(rblocks), L_(fits), c.pmax, D, s);
-    if (e1 != TLS_OK) return e1;
+    return done(residual_class(L_(rblocks), L_(fits), c.pmax, D, s));
+  };
+
+  // The classes are independent: up to BATCH_STREAMS of them run at once,
+  // each on a stream of its own driven by a host thread; the caller's stream
+  // orders them after the uploads above and waits for all of them.
+  const int nw = std::min<int>(static_cast<int>(classes.size()), BATCH_STREAMS);
+  std::vector<PassTimer> timers(BATCH_STREAMS);
+  if (nw > 0) {
+    TLS_CHECK(ensure_batch_streams(ctx));
+    TLS_CHECK(hipEventRecord(ctx->bready, s));
+    std::atomic<int> next{0};
+    std::vector<tls_status> wst(nw, TLS_OK);
+    auto worker = [&](int w) {
+      hipStream_t cs = ctx->bstream[w];
+      timers[w].pool = &ctx->bevents[w];
+      if (hipSetDevice(ctx->device) != hipSuccess || hipStreamWaitEvent(cs, ctx->bready, 0)) {
+        wst[w] = TLS_EDEVICE;
+      } else {
+        for (int k; (k = next.fetch_add(1)) < static_cast<int>(classes.size());) {
+          const tls_status e = run_class(classes[k], cs, hcounts + 8 * w,
+                                         o.profile ? &timers[w] : nullptr);
+          if (e != TLS_OK) {
+            wst[w] = e;
+            break;
+          }
+        }
+      }
+      if (hipEventRecord(ctx->bdone[w], cs) != hipSuccess && wst[w] == TLS_OK) wst[w] = TLS_EDEVICE;
+    };
+    std::vector<std::thread> th;
+    for (int w = 1; w < nw; ++w) th.emplace_back(worker, w);
+    worker(0);
+    for (auto& t : th) t.join();
+    for (int w = 0; w < nw; ++w) TLS_CHECK(hipStreamWaitEvent(s, ctx->bdone[w], 0));
+    for (int w = 0; w < nw; ++w)
+      if (wst[w] != TLS_OK) return wst[w];
   }
   if (nb > 0) {
     TLS_CHECK(collect_b(I + collect_off, nb, D, mixed ? 1 : 0, dcoef, drec, s));
@@ -538,7 +639,13 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
   const auto t1 = std::chrono::steady_clock::now();
   const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   double pass_ms = 0.0;
-  TLS_CHECK(timer.total_ms(&pass_ms));
+  int pass_count = 0;
+  for (int w = 0; w < nw; ++w) {
+    double x = 0.0;
+    TLS_CHECK(timers[w].total_ms(&x));
+    pass_ms += x;
+    pass_count += static_cast<int>(timers[w].n);
+  }
 
   int64_t off = 0;
   for (int j = 0; j < nb; ++j) {
@@ -550,7 +657,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     if (res) {
       record_result(hrec[j], pl, ms, &res[i]);
       res[i].pass_ms = pass_ms;  // the whole batch's launches of the dominant pass
-      res[i].pass_count = static_cast<int>(timer.n);
+      res[i].pass_count = pass_count;
     }
     st[i] = record_status(hrec[j], coef, pl.p);
   }

@@ -19,6 +19,9 @@
 
 using namespace tls;
 
+// Streams on which a batched call runs its launch classes concurrently.
+constexpr int BATCH_STREAMS = 4;
+
 struct tls_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -33,6 +36,14 @@ struct tls_ctx {
   size_t pinned_bytes = 0;
   std::vector<hipEvent_t> events;  // profile = 1: pairs around each Toeplitz pass
   hipEvent_t chunk_ev[2] = {nullptr, nullptr};  // ends of the LSQR chunks in flight
+  // batched calls: one stream per concurrent launch class, its end event,
+  // the event the class streams wait on, and profile = 1 event pools
+  hipStream_t bstream[BATCH_STREAMS] = {};
+  hipEvent_t bdone[BATCH_STREAMS] = {};
+  hipEvent_t bready = nullptr;
+  std::vector<hipEvent_t> bevents[BATCH_STREAMS];
+  // autotuned log2 block lengths, [precision][order bucket][length bucket]; 0 = not tuned
+  int8_t tune[TLS_TUNE_PRECS][TLS_TUNE_PBUCKETS][TLS_TUNE_MBUCKETS] = {};
 };
 
 struct Plan {
@@ -162,16 +173,32 @@ hipError_t ensure_pinned(tls_ctx* c, size_t bytes) {
 }
 
 // Event pair `i` (created on first use; kept for the context's lifetime).
-hipError_t pass_events(tls_ctx* c, size_t i, hipEvent_t* a, hipEvent_t* b) {
-  while (c->events.size() < 2 * (i + 1)) {
+// Event pair i of a pool (created on first use, kept for later calls).
+hipError_t pool_events(std::vector<hipEvent_t>& pool, size_t i, hipEvent_t* a, hipEvent_t* b) {
+  while (pool.size() < 2 * (i + 1)) {
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return r;
-    c->events.push_back(e);
+    pool.push_back(e);
   }
-  *a = c->events[2 * i];
-  *b = c->events[2 * i + 1];
+  *a = pool[2 * i];
+  *b = pool[2 * i + 1];
   return hipSuccess;
+}
+
+hipError_t pass_events(tls_ctx* c, size_t i, hipEvent_t* a, hipEvent_t* b) {
+  return pool_events(c->events, i, a, b);
+}
+
+// The batched call's class streams and events (created on first use).
+hipError_t ensure_batch_streams(tls_ctx* c) {
+  if (c->bready) return hipSuccess;
+  for (int w = 0; w < BATCH_STREAMS; ++w) {
+    hipError_t e = hipStreamCreate(&c->bstream[w]);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->bdone[w], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventCreateWithFlags(&c->bready, hipEventDisableTiming);
 }
 
 hipStream_t pick_stream(tls_ctx* c, void* s) {
@@ -193,12 +220,29 @@ int auto_block(int p, int64_t m) {
   return lg;
 }
 
-tls_status make_plan(int64_t n, int p, const tls_options& o, Plan* pl) {
+// Buckets of the autotuner's table: order bucket ceil(log2 p), length bucket
+// ceil(log2 m) (clamped to the table).
+int tune_pbucket(int p) { return ilog2(p); }
+int tune_mbucket(int64_t m) {
+  const int b = ilog2(m);
+  return b < TLS_TUNE_MBUCKETS ? b : TLS_TUNE_MBUCKETS - 1;
+}
+int tune_prec(int precision) { return precision == TLS_PREC_MIXED ? 1 : 0; }
+
+// ctx: NULL, or the context whose autotuned table supplies the block length
+// when the options leave it automatic.
+tls_status make_plan(int64_t n, int p, const tls_options& o, Plan* pl,
+                     const tls_ctx* ctx = nullptr) {
   pl->n = n;
   pl->p = p;
   pl->m = n - p;
   pl->prec = o.precision;
-  int lg = o.block_lg > 0 ? o.block_lg : auto_block(p, pl->m);
+  int lg = o.block_lg;
+  if (lg <= 0 && ctx) {
+    lg = ctx->tune[tune_prec(o.precision)][tune_pbucket(p)][tune_mbucket(pl->m)];
+    if (lg > 0 && (1 << lg) < 2 * p) lg = 0;
+  }
+  if (lg <= 0) lg = auto_block(p, pl->m);
   if (lg < 7 || lg > LG_BMAX) return TLS_EUNSUPPORTED;
   pl->B = 1 << lg;
   if (pl->B < 2 * p) return TLS_EUNSUPPORTED;
@@ -387,7 +431,7 @@ hipError_t batch_zero_ints(int* x, int n, hipStream_t s);
 
 // Event pairs around launches of the dominant pass (profile = 1).
 struct PassTimer {
-  tls_ctx* ctx = nullptr;
+  std::vector<hipEvent_t>* pool = nullptr;
   size_t n = 0;
   hipError_t begin(hipStream_t s);
   hipError_t end(hipStream_t s);

@@ -329,6 +329,15 @@ void tls_destroy(tls_ctx* c) {
   if (!c) return;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
+  for (int w = 0; w < BATCH_STREAMS; ++w) {
+    if (c->bstream[w]) {
+      hipStreamSynchronize(c->bstream[w]);
+      hipStreamDestroy(c->bstream[w]);
+    }
+    if (c->bdone[w]) hipEventDestroy(c->bdone[w]);
+    for (hipEvent_t e : c->bevents[w]) hipEventDestroy(e);
+  }
+  if (c->bready) hipEventDestroy(c->bready);
   if (c->ws) hipFree(c->ws);
   if (c->pinned) hipHostFree(c->pinned);
   if (c->tw64) hipFree(c->tw64);
@@ -350,7 +359,7 @@ tls_status tls_fit_ex(tls_ctx* ctx, const double* series, int64_t n, int32_t p, 
   for (int64_t i = 0; i < n; ++i)
     if (!isfinite(series[i])) return TLS_EINVAL;
   Plan pl;
-  st = make_plan(n, p, o, &pl);
+  st = make_plan(n, p, o, &pl, ctx);
   if (st != TLS_OK) return st;
   if (hipSetDevice(ctx->device) != hipSuccess) return TLS_EDEVICE;
   return run_fit(ctx, pl, o, nullptr, series, tol, ctx->stream, coef, out);
@@ -363,7 +372,7 @@ tls_status tls_fit_device(tls_ctx* ctx, const double* d_series, int64_t n, int32
   tls_status st = validate(n, p, tol, o);
   if (st != TLS_OK) return st;
   Plan pl;
-  st = make_plan(n, p, o, &pl);
+  st = make_plan(n, p, o, &pl, ctx);
   if (st != TLS_OK) return st;
   if (hipSetDevice(ctx->device) != hipSuccess) return TLS_EDEVICE;
   return run_fit(ctx, pl, o, d_series, nullptr, tol, pick_stream(ctx, stream), coef, out);

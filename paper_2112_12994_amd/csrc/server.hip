@@ -447,7 +447,7 @@ tls_status submit(tls_server* S, const double* host_y, const double* dev_y, int6
     for (int64_t i = 0; i < n; ++i)
       if (!isfinite(host_y[i])) return TLS_EINVAL;
   auto* r = new Request();
-  st = make_plan(n, p, S->opt, &r->pl);
+  st = make_plan(n, p, S->opt, &r->pl, S->ctx);
   if (st == TLS_OK && r->pl.ldq > BATCH_LDQ_MAX) st = TLS_EUNSUPPORTED;
   if (st == TLS_OK) {
     FitBufs tmp{};

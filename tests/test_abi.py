@@ -37,10 +37,23 @@ def test_status_strings(capi):
     assert capi.status_string(99) == "unknown status"
 
 
+def test_option_and_tuning_layout(capi):
+    """The binding's option struct has the header's size, and its table index
+    uses the library's buckets: ceil(log2 p), ceil(log2 m) clamped to 40."""
+    import ctypes
+    assert ctypes.sizeof(capi.TlsOptions) == 10 * 4 + 2 * 8 + 2 * 4 + 3 * 8
+    assert capi.TUNE_ENTRIES == 2 * 11 * 41
+    assert capi.tune_index(capi.PREC_F64, 1, 1) == 0
+    assert capi.tune_index(capi.PREC_F64, 100, 4194204) == 7 * 41 + 22
+    assert capi.tune_index(capi.PREC_F64, 64, 1 << 12) == 6 * 41 + 12
+    assert capi.tune_index(capi.PREC_MIXED, 65, (1 << 12) + 1) == (11 + 7) * 41 + 13
+    assert capi.tune_index(capi.PREC_F64, 1024, 1 << 50) == 10 * 41 + 40
+
+
 def test_default_options(capi):
     o = capi.options()
-    assert (o.precision, o.sketch, o.jl_kind, o.gamma, o.jl_k, o.max_iter, o.warm_start) == \
-        (0, 0, 0, 8, 8, 1000, 1)
+    assert (o.precision, o.sketch, o.jl_kind, o.gamma, o.jl_k, o.max_iter, o.warm_start,
+            o.no_graph) == (0, 0, 0, 8, 8, 1000, 1, 0)
     with pytest.raises(TypeError):
         capi.options(bogus=1)
 

@@ -151,3 +151,25 @@ def test_batch_mixed_fp64_finish_equals_single(ctx):
             % (p, o["refine_steps"], o["iters"], o["istop"], o["kappa_est"], o["resid_norm"],
                f64["resid_norm"]))
         assert abs(o["resid_norm"] - f64["resid_norm"]) <= 1e-9 * f64["resid_norm"]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_graph_replay_equals_direct_launches(ctx, prec):
+    """Each chunk of LSQR (or inner refinement) steps of a class is a HIP
+    graph replayed many times; three calls in a row, with other device work
+    and synchronisations between them, equal the directly launched batch bit
+    for bit."""
+    c = capi()
+    say("batch graphs", prec)
+    fits = synth.workload_batch(seed=19, count=40, lo_exp=12, hi_exp=16)
+    ys, ps = [f.y for f in fits], [f.p for f in fits]
+    devs = [to_dev(y) for y in ys]
+    s0, ref = ctx.fit_batch_device(devs, ps, 1e-10, request_id=11, precision=prec, no_graph=1)
+    for rep in range(3):
+        ctx.fit(ys[rep], ps[rep], 1e-10)  # eager work between the replays
+        s1, got = ctx.fit_batch_device(devs, ps, 1e-10, request_id=11, precision=prec)
+        assert s1 == s0
+        for a, b in zip(ref, got):
+            assert a["status"] == b["status"]
+            assert a["coef"].tobytes() == b["coef"].tobytes()
+            assert a["iters"] == b["iters"]
