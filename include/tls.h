@@ -83,7 +83,8 @@ typedef struct tls_options {
   int32_t no_graph;    /* batched calls: 1 launches every step directly; 0 (default) captures
                           each chunk of LSQR (or inner refinement) steps of a launch class once
                           as a HIP graph and replays it (not while profile = 1) */
-  int32_t reserved0;
+  int32_t tick_steps;  /* servers: LSQR steps each fit in flight takes per worker tick (default
+                          4; more steps per tick finish each request in fewer ticks) */
   int64_t reserved[3];
 } tls_options;
 
@@ -205,7 +206,8 @@ tls_status tls_set_tuning(tls_ctx* ctx, const int8_t* table);
 /* ---- served continuous batching ----------------------------------------------
  * A server admits fit requests as they arrive and runs them to completion on
  * one device: each tick of its worker thread sets up the newly admitted fits
- * and runs one LSQR step for every fit in flight, all as batched launches, so
+ * and runs tick_steps LSQR steps (an option, default 4) for every fit in
+ * flight, all as batched launches, so
  * short and long, small-p and large-p requests share the device.  A request is
  * admitted first come, first served once its device footprint (series copy,
  * block spectra, sketch, factors, LSQR state: about 25 bytes per sample plus

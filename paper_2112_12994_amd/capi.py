@@ -49,7 +49,7 @@ class TlsOptions(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("request_id", ctypes.c_uint64),
         ("no_graph", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("tick_steps", ctypes.c_int32),
         ("reserved", ctypes.c_int64 * 3),
     ]
 

@@ -524,18 +524,35 @@ __device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R,
                                                            double* __restrict__ Mt,
                                                            double* __restrict__ phi0,
                                                            int* __restrict__ status) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   {
-    // Mt = M^T: one wavefront per row of M, lanes over its columns
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = wid; i < p; i += NT / 64)
-      for (int j = lane; j < p; j += 64) Mt[static_cast<size_t>(j) * p + i] = M[static_cast<size_t>(i) * p + j];
+    // Mt = M^T through 32 x 32 LDS tiles (rows read and written whole)
+    __shared__ double tile[32][33];
+    const int nt = (p + 31) / 32;
+    for (int t = 0; t < nt * nt; ++t) {
+      const int bi = t / nt, bj = t % nt;
+      __syncthreads();
+      for (int e = threadIdx.x; e < 1024; e += NT) {
+        const int r = e >> 5, c = e & 31;
+        const int i = bi * 32 + r, j = bj * 32 + c;
+        tile[r][c] = (i < p && j < p) ? M[static_cast<size_t>(i) * p + j] : 0.0;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 1024; e += NT) {
+        const int r = e >> 5, c = e & 31;
+        const int i = bj * 32 + r, j = bi * 32 + c;
+        if (i < p && j < p) Mt[static_cast<size_t>(i) * p + j] = tile[c][r];
+      }
+    }
   }
   if (phi0 && q > p) {
-    for (int i = threadIdx.x; i < p; i += NT) {
+    // phi0_i = M[i, i:] R[i:, p]: one wavefront per row, lanes over the row
+    for (int i = wid; i < p; i += NT / 64) {
       double acc = 0.0;
-      for (int j = i; j < p; ++j)
+      for (int j = i + lane; j < p; j += 64)
         acc += M[static_cast<size_t>(i) * p + j] * R[static_cast<size_t>(j) * q + p];
-      phi0[i] = acc;
+      acc = wave_sum(acc);
+      if (lane == 0) phi0[i] = acc;
     }
   }
   if (threadIdx.x < 64) {

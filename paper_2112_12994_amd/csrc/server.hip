@@ -5,9 +5,10 @@
 // admitted (first come, first served) as soon as its device footprint fits in
 // the arena and a slot is free.  Every tick of the worker:
 //   1. sets up the newly admitted fits (spectra, two-stage sketch, QR,
-//      inverse, warm start, first LSQR step), batched by launch class;
-//   2. runs one LSQR step for every fit already iterating, batched by FFT
-//      length and step variant, whatever its age;
+//      inverse, warm start, first LSQR steps), batched by launch class;
+//   2. runs tick_steps (default 4) LSQR steps for every fit already
+//      iterating, batched by FFT length and step variant, whatever its age
+//      (a fit that converges on the way skips the remaining steps);
 //   3. computes the FP64 residual and collects coefficients and results of
 //      the fits that finished in the previous tick;
 // then synchronises once, hands finished results to their tickets and
@@ -208,6 +209,7 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
   hipStream_t s = S->stream;
   const tls_options& o = S->opt;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
+  const int steps = o.tick_steps > 0 ? o.tick_steps : 4;
   hipError_t e;
 
   // descriptors of the new fits, series copies
@@ -323,18 +325,21 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
     if (setup_class(ctx, su.key, su.pmax, su.ldqmax, I, su.l, S->dD, o, s) != TLS_OK)
       return hipErrorUnknown;
     const ClassLists& l = su.l;
-    if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, true, I + l.blocks.off,
-                        l.blocks.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,
-                        S->dCounts, S->dDone, nullptr, s) != TLS_OK)
-      return hipErrorUnknown;
+    for (int k = 0; k < steps; ++k)
+      if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, I + l.blocks.off,
+                          l.blocks.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,
+                          S->dCounts, S->dDone, nullptr, s) != TLS_OK)
+        return hipErrorUnknown;
   }
-  // 2. one LSQR step of every iterating fit
-  for (const Iter& it : iters) {
-    if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, I + it.blocks.off, it.blocks.n,
-                        I + it.cols.off, it.cols.n, I + it.fits.off, it.fits.n, S->dD, S->dCounts,
-                        S->dDone, nullptr, s) != TLS_OK)
-      return hipErrorUnknown;
-  }
+  // 2. tick_steps LSQR steps of every iterating fit (fits that finish on
+  // the way skip the remaining steps)
+  for (int k = 0; k < steps; ++k)
+    for (const Iter& it : iters) {
+      if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, I + it.blocks.off, it.blocks.n,
+                          I + it.cols.off, it.cols.n, I + it.fits.off, it.fits.n, S->dD,
+                          S->dCounts, S->dDone, nullptr, s) != TLS_OK)
+        return hipErrorUnknown;
+    }
   // 3. residual and results of the fits that finished in the previous tick
   if (!finishing.empty()) {
     if (residual_class(I + fin_rblocks.off, fin_rblocks.n, I + fin_fits.off, fin_fits.n, fin_pmax,

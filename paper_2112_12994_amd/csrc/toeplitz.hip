@@ -130,56 +130,87 @@ __global__ __launch_bounds__(NT) void colsum_kernel(const double* __restrict__ p
 // Direct FP64 residual r_i = b_i - sum_j phi_j X[i, j] = y[p+i] - sum_j phi_j y[p-1+i-j],
 // summed over j in order, row by row (the error of each row is bounded by
 // the row's own terms rather than by whole-window norms as in the FFT
-// products).  Each workgroup stages its rows' samples and phi in LDS and
-// writes one partial of ||r||^2.
-template <int NT, int RPT>
+// products).  Each workgroup stages its rows' samples in LDS (one pad word
+// per R samples, so that lanes R samples apart hit different banks) and
+// writes one partial of ||r||^2.  Thread k owns R consecutive rows: at lag
+// j they need samples t .. t + R - 1, t = kR + p - 1 - j, so one new sample
+// per lag enters a register ring and every lag costs one LDS read for R
+// FMAs; phi_j is a uniform (scalar) load.
+constexpr int RESID_R = 8;
+
+__host__ __device__ __forceinline__ int resid_skew(int t) { return t + t / RESID_R; }
+
+template <int NT>
 __device__ __forceinline__ void resid_direct_body(const double* __restrict__ y, int64_t m,
-                                                          int p, const double* __restrict__ phi,
-                                                          double* __restrict__ partial, int tile) {
-  extern __shared__ double sh[];
-  double* sphi = sh;
-  double* sy = sh + p;
+                                                  int p, const double* __restrict__ phi,
+                                                  double* __restrict__ partial, int tile) {
+  constexpr int R = RESID_R;
+  extern __shared__ double sy[];
   __shared__ double red[NT / 64];
-  constexpr int TILE = NT * RPT;
+  constexpr int TILE = NT * R;
   const int64_t row0 = static_cast<int64_t>(tile) * TILE;
-  for (int j = threadIdx.x; j < p; j += NT) sphi[j] = phi[j];
-  // samples y[row0 .. row0 + TILE + p) (rows use y[i .. i + p])
+  // samples y[row0 .. row0 + TILE + p) (row i uses y[i .. i + p])
   for (int t = threadIdx.x; t < TILE + p; t += NT) {
     const int64_t g = row0 + t;
-    sy[t] = g < m + p ? y[g] : 0.0;
+    sy[resid_skew(t)] = g < m + p ? y[g] : 0.0;
   }
   __syncthreads();
-  double acc = 0.0;
+  const int w = threadIdx.x * R + p - 1;  // sample of row 0 at lag 0
+  double acc[R], ring[R];
 #pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int t = threadIdx.x + k * NT;
-    if (row0 + t < m) {
-      double r = sy[t + p];
-      for (int j = 0; j < p; ++j) r -= sphi[j] * sy[t + p - 1 - j];
-      acc += r * r;
+  for (int r = 0; r < R; ++r) {
+    acc[r] = sy[resid_skew(w + 1 + r)];  // b of row r
+    ring[r] = sy[resid_skew(w + r)];     // lag 0 sample of row r, in slot r
+  }
+  // at lag j the sample of row r sits in slot (r - j) mod R
+  for (int jb = 0; jb < p; jb += R) {
+#pragma unroll
+    for (int jj = 0; jj < R; ++jj) {
+      const int j = jb + jj;
+      if (j < p) {
+        const double f = phi[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] -= f * ring[(r - jj + R) % R];
+        // the sample entering at lag j + 1 (row 0) replaces row R-1's
+        const int tn = w - j - 1;
+        ring[(R - 1 - jj + R) % R] = tn >= 0 ? sy[resid_skew(tn)] : 0.0;
+      }
     }
   }
-  const double tot = block_sum<NT>(acc, red);
+  double ss = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (row0 + threadIdx.x * R + r < m) ss += acc[r] * acc[r];
+  const double tot = block_sum<NT>(ss, red);
   if (threadIdx.x == 0) partial[tile] = tot;
 }
 
-template <int NT, int RPT>
+template <int NT>
 __global__ __launch_bounds__(NT) void resid_direct_kernel(const double* __restrict__ y, int64_t m,
                                                           int p, const double* __restrict__ phi,
                                                           double* __restrict__ partial) {
-  resid_direct_body<NT, RPT>(y, m, p, phi, partial, blockIdx.x);
+  resid_direct_body<NT>(y, m, p, phi, partial, blockIdx.x);
 }
 
 }  // namespace
 
-int resid_direct_blocks(int64_t m) { return static_cast<int>((m + 1023) / 1024); }
+constexpr int RESID_NT = 256;
+constexpr int RESID_TILE = RESID_NT * RESID_R;
+
+int resid_direct_blocks(int64_t m) {
+  return static_cast<int>((m + RESID_TILE - 1) / RESID_TILE);
+}
+
+// LDS of one residual workgroup: the skewed samples of its rows
+size_t resid_lds_bytes(int p) {
+  return static_cast<size_t>(resid_skew(RESID_TILE + p) + 1) * sizeof(double);
+}
 
 hipError_t launch_resid_direct(const double* y, int64_t m, int p, const double* phi,
                                double* partial, hipStream_t st) {
   const int nb = resid_direct_blocks(m);
-  const size_t shm = (static_cast<size_t>(p) + 1024 + p) * sizeof(double);
-  hipLaunchKernelGGL((resid_direct_kernel<256, 4>), dim3(nb), dim3(256), shm, st, y, m, p, phi,
-                     partial);
+  hipLaunchKernelGGL((resid_direct_kernel<RESID_NT>), dim3(nb), dim3(RESID_NT), resid_lds_bytes(p),
+                     st, y, m, p, phi, partial);
   return hipGetLastError();
 }
 
@@ -326,19 +357,20 @@ __global__ __launch_bounds__(NT) void colsum_b_kernel(const Item* __restrict__ i
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
   if (variant == 3) {
-    colsum_body<NT>(d.rpart, static_cast<int>((d.m + 1023) / 1024), d.rr, nullptr, it.idx);
+    colsum_body<NT>(d.rpart, static_cast<int>((d.m + RESID_TILE - 1) / RESID_TILE), d.rr, nullptr,
+                    it.idx);
     return;
   }
   const int* flag = variant == 0 ? &d.st->done : (variant == 1 ? &d.rst->done : &d.rst->inner_done);
   colsum_body<NT>(d.partial, d.nblocks, d.g, flag, it.idx);
 }
 
-template <int NT, int RPT>
+template <int NT>
 __global__ __launch_bounds__(NT) void resid_b_kernel(const Item* __restrict__ items,
                                                      const FitDesc* __restrict__ D) {
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
-  resid_direct_body<NT, RPT>(d.y, d.m, d.p, d.phi, d.rpart, it.idx);
+  resid_direct_body<NT>(d.y, d.m, d.p, d.phi, d.rpart, it.idx);
 }
 
 template <int LGN>
@@ -466,8 +498,8 @@ hipError_t launch_colsum_b(int variant, const Item* items, int nitems, const Fit
 hipError_t launch_resid_b(const Item* items, int nitems, const FitDesc* D, int pmax,
                           hipStream_t st) {
   if (nitems < 1) return hipSuccess;
-  const size_t shm = (static_cast<size_t>(pmax) + 1024 + pmax) * sizeof(double);
-  hipLaunchKernelGGL((resid_b_kernel<256, 4>), dim3(nitems), dim3(256), shm, st, items, D);
+  hipLaunchKernelGGL((resid_b_kernel<RESID_NT>), dim3(nitems), dim3(RESID_NT),
+                     resid_lds_bytes(pmax), st, items, D);
   return hipGetLastError();
 }
 

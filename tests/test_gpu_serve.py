@@ -153,3 +153,18 @@ def test_serve_destroy_with_requests_in_flight(ctx):
     for i, (y, p) in enumerate(work):
         srv.submit(y, p, 1e-10, request_id=i)
     srv.close()  # runs everything to completion, discards the results
+
+
+@pytest.mark.parametrize("tick_steps", [1, 7])
+def test_serve_tick_steps_equal_single(ctx, tick_steps):
+    """Any number of LSQR steps per tick gives every request its single-fit
+    result (fits that converge inside a tick skip its remaining steps)."""
+    c = capi()
+    say("serve tick steps", tick_steps)
+    work = _series(7, 16, lo=10, hi=15)
+    with c.Server(ctx, 1 << 30, 32, tick_steps=tick_steps) as srv:
+        tickets = [srv.submit_device(to_dev(y), p, 1e-10, request_id=300 + i)
+                   for i, (y, p) in enumerate(work)]
+        outs = [srv.wait(t) for t in tickets]
+    for i, ((y, p), o) in enumerate(zip(work, outs)):
+        _check_same(ctx, y, p, 300 + i, o)
