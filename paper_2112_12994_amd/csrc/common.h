@@ -65,6 +65,28 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return t;
 }
 
+// Sum of a column of nblocks partials in one fixed order for any workgroup
+// of NT >= 256 threads: thread t < 256 adds rows t, t + 256, ..., then the
+// four wavefront sums are added in order (the same result as block_sum<256>
+// over those threads).  `scratch` holds >= 4 doubles.
+template <int NT>
+__device__ __forceinline__ double column_sum(const double* __restrict__ col, int nblocks,
+                                             double* scratch) {
+  static_assert(NT >= 256, "column_sum needs 256 threads");
+  double s = 0.0;
+  if (threadIdx.x < 256)
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += col[b];
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0 && wid < 4) scratch[wid] = s;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t += scratch[i];
+  return t;
+}
+
 }  // namespace tls
 
 namespace tls {

@@ -43,7 +43,21 @@ __device__ __forceinline__ void gram_body(const double* __restrict__ A, int crow
   const int cj = tj * 16 + (lane & 15);
   const int kr = lane >> 4;
   d4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int r0 = wv * 4; r0 < crows; r0 += 16) {
+  // eight row steps per round so that their loads are in flight together
+  // (the accumulation order is the plain one)
+  int r0 = wv * 4;
+  for (; r0 + 7 * 16 < crows; r0 += 8 * 16) {
+    double a[8], b[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const double* row = A + static_cast<size_t>(r0 + 16 * k + kr) * ldq;
+      a[k] = row[ci];
+      b[k] = row[cj];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k], b[k], acc, 0, 0, 0);
+  }
+  for (; r0 < crows; r0 += 16) {
     const double* row = A + static_cast<size_t>(r0 + kr) * ldq;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(row[ci], row[cj], acc, 0, 0, 0);
   }
@@ -273,7 +287,8 @@ __global__ __launch_bounds__(1024) void chol_reg32_kernel(const double* __restri
 // divided by R_ii and R[r][i] times it is subtracted from every row r < i.
 template <int QT>
 __device__ __forceinline__ void triinv_reg_body(const double* __restrict__ R, int ldr, int n,
-                                                         double* __restrict__ M, int ldm) {
+                                                         double* __restrict__ M, int ldm,
+                                                         double* __restrict__ Mt) {
   extern __shared__ double Rs[];  // n x (n + 1)
   __shared__ double pub[2][16 * QT];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -337,20 +352,28 @@ __device__ __forceinline__ void triinv_reg_body(const double* __restrict__ R, in
 #pragma unroll
     for (int b = 0; b < QT; ++b) {
       const int r = ty + 16 * a, c = tx + 16 * b;
-      if (r < ldm && c < ldm) M[static_cast<size_t>(r) * ldm + c] = (r < n && c < n) ? reg[a][b] : 0.0;
+      if (r < ldm && c < ldm) {
+        const double x = (r < n && c < n) ? reg[a][b] : 0.0;
+        M[static_cast<size_t>(r) * ldm + c] = x;
+        if (Mt) Mt[static_cast<size_t>(c) * ldm + r] = x;
+      }
     }
   // rows / columns of the ldm block beyond 16 QT (only when ldm > 16 QT)
   if (ldm > 16 * QT)
     for (int e = threadIdx.x; e < ldm * ldm; e += 256) {
       const int r = e / ldm, c = e % ldm;
-      if (r >= 16 * QT || c >= 16 * QT) M[e] = 0.0;
+      if (r >= 16 * QT || c >= 16 * QT) {
+        M[e] = 0.0;
+        if (Mt) Mt[e] = 0.0;
+      }
     }
 }
 
 template <int QT>
 __global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restrict__ R, int ldr, int n,
-                                                         double* __restrict__ M, int ldm) {
-  triinv_reg_body<QT>(R, ldr, n, M, ldm);
+                                                         double* __restrict__ M, int ldm,
+                                                         double* __restrict__ Mt) {
+  triinv_reg_body<QT>(R, ldr, n, M, ldm, Mt);
 }
 
 // A <- A R^{-1} on the first q columns, 16 rows per wavefront (rows are
@@ -358,11 +381,15 @@ __global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restric
 // 16 x 16 diagonal block by forward substitution (one lane per row), then the
 // trailing columns A[:, K] -= X[:, J] R[J, K] on the FP64 matrix cores.
 // Backward stable, unlike a product with an explicitly inverted R.
+// RALL (ldq <= 128): all of R is staged in LDS once, ahead of the column
+// blocks, instead of 16 rows per block (the arithmetic is the same).
+template <bool RALL>
 __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, int q,
                                                        const double* __restrict__ R, int rt) {
-  extern __shared__ double T[];  // 16 x (ldq + 1) rows of A, then 16 x ldq rows of R
+  // 16 x (ldq + 1) rows of A, then 16 (RALL: ldq) x ldq rows of R
+  extern __shared__ double T[];
   const int ld = ldq + 1;
-  double* Rp = T + 16 * ld;
+  double* const Rbase = T + 16 * ld;
   const int lane = threadIdx.x;
   const size_t r0 = static_cast<size_t>(rt) * 16;
   // the 16 rows of A: lanes over columns, 16 rows' loads in flight
@@ -374,18 +401,24 @@ __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, 
     for (int r = 0; r < 16; ++r) T[r * ld + c] = v[r];
   }
   const int nt = (q + 15) / 16;
-  for (int J = 0; J < nt; ++J) {
-    const int j0 = J * 16;
-    // rows j0 .. j0+15 of R from column j0 on (zero outside q x q; R is
-    // upper triangular, so nothing left of j0 is read)
+  // rows j0 .. j0+15 of R from column j0 on into dst (zero outside q x q;
+  // R is upper triangular, so nothing left of j0 is read)
+  auto stage_rows = [&](int j0, double* dst) {
     for (int cc = j0 + lane; cc < ldq; cc += 64) {
       double v[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r)
         v[r] = (j0 + r < q && cc < q) ? R[static_cast<size_t>(j0 + r) * q + cc] : 0.0;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) Rp[r * ldq + cc] = v[r];
+      for (int r = 0; r < 16; ++r) dst[r * ldq + cc] = v[r];
     }
+  };
+  if constexpr (RALL)
+    for (int J = 0; J < nt; ++J) stage_rows(J * 16, Rbase + static_cast<size_t>(J) * 16 * ldq);
+  for (int J = 0; J < nt; ++J) {
+    const int j0 = J * 16;
+    double* const Rp = RALL ? Rbase + static_cast<size_t>(j0) * ldq : Rbase;
+    if constexpr (!RALL) stage_rows(j0, Rp);
     __syncthreads();
     if (lane < 16) {
       double* row = T + lane * ld;
@@ -419,9 +452,17 @@ __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, 
   }
 }
 
+template <bool RALL>
 __global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, int ldq, int q,
                                                        const double* __restrict__ R) {
-  trsm_tile_body(A, ldq, q, R, blockIdx.x);
+  trsm_tile_body<RALL>(A, ldq, q, R, blockIdx.x);
+}
+
+// LDS of the tiled solve: 16 rows of A, then 16 rows of R or (ldq <= 128) all of R
+bool trsm_rall(int ldq) { return ldq <= 128; }
+size_t trsm_lds_bytes(int ldq) {
+  const size_t rrows = trsm_rall(ldq) ? static_cast<size_t>(ldq) : 16;
+  return (16 * static_cast<size_t>(ldq + 1) + rrows * ldq) * sizeof(double);
 }
 
 // status |= 4 when min|R_ii| <= k u max|R_ii| over the first k = rank_cols
@@ -454,7 +495,8 @@ __global__ __launch_bounds__(64) void rank_test_kernel(const double* __restrict_
 // columns of R staged in LDS 32 at a time (n x 33 doubles) instead of all of R.
 template <int QT>
 __device__ __forceinline__ void triinv_reg32_body(const double* __restrict__ R, int ldr, int n,
-                                                  double* __restrict__ M, int ldm) {
+                                                  double* __restrict__ M, int ldm,
+                                                  double* __restrict__ Mt) {
   constexpr int TD = 32;
   extern __shared__ double Rc[];  // rows x 33: columns 32 a0 .. 32 a0 + 31 of R
   __shared__ double pub[2][TD * QT];
@@ -508,43 +550,29 @@ __device__ __forceinline__ void triinv_reg32_body(const double* __restrict__ R, 
 #pragma unroll
     for (int b = 0; b < QT; ++b) {
       const int r = ty + TD * a, c = tx + TD * b;
-      if (r < ldm && c < ldm) M[static_cast<size_t>(r) * ldm + c] = (r < n && c < n) ? reg[a][b] : 0.0;
+      if (r < ldm && c < ldm) {
+        const double x = (r < n && c < n) ? reg[a][b] : 0.0;
+        M[static_cast<size_t>(r) * ldm + c] = x;
+        if (Mt) Mt[static_cast<size_t>(c) * ldm + r] = x;
+      }
     }
 }
 
 template <int QT>
 __global__ __launch_bounds__(1024) void triinv_reg32_kernel(const double* __restrict__ R, int ldr,
-                                                            int n, double* __restrict__ M, int ldm) {
-  triinv_reg32_body<QT>(R, ldr, n, M, ldm);
+                                                            int n, double* __restrict__ M, int ldm,
+                                                            double* __restrict__ Mt) {
+  triinv_reg32_body<QT>(R, ldr, n, M, ldm, Mt);
 }
 
+// After a register inverse (which also wrote M^T): phi0 = M R[:p, p] (the
+// compressed problem's solution) and the rank test min|R_ii| <= p u max|R_ii|.
 template <int NT>
 __device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R, int q,
                                                            int p, const double* __restrict__ M,
-                                                           double* __restrict__ Mt,
                                                            double* __restrict__ phi0,
                                                            int* __restrict__ status) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  {
-    // Mt = M^T through 32 x 32 LDS tiles (rows read and written whole)
-    __shared__ double tile[32][33];
-    const int nt = (p + 31) / 32;
-    for (int t = 0; t < nt * nt; ++t) {
-      const int bi = t / nt, bj = t % nt;
-      __syncthreads();
-      for (int e = threadIdx.x; e < 1024; e += NT) {
-        const int r = e >> 5, c = e & 31;
-        const int i = bi * 32 + r, j = bj * 32 + c;
-        tile[r][c] = (i < p && j < p) ? M[static_cast<size_t>(i) * p + j] : 0.0;
-      }
-      __syncthreads();
-      for (int e = threadIdx.x; e < 1024; e += NT) {
-        const int r = e >> 5, c = e & 31;
-        const int i = bj * 32 + r, j = bi * 32 + c;
-        if (i < p && j < p) Mt[static_cast<size_t>(i) * p + j] = tile[c][r];
-      }
-    }
-  }
   if (phi0 && q > p) {
     // phi0_i = M[i, i:] R[i:, p]: one wavefront per row, lanes over the row
     for (int i = wid; i < p; i += NT / 64) {
@@ -575,10 +603,9 @@ __device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R,
 template <int NT>
 __global__ __launch_bounds__(NT) void triinv_finish_kernel(const double* __restrict__ R, int q,
                                                            int p, const double* __restrict__ M,
-                                                           double* __restrict__ Mt,
                                                            double* __restrict__ phi0,
                                                            int* __restrict__ status) {
-  triinv_finish_body<NT>(R, q, p, M, Mt, phi0, status);
+  triinv_finish_body<NT>(R, q, p, M, phi0, status);
 }
 
 
@@ -1145,34 +1172,36 @@ void chol_launch(double* G, int ldq, int q, int crows, int shift_mode, double* R
 }
 
 template <int QT>
-void triinv_reg_launch(const double* R, int ldr, int n, double* M, int ldm, hipStream_t st) {
+void triinv_reg_launch(const double* R, int ldr, int n, double* M, int ldm, double* Mt,
+                       hipStream_t st) {
   hipLaunchKernelGGL((triinv_reg_kernel<QT>), dim3(1), dim3(256),
-                     static_cast<size_t>(n) * (n + 1) * sizeof(double), st, R, ldr, n, M, ldm);
+                     static_cast<size_t>(n) * (n + 1) * sizeof(double), st, R, ldr, n, M, ldm, Mt);
 }
 
 }  // namespace
 
-// Triangular inverse of R[:n,:n] into M with leading dimension ldm >= n,
-// zero-padded, for n <= 224 (register tiles on 16 x 16 or 32 x 32 thread
+// Triangular inverse of R[:n,:n] into M (and its transpose into Mt when
+// given) with leading dimension ldm >= n, zero-padded, for n <= 224 (register tiles on 16 x 16 or 32 x 32 thread
 // grids; larger orders take the blocked kernels through launch_triinv).
-hipError_t tri_inverse(const double* R, int ldr, int n, double* M, int ldm, hipStream_t st) {
+hipError_t tri_inverse(const double* R, int ldr, int n, double* M, int ldm, double* Mt,
+                       hipStream_t st) {
   const size_t shm32 = static_cast<size_t>(n) * 33 * sizeof(double);
   switch (reg_tiles(n)) {
 #define TLS_TRI32(K)                                                                          \
   case 100 + K:                                                                               \
     hipLaunchKernelGGL((triinv_reg32_kernel<K>), dim3(1), dim3(1024), shm32, st, R, ldr, n, M, \
-                       ldm);                                                                  \
+                       ldm, Mt);                                                                  \
     break;
     TLS_TRI32(5) TLS_TRI32(6) TLS_TRI32(7)
 #undef TLS_TRI32
-    case 1: triinv_reg_launch<1>(R, ldr, n, M, ldm, st); break;
-    case 2: triinv_reg_launch<2>(R, ldr, n, M, ldm, st); break;
-    case 3: triinv_reg_launch<3>(R, ldr, n, M, ldm, st); break;
-    case 4: triinv_reg_launch<4>(R, ldr, n, M, ldm, st); break;
-    case 5: triinv_reg_launch<5>(R, ldr, n, M, ldm, st); break;
-    case 6: triinv_reg_launch<6>(R, ldr, n, M, ldm, st); break;
-    case 7: triinv_reg_launch<7>(R, ldr, n, M, ldm, st); break;
-    case 8: triinv_reg_launch<8>(R, ldr, n, M, ldm, st); break;
+    case 1: triinv_reg_launch<1>(R, ldr, n, M, ldm, Mt, st); break;
+    case 2: triinv_reg_launch<2>(R, ldr, n, M, ldm, Mt, st); break;
+    case 3: triinv_reg_launch<3>(R, ldr, n, M, ldm, Mt, st); break;
+    case 4: triinv_reg_launch<4>(R, ldr, n, M, ldm, Mt, st); break;
+    case 5: triinv_reg_launch<5>(R, ldr, n, M, ldm, Mt, st); break;
+    case 6: triinv_reg_launch<6>(R, ldr, n, M, ldm, Mt, st); break;
+    case 7: triinv_reg_launch<7>(R, ldr, n, M, ldm, Mt, st); break;
+    case 8: triinv_reg_launch<8>(R, ldr, n, M, ldm, Mt, st); break;
     default:
       return hipErrorInvalidValue;
   }
@@ -1190,11 +1219,12 @@ __global__ __launch_bounds__(256) void gram_gated_kernel(const int* __restrict__
   gram_body(A, crows, ldq, G, blockIdx.x);
 }
 
+template <bool RALL>
 __global__ __launch_bounds__(64) void trsm_tile_gated_kernel(const int* __restrict__ gate,
                                                              double* __restrict__ A, int ldq, int q,
                                                              const double* __restrict__ R) {
   if (!(*gate & 8)) return;
-  trsm_tile_body(A, ldq, q, R, blockIdx.x);
+  trsm_tile_body<RALL>(A, ldq, q, R, blockIdx.x);
 }
 
 // Row i of T = R3 R2 when the third sweep ran, else of T = R2.
@@ -1223,7 +1253,8 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sw
   double* Rs[3] = {sweeps == 1 ? R : R1, R2, R3};
   // the third sweep is gated on status bit 8 from the second Cholesky
   const bool gate3 = sweeps == 3 && ldq <= 1024;
-  const size_t trsm_shm = (16 * (ldq + 1) + 16 * ldq) * sizeof(double);
+  const size_t trsm_shm = trsm_lds_bytes(ldq);
+  const bool rall = trsm_rall(ldq);
   for (int sweep = 0; sweep < sweeps; ++sweep) {
     const bool gated = gate3 && sweep == 2;
     if (gated)
@@ -1234,12 +1265,20 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sw
                 rank_cols, gated ? status : nullptr, st);
     if (sweep == sweeps - 1) break;
     if (ldq <= 1024) {
-      if (gate3 && sweep == 1)
-        hipLaunchKernelGGL(trsm_tile_gated_kernel, dim3(crows / 16), dim3(64), trsm_shm, st, status,
-                           A, ldq, q, Rs[sweep]);
-      else
-        hipLaunchKernelGGL(trsm_tile_kernel, dim3(crows / 16), dim3(64), trsm_shm, st, A, ldq, q,
-                           Rs[sweep]);
+      if (gate3 && sweep == 1) {
+        if (rall)
+          hipLaunchKernelGGL(trsm_tile_gated_kernel<true>, dim3(crows / 16), dim3(64), trsm_shm, st,
+                             status, A, ldq, q, Rs[sweep]);
+        else
+          hipLaunchKernelGGL(trsm_tile_gated_kernel<false>, dim3(crows / 16), dim3(64), trsm_shm, st,
+                             status, A, ldq, q, Rs[sweep]);
+      } else if (rall) {
+        hipLaunchKernelGGL(trsm_tile_kernel<true>, dim3(crows / 16), dim3(64), trsm_shm, st, A, ldq,
+                           q, Rs[sweep]);
+      } else {
+        hipLaunchKernelGGL(trsm_tile_kernel<false>, dim3(crows / 16), dim3(64), trsm_shm, st, A, ldq,
+                           q, Rs[sweep]);
+      }
     } else {
       hipLaunchKernelGGL(trsm_global_kernel, dim3((crows + 63) / 64), dim3(64), 0, st, A, crows,
                          ldq, q, Rs[sweep]);
@@ -1262,9 +1301,9 @@ hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, d
                          int* status, hipStream_t st) {
   if (p < 1 || q < p) return hipErrorInvalidValue;
   if (reg_tiles(p) != 0) {
-    hipError_t e = tri_inverse(R, q, p, M, p, st);
+    hipError_t e = tri_inverse(R, q, p, M, p, Mt, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((triinv_finish_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, Mt, phi0,
+    hipLaunchKernelGGL((triinv_finish_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, phi0,
                        status);
   } else {
     inv_blk_launch(R, q, p, M, Mt, phi0, status, st);
@@ -1324,12 +1363,13 @@ __global__ __launch_bounds__(1024) void chol_b32_kernel(const Item* __restrict__
   chol_reg_body<QT, 32>(d.G, d.ldq, d.q, d.crows, shift_mode, R, status, fail_bit, d.p);
 }
 
+template <bool RALL>
 __global__ __launch_bounds__(64) void trsm_b_kernel(const Item* __restrict__ items,
                                                     const FitDesc* __restrict__ D, int which) {
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
   if (which == 1 && !(d.status[0] & 8)) return;  // only feeds the third sweep
-  trsm_tile_body(d.A, d.ldq, d.q, which == 0 ? d.R1 : d.R2, it.idx);
+  trsm_tile_body<RALL>(d.A, d.ldq, d.q, which == 0 ? d.R1 : d.R2, it.idx);
 }
 
 __global__ __launch_bounds__(256) void trmm_b_kernel(const Item* __restrict__ items,
@@ -1381,9 +1421,9 @@ __global__ __launch_bounds__(256) void triinv_b_kernel(const Item* __restrict__ 
   const FitDesc& d = D[items[blockIdx.x].fit];
   double* M = stage == 1 ? d.M0 : d.M;
   double* Mt = stage == 1 ? d.Mt0 : d.Mt;
-  triinv_reg_body<QT>(d.R, d.q, d.p, M, d.p);
+  triinv_reg_body<QT>(d.R, d.q, d.p, M, d.p, Mt);
   __syncthreads();
-  triinv_finish_body<256>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
+  triinv_finish_body<256>(d.R, d.q, d.p, M, stage == 1 ? nullptr : d.phi0,
                           stage == 1 ? d.status + 3 : d.status + 1);
   if (stage == 2) diag_range(d);
 }
@@ -1395,9 +1435,9 @@ __global__ __launch_bounds__(1024) void triinv_b32_kernel(const Item* __restrict
   const FitDesc& d = D[items[blockIdx.x].fit];
   double* M = stage == 1 ? d.M0 : d.M;
   double* Mt = stage == 1 ? d.Mt0 : d.Mt;
-  triinv_reg32_body<QT>(d.R, d.q, d.p, M, d.p);
+  triinv_reg32_body<QT>(d.R, d.q, d.p, M, d.p, Mt);
   __syncthreads();
-  triinv_finish_body<1024>(d.R, d.q, d.p, M, Mt, stage == 1 ? nullptr : d.phi0,
+  triinv_finish_body<1024>(d.R, d.q, d.p, M, stage == 1 ? nullptr : d.phi0,
                            stage == 1 ? d.status + 3 : d.status + 1);
   if (stage == 2) diag_range(d);
 }
@@ -1516,8 +1556,7 @@ template <int QT>
 hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtiles, int nrowtiles,
                    const Item* rows, int nrows, const Item* fits, int nfits, int ldqmax,
                    const FitDesc* D, hipStream_t st) {
-  const size_t trsm_shm = (16 * static_cast<size_t>(ldqmax + 1) + 16 * static_cast<size_t>(ldqmax)) *
-                          sizeof(double);
+  const size_t trsm_shm = trsm_lds_bytes(ldqmax);
   const int sweeps = stage == 1 ? 1 : 3;
   for (int sweep = 0; sweep < sweeps; ++sweep) {
     hipLaunchKernelGGL(gram_b_kernel, dim3(ntiles), dim3(256), 0, st, tiles, D,
@@ -1531,7 +1570,8 @@ hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtile
     else
       chol_blk_b(fits, nfits, ldqmax, stage == 1 ? -1 : sweep, D, st);
     if (sweep < sweeps - 1)
-      hipLaunchKernelGGL(trsm_b_kernel, dim3(nrowtiles), dim3(64), trsm_shm, st, rowtiles, D, sweep);
+      hipLaunchKernelGGL((trsm_b_kernel<(QT >= 1 && QT <= 8)>), dim3(nrowtiles), dim3(64), trsm_shm,
+                         st, rowtiles, D, sweep);
   }
   if (stage == 2) {
     hipLaunchKernelGGL(trmm_b_kernel, dim3(nrows), dim3(256), 0, st, rows, D, 0);

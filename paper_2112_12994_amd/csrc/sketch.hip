@@ -138,46 +138,73 @@ __device__ __forceinline__ double wave_incl_scan(double v) {
   return v;
 }
 
-// One wavefront per draw: target = u * total; find the chunk by binary search
-// on the prefix, then the first row in the chunk whose running total exceeds
-// the target.  scale = 1 / sqrt(c * s_i / total).
+// One wavefront per draw: target = u * total; find the last chunk whose
+// prefix is <= target by a 64-way search (each round probes 64 evenly spaced
+// prefixes and keeps the bracket of the last one <= target), then the first
+// row of the chunk whose running total exceeds the target.  The chunk is
+// staged in LDS so that lane l owns rows 64 l .. 64 l + 63 of it: a wave
+// scan of the lane totals gives each lane its starting total, every lane
+// runs its 64 rows in order, and the lowest lane that crosses the target
+// holds the draw.  scale = 1 / sqrt(c * s_i / total).
 template <typename T>
 __device__ __forceinline__ void draw_body(const T* __restrict__ s, int64_t m,
-                                                  const double* __restrict__ pre, int nch,
-                                                  const double* __restrict__ u, int c,
-                                                  int64_t* __restrict__ idx,
-                                                  double* __restrict__ scale, uint64_t seed,
-                                                  uint32_t fit, int t) {
+                                          const double* __restrict__ pre, int nch,
+                                          const double* __restrict__ u, int c,
+                                          int64_t* __restrict__ idx,
+                                          double* __restrict__ scale, uint64_t seed,
+                                          uint32_t fit, int t) {
+  __shared__ double seg[CHUNK + CHUNK / 64];  // row e of the chunk at e + e / 64
   const int lane = threadIdx.x;
   const double total = pre[nch];
   const double ut = u ? u[t] : philox_u01(static_cast<uint64_t>(t), RNG_LEVERAGE, fit, seed);
   const double target = ut * total;
-  int lo = 0, hi = nch - 1;  // last chunk with pre[k] <= target
+  int lo = 0, hi = nch - 1;  // invariant: pre[lo] <= target
   while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (pre[mid] <= target)
-      lo = mid;
-    else
-      hi = mid - 1;
+    const int step = (hi - lo + 64) / 64;
+    const int k = lo + lane * step;
+    const uint64_t le = __ballot(k <= hi && pre[k] <= target);
+    lo += (63 - __builtin_clzll(le)) * step;
+    hi = min(hi, lo + step - 1);
   }
   const int64_t base = static_cast<int64_t>(lo) * CHUNK;
-  double running = pre[lo];
-  int64_t found = -1, lastpos = -1;
-  for (int off = 0; off < CHUNK && base + off < m; off += 64) {
-    const int64_t g = base + off + lane;
-    const double v = g < m ? static_cast<double>(s[g]) : 0.0;
-    const double incl = wave_incl_scan(v);
-    const uint64_t hit = __ballot(running + incl > target && v > 0.0);
-    const uint64_t pos = __ballot(v > 0.0);
-    if (pos) lastpos = base + off + 63 - __builtin_clzll(pos);
-    if (hit) {
-      found = base + off + __builtin_ctzll(hit);
-      break;
-    }
-    running += __shfl(incl, 63, 64);
+  for (int i = 0; i < 64; ++i) {
+    const int64_t g = base + i * 64 + lane;
+    seg[i * 65 + lane] = g < m ? static_cast<double>(s[g]) : 0.0;
   }
-  if (found < 0) found = lastpos;  // target within rounding of the chunk end
-  if (found < 0) found = base;     // all-zero chunk cannot be reached by a positive total
+  __syncthreads();
+  double v[64];
+  double loc = 0.0;
+  int lastk = -1;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    v[k] = seg[lane * 65 + k];
+    loc += v[k];
+    if (v[k] > 0.0) lastk = k;
+  }
+  const double incl = wave_incl_scan(loc);
+  const double up = __shfl_up(incl, 1, 64);
+  double running = pre[lo] + (lane ? up : 0.0);
+  int hitk = -1;
+#pragma unroll
+  for (int k = 0; k < 64; ++k) {
+    running += v[k];
+    if (hitk < 0 && running > target && v[k] > 0.0) hitk = k;
+  }
+  int64_t found;
+  const uint64_t hit = __ballot(hitk >= 0);
+  if (hit) {
+    const int L = __builtin_ctzll(hit);
+    found = base + 64 * L + __shfl(hitk, L, 64);
+  } else {
+    // target within rounding of the chunk end: its last positive row
+    const uint64_t pos = __ballot(lastk >= 0);
+    if (pos) {
+      const int L = 63 - __builtin_clzll(pos);
+      found = base + 64 * L + __shfl(lastk, L, 64);
+    } else {
+      found = base;  // an all-zero chunk cannot be reached by a positive total
+    }
+  }
   if (lane == 0) {
     idx[t] = found;
     const double sv = static_cast<double>(s[found]);

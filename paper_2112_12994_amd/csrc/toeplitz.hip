@@ -111,12 +111,9 @@ template <int NT>
 __device__ __forceinline__ void colsum_body(const double* __restrict__ partial,
                                                     int nblocks, double* __restrict__ out,
                                                     const int* __restrict__ flag, int j) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[4];
   if (flag && *flag) return;
-  const double* colp = partial + static_cast<size_t>(j) * nblocks;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += NT) s += colp[b];
-  const double tot = block_sum<NT>(s, red);
+  const double tot = column_sum<NT>(partial + static_cast<size_t>(j) * nblocks, nblocks, red);
   if (threadIdx.x == 0) out[j] = tot;
 }
 
