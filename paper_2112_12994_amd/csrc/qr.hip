@@ -421,13 +421,27 @@ __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, 
     if constexpr (!RALL) stage_rows(j0, Rp);
     __syncthreads();
     if (lane < 16) {
+      // the row's 16 entries of this block in registers (R rows read as
+      // LDS broadcasts): the same operations in the same order as a
+      // substitution in place, without an LDS round trip per step
       double* row = T + lane * ld;
-      for (int jj = 0; jj < 16 && j0 + jj < q; ++jj) {
-        const double* rj = Rp + jj * ldq;
-        const double x = row[j0 + jj] / rj[j0 + jj];
-        row[j0 + jj] = x;
-        for (int kk = jj + 1; kk < 16 && j0 + kk < q; ++kk) row[j0 + kk] -= x * rj[j0 + kk];
+      const int nj = min(16, q - j0);
+      double xr[16];
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) xr[kk] = row[j0 + kk];
+#pragma unroll
+      for (int jj = 0; jj < 16; ++jj) {
+        if (jj < nj) {
+          const double* rj = Rp + jj * ldq;
+          const double x = xr[jj] / rj[j0 + jj];
+          xr[jj] = x;
+#pragma unroll
+          for (int kk = jj + 1; kk < 16; ++kk)
+            if (kk < nj) xr[kk] -= x * rj[j0 + kk];
+        }
       }
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) row[j0 + kk] = xr[kk];
     }
     __syncthreads();
     for (int K = J + 1; K < nt; ++K) {
