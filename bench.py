@@ -45,6 +45,9 @@ WORKLOAD_TEXT = {
              "N(0,1) innovations, seed 0; sketch 8p rows, tol 1e-10",
     "batch": "2048 independent series, n=round(2^U(12,18)), p~U{4..64}, pole moduli U[0.3,0.95], "
              "t5 innovations, seed 0; one batched call per step; sketch 8p rows, tol 1e-10",
+    "sketch": "AR(100) series, n=2^22 (the ar100 series); compressed (sketch-and-solve) "
+              "estimator of eq. (OLSc) for sketch sizes c = gamma p, gamma in 2..64, FP64; "
+              "errors against the FP64 OLS fit of the same series",
     "serve": "Poisson arrivals at 5000 requests/s, each a series drawn with replacement from a pool "
              "of resident series with n=round(2^U(10,20)), p~U{2..200}, pole moduli U[0.5,0.95], "
              "N(0,1) innovations, seed 0; FP64, sketch 8p rows, tol 1e-10",
@@ -380,6 +383,54 @@ def batch_bench(args, torch, synth, capi):
     print(json.dumps(line), flush=True)
 
 
+def sketch_bench(args, torch, synth, capi):
+    """The paper's compressed estimator (Section 2.1, eq. (OLSc)) on the AR(100)
+    n=2^22 series for a sweep of sketch sizes (the error-versus-c study of
+    Section 4.1, here on the synthetic series): per gamma, fits/s of the
+    compressed estimator (estimator = TLS_EST_SKETCH, no LSQR), its relative
+    coefficient error and residual ratio against the FP64 OLS fit.  value:
+    fits/s at gamma = 8."""
+    f = synth.WORKLOADS["ar100"](seed=0)
+    y, p = f.y, f.p
+    dy = torch.from_numpy(y).to("cuda:0")
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    ctx = capi.Context(0, precision=0)
+    ctx.fit_device(dy, p, 1e-10, stream=stream)  # warm-up
+    ols = ctx.fit_device(dy, p, 1e-10, stream=stream)
+    rows = []
+    value = None
+    for gamma in (2, 4, 8, 16, 32, 64):
+        for _ in range(args.warmup):
+            out = ctx.fit_device(dy, p, 1e-10, stream=stream, gamma=gamma, estimator=capi.EST_SKETCH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = ctx.fit_device(dy, p, 1e-10, stream=stream, gamma=gamma, estimator=capi.EST_SKETCH)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        err = float(np.linalg.norm(out["coef"] - ols["coef"]) / np.linalg.norm(ols["coef"]))
+        rows.append({"gamma": gamma, "c": gamma * p, "ms_per_fit": dt * 1e3, "fits_per_s": 1.0 / dt,
+                     "rel_err_vs_ols": err, "resid_ratio": out["resid_norm"] / ols["resid_norm"],
+                     "status": capi.status_string(out["status"])})
+        print(f"[bench] gamma {gamma}: {dt * 1e3:.3f} ms, err {err:.3g}, "
+              f"ratio {rows[-1]['resid_ratio']:.6f}", file=sys.stderr, flush=True)
+        if gamma == 8:
+            value = 1.0 / dt
+    line = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 / value, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["sketch"], "n": int(y.size), "p": p,
+                   "estimator": "compressed (sketch-and-solve)", "value_at_gamma": 8},
+        "sweep": rows,
+        "ols_reference": {"iters": ols["iters"], "resid_norm": ols["resid_norm"],
+                          "ms_per_fit": ols["t_total_ms"]},
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args, torch, synth, capi):
     """Open-loop served workload: one thread submits requests at their Poisson
     arrival times (series resident in device memory, borrowed by the server),
@@ -565,6 +616,9 @@ def main():
         return
     if args.workload == "serve":
         serve_bench(args, torch, synth, capi)
+        return
+    if args.workload == "sketch":
+        sketch_bench(args, torch, synth, capi)
         return
     f = synth.WORKLOADS[args.workload](seed=0, **({"n": args.n} if args.n else {}))
     prec = 1 if args.precision == "mixed" else 0

@@ -60,6 +60,16 @@ const char* tls_status_string(tls_status s);
 #define TLS_JL_SRHT 0     /* k x p subsampled randomized Hadamard map (Definition 2.4, Algorithm 1) */
 #define TLS_JL_GAUSS 1    /* k x p Gaussian map, entries N(0, 1/k) (eq. (glev)) */
 
+/* What a fit returns.  OLS: the least-squares solution of Theorem 2.2,
+ * reached by LSQR preconditioned with the sketch's R.  SKETCH: the compressed
+ * (sketch-and-solve) estimator of Section 2.1, the solution of eq. (OLSc)
+ * min ||S X phi - S b|| on the sampled, rescaled rows, from the same QR of
+ * [S X | S b] (no LSQR iterations; resid_norm is still the FP64 residual of
+ * the full problem, so resid_norm / (the OLS residual) is the paper's
+ * residual ratio). */
+#define TLS_EST_OLS 0
+#define TLS_EST_SKETCH 1
+
 /* Autotuned block lengths: one log2 B per (precision, order bucket ceil(log2 p),
  * length bucket ceil(log2 (n - p)), clamped to 40); 0 = not tuned. */
 #define TLS_TUNE_PRECS 2
@@ -85,7 +95,9 @@ typedef struct tls_options {
                           as a HIP graph and replays it (not while profile = 1) */
   int32_t tick_steps;  /* servers: LSQR steps each fit in flight takes per worker tick (default
                           4; more steps per tick finish each request in fewer ticks) */
-  int64_t reserved[3];
+  int32_t estimator;   /* TLS_EST_* (default OLS) */
+  int32_t reserved1;
+  int64_t reserved[2];
 } tls_options;
 
 typedef struct tls_result {

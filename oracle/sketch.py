@@ -11,6 +11,9 @@ leverage_sample: Algorithm 2 / eq. (ldist): pi_i = l_i / sum_k l_k, c draws
   whose running score total exceeds u * total (inverse CDF, the running total
   accumulated in row order).
 sketch_rows: the sampled, rescaled rows of [X | b] (eq. (OLSc) with S applied).
+compressed_solution: the compressed (sketch-and-solve) estimator of Section
+  2.1, the minimiser of ||S X phi - S b|| (eq. (OLSc)), by Householder QR of
+  S X.
 hadamard: Definition 2.4, H_0 = 1 and H_m = [[H, H], [H, -H]] / sqrt(2),
   of size 2^m (the paper's size label is garbled; H_m is 2^m x 2^m here).
 srht_map: a k x p subsampled randomized Hadamard map sqrt(P/k) S H D on the
@@ -19,7 +22,11 @@ srht_map: a k x p subsampled randomized Hadamard map sqrt(P/k) S H D on the
 jl_omega: Omega = R^{-1} Pi^T, the k columns whose row products give the
   approximate generalised leverage scores of eq. (glev).
 
-Parity pins (tests/test_oracle_sketch.py): a hand-worked inverse-CDF example;
+Parity pins (tests/test_oracle_sketch.py): the compressed estimator with every
+row at unit scale equals the full least-squares solution, recovers the
+coefficients of a noise-free AR series from any sampled rows, has the p = 1
+closed form sum s^2 x b / sum s^2 x^2, and ignores a common row scale and row
+duplication; a hand-worked inverse-CDF example;
 E[S^T S] = I for the rescaled sampling matrix (Monte Carlo); H_m orthonormal
 and H_1 written out; E||Pi x||^2 = ||x||^2 for the SRHT map.
 """
@@ -60,6 +67,14 @@ def sketch_rows(y, p: int, idx, scale) -> np.ndarray:
     idx = np.asarray(idx, np.int64)
     scale = np.asarray(scale, np.float64)
     return np.column_stack([X[idx, :], b[idx]]) * scale[:, None]
+
+
+def compressed_solution(A) -> np.ndarray:
+    """Minimiser of ||S X phi - S b|| for the sketch A = [S X | S b] (c x (p+1),
+    sketch_rows): the compressed estimator of Section 2.1, eq. (OLSc)."""
+    A = np.asarray(A, np.float64)
+    Q, R = sla.qr(A[:, :-1], mode="economic")
+    return sla.solve_triangular(R, Q.T @ A[:, -1])
 
 
 def hadamard(mexp: int) -> np.ndarray:

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libtls.so")
 PREC_F64, PREC_MIXED = 0, 1
 SKETCH_LEVERAGE, SKETCH_UNIFORM = 0, 1
 JL_SRHT, JL_GAUSS = 0, 1
+EST_OLS, EST_SKETCH = 0, 1
 
 # Philox stream numbers of one fit (include/tls.h, tls_op_* documentation)
 RNG_UNIFORM_ROWS, RNG_SRHT_SIGNS, RNG_SRHT_ROWS, RNG_LEVERAGE, RNG_GAUSS = range(5)
@@ -50,7 +51,9 @@ class TlsOptions(ctypes.Structure):
         ("request_id", ctypes.c_uint64),
         ("no_graph", ctypes.c_int32),
         ("tick_steps", ctypes.c_int32),
-        ("reserved", ctypes.c_int64 * 3),
+        ("estimator", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
+        ("reserved", ctypes.c_int64 * 2),
     ]
 
 

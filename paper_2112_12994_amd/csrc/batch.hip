@@ -76,6 +76,21 @@ __global__ void zero_ints_kernel(int* x, int n) {
   if (i < n) x[i] = 0;
 }
 
+// The compressed estimator (eq. (OLSc)): phi = phi0 from the final QR, no
+// LSQR iterations; the fit is counted as finished (and appended to
+// done_list when given).
+__global__ void compressed_b_kernel(const Item* __restrict__ fits, const FitDesc* __restrict__ D,
+                                    int* __restrict__ counts, int* __restrict__ done_list) {
+  const int f = fits[blockIdx.x].fit;
+  const FitDesc& d = D[f];
+  for (int i = threadIdx.x; i < d.p; i += blockDim.x) d.phi[i] = d.phi0[i];
+  if (threadIdx.x == 0) {
+    d.st->done = 1;
+    atomicAdd(counts, 1);
+    if (done_list) done_list[atomicAdd(counts + 2, 1)] = f;
+  }
+}
+
 __global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* __restrict__ D,
                                  int mixed, double* __restrict__ coef, FitRec* __restrict__ rec) {
   const Item it = items[blockIdx.x];
@@ -316,7 +331,7 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
   TLS_CHECK(launch_triinv_b(2, k.pt, L_(fits), pmax, D, s));
   if (l.fits.n > 0) {
     hipLaunchKernelGGL(post_qr_b_kernel, dim3(l.fits.n), dim3(64), 0, s, I + l.fits.off, D,
-                       o.warm_start ? 1 : 0, mixed ? 1 : 0);
+                       o.warm_start || o.estimator == TLS_EST_SKETCH ? 1 : 0, mixed ? 1 : 0);
     TLS_CHECK(hipGetLastError());
   }
   return TLS_OK;
@@ -342,6 +357,13 @@ tls_status residual_class(const Item* rblocks, int nrblocks, const Item* fits, i
   TLS_CHECK(launch_resid_b(rblocks, nrblocks, D, pmax, s));
   TLS_CHECK(launch_colsum_b(3, fits, nfits, D, s));
   return TLS_OK;
+}
+
+hipError_t launch_compressed_b(const Item* fits, int nfits, const FitDesc* D, int* counts,
+                               int* done_list, hipStream_t s) {
+  if (nfits < 1) return hipSuccess;
+  hipLaunchKernelGGL(compressed_b_kernel, dim3(nfits), dim3(64), 0, s, fits, D, counts, done_list);
+  return hipGetLastError();
 }
 
 hipError_t collect_b(const Item* fits, int nfits, const FitDesc* D, int mixed, double* coef,
@@ -511,6 +533,10 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     const hipStream_t s = cs;
     const tls_status e0 = setup_class(ctx, c.key, c.pmax, c.ldqmax, I, l, D, o, s);
     if (e0 != TLS_OK) return e0;
+    if (o.estimator == TLS_EST_SKETCH) {
+      TLS_CHECK(launch_compressed_b(L_(fits), D, cnt, nullptr, s));
+      return residual_class(L_(rblocks), L_(fits), c.pmax, D, s);
+    }
     GraphSlot g_lsqr, g_inner, g_inner_tail;
     auto done = [&](tls_status e) {
       // the graphs' last launches finished at the host's final check

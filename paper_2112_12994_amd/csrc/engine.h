@@ -265,6 +265,7 @@ tls_status validate(int64_t n, int p, double tol, const tls_options& o) {
   if (o.precision != TLS_PREC_F64 && o.precision != TLS_PREC_MIXED) return TLS_EINVAL;
   if (o.sketch != TLS_SKETCH_LEVERAGE && o.sketch != TLS_SKETCH_UNIFORM) return TLS_EINVAL;
   if (o.jl_kind != TLS_JL_SRHT && o.jl_kind != TLS_JL_GAUSS) return TLS_EINVAL;
+  if (o.estimator != TLS_EST_OLS && o.estimator != TLS_EST_SKETCH) return TLS_EINVAL;
   if (p > P_MAX) return TLS_EUNSUPPORTED;
   if (n > (int64_t{1} << 40)) return TLS_EUNSUPPORTED;
   return TLS_OK;
@@ -452,6 +453,9 @@ tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool firs
 tls_status residual_class(const Item* rblocks, int nrblocks, const Item* fits, int nfits, int pmax,
                           FitDesc* D, hipStream_t s);
 // Coefficients (packed at item.idx) and result records (rec[k] for the k-th item).
+// The compressed estimator for the listed fits: phi = phi0, marked finished.
+hipError_t launch_compressed_b(const Item* fits, int nfits, const FitDesc* D, int* counts,
+                               int* done_list, hipStream_t s);
 hipError_t collect_b(const Item* fits, int nfits, const FitDesc* D, int mixed, double* coef,
                      FitRec* rec, hipStream_t s);
 // Per-fit status from a record and the returned coefficients.

@@ -59,7 +59,8 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 3, b.R, b.G, b.R1, b.R2, b.status, s));
   TLS_CHECK(launch_triinv(b.R, q, p, b.M, b.Mt, b.phi0, b.status + 1, s));
   hipLaunchKernelGGL(diag_minmax_kernel, dim3(1), dim3(64), 0, s, b.R, q, p, b.dminmax);
-  if (!o.warm_start) {
+  const bool compressed = o.estimator == TLS_EST_SKETCH;
+  if (!o.warm_start && !compressed) {
     hipLaunchKernelGGL(zero_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phi0, p);
   }
   TLS_CHECK(hipGetLastError());
@@ -133,7 +134,11 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     return TLS_OK;
   };
 
-  if (prec == TLS_PREC_F64) {
+  if (compressed) {
+    // the compressed problem's solution (eq. (OLSc)), no iterations
+    hipLaunchKernelGGL(copy_vec_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phi0, p, b.phi);
+    TLS_CHECK(hipGetLastError());
+  } else if (prec == TLS_PREC_F64) {
     const tls_status e = lsqr64(b.Yhat, o.profile != 0);
     if (e != TLS_OK) return e;
     total_iters = ho->st.iter;

@@ -325,6 +325,12 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
     if (setup_class(ctx, su.key, su.pmax, su.ldqmax, I, su.l, S->dD, o, s) != TLS_OK)
       return hipErrorUnknown;
     const ClassLists& l = su.l;
+    if (o.estimator == TLS_EST_SKETCH) {
+      // the compressed estimator: finished at set-up
+      e = launch_compressed_b(I + l.fits.off, l.fits.n, S->dD, S->dCounts, S->dDone, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     for (int k = 0; k < steps; ++k)
       if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, I + l.blocks.off,
                           l.blocks.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,

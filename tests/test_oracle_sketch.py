@@ -105,3 +105,46 @@ def test_philox_uniform_moments():
     z = oracle.philox_normal(100000, 2, 0, 42)
     assert abs(z.mean()) < 5 / np.sqrt(z.size)
     assert abs(z.var() - 1) < 5 * np.sqrt(2 / z.size)
+
+
+def test_compressed_solution_all_rows_is_ols(rng):
+    """With every row at unit scale the compressed problem is the full one."""
+    y = synth.ar_series(600, 5, rng, 0.3, 0.9)
+    m = y.size - 5
+    A = oracle.sketch_rows(y, 5, np.arange(m), np.ones(m))
+    ref = oracle.fit_qr(y, 5)["phi"]
+    assert oracle.rel_error(oracle.compressed_solution(A), ref) <= 1e-12
+
+
+def test_compressed_solution_noise_free_recovery(rng):
+    """A noise-free AR(3) recursion is solved exactly by any p or more
+    independent sampled rows, whatever their scales."""
+    phi = np.array([0.5, -0.3, 0.1])
+    y = np.zeros(400)
+    y[:3] = [1.0, -0.7, 0.4]
+    for t in range(3, y.size):
+        y[t] = phi[0] * y[t - 1] + phi[1] * y[t - 2] + phi[2] * y[t - 3]
+    m = y.size - 3
+    idx = rng.integers(0, 60, 12)  # early rows, before the recursion decays
+    A = oracle.sketch_rows(y, 3, idx, rng.uniform(0.5, 3.0, idx.size))
+    assert oracle.rel_error(oracle.compressed_solution(A), phi) <= 1e-10
+
+
+def test_compressed_solution_p1_closed_form(rng):
+    """p = 1: phi = sum s^2 x b / sum s^2 x^2 over the sampled rows."""
+    y = rng.standard_normal(300)
+    idx = rng.integers(0, 299, 40)
+    s = rng.uniform(0.2, 2.0, 40)
+    x, b = y[idx], y[idx + 1]
+    want = np.sum(s * s * x * b) / np.sum(s * s * x * x)
+    got = oracle.compressed_solution(oracle.sketch_rows(y, 1, idx, s))[0]
+    assert abs(got - want) <= 1e-13 * abs(want)
+
+
+def test_compressed_solution_scale_and_duplication_invariant(rng):
+    y = synth.ar_series(800, 6, rng, 0.3, 0.9)
+    idx = rng.integers(0, 794, 50)
+    A = oracle.sketch_rows(y, 6, idx, np.ones(50))
+    a = oracle.compressed_solution(A)
+    assert oracle.rel_error(oracle.compressed_solution(3.7 * A), a) <= 1e-13
+    assert oracle.rel_error(oracle.compressed_solution(np.vstack([A, A])), a) <= 1e-13
