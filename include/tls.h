@@ -215,6 +215,24 @@ tls_status tls_autotune(tls_ctx* ctx, int32_t precision, int32_t p_min, int32_t 
 tls_status tls_get_tuning(const tls_ctx* ctx, int8_t* table);
 tls_status tls_set_tuning(tls_ctx* ctx, const int8_t* table);
 
+/* ---- partial autocorrelations and order selection --------------------------
+ * The PACF at lags 1..pmax (Definition of the PACF; Algorithm 3's loop over
+ * orders): for lag h, the AR(h) fit on the series prefix of n - pmax + h
+ * samples (every fit has n - pmax rows), tau_h = its last coefficient
+ * phi_{h,h}.  All pmax fits run as one batched call with the options given
+ * (estimator OLS: exact PACF; estimator SKETCH: the compressed estimates of
+ * Algorithm 3).  *order (optional) receives the largest h with |tau_h| >=
+ * 1.96 / sqrt(rows), rows = n - pmax for OLS or the lag's c sampled rows
+ * for the compressed estimator (Algorithm 3's order rule), 0 when no lag
+ * passes.  d_series: device pointer, read on `stream`; pacf: host [pmax];
+ * lag_status (optional): host [pmax], each lag's fit status (lags whose fit
+ * failed do not count for the order).  Returns TLS_OK when every lag's fit
+ * is TLS_OK, else the first failing status; TLS_EINVAL for NULL pointers,
+ * pmax < 1 or n < 2 pmax + 1, TLS_EUNSUPPORTED for pmax > 1024. */
+tls_status tls_pacf_device(tls_ctx* ctx, const double* d_series, int64_t n, int32_t pmax,
+                           double tol, const tls_options* opt, void* stream, double* pacf,
+                           int32_t* order, tls_status* lag_status);
+
 /* ---- served continuous batching ----------------------------------------------
  * A server admits fit requests as they arrive and runs them to completion on
  * one device: each tick of its worker thread sets up the newly admitted fits

@@ -28,3 +28,4 @@ from .sketch import (  # noqa: F401
 )
 from .philox import philox4x32_10, philox_uniform, philox_normal  # noqa: F401
 from .lsqr import lsqr  # noqa: F401
+from .pacf import pacf, pacf_compressed, pacf_order  # noqa: F401

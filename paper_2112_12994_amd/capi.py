@@ -162,6 +162,8 @@ _SIGS = {
     "tls_wait": (_i32, [_vp, _u64, _dp, _c.POINTER(TlsResult), _c.POINTER(_i32)]),
     "tls_server_get_stats": (_i32, [_vp, _c.POINTER(TlsServerStats)]),
     "tls_server_destroy": (None, [_vp]),
+    "tls_pacf_device": (_i32, [_ctxp, _vp, _i64, _i32, _c.c_double, _c.POINTER(TlsOptions), _vp,
+                               _dp, _c.POINTER(_i32), _c.POINTER(_i32)]),
     "tls_autotune": (_i32, [_ctxp, _i32, _i32, _i32, _i64, _i64, _c.POINTER(_i32)]),
     "tls_get_tuning": (_i32, [_ctxp, _c.POINTER(_c.c_int8)]),
     "tls_set_tuning": (_i32, [_ctxp, _c.POINTER(_c.c_int8)]),
@@ -378,6 +380,17 @@ class Context:
                   stream=None):
         return lib.tls_op_gather(self._h, _ptr(d_y), d_y.numel(), p, mode, _ptr(d_idx),
                                  _ptr(d_scale), c, crows, ldq, _ptr(d_A), seed, fit, _stream(stream))
+
+    def pacf_device(self, d_series, pmax: int, tol: float = 1e-10, stream=None, **opts):
+        """tls_pacf_device: (status, pacf[pmax], order, per-lag statuses)."""
+        pacf = np.zeros(pmax)
+        order = _i32(0)
+        st = np.zeros(pmax, dtype=np.int32)
+        o = self._opt(opts)
+        s = lib.tls_pacf_device(self._h, _ptr(d_series), d_series.numel(), pmax, tol,
+                                ctypes.byref(o), _stream(stream), _dptr(pacf), ctypes.byref(order),
+                                st.ctypes.data_as(ctypes.POINTER(_i32)))
+        return s, pacf, order.value, st
 
     def autotune(self, precision: int, p_min: int, p_max: int, n_min: int, n_max: int) -> int:
         """Measure block lengths on the device; returns the table entries written."""

@@ -448,6 +448,45 @@ tls_status tls_fit_batch_device(tls_ctx* ctx, int32_t count, const double* const
   return first;
 }
 
+tls_status tls_pacf_device(tls_ctx* ctx, const double* d_series, int64_t n, int32_t pmax,
+                           double tol, const tls_options* opt, void* stream, double* pacf,
+                           int32_t* order, tls_status* lag_status) {
+  if (!ctx || !d_series || !pacf || pmax < 1) return TLS_EINVAL;
+  if (n < 2 * static_cast<int64_t>(pmax) + 1) return TLS_EINVAL;
+  if (pmax > P_MAX) return TLS_EUNSUPPORTED;
+  hipSetDevice(ctx->device);
+  // lag h: the AR(h) fit on the prefix of n - pmax + h samples (n - pmax rows each)
+  std::vector<const double*> ptr(pmax, d_series);
+  std::vector<int64_t> nh(pmax), off(pmax);
+  std::vector<int32_t> ph(pmax);
+  int64_t total = 0;
+  for (int32_t h = 1; h <= pmax; ++h) {
+    nh[h - 1] = n - pmax + h;
+    ph[h - 1] = h;
+    off[h - 1] = total;
+    total += h;
+  }
+  std::vector<double> coef(static_cast<size_t>(total));
+  std::vector<tls_result> res(pmax);
+  std::vector<tls_status> fs(pmax, TLS_OK);
+  const tls_options& o = eff_opt(ctx, opt);
+  const tls_status first = run_batch(ctx, pmax, nullptr, ptr.data(), nh.data(), ph.data(), tol, o,
+                                     pick_stream(ctx, stream), coef.data(), off.data(), res.data(),
+                                     fs.data());
+  const bool compressed = o.estimator == TLS_EST_SKETCH;
+  int32_t best = 0;
+  for (int32_t h = 1; h <= pmax; ++h) {
+    const double tau = coef[static_cast<size_t>(off[h - 1] + h - 1)];
+    pacf[h - 1] = tau;
+    if (lag_status) lag_status[h - 1] = fs[h - 1];
+    // 95% band of a zero PACF over the rows the lag-h estimate used
+    const double rows = compressed ? res[h - 1].sketch_rows : static_cast<double>(n - pmax);
+    if (fs[h - 1] == TLS_OK && rows > 0 && fabs(tau) >= 1.96 / sqrt(rows)) best = h;
+  }
+  if (order) *order = best;
+  return first;
+}
+
 // ---- step-level entry points -----------------------------------------------
 
 int64_t tls_num_blocks(int64_t n, int32_t p, int32_t B) {

@@ -94,8 +94,17 @@ def workload_serve(seed: int = 0, rate: float = 5000.0, duration: float = 60.0,
     return t, which, fits
 
 
+def workload_pacf(seed: int = 0, n: int = 2_000_000) -> Fit:
+    """AR(150), n = 2,000,000 (the size of the paper's PACF timing study,
+    Section 4.1), pole generator with moduli U[0.5, 0.95]; PACF up to lag 250."""
+    rng = np.random.default_rng(seed)
+    y = ar_series(n, 150, rng, 0.5, 0.95, "normal")
+    return Fit(y, 250, 8, 1e-10, {"workload": "pacf", "n": n, "seed": seed, "order": 150})
+
+
 WORKLOADS = {
     "ar3": workload_ar3,
     "ar100": workload_ar100,
     "ar500": workload_ar500,
+    "pacf": workload_pacf,
 }
