@@ -51,6 +51,10 @@ WORKLOAD_TEXT = {
     "pacf": "AR(150) series, n=2,000,000, 75 pole pairs with moduli U[0.5,0.95] and angles U(0,pi), "
             "N(0,1) innovations, seed 0; PACF at lags 1..250 (one AR(h) fit per lag on the prefix "
             "of n-250+h samples), exact (FP64 OLS) and compressed (sketch 8h rows), tol 1e-10",
+    "rh": "AR(5), AR(20), AR(100) series, n=2,000,000, pole moduli U[0.5,0.95], N(0,1) innovations, "
+          "seed 0, without and with 1000 outliers (+U[-3,3]+N(0,100), Section 4.2); lags 1..p on "
+          "the prefix windows of the PACF study; compressed estimates from the leverage (LSAR) and "
+          "repeated-halving (RH) sketches with c = 20h rows against the exact FP64 OLS fits",
     "serve": "Poisson arrivals at 5000 requests/s, each a series drawn with replacement from a pool "
              "of resident series with n=round(2^U(10,20)), p~U{2..200}, pole moduli U[0.5,0.95], "
              "N(0,1) innovations, seed 0; FP64, sketch 8p rows, tol 1e-10",
@@ -497,6 +501,66 @@ def pacf_bench(args, torch, synth, capi):
     print(json.dumps(line), flush=True)
 
 
+def rh_bench(args, torch, synth, capi):
+    """The LSAR-versus-RH comparison of Sections 4.1-4.2 on synthetic data:
+    relative percentage coefficient error (100 ||phi_c - phi*|| / ||phi*||)
+    of the compressed estimate at every lag 1..p, from the leverage sketch and
+    from the repeated-halving sketch, with and without outliers, and the time
+    of each batch of lag fits.  value: LSAR compressed lag fits/s on AR(100)."""
+    models = (5, 20, 100)
+    n = 2_000_000
+    ctx = capi.Context(0, precision=0)
+    stream = torch.cuda.current_stream()
+    out, value = [], None
+    for p in models:
+        for outliers in (False, True):
+            rng = np.random.default_rng(p)
+            y = synth.ar_series(n, p, rng, 0.5, 0.95)
+            if outliers:
+                y = synth.add_outliers(y, np.random.default_rng(1000 + p), 1000)
+            dy = torch.from_numpy(np.ascontiguousarray(y)).to("cuda:0")
+            lags = list(range(1, p + 1))
+            ptrs = [dy[: n - p + h] for h in lags]  # prefix views, no copies
+            res = {}
+            for name, opts in (("exact", {}),
+                               ("lsar", {"estimator": capi.EST_SKETCH, "gamma": 20}),
+                               ("rh", {"estimator": capi.EST_SKETCH, "gamma": 20,
+                                       "sketch": capi.SKETCH_RH})):
+                ctx.fit_batch_device(ptrs, lags, 1e-10, stream=stream, **opts)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s, fits = ctx.fit_batch_device(ptrs, lags, 1e-10, stream=stream, **opts)
+                torch.cuda.synchronize()
+                res[name] = (time.perf_counter() - t0, fits, s)
+            ex = res["exact"][1]
+            row = {"p": p, "outliers": outliers, "lags": len(lags)}
+            for name in ("exact", "lsar", "rh"):
+                t, fits, s = res[name]
+                row[name + "_seconds"] = t
+                row[name + "_status"] = capi.status_string(s)
+                if name != "exact":
+                    errs = [100 * np.linalg.norm(f["coef"] - e["coef"]) / np.linalg.norm(e["coef"])
+                            for f, e in zip(fits, ex)]
+                    row[name + "_mean_pct_err"] = float(np.mean(errs))
+                    row[name + "_max_pct_err"] = float(np.max(errs))
+            print(f"[bench] AR({p}) outliers={outliers}: exact {row['exact_seconds']:.3f} s, "
+                  f"LSAR {row['lsar_seconds']:.3f} s err {row['lsar_mean_pct_err']:.2f}%, "
+                  f"RH {row['rh_seconds']:.3f} s err {row['rh_mean_pct_err']:.2f}%",
+                  file=sys.stderr, flush=True)
+            if p == models[-1] and not outliers:
+                value = len(lags) / row["lsar_seconds"]
+            out.append(row)
+    line = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": 1e3 / value, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["rh"], "value": "LSAR compressed lag fits/s, AR(100)"},
+        "comparison": out,
+    }
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def serve_bench(args, torch, synth, capi):
     """Open-loop served workload: one thread submits requests at their Poisson
     arrival times (series resident in device memory, borrowed by the server),
@@ -688,6 +752,9 @@ def main():
         return
     if args.workload == "pacf":
         pacf_bench(args, torch, synth, capi)
+        return
+    if args.workload == "rh":
+        rh_bench(args, torch, synth, capi)
         return
     f = synth.WORKLOADS[args.workload](seed=0, **({"n": args.n} if args.n else {}))
     prec = 1 if args.precision == "mixed" else 0

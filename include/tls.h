@@ -56,6 +56,12 @@ const char* tls_status_string(tls_status s);
 
 #define TLS_SKETCH_LEVERAGE 0 /* uniform trials -> generalised leverage scores -> leverage sampling */
 #define TLS_SKETCH_UNIFORM 1  /* uniform trials only (Algorithm 1's sampling without the transform) */
+#define TLS_SKETCH_RH 2       /* repeated halving (Algorithm 4): nested uniform halvings of the rows
+                                 (row r is in level i when its stream-5 draw is below 2^-i), the
+                                 uniform sketch standing for the smallest; each level's rows are
+                                 scored (eq. (glev)) w.r.t. the sketch of the level below and sampled
+                                 into the next sketch, up to all rows.  Batched calls run such fits
+                                 one at a time; servers reject it (TLS_EUNSUPPORTED) */
 
 #define TLS_JL_SRHT 0     /* k x p subsampled randomized Hadamard map (Definition 2.4, Algorithm 1) */
 #define TLS_JL_GAUSS 1    /* k x p Gaussian map, entries N(0, 1/k) (eq. (glev)) */
@@ -263,8 +269,8 @@ typedef struct tls_server_stats {
 
 /* Create a server on ctx's device with `hbm_budget` bytes of device memory
  * (allocated now, at least 1 MiB) and at most `max_slots` fits in flight.
- * opt NULL = the context's options; only TLS_PREC_F64 is served
- * (TLS_EUNSUPPORTED otherwise).  TLS_ENOMEM if the budget cannot be allocated. */
+ * opt NULL = the context's options; only TLS_PREC_F64 is served, and not the
+ * repeated-halving sketch (TLS_EUNSUPPORTED otherwise).  TLS_ENOMEM if the budget cannot be allocated. */
 tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
                              const tls_options* opt, tls_server** out);
 
@@ -338,6 +344,13 @@ tls_status tls_op_scores(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t
 tls_status tls_op_sample(tls_ctx* ctx, int32_t prec, const void* d_scores, int64_t m,
                          const double* d_u, int32_t c, uint64_t seed, uint32_t fit,
                          int64_t* d_idx, double* d_scale, void* stream);
+
+/* Repeated halving (Algorithm 4): zero the entries r of d_scores (m values,
+ * FP64 or FP32 by prec, device) whose row is outside level `level` >= 0,
+ * i.e. whose Philox stream-5 draw u_r of (seed, fit) is not below 2^-level
+ * (level 0 keeps every row). */
+tls_status tls_op_rh_mask(tls_ctx* ctx, int32_t prec, void* d_scores, int64_t m, int32_t level,
+                          uint64_t seed, uint32_t fit, void* stream);
 
 /* Sketch rows scale_t * [X(idx_t, :), b(idx_t)] into d_A (device FP64,
  * row-major, crows x ldq; rows >= c and columns >= p+1 zeroed).

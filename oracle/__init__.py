@@ -24,7 +24,7 @@ from .leverage import (  # noqa: F401
 )
 from .sketch import (  # noqa: F401
     uniform_rows, leverage_sample, sketch_rows, hadamard, srht_map, jl_omega,
-    compressed_solution,
+    compressed_solution, rh_levels, rh_level_mask,
 )
 from .philox import philox4x32_10, philox_uniform, philox_normal  # noqa: F401
 from .lsqr import lsqr  # noqa: F401

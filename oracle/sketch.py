@@ -11,6 +11,10 @@ leverage_sample: Algorithm 2 / eq. (ldist): pi_i = l_i / sum_k l_k, c draws
   whose running score total exceeds u * total (inverse CDF, the running total
   accumulated in row order).
 sketch_rows: the sampled, rescaled rows of [X | b] (eq. (OLSc) with S applied).
+rh_levels, rh_level_mask: the nested uniform halvings of Algorithm 4 (repeated
+  halving): row r belongs to level i when its draw u_r < 2^-i (so each level
+  is a uniform half of the one before, in expectation), with as many levels
+  as halvings of m rows until a level holds no more than c rows.
 compressed_solution: the compressed (sketch-and-solve) estimator of Section
   2.1, the minimiser of ||S X phi - S b|| (eq. (OLSc)), by Householder QR of
   S X.
@@ -67,6 +71,19 @@ def sketch_rows(y, p: int, idx, scale) -> np.ndarray:
     idx = np.asarray(idx, np.int64)
     scale = np.asarray(scale, np.float64)
     return np.column_stack([X[idx, :], b[idx]]) * scale[:, None]
+
+
+def rh_levels(m: int, c: int) -> int:
+    """Halvings of m rows until a level holds no more than c rows (>= 1)."""
+    levels = 1
+    while (m >> levels) > c:
+        levels += 1
+    return levels
+
+
+def rh_level_mask(u, level: int) -> np.ndarray:
+    """Rows of level `level`: u_r < 2^-level (u: one uniform draw per row)."""
+    return np.asarray(u, np.float64) < 2.0 ** (-level)
 
 
 def compressed_solution(A) -> np.ndarray:

@@ -18,12 +18,12 @@ LIB_PATH = os.path.join(_PKG, "libtls.so")
 (TLS_OK, TLS_EINVAL, TLS_ERANK, TLS_ENOCONV, TLS_ENOMEM, TLS_EDEVICE, TLS_EUNSUPPORTED,
  TLS_EAGAIN) = range(8)
 PREC_F64, PREC_MIXED = 0, 1
-SKETCH_LEVERAGE, SKETCH_UNIFORM = 0, 1
+SKETCH_LEVERAGE, SKETCH_UNIFORM, SKETCH_RH = 0, 1, 2
 JL_SRHT, JL_GAUSS = 0, 1
 EST_OLS, EST_SKETCH = 0, 1
 
 # Philox stream numbers of one fit (include/tls.h, tls_op_* documentation)
-RNG_UNIFORM_ROWS, RNG_SRHT_SIGNS, RNG_SRHT_ROWS, RNG_LEVERAGE, RNG_GAUSS = range(5)
+RNG_UNIFORM_ROWS, RNG_SRHT_SIGNS, RNG_SRHT_ROWS, RNG_LEVERAGE, RNG_GAUSS, RNG_RH_LEVEL = range(6)
 TUNE_PRECS, TUNE_PBUCKETS, TUNE_MBUCKETS = 2, 11, 41
 TUNE_ENTRIES = TUNE_PRECS * TUNE_PBUCKETS * TUNE_MBUCKETS
 
@@ -173,6 +173,7 @@ _SIGS = {
                                _vp, _vp, _vp, _i32, _vp, _vp]),
     "tls_op_scores": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _vp, _i32, _vp, _vp]),
     "tls_op_sample": (_i32, [_ctxp, _i32, _vp, _i64, _vp, _i32, _u64, _u32, _vp, _vp, _vp]),
+    "tls_op_rh_mask": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _u64, _u32, _vp]),
     "tls_op_gather": (_i32, [_ctxp, _vp, _i64, _i32, _i32, _vp, _vp, _i32, _i32, _i32, _vp, _u64,
                              _u32, _vp]),
     "tls_op_qr": (_i32, [_ctxp, _vp, _i32, _i32, _i32, _vp, _c.POINTER(_i32), _vp]),
@@ -413,6 +414,10 @@ class Context:
         if t.size != TUNE_ENTRIES:
             raise ValueError("tuning table must have %d entries" % TUNE_ENTRIES)
         return lib.tls_set_tuning(self._h, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+
+    def op_rh_mask(self, prec, d_scores, m, level, seed, fit, stream=None):
+        return lib.tls_op_rh_mask(self._h, prec, _ptr(d_scores), m, level, seed, fit,
+                                  _stream(stream))
 
     def op_qr(self, d_A, crows, q, ldq, d_R, stream=None):
         st = _i32(0)

@@ -427,7 +427,9 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         }
     if (st[i] == TLS_OK) st[i] = make_plan(n[i], p[i], o, &plans[i], ctx);
     if (st[i] != TLS_OK) continue;
-    if (plans[i].ldq > BATCH_LDQ_MAX) {
+    // beyond the batched kernels' limits, or a repeated-halving sketch (its
+    // level loop is in the single-fit driver): one fit at a time
+    if (plans[i].ldq > BATCH_LDQ_MAX || o.sketch == TLS_SKETCH_RH) {
       singles.push_back(i);
       continue;
     }

@@ -129,6 +129,7 @@ enum RngStream : uint32_t {
   RNG_SRHT_ROWS = 2,     // rows of the randomized Hadamard map
   RNG_LEVERAGE = 3,      // leverage-score draws
   RNG_GAUSS = 4,         // Gaussian JL map (Box-Muller pairs)
+  RNG_RH_LEVEL = 5,      // repeated halving: row r belongs to level i when u_r < 2^-i
 };
 
 }  // namespace tls

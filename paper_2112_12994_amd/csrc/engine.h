@@ -220,6 +220,14 @@ int auto_block(int p, int64_t m) {
   return lg;
 }
 
+// Repeated halving: the number of halvings of the m rows until a level holds
+// no more than c rows (at least 1: one level is the plain leverage sketch).
+int rh_levels(int64_t m, int c) {
+  int l = 1;
+  while ((m >> l) > c) ++l;
+  return l;
+}
+
 // Buckets of the autotuner's table: order bucket ceil(log2 p), length bucket
 // ceil(log2 m) (clamped to the table).
 int tune_pbucket(int p) { return ilog2(p); }
@@ -263,7 +271,9 @@ tls_status validate(int64_t n, int p, double tol, const tls_options& o) {
   if (p < 1 || n < 2 * static_cast<int64_t>(p) + 1) return TLS_EINVAL;
   if (!(tol > 0.0 && tol < 1.0)) return TLS_EINVAL;
   if (o.precision != TLS_PREC_F64 && o.precision != TLS_PREC_MIXED) return TLS_EINVAL;
-  if (o.sketch != TLS_SKETCH_LEVERAGE && o.sketch != TLS_SKETCH_UNIFORM) return TLS_EINVAL;
+  if (o.sketch != TLS_SKETCH_LEVERAGE && o.sketch != TLS_SKETCH_UNIFORM &&
+      o.sketch != TLS_SKETCH_RH)
+    return TLS_EINVAL;
   if (o.jl_kind != TLS_JL_SRHT && o.jl_kind != TLS_JL_GAUSS) return TLS_EINVAL;
   if (o.estimator != TLS_EST_OLS && o.estimator != TLS_EST_SKETCH) return TLS_EINVAL;
   if (p > P_MAX) return TLS_EUNSUPPORTED;

@@ -44,16 +44,27 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   } else {
     TLS_CHECK(launch_gather(d_y, pl.m, p, 1, nullptr, nullptr, pl.c, pl.crows, pl.ldq, b.A, b.idx,
                             b.scale, seed, fit, s));
-    if (o.sketch == TLS_SKETCH_LEVERAGE) {
-      TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 1, b.R, b.G, b.R1, b.R2, b.status + 2, s));
-      TLS_CHECK(launch_triinv(b.R, q, p, b.M0, b.Mt0, nullptr, b.status + 3, s));
-      TLS_CHECK(launch_jl_omega(b.M0, p, pl.k, o.jl_kind, b.Pi, b.Om, seed, fit, s));
-      TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.Om, p, p, pl.k, invB, b.Omhat, ctx->tw, nullptr, s));
-      TLS_CHECK(launch_scores(prec, pl.lgn, b.Yhat, b.Omhat, pl.k, b.u, ctx->tw, pl.m, p, pl.L,
-                              pl.nblocks, s));
-      TLS_CHECK(launch_sample(prec, b.u, pl.m, nullptr, pl.c, b.idx, b.scale, b.swork, seed, fit, s));
-      TLS_CHECK(launch_gather(d_y, pl.m, p, 0, b.idx, b.scale, pl.c, pl.crows, pl.ldq, b.A,
-                              nullptr, nullptr, seed, fit, s));
+    if (o.sketch == TLS_SKETCH_LEVERAGE || o.sketch == TLS_SKETCH_RH) {
+      // Leverage sketch: one level (scores of all rows w.r.t. the uniform
+      // sketch).  Repeated halving: the uniform sketch stands for the
+      // smallest of the nested halvings; going up, each level's rows are
+      // scored w.r.t. the sketch of the level below and sampled into the
+      // next sketch, the last level being all rows.
+      const int levels = o.sketch == TLS_SKETCH_RH ? rh_levels(pl.m, pl.c) : 1;
+      for (int lev = levels - 1; lev >= 0; --lev) {
+        TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 1, b.R, b.G, b.R1, b.R2, b.status + 2, s));
+        TLS_CHECK(launch_triinv(b.R, q, p, b.M0, b.Mt0, nullptr, b.status + 3, s));
+        TLS_CHECK(launch_jl_omega(b.M0, p, pl.k, o.jl_kind, b.Pi, b.Om, seed, fit, s));
+        TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.Om, p, p, pl.k, invB, b.Omhat, ctx->tw, nullptr,
+                                    s));
+        TLS_CHECK(launch_scores(prec, pl.lgn, b.Yhat, b.Omhat, pl.k, b.u, ctx->tw, pl.m, p, pl.L,
+                                pl.nblocks, s));
+        if (lev > 0) TLS_CHECK(launch_rh_mask(prec, b.u, pl.m, lev, seed, fit, s));
+        TLS_CHECK(launch_sample(prec, b.u, pl.m, nullptr, pl.c, b.idx, b.scale, b.swork, seed, fit,
+                                s, static_cast<uint64_t>(lev) * pl.c));
+        TLS_CHECK(launch_gather(d_y, pl.m, p, 0, b.idx, b.scale, pl.c, pl.crows, pl.ldq, b.A,
+                                nullptr, nullptr, seed, fit, s));
+      }
     }
   }
   TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 3, b.R, b.G, b.R1, b.R2, b.status, s));
@@ -565,6 +576,15 @@ tls_status tls_op_scores(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t
   TLS_CHECK(launch_small_rfft(pr, lgn, d_omega, p, p, k, 1.0 / B, ctx->ws, ctx->tw, nullptr, s));
   TLS_CHECK(launch_scores(pr, lgn, d_spec, ctx->ws, k, d_scores, ctx->tw, n - p, p, B - p + 1,
                           static_cast<int>(nb), s));
+  return TLS_OK;
+}
+
+tls_status tls_op_rh_mask(tls_ctx* ctx, int32_t prec, void* d_scores, int64_t m, int32_t level,
+                          uint64_t seed, uint32_t fit, void* stream) {
+  if (!ctx || !d_scores || m < 1 || level < 0) return TLS_EINVAL;
+  hipSetDevice(ctx->device);
+  TLS_CHECK(launch_rh_mask(prec == TLS_PREC_F64 ? PREC_F64 : PREC_F32, d_scores, m, level, seed,
+                           fit, pick_stream(ctx, stream)));
   return TLS_OK;
 }
 

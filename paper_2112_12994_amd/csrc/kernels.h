@@ -53,9 +53,13 @@ hipError_t launch_philox_uniform(double* out, int64_t count, uint32_t stream, ui
 hipError_t launch_gather(const double* y, int64_t m, int p, int mode, const int64_t* idx,
                          const double* scale, int c, int crows, int ldq, double* A, int64_t* idx_out,
                          double* scale_out, uint64_t seed, uint32_t fit, hipStream_t st);
+// draw0: counter of the first Philox draw (draw t uses counter draw0 + t)
 hipError_t launch_sample(int prec, const void* scores, int64_t m, const double* u, int c,
                          int64_t* idx, double* scale, double* work, uint64_t seed, uint32_t fit,
-                         hipStream_t st);
+                         hipStream_t st, uint64_t draw0 = 0);
+// Repeated halving: scores of rows outside level `level` set to zero.
+hipError_t launch_rh_mask(int prec, void* scores, int64_t m, int level, uint64_t seed,
+                          uint32_t fit, hipStream_t st);
 size_t sample_work_doubles(int64_t m);
 hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, double* Om,
                            uint64_t seed, uint32_t fit, hipStream_t st);

@@ -518,7 +518,7 @@ tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
                              const tls_options* opt, tls_server** out) {
   if (!ctx || !out || max_slots < 1 || hbm_budget < (size_t{1} << 20)) return TLS_EINVAL;
   const tls_options o = opt ? *opt : ctx->opt;
-  if (o.precision != TLS_PREC_F64) return TLS_EUNSUPPORTED;
+  if (o.precision != TLS_PREC_F64 || o.sketch == TLS_SKETCH_RH) return TLS_EUNSUPPORTED;
   if (hipSetDevice(ctx->device) != hipSuccess) return TLS_EDEVICE;
   auto* S = new tls_server();
   S->ctx = ctx;

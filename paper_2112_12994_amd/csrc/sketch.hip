@@ -152,11 +152,11 @@ __device__ __forceinline__ void draw_body(const T* __restrict__ s, int64_t m,
                                           const double* __restrict__ u, int c,
                                           int64_t* __restrict__ idx,
                                           double* __restrict__ scale, uint64_t seed,
-                                          uint32_t fit, int t) {
+                                          uint32_t fit, int t, uint64_t draw0 = 0) {
   __shared__ double seg[CHUNK + CHUNK / 64];  // row e of the chunk at e + e / 64
   const int lane = threadIdx.x;
   const double total = pre[nch];
-  const double ut = u ? u[t] : philox_u01(static_cast<uint64_t>(t), RNG_LEVERAGE, fit, seed);
+  const double ut = u ? u[t] : philox_u01(draw0 + static_cast<uint64_t>(t), RNG_LEVERAGE, fit, seed);
   const double target = ut * total;
   int lo = 0, hi = nch - 1;  // invariant: pre[lo] <= target
   while (lo < hi) {
@@ -218,8 +218,20 @@ __global__ __launch_bounds__(64) void draw_kernel(const T* __restrict__ s, int64
                                                   const double* __restrict__ u, int c,
                                                   int64_t* __restrict__ idx,
                                                   double* __restrict__ scale, uint64_t seed,
-                                                  uint32_t fit) {
-  draw_body<T>(s, m, pre, nch, u, c, idx, scale, seed, fit, blockIdx.x);
+                                                  uint32_t fit, uint64_t draw0) {
+  draw_body<T>(s, m, pre, nch, u, c, idx, scale, seed, fit, blockIdx.x, draw0);
+}
+
+// Repeated halving: zero the scores of the rows outside level `level` (row r
+// is kept when its level draw u_r < 2^-level: nested uniform subsets of
+// about m / 2^level rows).
+template <typename T>
+__global__ __launch_bounds__(256) void rh_mask_kernel(T* __restrict__ s, int64_t m, int level,
+                                                      uint64_t seed, uint32_t fit) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= m) return;
+  const double u = philox_u01(static_cast<uint64_t>(r), RNG_RH_LEVEL, fit, seed);
+  if (!(u < ldexp(1.0, -level))) s[r] = T(0);
 }
 
 // Pi (k x p) and Omega = M Pi^T (p x k, column-major).  kind 0: subsampled
@@ -300,9 +312,22 @@ size_t sample_work_doubles(int64_t m) {
   return static_cast<size_t>(2 * nch + 1);
 }
 
+hipError_t launch_rh_mask(int prec, void* scores, int64_t m, int level, uint64_t seed,
+                          uint32_t fit, hipStream_t st) {
+  if (m < 1 || level < 0) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>((m + 255) / 256));
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL((rh_mask_kernel<double>), grid, dim3(256), 0, st, static_cast<double*>(scores),
+                       m, level, seed, fit);
+  else
+    hipLaunchKernelGGL((rh_mask_kernel<float>), grid, dim3(256), 0, st, static_cast<float*>(scores),
+                       m, level, seed, fit);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample(int prec, const void* scores, int64_t m, const double* u, int c,
                          int64_t* idx, double* scale, double* work, uint64_t seed, uint32_t fit,
-                         hipStream_t st) {
+                         hipStream_t st, uint64_t draw0) {
   if (m < 1 || c < 1) return hipErrorInvalidValue;
   const int nch = static_cast<int>((m + CHUNK - 1) / CHUNK);
   double* sums = work;
@@ -318,11 +343,11 @@ hipError_t launch_sample(int prec, const void* scores, int64_t m, const double* 
   if (prec == PREC_F64) {
     hipLaunchKernelGGL((draw_kernel<double>), dim3(c), dim3(64), 0, st,
                        static_cast<const double*>(scores), m, pre, nch, u, c, idx, scale, seed,
-                       fit);
+                       fit, draw0);
   } else {
     hipLaunchKernelGGL((draw_kernel<float>), dim3(c), dim3(64), 0, st,
                        static_cast<const float*>(scores), m, pre, nch, u, c, idx, scale, seed,
-                       fit);
+                       fit, draw0);
   }
   return hipGetLastError();
 }

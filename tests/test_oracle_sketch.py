@@ -148,3 +148,21 @@ def test_compressed_solution_scale_and_duplication_invariant(rng):
     a = oracle.compressed_solution(A)
     assert oracle.rel_error(oracle.compressed_solution(3.7 * A), a) <= 1e-13
     assert oracle.rel_error(oracle.compressed_solution(np.vstack([A, A])), a) <= 1e-13
+
+
+def test_rh_levels_are_nested_halvings():
+    """Algorithm 4's halvings: each level is contained in the one below and
+    holds about half its rows; the level count stops at <= c rows."""
+    m = 1 << 16
+    u = oracle.philox_uniform(m, 5, 3, 11)
+    prev = np.ones(m, dtype=bool)
+    for lev in range(1, 8):
+        cur = oracle.rh_level_mask(u, lev)
+        assert np.all(prev[cur])  # nested
+        frac = cur.sum() / max(prev.sum(), 1)
+        assert abs(frac - 0.5) <= 4 * np.sqrt(0.25 / prev.sum())
+        prev = cur
+    assert oracle.rh_levels(4194204, 800) == 13  # 4194204 / 2^13 = 512 <= 800 < 1024
+    assert oracle.rh_levels(1000, 800) == 1
+    assert oracle.rh_levels(1601, 800) == 1  # one halving leaves 800 rows
+    assert oracle.rh_levels(1602, 800) == 2
