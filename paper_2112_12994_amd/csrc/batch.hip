@@ -91,6 +91,17 @@ __global__ void compressed_b_kernel(const Item* __restrict__ fits, const FitDesc
   }
 }
 
+// flags[k] = 1 when the k-th listed fit has finished (which 0: its LSQR,
+// 1: its mixed-precision refinement).
+__global__ void done_flags_b_kernel(const Item* __restrict__ fits, int nfits,
+                                    const FitDesc* __restrict__ D, int which,
+                                    int* __restrict__ flags) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nfits) return;
+  const FitDesc& d = D[fits[k].fit];
+  flags[k] = (which == 0 ? d.st->done : d.rst->done) ? 1 : 0;
+}
+
 __global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* __restrict__ D,
                                  int mixed, double* __restrict__ coef, FitRec* __restrict__ rec) {
   const Item it = items[blockIdx.x];
@@ -366,6 +377,14 @@ hipError_t launch_compressed_b(const Item* fits, int nfits, const FitDesc* D, in
   return hipGetLastError();
 }
 
+hipError_t launch_done_flags_b(const Item* fits, int nfits, const FitDesc* D, int which,
+                               int* flags, hipStream_t s) {
+  if (nfits < 1) return hipSuccess;
+  hipLaunchKernelGGL(done_flags_b_kernel, dim3((nfits + 255) / 256), dim3(256), 0, s, fits, nfits, D,
+                     which, flags);
+  return hipGetLastError();
+}
+
 hipError_t collect_b(const Item* fits, int nfits, const FitDesc* D, int mixed, double* coef,
                      FitRec* rec, hipStream_t s) {
   if (nfits < 1) return hipSuccess;
@@ -485,6 +504,8 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
   const size_t ncounts = 4 * std::max<size_t>(classes.size(), 1);
   const size_t off_D = reserve(sizeof(FitDesc) * std::max(nb, 1));
   const size_t off_items = reserve(sizeof(Item) * std::max<size_t>(items.size(), 1));
+  const size_t off_items2 = reserve(sizeof(Item) * std::max<size_t>(items.size(), 1));
+  const size_t off_flags = reserve(sizeof(int) * std::max(nb, 1));
   const size_t off_counts = reserve(sizeof(int) * ncounts);
   const size_t off_coef = reserve(sizeof(double) * std::max<int64_t>(coef_total, 1));
   const size_t off_rec = reserve(sizeof(FitRec) * std::max(nb, 1));
@@ -504,6 +525,8 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
               tol, &desc[j]);
   }
   FitDesc* D = reinterpret_cast<FitDesc*>(base + off_D);
+  Item* items2 = reinterpret_cast<Item*>(base + off_items2);  // compacted step lists
+  int* dflags = reinterpret_cast<int*>(base + off_flags);
   const Item* I = reinterpret_cast<const Item*>(base + off_items);
   int* counts = reinterpret_cast<int*>(base + off_counts);
   double* dcoef = reinterpret_cast<double*>(base + off_coef);
@@ -540,23 +563,85 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       return residual_class(L_(rblocks), L_(fits), c.pmax, D, s);
     }
     GraphSlot g_lsqr, g_inner, g_inner_tail;
+    auto drop_graphs = [&]() {
+      for (GraphSlot* g : {&g_lsqr, &g_inner, &g_inner_tail})
+        if (g->exec) {
+          hipGraphExecDestroy(g->exec);
+          g->exec = nullptr;
+        }
+    };
     auto done = [&](tls_status e) {
       // the graphs' last launches finished at the host's final check
-      for (GraphSlot* g : {&g_lsqr, &g_inner, &g_inner_tail})
-        if (g->exec) hipGraphExecDestroy(g->exec);
+      drop_graphs();
       return e;
     };
+
+    // The step lists (blocks, columns, fits) of the fits still iterating.
+    // When at least half of a list's fits have finished, the lists are
+    // rebuilt without them (in this class's region of the second item
+    // buffer), so that the stragglers do not pay for launches over every
+    // finished fit's blocks; the graphs are captured again.
+    struct Lists {
+      const Item *blocks, *cols, *fits;
+      int nblocks, ncols, nfits;
+      std::vector<int> desc;  // descriptor index of each fit item, in list order
+    };
+    auto full_lists = [&]() {
+      Lists sl{I + l.blocks.off, I + l.cols.off, I + l.fits.off, l.blocks.n, l.cols.n, l.fits.n, {}};
+      for (int j = 0; j < c.count; ++j) sl.desc.push_back(c.first + j);
+      return sl;
+    };
+    std::vector<int> hflags;
+    // which: 0 = LSQR finished (st->done), 1 = refinement finished (rst->done)
+    auto compact = [&](Lists& sl, int which) -> tls_status {
+      int* dfl = dflags + c.first;
+      TLS_CHECK(launch_done_flags_b(sl.fits, sl.nfits, D, which, dfl, s));
+      hflags.resize(sl.nfits);
+      TLS_CHECK(hipMemcpyAsync(hflags.data(), dfl, sl.nfits * sizeof(int), hipMemcpyDeviceToHost, s));
+      TLS_CHECK(hipStreamSynchronize(s));
+      std::vector<Item> b2, c2, f2;
+      std::vector<int> keep;
+      for (int k = 0; k < sl.nfits; ++k) {
+        if (hflags[k]) continue;
+        const int j = sl.desc[k];
+        const Plan& pl = plans[order[j]];
+        for (int t = 0; t < pl.nblocks; ++t) b2.push_back({j, t});
+        for (int t = 0; t <= pl.p; ++t) c2.push_back({j, t});
+        f2.push_back({j, 0});
+        keep.push_back(j);
+      }
+      if (keep.empty()) return TLS_OK;
+      Item* base2 = items2;
+      TLS_CHECK(hipMemcpyAsync(base2 + l.blocks.off, b2.data(), b2.size() * sizeof(Item),
+                               hipMemcpyHostToDevice, s));
+      TLS_CHECK(hipMemcpyAsync(base2 + l.cols.off, c2.data(), c2.size() * sizeof(Item),
+                               hipMemcpyHostToDevice, s));
+      TLS_CHECK(hipMemcpyAsync(base2 + l.fits.off, f2.data(), f2.size() * sizeof(Item),
+                               hipMemcpyHostToDevice, s));
+      // the host vectors must outlive the copies
+      TLS_CHECK(hipStreamSynchronize(s));
+      sl = Lists{base2 + l.blocks.off, base2 + l.cols.off, base2 + l.fits.off,
+                 static_cast<int>(b2.size()), static_cast<int>(c2.size()),
+                 static_cast<int>(f2.size()), keep};
+      drop_graphs();
+      return TLS_OK;
+    };
+    auto worth_compacting = [](int remaining, int listed) {
+      return listed >= 8 && remaining * 2 <= listed;
+    };
+#define SL_(lst) sl.lst, sl.n##lst
 
     // FP64 LSQR over the class from phi0 (fits already done skip every
     // step); cnt[0] holds the number of finished fits.  Every chunk after
     // the first is the same sequence of launches: a graph when enabled.
     auto lsqr64 = [&](PassTimer* t) -> tls_status {
+      Lists sl = full_lists();
       for (int launched = 0;; launched += B_CHUNK_ITERS) {
         auto chunk = [&, launched]() -> tls_status {
           for (int it = 0; it < B_CHUNK_ITERS; ++it) {
             const tls_status e = lsqr_step_class(ctx, c.key.lgn, c.pmax, c.key.mlds != 0,
-                                                 launched == 0 && it == 0, L_(blocks), L_(cols),
-                                                 L_(fits), D, cnt, nullptr, t, s);
+                                                 launched == 0 && it == 0, SL_(blocks), SL_(cols),
+                                                 SL_(fits), D, cnt, nullptr, t, s);
             if (e != TLS_OK) return e;
           }
           return TLS_OK;
@@ -566,6 +651,10 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         TLS_CHECK(hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         TLS_CHECK(hipStreamSynchronize(s));
         if (hc[0] >= c.count || launched > max_iter) break;
+        if (!t && worth_compacting(c.count - hc[0], sl.nfits)) {
+          const tls_status ec = compact(sl, 0);
+          if (ec != TLS_OK) return ec;
+        }
       }
       return TLS_OK;
     };
@@ -573,14 +662,15 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       const tls_status e = lsqr64(tm);
       if (e != TLS_OK) return done(e);
     } else {
+      Lists sl = full_lists();
       for (int outer = 0; outer <= max_refine; ++outer) {
         if (hipError_t he = batch_zero_ints(cnt, 2, s)) return done(hip_status(he));
         auto outer_step = [&]() -> hipError_t {
-          hipError_t he = launch_small_rfft_b(PREC_F64, c.key.lgn, 2, L_(fits), D, ctx->tw, s);
-          if (!he) he = launch_toep_b(PREC_F64, c.key.lgn, BP_OUTER64, L_(blocks), D, ctx->consts,
+          hipError_t he = launch_small_rfft_b(PREC_F64, c.key.lgn, 2, SL_(fits), D, ctx->tw, s);
+          if (!he) he = launch_toep_b(PREC_F64, c.key.lgn, BP_OUTER64, SL_(blocks), D, ctx->consts,
                                       ctx->tw, s);
-          if (!he) he = launch_colsum_b(1, L_(cols), D, s);
-          if (!he) he = launch_refine_outer_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s);
+          if (!he) he = launch_colsum_b(1, SL_(cols), D, s);
+          if (!he) he = launch_refine_outer_b(c.key.lgn, SL_(fits), c.pmax, D, cnt, ctx->tw, s);
           return he;
         };
         if (hipError_t he = outer_step()) return done(hip_status(he));
@@ -589,11 +679,11 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
           auto inner = [&, it, kend]() -> tls_status {
             for (int k = it; k < kend; ++k) {
               if (tm) TLS_CHECK(tm->begin(s));
-              TLS_CHECK(launch_toep_b(PREC_F32, c.key.lgn, BP_INNER32, L_(blocks), D, ctx->consts,
+              TLS_CHECK(launch_toep_b(PREC_F32, c.key.lgn, BP_INNER32, SL_(blocks), D, ctx->consts,
                                       ctx->tw, s));
               if (tm) TLS_CHECK(tm->end(s));
-              TLS_CHECK(launch_colsum_b(2, L_(cols), D, s));
-              TLS_CHECK(launch_refine_cg_b(c.key.lgn, L_(fits), c.pmax, D, cnt, ctx->tw, s));
+              TLS_CHECK(launch_colsum_b(2, SL_(cols), D, s));
+              TLS_CHECK(launch_refine_cg_b(c.key.lgn, SL_(fits), c.pmax, D, cnt, ctx->tw, s));
             }
             return TLS_OK;
           };
@@ -603,9 +693,14 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
           if (hipError_t he = hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s))
             return done(hip_status(he));
           if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
-          if (hc[1] >= c.count) break;
+          if (hc[1] >= sl.nfits) break;
         }
-        if (hc[0] >= c.count) break;
+        // counts[0]: fits of the current lists whose refinement has finished
+        if (hc[0] >= sl.nfits) break;
+        if (!tm && worth_compacting(sl.nfits - hc[0], sl.nfits)) {
+          const tls_status ec = compact(sl, 1);
+          if (ec != TLS_OK) return done(ec);
+        }
       }
       // FP64 finish for the fits whose refinement stopped short
       if (hipError_t he = batch_zero_ints(cnt, 4, s)) return done(hip_status(he));
@@ -616,10 +711,12 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         return done(hip_status(he));
       if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
       if (hc[0] < c.count) {
+        drop_graphs();
         const tls_status e = lsqr64(nullptr);
         if (e != TLS_OK) return done(e);
       }
     }
+#undef SL_
     return done(residual_class(L_(rblocks), L_(fits), c.pmax, D, s));
   };
 

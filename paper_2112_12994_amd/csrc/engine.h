@@ -463,6 +463,9 @@ tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool firs
 tls_status residual_class(const Item* rblocks, int nrblocks, const Item* fits, int nfits, int pmax,
                           FitDesc* D, hipStream_t s);
 // Coefficients (packed at item.idx) and result records (rec[k] for the k-th item).
+// flags[k] = 1 when the k-th listed fit has finished (which 0: LSQR, 1: refinement).
+hipError_t launch_done_flags_b(const Item* fits, int nfits, const FitDesc* D, int which,
+                               int* flags, hipStream_t s);
 // The compressed estimator for the listed fits: phi = phi0, marked finished.
 hipError_t launch_compressed_b(const Item* fits, int nfits, const FitDesc* D, int* counts,
                                int* done_list, hipStream_t s);

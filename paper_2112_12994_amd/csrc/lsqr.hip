@@ -351,7 +351,7 @@ template <int LGN, typename TS>
 hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, const double* Mt,
                     double* v, double* w, double* z, const double* phi0, double* phi, void* Vhat,
                     const Twiddles& tw, hipStream_t stream) {
-  constexpr int NT = 256;
+  constexpr int NT = 512;  // M in LDS: 8 wavefronts
   const size_t small = 2 * static_cast<size_t>(p) * sizeof(double);
   const size_t with_m = small + static_cast<size_t>(p) * (p | 1) * sizeof(double);
   if (lsqr_step_lds(LGN, p)) {
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(NT) void refine_cg_b_kernel(const Item* __restrict_
 template <int LGN, typename TS>
 hipError_t step_b(const Item* fits, int nfits, int pmax, bool mlds, const FitDesc* D, int* counts,
                   int* done_list, const Twiddles& tw, hipStream_t s) {
-  constexpr int NT = 256;
+  constexpr int NT = 512;  // as the single-fit step
   const size_t small = 2 * static_cast<size_t>(pmax) * sizeof(double);
   const size_t with_m = small + static_cast<size_t>(pmax) * (pmax | 1) * sizeof(double);
   const cx<double>* tab = static_cast<const cx<double>*>(tw.d64);
