@@ -74,8 +74,18 @@ __device__ __forceinline__ double column_sum(const double* __restrict__ col, int
                                              double* scratch) {
   static_assert(NT >= 256, "column_sum needs 256 threads");
   double s = 0.0;
-  if (threadIdx.x < 256)
-    for (int b = threadIdx.x; b < nblocks; b += 256) s += col[b];
+  if (threadIdx.x < 256) {
+    // eight loads in flight per round, added in the plain loop's order
+    int b = threadIdx.x;
+    for (; b + 7 * 256 < nblocks; b += 8 * 256) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = col[b + 256 * k];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; b < nblocks; b += 256) s += col[b];
+  }
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();

@@ -358,19 +358,6 @@ __global__ void copy_vec_kernel(const double* a, int n, double* b) {
   if (i < n) b[i] = a[i];
 }
 
-__global__ void diag_minmax_kernel(const double* R, int q, int p, double* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double a = 0.0, b = INFINITY;
-    for (int i = 0; i < p; ++i) {
-      const double d = fabs(R[static_cast<size_t>(i) * q + i]);
-      a = fmax(a, d);
-      b = fmin(b, d);
-    }
-    out[0] = a;
-    out[1] = b;
-  }
-}
-
 __global__ void zero_kernel(double* x, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0.0;

@@ -68,8 +68,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     }
   }
   TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 3, b.R, b.G, b.R1, b.R2, b.status, s));
-  TLS_CHECK(launch_triinv(b.R, q, p, b.M, b.Mt, b.phi0, b.status + 1, s));
-  hipLaunchKernelGGL(diag_minmax_kernel, dim3(1), dim3(64), 0, s, b.R, q, p, b.dminmax);
+  TLS_CHECK(launch_triinv(b.R, q, p, b.M, b.Mt, b.phi0, b.status + 1, s, b.dminmax));
   const bool compressed = o.estimator == TLS_EST_SKETCH;
   if (!o.warm_start && !compressed) {
     hipLaunchKernelGGL(zero_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phi0, p);

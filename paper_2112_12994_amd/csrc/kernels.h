@@ -84,8 +84,9 @@ inline int reg_tiles(int n) {
 }
 hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sweeps, double* R,
                      double* G, double* R1, double* R2, int* status, hipStream_t st);
+// dminmax (optional): max and min |R_ii| over the first p diagonal entries.
 hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, double* phi0,
-                         int* status, hipStream_t st);
+                         int* status, hipStream_t st, double* dminmax = nullptr);
 
 // LSQR p-side step and state
 struct LsqrState {

@@ -580,12 +580,14 @@ __global__ __launch_bounds__(1024) void triinv_reg32_kernel(const double* __rest
 }
 
 // After a register inverse (which also wrote M^T): phi0 = M R[:p, p] (the
-// compressed problem's solution) and the rank test min|R_ii| <= p u max|R_ii|.
+// compressed problem's solution), the rank test min|R_ii| <= p u max|R_ii|,
+// and (when dminmax is given) that max and min.
 template <int NT>
 __device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R, int q,
                                                            int p, const double* __restrict__ M,
                                                            double* __restrict__ phi0,
-                                                           int* __restrict__ status) {
+                                                           int* __restrict__ status,
+                                                           double* __restrict__ dminmax = nullptr) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   if (phi0 && q > p) {
     // phi0_i = M[i, i:] R[i:, p]: one wavefront per row, lanes over the row
@@ -611,6 +613,10 @@ __device__ __forceinline__ void triinv_finish_body(const double* __restrict__ R,
     }
     if (threadIdx.x == 0 && status && !(b > static_cast<double>(p) * 0x1p-53 * a))
       atomicOr(status, 4);
+    if (threadIdx.x == 0 && dminmax) {
+      dminmax[0] = a;
+      dminmax[1] = b;
+    }
   }
 }
 
@@ -618,8 +624,9 @@ template <int NT>
 __global__ __launch_bounds__(NT) void triinv_finish_kernel(const double* __restrict__ R, int q,
                                                            int p, const double* __restrict__ M,
                                                            double* __restrict__ phi0,
-                                                           int* __restrict__ status) {
-  triinv_finish_body<NT>(R, q, p, M, phi0, status);
+                                                           int* __restrict__ status,
+                                                           double* __restrict__ dminmax) {
+  triinv_finish_body<NT>(R, q, p, M, phi0, status, dminmax);
 }
 
 
@@ -1112,8 +1119,9 @@ __global__ __launch_bounds__(256) void inv_blk_finish_kernel(const double* __res
                                                              int p, const double* __restrict__ M,
                                                              double* __restrict__ Mt,
                                                              double* __restrict__ phi0,
-                                                             int* __restrict__ status) {
-  inv_blk_finish_body(R, q, p, M, Mt, phi0, status, nullptr, blockIdx.x);
+                                                             int* __restrict__ status,
+                                                             double* __restrict__ dminmax) {
+  inv_blk_finish_body(R, q, p, M, Mt, phi0, status, dminmax, blockIdx.x);
 }
 
 void chol_blk_launch(double* G, int ldq, int q, int crows, int shift_mode, double* R, int* status,
@@ -1134,13 +1142,13 @@ void chol_blk_launch(double* G, int ldq, int q, int crows, int shift_mode, doubl
 
 // Mt doubles as the store of the diagonal block inverses until the finish.
 void inv_blk_launch(const double* R, int q, int p, double* M, double* Mt, double* phi0,
-                    int* status, hipStream_t st) {
+                    int* status, double* dminmax, hipStream_t st) {
   const int nbp = (p + NBK - 1) / NBK;
   hipLaunchKernelGGL(inv_blk_diag_kernel, dim3(nbp), dim3(256), 0, st, R, q, p, M, Mt);
   for (int d = 1; d < nbp; ++d)
     hipLaunchKernelGGL(inv_blk_off_kernel, dim3(nbp - d), dim3(256), 0, st, R, q, p, M, Mt, d);
   hipLaunchKernelGGL(inv_blk_finish_kernel, dim3(nbp * nbp + nbp), dim3(256), 0, st, R, q, p, M, Mt,
-                     phi0, status);
+                     phi0, status, dminmax);
 }
 
 }  // namespace
@@ -1312,15 +1320,15 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sw
 }
 
 hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, double* phi0,
-                         int* status, hipStream_t st) {
+                         int* status, hipStream_t st, double* dminmax) {
   if (p < 1 || q < p) return hipErrorInvalidValue;
   if (reg_tiles(p) != 0) {
     hipError_t e = tri_inverse(R, q, p, M, p, Mt, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((triinv_finish_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, phi0,
-                       status);
+                       status, dminmax);
   } else {
-    inv_blk_launch(R, q, p, M, Mt, phi0, status, st);
+    inv_blk_launch(R, q, p, M, Mt, phi0, status, dminmax, st);
   }
   return hipGetLastError();
 }

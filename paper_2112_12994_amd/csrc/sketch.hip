@@ -78,10 +78,17 @@ __device__ __forceinline__ void chunk_sum_body(const T* __restrict__ s, int64_t 
   __shared__ double red[NT / 64];
   const int64_t base = static_cast<int64_t>(chunk) * CHUNK;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < CHUNK; i += NT) {
-    const int64_t g = base + i;
-    if (g < m) acc += static_cast<double>(s[g]);
+  // all of the thread's loads in flight, added in row order
+  constexpr int PER = CHUNK / NT;
+  double v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int64_t g = base + threadIdx.x + static_cast<int64_t>(k) * NT;
+    v[k] = g < m ? static_cast<double>(s[g]) : 0.0;
   }
+#pragma unroll
+  for (int k = 0; k < PER; ++k)
+    if (base + threadIdx.x + static_cast<int64_t>(k) * NT < m) acc += v[k];
   const double tot = block_sum<NT>(acc, red);
   if (threadIdx.x == 0) out[chunk] = tot;
 }
