@@ -34,6 +34,20 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a) {
   return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
 }
 
+// The thread index as a value the compiler cannot see through: index and
+// address arithmetic derived from it in one phase of a kernel is then redone
+// in the next rather than kept live in registers across the phases between.
+__device__ __forceinline__ int opaque_tid() {
+  int t = static_cast<int>(threadIdx.x);
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Make the accumulator x materialise here: the products folded into it are
+// evaluated now instead of being deferred (with their operands kept live) to
+// x's first later use.
+__device__ __forceinline__ void settle(double& x) { asm volatile("" : "+v"(x)); }
+
 __device__ __forceinline__ int bitrev(int k, int lg) {
   return static_cast<int>(__builtin_bitreverse32(static_cast<uint32_t>(k)) >> (32 - lg));
 }

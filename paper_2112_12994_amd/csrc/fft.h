@@ -202,7 +202,7 @@ template <typename T, bool DIT, bool INV, int N, int NT, int R, int LGH>
 __device__ __forceinline__ void stage(cx<T>* s, const cx<T>* __restrict__ tab) {
   constexpr int h = 1 << LGH;
   constexpr int LGR = R == 8 ? 3 : (R == 4 ? 2 : 1);
-  for (int q = threadIdx.x; q < N / R; q += NT) {
+  for (int q = opaque_tid(); q < N / R; q += NT) {
     const int r = q & (h - 1);
     const int base = ((q >> LGH) << (LGH + LGR)) + r;
     cx<T> a[R];

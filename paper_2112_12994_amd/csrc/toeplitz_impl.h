@@ -31,6 +31,40 @@ __device__ __forceinline__ void load_pair(const cx<T>* __restrict__ P, int k, in
   }
 }
 
+// The bin pairs (k, N-k) of a packed spectrum for k = tid + ip NT < N/2,
+// plus the self-paired bin N/2, all loaded before any is used so that the
+// whole set costs one memory round trip.  With `tab`, also the real-FFT
+// twiddles exp(-2 pi i k / B) of those bins.
+template <typename T, int LGN, int NT>
+struct PairLoads {
+  static constexpr int N = 1 << LGN;
+  static constexpr int NP = (N / 2 + NT - 1) / NT;
+  static constexpr bool FULL = NP * NT == N / 2;  // every (thread, ip) has a bin
+  cx<T> a[NP], b[NP], w[NP], yh, wh;
+  __device__ __forceinline__ void load(const cx<T>* __restrict__ P, const cx<T>* __restrict__ tab) {
+    const int tid = opaque_tid();
+#pragma unroll
+    for (int ip = 0; ip < NP; ++ip) {
+      int k = tid + ip * NT;
+      if (!FULL) k = k < N / 2 ? k : 0;
+      a[ip] = P[k];
+      b[ip] = P[(N - k) & (N - 1)];
+      if (tab) w[ip] = twiddle<T, false>(tab, k, LGN + 1);
+    }
+    yh = P[N / 2];
+    if (tab) wh = twiddle<T, false>(tab, N / 2, LGN + 1);
+  }
+  // the bins k and N-k (bin 0 pairs with bin N: both real, packed in word 0)
+  __device__ __forceinline__ void get(int ip, int k, cx<T>& xk, cx<T>& xnk) const {
+    xk = a[ip];
+    xnk = b[ip];
+    if (k == 0) {
+      xk = {a[ip].x, T(0)};
+      xnk = {a[ip].y, T(0)};
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Block spectra of the series (computed in FP64, stored as TS).
 template <int LGN, int NT, typename TS>
@@ -123,7 +157,6 @@ __device__ __forceinline__ void toep_pass_body(
     const int* __restrict__ flag, const cx<T>* __restrict__ tab, int64_t m, int p, int L,
     int nblocks, int blk) {
   constexpr int N = 1 << LGN;
-  constexpr int NPAIR = (N / 2 + 1 + NT - 1) / NT;
   constexpr int NEL = N / NT;
   static_assert(N % NT == 0, "block transform must cover the workgroup");
   __shared__ cx<T> s[N];
@@ -136,20 +169,29 @@ __device__ __forceinline__ void toep_pass_body(
   double nrm = 0.0;
   if constexpr ((MODE & PM_MV) != 0) {
     // spectrum of X v on this block: Y * V (V pre-scaled by 1/B), in the
-    // half-length complex form, bit-reversed for the inverse transform
+    // half-length complex form, bit-reversed for the inverse transform.
+    // Every operand is loaded before any is used (one memory round trip).
+    PairLoads<T, LGN, NT> ly, lv;
+    ly.load(Y, tab);
+    lv.load(Vhat, nullptr);
 #pragma unroll
-    for (int ip = 0; ip < NPAIR; ++ip) {
+    for (int ip = 0; ip < PairLoads<T, LGN, NT>::NP; ++ip) {
       const int k = tid + ip * NT;
-      if (k <= N / 2) {
+      if (PairLoads<T, LGN, NT>::FULL || k < N / 2) {
         cx<T> yk, ynk, vk, vnk;
-        load_pair(Y, k, N, yk, ynk);
-        load_pair(Vhat, k, N, vk, vnk);
-        const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
+        ly.get(ip, k, yk, ynk);
+        lv.get(ip, k, vk, vnk);
         cx<T> Zk, Znk;
-        irfft_pre(cmul(yk, vk), cmul(ynk, vnk), w, Zk, Znk);
+        irfft_pre(cmul(yk, vk), cmul(ynk, vnk), ly.w[ip], Zk, Znk);
         s[swz<T>(bitrev(k, LGN))] = Zk;
-        if (k != 0 && 2 * k != N) s[swz<T>(bitrev(N - k, LGN))] = Znk;
+        if (k != 0) s[swz<T>(bitrev(N - k, LGN))] = Znk;
       }
+    }
+    if (tid == 0) {  // the self-paired bin N/2
+      const cx<T> x = cmul(ly.yh, lv.yh);
+      cx<T> Zk, Znk;
+      irfft_pre(x, x, ly.wh, Zk, Znk);
+      s[swz<T>(bitrev(N / 2, LGN))] = Zk;
     }
     __syncthreads();
   }
@@ -191,6 +233,7 @@ __device__ __forceinline__ void toep_pass_body(
       const cx<T> o = emap(t, s[swz<T>(t)], w0[e], w1[e]);
       if constexpr ((MODE & PM_RMV) != 0) s[swz<T>(t)] = o;
     }
+    settle(nrm);
     if constexpr ((MODE & PM_RMV) != 0) {
       __syncthreads();
       fft_dif<T, false, LGN, NT>(s, tab);
@@ -205,6 +248,7 @@ __device__ __forceinline__ void toep_pass_body(
       nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
       s[swz<T>(t)] = {o0, o1};
     }
+    settle(nrm);
     __syncthreads();
     fft_dif<T, false, LGN, NT>(s, tab);
   }
@@ -212,22 +256,33 @@ __device__ __forceinline__ void toep_pass_body(
   if constexpr ((MODE & PM_RMV) != 0) {
     // block share of X^T e: correlation of the window with e, via
     // conj(E) * Y per bin pair, then the inverse transform's first p outputs
+    // (Y reloaded, a cache hit, rather than kept live across the transforms)
+    PairLoads<T, LGN, NT> ly;
+    ly.load(Y, tab);
 #pragma unroll
-    for (int ip = 0; ip < NPAIR; ++ip) {
+    for (int ip = 0; ip < PairLoads<T, LGN, NT>::NP; ++ip) {
       const int k = tid + ip * NT;
-      if (k <= N / 2) {
+      if (PairLoads<T, LGN, NT>::FULL || k < N / 2) {
         const int bk = bitrev(k, LGN);
         const int bnk = bitrev((N - k) & (N - 1), LGN);
-        const cx<T> w = twiddle<T, false>(tab, k, LGN + 1);
         cx<T> Xk, Xnk;
-        rfft_post(s[swz<T>(bk)], s[swz<T>(bnk)], w, Xk, Xnk);
-        cx<T> yk2, ynk2;  // reloaded (cache hit) rather than kept live across the transforms
-        load_pair(Y, k, N, yk2, ynk2);
+        rfft_post(s[swz<T>(bk)], s[swz<T>(bnk)], ly.w[ip], Xk, Xnk);
+        cx<T> yk2, ynk2;
+        ly.get(ip, k, yk2, ynk2);
         cx<T> Zk, Znk;
-        irfft_pre(cmulconj(yk2, Xk), cmulconj(ynk2, Xnk), w, Zk, Znk);
+        irfft_pre(cmulconj(yk2, Xk), cmulconj(ynk2, Xnk), ly.w[ip], Zk, Znk);
         s[swz<T>(bk)] = Zk;
-        if (k != 0 && 2 * k != N) s[swz<T>(bnk)] = Znk;
+        if (k != 0) s[swz<T>(bnk)] = Znk;
       }
+    }
+    if (tid == 0) {  // the self-paired bin N/2
+      const int bh = bitrev(N / 2, LGN);
+      cx<T> Xk, Xnk;
+      const cx<T> z = s[swz<T>(bh)];
+      rfft_post(z, z, ly.wh, Xk, Xnk);
+      cx<T> Zk, Znk;
+      irfft_pre(cmulconj(ly.yh, Xk), cmulconj(ly.yh, Xnk), ly.wh, Zk, Znk);
+      s[swz<T>(bh)] = Zk;
     }
     __syncthreads();
     fft_dit<T, true, LGN, NT>(s, tab);
