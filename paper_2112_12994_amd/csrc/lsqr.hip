@@ -114,7 +114,15 @@ __device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, i
 }
 
 // MLDS: M (p <= 128) is staged once into LDS (rows padded to an odd length)
-// and every product with M or M^T reads it there.
+// and every product with M or M^T reads it there, PARTS = NT / 128 threads
+// per output (partial sums over every PARTS-th term, combined by a fixed
+// butterfly: every thread of the group ends with the same value).
+template <int PARTS>
+__device__ __forceinline__ double parts_sum_t(double x) {
+#pragma unroll
+  for (int off = 1; off < PARTS; off <<= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
 template <int LGN, int NT, typename TS, bool MLDS>
 __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st,
                                                        const double* __restrict__ g,
@@ -128,6 +136,9 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
                                                        cx<TS>* __restrict__ Vhat,
                                                        const cx<double>* __restrict__ tab) {
   constexpr int N = 1 << LGN;
+  constexpr int PARTS = NT / 128 > 0 ? NT / 128 : 1;
+  static_assert(!MLDS || PARTS * 128 == NT, "M in LDS: NT / 128 threads per output");
+  auto parts_sum = [](double x) { return parts_sum_t<PARTS>(x); };
   __shared__ cx<double> s[N];
   extern __shared__ double smem[];
   double* sg = smem;
@@ -156,15 +167,13 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
   // v~ = M^T (X^T u) - beta v: row j of M^T (= column j of M) is Mt[j][0..j]
   double hsq = 0.0;
   if constexpr (MLDS) {
-    for (int j = tid; j < p; j += NT) {
-      double a0 = 0.0, a1 = 0.0;
-      int i = 0;
-      for (; i + 1 <= j; i += 2) {
-        a0 += sM[i * ldm + j] * sg[i];
-        a1 += sM[(i + 1) * ldm + j] * sg[i + 1];
-      }
-      if (i <= j) a0 += sM[i * ldm + j] * sg[i];
-      const double acc = a0 + a1;
+    // PARTS consecutive threads per output j, each over every PARTS-th i
+    const int j = tid / PARTS, part = tid % PARTS;
+    double acc = 0.0;
+    if (j < p)
+      for (int i = part; i <= j; i += PARTS) acc += sM[i * ldm + j] * sg[i];
+    acc = parts_sum(acc);
+    if (j < p && part == 0) {
       const double h = init ? acc : acc - beta * v[j];
       sv[j] = h;
       hsq += h * h;
@@ -264,16 +273,12 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
   if (!done) {
     // q = M v_new into sg, then its packed spectrum scaled by 1/B.
     if constexpr (MLDS) {
-      for (int i = tid; i < p; i += NT) {
-        double a0 = 0.0, a1 = 0.0;
-        int j = i;
-        for (; j + 1 < p; j += 2) {
-          a0 += sM[i * ldm + j] * sv[j];
-          a1 += sM[i * ldm + j + 1] * sv[j + 1];
-        }
-        if (j < p) a0 += sM[i * ldm + j] * sv[j];
-        sg[i] = a0 + a1;
-      }
+      const int i = tid / PARTS, part = tid % PARTS;
+      double acc = 0.0;
+      if (i < p)
+        for (int j = i + part; j < p; j += PARTS) acc += sM[i * ldm + j] * sv[j];
+      acc = parts_sum(acc);
+      if (i < p && part == 0) sg[i] = acc;
     } else {
       tri_gemv_rows<NT, true>(M, p, sv, [&](int i, double acc) { sg[i] = acc; });
     }
