@@ -89,16 +89,16 @@ __device__ __forceinline__ double column_sum(const double* __restrict__ col, int
   static_assert(NT >= 256, "column_sum needs 256 threads");
   double s = 0.0;
   if (threadIdx.x < 256) {
-    // eight loads in flight per round, added in the plain loop's order
-    int b = threadIdx.x;
-    for (; b + 7 * 256 < nblocks; b += 8 * 256) {
-      double v[8];
+    // up to 24 loads in flight per round (one round up to 6144 blocks),
+    // added in the plain loop's order
+    constexpr int U = 24;
+    for (int b = threadIdx.x; b < nblocks; b += U * 256) {
+      double v[U];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = col[b + 256 * k];
+      for (int k = 0; k < U; ++k) v[k] = b + 256 * k < nblocks ? col[b + 256 * k] : 0.0;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s += v[k];
+      for (int k = 0; k < U; ++k) s += v[k];
     }
-    for (; b < nblocks; b += 256) s += col[b];
   }
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
