@@ -68,6 +68,18 @@ def test_fit_f64_matches_oracle(ctx, p, n, seed):
     _check_fit(out, y, p)
 
 
+@pytest.mark.parametrize("p,n,block_lg", [(2, 1 << 21, 0), (5, 1 << 21, 7)])
+def test_many_blocks(ctx, p, n, block_lg):
+    """More block partial sums than one round of the column-sum loads covers
+    (about 8200 and 16,900 blocks against 6144 per round)."""
+    say("fit many blocks", p, n, block_lg)
+    rng = np.random.default_rng(11 + p)
+    y = synth.ar_series(n, p, rng, 0.3, 0.9)
+    out = ctx.fit(y, p, 1e-10, block_lg=block_lg)
+    assert out["n_blocks"] > 6144, out["n_blocks"]
+    _check_fit(out, y, p)
+
+
 @pytest.mark.parametrize("sketch,jl", [(1, 0), (0, 1), (0, 0)])
 def test_sketch_variants_converge_to_same_solution(ctx, sketch, jl):
     say("fit sketch variant", sketch, jl)
