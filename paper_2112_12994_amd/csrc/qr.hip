@@ -380,9 +380,17 @@ __global__ __launch_bounds__(256) void triinv_reg_kernel(const double* __restric
 // independent).  Blocked by 16 columns as in LAPACK's triangular solve: the
 // 16 x 16 diagonal block by forward substitution (one lane per row), then the
 // trailing columns A[:, K] -= X[:, J] R[J, K] on the FP64 matrix cores.
-// Backward stable, unlike a product with an explicitly inverted R.
 // RALL (ldq <= 128): all of R is staged in LDS once, ahead of the column
-// blocks, instead of 16 rows per block (the arithmetic is the same).
+// blocks, instead of 16 rows per block.  With ldq <= TRSM_DINV_LDQ the 16 x 16
+// diagonal blocks are inverted first (one column per lane, back substitution,
+// all blocks at once) and each block step is X_J = T_J R_JJ^{-1} on the
+// matrix cores, as GPU triangular solves commonly do: the per-row
+// substitution chain (16 dependent divides per block) is the solve's
+// critical path otherwise.  Its error is bounded by u kappa(R_JJ) per block
+// instead of u; the Cholesky QR sweeps that follow re-orthogonalise.
+// diagonal-block inverses fit in LDS beside all of R up to this ldq
+constexpr int TRSM_DINV_LDQ = 112;
+
 template <bool RALL>
 __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, int q,
                                                        const double* __restrict__ R, int rt) {
@@ -413,14 +421,49 @@ __device__ __forceinline__ void trsm_tile_body(double* __restrict__ A, int ldq, 
       for (int r = 0; r < 16; ++r) dst[r * ldq + cc] = v[r];
     }
   };
-  if constexpr (RALL)
+  const bool dinv = RALL && ldq <= TRSM_DINV_LDQ;
+  double* const Dinv = Rbase + static_cast<size_t>(ldq) * ldq;  // nt x 16 x 16 (dinv)
+  if constexpr (RALL) {
     for (int J = 0; J < nt; ++J) stage_rows(J * 16, Rbase + static_cast<size_t>(J) * 16 * ldq);
+    if (dinv) {
+      __syncthreads();
+      // column c of R_JJ^{-1}: U x = e_c from the last row up (rows past q:
+      // the identity)
+      for (int col = lane; col < nt * 16; col += 64) {
+        const int J = col >> 4, c = col & 15, j0 = J * 16;
+        const double* U = Rbase + static_cast<size_t>(j0) * ldq + j0;
+        double x[16];
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          double acc = i == c ? 1.0 : 0.0;
+#pragma unroll
+          for (int k = i + 1; k < 16; ++k) acc -= U[i * ldq + k] * x[k];
+          x[i] = j0 + i < q ? acc / U[i * ldq + i] : (i == c ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) Dinv[J * 256 + i * 16 + c] = x[i];
+      }
+    }
+  }
   for (int J = 0; J < nt; ++J) {
     const int j0 = J * 16;
     double* const Rp = RALL ? Rbase + static_cast<size_t>(j0) * ldq : Rbase;
     if constexpr (!RALL) stage_rows(j0, Rp);
     __syncthreads();
-    if (lane < 16) {
+    if (dinv) {
+      // X_J = T_J R_JJ^{-1}: all reads of T_J precede the writes
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      double xa[4];
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) xa[k4] = T[(lane & 15) * ld + j0 + 4 * k4 + (lane >> 4)];
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const double db = Dinv[J * 256 + (4 * k4 + (lane >> 4)) * 16 + (lane & 15)];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[k4], db, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) T[(4 * v + (lane >> 4)) * ld + j0 + (lane & 15)] = acc[v];
+    } else if (lane < 16) {
       // the row's 16 entries of this block in registers (R rows read as
       // LDS broadcasts): the same operations in the same order as a
       // substitution in place, without an LDS round trip per step
@@ -476,7 +519,8 @@ __global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, i
 bool trsm_rall(int ldq) { return ldq <= 128; }
 size_t trsm_lds_bytes(int ldq) {
   const size_t rrows = trsm_rall(ldq) ? static_cast<size_t>(ldq) : 16;
-  return (16 * static_cast<size_t>(ldq + 1) + rrows * ldq) * sizeof(double);
+  const size_t dinv = ldq <= TRSM_DINV_LDQ ? 16 * static_cast<size_t>(ldq) : 0;
+  return (16 * static_cast<size_t>(ldq + 1) + rrows * ldq + dinv) * sizeof(double);
 }
 
 // status |= 4 when min|R_ii| <= k u max|R_ii| over the first k = rank_cols
