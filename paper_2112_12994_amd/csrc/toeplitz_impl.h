@@ -197,20 +197,23 @@ __device__ __forceinline__ void toep_pass_body(
   }
   // e at the rows of this block (zero outside them) from the inverse
   // transform value z = ((X v)[2t], (X v)[2t+1]) at packed position t
+  // rows of this block: window positions [p - 1, hi) (32-bit offsets from
+  // the row at position 0; the 64-bit base is uniform)
+  const int hi = static_cast<int>(m - row0 < 2 * N ? m - row0 : 2 * N);
+  T* const ub = u_out ? u_out + row0 : nullptr;
   auto emap = [&](int t, cx<T> z, T wa, T wb) -> cx<T> {
     const T s1 = static_cast<T>(coef[0]);
     const T s2 = static_cast<T>(coef[1]);
     T o0 = T(0), o1 = T(0);
-    const int64_t i0 = row0 + 2 * t;
-    if (2 * t >= p - 1 && i0 < m) {
+    if (2 * t >= p - 1 && 2 * t < hi) {
       o0 = s1 * z.x;
       if (w_in) o0 += s2 * wa;
-      if (u_out) u_out[i0] = o0;
+      if (ub) ub[2 * t] = o0;
     }
-    if (2 * t + 1 >= p - 1 && i0 + 1 < m) {
+    if (2 * t + 1 >= p - 1 && 2 * t + 1 < hi) {
       o1 = s1 * z.y;
       if (w_in) o1 += s2 * wb;
-      if (u_out) u_out[i0 + 1] = o1;
+      if (ub) ub[2 * t + 1] = o1;
     }
     nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
     return cx<T>{o0, o1};
@@ -221,11 +224,12 @@ __device__ __forceinline__ void toep_pass_body(
     // the w terms of all this thread's rows are loaded before any is used
     // (one memory round trip rather than one per element)
     T w0[NEL], w1[NEL];
+    const T* const wbase = w_in ? w_in + row0 : nullptr;
 #pragma unroll
     for (int e = 0; e < NEL; ++e) {
-      const int64_t i0 = row0 + 2 * (tid + e * NT);
-      w0[e] = (w_in && i0 >= 0 && i0 < m) ? w_in[i0] : T(0);
-      w1[e] = (w_in && i0 + 1 >= 0 && i0 + 1 < m) ? w_in[i0 + 1] : T(0);
+      const int r = 2 * (tid + e * NT);
+      w0[e] = (wbase && r >= p - 1 && r < hi) ? wbase[r] : T(0);
+      w1[e] = (wbase && r + 1 >= p - 1 && r + 1 < hi) ? wbase[r + 1] : T(0);
     }
 #pragma unroll
     for (int e = 0; e < NEL; ++e) {
@@ -239,12 +243,12 @@ __device__ __forceinline__ void toep_pass_body(
       fft_dif<T, false, LGN, NT>(s, tab);
     }
   } else {
+    const T* const uib = u_in + row0;
 #pragma unroll
     for (int e = 0; e < NEL; ++e) {
       const int t = tid + e * NT;
-      const int64_t i0 = row0 + 2 * t;
-      const T o0 = (2 * t >= p - 1 && i0 < m) ? u_in[i0] : T(0);
-      const T o1 = (2 * t + 1 >= p - 1 && i0 + 1 < m) ? u_in[i0 + 1] : T(0);
+      const T o0 = (2 * t >= p - 1 && 2 * t < hi) ? uib[2 * t] : T(0);
+      const T o1 = (2 * t + 1 >= p - 1 && 2 * t + 1 < hi) ? uib[2 * t + 1] : T(0);
       nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
       s[swz<T>(t)] = {o0, o1};
     }
