@@ -271,6 +271,79 @@ __device__ __forceinline__ void fft_dif(cx<T>* s, const cx<T>* __restrict__ tab)
   dif_down<T, INV, LGN, NT, P::RLAST == 8 ? P::LGLAST : P::LGLAST - 3>(s, tab);
 }
 
+// The outermost stage of a transform (the last stage of fft_dit, the first of
+// fft_dif) has radix R = RLAST and span H = N / R: its groups are q < H with
+// points q + k H.  When H is a multiple of NT, thread tid owns the groups
+// q = tid + c NT (c < H / NT), whose points are exactly tid + e NT with
+// e = c + k (H / NT): the stage can leave its outputs in (or take its inputs
+// from) the per-thread array v[e] <-> point tid + e NT, the layout of the
+// pointwise step between an inverse and a forward transform, which then
+// costs no LDS round trip.
+template <int LGN, int NT>
+struct Outer {
+  using P = Plan8<LGN>;
+  static constexpr int R = P::RLAST;
+  static constexpr int LGH = P::LGLAST;
+  static constexpr int H = 1 << LGH;
+  static constexpr bool REGS = H % NT == 0;
+  static constexpr int C = REGS ? H / NT : 1;
+};
+// fft_dit with the result in registers: v[e] = value at point tid + e NT.
+// Ends without a barrier; the caller may then overwrite exactly these points
+// of s (fft_dif_in does) without one.
+template <typename T, bool INV, int LGN, int NT>
+__device__ __forceinline__ void fft_dit_out(cx<T>* s, const cx<T>* __restrict__ tab,
+                                            cx<T> (&v)[(1 << LGN) / NT]) {
+  using O = Outer<LGN, NT>;
+  const int tid = opaque_tid();
+  if constexpr (O::REGS) {
+    dit_from<T, INV, LGN, NT, 0, true>(s, tab);
+#pragma unroll
+    for (int c = 0; c < O::C; ++c) {
+      const int q = tid + c * NT;
+      cx<T> a[O::R];
+#pragma unroll
+      for (int k = 0; k < O::R; ++k) a[k] = s[swz<T>(q + k * O::H)];
+      const Tw<T, O::R, O::LGH> tw(tab, q);
+      bfly<T, true, INV, O::R, O::LGH>(a, tw);
+#pragma unroll
+      for (int k = 0; k < O::R; ++k) v[c + k * O::C] = a[k];
+    }
+  } else {
+    fft_dit<T, INV, LGN, NT>(s, tab);
+#pragma unroll
+    for (int e = 0; e < (1 << LGN) / NT; ++e) v[e] = s[swz<T>(tid + e * NT)];
+  }
+}
+// fft_dif with the input in registers (v[e] at point tid + e NT); no other
+// thread may still read these points of s.  Ends with a barrier like fft_dif.
+template <typename T, bool INV, int LGN, int NT>
+__device__ __forceinline__ void fft_dif_in(cx<T>* s, const cx<T>* __restrict__ tab,
+                                           const cx<T> (&v)[(1 << LGN) / NT]) {
+  using O = Outer<LGN, NT>;
+  const int tid = opaque_tid();
+  if constexpr (O::REGS) {
+#pragma unroll
+    for (int c = 0; c < O::C; ++c) {
+      const int q = tid + c * NT;
+      cx<T> a[O::R];
+#pragma unroll
+      for (int k = 0; k < O::R; ++k) a[k] = v[c + k * O::C];
+      const Tw<T, O::R, O::LGH> tw(tab, q);
+      bfly<T, false, INV, O::R, O::LGH>(a, tw);
+#pragma unroll
+      for (int k = 0; k < O::R; ++k) s[swz<T>(q + k * O::H)] = a[k];
+    }
+    __syncthreads();
+    dif_down<T, INV, LGN, NT, O::LGH - 3>(s, tab);
+  } else {
+#pragma unroll
+    for (int e = 0; e < (1 << LGN) / NT; ++e) s[swz<T>(tid + e * NT)] = v[e];
+    __syncthreads();
+    fft_dif<T, INV, LGN, NT>(s, tab);
+  }
+}
+
 // Forward real-FFT post-step for the bin pair (k, N-k): from Z[k], Z[N-k]
 // (complex DFT_N of the packed sequence) give X[k], X[N-k] of the real DFT_B.
 // w = exp(-2 pi i k / B).  For k = 0 pass zk == znk (Z[N] = Z[0]) and read

@@ -205,22 +205,33 @@ __device__ __forceinline__ void toep_pass_body(
     const T s1 = static_cast<T>(coef[0]);
     const T s2 = static_cast<T>(coef[1]);
     T o0 = T(0), o1 = T(0);
+    // explicit fused operations: the same rounding in every kernel that
+    // inlines this pass, whatever the compiler knows about w_in there
     if (2 * t >= p - 1 && 2 * t < hi) {
       o0 = s1 * z.x;
-      if (w_in) o0 += s2 * wa;
+      if (w_in) o0 = fma(s2, wa, o0);
       if (ub) ub[2 * t] = o0;
     }
     if (2 * t + 1 >= p - 1 && 2 * t + 1 < hi) {
       o1 = s1 * z.y;
-      if (w_in) o1 += s2 * wb;
+      if (w_in) o1 = fma(s2, wb, o1);
       if (ub) ub[2 * t + 1] = o1;
     }
-    nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
+    nrm = fma(static_cast<double>(o0), static_cast<double>(o0), nrm);
+    nrm = fma(static_cast<double>(o1), static_cast<double>(o1), nrm);
     return cx<T>{o0, o1};
   };
 
+  // v[e]: the value at packed position tid + e NT between the transforms
+  // (their outermost butterflies run on it in registers)
+  cx<T> v[NEL];
   if constexpr ((MODE & PM_MV) != 0) {
-    fft_dit<T, true, LGN, NT>(s, tab);
+    fft_dit_out<T, true, LGN, NT>(s, tab, v);
+    // the butterflies finish before the w loads are issued (hoisted above
+    // them, the loads would keep both sets of registers live)
+#pragma unroll
+    for (int e = 0; e < NEL; ++e) asm volatile("" : "+v"(v[e].x), "+v"(v[e].y));
+    asm volatile("" ::: "memory");
     // the w terms of all this thread's rows are loaded before any is used
     // (one memory round trip rather than one per element)
     T w0[NEL], w1[NEL];
@@ -232,16 +243,9 @@ __device__ __forceinline__ void toep_pass_body(
       w1[e] = (wbase && r + 1 >= p - 1 && r + 1 < hi) ? wbase[r + 1] : T(0);
     }
 #pragma unroll
-    for (int e = 0; e < NEL; ++e) {
-      const int t = tid + e * NT;
-      const cx<T> o = emap(t, s[swz<T>(t)], w0[e], w1[e]);
-      if constexpr ((MODE & PM_RMV) != 0) s[swz<T>(t)] = o;
-    }
+    for (int e = 0; e < NEL; ++e) v[e] = emap(tid + e * NT, v[e], w0[e], w1[e]);
     settle(nrm);
-    if constexpr ((MODE & PM_RMV) != 0) {
-      __syncthreads();
-      fft_dif<T, false, LGN, NT>(s, tab);
-    }
+    if constexpr ((MODE & PM_RMV) != 0) fft_dif_in<T, false, LGN, NT>(s, tab, v);
   } else {
     const T* const uib = u_in + row0;
 #pragma unroll
@@ -249,14 +253,13 @@ __device__ __forceinline__ void toep_pass_body(
       const int t = tid + e * NT;
       const T o0 = (2 * t >= p - 1 && 2 * t < hi) ? uib[2 * t] : T(0);
       const T o1 = (2 * t + 1 >= p - 1 && 2 * t + 1 < hi) ? uib[2 * t + 1] : T(0);
-      nrm += static_cast<double>(o0) * o0 + static_cast<double>(o1) * o1;
-      s[swz<T>(t)] = {o0, o1};
+      nrm = fma(static_cast<double>(o0), static_cast<double>(o0), nrm);
+      nrm = fma(static_cast<double>(o1), static_cast<double>(o1), nrm);
+      v[e] = {o0, o1};
     }
     settle(nrm);
-    __syncthreads();
-    fft_dif<T, false, LGN, NT>(s, tab);
+    fft_dif_in<T, false, LGN, NT>(s, tab, v);
   }
-
   if constexpr ((MODE & PM_RMV) != 0) {
     // block share of X^T e: correlation of the window with e, via
     // conj(E) * Y per bin pair, then the inverse transform's first p outputs
