@@ -79,6 +79,7 @@ struct FitBufs {
   void* Vhat32;     // mixed: FP32 spectrum of the CG direction
   RefineState* rst; // mixed: refinement state
   double *cw, *cres, *cd;  // mixed: CG vectors
+  double* pack;     // p + 7: phi, ||r||^2, |R_ii| range, status (one copy out)
 };
 
 namespace {
@@ -313,6 +314,7 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->phi0 = a.take<double>(pl.p);
   b->phi = a.take<double>(pl.p);
   b->phib = a.take<double>(pl.p);
+  b->pack = a.take<double>(pl.p + 8);
   b->idx = a.take<int64_t>(pl.c);
   b->scale = a.take<double>(pl.c);
   b->swork = a.take<double>(sample_work_doubles(pl.m));
@@ -350,6 +352,21 @@ __global__ void fill_refine_kernel(RefineState* st, double tol, int max_refine, 
     s.inner_max = inner_max;
     s.inner_tol = inner_tol;
     *st = s;
+  }
+}
+
+// The results of a fit in one buffer for a single device-to-host copy:
+// phi (p), ||r||^2, max and min |R_ii|, the four status words.
+__global__ void pack_results_kernel(const double* __restrict__ phi, int p,
+                                    const double* __restrict__ rr,
+                                    const double* __restrict__ dminmax,
+                                    const int* __restrict__ status, double* __restrict__ out) {
+  for (int i = threadIdx.x; i < p; i += blockDim.x) out[i] = phi[i];
+  if (threadIdx.x == 0) {
+    out[p] = rr[0];
+    out[p + 1] = dminmax[0];
+    out[p + 2] = dminmax[1];
+    for (int k = 0; k < 4; ++k) out[p + 3 + k] = static_cast<double>(status[k]);
   }
 }
 

@@ -242,13 +242,17 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   // FP64 residual of the returned coefficients, row by row.
   TLS_CHECK(launch_resid_direct(d_y, pl.m, p, b.phi, b.rpart, s));
   TLS_CHECK(launch_colsum(b.rpart, resid_direct_blocks(pl.m), 1, b.rr, nullptr, s));
-  TLS_CHECK(hipMemcpyAsync(hphi, b.phi, p * sizeof(double), hipMemcpyDeviceToHost, s));
-  TLS_CHECK(hipMemcpyAsync(ho->rr, b.rr, sizeof(double), hipMemcpyDeviceToHost, s));
-  TLS_CHECK(hipMemcpyAsync(ho->dminmax, b.dminmax, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-  TLS_CHECK(hipMemcpyAsync(ho->status, b.status, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  hipLaunchKernelGGL(pack_results_kernel, dim3(1), dim3(256), 0, s, b.phi, p, b.rr, b.dminmax,
+                     b.status, b.pack);
+  TLS_CHECK(hipGetLastError());
+  TLS_CHECK(hipMemcpyAsync(hphi, b.pack, (p + 7) * sizeof(double), hipMemcpyDeviceToHost, s));
   TLS_CHECK(hipStreamSynchronize(s));
 
   memcpy(coef, hphi, p * sizeof(double));
+  ho->rr[0] = hphi[p];
+  ho->dminmax[0] = hphi[p + 1];
+  ho->dminmax[1] = hphi[p + 2];
+  for (int k = 0; k < 4; ++k) ho->status[k] = static_cast<int>(hphi[p + 3 + k]);
   const auto t1 = std::chrono::steady_clock::now();
   if (res) {
     memset(res, 0, sizeof(*res));
