@@ -80,6 +80,18 @@ def test_many_blocks(ctx, p, n, block_lg):
     _check_fit(out, y, p)
 
 
+@pytest.mark.parametrize("p,block_lg", [(40, 11), (40, 12), (40, 13), (300, 14)])
+def test_forced_block_lengths(ctx, p, block_lg):
+    """Every transform length the pass can take above the default (2^11 ..
+    2^14, where a thread owns several butterfly groups of each stage)."""
+    say("fit block length", p, block_lg)
+    rng = np.random.default_rng(31 + block_lg)
+    y = synth.ar_series(200000, p, rng, 0.3, 0.9)
+    out = ctx.fit(y, p, 1e-10, block_lg=block_lg)
+    assert out["block_len"] == 1 << block_lg, out["block_len"]
+    _check_fit(out, y, p)
+
+
 @pytest.mark.parametrize("sketch,jl", [(1, 0), (0, 1), (0, 0)])
 def test_sketch_variants_converge_to_same_solution(ctx, sketch, jl):
     say("fit sketch variant", sketch, jl)
