@@ -195,12 +195,13 @@ __device__ __forceinline__ void toep_pass_body(
     }
     __syncthreads();
   }
-  // e at the rows of this block (zero outside them) from the inverse
-  // transform value z = ((X v)[2t], (X v)[2t+1]) at packed position t
-  // rows of this block: window positions [p - 1, hi) (32-bit offsets from
-  // the row at position 0; the 64-bit base is uniform)
+  // the rows of this block sit at window positions [p - 1, hi); they are
+  // addressed by 32-bit offsets from the row at position 0 (the 64-bit base
+  // is uniform; positions below p - 1 are never accessed)
   const int hi = static_cast<int>(m - row0 < 2 * N ? m - row0 : 2 * N);
   T* const ub = u_out ? u_out + row0 : nullptr;
+  // e at the rows of this block (zero outside them) from the inverse
+  // transform value z = ((X v)[2t], (X v)[2t+1]) at packed position t
   auto emap = [&](int t, cx<T> z, T wa, T wb) -> cx<T> {
     const T s1 = static_cast<T>(coef[0]);
     const T s2 = static_cast<T>(coef[1]);
