@@ -1369,7 +1369,7 @@ hipError_t launch_triinv(const double* R, int q, int p, double* M, double* Mt, d
   if (reg_tiles(p) != 0) {
     hipError_t e = tri_inverse(R, q, p, M, p, Mt, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((triinv_finish_kernel<256>), dim3(1), dim3(256), 0, st, R, q, p, M, phi0,
+    hipLaunchKernelGGL((triinv_finish_kernel<1024>), dim3(1), dim3(1024), 0, st, R, q, p, M, phi0,
                        status, dminmax);
   } else {
     inv_blk_launch(R, q, p, M, Mt, phi0, status, dminmax, st);
