@@ -278,11 +278,15 @@ __device__ __forceinline__ void jl_omega_body(const double* __restrict__ M, int 
     if (Pi) Pi[static_cast<size_t>(q) * p + j] = val;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < p; i += NT) {
-    double acc = 0.0;
+  // Om[:, q] = M prow: one wavefront per row, lanes over its columns (the
+  // row's result does not depend on which wavefront computes it)
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = wid; i < p; i += NT / 64) {
     const double* mi = M + static_cast<size_t>(i) * p;
-    for (int j = i; j < p; ++j) acc += mi[j] * prow[j];
-    Om[static_cast<size_t>(q) * p + i] = acc;
+    double acc = 0.0;
+    for (int j = i + lane; j < p; j += 64) acc += mi[j] * prow[j];
+    acc = wave_sum(acc);
+    if (lane == 0) Om[static_cast<size_t>(q) * p + i] = acc;
   }
 }
 
@@ -362,7 +366,7 @@ hipError_t launch_sample(int prec, const void* scores, int64_t m, const double* 
 hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, double* Om,
                            uint64_t seed, uint32_t fit, hipStream_t st) {
   if (p < 1 || k < 1 || p > 8192) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((jl_omega_kernel<256>), dim3(k), dim3(256), p * sizeof(double), st, M, p, k,
+  hipLaunchKernelGGL((jl_omega_kernel<1024>), dim3(k), dim3(1024), p * sizeof(double), st, M, p, k,
                      kind, Pi, Om, seed, fit);
   return hipGetLastError();
 }
