@@ -174,9 +174,17 @@ __device__ __forceinline__ void draw_body(const T* __restrict__ s, int64_t m,
     hi = min(hi, lo + step - 1);
   }
   const int64_t base = static_cast<int64_t>(lo) * CHUNK;
-  for (int i = 0; i < 64; ++i) {
-    const int64_t g = base + i * 64 + lane;
-    seg[i * 65 + lane] = g < m ? static_cast<double>(s[g]) : 0.0;
+  // the chunk's rows, 32 loads in flight per lane before any is stored
+#pragma unroll
+  for (int i0 = 0; i0 < 64; i0 += 32) {
+    double tv[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int64_t g = base + (i0 + i) * 64 + lane;
+      tv[i] = g < m ? static_cast<double>(s[g]) : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < 32; ++i) seg[(i0 + i) * 65 + lane] = tv[i];
   }
   __syncthreads();
   double v[64];
