@@ -146,10 +146,21 @@ __device__ __forceinline__ void resid_direct_body(const double* __restrict__ y, 
   __shared__ double red[NT / 64];
   constexpr int TILE = NT * R;
   const int64_t row0 = static_cast<int64_t>(tile) * TILE;
-  // samples y[row0 .. row0 + TILE + p) (row i uses y[i .. i + p])
-  for (int t = threadIdx.x; t < TILE + p; t += NT) {
-    const int64_t g = row0 + t;
-    sy[resid_skew(t)] = g < m + p ? y[g] : 0.0;
+  // samples y[row0 .. row0 + TILE + p) (row i uses y[i .. i + p]), up to 16
+  // loads per thread in flight before any is stored
+  for (int t0 = threadIdx.x; t0 < TILE + p; t0 += 16 * NT) {
+    double v[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int t = t0 + k * NT;
+      const int64_t g = row0 + t;
+      v[k] = (t < TILE + p && g < m + p) ? y[g] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int t = t0 + k * NT;
+      if (t < TILE + p) sy[resid_skew(t)] = v[k];
+    }
   }
   __syncthreads();
   const int w = threadIdx.x * R + p - 1;  // sample of row 0 at lag 0

@@ -74,9 +74,18 @@ __device__ __forceinline__ void spectra_body(const double* __restrict__ y, int64
   constexpr int N = 1 << LGN;
   __shared__ cx<double> s[N];
   const int64_t start = static_cast<int64_t>(blk) * L;
-  for (int t = threadIdx.x; t < N; t += NT) {
-    const int64_t i0 = start + 2 * t;
-    s[swz<double>(t)] = {i0 < n ? y[i0] : 0.0, i0 + 1 < n ? y[i0 + 1] : 0.0};
+  // up to 8 sample pairs per thread in flight before any is stored
+  for (int t0 = threadIdx.x; t0 < N; t0 += 8 * NT) {
+    cx<double> v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t i0 = start + 2 * (t0 + k * NT);
+      v[k] = {t0 + k * NT < N && i0 < n ? y[i0] : 0.0,
+              t0 + k * NT < N && i0 + 1 < n ? y[i0 + 1] : 0.0};
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (t0 + k * NT < N) s[swz<double>(t0 + k * NT)] = v[k];
   }
   __syncthreads();
   fft_dif<double, false, LGN, NT>(s, tab);
