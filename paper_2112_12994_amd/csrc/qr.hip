@@ -134,8 +134,17 @@ __device__ __forceinline__ void trmm_body(const double* __restrict__ Ra,
                                                   double* __restrict__ C, int i) {
   const double* ra = Ra + static_cast<size_t>(i) * q;
   for (int j = threadIdx.x; j < q; j += NT) {
+    // eight terms' loads in flight, summed in the plain order
     double acc = 0.0;
-    for (int k = i; k <= j; ++k) acc += ra[k] * Rb[static_cast<size_t>(k) * q + j];
+    int k = i;
+    for (; k + 7 <= j; k += 8) {
+      double rb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) rb[u] = Rb[static_cast<size_t>(k + u) * q + j];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += ra[k + u] * rb[u];
+    }
+    for (; k <= j; ++k) acc += ra[k] * Rb[static_cast<size_t>(k) * q + j];
     C[static_cast<size_t>(i) * q + j] = acc;
   }
 }
