@@ -195,6 +195,11 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
     if (threadIdx.x == 0) s_fail = 0;
     __syncthreads();
     double dmin = INFINITY, dmax = 0.0;
+    // an unshifted attempt that will be redone with the shift stops at its
+    // first failed pivot (d is the same LDS word in every thread, so the
+    // whole workgroup leaves the column loop together)
+    const bool stop_on_fail = shift_mode == 2 && attempt == 0;
+    bool stopped = false;
     // column j = TD a0 + jj: tiles left of / above tile a0 are final (row j's
     // multipliers vanish there), so the register tile indices are static
 #pragma unroll
@@ -211,6 +216,10 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
         double d = pj[j];
         if (!(d > floor_)) {
           if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
+          if (j < rank_cols && stop_on_fail) {
+            stopped = true;
+            break;
+          }
           d = floor_;
         }
         if (j < rank_cols) {
@@ -248,9 +257,11 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
 #pragma unroll
           for (int b = a0; b < QT; ++b) reg[a][b] -= fi[a] * fk[b];
       }
+      if (stopped) break;
     }
     __syncthreads();
     const int failed = s_fail;
+    if (stopped) continue;  // redone with the shift; R is written by that attempt
     // R (q x q, row-major, zero below the diagonal) from the register tiles
 #pragma unroll
     for (int a = 0; a < QT; ++a)

@@ -265,10 +265,11 @@ def test_gather(ctx, mode):
 @pytest.mark.parametrize("c_rows,q,decades", [(64, 4, 3), (800, 101, 3), (2000, 65, 3), (400, 200, 3),
                                                 (4000, 129, 3), (1792, 224, 3), (1808, 225, 3),
                                                 (2400, 257, 3), (4008, 501, 3), (3000, 300, 7),
-                                                (8200, 1025, 3)])
+                                                (8200, 1025, 3), (800, 101, 12), (2400, 101, 13)])
 def test_qr_matches_lapack(ctx, c_rows, q, decades):
     """Orders above 224 take the blocked Cholesky (32 x 32 blocks): whole and
-    ragged last blocks, and columns scaled over 7 decades."""
+    ragged last blocks, and columns scaled over 7 decades; at 12 and 13
+    decades the unshifted sweeps can break down and are redone shifted."""
     c = capi()
     torch, dev = torch_dev()
     say("qr", c_rows, q, decades)
