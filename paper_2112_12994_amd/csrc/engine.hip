@@ -105,7 +105,10 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     if (e != TLS_OK) return e;
     // Chunks of iterations with one chunk always queued behind the one the
     // host waits for, so the device never idles on the host's convergence
-    // check; iterations queued after convergence exit at once.
+    // check; iterations queued after convergence exit at once.  The first
+    // check comes after CHUNK_ITERS iterations with half as many queued
+    // behind it, later chunks are two iterations long, so at most a few
+    // launches run past convergence.
     int launched = 0;
     auto chunk = [&](int iters, int slot) -> tls_status {
       for (int it = 0; it < iters; ++it) {
@@ -118,7 +121,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       return TLS_OK;
     };
     e = chunk(CHUNK_ITERS, 0);
-    if (e == TLS_OK) e = chunk(CHUNK_ITERS, 1);
+    if (e == TLS_OK) e = chunk(CHUNK_ITERS / 2, 1);
     if (e != TLS_OK) return e;
     for (int k = 0;; ++k) {
       const int slot = k & 1;
