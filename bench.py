@@ -792,9 +792,14 @@ def main():
     print(f"[bench] timed {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
 
     B, nb = out["block_len"], out["n_blocks"]
-    if prec == 0:
+    # the profiled fits report which pass dominated: the fused FP64 LSQR pass
+    # (FP64 fits, and mixed fits whose FP64 finish took the most time) or the
+    # FP32 normal-equation pass of the refinement
+    if out["pass_kind"] == 0:
         bytes_pass = fused_pass_bytes(y.size, p, B, nb, 8)
         kernel_name = "toep_pass_kernel<double, fused>: e = X v - a u, X^T e, ||e||^2"
+        if prec != 0:
+            kernel_name += " (the FP64 LSQR finish of the mixed fit)"
     else:
         # the CG pass reads only the FP32 spectra and writes the block partials
         bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * nb * 8

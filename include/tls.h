@@ -126,13 +126,16 @@ typedef struct tls_result {
   int32_t n_blocks;    /* FFT blocks per pass */
   double t_total_ms;   /* wall time of the call */
   double pass_ms;      /* profile = 1: summed device time of every launch of the dominant
-                          Toeplitz pass (FP64: the fused LSQR pass; mixed: the FP32
-                          normal-equation pass), including launches queued after the fit
-                          had converged, which exit at once */
+                          Toeplitz pass (pass_kind says which), including launches queued
+                          after the fit had converged, which exit at once */
   int32_t pass_count;  /* profile = 1: number of those launches (batched calls: pass_ms and
                           pass_count cover the whole batch's launches, the same in every
                           fit's result) */
   int32_t pass_worked; /* profile = 1: how many of them did work */
+  int32_t pass_kind;   /* which pass the three fields above cover: 0 the fused FP64 LSQR
+                          pass, 1 the FP32 normal-equation pass of the mixed refinement.
+                          A mixed single fit whose FP64 LSQR finish ran reports whichever
+                          of the two took more device time; batched mixed fits report 1 */
 } tls_result;
 
 typedef struct tls_ctx tls_ctx;

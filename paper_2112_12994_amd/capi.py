@@ -87,6 +87,7 @@ class TlsResult(ctypes.Structure):
         ("pass_ms", ctypes.c_double),
         ("pass_count", ctypes.c_int32),
         ("pass_worked", ctypes.c_int32),
+        ("pass_kind", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -783,6 +783,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       record_result(hrec[j], pl, ms, &res[i]);
       res[i].pass_ms = pass_ms;  // the whole batch's launches of the dominant pass
       res[i].pass_count = pass_count;
+      res[i].pass_kind = mixed ? 1 : 0;  // mixed: only the FP32 passes are timed
     }
     st[i] = record_status(hrec[j], coef, pl.p);
   }

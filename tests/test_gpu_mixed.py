@@ -100,3 +100,26 @@ def test_mixed_device_input_deterministic(ctx):
     a = ctx.fit_device(to_dev(y), 20, 1e-10, precision=MIXED)
     b = ctx.fit(y, 20, 1e-10, precision=MIXED)
     assert a["coef"].tobytes() == b["coef"].tobytes()
+
+
+def test_profiled_pass_kind(ctx):
+    """profile = 1 reports which pass its timings cover: the fused FP64 pass
+    for an FP64 fit; the FP32 normal-equation pass for a mixed fit whose
+    refinement converges; for a mixed fit with an FP64 finish, whichever took
+    more device time.  Profiling changes no result."""
+    say("profiled pass kind")
+    f = synth.workload_ar100(seed=0, n=1 << 18)
+    a = ctx.fit(f.y, 100, 1e-10, profile=1)
+    assert a["pass_kind"] == 0
+    assert a["pass_count"] >= a["pass_worked"] >= a["iters"] >= 1 and a["pass_ms"] > 0
+    b0 = ctx.fit(f.y, 100, 1e-10, precision=MIXED)
+    b = ctx.fit(f.y, 100, 1e-10, precision=MIXED, profile=1)
+    assert b["coef"].tobytes() == b0["coef"].tobytes()
+    assert b["pass_kind"] in (0, 1) and b["pass_count"] >= b["pass_worked"] >= 1 and b["pass_ms"] > 0
+    g = synth.workload_ar3(seed=0)
+    c0 = ctx.fit(g.y, 3, 1e-10, gamma=g.gamma, precision=MIXED)
+    c = ctx.fit(g.y, 3, 1e-10, gamma=g.gamma, precision=MIXED, profile=1)
+    say("   ar100 mixed kind=%d count=%d; ar3 mixed kind=%d istop=%d refine=%d"
+        % (b["pass_kind"], b["pass_count"], c["pass_kind"], c["istop"], c["refine_steps"]))
+    assert c["coef"].tobytes() == c0["coef"].tobytes()
+    assert c["pass_kind"] == 1 and c["pass_count"] >= c["pass_worked"] >= 1
