@@ -79,9 +79,10 @@ def hbm_profile_name(workload: str, precision: str) -> str:
     return os.path.join(ROOT, "profiles", f"toep_pass_{precision}_{workload}_hbm_counters.txt")
 
 
-def read_hbm_profile(workload: str, precision: str):
+def read_hbm_profile(workload: str, precision: str, kernel_prefix: str = "toep_pass_kernel<double"):
     """HBM bytes per launch of the dominant pass from the committed counter
-    summary, or None when there is none or the pass sources changed since."""
+    summary, or None when there is none, it covers another kernel, or the
+    pass sources changed since."""
     path = hbm_profile_name(workload, precision)
     if not os.path.exists(path):
         return None, "no counter profile"
@@ -91,6 +92,8 @@ def read_hbm_profile(workload: str, precision: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
+    if not kv.get("kernel", "").startswith(kernel_prefix):
+        return None, f"the counter profile covers {kv.get('kernel')}, not the timed pass"
     if kv.get("source_hash") != pass_source_hash():
         return None, "pass sources changed since the counters were taken"
     return float(kv["hbm_bytes_per_dispatch"]), os.path.relpath(path, ROOT)
@@ -812,7 +815,9 @@ def main():
     achieved = bytes_launch / avg_pass_s / 1e9 if pass_count else 0.0
     traffic, traffic_src = None, "non-default configuration"
     if not args.block_lg and not args.n:
-        traffic, traffic_src = read_hbm_profile(args.workload, args.precision)
+        traffic, traffic_src = read_hbm_profile(
+            args.workload, args.precision,
+            "toep_pass_kernel<double" if out["pass_kind"] == 0 else "toep_pass_kernel<float")
     if args.workload == "ar500":
         ref = ctx.fit_device(dy, p, f.tol, stream=stream, precision=0)
         acc = gpu_fp64_agreement(y, p, out, ref)

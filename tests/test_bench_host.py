@@ -21,10 +21,11 @@ def test_fused_pass_bytes_ar100():
     assert bench.fused_pass_bytes(1 << 22, 100, 1024, 4535, 8) == expect
 
 
-def _profile(path, source_hash, value):
+def _profile(path, source_hash, value, kernel="toep_pass_kernel<double, 9, 64, 3>"):
     with open(path, "w") as fh:
         fh.write("# test profile\n")
         fh.write(f"source_hash: {source_hash}\n")
+        fh.write(f"kernel: {kernel}\n")
         fh.write(f"hbm_bytes_per_dispatch: {value}\n")
 
 
@@ -38,6 +39,10 @@ def test_hbm_profile_gate(tmp_path, monkeypatch):
     _profile(path, "0" * 16, 12345)
     value, why = bench.read_hbm_profile("ar100", "f64")
     assert value is None and "changed" in why
+    _profile(path, bench.pass_source_hash(), 12345, "toep_pass_kernel<float, 9, 64, 3>")
+    value, why = bench.read_hbm_profile("ar100", "f64")
+    assert value is None and "covers" in why
+    assert bench.read_hbm_profile("ar100", "f64", "toep_pass_kernel<float")[0] == 12345.0
 
 
 def test_committed_profile_matches_sources():
