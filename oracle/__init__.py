@@ -24,8 +24,9 @@ from .leverage import (  # noqa: F401
 )
 from .sketch import (  # noqa: F401
     uniform_rows, leverage_sample, sketch_rows, hadamard, srht_map, jl_omega,
-    compressed_solution, rh_levels, rh_level_mask,
+    compressed_solution, rh_levels, rh_level_mask, rh_sketch,
 )
 from .philox import philox4x32_10, philox_uniform, philox_normal  # noqa: F401
 from .lsqr import lsqr  # noqa: F401
 from .pacf import pacf, pacf_compressed, pacf_order  # noqa: F401
+from .lsar import lsar_pacf, scores_lag1, scores_next, residual as lsar_residual  # noqa: F401

@@ -25,7 +25,6 @@ identity between the G-form and the Omega-form.
 from __future__ import annotations
 
 import numpy as np
-import scipy.linalg as sla
 
 from .toeplitz import lag_matrix
 
@@ -76,9 +75,3 @@ def scores_from_omega(y, p: int, Omega) -> np.ndarray:
     X, _ = lag_matrix(y, p)
     Z = X @ np.asarray(Omega, np.float64)
     return np.sum(Z * Z, axis=1)
-
-
-def omega_from_r(R, Pi) -> np.ndarray:
-    """Omega = R^{-1} Pi^T for upper-triangular R (d x d) and Pi (k x d)."""
-    return sla.solve_triangular(np.asarray(R, np.float64), np.asarray(Pi, np.float64).T,
-                                lower=False)

@@ -16,7 +16,12 @@ compressed estimator on given sampled rows.
 Parity pins (tests/test_oracle_pacf.py): the h = 1 closed form
 sum y_i y_{i+1} / sum y_i^2 over the rows; the Frisch-Waugh-Lovell ratio of
 independently computed residuals (numpy lstsq) at every lag; an AR(1) series
-whose PACF vanishes beyond lag 1 within its sampling band.
+whose PACF vanishes beyond lag 1 within its sampling band.  pacf_compressed:
+with every row once at unit scale it equals pacf; its lag-1 value on sampled
+rows has the weighted closed form sum s^2 y_i y_{i+1} / sum s^2 y_i^2; at
+every lag it equals the weighted Frisch-Waugh-Lovell ratio on the sampled
+rows with the lags taken by explicit indexing (a window one sample off fails
+that pin, which a test plants and checks).
 """
 from __future__ import annotations
 

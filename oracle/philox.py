@@ -19,7 +19,10 @@ counter (j, 0, s, f) and key (S mod 2^32, S >> 32); the four output words
 and a standard normal by Box-Muller from the pair (u, u') of draws 2j, 2j+1:
 sqrt(-2 ln u) cos(2 pi u').
 
-Parity pin: the known-answer vectors in tests/golden/philox4x32_10_kat.txt.
+Parity pins: the known-answer vectors in tests/golden/philox4x32_10_kat.txt;
+two normals worked by hand from the first of them and the Box-Muller pairing
+(tests/golden/philox_normal_box_muller.txt), which a swap of cos and sin or
+of the pair fails.
 """
 from __future__ import annotations
 

@@ -15,6 +15,14 @@ rh_levels, rh_level_mask: the nested uniform halvings of Algorithm 4 (repeated
   halving): row r belongs to level i when its draw u_r < 2^-i (so each level
   is a uniform half of the one before, in expectation), with as many levels
   as halvings of m rows until a level holds no more than c rows.
+rh_sketch: Algorithm 4 end to end.  The smallest level is stood for by c
+  uniform row trials (scale sqrt(m/c)); going up, level i's rows are scored
+  with the approximate generalised leverage scores of eq. (glev) with respect
+  to the sketch of level i + 1 (R from a Householder QR of that sketch's
+  first p columns, Omega = R^{-1} Pi^T with one k x p JL map Pi for every
+  level), rows outside level i get score zero, and c rows are drawn from the
+  scores (leverage_sample with that level's draws) to form level i's sketch;
+  level 0 is all rows, and its sketch is the result.
 compressed_solution: the compressed (sketch-and-solve) estimator of Section
   2.1, the minimiser of ||S X phi - S b|| (eq. (OLSc)), by Householder QR of
   S X.
@@ -26,7 +34,12 @@ srht_map: a k x p subsampled randomized Hadamard map sqrt(P/k) S H D on the
 jl_omega: Omega = R^{-1} Pi^T, the k columns whose row products give the
   approximate generalised leverage scores of eq. (glev).
 
-Parity pins (tests/test_oracle_sketch.py): the compressed estimator with every
+Parity pins (tests/test_oracle_sketch.py): rh_sketch with one level is the
+one-level leverage sketch (uniform trials, eq. (glev) scores w.r.t. them,
+leverage sampling) built step by step; rows drawn at a level above 0 lie in
+that level and level 0 draws from all rows; with k = p and Pi = I its top-level
+scores are the exact generalised scores of Definition 3.6 w.r.t. the level
+below.  The compressed estimator with every
 row at unit scale equals the full least-squares solution, recovers the
 coefficients of a noise-free AR series from any sampled rows, has the p = 1
 closed form sum s^2 x b / sum s^2 x^2, and ignores a common row scale and row
@@ -39,7 +52,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from .toeplitz import lag_matrix
+from .toeplitz import lag_matrix, matvec
 
 
 def uniform_rows(u, m: int, c: int | None = None):
@@ -119,3 +132,26 @@ def jl_omega(R, Pi) -> np.ndarray:
     """Omega = R^{-1} Pi^T (p x k) for upper-triangular R."""
     return sla.solve_triangular(np.asarray(R, np.float64), np.asarray(Pi, np.float64).T,
                                 lower=False)
+
+
+def rh_sketch(y, p: int, c: int, u_uniform, u_level, Pi, level_draws):
+    """Algorithm 4 (module doc).  u_uniform: c uniforms of the smallest
+    level's trials; u_level: one uniform per row (the nested halvings);
+    Pi: k x p JL map; level_draws[i]: c uniforms of level i's draws, for
+    i < rh_levels(m, c).  Returns (A, idx, scale, levels): the final sketch
+    [S X | S b], its rows and scales, and the number of levels."""
+    y = np.asarray(y, np.float64)
+    m = y.size - p
+    levels = rh_levels(m, c)
+    idx, scale = uniform_rows(u_uniform, m, c)
+    A = sketch_rows(y, p, idx, scale)
+    for lev in range(levels - 1, -1, -1):
+        R = sla.qr(A[:, :p], mode="r")[0][:p, :p]
+        Omega = jl_omega(R, Pi)
+        Z = np.column_stack([matvec(y, p, Omega[:, q]) for q in range(Omega.shape[1])])
+        s = np.sum(Z * Z, axis=1)
+        if lev > 0:
+            s = np.where(rh_level_mask(u_level, lev), s, 0.0)
+        idx, scale = leverage_sample(s, level_draws[lev], c)
+        A = sketch_rows(y, p, idx, scale)
+    return A, idx, scale, levels
