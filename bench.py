@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOAD_TEXT = {
     "ar100": "AR(100) series, n=2^22, 50 pole pairs with moduli U[0.5,0.95] and angles "
-             "U(0,pi), N(0,1) innovations, seed 0; sketch 24p rows, LSQR tol 1e-10, FP64",
+             "U(0,pi), N(0,1) innovations, seed 0; sketch 8p rows, LSQR tol 1e-10, FP64",
     "ar3": "AR(3), phi=(0.5,-0.3,0.1), n=10000, N(0,1), burn-in 500, seed 0; sketch 20p, "
            "LSQR tol 1e-10, FP64",
     "ar500": "AR(500) series, n=2^25, 250 pole pairs with moduli U[0.5,0.95] and angles U(0,pi), "
@@ -191,7 +191,8 @@ def cpu_baseline(y: np.ndarray, p: int, budget_s: float = 20.0) -> dict:
             break
         rows = min(m_full, rows * 4)
     per_solve = t * m_full / rows
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": int(cores),
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"oracle.fit_qr (dense [X|b] + LAPACK Householder QR) on the first "
                       f"{rows + p} samples ({rows} rows) in {t:.2f} s, scaled by {m_full}/{rows} "
                       f"rows to one full-size solve"}
@@ -356,7 +357,8 @@ def batch_bench(args, torch, synth, capi):
             cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1])
         except Exception:  # pragma: no cover
             cores = os.cpu_count() or 1
-        cpu = {"value": len(fits) / total, "unit": "solves/s", "cores": int(cores), "kind": "oracle",
+        cpu = {"value": len(fits) / total, "unit": "solves/s", "cores": int(cores),
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"oracle.fit_qr on the first {done} of the {len(fits)} series in {t:.1f} s, "
                          f"scaled by the m (p+1)^2 cost of all series"}
     classes = sorted({(o["block_len"]) for o in outs})
@@ -480,7 +482,8 @@ def pacf_bench(args, torch, synth, capi):
             sub[h - 1] = ctx.fit(y[: nsub - lags + h], h, 1e-10)["coef"][h - 1]
         cost_sample = sum((nsub - lags) * (h + 1) ** 2 for h in range(1, lags + 1))
         cost_all = sum((y.size - pmax) * (h + 1) ** 2 for h in range(1, pmax + 1))
-        cpu = {"value": pmax / (t * cost_all / cost_sample), "unit": "lag fits/s", "cores": 16,
+        cpu = {"value": pmax / (t * cost_all / cost_sample), "unit": "lag fits/s",
+               "cores": lapack_threads(), "cpu_model": cpu_model(),
                "kind": "oracle",
                "sample": f"oracle.pacf of lags 1..{lags} on the first {nsub} samples in {t:.2f} s, "
                          f"scaled by the m (h+1)^2 cost of all {pmax} lags at full length",
@@ -664,7 +667,8 @@ def serve_bench(args, torch, synth, capi):
                 break
         t = time.perf_counter() - tc0
         total = t * sum(cost) / sum(cost[:done])
-        cpu = {"value": arrivals.size / total, "unit": "requests/s", "cores": os.cpu_count() or 1,
+        cpu = {"value": arrivals.size / total, "unit": "requests/s", "cores": lapack_threads(),
+               "cpu_model": cpu_model(),
                "kind": "oracle",
                "sample": f"oracle.fit_qr on the first {done} of {arrivals.size} requests in {t:.1f} s, "
                          f"scaled by the m (p+1)^2 cost of all requests"}
@@ -692,6 +696,100 @@ def serve_bench(args, torch, synth, capi):
     print(json.dumps(line), flush=True)
 
 
+def time_fits(ctx, dy, p, tol, stream, torch, steps, warmup, **opts):
+    """`warmup` untimed fits, then `steps` timed fits of the resident series.
+    HIP events bracket every pass of the last tenth of the timed fits (at
+    least one): they give the pass's launch durations, and since an event
+    record between kernels adds a gap, the other fits run without them."""
+    out = None
+    for _ in range(warmup):
+        out = ctx.fit_device(dy, p, tol, stream=stream, **opts)
+    torch.cuda.synchronize()
+    nprof = max(1, steps // 10)
+    pass_ms, pass_count, pass_worked, iters = 0.0, 0, 0, []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        out = ctx.fit_device(dy, p, tol, stream=stream, profile=int(i >= steps - nprof), **opts)
+        pass_ms += out["pass_ms"]
+        pass_count += out["pass_count"]
+        pass_worked += out["pass_worked"]
+        iters.append(out["iters"])
+    torch.cuda.synchronize()
+    return {"out": out, "elapsed": time.perf_counter() - t0, "pass_ms": pass_ms,
+            "pass_count": pass_count, "pass_worked": pass_worked, "iters": iters, "nprof": nprof}
+
+
+def roofline_record(n, p, run, steps, prec, traffic, traffic_src):
+    """Roofline of the dominant pass from the event-timed launches of `run`.
+    Every launch is timed, including the few queued after a fit converged
+    (they exit at once): bytes per launch is the algorithmic bytes of a
+    working pass times the fraction of launches that worked."""
+    out = run["out"]
+    B, nb = out["block_len"], out["n_blocks"]
+    if out["pass_kind"] == 0:
+        bytes_pass = fused_pass_bytes(n, p, B, nb, 8)
+        kernel_name = "toep_pass_kernel<double, fused>: e = X v - a u, X^T e, ||e||^2"
+        if prec != 0:
+            kernel_name += " (the FP64 LSQR finish of the mixed fit)"
+    else:
+        # the CG pass reads only the FP32 spectra and writes the block partials
+        bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * nb * 8
+        kernel_name = "toep_pass_kernel<float, fused>: X^T X v (CG normal-equation product)"
+    cnt = max(run["pass_count"], 1)
+    avg_pass_s = run["pass_ms"] / cnt / 1e3
+    bytes_launch = bytes_pass * run["pass_worked"] / cnt
+    achieved = bytes_launch / avg_pass_s / 1e9 if run["pass_count"] else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_source": traffic_src,
+            "kernel": kernel_name, "bytes_per_launch": bytes_launch,
+            "bytes_per_working_launch": bytes_pass, "avg_launch_us": avg_pass_s * 1e6,
+            "launches_timed": run["pass_count"], "launches_worked": run["pass_worked"],
+            "timed_in": f"HIP events around every pass of the last {run['nprof']} of the "
+                        f"{steps} timed fits"}
+
+
+def hbm_resident_record(ctx, torch, synth, capi, stream, steps=3):
+    """The fused FP64 pass on a working set far above the 256 MB Infinity
+    Cache: the AR(500), n = 2^25 series (0.86 GB of spectra and u per pass),
+    FP64 fits with every pass event-timed; counter traffic from the
+    committed profile of that configuration."""
+    t0 = time.perf_counter()
+    f = synth.workload_ar500(seed=0)
+    print(f"[bench] AR(500) n=2^25 series generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    dy = torch.from_numpy(f.y).to("cuda:0")
+    run = time_fits(ctx, dy, f.p, f.tol, stream, torch, steps, 1, precision=0, gamma=f.gamma)
+    traffic, src = read_hbm_profile("ar500", "f64")
+    rec = roofline_record(f.y.size, f.p, run, steps, 0, traffic, src)
+    rec["timed_in"] = f"HIP events around every pass of {steps} FP64 fits"
+    rec.update({"workload": "AR(500), n=2^25, seed 0, FP64, sketch 8p rows, tol 1e-10",
+                "iters": int(np.median(run["iters"])),
+                "status": capi.status_string(run["out"]["status"]),
+                "working_set_bytes": rec["bytes_per_working_launch"]})
+    del dy
+    torch.cuda.empty_cache()
+    return rec
+
+
+def lapack_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count() or 1]))
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -699,10 +797,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ar100", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="ar100: skip the 24p-sketch and HBM-resident AR(500) sub-records")
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed"])
     ap.add_argument("--block-lg", type=int, default=0, help="log2 FFT block length (0 = automatic)")
     ap.add_argument("--n", type=int, default=0, help="override the series length")
-    ap.add_argument("--duration", type=float, default=20.0, help="serve: seconds of arrivals")
+    ap.add_argument("--duration", type=float, default=60.0, help="serve: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=5000.0, help="serve: requests per second")
     ap.add_argument("--pool", type=int, default=512, help="serve: resident series in the pool")
     ap.add_argument("--serve-budget", type=int, default=64, help="serve: HBM budget in GiB")
@@ -768,56 +868,18 @@ def main():
     ctx = capi.Context(0, gamma=f.gamma, precision=prec, block_lg=args.block_lg)
     stream = torch.cuda.current_stream()
 
-    out = None
-    for _ in range(args.warmup):
-        out = ctx.fit_device(dy, p, f.tol, stream=stream)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done: status {out['status'] if out else None}", file=sys.stderr, flush=True)
-
-    pass_ms = 0.0
-    pass_count = 0
-    pass_worked = 0
-    iters = []
-    # HIP events around every pass of the last `nprof` timed fits give the
-    # pass's launch durations; the events themselves add gaps between
-    # kernels, so the other fits run without them.
-    nprof = max(1, args.steps // 10)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        out = ctx.fit_device(dy, p, f.tol, stream=stream, profile=int(i >= args.steps - nprof))
-        pass_ms += out["pass_ms"]
-        pass_count += out["pass_count"]
-        pass_worked += out["pass_worked"]
-        iters.append(out["iters"])
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    print(f"[bench] timed {args.steps} steps in {elapsed:.4f} s", file=sys.stderr, flush=True)
-
+    run = time_fits(ctx, dy, p, f.tol, stream, torch, args.steps, args.warmup)
+    out = run["out"]
+    print(f"[bench] timed {args.steps} steps in {run['elapsed']:.4f} s", file=sys.stderr, flush=True)
     B, nb = out["block_len"], out["n_blocks"]
-    # the profiled fits report which pass dominated: the fused FP64 LSQR pass
-    # (FP64 fits, and mixed fits whose FP64 finish took the most time) or the
-    # FP32 normal-equation pass of the refinement
-    if out["pass_kind"] == 0:
-        bytes_pass = fused_pass_bytes(y.size, p, B, nb, 8)
-        kernel_name = "toep_pass_kernel<double, fused>: e = X v - a u, X^T e, ||e||^2"
-        if prec != 0:
-            kernel_name += " (the FP64 LSQR finish of the mixed fit)"
-    else:
-        # the CG pass reads only the FP32 spectra and writes the block partials
-        bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * nb * 8
-        kernel_name = "toep_pass_kernel<float, fused>: X^T X v (CG normal-equation product)"
-    # Every launch of the pass is timed, including the few queued after a fit
-    # converged (they exit at once): bytes per launch is the algorithmic bytes
-    # of a working pass times the fraction of launches that worked.
-    avg_pass_s = pass_ms / max(pass_count, 1) / 1e3
-    bytes_launch = bytes_pass * pass_worked / max(pass_count, 1)
-    achieved = bytes_launch / avg_pass_s / 1e9 if pass_count else 0.0
     traffic, traffic_src = None, "non-default configuration"
     if not args.block_lg and not args.n:
         traffic, traffic_src = read_hbm_profile(
             args.workload, args.precision,
             "toep_pass_kernel<double" if out["pass_kind"] == 0 else "toep_pass_kernel<float")
+    roof = roofline_record(y.size, p, run, args.steps, prec, traffic, traffic_src)
+    elapsed = run["elapsed"]
+    iters = run["iters"]
     if args.workload == "ar500":
         ref = ctx.fit_device(dy, p, f.tol, stream=stream, precision=0)
         acc = gpu_fp64_agreement(y, p, out, ref)
@@ -838,21 +900,26 @@ def main():
         "dtype": "f64" if prec == 0 else "f32 products, f64 recurrences",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "n": int(y.size), "p": p,
-                   "sketch_rows": out["sketch_rows"], "fft_block": B, "fft_blocks": nb,
+                   "sketch_rows": out["sketch_rows"], "sketch_gamma": f.gamma,
+                   "fft_block": B, "fft_blocks": nb,
                    "precision": args.precision, "iters": int(np.median(iters)),
                    "refine_steps": out["refine_steps"], "kappa_est_R": out["kappa_est"],
                    "status": capi.status_string(out["status"])},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_source": traffic_src,
-                     "kernel": kernel_name,
-                     "bytes_per_launch": bytes_launch, "bytes_per_working_launch": bytes_pass,
-                     "avg_launch_us": avg_pass_s * 1e6,
-                     "launches_timed": pass_count, "launches_worked": pass_worked,
-                     "timed_in": f"HIP events around every pass of the last {nprof} of the "
-                                 f"{args.steps} timed fits"},
+        "roofline": roof,
         "accuracy": acc,
     }
+    if args.workload == "ar100" and not args.n and not args.block_lg and not args.no_extras:
+        # the same series on a 24p-row sketch: fewer LSQR iterations for a larger QR
+        r24 = time_fits(ctx, dy, p, f.tol, stream, torch, args.steps, args.warmup, gamma=24)
+        line["sketch_24p"] = {
+            "what": "the same fit with a 24p-row sketch (not the configured 8p)",
+            "value": args.steps / r24["elapsed"], "unit": "solves/s",
+            "ms_per_step": r24["elapsed"] / args.steps * 1e3,
+            "iters": int(np.median(r24["iters"])), "sketch_rows": r24["out"]["sketch_rows"],
+            "roofline_frac": roofline_record(y.size, p, r24, args.steps, prec, None, "")["frac"]}
+        del dy
+        torch.cuda.empty_cache()
+        line["hbm_resident"] = hbm_resident_record(ctx, torch, synth, capi, stream)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(y, p)
     ctx.close()

@@ -23,8 +23,8 @@
  *    context's own stream.  tls_op_* calls only enqueue work; tls_fit* calls
  *    return after the fit is complete.
  *  - Every call returns a tls_status; no exception crosses the ABI.  On any
- *    status other than TLS_OK, TLS_ENOCONV and TLS_ERANK, outputs are left
- *    unwritten.
+ *    status other than TLS_OK, TLS_ENOCONV, TLS_ESTALL and TLS_ERANK, outputs
+ *    are left unwritten.
  *  - A context is not thread-safe; use one context per host thread.
  */
 #ifndef TLS_H_
@@ -41,12 +41,16 @@ typedef int32_t tls_status;
 #define TLS_OK 0          /* success */
 #define TLS_EINVAL 1      /* invalid argument: NULL pointer, p < 1, n < 2p + 1, tol not in (0,1), non-finite data */
 #define TLS_ERANK 2       /* X numerically rank deficient (Theorem 2.2's singular case), or the preconditioned
-                             iteration broke down numerically; outputs hold the last finite iterate */
+                             iteration broke down numerically, or a returned coefficient is not
+                             finite (overflow on finite data); outputs hold the last iterate */
 #define TLS_ENOCONV 3     /* iteration limit reached; outputs hold the last iterate */
 #define TLS_ENOMEM 4      /* device allocation failed */
 #define TLS_EDEVICE 5     /* HIP runtime error */
 #define TLS_EUNSUPPORTED 6 /* size outside the supported range (p > 1024 or FFT block limits) */
 #define TLS_EAGAIN 7      /* served request not finished yet (tls_poll) */
+#define TLS_ESTALL 8      /* tol was not met: the iteration stopped improving first (istop 5: the
+                             rounding of the FFT products was reached, i.e. the conditioning of X
+                             is beyond the working precision); outputs hold the best iterate */
 
 /* Static description of a status code. */
 const char* tls_status_string(tls_status s);
@@ -115,7 +119,7 @@ typedef struct tls_result {
   int32_t istop;       /* stop reason: 1, 2 converged; 3 exact; 4 breakdown; 5 the
                           ||A^T r|| estimate stopped decreasing (30 iterations without
                           halving: the rounding of the FFT products was reached before
-                          tol; the iterate is returned with TLS_OK); 7 iteration
+                          tol; the best iterate is returned with TLS_ESTALL); 7 iteration
                           limit.  Mixed precision: 2 when the FP64 refinement converged;
                           when it stopped contracting (conditioning beyond the FP32
                           products' resolution) or hit its step limit, FP64 LSQR finishes

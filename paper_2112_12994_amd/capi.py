@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtls.so")
 
 (TLS_OK, TLS_EINVAL, TLS_ERANK, TLS_ENOCONV, TLS_ENOMEM, TLS_EDEVICE, TLS_EUNSUPPORTED,
- TLS_EAGAIN) = range(8)
+ TLS_EAGAIN, TLS_ESTALL) = range(9)
 PREC_F64, PREC_MIXED = 0, 1
 SKETCH_LEVERAGE, SKETCH_UNIFORM, SKETCH_RH = 0, 1, 2
 JL_SRHT, JL_GAUSS = 0, 1

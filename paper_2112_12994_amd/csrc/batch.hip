@@ -394,9 +394,10 @@ hipError_t collect_b(const Item* fits, int nfits, const FitDesc* D, int mixed, d
 
 tls_status record_status(const FitRec& r, const double* coef, int p) {
   for (int k = 0; k < p; ++k)
-    if (!isfinite(coef[k])) return TLS_EINVAL;
+    if (!isfinite(coef[k])) return TLS_ERANK;
   if ((r.status[0] & 6) || (r.status[1] & 4) || r.istop == 4) return TLS_ERANK;
   if (r.istop == 7) return TLS_ENOCONV;
+  if (r.istop == 5) return TLS_ESTALL;
   return TLS_OK;
 }
 

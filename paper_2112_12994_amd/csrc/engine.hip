@@ -280,10 +280,12 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     res->pass_kind = pass_kind;
     res->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   }
+  // a non-finite coefficient from finite data is a numerical breakdown
   for (int i = 0; i < p; ++i)
-    if (!isfinite(coef[i])) return TLS_EINVAL;
+    if (!isfinite(coef[i])) return TLS_ERANK;
   if ((ho->status[0] & 6) || (ho->status[1] & 4) || istop == 4) return TLS_ERANK;
   if (istop == 7) return TLS_ENOCONV;
+  if (istop == 5) return TLS_ESTALL;
   return TLS_OK;
 }
 
@@ -309,6 +311,7 @@ const char* tls_status_string(tls_status s) {
     case TLS_EDEVICE: return "HIP runtime error";
     case TLS_EUNSUPPORTED: return "size outside the supported range";
     case TLS_EAGAIN: return "request not finished yet";
+    case TLS_ESTALL: return "iteration stalled at the working precision before tol";
     default: return "unknown status";
   }
 }
@@ -426,7 +429,7 @@ tls_status tls_fit(const double* series, int64_t n, int32_t p, double tol, doubl
   }
   tls_result r;
   tls_status st = tls_fit_ex(g_default, series, n, p, tol, nullptr, coef, &r);
-  if (st == TLS_OK || st == TLS_ENOCONV || st == TLS_ERANK) {
+  if (st == TLS_OK || st == TLS_ENOCONV || st == TLS_ESTALL || st == TLS_ERANK) {
     if (resid_norm) *resid_norm = r.resid_norm;
     if (iters) *iters = r.iters;
   }
@@ -446,7 +449,7 @@ tls_status tls_fit_batch(tls_ctx* ctx, int32_t count, const double* const* serie
                                      ctx->stream, coef_packed, coef_offset, r.data(), fs.data());
   for (int32_t i = 0; i < count; ++i) {
     if (per_fit_status) per_fit_status[i] = fs[i];
-    if (fs[i] == TLS_OK || fs[i] == TLS_ENOCONV || fs[i] == TLS_ERANK) {
+    if (fs[i] == TLS_OK || fs[i] == TLS_ENOCONV || fs[i] == TLS_ESTALL || fs[i] == TLS_ERANK) {
       if (resid_norm) resid_norm[i] = r[i].resid_norm;
       if (iters) iters[i] = r[i].iters;
     }

@@ -36,6 +36,20 @@ bool lsqr_step_lds(int lgn, int p) {
   return p <= 128 && with_m + lds_static <= 160 * 1024;
 }
 
+// Dynamic LDS of the refinement kernels: three p-vectors, plus M (rows of
+// odd length p | 1) when it is staged.
+size_t refine_shm(int pmax, bool mlds) {
+  return (3 * static_cast<size_t>(pmax) + (mlds ? static_cast<size_t>(pmax) * (pmax | 1) : 0)) *
+         sizeof(double);
+}
+
+// The refinement kernels stage M in LDS when p <= 128 and it fits beside
+// their static 2^LGN-point FP64 transform buffer and reduction words.
+bool refine_lds(int lgn, int pmax) {
+  const size_t lds_static = static_cast<size_t>(1 << lgn) * 16 + 64;
+  return pmax <= 128 && lds_static + refine_shm(pmax, true) <= 160 * 1024;
+}
+
 namespace {
 
 // Stages the p x p (p <= 128) row-major upper triangular matrix M into LDS
@@ -454,7 +468,8 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
                                                           double* __restrict__ res,
                                                           double* __restrict__ d,
                                                           cx<float>* __restrict__ Vhat32,
-                                                          const cx<double>* __restrict__ tab) {
+                                                          const cx<double>* __restrict__ tab,
+                                                          bool mlds) {
   constexpr int N = 1 << LGN;
   __shared__ cx<double> s[N];
   __shared__ double red[NT / 64];
@@ -464,8 +479,13 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
   double* sq = sh + p;    // p
   double* sM = sq + p;    // p x ldm when lds
   const int ldm = p | 1;
-  const bool lds = p <= 128;
+  const bool lds = mlds && p <= 128;
   if (st->done) return;
+  // every thread reads the state it decides on before thread 0 rewrites it
+  // (the barrier ahead of the state update below)
+  const int outer = st->outer;
+  const double hbest = st->hbest, hprev = st->hprev, tol = st->tol;
+  const int max_refine = st->max_refine;
   if (lds)
     stage_m<NT>(M, p, ldm, sM);
   for (int i = threadIdx.x; i < p; i += NT) sx[i] = g64[i];
@@ -473,21 +493,20 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
   gemv_m<NT, true>(M, Mt, sM, ldm, lds, p, sx, sh);  // h = M^T X^T r
   const double hh = dot_block<NT>(sh, sh, p, red);
   const double hn = sqrt(hh), rn = sqrt(g64[p]);
-  const int outer = st->outer;
   // keep the best iterate: the FP32 products may stop contracting, or expand,
   // beyond their resolution
-  const bool best = outer == 0 || hn < st->hbest;
+  const bool best = outer == 0 || hn < hbest;
   if (best)
     for (int i = threadIdx.x; i < p; i += NT) phib[i] = phi[i];
   bool done = false;
   int stop = 0;
-  if (hn <= st->tol * rn) {
+  if (hn <= tol * rn) {
     done = true;
     stop = 1;
-  } else if (outer >= st->max_refine) {
+  } else if (outer >= max_refine) {
     done = true;
     stop = 7;
-  } else if (outer > 0 && !(hn < 0.5 * st->hprev)) {
+  } else if (outer > 0 && !(hn < 0.5 * hprev)) {
     done = true;  // no further contraction (FP32 products at their resolution)
     stop = 5;
   }
@@ -500,6 +519,7 @@ __device__ __forceinline__ void refine_outer_body(int p, RefineState* __restrict
     gemv_m<NT, false>(M, Mt, sM, ldm, lds, p, sh, sq);  // M d
     spectrum_of<LGN, NT, float>(sq, p, s, Vhat32, tab);
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     st->rnorm = rn;
     st->hprev = st->hnorm > 0.0 ? fmin(st->hnorm, hn) : hn;
@@ -526,8 +546,9 @@ __global__ __launch_bounds__(NT) void refine_outer_kernel(int p, RefineState* __
                                                           double* __restrict__ res,
                                                           double* __restrict__ d,
                                                           cx<float>* __restrict__ Vhat32,
-                                                          const cx<double>* __restrict__ tab) {
-  refine_outer_body<LGN, NT>(p, st, g64, M, Mt, phi, phib, w, res, d, Vhat32, tab);
+                                                          const cx<double>* __restrict__ tab,
+                                                          bool mlds) {
+  refine_outer_body<LGN, NT>(p, st, g64, M, Mt, phi, phib, w, res, d, Vhat32, tab, mlds);
 }
 
 template <int LGN, int NT>
@@ -540,7 +561,8 @@ __device__ __forceinline__ void refine_cg_body(int p, RefineState* __restrict__ 
                                                        double* __restrict__ d,
                                                        double* __restrict__ phi,
                                                        cx<float>* __restrict__ Vhat32,
-                                                       const cx<double>* __restrict__ tab) {
+                                                       const cx<double>* __restrict__ tab,
+                                                       bool mlds) {
   constexpr int N = 1 << LGN;
   __shared__ cx<double> s[N];
   __shared__ double red[NT / 64];
@@ -550,7 +572,7 @@ __device__ __forceinline__ void refine_cg_body(int p, RefineState* __restrict__ 
   double* sq = st_ + p; // p
   double* sM = sq + p;
   const int ldm = p | 1;
-  const bool lds = p <= 128;
+  const bool lds = mlds && p <= 128;
   if (st->inner_done) return;
   if (lds)
     stage_m<NT>(M, p, ldm, sM);
@@ -600,8 +622,9 @@ __global__ __launch_bounds__(NT) void refine_cg_kernel(int p, RefineState* __res
                                                        double* __restrict__ d,
                                                        double* __restrict__ phi,
                                                        cx<float>* __restrict__ Vhat32,
-                                                       const cx<double>* __restrict__ tab) {
-  refine_cg_body<LGN, NT>(p, st, g, M, Mt, w, res, d, phi, Vhat32, tab);
+                                                       const cx<double>* __restrict__ tab,
+                                                       bool mlds) {
+  refine_cg_body<LGN, NT>(p, st, g, M, Mt, w, res, d, phi, Vhat32, tab, mlds);
 }
 
 template <int LGN>
@@ -609,11 +632,10 @@ hipError_t refine_outer_one(int p, RefineState* st, const double* g64, const dou
                             const double* Mt, const double* phi, double* phib, double* w,
                             double* res, double* d, void* Vhat32, const Twiddles& tw,
                             hipStream_t s) {
-  const size_t shm = (3 * static_cast<size_t>(p) + (p <= 128 ? static_cast<size_t>(p) * (p | 1) : 0)) *
-                     sizeof(double);
-  hipLaunchKernelGGL((refine_outer_kernel<LGN, 256>), dim3(1), dim3(256), shm, s, p, st, g64, M, Mt,
-                     phi, phib, w, res, d, static_cast<cx<float>*>(Vhat32),
-                     static_cast<const cx<double>*>(tw.d64));
+  const bool mlds = refine_lds(LGN, p);
+  hipLaunchKernelGGL((refine_outer_kernel<LGN, 256>), dim3(1), dim3(256), refine_shm(p, mlds), s, p,
+                     st, g64, M, Mt, phi, phib, w, res, d, static_cast<cx<float>*>(Vhat32),
+                     static_cast<const cx<double>*>(tw.d64), mlds);
   return hipGetLastError();
 }
 
@@ -621,11 +643,10 @@ template <int LGN>
 hipError_t refine_cg_one(int p, RefineState* st, const double* g, const double* M, const double* Mt,
                          double* w, double* res, double* d, double* phi, void* Vhat32,
                          const Twiddles& tw, hipStream_t s) {
-  const size_t shm = (3 * static_cast<size_t>(p) + (p <= 128 ? static_cast<size_t>(p) * (p | 1) : 0)) *
-                     sizeof(double);
-  hipLaunchKernelGGL((refine_cg_kernel<LGN, 256>), dim3(1), dim3(256), shm, s, p, st, g, M, Mt, w,
-                     res, d, phi, static_cast<cx<float>*>(Vhat32),
-                     static_cast<const cx<double>*>(tw.d64));
+  const bool mlds = refine_lds(LGN, p);
+  hipLaunchKernelGGL((refine_cg_kernel<LGN, 256>), dim3(1), dim3(256), refine_shm(p, mlds), s, p, st,
+                     g, M, Mt, w, res, d, phi, static_cast<cx<float>*>(Vhat32),
+                     static_cast<const cx<double>*>(tw.d64), mlds);
   return hipGetLastError();
 }
 
@@ -733,11 +754,12 @@ template <int LGN, int NT>
 __global__ __launch_bounds__(NT) void refine_outer_b_kernel(const Item* __restrict__ fits,
                                                             const FitDesc* __restrict__ D,
                                                             int* __restrict__ counts,
-                                                            const cx<double>* __restrict__ tab) {
+                                                            const cx<double>* __restrict__ tab,
+                                                            bool mlds) {
   const FitDesc& d = D[fits[blockIdx.x].fit];
   if (!d.rst->done)
     refine_outer_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.phi, d.phib, d.cw, d.cres, d.cd,
-                               static_cast<cx<float>*>(d.Vhat32), tab);
+                               static_cast<cx<float>*>(d.Vhat32), tab, mlds);
   if (threadIdx.x == 0) {
     if (d.rst->done) atomicAdd(counts, 1);
     if (d.rst->inner_done) atomicAdd(counts + 1, 1);
@@ -748,11 +770,12 @@ template <int LGN, int NT>
 __global__ __launch_bounds__(NT) void refine_cg_b_kernel(const Item* __restrict__ fits,
                                                          const FitDesc* __restrict__ D,
                                                          int* __restrict__ counts,
-                                                         const cx<double>* __restrict__ tab) {
+                                                         const cx<double>* __restrict__ tab,
+                                                         bool mlds) {
   const FitDesc& d = D[fits[blockIdx.x].fit];
   if (d.rst->inner_done) return;
   refine_cg_body<LGN, NT>(d.p, d.rst, d.g, d.M, d.Mt, d.cw, d.cres, d.cd, d.phi,
-                          static_cast<cx<float>*>(d.Vhat32), tab);
+                          static_cast<cx<float>*>(d.Vhat32), tab, mlds);
   if (threadIdx.x == 0 && d.rst->inner_done) atomicAdd(counts + 1, 1);
 }
 
@@ -772,24 +795,22 @@ hipError_t step_b(const Item* fits, int nfits, int pmax, bool mlds, const FitDes
   return hipGetLastError();
 }
 
-size_t refine_shm(int pmax) {
-  return (3 * static_cast<size_t>(pmax) +
-          (pmax <= 128 ? static_cast<size_t>(pmax) * (pmax | 1) : 0)) * sizeof(double);
-}
-
 template <int LGN>
 hipError_t outer_b(const Item* fits, int nfits, int pmax, const FitDesc* D, int* counts,
                    const Twiddles& tw, hipStream_t s) {
-  hipLaunchKernelGGL((refine_outer_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax), s,
-                     fits, D, counts, static_cast<const cx<double>*>(tw.d64));
+  const bool mlds = refine_lds(LGN, pmax);
+  hipLaunchKernelGGL((refine_outer_b_kernel<LGN, 256>), dim3(nfits), dim3(256),
+                     refine_shm(pmax, mlds), s, fits, D, counts,
+                     static_cast<const cx<double>*>(tw.d64), mlds);
   return hipGetLastError();
 }
 
 template <int LGN>
 hipError_t cg_b(const Item* fits, int nfits, int pmax, const FitDesc* D, int* counts,
                 const Twiddles& tw, hipStream_t s) {
-  hipLaunchKernelGGL((refine_cg_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax), s,
-                     fits, D, counts, static_cast<const cx<double>*>(tw.d64));
+  const bool mlds = refine_lds(LGN, pmax);
+  hipLaunchKernelGGL((refine_cg_b_kernel<LGN, 256>), dim3(nfits), dim3(256), refine_shm(pmax, mlds),
+                     s, fits, D, counts, static_cast<const cx<double>*>(tw.d64), mlds);
   return hipGetLastError();
 }
 

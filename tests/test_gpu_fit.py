@@ -38,7 +38,12 @@ def _check_fit(out, y, p, gate=1e-6, tol=1e-10):
     err = oracle.rel_error(out["coef"], phi)
     say("   kappa=%.3g err=%.3g (bound %.2g) fit=%.3g (bound %.2g) iters=%d istop=%d"
         % (ref["kappa"], err, coef_b, xd / xphi, fit_b, out["iters"], out["istop"]))
-    assert out["status"] == c.TLS_OK, c.status_string(out["status"])
+    if out["status"] == c.TLS_ESTALL:
+        # the iteration reached the rounding of the products before tol: only
+        # where the conditioning puts the coefficients beyond FP64 resolution
+        assert out["istop"] == 5 and coef_b > gate, (coef_b, out["istop"])
+    else:
+        assert out["status"] == c.TLS_OK, c.status_string(out["status"])
     if coef_b < gate:
         assert err <= gate
     assert xd / xphi <= max(10 * fit_b, 1e-14)

@@ -34,7 +34,11 @@ def _check_mixed(out, y, p, gate=1e-4, tol=1e-10):
     say("   kappa=%.3g err=%.3g (bound %.2g) fit=%.3g refine=%d inner=%d istop=%d"
         % (ref["kappa"], err, coef_b, xd / xphi, out["refine_steps"], out["iters"], out["istop"]))
     rt = resid_tol(phi, ref["rnorm"], smax, np.abs(y).max(), p, xd)
-    assert out["status"] == c.TLS_OK, c.status_string(out["status"])
+    if out["status"] == c.TLS_ESTALL:
+        # the FP64 finish reached the rounding of its products before tol
+        assert out["istop"] == 5 and coef_b > gate, (coef_b, out["istop"])
+    else:
+        assert out["status"] == c.TLS_OK, c.status_string(out["status"])
     if coef_b < gate:
         assert err <= gate
     assert err <= max(100 * coef_b, 1e-12)
@@ -53,6 +57,19 @@ def test_mixed_matches_oracle(ctx, p, n, seed, rlo, rhi):
     y = synth.ar_series(n, p, rng, rlo, rhi)
     out = ctx.fit(y, p, 1e-10, precision=MIXED)
     _check_mixed(out, y, p)
+
+
+@pytest.mark.parametrize("block_lg", [12, 13, 14])
+def test_mixed_p128_long_blocks(ctx, block_lg):
+    """p = 128 with transform lengths 2^12..2^14: the refinement kernels'
+    transform buffer leaves too little LDS for M there at the longer lengths,
+    so they read M from global memory (the launch must not exceed LDS)."""
+    say("mixed p128 block_lg", block_lg)
+    rng = np.random.default_rng(40 + block_lg)
+    y = synth.ar_series(60000, 128, rng, 0.3, 0.8)
+    out = ctx.fit(y, 128, 1e-10, precision=MIXED, block_lg=block_lg)
+    assert out["block_len"] == 1 << block_lg
+    _check_mixed(out, y, 128)
 
 
 def test_mixed_ar500_shape(ctx):
