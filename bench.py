@@ -162,13 +162,23 @@ def prof_summary(kind: str, dirs: list, out: str, cmd: str, title: str):
     print("\n".join(lines))
 
 
+def pass_groups(B: int, nblocks: int) -> int:
+    """Workgroups of the Toeplitz pass: blocks are taken 4 at a time up to
+    B = 1024, 2 at a time up to B = 4096, else singly (the library's
+    pass_nw)."""
+    lgn = B.bit_length() - 2
+    nw = 4 if lgn <= 9 else (2 if lgn <= 11 else 1)
+    return -(-nblocks // nw)
+
+
 def fused_pass_bytes(n: int, p: int, B: int, nblocks: int, elem: int) -> int:
     """Algorithmic bytes of one fused pass: read every block spectrum
     (B/2 complex words per block), read and write the m-vector u, read v's
-    spectrum once, write the (p+1) partial sums of every block."""
+    spectrum once, write the (p+1) partial sums of every block group."""
     m = n - p
     spec = nblocks * (B // 2) * 2 * elem
-    return spec + 2 * m * elem + (B // 2) * 2 * elem + (p + 1) * nblocks * 8
+    return (spec + 2 * m * elem + (B // 2) * 2 * elem
+            + (p + 1) * pass_groups(B, nblocks) * 8)
 
 
 def cpu_baseline(y: np.ndarray, p: int, budget_s: float = 20.0) -> dict:
@@ -733,7 +743,7 @@ def roofline_record(n, p, run, steps, prec, traffic, traffic_src):
             kernel_name += " (the FP64 LSQR finish of the mixed fit)"
     else:
         # the CG pass reads only the FP32 spectra and writes the block partials
-        bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * nb * 8
+        bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * pass_groups(B, nb) * 8
         kernel_name = "toep_pass_kernel<float, fused>: X^T X v (CG normal-equation product)"
     cnt = max(run["pass_count"], 1)
     avg_pass_s = run["pass_ms"] / cnt / 1e3

@@ -168,6 +168,7 @@ ClassLists build_lists(std::vector<Item>& items, const std::vector<int>& desc,
   ClassLists c;
   auto sampled = [lev](const Plan& q) { return lev && !q.all_rows; };
   c.blocks = add_items(items, desc, plans, [](const Plan& q) { return q.nblocks; });
+  c.groups = add_items(items, desc, plans, [](const Plan& q) { return q.ngroups; });
   c.blocks1 = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? q.nblocks : 0; });
   c.rows1 = add_items(items, desc, plans, [](const Plan& q) { return q.crows; });
   c.rows2 = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? q.crows : 0; });
@@ -204,6 +205,7 @@ void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, 
   d->k = pl.k;
   d->L = pl.L;
   d->nblocks = pl.nblocks;
+  d->ngroups = pl.ngroups;
   d->nchunks = static_cast<int>((sample_work_doubles(pl.m) - 1) / 2);
   d->all_rows = pl.all_rows;
   d->fit = fit;
@@ -349,12 +351,12 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
 }
 
 tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
-                           const Item* blocks, int nblocks, const Item* cols, int ncols,
+                           const Item* groups, int ngroups, const Item* cols, int ncols,
                            const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
                            PassTimer* tm, hipStream_t s) {
   if (first) TLS_CHECK(launch_small_rfft_b(PREC_F64, lgn, 1, fits, nfits, D, ctx->tw, s));
   if (tm) TLS_CHECK(tm->begin(s));
-  TLS_CHECK(launch_toep_b(PREC_F64, lgn, first ? BP_LSQR_FIRST : BP_LSQR, blocks, nblocks, D,
+  TLS_CHECK(launch_toep_b(PREC_F64, lgn, first ? BP_LSQR_FIRST : BP_LSQR, groups, ngroups, D,
                           ctx->consts, ctx->tw, s));
   if (tm) TLS_CHECK(tm->end(s));
   TLS_CHECK(launch_colsum_b(0, cols, ncols, D, s));
@@ -577,18 +579,18 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       return e;
     };
 
-    // The step lists (blocks, columns, fits) of the fits still iterating.
+    // The step lists (pass block groups, columns, fits) of the fits still iterating.
     // When at least half of a list's fits have finished, the lists are
     // rebuilt without them (in this class's region of the second item
     // buffer), so that the stragglers do not pay for launches over every
     // finished fit's blocks; the graphs are captured again.
     struct Lists {
-      const Item *blocks, *cols, *fits;
-      int nblocks, ncols, nfits;
+      const Item *groups, *cols, *fits;
+      int ngroups, ncols, nfits;
       std::vector<int> desc;  // descriptor index of each fit item, in list order
     };
     auto full_lists = [&]() {
-      Lists sl{I + l.blocks.off, I + l.cols.off, I + l.fits.off, l.blocks.n, l.cols.n, l.fits.n, {}};
+      Lists sl{I + l.groups.off, I + l.cols.off, I + l.fits.off, l.groups.n, l.cols.n, l.fits.n, {}};
       for (int j = 0; j < c.count; ++j) sl.desc.push_back(c.first + j);
       return sl;
     };
@@ -606,14 +608,14 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         if (hflags[k]) continue;
         const int j = sl.desc[k];
         const Plan& pl = plans[order[j]];
-        for (int t = 0; t < pl.nblocks; ++t) b2.push_back({j, t});
+        for (int t = 0; t < pl.ngroups; ++t) b2.push_back({j, t});
         for (int t = 0; t <= pl.p; ++t) c2.push_back({j, t});
         f2.push_back({j, 0});
         keep.push_back(j);
       }
       if (keep.empty()) return TLS_OK;
       Item* base2 = items2;
-      TLS_CHECK(hipMemcpyAsync(base2 + l.blocks.off, b2.data(), b2.size() * sizeof(Item),
+      TLS_CHECK(hipMemcpyAsync(base2 + l.groups.off, b2.data(), b2.size() * sizeof(Item),
                                hipMemcpyHostToDevice, s));
       TLS_CHECK(hipMemcpyAsync(base2 + l.cols.off, c2.data(), c2.size() * sizeof(Item),
                                hipMemcpyHostToDevice, s));
@@ -621,7 +623,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
                                hipMemcpyHostToDevice, s));
       // the host vectors must outlive the copies
       TLS_CHECK(hipStreamSynchronize(s));
-      sl = Lists{base2 + l.blocks.off, base2 + l.cols.off, base2 + l.fits.off,
+      sl = Lists{base2 + l.groups.off, base2 + l.cols.off, base2 + l.fits.off,
                  static_cast<int>(b2.size()), static_cast<int>(c2.size()),
                  static_cast<int>(f2.size()), keep};
       drop_graphs();
@@ -641,7 +643,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         auto chunk = [&, launched]() -> tls_status {
           for (int it = 0; it < B_CHUNK_ITERS; ++it) {
             const tls_status e = lsqr_step_class(ctx, c.key.lgn, c.pmax, c.key.mlds != 0,
-                                                 launched == 0 && it == 0, SL_(blocks), SL_(cols),
+                                                 launched == 0 && it == 0, SL_(groups), SL_(cols),
                                                  SL_(fits), D, cnt, nullptr, t, s);
             if (e != TLS_OK) return e;
           }
@@ -668,7 +670,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         if (hipError_t he = batch_zero_ints(cnt, 2, s)) return done(hip_status(he));
         auto outer_step = [&]() -> hipError_t {
           hipError_t he = launch_small_rfft_b(PREC_F64, c.key.lgn, 2, SL_(fits), D, ctx->tw, s);
-          if (!he) he = launch_toep_b(PREC_F64, c.key.lgn, BP_OUTER64, SL_(blocks), D, ctx->consts,
+          if (!he) he = launch_toep_b(PREC_F64, c.key.lgn, BP_OUTER64, SL_(groups), D, ctx->consts,
                                       ctx->tw, s);
           if (!he) he = launch_colsum_b(1, SL_(cols), D, s);
           if (!he) he = launch_refine_outer_b(c.key.lgn, SL_(fits), c.pmax, D, cnt, ctx->tw, s);
@@ -680,7 +682,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
           auto inner = [&, it, kend]() -> tls_status {
             for (int k = it; k < kend; ++k) {
               if (tm) TLS_CHECK(tm->begin(s));
-              TLS_CHECK(launch_toep_b(PREC_F32, c.key.lgn, BP_INNER32, SL_(blocks), D, ctx->consts,
+              TLS_CHECK(launch_toep_b(PREC_F32, c.key.lgn, BP_INNER32, SL_(groups), D, ctx->consts,
                                       ctx->tw, s));
               if (tm) TLS_CHECK(tm->end(s));
               TLS_CHECK(launch_colsum_b(2, SL_(cols), D, s));

@@ -34,11 +34,15 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a) {
   return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
 }
 
-// The thread index as a value the compiler cannot see through: index and
-// address arithmetic derived from it in one phase of a kernel is then redone
-// in the next rather than kept live in registers across the phases between.
+// The index of the calling thread within its group of NT threads (NT a power
+// of two; NT = the workgroup size gives threadIdx.x), as a value the compiler
+// cannot see through: index and address arithmetic derived from it in one
+// phase of a kernel is then redone in the next rather than kept live in
+// registers across the phases between.
+template <int NT>
 __device__ __forceinline__ int opaque_tid() {
-  int t = static_cast<int>(threadIdx.x);
+  static_assert((NT & (NT - 1)) == 0, "thread groups are powers of two");
+  int t = static_cast<int>(threadIdx.x) & (NT - 1);
   asm volatile("" : "+v"(t));
   return t;
 }

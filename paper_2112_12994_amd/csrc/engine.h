@@ -47,7 +47,7 @@ struct tls_ctx {
 };
 
 struct Plan {
-  int prec, B, lgn, L, nblocks, p, q, ldq, c, crows, k, all_rows;
+  int prec, B, lgn, L, nblocks, ngroups, p, q, ldq, c, crows, k, all_rows;
   int64_t n, m;
 };
 
@@ -57,7 +57,7 @@ struct FitBufs {
   void* Yhat;       // spectra in compute precision
   void* Yhat64;     // FP64 spectra (mixed: residual passes)
   void* u;          // m-vector (also sketch scores)
-  double* partial;  // (p+1) x nblocks
+  double* partial;  // (p+1) x ngroups (Toeplitz pass partials per block group)
   double* g;        // p+1
   double* A;        // crows x ldq
   double* G;        // ldq^2 + 2 q^2
@@ -106,21 +106,27 @@ int ilog2(int64_t x) {
   return l;
 }
 
+// Twiddle table: for L = 2, 4, ..., BMAX the factors exp(-2 pi i e / L),
+// e < L/2, at indices L/2 - 1 + e (BMAX - 1 entries; the last word unused).
 hipError_t build_twiddles(tls_ctx* c) {
-  std::vector<cx<double>> t64(NMAX);
-  std::vector<cx<float>> t32(NMAX);
-  for (int k = 0; k < NMAX; ++k) {
-    const long double a = -2.0L * 3.141592653589793238462643383279502884L * k / BMAX;
-    t64[k] = {static_cast<double>(cosl(a)), static_cast<double>(sinl(a))};
-    t32[k] = {static_cast<float>(cosl(a)), static_cast<float>(sinl(a))};
+  std::vector<cx<double>> t64(BMAX, cx<double>{0.0, 0.0});
+  std::vector<cx<float>> t32(BMAX, cx<float>{0.f, 0.f});
+  for (int lg = 1; lg <= LG_BMAX; ++lg) {
+    const int half = 1 << (lg - 1);
+    for (int e = 0; e < half; ++e) {
+      const long double k = static_cast<long double>(e) * (BMAX >> lg);
+      const long double a = -2.0L * 3.141592653589793238462643383279502884L * k / BMAX;
+      t64[half - 1 + e] = {static_cast<double>(cosl(a)), static_cast<double>(sinl(a))};
+      t32[half - 1 + e] = {static_cast<float>(cosl(a)), static_cast<float>(sinl(a))};
+    }
   }
-  hipError_t e = hipMalloc(&c->tw64, NMAX * sizeof(cx<double>));
+  hipError_t e = hipMalloc(&c->tw64, BMAX * sizeof(cx<double>));
   if (e != hipSuccess) return e;
-  e = hipMalloc(&c->tw32, NMAX * sizeof(cx<float>));
+  e = hipMalloc(&c->tw32, BMAX * sizeof(cx<float>));
   if (e != hipSuccess) return e;
-  e = hipMemcpy(c->tw64, t64.data(), NMAX * sizeof(cx<double>), hipMemcpyHostToDevice);
+  e = hipMemcpy(c->tw64, t64.data(), BMAX * sizeof(cx<double>), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
-  e = hipMemcpy(c->tw32, t32.data(), NMAX * sizeof(cx<float>), hipMemcpyHostToDevice);
+  e = hipMemcpy(c->tw32, t32.data(), BMAX * sizeof(cx<float>), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   c->tw.d64 = c->tw64;
   c->tw.d32 = c->tw32;
@@ -258,6 +264,7 @@ tls_status make_plan(int64_t n, int p, const tls_options& o, Plan* pl,
   pl->lgn = lg - 1;
   pl->L = pl->B - p + 1;
   pl->nblocks = static_cast<int>((pl->m + pl->L - 1) / pl->L);
+  pl->ngroups = pass_groups(pl->lgn, pl->nblocks);
   pl->q = p + 1;
   pl->ldq = (pl->q + 15) / 16 * 16;
   const int64_t c = static_cast<int64_t>(o.gamma > 0 ? o.gamma : 8) * p;
@@ -293,7 +300,7 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->Yhat64 = pl.prec == TLS_PREC_MIXED ? a.take<char>(static_cast<size_t>(pl.nblocks) * N * 16)
                                         : b->Yhat;
   b->u = a.take<char>(static_cast<size_t>(pl.m) * (pl.prec == TLS_PREC_F64 ? 8 : 8));
-  b->partial = a.take<double>(static_cast<size_t>(pl.p + 1) * pl.nblocks);
+  b->partial = a.take<double>(static_cast<size_t>(pl.p + 1) * pl.ngroups);
   b->g = a.take<double>(pl.p + 1);
   b->A = a.take<double>(static_cast<size_t>(pl.crows) * pl.ldq);
   b->G = a.take<double>(qr_scratch_doubles(pl.crows, pl.q, pl.ldq));
@@ -422,7 +429,7 @@ constexpr int BATCH_LDQ_MAX = 1024;
 
 // Work-item lists of one class (offsets into one device item table).
 struct ClassLists {
-  List blocks, blocks1, rows1, rows2, tiles1, tiles2, rowtiles2, trmm2, fits, fits1, jl, chunks,
+  List blocks, groups, blocks1, rows1, rows2, tiles1, tiles2, rowtiles2, trmm2, fits, fits1, jl, chunks,
       draws, cols, rblocks;
 };
 // Appends the lists of the fits with descriptor indices desc[i] and plans
@@ -460,7 +467,7 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
 // One FP64 LSQR step for the listed fits: the fused pass (first: from b and
 // phi0, after the spectrum of phi0), the column sums and the p-side step.
 tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
-                           const Item* blocks, int nblocks, const Item* cols, int ncols,
+                           const Item* groups, int ngroups, const Item* cols, int ncols,
                            const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
                            PassTimer* tm, hipStream_t s);
 // FP64 residual of phi (row-wise) for the listed fits.

@@ -95,7 +95,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
         TLS_CHECK(hipEventRecord(eb, s));
         ++npass;
       }
-      TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, flag, s));
+      TLS_CHECK(launch_colsum(b.partial, pl.ngroups, p + 1, b.g, flag, s));
       TLS_CHECK(launch_lsqr_step(PREC_F64, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
                                  b.phi, b.Vhat, ctx->tw, s));
       return TLS_OK;
@@ -182,7 +182,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       TLS_CHECK(launch_small_rfft(PREC_F64, pl.lgn, b.phi, p, p, 1, invB, b.Vhat, ctx->tw, nullptr, s));
       TLS_CHECK(launch_toep(PREC_F64, pl.lgn, MODE_FUSED, b.Yhat64, b.Vhat, d_y + p, nullptr, nullptr,
                             b.partial, ctx->consts, &b.rst->done, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
-      TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, &b.rst->done, s));
+      TLS_CHECK(launch_colsum(b.partial, pl.ngroups, p + 1, b.g, &b.rst->done, s));
       TLS_CHECK(launch_refine_outer(pl.lgn, p, b.rst, b.g, b.M, b.Mt, b.phi, b.phib, b.cw, b.cres,
                                     b.cd, b.Vhat32, ctx->tw, s));
       for (int it = 0; it < inner_max; it += INNER_CHUNK) {
@@ -198,7 +198,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
             TLS_CHECK(hipEventRecord(eb, s));
             ++npass;
           }
-          TLS_CHECK(launch_colsum(b.partial, pl.nblocks, p + 1, b.g, &b.rst->inner_done, s));
+          TLS_CHECK(launch_colsum(b.partial, pl.ngroups, p + 1, b.g, &b.rst->inner_done, s));
           TLS_CHECK(launch_refine_cg(pl.lgn, p, b.rst, b.g, b.M, b.Mt, b.cw, b.cres, b.cd, b.phi,
                                      b.Vhat32, ctx->tw, s));
         }
@@ -549,14 +549,15 @@ tls_status tls_op_toeplitz(tls_ctx* ctx, int32_t prec, const void* d_spec, int64
   a.take<double>(p);
   a.take<double>(2);
   a.take<char>(static_cast<size_t>(B / 2) * 16);
-  a.take<double>(static_cast<size_t>(p + 1) * nb);
+  const int ng = pass_groups(lgn, nb);
+  a.take<double>(static_cast<size_t>(p + 1) * ng);
   TLS_CHECK(ensure_ws(ctx, a.need + 256));
   a.need = 0;
   a.base = static_cast<char*>(ctx->ws);
   double* dv = a.take<double>(p);
   double* dcoef = a.take<double>(2);
   void* Vh = a.take<char>(static_cast<size_t>(B / 2) * 16);
-  double* part = a.take<double>(static_cast<size_t>(p + 1) * nb);
+  double* part = a.take<double>(static_cast<size_t>(p + 1) * ng);
   int mode = MODE_RMV;
   if (v) {
     const double cf[2] = {s1, s2};
@@ -568,9 +569,9 @@ tls_status tls_op_toeplitz(tls_ctx* ctx, int32_t prec, const void* d_spec, int64
   TLS_CHECK(launch_toep(pr, lgn, mode, d_spec, Vh, d_w, d_e, d_u_in, part, dcoef, nullptr, ctx->tw,
                         n - p, p, B - p + 1, nb, s));
   if (mode & PM_RMV) {
-    TLS_CHECK(launch_colsum(part, nb, p + 1, d_out, nullptr, s));
+    TLS_CHECK(launch_colsum(part, ng, p + 1, d_out, nullptr, s));
   } else {
-    TLS_CHECK(launch_colsum(part + static_cast<size_t>(p) * nb, nb, 1, d_out + p, nullptr, s));
+    TLS_CHECK(launch_colsum(part + static_cast<size_t>(p) * ng, ng, 1, d_out + p, nullptr, s));
   }
   // the host copies above read pageable memory; finish before returning
   TLS_CHECK(hipStreamSynchronize(s));

@@ -11,8 +11,11 @@
 // unscaled.  Real <-> half-length complex conversion works on bin pairs
 // (k, N-k) (rfft_post / irfft_pre), which every caller does in registers.
 //
-// Twiddles come from one table tab[k] = exp(-2 pi i k / BMAX), k < BMAX/2,
-// built once on the host in extended precision; w_L^e = tab[e * BMAX / L].
+// Twiddles come from one table built once on the host in extended
+// precision that holds, for every power of two L <= BMAX, the L/2 factors
+// w_L^e = exp(-2 pi i e / L), e < L/2, contiguously from index L/2 - 1: the
+// threads of a stage, which need consecutive exponents of one L, then read
+// consecutive words.
 #pragma once
 
 #include "common.h"
@@ -29,9 +32,24 @@ __device__ __forceinline__ int swz(int i) {
   return i ^ ((i >> LG) & ((1 << LG) - 1));
 }
 
+// Barrier of a group of NT threads that exchange data through LDS.  A
+// group of one wavefront needs none: its LDS operations are performed in
+// issue order, so the fences only keep the compiler from moving LDS
+// accesses across this point.
+template <int NT>
+__device__ __forceinline__ void group_sync() {
+  if constexpr (NT == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <typename T, bool INV>
 __device__ __forceinline__ cx<T> twiddle(const cx<T>* __restrict__ tab, int e, int lgL) {
-  cx<T> w = tab[e << (LG_BMAX - lgL)];
+  cx<T> w = tab[((1 << lgL) >> 1) - 1 + e];
   if (INV) w.y = -w.y;
   return w;
 }
@@ -202,7 +220,7 @@ template <typename T, bool DIT, bool INV, int N, int NT, int R, int LGH>
 __device__ __forceinline__ void stage(cx<T>* s, const cx<T>* __restrict__ tab) {
   constexpr int h = 1 << LGH;
   constexpr int LGR = R == 8 ? 3 : (R == 4 ? 2 : 1);
-  for (int q = opaque_tid(); q < N / R; q += NT) {
+  for (int q = opaque_tid<NT>(); q < N / R; q += NT) {
     const int r = q & (h - 1);
     const int base = ((q >> LGH) << (LGH + LGR)) + r;
     cx<T> a[R];
@@ -230,15 +248,15 @@ __device__ __forceinline__ void dit_from(cx<T>* s, const cx<T>* __restrict__ tab
   if constexpr (LGH + 3 <= LGN) {
     if constexpr (!(SKIP_LAST && LGH + 3 == LGN)) {
       stage<T, true, INV, N, NT, 8, LGH>(s, tab);
-      __syncthreads();
+      group_sync<NT>();
     }
     dit_from<T, INV, LGN, NT, LGH + 3, SKIP_LAST>(s, tab);
   } else if constexpr (LGN - LGH == 2 && !SKIP_LAST) {
     stage<T, true, INV, N, NT, 4, LGH>(s, tab);
-    __syncthreads();
+    group_sync<NT>();
   } else if constexpr (LGN - LGH == 1 && !SKIP_LAST) {
     stage<T, true, INV, N, NT, 2, LGH>(s, tab);
-    __syncthreads();
+    group_sync<NT>();
   }
 }
 
@@ -247,7 +265,7 @@ __device__ __forceinline__ void dif_down(cx<T>* s, const cx<T>* __restrict__ tab
   constexpr int N = 1 << LGN;
   if constexpr (LGH >= 0) {
     stage<T, false, INV, N, NT, 8, LGH>(s, tab);
-    __syncthreads();
+    group_sync<NT>();
     dif_down<T, INV, LGN, NT, LGH - 3>(s, tab);
   }
 }
@@ -266,7 +284,7 @@ __device__ __forceinline__ void fft_dif(cx<T>* s, const cx<T>* __restrict__ tab)
   using P = Plan8<LGN>;
   if constexpr (P::RLAST != 8) {
     stage<T, false, INV, N, NT, P::RLAST, P::LGLAST>(s, tab);
-    __syncthreads();
+    group_sync<NT>();
   }
   dif_down<T, INV, LGN, NT, P::RLAST == 8 ? P::LGLAST : P::LGLAST - 3>(s, tab);
 }
@@ -295,7 +313,7 @@ template <typename T, bool INV, int LGN, int NT>
 __device__ __forceinline__ void fft_dit_out(cx<T>* s, const cx<T>* __restrict__ tab,
                                             cx<T> (&v)[(1 << LGN) / NT]) {
   using O = Outer<LGN, NT>;
-  const int tid = opaque_tid();
+  const int tid = opaque_tid<NT>();
   if constexpr (O::REGS) {
     dit_from<T, INV, LGN, NT, 0, true>(s, tab);
 #pragma unroll
@@ -321,7 +339,7 @@ template <typename T, bool INV, int LGN, int NT>
 __device__ __forceinline__ void fft_dif_in(cx<T>* s, const cx<T>* __restrict__ tab,
                                            const cx<T> (&v)[(1 << LGN) / NT]) {
   using O = Outer<LGN, NT>;
-  const int tid = opaque_tid();
+  const int tid = opaque_tid<NT>();
   if constexpr (O::REGS) {
 #pragma unroll
     for (int c = 0; c < O::C; ++c) {
@@ -334,12 +352,12 @@ __device__ __forceinline__ void fft_dif_in(cx<T>* s, const cx<T>* __restrict__ t
 #pragma unroll
       for (int k = 0; k < O::R; ++k) s[swz<T>(q + k * O::H)] = a[k];
     }
-    __syncthreads();
+    group_sync<NT>();
     dif_down<T, INV, LGN, NT, O::LGH - 3>(s, tab);
   } else {
 #pragma unroll
     for (int e = 0; e < (1 << LGN) / NT; ++e) s[swz<T>(tid + e * NT)] = v[e];
-    __syncthreads();
+    group_sync<NT>();
     fft_dif<T, INV, LGN, NT>(s, tab);
   }
 }

@@ -19,8 +19,8 @@ constexpr int MODE_MV = PM_MV;              // e = s1 Xv + s2 w, ||e||^2
 constexpr int MODE_RMV = PM_RMV;            // X^T u, ||u||^2
 
 struct Twiddles {
-  const void* d64 = nullptr;  // cx<double>[NMAX]
-  const void* d32 = nullptr;  // cx<float>[NMAX]
+  const void* d64 = nullptr;  // cx<double>[BMAX], see build_twiddles
+  const void* d32 = nullptr;  // cx<float>[BMAX]
 };
 
 // threads per workgroup used for a transform of complex length 2^lgn
@@ -29,8 +29,18 @@ inline int fft_threads(int lgn) {
   return n8 < 64 ? 64 : (n8 > 256 ? 256 : n8);
 }
 
+// Blocks per workgroup of the Toeplitz pass: that many blocks are
+// transformed side by side (each by fft_threads(lgn) threads) and their X^T
+// products share one inverse transform; the pass writes its partials per
+// group of pass_nw(lgn) consecutive blocks.
+constexpr int pass_nw(int lgn) { return lgn <= 9 ? 4 : (lgn <= 11 ? 2 : 1); }
+inline int pass_groups(int lgn, int nblocks) {
+  return (nblocks + pass_nw(lgn) - 1) / pass_nw(lgn);
+}
+
 hipError_t launch_spectra(int prec, int lgn, const double* y, int64_t n, int L, int nblocks,
                           void* Yhat, const Twiddles& tw, hipStream_t st);
+// partial: (p + 1) x pass_groups(lgn, nblocks) doubles, column-major.
 hipError_t launch_toep(int prec, int lgn, int mode, const void* Yhat, const void* Vhat,
                        const void* w_in, void* u_out, const void* u_in, double* partial,
                        const double* coef, const int* flag, const Twiddles& tw, int64_t m, int p,
@@ -127,7 +137,7 @@ struct FitDesc {
   const double* y;
   int64_t n, m;
   double tol;
-  int p, q, ldq, c, crows, k, L, nblocks, nchunks, all_rows;
+  int p, q, ldq, c, crows, k, L, nblocks, ngroups, nchunks, all_rows;
   uint32_t fit;
   void* Yhat;
   void* Yhat64;

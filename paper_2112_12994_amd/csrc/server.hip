@@ -263,7 +263,7 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
   struct Iter {
     int lgn, pmax;
     bool mlds;
-    List blocks, cols, fits;
+    List groups, cols, fits;  // pass block groups, columns of the partials, fits
   };
   std::vector<Iter> iters;
   {
@@ -271,10 +271,10 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
     for (Request* r : active) g[{r->pl.lgn, lsqr_step_lds(r->pl.lgn, r->pl.p) ? 1 : 0}].push_back(r);
     for (auto& kv : g) {
       Iter it{kv.first.first, 0, kv.first.second != 0, {}, {}, {}};
-      it.blocks.off = static_cast<int>(items.size());
+      it.groups.off = static_cast<int>(items.size());
       for (Request* r : kv.second)
-        for (int j = 0; j < r->pl.nblocks; ++j) items.push_back({r->slot, j});
-      it.blocks.n = static_cast<int>(items.size()) - it.blocks.off;
+        for (int j = 0; j < r->pl.ngroups; ++j) items.push_back({r->slot, j});
+      it.groups.n = static_cast<int>(items.size()) - it.groups.off;
       it.cols.off = static_cast<int>(items.size());
       for (Request* r : kv.second)
         for (int j = 0; j <= r->pl.p; ++j) items.push_back({r->slot, j});
@@ -332,8 +332,8 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
       continue;
     }
     for (int k = 0; k < steps; ++k)
-      if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, I + l.blocks.off,
-                          l.blocks.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,
+      if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, I + l.groups.off,
+                          l.groups.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,
                           S->dCounts, S->dDone, nullptr, s) != TLS_OK)
         return hipErrorUnknown;
   }
@@ -341,7 +341,7 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
   // the way skip the remaining steps)
   for (int k = 0; k < steps; ++k)
     for (const Iter& it : iters) {
-      if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, I + it.blocks.off, it.blocks.n,
+      if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, I + it.groups.off, it.groups.n,
                           I + it.cols.off, it.cols.n, I + it.fits.off, it.fits.n, S->dD,
                           S->dCounts, S->dDone, nullptr, s) != TLS_OK)
         return hipErrorUnknown;

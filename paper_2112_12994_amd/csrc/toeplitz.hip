@@ -28,11 +28,13 @@ hipError_t toep_one(const void* Yhat, const void* Vhat, const void* w_in, void* 
                     const void* u_in, double* partial, const double* coef, const int* flag,
                     const Twiddles& tw, int64_t m, int p, int L, int nblocks, hipStream_t st) {
   constexpr int NT = nt_for(LGN);
-  hipLaunchKernelGGL((toep_pass_kernel<T, LGN, NT, MODE>), dim3(nblocks), dim3(NT), 0, st,
+  constexpr int NW = pass_nw(LGN);
+  const int ngroups = pass_groups(LGN, nblocks);
+  hipLaunchKernelGGL((toep_pass_kernel<T, LGN, NT, NW, MODE>), dim3(ngroups), dim3(NT * NW), 0, st,
                      static_cast<const cx<T>*>(Yhat), static_cast<const cx<T>*>(Vhat),
                      static_cast<const T*>(w_in), static_cast<T*>(u_out),
                      static_cast<const T*>(u_in), partial, coef, flag, tab_of<T>(tw), m, p, L,
-                     nblocks);
+                     nblocks, ngroups);
   return hipGetLastError();
 }
 
@@ -316,33 +318,34 @@ __device__ __forceinline__ P opaque_ptr(P x) {
 }
 
 template <typename T, int LGN, int NT, int VARIANT>
-__global__ __launch_bounds__(NT) void toep_b_kernel(const Item* __restrict__ items,
+__global__ __launch_bounds__(NT * pass_nw(LGN)) void toep_b_kernel(const Item* __restrict__ items,
                                                     const FitDesc* __restrict__ D,
                                                     const double* __restrict__ consts,
                                                     const cx<T>* __restrict__ tab) {
+  constexpr int NW = pass_nw(LGN);
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
   if constexpr (VARIANT == BP_LSQR_FIRST || VARIANT == BP_LSQR) {
     const T* w = VARIANT == BP_LSQR_FIRST ? reinterpret_cast<const T*>(d.y + d.p)
                                           : static_cast<const T*>(d.u);
-    toep_pass_body<T, LGN, NT, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat64),
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat64),
                                            static_cast<const cx<T>*>(d.Vhat), opaque_ptr(w),
                                            opaque_ptr(static_cast<T*>(d.u)),
                                            opaque_ptr(static_cast<const T*>(nullptr)), d.partial,
                                            d.st->coef, &d.st->done, tab, d.m, d.p, d.L,
-                                           d.nblocks, it.idx);
+                                           d.nblocks, d.ngroups, it.idx);
   } else if constexpr (VARIANT == BP_OUTER64) {
-    toep_pass_body<T, LGN, NT, MODE_FUSED>(
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(
         static_cast<const cx<T>*>(d.Yhat64), static_cast<const cx<T>*>(d.Vhat),
         opaque_ptr(reinterpret_cast<const T*>(d.y + d.p)), opaque_ptr(static_cast<T*>(nullptr)),
         opaque_ptr(static_cast<const T*>(nullptr)), d.partial, consts, &d.rst->done, tab, d.m,
-        d.p, d.L, d.nblocks, it.idx);
+        d.p, d.L, d.nblocks, d.ngroups, it.idx);
   } else {
-    toep_pass_body<T, LGN, NT, MODE_FUSED>(
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(
         static_cast<const cx<T>*>(d.Yhat), static_cast<const cx<T>*>(d.Vhat32),
         opaque_ptr(static_cast<const T*>(nullptr)), opaque_ptr(static_cast<T*>(nullptr)),
         opaque_ptr(static_cast<const T*>(nullptr)), d.partial, consts + 2, &d.rst->inner_done,
-        tab, d.m, d.p, d.L, d.nblocks, it.idx);
+        tab, d.m, d.p, d.L, d.nblocks, d.ngroups, it.idx);
   }
 }
 
@@ -383,7 +386,7 @@ __global__ __launch_bounds__(NT) void colsum_b_kernel(const Item* __restrict__ i
     return;
   }
   const int* flag = variant == 0 ? &d.st->done : (variant == 1 ? &d.rst->done : &d.rst->inner_done);
-  colsum_body<NT>(d.partial, d.nblocks, d.g, flag, it.idx);
+  colsum_body<NT>(d.partial, d.ngroups, d.g, flag, it.idx);
 }
 
 template <int NT>
@@ -400,19 +403,19 @@ hipError_t toep_b_sel(int prec, int variant, const Item* items, int nitems, cons
   constexpr int NT = nt_for(LGN);
   switch (variant) {
     case BP_LSQR_FIRST:
-      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_LSQR_FIRST>), dim3(nitems), dim3(NT), 0,
+      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_LSQR_FIRST>), dim3(nitems), dim3(NT * pass_nw(LGN)), 0,
                          st, items, D, consts, tab_of<double>(tw));
       break;
     case BP_LSQR:
-      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_LSQR>), dim3(nitems), dim3(NT), 0, st,
-                         items, D, consts, tab_of<double>(tw));
+      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_LSQR>), dim3(nitems), dim3(NT * pass_nw(LGN)), 0,
+                         st, items, D, consts, tab_of<double>(tw));
       break;
     case BP_OUTER64:
-      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_OUTER64>), dim3(nitems), dim3(NT), 0,
+      hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_OUTER64>), dim3(nitems), dim3(NT * pass_nw(LGN)), 0,
                          st, items, D, consts, tab_of<double>(tw));
       break;
     case BP_INNER32:
-      hipLaunchKernelGGL((toep_b_kernel<float, LGN, NT, BP_INNER32>), dim3(nitems), dim3(NT), 0,
+      hipLaunchKernelGGL((toep_b_kernel<float, LGN, NT, BP_INNER32>), dim3(nitems), dim3(NT * pass_nw(LGN)), 0,
                          st, items, D, consts, tab_of<float>(tw));
       break;
     default:

@@ -42,7 +42,7 @@ struct PairLoads {
   static constexpr bool FULL = NP * NT == N / 2;  // every (thread, ip) has a bin
   cx<T> a[NP], b[NP], w[NP], yh, wh;
   __device__ __forceinline__ void load(const cx<T>* __restrict__ P, const cx<T>* __restrict__ tab) {
-    const int tid = opaque_tid();
+    const int tid = opaque_tid<NT>();
 #pragma unroll
     for (int ip = 0; ip < NP; ++ip) {
       int k = tid + ip * NT;
@@ -156,22 +156,35 @@ __global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict
 // One pass over all blocks.  With v's packed spectrum pre-scaled by 1/B:
 //   e = s1 * (X v) + s2 * w          (PM_MV; the w term when w_in != NULL)
 //   u_out = e                        (when u_out != NULL; may alias w_in)
-//   partial[j*nb + blk] = block share of (X^T e)[j], j < p     (PM_RMV)
-//   partial[p*nb + blk] = block share of ||e||^2
+//   partial[j*ngroups + g] = share of (X^T e)[j] of block group g, j < p  (PM_RMV)
+//   partial[p*ngroups + g] = share of ||e||^2 of block group g
 // Without PM_MV the pass vector is u_in.  (s1, s2) = coef[0..1].
-template <typename T, int LGN, int NT, int MODE>
+//
+// A workgroup holds NW groups of NT threads; group `sub` transforms block
+// g NW + sub in its own LDS region (blocks past the end contribute zero).
+// X^T e needs only the first p outputs of the inverse transform of the sum
+// over blocks of conj(Y_b) E_b (the transform is linear and the same for
+// every block), so the NW product spectra are added in LDS in a fixed order
+// and one inverse transform per workgroup replaces one per block.
+template <typename T, int LGN, int NT, int NW, int MODE>
 __device__ __forceinline__ void toep_pass_body(
     const cx<T>* __restrict__ Yhat, const cx<T>* __restrict__ Vhat, const T* w_in, T* u_out,
     const T* __restrict__ u_in, double* __restrict__ partial, const double* __restrict__ coef,
     const int* __restrict__ flag, const cx<T>* __restrict__ tab, int64_t m, int p, int L,
-    int nblocks, int blk) {
+    int nblocks, int ngroups, int grp) {
   constexpr int N = 1 << LGN;
   constexpr int NEL = N / NT;
-  static_assert(N % NT == 0, "block transform must cover the workgroup");
-  __shared__ cx<T> s[N];
-  __shared__ double red[NT / 64];
+  constexpr int NTW = NT * NW;
+  static_assert(N % NT == 0, "block transform must cover the thread group");
+  __shared__ cx<T> s_all[NW * N];
+  __shared__ double red[NTW / 64];
   if (flag && *flag) return;
-  const int tid = threadIdx.x;
+  const int tid = static_cast<int>(threadIdx.x) & (NT - 1);
+  const int sub = NW == 1 ? 0 : static_cast<int>(threadIdx.x) / NT;
+  const int braw = grp * NW + sub;
+  const bool valid = braw < nblocks;
+  const int blk = valid ? braw : nblocks - 1;  // in-bounds loads; no rows below
+  cx<T>* const s = s_all + sub * N;
   const cx<T>* Y = Yhat + static_cast<size_t>(blk) * N;
   const int64_t row0 = static_cast<int64_t>(blk) * L - (p - 1);  // row at tau = 0
 
@@ -202,12 +215,13 @@ __device__ __forceinline__ void toep_pass_body(
       irfft_pre(x, x, ly.wh, Zk, Znk);
       s[swz<T>(bitrev(N / 2, LGN))] = Zk;
     }
-    __syncthreads();
+    group_sync<NT>();
   }
   // the rows of this block sit at window positions [p - 1, hi); they are
   // addressed by 32-bit offsets from the row at position 0 (the 64-bit base
-  // is uniform; positions below p - 1 are never accessed)
-  const int hi = static_cast<int>(m - row0 < 2 * N ? m - row0 : 2 * N);
+  // is uniform; positions below p - 1 are never accessed).  A block past the
+  // end has no rows (hi = 0): e = 0 there.
+  const int hi = valid ? static_cast<int>(m - row0 < 2 * N ? m - row0 : 2 * N) : 0;
   T* const ub = u_out ? u_out + row0 : nullptr;
   // e at the rows of this block (zero outside them) from the inverse
   // transform value z = ((X v)[2t], (X v)[2t+1]) at packed position t
@@ -271,9 +285,9 @@ __device__ __forceinline__ void toep_pass_body(
     fft_dif_in<T, false, LGN, NT>(s, tab, v);
   }
   if constexpr ((MODE & PM_RMV) != 0) {
-    // block share of X^T e: correlation of the window with e, via
-    // conj(E) * Y per bin pair, then the inverse transform's first p outputs
-    // (Y reloaded, a cache hit, rather than kept live across the transforms)
+    // this block's share of X^T e: correlation of the window with e, i.e.
+    // conj(E) * Y per bin pair (Y reloaded, a cache hit, rather than kept
+    // live across the transforms), left in the inverse transform's input form
     PairLoads<T, LGN, NT> ly;
     ly.load(Y, tab);
 #pragma unroll
@@ -301,27 +315,40 @@ __device__ __forceinline__ void toep_pass_body(
       irfft_pre(cmulconj(ly.yh, Xk), cmulconj(ly.yh, Xnk), ly.wh, Zk, Znk);
       s[swz<T>(bh)] = Zk;
     }
-    __syncthreads();
-    fft_dit<T, true, LGN, NT>(s, tab);
+    if constexpr (NW == 1) group_sync<NT>();
+    if constexpr (NW > 1) {
+      __syncthreads();
+      // the group's product spectra summed into region 0, blocks in order
+      // (every region is addressed through the same swizzle)
+      for (int i = static_cast<int>(threadIdx.x); i < N; i += NTW) {
+        cx<T> acc = s_all[i];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) acc = cadd(acc, s_all[w * N + i]);
+        s_all[i] = acc;
+      }
+      __syncthreads();
+    }
+    fft_dit<T, true, LGN, NTW>(s_all, tab);
     const double invB = 1.0 / static_cast<double>(2 * N);
-    for (int t = tid; 2 * t < p; t += NT) {
-      const cx<T> z = s[swz<T>(t)];
-      partial[static_cast<size_t>(2 * t) * nblocks + blk] = static_cast<double>(z.x) * invB;
+    for (int t = static_cast<int>(threadIdx.x); 2 * t < p; t += NTW) {
+      const cx<T> z = s_all[swz<T>(t)];
+      partial[static_cast<size_t>(2 * t) * ngroups + grp] = static_cast<double>(z.x) * invB;
       if (2 * t + 1 < p)
-        partial[static_cast<size_t>(2 * t + 1) * nblocks + blk] = static_cast<double>(z.y) * invB;
+        partial[static_cast<size_t>(2 * t + 1) * ngroups + grp] = static_cast<double>(z.y) * invB;
     }
   }
-  const double tot = block_sum<NT>(nrm, red);
-  if (tid == 0) partial[static_cast<size_t>(p) * nblocks + blk] = tot;
+  const double tot = block_sum<NTW>(nrm, red);
+  if (threadIdx.x == 0) partial[static_cast<size_t>(p) * ngroups + grp] = tot;
 }
 
-template <typename T, int LGN, int NT, int MODE>
-__global__ __launch_bounds__(NT) void toep_pass_kernel(
+template <typename T, int LGN, int NT, int NW, int MODE>
+__global__ __launch_bounds__(NT * NW) void toep_pass_kernel(
     const cx<T>* __restrict__ Yhat, const cx<T>* __restrict__ Vhat, const T* w_in, T* u_out,
     const T* __restrict__ u_in, double* __restrict__ partial, const double* __restrict__ coef,
     const int* __restrict__ flag, const cx<T>* __restrict__ tab, int64_t m, int p, int L,
-    int nblocks) {
-  toep_pass_body<T, LGN, NT, MODE>(Yhat, Vhat, w_in, u_out, u_in, partial, coef, flag, tab, m, p, L, nblocks, blockIdx.x);
+    int nblocks, int ngroups) {
+  toep_pass_body<T, LGN, NT, NW, MODE>(Yhat, Vhat, w_in, u_out, u_in, partial, coef, flag, tab, m,
+                                       p, L, nblocks, ngroups, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

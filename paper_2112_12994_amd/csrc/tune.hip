@@ -65,7 +65,7 @@ tls_status time_pass(tls_ctx* ctx, int prec, int64_t m, int p, int lg, hipEvent_
     else
       TLS_CHECK(launch_toep(prec, lgn, MODE_FUSED, t.spec, t.Vhat, nullptr, nullptr, nullptr,
                             t.partial, ctx->consts + 2, nullptr, ctx->tw, m, p, L, nb, s));
-    TLS_CHECK(launch_colsum(t.partial, nb, p + 1, t.g, nullptr, s));
+    TLS_CHECK(launch_colsum(t.partial, pass_groups(lgn, nb), p + 1, t.g, nullptr, s));
     TLS_CHECK(hipEventRecord(e1, s));
     TLS_CHECK(hipEventSynchronize(e1));
     float x = 0.f;

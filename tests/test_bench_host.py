@@ -13,11 +13,11 @@ import bench
 
 
 def test_fused_pass_bytes_ar100():
-    # n = 2^22, p = 100, B = 1024 (512 complex bins), 4535 blocks, FP64:
-    # spectra 4535*512*16, u read + written 2*(2^22-100)*8, v's spectrum
-    # 512*16, partial sums 101*4535*8
-    expect = 4535 * 512 * 16 + 2 * (4194304 - 100) * 8 + 512 * 16 + 101 * 4535 * 8
-    assert expect == 107930456
+    # n = 2^22, p = 100, B = 1024 (512 complex bins), 4535 blocks taken 4
+    # at a time (1134 groups), FP64: spectra 4535*512*16, u read + written
+    # 2*(2^22-100)*8, v's spectrum 512*16, partial sums 101*1134*8
+    expect = 4535 * 512 * 16 + 2 * (4194304 - 100) * 8 + 512 * 16 + 101 * 1134 * 8
+    assert expect == 105182448
     assert bench.fused_pass_bytes(1 << 22, 100, 1024, 4535, 8) == expect
 
 
