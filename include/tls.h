@@ -336,6 +336,26 @@ tls_status tls_op_toeplitz(tls_ctx* ctx, int32_t prec, const void* d_spec, int64
                            void* d_e, const void* d_u_in, int32_t want_rmv, double* d_out,
                            void* stream);
 
+/* tls_op_toeplitz without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results, bit for bit, as
+ * tls_op_toeplitz; its scratch lives in a fixed 16 MiB device array per
+ * device, held until the process ends, instead of the context workspace.
+ * The scratch is v, (s1, s2), v's spectrum (B/2 complex doubles) and the
+ * partial sums, (p + 1) x ceil(nblocks / g) doubles with g = 4 for
+ * B <= 1024, 2 for B <= 4096, else 1 (each slice rounded up to 256 bytes);
+ * sizes needing more than 16 MiB return TLS_EUNSUPPORTED before any work is
+ * queued (for p = 100, B = 1024: up to about 80 million series samples).
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (any contexts, streams or threads) race, so the caller must
+ * order them.  The array is not cleared between calls (every byte it uses is
+ * written before it is read).  The host copy of v is from pageable memory,
+ * so the call synchronises `stream` before returning. */
+tls_status tls_op_toeplitz_noalloc(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n,
+                                   int32_t p, int32_t B, const double* v, double s1, double s2,
+                                   const void* d_w, void* d_e, const void* d_u_in,
+                                   int32_t want_rmv, double* d_out, void* stream);
+
 /* Approximate generalised leverage scores in product form (eq. (glev)):
  * d_scores[i] = sum_q ((X omega_q)[i])^2 for the p x k matrix d_omega
  * (device FP64, column-major, columns contiguous).  d_scores: n-p values,

@@ -172,6 +172,8 @@ _SIGS = {
     "tls_op_spectra": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _vp, _vp]),
     "tls_op_toeplitz": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _dp, _c.c_double, _c.c_double,
                                _vp, _vp, _vp, _i32, _vp, _vp]),
+    "tls_op_toeplitz_noalloc": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _dp, _c.c_double,
+                                       _c.c_double, _vp, _vp, _vp, _i32, _vp, _vp]),
     "tls_op_scores": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _i32, _vp, _i32, _vp, _vp]),
     "tls_op_sample": (_i32, [_ctxp, _i32, _vp, _i64, _vp, _i32, _u64, _u32, _vp, _vp, _vp]),
     "tls_op_rh_mask": (_i32, [_ctxp, _i32, _vp, _i64, _i32, _u64, _u32, _vp]),
@@ -369,6 +371,14 @@ class Context:
         return lib.tls_op_toeplitz(self._h, prec, _ptr(d_spec), n, p, B,
                                    None if vv is None else _dptr(vv), s1, s2, _ptr(d_w), _ptr(d_e),
                                    _ptr(d_u_in), 1 if want_rmv else 0, _ptr(d_out), _stream(stream))
+
+    def op_toeplitz_noalloc(self, prec, d_spec, n, p, B, v=None, s1=1.0, s2=0.0, d_w=None,
+                            d_e=None, d_u_in=None, want_rmv=True, d_out=None, stream=None):
+        vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
+        return lib.tls_op_toeplitz_noalloc(self._h, prec, _ptr(d_spec), n, p, B,
+                                           None if vv is None else _dptr(vv), s1, s2, _ptr(d_w),
+                                           _ptr(d_e), _ptr(d_u_in), 1 if want_rmv else 0,
+                                           _ptr(d_out), _stream(stream))
 
     def op_scores(self, prec, d_spec, n, p, B, d_omega, k, d_scores, stream=None):
         return lib.tls_op_scores(self._h, prec, _ptr(d_spec), n, p, B, _ptr(d_omega), k,

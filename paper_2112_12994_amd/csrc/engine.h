@@ -32,6 +32,7 @@ struct tls_ctx {
   double* consts = nullptr;  // {-1, 1, 1, 0}
   void* ws = nullptr;        // workspace
   size_t ws_bytes = 0;
+  void* scratch = nullptr;   // this device's fixed scratch array (tls_op_toeplitz_noalloc)
   void* pinned = nullptr;    // host staging
   size_t pinned_bytes = 0;
   std::vector<hipEvent_t> events;  // profile = 1: pairs around each Toeplitz pass

@@ -291,6 +291,76 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
 
 namespace {
 
+// Fixed scratch memory of the allocation-free pass (tls_op_toeplitz_noalloc):
+// one copy per device, held until the process ends and shared by every such
+// call on that device.  Host code never uses this name as an address: the
+// device address of each device's copy is looked up once (scratch_init) and
+// kept in g_scratch.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t{16} << 20;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+void* g_scratch[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// With `device` current: the device address of its scratch copy.
+hipError_t scratch_init(int device, void** out) {
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = ptr;
+  }
+  *out = g_scratch[device];
+  return hipSuccess;
+}
+
+// Scratch of one tls_op_toeplitz call: v, (s1, s2), v's packed spectrum and
+// the (p + 1) x groups block partials, 256-byte aligned slices from `base`.
+struct ToepScratch {
+  double* v;
+  double* coef;
+  void* Vh;
+  double* part;
+};
+size_t toep_scratch(int p, int B, int groups, char* base, ToepScratch* t) {
+  Arena a;
+  a.base = base;
+  t->v = a.take<double>(p);
+  t->coef = a.take<double>(2);
+  t->Vh = a.take<char>(static_cast<size_t>(B / 2) * 16);
+  t->part = a.take<double>(static_cast<size_t>(p + 1) * groups);
+  return a.need;
+}
+
+// The pass of tls_op_toeplitz with its scratch at `base`.
+tls_status toep_op(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n, int32_t p, int32_t B,
+                   const double* v, double s1, double s2, const void* d_w, void* d_e,
+                   const void* d_u_in, int32_t want_rmv, double* d_out, hipStream_t s,
+                   const ToepScratch& t, int nb, int ng) {
+  const int pr = prec == TLS_PREC_F64 ? PREC_F64 : PREC_F32;
+  const int lgn = ilog2(B) - 1;
+  int mode = MODE_RMV;
+  if (v) {
+    const double cf[2] = {s1, s2};
+    TLS_CHECK(hipMemcpyAsync(t.v, v, p * sizeof(double), hipMemcpyHostToDevice, s));
+    TLS_CHECK(hipMemcpyAsync(t.coef, cf, sizeof(cf), hipMemcpyHostToDevice, s));
+    TLS_CHECK(launch_small_rfft(pr, lgn, t.v, p, p, 1, 1.0 / B, t.Vh, ctx->tw, nullptr, s));
+    mode = want_rmv ? MODE_FUSED : MODE_MV;
+  }
+  TLS_CHECK(launch_toep(pr, lgn, mode, d_spec, t.Vh, d_w, d_e, d_u_in, t.part, t.coef, nullptr,
+                        ctx->tw, n - p, p, B - p + 1, nb, s));
+  if (mode & PM_RMV) {
+    TLS_CHECK(launch_colsum(t.part, ng, p + 1, d_out, nullptr, s));
+  } else {
+    TLS_CHECK(launch_colsum(t.part + static_cast<size_t>(p) * ng, ng, 1, d_out + p, nullptr, s));
+  }
+  // the host copies above read pageable memory; finish before returning
+  TLS_CHECK(hipStreamSynchronize(s));
+  return TLS_OK;
+}
+
 tls_ctx* g_default = nullptr;
 std::mutex g_default_mu;
 
@@ -348,6 +418,7 @@ tls_status tls_create(tls_ctx** out, int device, const tls_options* opt) {
   for (int k = 0; k < 2 && e == hipSuccess; ++k)
     e = hipEventCreateWithFlags(&c->chunk_ev[k], hipEventDisableTiming);
   if (e == hipSuccess) e = build_twiddles(c);
+  if (e == hipSuccess) e = scratch_init(device, &c->scratch);
   if (e != hipSuccess) {
     tls_destroy(c);
     return hip_status(e);
@@ -541,41 +612,34 @@ tls_status tls_op_toeplitz(tls_ctx* ctx, int32_t prec, const void* d_spec, int64
   const int64_t nb64 = tls_num_blocks(n, p, B);
   if (nb64 < 1) return TLS_EINVAL;
   const int nb = static_cast<int>(nb64);
+  const int ng = pass_groups(ilog2(B) - 1, nb);
   hipSetDevice(ctx->device);
-  hipStream_t s = pick_stream(ctx, stream);
-  const int pr = prec == TLS_PREC_F64 ? PREC_F64 : PREC_F32;
-  const int lgn = ilog2(B) - 1;
-  Arena a;
-  a.take<double>(p);
-  a.take<double>(2);
-  a.take<char>(static_cast<size_t>(B / 2) * 16);
-  const int ng = pass_groups(lgn, nb);
-  a.take<double>(static_cast<size_t>(p + 1) * ng);
-  TLS_CHECK(ensure_ws(ctx, a.need + 256));
-  a.need = 0;
-  a.base = static_cast<char*>(ctx->ws);
-  double* dv = a.take<double>(p);
-  double* dcoef = a.take<double>(2);
-  void* Vh = a.take<char>(static_cast<size_t>(B / 2) * 16);
-  double* part = a.take<double>(static_cast<size_t>(p + 1) * ng);
-  int mode = MODE_RMV;
-  if (v) {
-    const double cf[2] = {s1, s2};
-    TLS_CHECK(hipMemcpyAsync(dv, v, p * sizeof(double), hipMemcpyHostToDevice, s));
-    TLS_CHECK(hipMemcpyAsync(dcoef, cf, sizeof(cf), hipMemcpyHostToDevice, s));
-    TLS_CHECK(launch_small_rfft(pr, lgn, dv, p, p, 1, 1.0 / B, Vh, ctx->tw, nullptr, s));
-    mode = want_rmv ? MODE_FUSED : MODE_MV;
-  }
-  TLS_CHECK(launch_toep(pr, lgn, mode, d_spec, Vh, d_w, d_e, d_u_in, part, dcoef, nullptr, ctx->tw,
-                        n - p, p, B - p + 1, nb, s));
-  if (mode & PM_RMV) {
-    TLS_CHECK(launch_colsum(part, ng, p + 1, d_out, nullptr, s));
-  } else {
-    TLS_CHECK(launch_colsum(part + static_cast<size_t>(p) * ng, ng, 1, d_out + p, nullptr, s));
-  }
-  // the host copies above read pageable memory; finish before returning
-  TLS_CHECK(hipStreamSynchronize(s));
-  return TLS_OK;
+  ToepScratch t{};
+  TLS_CHECK(ensure_ws(ctx, toep_scratch(p, B, ng, nullptr, &t) + 256));
+  toep_scratch(p, B, ng, static_cast<char*>(ctx->ws), &t);
+  return toep_op(ctx, prec, d_spec, n, p, B, v, s1, s2, d_w, d_e, d_u_in, want_rmv, d_out,
+                 pick_stream(ctx, stream), t, nb, ng);
+}
+
+tls_status tls_op_toeplitz_noalloc(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n,
+                                   int32_t p, int32_t B, const double* v, double s1, double s2,
+                                   const void* d_w, void* d_e, const void* d_u_in,
+                                   int32_t want_rmv, double* d_out, void* stream) {
+  if (!ctx || !d_spec || !d_out) return TLS_EINVAL;
+  if (!v && (!d_u_in || !want_rmv)) return TLS_EINVAL;
+  const int64_t nb64 = tls_num_blocks(n, p, B);
+  if (nb64 < 1) return TLS_EINVAL;
+  if (nb64 > (int64_t{1} << 30)) return TLS_EUNSUPPORTED;
+  const int nb = static_cast<int>(nb64);
+  const int ng = pass_groups(ilog2(B) - 1, nb);
+  ToepScratch t{};
+  if (toep_scratch(p, B, ng, nullptr, &t) > NOALLOC_SCRATCH_BYTES) return TLS_EUNSUPPORTED;
+  if (!ctx->scratch) return TLS_EDEVICE;
+  hipSetDevice(ctx->device);
+  // every slice is written before it is read: nothing needs clearing
+  toep_scratch(p, B, ng, static_cast<char*>(ctx->scratch), &t);
+  return toep_op(ctx, prec, d_spec, n, p, B, v, s1, s2, d_w, d_e, d_u_in, want_rmv, d_out,
+                 pick_stream(ctx, stream), t, nb, ng);
 }
 
 tls_status tls_op_scores(tls_ctx* ctx, int32_t prec, const void* d_spec, int64_t n, int32_t p,
