@@ -457,7 +457,9 @@ def pacf_bench(args, torch, synth, capi):
     """The PACF study of Section 4.1 on synthetic data: lags 1..250 of an
     AR(150) series with n = 2,000,000, every lag an AR(h) fit, all lags in
     one batched call; exact (OLS) and compressed (estimator SKETCH, 8h rows,
-    2000 at the last lag) PACF.  value: exact lag fits per second."""
+    2000 at the last lag) PACF; and LSAR (Algorithm 3, tls_lsar_device:
+    the lags one after another, c = 2000 rows each, scores carried from lag
+    to lag).  value: exact lag fits per second."""
     import oracle
     f = synth.WORKLOADS["pacf"](seed=0)
     y, pmax = f.y, f.p
@@ -479,6 +481,20 @@ def pacf_bench(args, torch, synth, capi):
                      "status": capi.status_string(s),
                      "lags_ok": int(np.sum(st == capi.TLS_OK)), "tau": tau}
         print(f"[bench] {name} PACF: {dt:.3f} s, order {order}", file=sys.stderr, flush=True)
+    # LSAR (Algorithm 3): c = 2000 rows at every lag, as in the paper's study
+    c_lsar = 2000
+    for _ in range(args.warmup):
+        ctx.lsar_device(dy, pmax, c_lsar, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        la = ctx.lsar_device(dy, pmax, c_lsar, stream=stream)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res["lsar"] = {"seconds": dt, "lag_fits_per_s": pmax / dt, "order": la["order"],
+                   "status": capi.status_string(la["status"]), "rows_per_lag": c_lsar,
+                   "lags_ok": int(np.sum(la["lag_status"] == capi.TLS_OK)), "tau": la["pacf"]}
+    print(f"[bench] LSAR PACF: {dt:.3f} s, order {la['order']}", file=sys.stderr, flush=True)
     diff = np.abs(res["exact"]["tau"] - res["compressed"]["tau"])
     # oracle on a bounded sample: the first lags on a prefix, timed on the host
     cpu = None
@@ -498,6 +514,20 @@ def pacf_bench(args, torch, synth, capi):
                "sample": f"oracle.pacf of lags 1..{lags} on the first {nsub} samples in {t:.2f} s, "
                          f"scaled by the m (h+1)^2 cost of all {pmax} lags at full length",
                "max_abs_tau_diff_vs_gpu_on_sample": float(np.abs(ref - sub).max())}
+        # the oracle's LSAR on the same kind of sample: its per-lag cost is a
+        # residual over the rows (R h) and the compressed QR (c h^2)
+        import oracle.lsar as olsar
+        draws = [oracle.philox_uniform(c_lsar, capi.RNG_LEVERAGE, 0, 0, start=(h - 1) * c_lsar)
+                 for h in range(1, lags + 1)]
+        t0 = time.perf_counter()
+        olsar.lsar_pacf(y[:nsub], lags, c_lsar, draws)
+        t = time.perf_counter() - t0
+        cost_sample = sum((nsub - lags) * h + c_lsar * h * h for h in range(1, lags + 1))
+        cost_all = sum((y.size - pmax) * h + c_lsar * h * h for h in range(1, pmax + 1))
+        cpu["lsar"] = {"value": pmax / (t * cost_all / cost_sample), "unit": "lag fits/s",
+                       "sample": f"oracle.lsar.lsar_pacf of lags 1..{lags} on the first {nsub} "
+                                 f"samples (c = {c_lsar}) in {t:.2f} s, scaled by the "
+                                 f"R h + c h^2 cost of all {pmax} lags at full length"}
     line = {
         "metric": METRIC, "value": res["exact"]["lag_fits_per_s"], "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -507,7 +537,10 @@ def pacf_bench(args, torch, synth, capi):
                    "true_order": 150},
         "exact": {k: v for k, v in res["exact"].items() if k != "tau"},
         "compressed": {k: v for k, v in res["compressed"].items() if k != "tau"},
+        "lsar": {k: v for k, v in res["lsar"].items() if k != "tau"},
         "max_abs_tau_diff_exact_vs_compressed": float(diff.max()),
+        "max_abs_tau_diff_exact_vs_lsar": float(np.abs(res["exact"]["tau"]
+                                                       - res["lsar"]["tau"]).max()),
         "paper_context": "the paper reports a ~700 s gap between exact and compressed PACF "
                          "for AR(150), n=2e6, 250 lags (MATLAB, 4-core laptop CPU)",
     }
@@ -520,9 +553,12 @@ def pacf_bench(args, torch, synth, capi):
 def rh_bench(args, torch, synth, capi):
     """The LSAR-versus-RH comparison of Sections 4.1-4.2 on synthetic data:
     relative percentage coefficient error (100 ||phi_c - phi*|| / ||phi*||)
-    of the compressed estimate at every lag 1..p, from the leverage sketch and
-    from the repeated-halving sketch, with and without outliers, and the time
-    of each batch of lag fits.  value: LSAR compressed lag fits/s on AR(100)."""
+    of the compressed estimate at every lag 1..p against the exact fit of
+    that lag, with and without outliers, and the time of each method's lags:
+    LSAR (Algorithm 3: scores carried from lag to lag, c = 20p rows at every
+    lag), repeated halving (Algorithm 4, 20h rows at lag h) and, for
+    reference, the one-level generalised leverage sketch (eq. (glev) scores
+    w.r.t. a uniform sketch, 20h rows).  value: LSAR lag fits/s on AR(100)."""
     models = (5, 20, 100)
     n = 2_000_000
     ctx = capi.Context(0, precision=0)
@@ -539,7 +575,7 @@ def rh_bench(args, torch, synth, capi):
             ptrs = [dy[: n - p + h] for h in lags]  # prefix views, no copies
             res = {}
             for name, opts in (("exact", {}),
-                               ("lsar", {"estimator": capi.EST_SKETCH, "gamma": 20}),
+                               ("leverage1", {"estimator": capi.EST_SKETCH, "gamma": 20}),
                                ("rh", {"estimator": capi.EST_SKETCH, "gamma": 20,
                                        "sketch": capi.SKETCH_RH})):
                 ctx.fit_batch_device(ptrs, lags, 1e-10, stream=stream, **opts)
@@ -548,9 +584,16 @@ def rh_bench(args, torch, synth, capi):
                 s, fits = ctx.fit_batch_device(ptrs, lags, 1e-10, stream=stream, **opts)
                 torch.cuda.synchronize()
                 res[name] = (time.perf_counter() - t0, fits, s)
+            ctx.lsar_device(dy, p, 20 * p, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            la = ctx.lsar_device(dy, p, 20 * p, stream=stream)
+            torch.cuda.synchronize()
+            res["lsar"] = (time.perf_counter() - t0, [{"coef": ph} for ph in la["phi"]],
+                           la["status"])
             ex = res["exact"][1]
             row = {"p": p, "outliers": outliers, "lags": len(lags)}
-            for name in ("exact", "lsar", "rh"):
+            for name in ("exact", "lsar", "rh", "leverage1"):
                 t, fits, s = res[name]
                 row[name + "_seconds"] = t
                 row[name + "_status"] = capi.status_string(s)
@@ -561,7 +604,8 @@ def rh_bench(args, torch, synth, capi):
                     row[name + "_max_pct_err"] = float(np.max(errs))
             print(f"[bench] AR({p}) outliers={outliers}: exact {row['exact_seconds']:.3f} s, "
                   f"LSAR {row['lsar_seconds']:.3f} s err {row['lsar_mean_pct_err']:.2f}%, "
-                  f"RH {row['rh_seconds']:.3f} s err {row['rh_mean_pct_err']:.2f}%",
+                  f"RH {row['rh_seconds']:.3f} s err {row['rh_mean_pct_err']:.2f}%, one-level "
+                  f"{row['leverage1_seconds']:.3f} s err {row['leverage1_mean_pct_err']:.2f}%",
                   file=sys.stderr, flush=True)
             if p == models[-1] and not outliers:
                 value = len(lags) / row["lsar_seconds"]

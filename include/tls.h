@@ -239,12 +239,41 @@ tls_status tls_set_tuning(tls_ctx* ctx, const int8_t* table);
  * for the compressed estimator (Algorithm 3's order rule), 0 when no lag
  * passes.  d_series: device pointer, read on `stream`; pacf: host [pmax];
  * lag_status (optional): host [pmax], each lag's fit status (lags whose fit
- * failed do not count for the order).  Returns TLS_OK when every lag's fit
- * is TLS_OK, else the first failing status; TLS_EINVAL for NULL pointers,
+ * failed do not count for the order; a stalled fit, TLS_ESTALL, holds its
+ * best iterate and counts).  Returns TLS_OK when every lag's fit is TLS_OK,
+ * else the first other status; TLS_EINVAL for NULL pointers,
  * pmax < 1 or n < 2 pmax + 1, TLS_EUNSUPPORTED for pmax > 1024. */
 tls_status tls_pacf_device(tls_ctx* ctx, const double* d_series, int64_t n, int32_t pmax,
                            double tol, const tls_options* opt, void* stream, double* pacf,
                            int32_t* order, tls_status* lag_status);
+
+/* ---- LSAR: PACF through approximate leverage scores carried across lags ------
+ * Section 3.1 (the LSAR algorithm), the approximate leverage scores
+ * definition, eqs. (FALS), (FAR), (FASD), and Algorithm 3.  Lag h (1..pmax)
+ * fits AR(h) on the series prefix of n - pmax + h samples (every lag has
+ * R = n - pmax rows) by the compressed estimator of eq. (OLSc) on c rows drawn
+ * with replacement from pi_h = l_h / h and rescaled 1/sqrt(c pi_h), where
+ * l_1(i) = y[i]^2 / sum_{t<R} y[t]^2 and l_h = l_{h-1} + r_{h-1}^2 / ||r_{h-1}||^2
+ * with r_{h-1} = X_{h-1} phi_{h-1} - b_{h-1} over all R rows and phi_{h-1} the
+ * previous lag's compressed solution.  tau_h = phi_h[h-1].  The block spectra
+ * of the series are computed once and every lag's residual is one FFT pass
+ * over them.  Lag h draws Philox stream 3 uniforms (h-1) c .. h c - 1 of
+ * (opt.seed, opt.request_id); opt.block_lg may fix the FFT block length.
+ * d_series: device, n doubles, read on `stream`.  pacf: host [pmax] out.
+ * order (optional, host): the largest h whose fit succeeded with
+ * |tau_h| >= 1.96 / sqrt(c), 0 when none.  phi_packed (optional, host,
+ * pmax (pmax + 1) / 2 doubles): lag h's coefficients at h (h - 1) / 2.
+ * rows (optional, host, pmax c int64): lag h's sampled rows at (h - 1) c.
+ * lag_status (optional, host [pmax]): TLS_ERANK where lag h's compressed
+ * problem was numerically rank deficient.  d_scores (optional, device,
+ * n - pmax doubles): the scores l_pmax of the last lag.  Returns TLS_OK when
+ * every lag succeeded, else the first failing status; TLS_EINVAL for NULL
+ * pointers, pmax < 1, n < 2 pmax + 1 or c outside [pmax + 1, n - pmax];
+ * TLS_EUNSUPPORTED for pmax > 1024. */
+tls_status tls_lsar_device(tls_ctx* ctx, const double* d_series, int64_t n, int32_t pmax,
+                           int32_t c, const tls_options* opt, void* stream, double* pacf,
+                           int32_t* order, double* phi_packed, int64_t* rows,
+                           tls_status* lag_status, double* d_scores);
 
 /* ---- served continuous batching ----------------------------------------------
  * A server admits fit requests as they arrive and runs them to completion on

@@ -165,6 +165,8 @@ _SIGS = {
     "tls_server_destroy": (None, [_vp]),
     "tls_pacf_device": (_i32, [_ctxp, _vp, _i64, _i32, _c.c_double, _c.POINTER(TlsOptions), _vp,
                                _dp, _c.POINTER(_i32), _c.POINTER(_i32)]),
+    "tls_lsar_device": (_i32, [_ctxp, _vp, _i64, _i32, _i32, _c.POINTER(TlsOptions), _vp, _dp,
+                               _c.POINTER(_i32), _dp, _c.POINTER(_i64), _c.POINTER(_i32), _vp]),
     "tls_autotune": (_i32, [_ctxp, _i32, _i32, _i32, _i64, _i64, _c.POINTER(_i32)]),
     "tls_get_tuning": (_i32, [_ctxp, _c.POINTER(_c.c_int8)]),
     "tls_set_tuning": (_i32, [_ctxp, _c.POINTER(_c.c_int8)]),
@@ -403,6 +405,24 @@ class Context:
                                 ctypes.byref(o), _stream(stream), _dptr(pacf), ctypes.byref(order),
                                 st.ctypes.data_as(ctypes.POINTER(_i32)))
         return s, pacf, order.value, st
+
+    def lsar_device(self, d_series, pmax: int, c: int, stream=None, d_scores=None, **opts):
+        """tls_lsar_device: dict with status, pacf[pmax], order, phi (list: lag h's
+        coefficients), rows (pmax x c sampled rows), lag_status[pmax]; the last
+        lag's scores go to the device tensor d_scores when given."""
+        pacf = np.zeros(pmax)
+        order = _i32(0)
+        phi = np.zeros(pmax * (pmax + 1) // 2)
+        rows = np.zeros((pmax, c), dtype=np.int64)
+        st = np.zeros(pmax, dtype=np.int32)
+        o = self._opt(opts)
+        s = lib.tls_lsar_device(self._h, _ptr(d_series), d_series.numel(), pmax, c,
+                                ctypes.byref(o), _stream(stream), _dptr(pacf), ctypes.byref(order),
+                                _dptr(phi), rows.ctypes.data_as(ctypes.POINTER(_i64)),
+                                st.ctypes.data_as(ctypes.POINTER(_i32)), _ptr(d_scores))
+        phis = [phi[h * (h - 1) // 2: h * (h - 1) // 2 + h].copy() for h in range(1, pmax + 1)]
+        return {"status": s, "pacf": pacf, "order": order.value, "phi": phis, "rows": rows,
+                "lag_status": st}
 
     def autotune(self, precision: int, p_min: int, p_max: int, n_min: int, n_max: int) -> int:
         """Measure block lengths on the device; returns the table entries written."""

@@ -578,7 +578,9 @@ tls_status tls_pacf_device(tls_ctx* ctx, const double* d_series, int64_t n, int3
     if (lag_status) lag_status[h - 1] = fs[h - 1];
     // 95% band of a zero PACF over the rows the lag-h estimate used
     const double rows = compressed ? res[h - 1].sketch_rows : static_cast<double>(n - pmax);
-    if (fs[h - 1] == TLS_OK && rows > 0 && fabs(tau) >= 1.96 / sqrt(rows)) best = h;
+    // a stalled fit (TLS_ESTALL) holds the best iterate at working precision
+    const bool usable = fs[h - 1] == TLS_OK || fs[h - 1] == TLS_ESTALL;
+    if (usable && rows > 0 && fabs(tau) >= 1.96 / sqrt(rows)) best = h;
   }
   if (order) *order = best;
   return first;
