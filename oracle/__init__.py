@@ -23,7 +23,8 @@ from .leverage import (  # noqa: F401
     approx_generalized_scores, scores_from_omega, ar1_leverage,
 )
 from .sketch import (  # noqa: F401
-    uniform_rows, leverage_sample, sketch_rows, hadamard, srht_map, jl_omega,
+    uniform_rows, leverage_sample, sketch_rows, sketch_r, shifted_r, hadamard, srht_map,
+    jl_omega,
     compressed_solution, rh_levels, rh_level_mask, rh_sketch,
 )
 from .philox import philox4x32_10, philox_uniform, philox_normal  # noqa: F401

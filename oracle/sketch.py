@@ -18,8 +18,8 @@ rh_levels, rh_level_mask: the nested uniform halvings of Algorithm 4 (repeated
 rh_sketch: Algorithm 4 end to end.  The smallest level is stood for by c
   uniform row trials (scale sqrt(m/c)); going up, level i's rows are scored
   with the approximate generalised leverage scores of eq. (glev) with respect
-  to the sketch of level i + 1 (R from a Householder QR of that sketch's
-  first p columns, Omega = R^{-1} Pi^T with one k x p JL map Pi for every
+  to the sketch of level i + 1 (R from one shifted Cholesky QR sweep of that
+  sketch, shifted_r, Omega = R^{-1} Pi^T with one k x p JL map Pi for every
   level), rows outside level i get score zero, and c rows are drawn from the
   scores (leverage_sample with that level's draws) to form level i's sketch;
   level 0 is all rows, and its sketch is the result.
@@ -128,6 +128,36 @@ def srht_map(p: int, k: int, u_signs, u_rows) -> np.ndarray:
     return Pi[:, :p]
 
 
+def sketch_r(A, p: int) -> np.ndarray:
+    """R of a sketch's first p columns with a non-negative diagonal, the
+    unique upper-triangular factor with R^T R = A^T A.  A QR fixes R only up
+    to the signs of its rows; the generalised scores of eq. (glev) use R only
+    through R^{-1}, but once a JL map multiplies R^{-1} the approximate scores
+    depend on those signs (R^{-1} D Pi^T is another map for every sign
+    matrix D), so they are fixed here."""
+    R = sla.qr(np.asarray(A, np.float64)[:, :p], mode="r")[0][:p, :p]
+    return R * np.where(np.diag(R) < 0, -1.0, 1.0)[:, None]
+
+
+def shifted_r(A, p: int) -> np.ndarray:
+    """The factor that approximate scores are taken with respect to: R[:p, :p]
+    of one sweep of shifted Cholesky QR (Fukaya, Kannan, Nakatsukasa,
+    Yamamoto, Yanagisawa, SIAM J. Sci. Comput. 2020) of the q-column sketch A,
+    i.e. the transposed Cholesky factor of A^T A + s I with the shift
+    s = 11 (c' q + q (q + 1)) u tr(A^T A), u = 2^-53 and c' the sketch's row
+    count rounded up to a multiple of 16 (zero rows padding it to the row
+    tiles).  It equals the QR factor of A with a non-negative diagonal
+    (sketch_r) up to relative O(s / sigma_min(A)^2); the approximate scores
+    are defined with respect to this factor, which exists for any A."""
+    A = np.asarray(A, np.float64)
+    q = A.shape[1]
+    crows = -(-A.shape[0] // 16) * 16
+    G = A.T @ A
+    s = 11.0 * (crows * q + q * (q + 1)) * 2.0 ** -53 * np.trace(G)
+    L = np.linalg.cholesky(G + s * np.eye(q))
+    return L.T[:p, :p]
+
+
 def jl_omega(R, Pi) -> np.ndarray:
     """Omega = R^{-1} Pi^T (p x k) for upper-triangular R."""
     return sla.solve_triangular(np.asarray(R, np.float64), np.asarray(Pi, np.float64).T,
@@ -146,8 +176,7 @@ def rh_sketch(y, p: int, c: int, u_uniform, u_level, Pi, level_draws):
     idx, scale = uniform_rows(u_uniform, m, c)
     A = sketch_rows(y, p, idx, scale)
     for lev in range(levels - 1, -1, -1):
-        R = sla.qr(A[:, :p], mode="r")[0][:p, :p]
-        Omega = jl_omega(R, Pi)
+        Omega = jl_omega(shifted_r(A, p), Pi)
         Z = np.column_stack([matvec(y, p, Omega[:, q]) for q in range(Omega.shape[1])])
         s = np.sum(Z * Z, axis=1)
         if lev > 0:

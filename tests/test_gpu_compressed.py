@@ -104,3 +104,40 @@ def test_estimator_rejects_unknown(ctx):
     c = capi()
     y = np.random.default_rng(0).standard_normal(1000)
     assert ctx.fit(y, 3, 1e-10, estimator=2)["status"] == c.TLS_EINVAL
+
+
+@pytest.mark.parametrize("p,n,seed", [(6, 60000, 0), (15, 150000, 1), (40, 300000, 2)])
+def test_compressed_leverage_matches_oracle(ctx, p, n, seed):
+    """The one-level leverage sketch end to end against the oracle fed the
+    same Philox draws: uniform trials -> R of one shifted Cholesky QR sweep
+    (oracle.shifted_r) -> Omega = R^{-1} Pi^T with the SRHT map -> eq. (glev)
+    scores -> leverage draws -> compressed solution.  The two factors differ
+    by rounding (relative ~ q u kappa^2 of the uniform sketch), which moves
+    no draw here, so the estimates agree to the final QR's backward error
+    plus that rounding's effect on the row scales."""
+    import math
+    c = capi()
+    say("compressed leverage vs oracle", p, n)
+    rng = np.random.default_rng(90 + seed)
+    y = synth.ar_series(n, p, rng, 0.3, 0.7)
+    fit_id, rseed, k, cc = 21 + seed, 17, 8, 8 * p
+    out = ctx.fit(y, p, 1e-10, estimator=c.EST_SKETCH, seed=rseed, request_id=fit_id)
+    assert out["status"] == c.TLS_OK
+    m = n - p
+    P = 1 << max(0, math.ceil(math.log2(p)))
+    Pi = oracle.srht_map(p, k, oracle.philox_uniform(P, c.RNG_SRHT_SIGNS, fit_id, rseed),
+                         oracle.philox_uniform(k, c.RNG_SRHT_ROWS, fit_id, rseed))
+    i0, s0 = oracle.uniform_rows(oracle.philox_uniform(cc, c.RNG_UNIFORM_ROWS, fit_id, rseed),
+                                 m, cc)
+    B = oracle.sketch_rows(y, p, i0, s0)
+    sc = oracle.scores_from_omega(y, p, oracle.jl_omega(oracle.shifted_r(B, p), Pi))
+    i1, s1 = oracle.leverage_sample(sc, oracle.philox_uniform(cc, c.RNG_LEVERAGE, fit_id, rseed),
+                                    cc)
+    A = oracle.sketch_rows(y, p, i1, s1)
+    ref = oracle.compressed_solution(A)
+    kap = oracle.kappa(np.linalg.qr(A[:, :-1], mode="r"))
+    kap0 = oracle.kappa(np.linalg.qr(B[:, :p], mode="r"))
+    r_rel = 16 * (p + 1) * 2.0 ** -53 * kap0 ** 2
+    err = oracle.rel_error(out["coef"], ref)
+    say("   kappa(SX)=%.3g err=%.3g" % (kap, err))
+    assert err <= max(1e-12, 1e-14 * kap * p) + 4 * kap * r_rel

@@ -3,6 +3,8 @@ mask equals the oracle's nested halvings bit for bit; with a single level it
 is the leverage sketch bit for bit; fits converge to the OLS solution like
 the other sketches; the compressed estimate's residual ratio is in
 [1, 1 + eps); batched calls equal single fits; servers reject it."""
+import math
+
 import numpy as np
 import pytest
 
@@ -85,3 +87,42 @@ def test_rh_compressed_ratio_batch_and_server(ctx):
     with pytest.raises(c.TlsError) as e:
         c.Server(ctx, 1 << 28, 8, sketch=c.SKETCH_RH)
     assert e.value.status == c.TLS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("p,n,seed", [(6, 60000, 0), (12, 150000, 1), (20, 400000, 2)])
+def test_rh_compressed_matches_oracle(ctx, p, n, seed):
+    """The compressed estimate from the repeated-halving sketch against the
+    oracle's Algorithm 4 fed the same Philox draws (smallest level's uniform
+    trials, the rows' level draws, the SRHT map, each level's leverage
+    draws); both take every level's scores with respect to the factor of one
+    shifted Cholesky QR sweep of the level below (oracle.shifted_r).  The
+    factors differ by rounding, which moves no draw on these
+    well-conditioned series, so the estimates agree to the QR backward error
+    plus that rounding's effect on the row scales."""
+    c = capi()
+    say("rh compressed vs oracle", p, n)
+    rng = np.random.default_rng(70 + seed)
+    y = synth.ar_series(n, p, rng, 0.3, 0.7)
+    fit_id, rseed, k = 5 + seed, 13, 8
+    cc = 8 * p
+    out = ctx.fit(y, p, 1e-10, sketch=c.SKETCH_RH, estimator=c.EST_SKETCH, seed=rseed,
+                  request_id=fit_id)
+    assert out["status"] == c.TLS_OK
+    m = n - p
+    levels = oracle.rh_levels(m, cc)
+    P = 1 << max(0, math.ceil(math.log2(p)))
+    Pi = oracle.srht_map(p, k, oracle.philox_uniform(P, c.RNG_SRHT_SIGNS, fit_id, rseed),
+                         oracle.philox_uniform(k, c.RNG_SRHT_ROWS, fit_id, rseed))
+    draws = [oracle.philox_uniform(cc, c.RNG_LEVERAGE, fit_id, rseed, start=i * cc)
+             for i in range(levels)]
+    A, idx, scale, lev = oracle.rh_sketch(
+        y, p, cc, oracle.philox_uniform(cc, c.RNG_UNIFORM_ROWS, fit_id, rseed),
+        oracle.philox_uniform(m, c.RNG_RH_LEVEL, fit_id, rseed), Pi, draws)
+    assert lev == levels and levels >= 3
+    ref = oracle.compressed_solution(A)
+    kap = oracle.kappa(np.linalg.qr(A[:, :-1], mode="r"))
+    err = oracle.rel_error(out["coef"], ref)
+    shift_rel = 16 * (p + 1) * 2.0 ** -53 * kap ** 2
+    say("   levels=%d kappa(SX)=%.3g err=%.3g" % (levels, kap, err))
+    assert err <= max(1e-12, 1e-14 * kap * p) + 4 * kap * shift_rel
+    assert abs(out["resid_norm"] - oracle.residual_norm(y, p, ref)) <= 1e-9 * out["resid_norm"]

@@ -198,7 +198,7 @@ def test_rh_sketch_one_level_is_the_leverage_sketch(rng):
     assert levels == 1
     i0, s0 = oracle.uniform_rows(uu, m, c)
     B = oracle.sketch_rows(y, p, i0, s0)
-    R = np.linalg.qr(B[:, :p], mode="r")
+    R = oracle.shifted_r(B, p)
     sc = oracle.scores_from_omega(y, p, oracle.jl_omega(R, Pi))
     i1, s1 = oracle.leverage_sample(sc, d0, c)
     assert np.array_equal(idx, i1)
@@ -230,7 +230,7 @@ def test_rh_sketch_levels_and_exact_scores(rng):
     B = oracle.sketch_rows(y, p, i, s)
     X, _ = oracle.lag_matrix(y, p)
     for lev in range(levels - 1, -1, -1):
-        R = np.linalg.qr(B[:, :p], mode="r")
+        R = oracle.shifted_r(B, p)
         sc = oracle.scores_from_omega(y, p, oracle.jl_omega(R, Pi))
         if lev == 0:
             np.testing.assert_allclose(sc, oracle.generalized_scores(X, B[:, :p]), rtol=1e-9)
@@ -242,3 +242,42 @@ def test_rh_sketch_levels_and_exact_scores(rng):
         B = oracle.sketch_rows(y, p, i, s)
     assert np.array_equal(i, idx)
     np.testing.assert_allclose(B, A, rtol=1e-12)
+
+
+def test_sketch_r_sign_convention(rng):
+    """sketch_r: upper triangular, non-negative diagonal, R^T R = A^T A, and
+    equal to the transposed Cholesky factor of A^T A (the factor that a
+    Cholesky-based QR produces), whatever signs the Householder QR chose."""
+    A = rng.standard_normal((40, 6)) * np.array([1, 10, 0.1, 3, 1e3, 1])
+    R = oracle.sketch_r(A, 5)
+    assert np.all(np.diag(R) >= 0) and np.allclose(R, np.triu(R))
+    np.testing.assert_allclose(R.T @ R, A[:, :5].T @ A[:, :5], rtol=1e-12, atol=1e-9)
+    L = np.linalg.cholesky(A[:, :5].T @ A[:, :5])
+    np.testing.assert_allclose(R, L.T, rtol=1e-9, atol=1e-9 * np.abs(L).max())
+    # flipping a row of A's QR factor changes the JL scores but not the exact ones
+    Pi = rng.standard_normal((3, 5))
+    D = np.diag([1, -1, 1, 1, -1.0])
+    y = synth.ar_series(400, 5, rng, 0.3, 0.8)
+    a = oracle.scores_from_omega(y, 5, oracle.jl_omega(R, Pi))
+    b = oracle.scores_from_omega(y, 5, oracle.jl_omega(D @ R, Pi))
+    assert np.abs(a - b).max() > 1e-6 * np.abs(a).max()
+    e1 = oracle.scores_from_omega(y, 5, oracle.jl_omega(R, np.eye(5)))
+    e2 = oracle.scores_from_omega(y, 5, oracle.jl_omega(D @ R, np.eye(5)))
+    np.testing.assert_allclose(e1, e2, rtol=1e-10)
+
+
+def test_shifted_r_definition(rng):
+    """shifted_r: (R^T R)[:p,:p] = A^T A + s I on the leading block with the
+    stated shift; close to sketch_r by O(s / sigma_min^2); a rank-deficient
+    sketch still has a finite factor (the shift keeps it positive definite)."""
+    A = rng.standard_normal((50, 6))
+    R = oracle.shifted_r(A, 5)
+    G = A.T @ A
+    s = 11.0 * (64 * 6 + 6 * 7) * 2.0 ** -53 * np.trace(G)   # 50 rows pad to 64
+    np.testing.assert_allclose(R.T @ R, G[:5, :5] + s * np.eye(5), rtol=1e-13, atol=1e-12)
+    Rq = oracle.sketch_r(A, 5)
+    sig = np.linalg.svd(A[:, :5], compute_uv=False)
+    assert np.abs(R - Rq).max() <= 10 * s / sig[-1] ** 2 * np.abs(Rq).max() + 1e-13 * np.abs(Rq).max()
+    B = np.column_stack([A[:, 0], A[:, 0], A[:, 1]])   # exactly rank 2
+    Rb = oracle.shifted_r(B, 3)
+    assert np.all(np.isfinite(Rb)) and np.all(np.diag(Rb) > 0)
