@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "AR(p) Toeplitz-LSQR solves/sec & FFT-matvec HBM GB/s at rel err 1e-6"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6  # MI355X dense FP64 matrix peak
 
 WORKLOAD_TEXT = {
     "ar100": "AR(100) series, n=2^22, 50 pole pairs with moduli U[0.5,0.95] and angles "
@@ -65,6 +66,39 @@ WORKLOAD_TEXT = {
 # profile are used only while these are unchanged.
 PASS_SOURCES = ["paper_2112_12994_amd/csrc/toeplitz_impl.h", "paper_2112_12994_amd/csrc/fft.h",
                 "paper_2112_12994_amd/csrc/common.h", "paper_2112_12994_amd/csrc/toeplitz.hip"]
+
+
+def qr_source_hash() -> str:
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2112_12994_amd/csrc/qr.hip"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_mfma_profile(workload: str):
+    """FP64-MFMA figures of the QR kernels from the committed counter summary
+    (profiles/qr_mfma_<workload>.txt) while qr.hip is unchanged since."""
+    path = os.path.join(ROOT, "profiles", f"qr_mfma_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    rows, hsh = [], None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("qr_source_hash:"):
+                hsh = line.split(":", 1)[1].strip()
+            elif line and not line.startswith(("#", "kernel", "qr_source_hash")):
+                f = line.split()
+                if len(f) >= 6:
+                    rows.append({"kernel": " ".join(f[:-5]), "dispatches": int(f[-5]),
+                                 "f64_mfma_flop_per_dispatch": float(f[-4]),
+                                 "avg_us": float(f[-3]), "tflops": float(f[-2]),
+                                 "util": float(f[-1])})
+    if hsh != qr_source_hash() or not rows:
+        return None
+    flop = sum(r["f64_mfma_flop_per_dispatch"] * r["dispatches"] for r in rows)
+    us = sum(r["avg_us"] * r["dispatches"] for r in rows)
+    return {"source": os.path.relpath(path, ROOT), "kernels": rows,
+            "util_over_mfma_kernels": flop / (us * 1e-6) / (FP64_MFMA_PEAK_TFS * 1e12)}
 
 
 def pass_source_hash() -> str:
@@ -119,7 +153,28 @@ def prof_summary(kind: str, dirs: list, out: str, cmd: str, title: str):
     """Compact text summaries of rocprofv3 CSV output (kernel statistics, or
     per-dispatch HBM counters with the copy-kernel calibration)."""
     lines = [f"# {title}", f"# command: {cmd}", f"source_hash: {pass_source_hash()}"]
-    if kind == "stats":
+    if kind == "mfma":
+        # dirs: counter run (SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES,
+        # GRBM_GUI_ACTIVE), kernel-statistics run of the same command
+        lines[2] = f"qr_source_hash: {qr_source_hash()}"
+        per = {}
+        for r in _rows(dirs[0], "counter_collection.csv"):
+            k = _short(r["kernel_name"])
+            d = per.setdefault(k, {}).setdefault(r["dispatch_id"], {})
+            d[r["counter_name"]] = float(r["counter_value"])
+        avg = {_short(r["name"]): float(r["averagens"]) for r in _rows(dirs[1], "kernel_stats.csv")}
+        lines.append(f"{'kernel':60s} {'disp':>5s} {'f64_mfma_flop':>14s} {'avg_us':>9s} "
+                     f"{'TFLOP/s':>8s} {'util_of_78.6':>12s}")
+        for k, ds in sorted(per.items()):
+            mops = [d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) for d in ds.values()]
+            if not any(mops):
+                continue
+            flop = 512.0 * sum(mops) / len(mops)
+            us = avg.get(k, float("nan")) / 1e3
+            tf = flop / (us * 1e-6) / 1e12 if us == us else float("nan")
+            lines.append(f"{k[:60]:60s} {len(ds):5d} {flop:14.4e} {us:9.2f} {tf:8.3f} "
+                         f"{tf / FP64_MFMA_PEAK_TFS:12.4f}")
+    elif kind == "stats":
         rows = _rows(dirs[0], "kernel_stats.csv")
         tot = sum(float(r["totaldurationns"]) for r in rows) or 1.0
         lines.append(f"{'kernel':90s} {'calls':>7s} {'total_us':>11s} {'avg_us':>9s} {'pct':>6s}")
@@ -140,6 +195,9 @@ def prof_summary(kind: str, dirs: list, out: str, cmd: str, title: str):
                 vals.setdefault(_short(r["kernel_name"]), []).append(float(r["counter_value"]))
             if match is None:  # the copy run: the kernel that moved the most
                 name = max(vals, key=lambda k: max(vals[k]))
+            elif match.endswith("*"):  # every kernel with this prefix, pooled
+                v = [x for k in vals if k.startswith(match[:-1]) for x in vals[k]]
+                return match, sum(v) / len(v), len(v)
             else:
                 name = next(k for k in vals if k.startswith(match))
             v = vals[name]
@@ -147,6 +205,8 @@ def prof_summary(kind: str, dirs: list, out: str, cmd: str, title: str):
 
         kname, fetch, nf = mean_for(dirs[0], "FETCH_SIZE", kern)
         _, write, nw = mean_for(dirs[1], "WRITE_SIZE", kern)
+        if kern.endswith("*"):
+            kname = kern + " (every instantiation)"
         cname, cfetch, _ = mean_for(dirs[2], "FETCH_SIZE", None)
         _, cwrite, _ = mean_for(dirs[3], "WRITE_SIZE", None)
         fs, ws = copy_bytes / (cfetch * 1024), copy_bytes / (cwrite * 1024)
@@ -320,26 +380,29 @@ def batch_bench(args, torch, synth, capi):
         if prec == 0:
             tot_bytes += fused_pass_bytes(f.y.size, f.p, B, nb, 8) * (o["iters"] + 1)
         else:
-            tot_bytes += (nb * (B // 2) * 8 + (B // 2) * 8 + (f.p + 1) * nb * 8) * o["iters"]
+            tot_bytes += (nb * (B // 2) * 8 + (B // 2) * 8
+                          + (f.p + 1) * pass_groups(B, nb) * 8) * o["iters"]
     avg_launch_s = pass_ms / max(pass_count, 1) / 1e3
     achieved = tot_bytes / (pass_ms / 1e3) / 1e9 if pass_ms else 0.0
     statuses = [o["status"] for o in outs]
 
     # plain path: one synchronous FP64 fit per series
-    ctx64 = capi.Context(0, gamma=8, precision=0)
-    for i in range(8):
-        ctx64.fit_device(dys[i], ps[i], 1e-10, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for d, p in zip(dys, ps):
-        ctx64.fit_device(d, p, 1e-10, stream=stream)
-    torch.cuda.synchronize()
-    plain = len(fits) / (time.perf_counter() - t0)
-    ctx64.close()
+    plain = None
+    if not args.no_extras:
+        ctx64 = capi.Context(0, gamma=8, precision=0)
+        for i in range(8):
+            ctx64.fit_device(dys[i], ps[i], 1e-10, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for d, p in zip(dys, ps):
+            ctx64.fit_device(d, p, 1e-10, stream=stream)
+        torch.cuda.synchronize()
+        plain = len(fits) / (time.perf_counter() - t0)
+        ctx64.close()
 
     # agreement with the oracle on every 32nd fit
     errs = []
-    for i in range(0, len(fits), 32):
+    for i in range(0, 0 if args.no_extras else len(fits), 32):
         ref = oracle.fit_qr(fits[i].y, fits[i].p)
         errs.append((ref["kappa"], oracle.rel_error(outs[i]["coef"], ref["phi"])))
     gate = 1e-4 if prec else 1e-6
@@ -372,6 +435,11 @@ def batch_bench(args, torch, synth, capi):
                "sample": f"oracle.fit_qr on the first {done} of the {len(fits)} series in {t:.1f} s, "
                          f"scaled by the m (p+1)^2 cost of all series"}
     classes = sorted({(o["block_len"]) for o in outs})
+    traffic, traffic_src = None, "non-default configuration"
+    if not args.block_lg:
+        traffic, traffic_src = read_hbm_profile(
+            "batch", args.precision, "toep_b_kernel<double" if prec == 0 else "toep_b_kernel<float")
+    mf = read_mfma_profile("batch")
     line = {
         "metric": METRIC, "value": args.steps * len(fits) / elapsed, "unit": "solves/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -388,8 +456,8 @@ def batch_bench(args, torch, synth, capi):
                    "fit_statuses": {capi.status_string(k): statuses.count(k) for k in set(statuses)},
                    "median_iters": int(np.median([o["iters"] for o in outs]))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "traffic_source": "no counter profile for the batched pass",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": traffic_src,
                      "kernel": "toep_b_kernel (batched Toeplitz pass, "
                                + ("FP64 fused LSQR pass)" if prec == 0 else "FP32 normal-equation pass)"),
                      "bytes_per_launch": tot_bytes / max(pass_count, 1),
@@ -399,6 +467,8 @@ def batch_bench(args, torch, synth, capi):
                                   "what": "one synchronous FP64 tls_fit_device per series"},
         "accuracy": {"oracle_sample": len(errs), "gate": gate, "by_kappa": strata},
     }
+    if mf:
+        line["qr_fp64_mfma"] = mf
     if cpu:
         line["cpu_baseline"] = cpu
     ctx.close()
@@ -816,6 +886,9 @@ def hbm_resident_record(ctx, torch, synth, capi, stream, steps=3):
     traffic, src = read_hbm_profile("ar500", "f64")
     rec = roofline_record(f.y.size, f.p, run, steps, 0, traffic, src)
     rec["timed_in"] = f"HIP events around every pass of {steps} FP64 fits"
+    mf = read_mfma_profile("ar500")
+    if mf:
+        rec["qr_fp64_mfma"] = mf
     rec.update({"workload": "AR(500), n=2^25, seed 0, FP64, sketch 8p rows, tol 1e-10",
                 "iters": int(np.median(run["iters"])),
                 "status": capi.status_string(run["out"]["status"]),
@@ -962,6 +1035,9 @@ def main():
         "roofline": roof,
         "accuracy": acc,
     }
+    mf = read_mfma_profile(args.workload) if not args.block_lg and not args.n else None
+    if mf:
+        line["qr_fp64_mfma"] = mf
     if args.workload == "ar100" and not args.n and not args.block_lg and not args.no_extras:
         # the same series on a 24p-row sketch: fewer LSQR iterations for a larger QR
         r24 = time_fits(ctx, dy, p, f.tol, stream, torch, args.steps, args.warmup, gamma=24)
