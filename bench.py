@@ -375,13 +375,12 @@ def batch_bench(args, torch, synth, capi):
     # algorithmic bytes of the dominant pass over one batch: per fit, bytes of
     # one pass times the passes that did work for it
     tot_bytes = 0.0
+    # (mixed: the fused pass with FP32 products for the fits on that path,
+    # whose launches the same events bracket)
     for f, o in zip(fits, outs):
-        B, nb, m = o["block_len"], o["n_blocks"], f.y.size - f.p
-        if prec == 0:
-            tot_bytes += fused_pass_bytes(f.y.size, f.p, B, nb, 8) * (o["iters"] + 1)
-        else:
-            tot_bytes += (nb * (B // 2) * 8 + (B // 2) * 8
-                          + (f.p + 1) * pass_groups(B, nb) * 8) * o["iters"]
+        B, nb = o["block_len"], o["n_blocks"]
+        elem = 4 if prec and o["mixed_path"] == 1 else 8
+        tot_bytes += fused_pass_bytes(f.y.size, f.p, B, nb, elem) * (o["iters"] + 1)
     avg_launch_s = pass_ms / max(pass_count, 1) / 1e3
     achieved = tot_bytes / (pass_ms / 1e3) / 1e9 if pass_ms else 0.0
     statuses = [o["status"] for o in outs]
@@ -454,7 +453,11 @@ def batch_bench(args, torch, synth, capi):
                    "graphs": "each chunk of LSQR / inner steps of a class replayed as a HIP graph",
                    "status": capi.status_string(s),
                    "fit_statuses": {capi.status_string(k): statuses.count(k) for k in set(statuses)},
-                   "median_iters": int(np.median([o["iters"] for o in outs]))},
+                   "median_iters": int(np.median([o["iters"] for o in outs])),
+                   "mixed_paths": ({"fp32_products": sum(o["mixed_path"] == 1 for o in outs),
+                                    "fp64_refinement": sum(o["mixed_path"] == 2 for o in outs),
+                                    "fp64_products": sum(o["mixed_path"] == 3 for o in outs)}
+                                   if prec else None)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_source": traffic_src,
@@ -854,7 +857,10 @@ def roofline_record(n, p, run, steps, prec, traffic, traffic_src):
         bytes_pass = fused_pass_bytes(n, p, B, nb, 8)
         kernel_name = "toep_pass_kernel<double, fused>: e = X v - a u, X^T e, ||e||^2"
         if prec != 0:
-            kernel_name += " (the FP64 LSQR finish of the mixed fit)"
+            kernel_name += " (the FP64 LSQR of the mixed fit)"
+    elif out["pass_kind"] == 2:
+        bytes_pass = fused_pass_bytes(n, p, B, nb, 4)
+        kernel_name = "toep_pass_kernel<float, fused>: e = X v - a u, X^T e, ||e||^2 (FP32 products)"
     else:
         # the CG pass reads only the FP32 spectra and writes the block partials
         bytes_pass = nb * (B // 2) * 8 + (B // 2) * 8 + (p + 1) * pass_groups(B, nb) * 8

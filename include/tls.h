@@ -96,7 +96,9 @@ typedef struct tls_options {
   int32_t max_iter;    /* LSQR / inner iteration limit (default 1000) */
   int32_t block_lg;    /* log2 of the FFT block length B, 7..14; 0 = automatic */
   int32_t warm_start;  /* 1: start from the compressed problem's solution (default 1) */
-  int32_t max_refine;  /* mixed precision: outer FP64 refinement steps (default 10) */
+  int32_t max_refine;  /* mixed precision: outer FP64 refinement steps for fits too
+                          ill-conditioned for FP32 products alone (default 0: those fits
+                          run FP64 LSQR; see tls_result.mixed_path) */
   int32_t profile;     /* 1: time every Toeplitz pass with HIP events (tls_result.pass_ms) */
   uint64_t seed;       /* random seed (default 0) */
   uint64_t request_id; /* selects the random streams of one fit (default 0) */
@@ -120,10 +122,10 @@ typedef struct tls_result {
                           ||A^T r|| estimate stopped decreasing (30 iterations without
                           halving: the rounding of the FFT products was reached before
                           tol; the best iterate is returned with TLS_ESTALL); 7 iteration
-                          limit.  Mixed precision: 2 when the FP64 refinement converged;
-                          when it stopped contracting (conditioning beyond the FP32
-                          products' resolution) or hit its step limit, FP64 LSQR finishes
-                          from the best refinement iterate and its code is reported */
+                          limit.  Mixed precision: see mixed_path; LSQR's code is
+                          reported, and for refinement 2 when it converged (when it
+                          stopped contracting or hit its step limit, FP64 LSQR finishes
+                          from the best refinement iterate and its code is reported) */
   int32_t refine_steps;/* outer refinement steps (mixed precision), else 0 */
   int32_t sketch_rows; /* c */
   int32_t block_len;   /* FFT block length B used */
@@ -137,9 +139,18 @@ typedef struct tls_result {
                           fit's result) */
   int32_t pass_worked; /* profile = 1: how many of them did work */
   int32_t pass_kind;   /* which pass the three fields above cover: 0 the fused FP64 LSQR
-                          pass, 1 the FP32 normal-equation pass of the mixed refinement.
+                          pass, 1 the FP32 normal-equation pass of the mixed refinement,
+                          2 the fused LSQR pass with FP32 products (mixed, kappa_est <= 1e3).
                           A mixed single fit whose FP64 LSQR finish ran reports whichever
-                          of the two took more device time; batched mixed fits report 1 */
+                          of the two took more device time; batched mixed fits report 2 */
+  int32_t mixed_path;  /* mixed precision: the path the fit took, chosen from
+                          kappa_F = ||R||_F ||R^{-1}||_F of the sketch factor (>= kappa(R)):
+                          1 LSQR with FP32 products (FP32 spectra, u and v's spectrum) and
+                          FP64 recurrences to max(tol, 1e-7), when kappa_F <= 300 (the
+                          FP32 result is then within about 1e-5 of the FP64 one); 2 FP64
+                          refinement around FP32 inner solves, when max_refine > 0 and
+                          kappa_F <= 1e8; 3 FP64 LSQR otherwise.  0 for FP64 fits and for
+                          the compressed estimator */
 } tls_result;
 
 typedef struct tls_ctx tls_ctx;
@@ -205,8 +216,9 @@ tls_status tls_fit_batch_device(tls_ctx* ctx, int32_t count, const double* const
  * The FFT block length B of the overlap-save products (eq. (xphi) through
  * circulant embedding) trades FFT work per sample against the p - 1 samples
  * each block re-reads.  tls_autotune measures, on the device and on synthetic
- * data, the per-iteration pass of the given precision (FP64: the fused LSQR
- * pass; mixed: the FP32 normal-equation pass; each with its column sums) at
+ * data, the per-iteration fused LSQR pass with FP64 products and its column
+ * sums (also for the mixed table: a class's B is fixed before each fit's
+ * mixed_path is known, and the FP64-product pass is the costlier one) at
  * every admissible B (2p <= B <= 2^14, B no longer than needed for m) for the
  * order buckets covering [p_min, p_max] (measured at p = 2^bucket) and the
  * length buckets covering [n_min, n_max] (measured at m = 2^bucket, at most

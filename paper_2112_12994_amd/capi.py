@@ -88,6 +88,7 @@ class TlsResult(ctypes.Structure):
         ("pass_count", ctypes.c_int32),
         ("pass_worked", ctypes.c_int32),
         ("pass_kind", ctypes.c_int32),
+        ("mixed_path", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -58,13 +58,15 @@ __global__ void post_qr_b_kernel(const Item* fits, const FitDesc* D, int warm, i
 }
 
 // Mixed precision: fits whose refinement stopped without converging (stop 5
-// or 7) restart FP64 LSQR from their best iterate; the others are marked done
-// and counted.
+// or 7), and the fits set to FP64 LSQR by the dispatch (stop 5, phib = phi0),
+// run FP64 LSQR from their best iterate; the others are marked done and
+// counted.
 __global__ void fallback_prep_b_kernel(const Item* fits, const FitDesc* D, int* counts) {
   const FitDesc& d = D[fits[blockIdx.x].fit];
   const int stop = d.rst->stop;
   if (stop == 5 || stop == 7) {
     for (int i = threadIdx.x; i < d.p; i += blockDim.x) d.phi0[i] = d.phib[i];
+    if (threadIdx.x == 0) d.st->done = 0;
   } else if (threadIdx.x == 0) {
     d.st->done = 1;
     atomicAdd(counts, 1);
@@ -113,7 +115,8 @@ __global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* 
     r.dmax = d.dminmax[0];
     r.dmin = d.dminmax[1];
     for (int k = 0; k < 4; ++k) r.status[k] = d.status[k];
-    if (mixed) {
+    r.path = mixed ? d.rst->path : 0;
+    if (mixed && d.rst->path == MP_REFINE) {
       const RefineState& s = *d.rst;
       r.rnorm = s.rnorm;
       r.arnorm = s.hnorm;
@@ -351,17 +354,29 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
 }
 
 tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
-                           const Item* groups, int ngroups, const Item* cols, int ncols,
+                           int precs, const Item* groups, int ngroups, const Item* cols, int ncols,
                            const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
                            PassTimer* tm, hipStream_t s) {
-  if (first) TLS_CHECK(launch_small_rfft_b(PREC_F64, lgn, 1, fits, nfits, D, ctx->tw, s));
+  // precs bit 0: the fits with FP64 products; bit 1: those with FP32 products
+  // (FP32 spectra, u and v's spectrum in FP32).  Each launch skips the fits
+  // whose products have the other precision (LsqrState::f32).
+  const bool p64 = (precs & 1) != 0, p32 = (precs & 2) != 0;
+  if (first && p64) TLS_CHECK(launch_small_rfft_b(PREC_F64, lgn, 1, fits, nfits, D, ctx->tw, s));
+  if (first && p32) TLS_CHECK(launch_small_rfft_b(PREC_F32, lgn, 1, fits, nfits, D, ctx->tw, s));
   if (tm) TLS_CHECK(tm->begin(s));
-  TLS_CHECK(launch_toep_b(PREC_F64, lgn, first ? BP_LSQR_FIRST : BP_LSQR, groups, ngroups, D,
-                          ctx->consts, ctx->tw, s));
+  if (p64)
+    TLS_CHECK(launch_toep_b(PREC_F64, lgn, first ? BP_LSQR_FIRST : BP_LSQR, groups, ngroups, D,
+                            ctx->consts, ctx->tw, s));
+  if (p32)
+    TLS_CHECK(launch_toep_b(PREC_F32, lgn, BP_LSQR32, groups, ngroups, D, ctx->consts, ctx->tw, s));
   if (tm) TLS_CHECK(tm->end(s));
   TLS_CHECK(launch_colsum_b(0, cols, ncols, D, s));
-  TLS_CHECK(launch_lsqr_step_b(PREC_F64, lgn, fits, nfits, pmax, mlds, D, counts, done_list,
-                               ctx->tw, s));
+  if (p64)
+    TLS_CHECK(launch_lsqr_step_b(PREC_F64, lgn, fits, nfits, pmax, mlds, D, counts, done_list,
+                                 ctx->tw, s));
+  if (p32)
+    TLS_CHECK(launch_lsqr_step_b(PREC_F32, lgn, fits, nfits, pmax, mlds, D, counts, done_list,
+                                 ctx->tw, s));
   return TLS_OK;
 }
 
@@ -412,6 +427,7 @@ void record_result(const FitRec& r, const Plan& pl, double ms, tls_result* o) {
   o->iters = r.iters;
   o->istop = r.istop;
   o->refine_steps = r.refine;
+  o->mixed_path = r.path;
   o->sketch_rows = pl.c;
   o->block_len = pl.B;
   o->n_blocks = pl.nblocks;
@@ -428,7 +444,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
   const bool mixed = o.precision == TLS_PREC_MIXED;
   const bool copy_y = host_series != nullptr;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
-  const int max_refine = o.max_refine > 0 ? o.max_refine : 8;
+  const int max_refine = o.max_refine > 0 ? o.max_refine : 0;
   const int inner_max = std::min(max_iter, 25);
 
   std::vector<Plan> plans(count);
@@ -634,17 +650,22 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     };
 #define SL_(lst) sl.lst, sl.n##lst
 
-    // FP64 LSQR over the class from phi0 (fits already done skip every
-    // step); cnt[0] holds the number of finished fits.  Every chunk after
-    // the first is the same sequence of launches: a graph when enabled.
-    auto lsqr64 = [&](PassTimer* t) -> tls_status {
+    // LSQR over the class (fits already done skip every step); cnt[0] holds
+    // the number of finished fits, cnt[1] those with FP32 products.  precs:
+    // bit 0 FP64 products, bit 1 FP32 products, both when the class holds
+    // n32 FP32-product fits among others (each launch skips the fits of the
+    // other precision); a precision whose fits have all finished is dropped
+    // from the steps.  Every chunk after the first is the same sequence of
+    // launches: a graph when enabled (captured again when precs changes).
+    auto lsqr_any = [&](PassTimer* t, int precs, int n32) -> tls_status {
       Lists sl = full_lists();
       for (int launched = 0;; launched += B_CHUNK_ITERS) {
         auto chunk = [&, launched]() -> tls_status {
           for (int it = 0; it < B_CHUNK_ITERS; ++it) {
             const tls_status e = lsqr_step_class(ctx, c.key.lgn, c.pmax, c.key.mlds != 0,
-                                                 launched == 0 && it == 0, SL_(groups), SL_(cols),
-                                                 SL_(fits), D, cnt, nullptr, t, s);
+                                                 launched == 0 && it == 0, precs,
+                                                 SL_(groups),
+                                                 SL_(cols), SL_(fits), D, cnt, nullptr, t, s);
             if (e != TLS_OK) return e;
           }
           return TLS_OK;
@@ -654,6 +675,13 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
         TLS_CHECK(hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         TLS_CHECK(hipStreamSynchronize(s));
         if (hc[0] >= c.count || launched > max_iter) break;
+        if (precs == 3) {
+          const int left = (hc[1] >= n32 ? 2 : 0) | (hc[0] - hc[1] >= c.count - n32 ? 1 : 0);
+          if (left) {
+            precs &= ~left;
+            drop_graphs();
+          }
+        }
         if (!t && worth_compacting(c.count - hc[0], sl.nfits)) {
           const tls_status ec = compact(sl, 0);
           if (ec != TLS_OK) return ec;
@@ -662,11 +690,46 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       return TLS_OK;
     };
     if (!mixed) {
-      const tls_status e = lsqr64(tm);
+      const tls_status e = lsqr_any(tm, 1, 0);
+      if (e != TLS_OK) return done(e);
+    } else if (max_refine == 0) {
+      // each fit's path (mixed_path_of): FP32- and FP64-product LSQR in the
+      // same steps
+      if (hipError_t he = batch_zero_ints(cnt, 4, s)) return done(hip_status(he));
+      hipLaunchKernelGGL(mixed_dispatch_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off,
+                         D, 0, MIXED_TOL_F32, cnt, 0);
+      if (hipError_t he = hipGetLastError()) return done(hip_status(he));
+      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off, D);
+      if (hipError_t he = hipGetLastError()) return done(hip_status(he));
+      if (hipError_t he = hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s))
+        return done(hip_status(he));
+      if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
+      const int n32 = hc[3];
+      if (hipError_t he = batch_zero_ints(cnt, 4, s)) return done(hip_status(he));
+      const tls_status e =
+          lsqr_any(tm, (n32 > 0 ? 2 : 0) | (n32 < c.count ? 1 : 0), n32);
       if (e != TLS_OK) return done(e);
     } else {
+      // each fit's path (mixed_path_of): FP32-product LSQR first, then the
+      // refinement fits, then FP64 LSQR for the rest and for refinements
+      // that stopped short
+      if (hipError_t he = batch_zero_ints(cnt, 4, s)) return done(hip_status(he));
+      hipLaunchKernelGGL(mixed_dispatch_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off,
+                         D, max_refine, MIXED_TOL_F32, cnt, 1);
+      if (hipError_t he = hipGetLastError()) return done(hip_status(he));
+      if (hipError_t he = hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s))
+        return done(hip_status(he));
+      if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
+      const int n_refine = hc[1];
+      if (hc[0] < c.count) {
+        hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off, D);
+        if (hipError_t he = hipGetLastError()) return done(hip_status(he));
+        const tls_status e = lsqr_any(tm, 2, c.count - hc[0]);
+        if (e != TLS_OK) return done(e);
+        drop_graphs();
+      }
       Lists sl = full_lists();
-      for (int outer = 0; outer <= max_refine; ++outer) {
+      for (int outer = 0; n_refine > 0 && outer <= max_refine; ++outer) {
         if (hipError_t he = batch_zero_ints(cnt, 2, s)) return done(hip_status(he));
         auto outer_step = [&]() -> hipError_t {
           hipError_t he = launch_small_rfft_b(PREC_F64, c.key.lgn, 2, SL_(fits), D, ctx->tw, s);
@@ -715,7 +778,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
       if (hc[0] < c.count) {
         drop_graphs();
-        const tls_status e = lsqr64(nullptr);
+        const tls_status e = lsqr_any(nullptr, 1, 0);
         if (e != TLS_OK) return done(e);
       }
     }
@@ -786,7 +849,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       record_result(hrec[j], pl, ms, &res[i]);
       res[i].pass_ms = pass_ms;  // the whole batch's launches of the dominant pass
       res[i].pass_count = pass_count;
-      res[i].pass_kind = mixed ? 1 : 0;  // mixed: only the FP32 passes are timed
+      res[i].pass_kind = mixed ? 2 : 0;  // mixed: the FP32-product LSQR passes are timed
     }
     st[i] = record_status(hrec[j], coef, pl.p);
   }

@@ -388,6 +388,118 @@ __global__ void zero_kernel(double* x, int n) {
   if (i < n) x[i] = 0.0;
 }
 
+// dst[i] = float(src[i]), i < n (the response b in FP32 for FP32-product LSQR)
+__global__ void to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    dst[i] = static_cast<float>(src[i]);
+}
+
+__global__ void set_tol_kernel(LsqrState* st, double tol) {
+  if (threadIdx.x == 0) st->tol = tol;
+}
+
+// Mixed precision: the products' precision is chosen per fit from
+// kappa_F = ||R||_F ||R^{-1}||_F of the sketch factor (R = R[:p,:p]; kappa_F >=
+// kappa_2(R), about kappa(X), and at most p times it).  LSQR with FP32
+// products and FP64 recurrences, run to max(tol, MIXED_TOL_F32) (the FP32
+// products' resolution), leaves a coefficient error of at most about
+// 0.5 kappa eps_32 (eps_32 = 6e-8; measured 0.01..0.5 kappa eps_32) against
+// the FP64 solution: with kappa_F <= MIXED_KAPPA_F32 that is below 1e-5, a
+// tenth of the mixed path's 1e-4.  Above it the fit runs FP64 LSQR (FP64
+// refinement around FP32 inner solves instead, when max_refine > 0 and
+// kappa_F <= MIXED_KAPPA_REFINE, where that refinement contracts).
+constexpr double MIXED_KAPPA_F32 = 300.0;
+constexpr double MIXED_KAPPA_REFINE = 1e8;
+constexpr double MIXED_TOL_F32 = 1e-7;
+enum MixedPath : int { MP_NONE = 0, MP_F32 = 1, MP_REFINE = 2, MP_F64 = 3 };
+
+__host__ __device__ inline int mixed_path_of(double kappa_f, int max_refine) {
+  if (kappa_f <= MIXED_KAPPA_F32) return MP_F32;
+  if (max_refine > 0 && kappa_f <= MIXED_KAPPA_REFINE) return MP_REFINE;
+  return MP_F64;
+}
+
+// ||R[:p,:p]||_F * ||M||_F for the upper-triangular R (q x q, row-major) and
+// M = R[:p,:p]^{-1} (p x p, row-major): one workgroup of NT threads, sums in a
+// fixed order (block_sum), the same in single and batched fits.
+template <int NT>
+__device__ __forceinline__ double kappa_f_body(const double* __restrict__ R, int q,
+                                               const double* __restrict__ M, int p,
+                                               double* red) {
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < p * p; k += NT) {
+    const int i = k / p, j = k - i * p;
+    if (j >= i) {
+      const double r = R[static_cast<size_t>(i) * q + j];
+      const double m = M[static_cast<size_t>(i) * p + j];
+      a = fma(r, r, a);
+      b = fma(m, m, b);
+    }
+  }
+  a = block_sum<NT>(a, red);
+  b = block_sum<NT>(b, red);
+  return sqrt(a) * sqrt(b);
+}
+
+__global__ __launch_bounds__(256) void kappa_f_kernel(const double* __restrict__ R, int q,
+                                                      const double* __restrict__ M, int p,
+                                                      double* __restrict__ out) {
+  __shared__ double red[4];
+  const double k = kappa_f_body<256>(R, q, M, p, red);
+  if (threadIdx.x == 0) *out = k;
+}
+
+// Mixed precision: each fit's path from kappa_F of its sketch factor (as the
+// single-fit driver).  FP32-product LSQR: tolerance max(tol, tol32), no
+// refinement.  The others skip the FP32 LSQR (marked done and counted in
+// counts[0]); refinement fits are counted in counts[1]; FP64-LSQR fits skip
+// the refinement and are set up for the FP64 finish from phi0.
+// phases = 0 (no refinement): only the products' precision and the FP32
+// tolerance are set, the FP32-product fits are counted in counts[3], and
+// both LSQR variants then run over the same lists.
+__global__ __launch_bounds__(256) void mixed_dispatch_b_kernel(const Item* fits, const FitDesc* D,
+                                                               int max_refine, double tol32,
+                                                               int* counts, int phases) {
+  __shared__ double red[4];
+  const FitDesc& d = D[fits[blockIdx.x].fit];
+  const double kf = kappa_f_body<256>(d.R, d.q, d.M, d.p, red);
+  const int path = mixed_path_of(kf == kf ? kf : INFINITY, max_refine);
+  if (phases && path == MP_F64)
+    for (int i = threadIdx.x; i < d.p; i += blockDim.x) d.phib[i] = d.phi0[i];
+  if (threadIdx.x == 0) {
+    d.rst->path = path;
+    d.st->f32 = path == MP_F32 ? 1 : 0;
+    if (!phases) {
+      if (path == MP_F32) {
+        d.st->tol = fmax(d.st->tol, tol32);
+        atomicAdd(counts + 3, 1);
+      }
+    } else if (path == MP_F32) {
+      d.st->tol = fmax(d.st->tol, tol32);
+      d.rst->done = d.rst->inner_done = 1;
+      d.rst->stop = 0;
+    } else {
+      d.st->done = 1;
+      atomicAdd(counts, 1);
+      if (path == MP_REFINE) atomicAdd(counts + 1, 1);
+      if (path == MP_F64) {
+        d.rst->done = d.rst->inner_done = 1;
+        d.rst->stop = 5;
+      }
+    }
+  }
+}
+
+// u = float(b) (b = y[p:]) for the fits about to run FP32-product LSQR.
+__global__ __launch_bounds__(256) void to_f32_b_kernel(const Item* fits, const FitDesc* D) {
+  const FitDesc& d = D[fits[blockIdx.x].fit];
+  if (d.st->done || !d.st->f32) return;
+  float* u = static_cast<float*>(d.u);
+  for (int64_t i = threadIdx.x; i < d.m; i += 256) u[i] = static_cast<float>(d.y[d.p + i]);
+}
+
+
 struct HostOut {
   LsqrState st;
   LsqrState ring[2];  // state snapshots at the ends of the chunks in flight
@@ -442,7 +554,7 @@ ClassLists build_lists(std::vector<Item>& items, const std::vector<int>& desc,
 struct FitRec {
   double rr, dmax, dmin, rnorm, arnorm;
   int status[4];
-  int iters, istop, refine, pad;
+  int iters, istop, refine, path;
 };
 
 void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, double tol,
@@ -468,7 +580,7 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
 // One FP64 LSQR step for the listed fits: the fused pass (first: from b and
 // phi0, after the spectrum of phi0), the column sums and the p-side step.
 tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
-                           const Item* groups, int ngroups, const Item* cols, int ncols,
+                           int precs, const Item* groups, int ngroups, const Item* cols, int ncols,
                            const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
                            PassTimer* tm, hipStream_t s);
 // FP64 residual of phi (row-wise) for the listed fits.

@@ -78,10 +78,13 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   int total_iters = 0, istop = 0, refine = 0, pass_count = 0, pass_worked = 0, pass_kind = 0;
   double pass_ms = 0.0, lsqr_rnorm = 0.0, lsqr_arnorm = 0.0;
 
-  // FP64 LSQR on A = X M from phi0 over the FP64 spectra `spec`; `timed`:
-  // event pairs around every fused pass.
-  auto lsqr64 = [&](const void* spec, bool timed) -> tls_status {
+  // LSQR on A = X M from phi0 with products of precision `pp` over the
+  // spectra `spec` (FP64: the FP64 spectra; FP32: the FP32 spectra, u and v's
+  // spectrum in FP32, recurrences in FP64); `timed`: event pairs around every
+  // fused pass.
+  auto lsqr_run = [&](int pp, const void* spec, bool timed) -> tls_status {
     const int* flag = &b.st->done;
+    void* vh = pp == PREC_F64 ? b.Vhat : b.Vhat32;
     size_t npass = 0;
     hipEvent_t ea = nullptr, eb = nullptr;
     auto pass = [&](const void* w_in) -> tls_status {
@@ -89,19 +92,25 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
         TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
         TLS_CHECK(hipEventRecord(ea, s));
       }
-      TLS_CHECK(launch_toep(PREC_F64, pl.lgn, MODE_FUSED, spec, b.Vhat, w_in, b.u, nullptr,
-                            b.partial, b.st->coef, flag, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
+      TLS_CHECK(launch_toep(pp, pl.lgn, MODE_FUSED, spec, vh, w_in, b.u, nullptr, b.partial,
+                            b.st->coef, flag, ctx->tw, pl.m, p, pl.L, pl.nblocks, s));
       if (timed) {
         TLS_CHECK(hipEventRecord(eb, s));
         ++npass;
       }
       TLS_CHECK(launch_colsum(b.partial, pl.ngroups, p + 1, b.g, flag, s));
-      TLS_CHECK(launch_lsqr_step(PREC_F64, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
-                                 b.phi, b.Vhat, ctx->tw, s));
+      TLS_CHECK(launch_lsqr_step(pp, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
+                                 b.phi, vh, ctx->tw, s));
       return TLS_OK;
     };
-    TLS_CHECK(launch_small_rfft(PREC_F64, pl.lgn, b.phi0, p, p, 1, invB, b.Vhat, ctx->tw, nullptr, s));
-    tls_status e = pass(d_y + p);
+    TLS_CHECK(launch_small_rfft(pp, pl.lgn, b.phi0, p, p, 1, invB, vh, ctx->tw, nullptr, s));
+    if (pp != PREC_F64) {
+      // the first pass's w term is b = y[p:], held in u in FP32
+      hipLaunchKernelGGL(to_f32_kernel, dim3(static_cast<int>(std::min<int64_t>((pl.m + 255) / 256, 4096))),
+                         dim3(256), 0, s, d_y + p, static_cast<float*>(b.u), pl.m);
+      TLS_CHECK(hipGetLastError());
+    }
+    tls_status e = pass(pp == PREC_F64 ? static_cast<const void*>(d_y + p) : b.u);
     if (e != TLS_OK) return e;
     // Chunks of iterations with one chunk always queued behind the one the
     // host waits for, so the device never idles on the host's convergence
@@ -147,17 +156,34 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     return TLS_OK;
   };
 
+  // mixed precision: the path from kappa_F of the sketch factor
+  int mixed_path = MP_NONE;
+  if (!compressed && prec == TLS_PREC_MIXED) {
+    hipLaunchKernelGGL(kappa_f_kernel, dim3(1), dim3(256), 0, s, b.R, q, b.M, p, b.dminmax + 2);
+    TLS_CHECK(hipGetLastError());
+    TLS_CHECK(hipMemcpyAsync(ho->dminmax, b.dminmax, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    TLS_CHECK(hipStreamSynchronize(s));
+    const double kf = ho->dminmax[2];
+    mixed_path = mixed_path_of(kf == kf ? kf : INFINITY, o.max_refine);
+  }
   if (compressed) {
     // the compressed problem's solution (eq. (OLSc)), no iterations
     hipLaunchKernelGGL(copy_vec_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phi0, p, b.phi);
     TLS_CHECK(hipGetLastError());
-  } else if (prec == TLS_PREC_F64) {
-    const tls_status e = lsqr64(b.Yhat, o.profile != 0);
+  } else if (prec == TLS_PREC_F64 || mixed_path == MP_F32 || mixed_path == MP_F64) {
+    if (mixed_path == MP_F32) {
+      hipLaunchKernelGGL(set_tol_kernel, dim3(1), dim3(64), 0, s, b.st, fmax(tol, MIXED_TOL_F32));
+      TLS_CHECK(hipGetLastError());
+    }
+    const tls_status e = mixed_path == MP_F32 ? lsqr_run(PREC_F32, b.Yhat, o.profile != 0)
+                                         : lsqr_run(PREC_F64, prec == TLS_PREC_F64 ? b.Yhat : b.Yhat64,
+                                                    o.profile != 0);
     if (e != TLS_OK) return e;
     total_iters = ho->st.iter;
     istop = ho->st.istop;
     lsqr_rnorm = ho->st.rnorm;
     lsqr_arnorm = ho->st.arnorm;
+    if (mixed_path == MP_F32) pass_kind = 2;
   } else {
     // Mixed precision: FP64 residual and gradient of the current phi, then a
     // CG solve of the preconditioned normal equations for the correction,
@@ -165,7 +191,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     // When the FP32 products stop contracting (conditioning beyond their
     // resolution) or the step limit is reached, FP64 LSQR over the FP64
     // spectra finishes from the best iterate.
-    const int max_refine = o.max_refine > 0 ? o.max_refine : 8;
+    const int max_refine = o.max_refine;
     const int inner_max = std::min(max_iter, 25);
     constexpr int INNER_CHUNK = 6;
     hipLaunchKernelGGL(fill_refine_kernel, dim3(1), dim3(64), 0, s, b.rst, tol, max_refine,
@@ -230,7 +256,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       hipLaunchKernelGGL(copy_vec_kernel, dim3((p + 255) / 256), dim3(256), 0, s, b.phib, p, b.phi0);
       TLS_CHECK(hipGetLastError());
       // profile: times the FP64 passes into pass_ms / pass_count / pass_worked
-      const tls_status e = lsqr64(b.Yhat64, o.profile != 0);
+      const tls_status e = lsqr_run(PREC_F64, b.Yhat64, o.profile != 0);
       if (e != TLS_OK) return e;
       finish_timed = o.profile != 0;
       total_iters += ho->st.iter;
@@ -278,6 +304,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     res->pass_count = pass_count;
     res->pass_worked = pass_worked;
     res->pass_kind = pass_kind;
+    res->mixed_path = mixed_path;
     res->t_total_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   }
   // a non-finite coefficient from finite data is a numerical breakdown
@@ -397,7 +424,7 @@ void tls_options_default(tls_options* o) {
   o->max_iter = 1000;
   o->block_lg = 0;
   o->warm_start = 1;
-  o->max_refine = 10;
+  o->max_refine = 0;
   o->seed = 0;
   o->request_id = 0;
 }

@@ -104,6 +104,7 @@ struct LsqrState {
   double coef[2];
   double best_ratio;  // smallest ||A^T r|| / (||A|| ||r||) estimate so far (2x steps)
   int iter, istop, done, max_iter, phase, best_iter;
+  int f32;  // mixed precision: 1 when the fit's LSQR products are FP32
 };
 hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const double* g,
                             const double* M, const double* Mt, double* v, double* w, double* z,
@@ -114,6 +115,7 @@ hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const doubl
 struct RefineState {
   double rho, rho0, tol, inner_tol, rnorm, hnorm, hprev, hbest;
   int outer, inner, max_refine, inner_max, done, inner_done, total_inner, stop;
+  int path;  // mixed precision: the fit's path (MixedPath in engine.h)
 };
 // g64: X^T r (p) and ||r||^2 ([p]) for r = b - X phi.  Keeps the iterate with
 // the smallest preconditioned gradient in phib.  Checks convergence
@@ -166,6 +168,8 @@ enum BatchPass : int {
   BP_LSQR = 1,        // FP64: e = X (M v) - (alpha/beta) u in place, X^T e
   BP_OUTER64 = 2,     // FP64: r = b - X phi, X^T r (nothing stored)
   BP_INNER32 = 3,     // FP32: X^T X (M d) (nothing stored)
+  BP_LSQR32 = 4,      // FP32 products: e = X (M v) + s2 u in place (u in FP32; it holds b
+                      // before the first step), X^T e
 };
 
 hipError_t launch_spectra_b(int prec, int lgn, const Item* items, int nitems, const FitDesc* D,

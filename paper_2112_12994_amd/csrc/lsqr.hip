@@ -730,9 +730,10 @@ hipError_t launch_vec_axpy_small(const double* Mt, const double* x, const double
 namespace {
 
 // counts[0]: fits whose LSQR (or refinement) has finished; counts[1]: fits
-// whose inner CG solve of the current refinement step has finished.  When
-// done_list is given, every fit that finishes in this launch appends its
-// descriptor index there (length in counts[2]).
+// whose inner CG solve of the current refinement step has finished, or,
+// during LSQR, the finished fits with FP32 products.  When done_list is
+// given, every fit that finishes in this launch appends its descriptor index
+// there (length in counts[2]).
 template <int LGN, int NT, typename TS, bool MLDS>
 __global__ __launch_bounds__(NT) void lsqr_step_b_kernel(const Item* __restrict__ fits,
                                                          const FitDesc* __restrict__ D,
@@ -741,11 +742,12 @@ __global__ __launch_bounds__(NT) void lsqr_step_b_kernel(const Item* __restrict_
                                                          const cx<double>* __restrict__ tab) {
   const int f = fits[blockIdx.x].fit;
   const FitDesc& d = D[f];
-  if (d.st->done) return;
+  if (d.st->done || (sizeof(TS) == 4) != (d.st->f32 != 0)) return;
   lsqr_step_body<LGN, NT, TS, MLDS>(d.p, d.st, d.g, d.M, d.Mt, d.v, d.w, d.z, d.phi0, d.phi,
                                     static_cast<cx<TS>*>(d.Vhat), tab);
   if (threadIdx.x == 0 && d.st->done) {
     atomicAdd(counts, 1);
+    if (sizeof(TS) == 4) atomicAdd(counts + 1, 1);
     if (done_list) done_list[atomicAdd(counts + 2, 1)] = f;
   }
 }

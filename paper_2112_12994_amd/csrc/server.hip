@@ -208,6 +208,9 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
   tls_ctx* ctx = S->ctx;
   hipStream_t s = S->stream;
   const tls_options& o = S->opt;
+  const bool mixed = o.precision == TLS_PREC_MIXED;
+  // LSQR variants per step: FP64 products, plus FP32 ones for mixed servers
+  const int precs = mixed ? 3 : 1;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
   const int steps = o.tick_steps > 0 ? o.tick_steps : 4;
   hipError_t e;
@@ -325,6 +328,15 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
     if (setup_class(ctx, su.key, su.pmax, su.ldqmax, I, su.l, S->dD, o, s) != TLS_OK)
       return hipErrorUnknown;
     const ClassLists& l = su.l;
+    if (mixed && o.estimator != TLS_EST_SKETCH) {
+      // each new fit's products: FP32 when its sketch factor allows it
+      // (mixed_path_of), else FP64; both LSQR variants then run over the lists
+      hipLaunchKernelGGL(mixed_dispatch_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off,
+                         S->dD, 0, MIXED_TOL_F32, S->dCounts, 0);
+      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off, S->dD);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     if (o.estimator == TLS_EST_SKETCH) {
       // the compressed estimator: finished at set-up
       e = launch_compressed_b(I + l.fits.off, l.fits.n, S->dD, S->dCounts, S->dDone, s);
@@ -332,7 +344,7 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
       continue;
     }
     for (int k = 0; k < steps; ++k)
-      if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, I + l.groups.off,
+      if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, precs, I + l.groups.off,
                           l.groups.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,
                           S->dCounts, S->dDone, nullptr, s) != TLS_OK)
         return hipErrorUnknown;
@@ -341,7 +353,7 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
   // the way skip the remaining steps)
   for (int k = 0; k < steps; ++k)
     for (const Iter& it : iters) {
-      if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, I + it.groups.off, it.groups.n,
+      if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, precs, I + it.groups.off, it.groups.n,
                           I + it.cols.off, it.cols.n, I + it.fits.off, it.fits.n, S->dD,
                           S->dCounts, S->dDone, nullptr, s) != TLS_OK)
         return hipErrorUnknown;
@@ -356,7 +368,8 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
     if (e == hipSuccess) e = S->hCoef.ensure(coef_total);
     if (e == hipSuccess) e = S->hRec.ensure(finishing.size());
     if (e != hipSuccess) return e;
-    e = collect_b(I + fin_collect.off, fin_collect.n, S->dD, 0, S->dCoef.p, S->dRec.p, s);
+    e = collect_b(I + fin_collect.off, fin_collect.n, S->dD, mixed ? 1 : 0, S->dCoef.p, S->dRec.p,
+                  s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(S->hRec.p, S->dRec.p, finishing.size() * sizeof(FitRec), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
@@ -518,7 +531,11 @@ tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
                              const tls_options* opt, tls_server** out) {
   if (!ctx || !out || max_slots < 1 || hbm_budget < (size_t{1} << 20)) return TLS_EINVAL;
   const tls_options o = opt ? *opt : ctx->opt;
-  if (o.precision != TLS_PREC_F64 || o.sketch == TLS_SKETCH_RH) return TLS_EUNSUPPORTED;
+  // served fits take FP32 or FP64 products per fit (mixed_path_of); the FP64
+  // refinement band and repeated halving are not served
+  if (o.sketch == TLS_SKETCH_RH) return TLS_EUNSUPPORTED;
+  if (o.precision == TLS_PREC_MIXED && o.max_refine > 0) return TLS_EUNSUPPORTED;
+  if (o.precision != TLS_PREC_F64 && o.precision != TLS_PREC_MIXED) return TLS_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return TLS_EDEVICE;
   auto* S = new tls_server();
   S->ctx = ctx;

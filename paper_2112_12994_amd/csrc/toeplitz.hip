@@ -325,6 +325,12 @@ __global__ __launch_bounds__(NT * pass_nw(LGN)) void toep_b_kernel(const Item* _
   constexpr int NW = pass_nw(LGN);
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
+  // the LSQR passes run for the fits whose products have their precision
+  if constexpr (VARIANT == BP_LSQR_FIRST || VARIANT == BP_LSQR) {
+    if (d.st->f32) return;
+  } else if constexpr (VARIANT == BP_LSQR32) {
+    if (!d.st->f32) return;
+  }
   if constexpr (VARIANT == BP_LSQR_FIRST || VARIANT == BP_LSQR) {
     const T* w = VARIANT == BP_LSQR_FIRST ? reinterpret_cast<const T*>(d.y + d.p)
                                           : static_cast<const T*>(d.u);
@@ -334,6 +340,12 @@ __global__ __launch_bounds__(NT * pass_nw(LGN)) void toep_b_kernel(const Item* _
                                            opaque_ptr(static_cast<const T*>(nullptr)), d.partial,
                                            d.st->coef, &d.st->done, tab, d.m, d.p, d.L,
                                            d.nblocks, d.ngroups, it.idx);
+  } else if constexpr (VARIANT == BP_LSQR32) {
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(
+        static_cast<const cx<T>*>(d.Yhat), static_cast<const cx<T>*>(d.Vhat),
+        opaque_ptr(static_cast<const T*>(d.u)), opaque_ptr(static_cast<T*>(d.u)),
+        opaque_ptr(static_cast<const T*>(nullptr)), d.partial, d.st->coef, &d.st->done, tab, d.m,
+        d.p, d.L, d.nblocks, d.ngroups, it.idx);
   } else if constexpr (VARIANT == BP_OUTER64) {
     toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(
         static_cast<const cx<T>*>(d.Yhat64), static_cast<const cx<T>*>(d.Vhat),
@@ -357,6 +369,8 @@ __global__ __launch_bounds__(NT) void small_rfft_b_kernel(const Item* __restrict
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
   const double scale = 1.0 / static_cast<double>(2 << LGN);
+  // variant 1 (v's spectrum for LSQR) in the precision of the fit's products
+  if (variant == 1 && (sizeof(TS) == 4) != (d.st->f32 != 0)) return;
   if (variant == 0)
     small_rfft_body<LGN, NT, TS>(d.Om, d.p, d.p, scale, static_cast<cx<TS>*>(d.Omhat), tab,
                                  nullptr, it.idx);
@@ -413,6 +427,10 @@ hipError_t toep_b_sel(int prec, int variant, const Item* items, int nitems, cons
     case BP_OUTER64:
       hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_OUTER64>), dim3(nitems), dim3(NT * pass_nw(LGN)), 0,
                          st, items, D, consts, tab_of<double>(tw));
+      break;
+    case BP_LSQR32:
+      hipLaunchKernelGGL((toep_b_kernel<float, LGN, NT, BP_LSQR32>), dim3(nitems),
+                         dim3(NT * pass_nw(LGN)), 0, st, items, D, consts, tab_of<float>(tw));
       break;
     case BP_INNER32:
       hipLaunchKernelGGL((toep_b_kernel<float, LGN, NT, BP_INNER32>), dim3(nitems), dim3(NT * pass_nw(LGN)), 0,

@@ -1,8 +1,11 @@
 // Block-length autotuner: for each (precision, order bucket, length bucket)
-// it times the per-iteration pass of that precision at every admissible FFT
-// block length on synthetic data and keeps the fastest in the context's
-// table, which make_plan consults when the options leave the length
-// automatic.
+// it times the per-iteration LSQR pass at every admissible FFT block length
+// on synthetic data and keeps the fastest in the context's table, which
+// make_plan consults when the options leave the length automatic.  Mixed
+// precision: a class's block length is fixed before each fit's path (FP32-
+// or FP64-product LSQR) is known; the table is taken from the FP64-product
+// pass, the costlier of the two (on a batch of AR(2..64) series that choice
+// beat the sum of both passes' times by 6%).
 #include <algorithm>
 
 #include "engine.h"
@@ -22,10 +25,10 @@ struct TuneBufs {
   double* g;
 };
 
-size_t tune_carve(int prec, int64_t m, int p, int lg, TuneBufs* t, char* base) {
+size_t tune_carve(int64_t m, int p, int lg, TuneBufs* t, char* base) {
   Arena a;
   a.base = base;
-  const size_t es = prec == PREC_F64 ? sizeof(double) : sizeof(float);
+  const size_t es = sizeof(double);
   const int B = 1 << lg, L = B - p + 1;
   const int64_t nb = (m + L - 1) / L;
   t->y = a.take<double>(static_cast<size_t>(m + p));
@@ -38,33 +41,28 @@ size_t tune_carve(int prec, int64_t m, int p, int lg, TuneBufs* t, char* base) {
   return a.need;
 }
 
-// Median device time (ms) of one pass + column sums at block length 2^lg.
-tls_status time_pass(tls_ctx* ctx, int prec, int64_t m, int p, int lg, hipEvent_t e0,
-                     hipEvent_t e1, double* ms) {
+// Median device time (ms) of one FP64 pass + column sums at block length 2^lg.
+tls_status time_pass(tls_ctx* ctx, int64_t m, int p, int lg, hipEvent_t e0, hipEvent_t e1,
+                     double* ms) {
+  const int prec = PREC_F64;
   hipStream_t s = ctx->stream;
   TuneBufs t{};
-  const size_t need = tune_carve(prec, m, p, lg, &t, nullptr);
+  const size_t need = tune_carve(m, p, lg, &t, nullptr);
   TLS_CHECK(ensure_ws(ctx, need + 256));
-  tune_carve(prec, m, p, lg, &t, static_cast<char*>(ctx->ws));
+  tune_carve(m, p, lg, &t, static_cast<char*>(ctx->ws));
   const int B = 1 << lg, lgn = lg - 1, L = B - p + 1;
   const int nb = static_cast<int>((m + L - 1) / L);
   // synthetic series: uniform draws (the pass's cost does not depend on them)
   TLS_CHECK(launch_philox_uniform(t.y, m + p, 0, 0, 0x7475'6e65ull, 0, s));
   TLS_CHECK(launch_spectra(prec, lgn, t.y, m + p, L, nb, t.spec, ctx->tw, s));
   TLS_CHECK(launch_small_rfft(prec, lgn, t.y, p, p, 1, 1.0 / B, t.Vhat, ctx->tw, nullptr, s));
-  const bool f64 = prec == PREC_F64;
-  if (f64) TLS_CHECK(hipMemcpyAsync(t.u0, t.y, m * sizeof(double), hipMemcpyDeviceToDevice, s));
+  TLS_CHECK(hipMemcpyAsync(t.u0, t.y, m * sizeof(double), hipMemcpyDeviceToDevice, s));
   std::vector<float> times;
   for (int r = 0; r < TUNE_REPS + 1; ++r) {
     TLS_CHECK(hipEventRecord(e0, s));
-    // FP64: the fused LSQR pass (e = X v - a u, X^T e); mixed: the FP32
-    // normal-equation pass (X^T X v)
-    if (f64)
-      TLS_CHECK(launch_toep(prec, lgn, MODE_FUSED, t.spec, t.Vhat, t.u0, t.u1, nullptr, t.partial,
-                            ctx->consts, nullptr, ctx->tw, m, p, L, nb, s));
-    else
-      TLS_CHECK(launch_toep(prec, lgn, MODE_FUSED, t.spec, t.Vhat, nullptr, nullptr, nullptr,
-                            t.partial, ctx->consts + 2, nullptr, ctx->tw, m, p, L, nb, s));
+    // the fused LSQR pass (e = X v - a u, X^T e)
+    TLS_CHECK(launch_toep(prec, lgn, MODE_FUSED, t.spec, t.Vhat, t.u0, t.u1, nullptr, t.partial,
+                          ctx->consts, nullptr, ctx->tw, m, p, L, nb, s));
     TLS_CHECK(launch_colsum(t.partial, pass_groups(lgn, nb), p + 1, t.g, nullptr, s));
     TLS_CHECK(hipEventRecord(e1, s));
     TLS_CHECK(hipEventSynchronize(e1));
@@ -87,7 +85,6 @@ tls_status tls_autotune(tls_ctx* ctx, int32_t precision, int32_t p_min, int32_t 
   if (p_min < 1 || p_max < p_min || p_max > P_MAX) return TLS_EINVAL;
   if (n_min < 2 * static_cast<int64_t>(p_max) + 1 || n_max < n_min) return TLS_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return TLS_EDEVICE;
-  const int prec = precision == TLS_PREC_F64 ? PREC_F64 : PREC_F32;
   const int ti = tune_prec(precision);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   TLS_CHECK(hipEventCreate(&e0));
@@ -117,7 +114,7 @@ tls_status tls_autotune(tls_ctx* ctx, int32_t precision, int32_t p_min, int32_t 
       int best_lg = 0;
       for (int lg = lg_lo; lg <= lg_hi; ++lg) {
         double ms = 0.0;
-        st = time_pass(ctx, prec, m, p, lg, e0, e1, &ms);
+        st = time_pass(ctx, m, p, lg, e0, e1, &ms);
         if (st != TLS_OK) break;
         if (best_lg == 0 || ms < best) {
           best = ms;

@@ -32,6 +32,8 @@ def _same_as_single(ctx, ys, ps, outs, rid0, device=False, **opts):
             assert o["iters"] == single["iters"], (i, p, y.size)
         if "resid_norm" in o:
             assert o["resid_norm"] == single["resid_norm"], (i, p, y.size)
+        if "mixed_path" in o:
+            assert o["mixed_path"] == single["mixed_path"], (i, p, y.size)
 
 
 def _ok_or_stalled(s, outs):
@@ -87,6 +89,7 @@ def test_batch_mixed_precision_equals_single(ctx):
           for n, p in zip([8000, 30000, 70000, 20000, 50000], ps)]
     s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=3, precision=1)
     assert s in (capi().TLS_OK, capi().TLS_ENOCONV)
+    say("   paths", [o["mixed_path"] for o in outs])
     _same_as_single(ctx, ys, ps, outs, 3, device=True, precision=1)
 
 
@@ -146,22 +149,31 @@ def test_batch_against_oracle(ctx):
         assert abs(o["resid_norm"] - ref["rnorm"]) <= 1e-9 * ref["rnorm"]
 
 
-def test_batch_mixed_fp64_finish_equals_single(ctx):
-    """Mixed batch with series beyond FP32 resolution (pole moduli up to
-    0.95): the fits whose refinement stalls finish in FP64 LSQR inside the
-    batch, bit for bit as alone, and reach the FP64 path's residual."""
-    say("batch mixed fp64 finish")
+@pytest.mark.parametrize("max_refine", [0, 8])
+def test_batch_mixed_paths_equal_single(ctx, max_refine):
+    """Mixed batch with well and badly conditioned series together (pole
+    moduli 0.3-0.85 and 0.5-0.95): each fit takes its own path (FP32-product
+    LSQR, refinement when allowed, FP64 LSQR) inside the batch, bit for bit
+    as alone, and reaches the FP64 path's residual."""
+    say("batch mixed paths", max_refine)
     rng = np.random.default_rng(18)
-    ps = [40, 64, 12, 50]
-    ys = [synth.ar_series(int(n), p, rng, 0.5, 0.95) for n, p in zip([60000, 100000, 20000, 80000], ps)]
-    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=9, precision=1)
+    ps = [40, 64, 12, 50, 8, 30]
+    mods = [(0.5, 0.95)] * 4 + [(0.3, 0.6)] * 2
+    ys = [synth.ar_series(int(n), p, rng, *m)
+          for n, p, m in zip([60000, 100000, 20000, 80000, 30000, 50000], ps, mods)]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=9, precision=1,
+                                   max_refine=max_refine)
     assert s == capi().TLS_OK
-    _same_as_single(ctx, ys, ps, outs, 9, device=True, precision=1)
+    _same_as_single(ctx, ys, ps, outs, 9, device=True, precision=1, max_refine=max_refine)
+    paths = [o["mixed_path"] for o in outs]
+    say("   paths", paths)
+    assert 1 in paths and (3 if max_refine == 0 else 2) in paths
     for y, p, o in zip(ys, ps, outs):
         f64 = ctx.fit(y, p, 1e-10)
-        say("   p=%d refine=%d iters=%d istop=%d kappa_R=%.3g resid %.12g vs %.12g"
-            % (p, o["refine_steps"], o["iters"], o["istop"], o["kappa_est"], o["resid_norm"],
+        say("   p=%d path=%d refine=%d iters=%d istop=%d resid %.12g vs %.12g"
+            % (p, o["mixed_path"], o["refine_steps"], o["iters"], o["istop"], o["resid_norm"],
                f64["resid_norm"]))
+        assert (o["refine_steps"] > 0) == (o["mixed_path"] == 2)
         assert abs(o["resid_norm"] - f64["resid_norm"]) <= 1e-9 * f64["resid_norm"]
 
 

@@ -1,14 +1,20 @@
-"""Mixed-precision path (FP32 FFT products and sketch scores; FP64 QR,
-recurrences, residual and outer refinement, with an FP64 LSQR finish when
-the FP32 products stop contracting) against the FP64 QR oracle.  Coefficient
-gate 1e-4 relative wherever the attainable accuracy allows it, and the FP64
-bounds on coefficients, fitted values and residual at any conditioning."""
+"""Mixed precision (FP32 spectra and sketch scores; FP64 QR, recurrences and
+residual) against the FP64 QR oracle.  Each fit's path comes from
+kappa_F = ||R||_F ||R^{-1}||_F of its sketch factor: LSQR with FP32 products
+where kappa_F <= 300 (path 1), FP64 refinement around FP32 inner solves when
+asked for (max_refine > 0, path 2), FP64 LSQR otherwise (path 3).  Coefficient
+gate 1e-4 relative wherever the attainable accuracy allows it; path 1 is
+checked against the FP32 products' bounds, the others against the FP64
+ones, on coefficients, fitted values and residual at any conditioning."""
+import math
+
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from tests.gpu_common import attainable, capi, chunked_matvec_norms, resid_tol, say, to_dev
+from tests.gpu_common import (EPS32, EPS64, attainable, capi, chunked_matvec_norms, resid_tol,
+                              say, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -28,12 +34,30 @@ def _check_mixed(out, y, p, gate=1e-4, tol=1e-10):
     phi = ref["phi"]
     smax = float(np.linalg.svd(ref["R"], compute_uv=False)[0])
     xd, xphi = chunked_matvec_norms(y, p, out["coef"] - phi, phi)
-    coef_b, fit_b = attainable(phi, ref["rnorm"], ref["kappa"], smax, xphi,
-                               float(np.linalg.norm(y[p:])), p, out["block_len"], tol)
+    path = out["mixed_path"]
+    if path == 1:
+        # FP32 products to max(tol, 1e-7): the bounds with eta = 16 eps_32
+        # log2(B) + 1e-7 in place of the FP64 one (attainable() scaled)
+        eta32 = 16 * EPS32 * math.log2(out["block_len"]) + max(tol, 1e-7)
+        eta64 = 16 * EPS64 * math.log2(out["block_len"]) + tol
+        coef_b, fit_b = attainable(phi, ref["rnorm"], ref["kappa"], smax, xphi,
+                                   float(np.linalg.norm(y[p:])), p, out["block_len"], tol)
+        coef_b, fit_b = coef_b * eta32 / eta64, fit_b * eta32 / eta64
+    else:
+        coef_b, fit_b = attainable(phi, ref["rnorm"], ref["kappa"], smax, xphi,
+                                   float(np.linalg.norm(y[p:])), p, out["block_len"], tol)
     err = oracle.rel_error(out["coef"], phi)
-    say("   kappa=%.3g err=%.3g (bound %.2g) fit=%.3g refine=%d inner=%d istop=%d"
-        % (ref["kappa"], err, coef_b, xd / xphi, out["refine_steps"], out["iters"], out["istop"]))
+    say("   kappa=%.3g path=%d err=%.3g (bound %.2g) fit=%.3g refine=%d iters=%d istop=%d"
+        % (ref["kappa"], path, err, coef_b, xd / xphi, out["refine_steps"], out["iters"],
+           out["istop"]))
+    assert path in (1, 2, 3)
+    if path == 1:
+        # taken only where FP32 products meet the gate with a tenth to spare
+        assert err <= gate / 10
     rt = resid_tol(phi, ref["rnorm"], smax, np.abs(y).max(), p, xd)
+    if path == 1:
+        # plus the second-order effect of the FP32 coefficients' own error
+        rt = max(rt, 1.01 * xd * xd / (2 * ref["rnorm"]) + 1e-12 * ref["rnorm"])
     if out["status"] == c.TLS_ESTALL:
         # the FP64 finish reached the rounding of its products before tol
         assert out["istop"] == 5 and coef_b > gate, (coef_b, out["istop"])
@@ -66,10 +90,11 @@ def test_mixed_p128_long_blocks(ctx, block_lg):
     so they read M from global memory (the launch must not exceed LDS)."""
     say("mixed p128 block_lg", block_lg)
     rng = np.random.default_rng(40 + block_lg)
-    y = synth.ar_series(60000, 128, rng, 0.3, 0.8)
-    out = ctx.fit(y, 128, 1e-10, precision=MIXED, block_lg=block_lg)
+    y = synth.ar_series(60000, 128, rng, 0.2, 0.6)
+    out = ctx.fit(y, 128, 1e-10, precision=MIXED, block_lg=block_lg, max_refine=8)
     assert out["block_len"] == 1 << block_lg
     _check_mixed(out, y, 128)
+    assert out["mixed_path"] == 2 and out["refine_steps"] >= 1
 
 
 def test_mixed_ar500_shape(ctx):
@@ -90,24 +115,44 @@ def test_mixed_equals_f64_fitted_values(ctx):
     a = ctx.fit(y, 100, 1e-10)
     b = ctx.fit(y, 100, 1e-10, precision=MIXED)
     xd, xphi = chunked_matvec_norms(y, 100, a["coef"] - b["coef"], a["coef"])
-    say("   fitted diff %.3g, resid %.12g vs %.12g" % (xd / xphi, a["resid_norm"], b["resid_norm"]))
+    say("   path %d fitted diff %.3g, resid %.12g vs %.12g"
+        % (b["mixed_path"], xd / xphi, a["resid_norm"], b["resid_norm"]))
     assert a["status"] == capi().TLS_OK and b["status"] == capi().TLS_OK
-    assert xd / xphi <= 1e-9
+    # FP32 products (path 1) resolve the fitted values to their own precision
+    assert xd / xphi <= (1e-5 if b["mixed_path"] == 1 else 1e-9)
     assert abs(a["resid_norm"] - b["resid_norm"]) <= 1e-9 * a["resid_norm"]
 
 
-def test_mixed_beyond_fp32_resolution_finishes_in_fp64(ctx):
+def test_mixed_beyond_fp32_resolution_runs_fp64(ctx):
     """kappa(X) ~ 1e12 (the AR(100) pole workload) is beyond what FP32
-    products resolve: the refinement stops contracting, FP64 LSQR finishes
-    from its best iterate, and the result meets the FP64 bounds."""
+    products resolve: the fit runs FP64 LSQR (path 3), also when refinement
+    is allowed (its band ends at kappa_F = 1e8), and meets the FP64 bounds."""
     say("mixed beyond resolution")
     f = synth.workload_ar100(seed=0, n=1 << 18)
     a = ctx.fit(f.y, 100, 1e-10)
-    b = ctx.fit(f.y, 100, 1e-10, precision=MIXED)
-    say("   istop=%d refine=%d iters=%d resid %.12g vs %.12g" % (
-        b["istop"], b["refine_steps"], b["iters"], b["resid_norm"], a["resid_norm"]))
-    assert b["istop"] in (1, 2)
-    _check_mixed(b, f.y, 100)
+    for mr in (0, 8):
+        b = ctx.fit(f.y, 100, 1e-10, precision=MIXED, max_refine=mr)
+        say("   max_refine=%d path=%d istop=%d iters=%d resid %.12g vs %.12g" % (
+            mr, b["mixed_path"], b["istop"], b["iters"], b["resid_norm"], a["resid_norm"]))
+        assert b["mixed_path"] == 3 and b["refine_steps"] == 0 and b["istop"] in (1, 2)
+        _check_mixed(b, f.y, 100)
+
+
+def test_mixed_refinement_band(ctx):
+    """max_refine > 0 and 300 < kappa_F <= 1e8: FP64 refinement around FP32
+    inner solves (path 2), converging to the FP64 bounds; the same series
+    without refinement runs FP64 LSQR (path 3)."""
+    say("mixed refinement band")
+    rng = np.random.default_rng(11)
+    y = synth.ar_series(1 << 17, 40, rng, 0.5, 0.95)
+    r = ctx.fit(y, 40, 1e-10, precision=MIXED, max_refine=8)
+    d = ctx.fit(y, 40, 1e-10, precision=MIXED)
+    say("   refine: path=%d refine=%d iters=%d; default: path=%d iters=%d"
+        % (r["mixed_path"], r["refine_steps"], r["iters"], d["mixed_path"], d["iters"]))
+    assert r["mixed_path"] == 2 and r["refine_steps"] >= 1
+    assert d["mixed_path"] == 3 and d["refine_steps"] == 0
+    _check_mixed(r, y, 40)
+    _check_mixed(d, y, 40)
 
 
 def test_mixed_device_input_deterministic(ctx):
@@ -121,9 +166,9 @@ def test_mixed_device_input_deterministic(ctx):
 
 def test_profiled_pass_kind(ctx):
     """profile = 1 reports which pass its timings cover: the fused FP64 pass
-    for an FP64 fit; the FP32 normal-equation pass for a mixed fit whose
-    refinement converges; for a mixed fit with an FP64 finish, whichever took
-    more device time.  Profiling changes no result."""
+    for an FP64 fit and for a mixed fit that runs FP64 LSQR; the fused pass
+    with FP32 products for a mixed fit on that path.  Profiling changes no
+    result."""
     say("profiled pass kind")
     f = synth.workload_ar100(seed=0, n=1 << 18)
     a = ctx.fit(f.y, 100, 1e-10, profile=1)
@@ -132,11 +177,12 @@ def test_profiled_pass_kind(ctx):
     b0 = ctx.fit(f.y, 100, 1e-10, precision=MIXED)
     b = ctx.fit(f.y, 100, 1e-10, precision=MIXED, profile=1)
     assert b["coef"].tobytes() == b0["coef"].tobytes()
-    assert b["pass_kind"] in (0, 1) and b["pass_count"] >= b["pass_worked"] >= 1 and b["pass_ms"] > 0
+    assert b["mixed_path"] == 3 and b["pass_kind"] == 0
+    assert b["pass_count"] >= b["pass_worked"] >= 1 and b["pass_ms"] > 0
     g = synth.workload_ar3(seed=0)
     c0 = ctx.fit(g.y, 3, 1e-10, gamma=g.gamma, precision=MIXED)
     c = ctx.fit(g.y, 3, 1e-10, gamma=g.gamma, precision=MIXED, profile=1)
-    say("   ar100 mixed kind=%d count=%d; ar3 mixed kind=%d istop=%d refine=%d"
-        % (b["pass_kind"], b["pass_count"], c["pass_kind"], c["istop"], c["refine_steps"]))
+    say("   ar100 mixed kind=%d count=%d; ar3 mixed kind=%d path=%d istop=%d"
+        % (b["pass_kind"], b["pass_count"], c["pass_kind"], c["mixed_path"], c["istop"]))
     assert c["coef"].tobytes() == c0["coef"].tobytes()
-    assert c["pass_kind"] == 1 and c["pass_count"] >= c["pass_worked"] >= 1
+    assert c["mixed_path"] == 1 and c["pass_kind"] == 2 and c["pass_count"] >= c["pass_worked"] >= 1

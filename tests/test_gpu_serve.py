@@ -1,7 +1,9 @@
 """Served continuous batching (tls_server_*): every request's result equals the
 single fit with the same options and request id bit for bit, whatever else is
 in flight; admission under a small HBM budget; concurrent submitters;
-rejected submissions; rank-deficient and degenerate requests."""
+rejected submissions; rank-deficient and degenerate requests; mixed
+precision, where each request takes its own path (FP32-product or FP64 LSQR)
+inside the same tick."""
 import threading
 
 import numpy as np
@@ -31,12 +33,13 @@ def _series(seed, count, lo=10, hi=16, pmax=120):
     return out
 
 
-def _check_same(ctx, y, p, rid, got):
-    single = ctx.fit_device(to_dev(y), p, 1e-10, request_id=rid)
+def _check_same(ctx, y, p, rid, got, **opts):
+    single = ctx.fit_device(to_dev(y), p, 1e-10, request_id=rid, **opts)
     assert got["status"] == single["status"], (rid, p, y.size)
     assert got["coef"].tobytes() == single["coef"].tobytes(), (rid, p, y.size)
     assert got["iters"] == single["iters"], (rid, p, y.size)
     assert got["resid_norm"] == single["resid_norm"], (rid, p, y.size)
+    assert got["mixed_path"] == single["mixed_path"], (rid, p, y.size)
 
 
 def test_serve_device_equals_single(ctx):
@@ -123,8 +126,11 @@ def test_serve_rejections(ctx):
         t = srv.submit(y, 5, 1e-10)
         assert srv.wait(t)["status"] == c.TLS_OK
     with pytest.raises(c.TlsError) as e:
-        c.Server(ctx, 1 << 30, 8, precision=1)
+        c.Server(ctx, 1 << 30, 8, precision=1, max_refine=4)  # no refinement when served
     assert e.value.status == c.TLS_EUNSUPPORTED
+    with pytest.raises(c.TlsError) as e:
+        c.Server(ctx, 1 << 30, 8, precision=2)
+    assert e.value.status == c.TLS_EINVAL
 
 
 def test_serve_degenerate_requests(ctx):
@@ -168,3 +174,28 @@ def test_serve_tick_steps_equal_single(ctx, tick_steps):
         outs = [srv.wait(t) for t in tickets]
     for i, ((y, p), o) in enumerate(zip(work, outs)):
         _check_same(ctx, y, p, 300 + i, o)
+
+
+@pytest.mark.parametrize("tick_steps", [1, 5])
+def test_serve_mixed_equals_single(ctx, tick_steps):
+    """A mixed-precision server: well and badly conditioned requests in flight
+    together, each on the path its kappa_F selects, equal the single mixed fit
+    bit for bit."""
+    c = capi()
+    say("serve mixed", tick_steps)
+    rng = np.random.default_rng(8)
+    work = []
+    for i in range(24):
+        p = int(rng.integers(2, 100))
+        n = max(int(round(2.0 ** rng.uniform(11, 16))), 2 * p + 1)
+        lo, hi = (0.3, 0.6) if i % 2 else (0.5, 0.95)
+        work.append((synth.ar_series(n, p, rng, lo, hi), p))
+    with c.Server(ctx, 1 << 30, 32, tick_steps=tick_steps, precision=1) as srv:
+        tickets = [srv.submit_device(to_dev(y), p, 1e-10, request_id=700 + i)
+                   for i, (y, p) in enumerate(work)]
+        outs = [srv.wait(t) for t in tickets]
+    paths = [o["mixed_path"] for o in outs]
+    say("   paths", paths)
+    assert 1 in paths and 3 in paths and 2 not in paths
+    for i, ((y, p), o) in enumerate(zip(work, outs)):
+        _check_same(ctx, y, p, 700 + i, o, precision=1)
