@@ -712,7 +712,7 @@ def serve_bench(args, torch, synth, capi):
     torch.cuda.synchronize()
     max_iter = args.max_iter or 200
     ctx = capi.Context(0, gamma=8, max_iter=max_iter)
-    srv = capi.Server(ctx, args.serve_budget << 30, args.serve_slots)
+    srv = capi.Server(ctx, args.serve_budget << 30, args.serve_slots, tick_steps=args.tick_steps)
     # warm-up: a burst of requests, all taken before the timed window
     warm = [srv.submit_device(dys[int(i)], pool[int(i)].p, 1e-10, request_id=10_000_000 + k)
             for k, i in enumerate(which[:args.warmup * 50])]
@@ -808,6 +808,7 @@ def serve_bench(args, torch, synth, capi):
                    "duration_s": duration, "pool_series": len(pool), "requests": int(arrivals.size),
                    "samples": samples, "hbm_budget_gib": args.serve_budget,
                    "max_slots": args.serve_slots, "max_iter": max_iter,
+                   "tick_steps": args.tick_steps or 24,
                    "fit_statuses": {capi.status_string(k): statuses.count(k) for k in set(statuses)}},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p90": float(np.percentile(lat, 90)),
                        "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean()),
@@ -940,6 +941,8 @@ def main():
     ap.add_argument("--pool", type=int, default=512, help="serve: resident series in the pool")
     ap.add_argument("--serve-budget", type=int, default=64, help="serve: HBM budget in GiB")
     ap.add_argument("--serve-slots", type=int, default=8192, help="serve: fits in flight at most")
+    ap.add_argument("--tick-steps", type=int, default=0,
+                    help="serve: LSQR steps per tick (0: the library default, 24)")
     ap.add_argument("--max-iter", type=int, default=0,
                     help="LSQR iteration limit (0: the library default, 1000; serve default 200)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

@@ -105,8 +105,9 @@ typedef struct tls_options {
   int32_t no_graph;    /* batched calls: 1 launches every step directly; 0 (default) captures
                           each chunk of LSQR (or inner refinement) steps of a launch class once
                           as a HIP graph and replays it (not while profile = 1) */
-  int32_t tick_steps;  /* servers: LSQR steps each fit in flight takes per worker tick (default
-                          4; more steps per tick finish each request in fewer ticks) */
+  int32_t tick_steps;  /* servers: LSQR steps each fit in flight takes per worker tick (0 =
+                          default 24: most fits then finish in the tick that sets them up; fewer
+                          steps make shorter ticks but more of them per request) */
   int32_t estimator;   /* TLS_EST_* (default OLS) */
   int32_t reserved1;
   int64_t reserved[2];
@@ -290,7 +291,7 @@ tls_status tls_lsar_device(tls_ctx* ctx, const double* d_series, int64_t n, int3
 /* ---- served continuous batching ----------------------------------------------
  * A server admits fit requests as they arrive and runs them to completion on
  * one device: each tick of its worker thread sets up the newly admitted fits
- * and runs tick_steps LSQR steps (an option, default 4) for every fit in
+ * and runs tick_steps LSQR steps (an option, default 24) for every fit in
  * flight, all as batched launches, so
  * short and long, small-p and large-p requests share the device.  A request is
  * admitted first come, first served once its device footprint (series copy,
@@ -317,8 +318,11 @@ typedef struct tls_server_stats {
 
 /* Create a server on ctx's device with `hbm_budget` bytes of device memory
  * (allocated now, at least 1 MiB) and at most `max_slots` fits in flight.
- * opt NULL = the context's options; only TLS_PREC_F64 is served, and not the
- * repeated-halving sketch (TLS_EUNSUPPORTED otherwise).  TLS_ENOMEM if the budget cannot be allocated. */
+ * opt NULL = the context's options.  TLS_PREC_F64 and TLS_PREC_MIXED are served
+ * (mixed: each fit's products FP32 or FP64 by its mixed_path, without the
+ * refinement band: max_refine > 0 gives TLS_EUNSUPPORTED), not the
+ * repeated-halving sketch (TLS_EUNSUPPORTED); other precisions TLS_EINVAL.
+ * TLS_ENOMEM if the budget cannot be allocated. */
 tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
                              const tls_options* opt, tls_server** out);
 

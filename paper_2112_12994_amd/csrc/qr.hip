@@ -172,7 +172,7 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
                                                        int* __restrict__ status, int fail_bit,
                                                        int rank_cols) {
   constexpr int NT = TD * TD;
-  __shared__ double pub[2][TD * QT];
+  __shared__ double pub[2][TD * QT + 1];
   __shared__ double red[NT / 64];
   __shared__ int s_fail;
   const int tx = threadIdx.x % TD, ty = threadIdx.x / TD;
@@ -208,12 +208,18 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
         const int j = TD * a0 + jj;
         if (j >= q) break;
         double* pj = pub[j & 1];
+        // row j beyond the diagonal (entries up to j published as zero, so
+        // the multipliers need no masks), the pivot in its own word
         if (ty == jj) {
 #pragma unroll
-          for (int b = a0; b < QT; ++b) pj[tx + TD * b] = reg[a0][b];
+          for (int b = a0; b < QT; ++b) {
+            const int k = tx + TD * b;
+            pj[k] = k > j ? reg[a0][b] : 0.0;
+            if (k == j) pj[TD * QT] = reg[a0][b];
+          }
         }
         __syncthreads();
-        double d = pj[j];
+        double d = pj[TD * QT];
         if (!(d > floor_)) {
           if (j < rank_cols && threadIdx.x == 0) s_fail = 1;
           if (j < rank_cols && stop_on_fail) {
@@ -226,10 +232,15 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
           dmin = fmin(dmin, d);
           dmax = fmax(dmax, d);
         }
-        // independent operations (shortest dependent chain per column)
-        const double invd = 1.0 / d;
-        const double isd = 1.0 / sqrt(d);
-        const double sd = sqrt(d);
+        // 1/sqrt(d) from the hardware estimate and three Newton steps
+        // (relative error of the estimate below 2^-20: 2^-60 after two,
+        // the third settles the last bit), sqrt(d) and 1/d from it
+        double isd = __builtin_amdgcn_rsq(d);
+        isd = fma(0.5 * isd, fma(-d * isd, isd, 1.0), isd);
+        isd = fma(0.5 * isd, fma(-d * isd, isd, 1.0), isd);
+        isd = fma(0.5 * isd, fma(-d * isd, isd, 1.0), isd);
+        const double sd = d * isd;
+        const double invd = isd * isd;
         // row j of R stays in the registers of its owner (not updated again);
         // R is written once after the last column
         if (ty == jj) {
@@ -239,23 +250,19 @@ __device__ __forceinline__ void chol_reg_body(const double* __restrict__ G, int 
             reg[a0][b] = k < j ? 0.0 : (k == j ? sd : reg[a0][b] * isd);
           }
         }
-        // rank-one update of the trailing rows and columns (index > j); pub
-        // entries beyond q are zero
+        // rank-one update of the trailing rows and columns (index > j) on
+        // the tiles on and above the diagonal (the factor reads only the
+        // upper triangle: row j's entries right of the pivot are also its
+        // column's entries below it); pub entries beyond q are zero
         double fi[QT], fk[QT];
 #pragma unroll
-        for (int a = a0; a < QT; ++a) {
-          const double v = pj[ty + TD * a] * invd;
-          fi[a] = (a > a0 || ty > jj) ? v : 0.0;
-        }
+        for (int a = a0; a < QT; ++a) fi[a] = pj[ty + TD * a] * invd;
 #pragma unroll
-        for (int b = a0; b < QT; ++b) {
-          const double v = pj[tx + TD * b];
-          fk[b] = (b > a0 || tx > jj) ? v : 0.0;
-        }
+        for (int b = a0; b < QT; ++b) fk[b] = pj[tx + TD * b];
 #pragma unroll
         for (int a = a0; a < QT; ++a)
 #pragma unroll
-          for (int b = a0; b < QT; ++b) reg[a][b] -= fi[a] * fk[b];
+          for (int b = a; b < QT; ++b) reg[a][b] = fma(-fi[a], fk[b], reg[a][b]);
       }
       if (stopped) break;
     }

@@ -6,14 +6,19 @@
 // the arena and a slot is free.  Every tick of the worker:
 //   1. sets up the newly admitted fits (spectra, two-stage sketch, QR,
 //      inverse, warm start, first LSQR steps), batched by launch class;
-//   2. runs tick_steps (default 4) LSQR steps for every fit already
+//   2. runs tick_steps (default 24) LSQR steps for every fit already
 //      iterating, batched by FFT length and step variant, whatever its age
 //      (a fit that converges on the way skips the remaining steps);
 //   3. computes the FP64 residual and collects coefficients and results of
 //      the fits that finished in the previous tick;
 // then synchronises once, hands finished results to their tickets and
-// releases their arena space and slots.  Series, spectra, the sketch factor
-// and the LSQR state stay resident in the arena for a fit's whole life.
+// releases their arena space and slots.  The work units of a tick (one
+// launch class's set-up, one iteration group's steps, the finishing lists)
+// touch disjoint fits, so they are spread over the server's streams by an
+// estimate of their device time: most of these kernels fill a few compute
+// units only, and concurrent units overlap their latency chains.  Series,
+// spectra, the sketch factor and the LSQR state stay resident in the arena
+// for a fit's whole life.
 //
 // Each fit runs the arithmetic of its single fit (the batched kernels share
 // the single-fit kernels' bodies and launch-class choices), so its result is
@@ -145,12 +150,25 @@ struct HostBuf {
   }
 };
 
+// Streams of a server: the worker's own plus SERVER_AUX more (the device
+// runs four hardware queues per process).
+constexpr int SERVER_AUX = 3;
+// LSQR steps per tick by default: at 5000 requests/s of AR(2..200) series
+// of 2^10..2^20 samples, 4, 8, 12 and 24 steps per tick gave median
+// latencies of 33, 25, 23 and 22 ms and 99th percentiles of 111, 77, 67 and
+// 57 ms (a request needs about 20 steps; shorter ticks cost more of them)
+constexpr int SERVER_TICK_STEPS = 24;
+
 }  // namespace
 
 struct tls_server {
   tls_ctx* ctx = nullptr;
   tls_options opt{};
   hipStream_t stream = nullptr;
+  hipStream_t aux[SERVER_AUX] = {};
+  hipEvent_t ev_start = nullptr;
+  hipEvent_t ev_fin = nullptr;
+  hipEvent_t ev_aux[SERVER_AUX] = {};
   char* arena = nullptr;
   size_t budget = 0;
   RangeAlloc alloc;
@@ -200,9 +218,24 @@ void fail_all(tls_server* S, std::vector<Request*>& lists, tls_status st) {
   S->cv_done.notify_all();
 }
 
+// Hands the finished requests to their tickets and frees their space.
+void deliver(tls_server* S, const std::vector<Request*>& finishing) {
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (Request* r : finishing) {
+    S->alloc.release(r->off, r->bytes);
+    S->free_slots.push_back(r->slot);
+    S->slot_req[r->slot] = nullptr;
+    r->done = true;
+  }
+  S->completed += finishing.size();
+  if (!finishing.empty()) S->cv_done.notify_all();
+}
+
 // One tick of device work; returns a HIP error or success.  `admitted` are
 // new fits (slots and arena space assigned); `active` iterate; `finishing`
-// finished in the previous tick.
+// finished in the previous tick: their residual and results go first on the
+// worker's stream, and they are delivered as soon as those are on the host,
+// while the rest of the tick still runs.
 hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Request*>& active,
                 std::vector<Request*>& finishing, std::vector<Request*>* newly_done) {
   tls_ctx* ctx = S->ctx;
@@ -212,7 +245,7 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
   // LSQR variants per step: FP64 products, plus FP32 ones for mixed servers
   const int precs = mixed ? 3 : 1;
   const int max_iter = o.max_iter > 0 ? o.max_iter : 1000;
-  const int steps = o.tick_steps > 0 ? o.tick_steps : 4;
+  const int steps = o.tick_steps > 0 ? o.tick_steps : SERVER_TICK_STEPS;
   hipError_t e;
 
   // descriptors of the new fits, series copies
@@ -318,47 +351,38 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
   const Item* I = S->dItems.p;
   e = batch_zero_ints(S->dCounts, 4, s);
   if (e != hipSuccess) return e;
-
-  // 1. set-up and first LSQR step of the new fits
   if (!admitted.empty()) {
     e = batch_init(I + init_fits.off, init_fits.n, S->dD, max_iter, 0, 0, 0.0, s);
     if (e != hipSuccess) return e;
   }
-  for (const Setup& su : setups) {
-    if (setup_class(ctx, su.key, su.pmax, su.ldqmax, I, su.l, S->dD, o, s) != TLS_OK)
-      return hipErrorUnknown;
-    const ClassLists& l = su.l;
-    if (mixed && o.estimator != TLS_EST_SKETCH) {
-      // each new fit's products: FP32 when its sketch factor allows it
-      // (mixed_path_of), else FP64; both LSQR variants then run over the lists
-      hipLaunchKernelGGL(mixed_dispatch_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off,
-                         S->dD, 0, MIXED_TOL_F32, S->dCounts, 0);
-      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off, S->dD);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
+
+  // Each unit to the stream with the least estimated device time so far
+  // (microseconds; a set-up is a chain of small factorisation kernels whose
+  // length grows with the order, an LSQR step costs a few launches plus
+  // its blocks).  Stream 0 (the worker's) also takes the finishing lists.
+  hipStream_t sv[SERVER_AUX + 1] = {s};
+  for (int k = 0; k < SERVER_AUX; ++k) sv[k + 1] = S->aux[k];
+  double load[SERVER_AUX + 1] = {};
+  bool used[SERVER_AUX + 1] = {true};
+  int64_t fin_samples = 0;
+  for (Request* r : finishing) fin_samples += r->pl.n;
+  load[0] = finishing.empty() ? 0.0 : 40.0 + 1e-4 * static_cast<double>(fin_samples);
+  auto pick = [&](double cost) {
+    int k = 0;
+    for (int j = 1; j <= SERVER_AUX; ++j)
+      if (load[j] < load[k]) k = j;
+    load[k] += cost;
+    if (!used[k]) {
+      used[k] = true;
+      // the stream starts after this tick's uploads and initialisation
+      if (hipStreamWaitEvent(sv[k], S->ev_start, 0) != hipSuccess) return -1;
     }
-    if (o.estimator == TLS_EST_SKETCH) {
-      // the compressed estimator: finished at set-up
-      e = launch_compressed_b(I + l.fits.off, l.fits.n, S->dD, S->dCounts, S->dDone, s);
-      if (e != hipSuccess) return e;
-      continue;
-    }
-    for (int k = 0; k < steps; ++k)
-      if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, precs, I + l.groups.off,
-                          l.groups.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,
-                          S->dCounts, S->dDone, nullptr, s) != TLS_OK)
-        return hipErrorUnknown;
-  }
-  // 2. tick_steps LSQR steps of every iterating fit (fits that finish on
-  // the way skip the remaining steps)
-  for (int k = 0; k < steps; ++k)
-    for (const Iter& it : iters) {
-      if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, precs, I + it.groups.off, it.groups.n,
-                          I + it.cols.off, it.cols.n, I + it.fits.off, it.fits.n, S->dD,
-                          S->dCounts, S->dDone, nullptr, s) != TLS_OK)
-        return hipErrorUnknown;
-    }
-  // 3. residual and results of the fits that finished in the previous tick
+    return k;
+  };
+  e = hipEventRecord(S->ev_start, s);
+  if (e != hipSuccess) return e;
+
+  // 1. residual and results of the fits that finished in the previous tick
   if (!finishing.empty()) {
     if (residual_class(I + fin_rblocks.off, fin_rblocks.n, I + fin_fits.off, fin_fits.n, fin_pmax,
                        S->dD, s) != TLS_OK)
@@ -374,25 +398,81 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
       e = hipMemcpyAsync(S->hRec.p, S->dRec.p, finishing.size() * sizeof(FitRec), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(S->hCoef.p, S->dCoef.p, coef_total * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(S->ev_fin, s);
+    if (e != hipSuccess) return e;
+  }
+
+  // 2. set-up and first LSQR steps of the new fits
+  for (const Setup& su : setups) {
+    const ClassLists& l = su.l;
+    const int si = pick(300.0 + 3.0 * su.pmax + steps * (15.0 + 0.02 * l.groups.n));
+    if (si < 0) return hipErrorUnknown;
+    const hipStream_t ss = sv[si];
+    if (setup_class(ctx, su.key, su.pmax, su.ldqmax, I, su.l, S->dD, o, ss) != TLS_OK)
+      return hipErrorUnknown;
+    if (mixed && o.estimator != TLS_EST_SKETCH) {
+      // each new fit's products: FP32 when its sketch factor allows it
+      // (mixed_path_of), else FP64; both LSQR variants then run over the lists
+      hipLaunchKernelGGL(mixed_dispatch_b_kernel, dim3(l.fits.n), dim3(256), 0, ss,
+                         I + l.fits.off, S->dD, 0, MIXED_TOL_F32, S->dCounts, 0);
+      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, ss, I + l.fits.off, S->dD);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (o.estimator == TLS_EST_SKETCH) {
+      // the compressed estimator: finished at set-up
+      e = launch_compressed_b(I + l.fits.off, l.fits.n, S->dD, S->dCounts, S->dDone, ss);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    for (int k = 0; k < steps; ++k)
+      if (lsqr_step_class(ctx, su.key.lgn, su.pmax, su.key.mlds != 0, k == 0, precs, I + l.groups.off,
+                          l.groups.n, I + l.cols.off, l.cols.n, I + l.fits.off, l.fits.n, S->dD,
+                          S->dCounts, S->dDone, nullptr, ss) != TLS_OK)
+        return hipErrorUnknown;
+  }
+  // 3. tick_steps LSQR steps of every iterating fit (fits that finish on
+  // the way skip the remaining steps)
+  for (const Iter& it : iters) {
+    const int si = pick(steps * (15.0 + 0.02 * it.groups.n));
+    if (si < 0) return hipErrorUnknown;
+    for (int k = 0; k < steps; ++k)
+      if (lsqr_step_class(ctx, it.lgn, it.pmax, it.mlds, false, precs, I + it.groups.off, it.groups.n,
+                          I + it.cols.off, it.cols.n, I + it.fits.off, it.fits.n, S->dD,
+                          S->dCounts, S->dDone, nullptr, sv[si]) != TLS_OK)
+        return hipErrorUnknown;
+  }
+  // the worker's stream waits for the others before the counters are read
+  for (int k = 1; k <= SERVER_AUX; ++k) {
+    if (!used[k]) continue;
+    e = hipEventRecord(S->ev_aux[k - 1], sv[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, S->ev_aux[k - 1], 0);
     if (e != hipSuccess) return e;
   }
   e = hipMemcpyAsync(S->hDone.p, S->dCounts, 4 * sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(S->hDone.p + 4, S->dDone, S->max_slots * sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
 
-  // results of the finishing fits
-  int64_t off = 0;
-  const auto now = Clock::now();
-  for (size_t k = 0; k < finishing.size(); ++k) {
-    Request* r = finishing[k];
-    r->coef.assign(S->hCoef.p + off, S->hCoef.p + off + r->pl.p);
-    off += r->pl.p;
-    record_result(S->hRec.p[k], r->pl, std::chrono::duration<double, std::milli>(now - r->t_submit).count(),
-                  &r->res);
-    r->status = record_status(S->hRec.p[k], r->coef.data(), r->pl.p);
+  // results of the finishing fits, delivered before the tick ends
+  if (!finishing.empty()) {
+    e = hipEventSynchronize(S->ev_fin);
+    if (e != hipSuccess) return e;
+    int64_t off = 0;
+    const auto now = Clock::now();
+    for (size_t k = 0; k < finishing.size(); ++k) {
+      Request* r = finishing[k];
+      r->coef.assign(S->hCoef.p + off, S->hCoef.p + off + r->pl.p);
+      off += r->pl.p;
+      record_result(S->hRec.p[k], r->pl,
+                    std::chrono::duration<double, std::milli>(now - r->t_submit).count(), &r->res);
+      r->status = record_status(S->hRec.p[k], r->coef.data(), r->pl.p);
+    }
+    deliver(S, finishing);
+    finishing.clear();  // handed over: no longer the worker's
   }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
   // fits that finished in this tick (setup's first step or an iteration)
   const int ndone = std::min(S->hDone.p[2], S->max_slots);
   for (int k = 0; k < ndone; ++k) {
@@ -438,18 +518,9 @@ void worker_main(tls_server* S) {
       fail_all(S, all, e == hipErrorOutOfMemory ? TLS_ENOMEM : TLS_EDEVICE);
       return;
     }
-    // hand over the finished requests, free their space
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      for (Request* r : finishing) {
-        S->alloc.release(r->off, r->bytes);
-        S->free_slots.push_back(r->slot);
-        S->slot_req[r->slot] = nullptr;
-        r->done = true;
-      }
-      S->completed += finishing.size();
       S->ticks += 1;
-      if (!finishing.empty()) S->cv_done.notify_all();
     }
     // new state: the fits done in this tick finish next tick
     std::vector<Request*> next_active;
@@ -543,6 +614,12 @@ tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
   S->budget = hbm_budget;
   S->max_slots = max_slots;
   hipError_t e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  for (int k = 0; k < SERVER_AUX && e == hipSuccess; ++k) {
+    e = hipStreamCreateWithFlags(&S->aux[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_aux[k], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_start, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_fin, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMalloc(&S->arena, hbm_budget);
   if (e == hipSuccess) e = hipMalloc(&S->dD, sizeof(FitDesc) * max_slots);
   if (e == hipSuccess) e = hipMalloc(&S->dCounts, 4 * sizeof(int));
@@ -554,6 +631,12 @@ tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
     if (S->dCounts) hipFree(S->dCounts);
     if (S->dDone) hipFree(S->dDone);
     S->hDone.release();
+    for (int k = 0; k < SERVER_AUX; ++k) {
+      if (S->aux[k]) hipStreamDestroy(S->aux[k]);
+      if (S->ev_aux[k]) hipEventDestroy(S->ev_aux[k]);
+    }
+    if (S->ev_start) hipEventDestroy(S->ev_start);
+    if (S->ev_fin) hipEventDestroy(S->ev_fin);
     if (S->stream) hipStreamDestroy(S->stream);
     delete S;
     return e == hipErrorOutOfMemory ? TLS_ENOMEM : TLS_EDEVICE;
@@ -612,6 +695,7 @@ void tls_server_destroy(tls_server* S) {
   if (S->worker.joinable()) S->worker.join();
   hipSetDevice(S->ctx->device);
   hipStreamSynchronize(S->stream);
+  for (int k = 0; k < SERVER_AUX; ++k) hipStreamSynchronize(S->aux[k]);
   for (auto& kv : S->reqs) delete kv.second;
   S->dItems.release();
   S->dCoef.release();
@@ -625,6 +709,12 @@ void tls_server_destroy(tls_server* S) {
   hipFree(S->dD);
   hipFree(S->dCounts);
   hipFree(S->dDone);
+  for (int k = 0; k < SERVER_AUX; ++k) {
+    hipStreamDestroy(S->aux[k]);
+    hipEventDestroy(S->ev_aux[k]);
+  }
+  hipEventDestroy(S->ev_start);
+  hipEventDestroy(S->ev_fin);
   hipStreamDestroy(S->stream);
   delete S;
 }
