@@ -451,10 +451,13 @@ tls_status tls_op_triinv(tls_ctx* ctx, const double* d_R, int32_t q, int32_t p, 
                          double* d_phi0, void* stream);
 
 /* The k x p JL map Pi (kind TLS_JL_*) from Philox streams of (seed, fit) and
- * Omega = M Pi^T (p x k column-major) for upper-triangular d_M (p x p
- * row-major).  d_Pi may be NULL. */
-tls_status tls_op_jl(tls_ctx* ctx, const double* d_M, int32_t p, int32_t k, int32_t kind,
-                     uint64_t seed, uint32_t fit, double* d_Pi, double* d_omega, void* stream);
+ * Omega = R[:p,:p]^{-1} Pi^T (p x k column-major; eq. (glev): the scores are
+ * the squared row norms of X Omega) for the upper-triangular q x q row-major
+ * d_R (q >= p; entries below the diagonal are not read), by back
+ * substitution.  d_Pi may be NULL.  TLS_EUNSUPPORTED for p > 1024. */
+tls_status tls_op_jl(tls_ctx* ctx, const double* d_R, int32_t q, int32_t p, int32_t k,
+                     int32_t kind, uint64_t seed, uint32_t fit, double* d_Pi, double* d_omega,
+                     void* stream);
 
 /* count Philox4x32-10 uniforms of stream `rng_stream`, fit `fit`, seed
  * `seed`, draws start .. start+count-1, into d_out (device FP64). */

@@ -184,7 +184,7 @@ _SIGS = {
                              _u32, _vp]),
     "tls_op_qr": (_i32, [_ctxp, _vp, _i32, _i32, _i32, _vp, _c.POINTER(_i32), _vp]),
     "tls_op_triinv": (_i32, [_ctxp, _vp, _i32, _i32, _vp, _vp, _vp]),
-    "tls_op_jl": (_i32, [_ctxp, _vp, _i32, _i32, _i32, _u64, _u32, _vp, _vp, _vp]),
+    "tls_op_jl": (_i32, [_ctxp, _vp, _i32, _i32, _i32, _i32, _u64, _u32, _vp, _vp, _vp]),
     "tls_op_philox": (_i32, [_ctxp, _u64, _u32, _u32, _u64, _i64, _vp, _vp]),
 }
 
@@ -460,9 +460,9 @@ class Context:
     def op_triinv(self, d_R, q, p, d_M, d_phi0=None, stream=None):
         return lib.tls_op_triinv(self._h, _ptr(d_R), q, p, _ptr(d_M), _ptr(d_phi0), _stream(stream))
 
-    def op_jl(self, d_M, p, k, kind, seed, fit, d_Pi, d_omega, stream=None):
-        return lib.tls_op_jl(self._h, _ptr(d_M), p, k, kind, seed, fit, _ptr(d_Pi), _ptr(d_omega),
-                             _stream(stream))
+    def op_jl(self, d_R, q, p, k, kind, seed, fit, d_Pi, d_omega, stream=None):
+        return lib.tls_op_jl(self._h, _ptr(d_R), q, p, k, kind, seed, fit, _ptr(d_Pi),
+                             _ptr(d_omega), _stream(stream))
 
     def op_philox(self, seed, rng_stream, fit, start, count, d_out, stream=None):
         return lib.tls_op_philox(self._h, seed, rng_stream, fit, start, count, _ptr(d_out),

@@ -224,8 +224,6 @@ void fill_desc(const Plan& pl, const FitBufs& b, const double* y, uint32_t fit, 
   d->R = b.R;
   d->M = b.M;
   d->Mt = b.Mt;
-  d->M0 = b.M0;
-  d->Mt0 = b.Mt0;
   d->Pi = b.Pi;
   d->Om = b.Om;
   d->Omhat = b.Omhat;
@@ -336,7 +334,6 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
   TLS_CHECK(launch_gather_b(1, L_(rows1), D, seed, s));
   if (l.fits1.n > 0) {
     TLS_CHECK(launch_qr_b(1, k.qt, L_(tiles1), nullptr, 0, nullptr, 0, L_(fits1), ldqmax, D, s));
-    TLS_CHECK(launch_triinv_b(1, k.pt, L_(fits1), pmax, D, s));
     TLS_CHECK(launch_jl_b(L_(jl), D, o.jl_kind, pmax, seed, s));
     TLS_CHECK(launch_small_rfft_b(cprec, k.lgn, 0, L_(jl), D, ctx->tw, s));
     TLS_CHECK(launch_scores_b(cprec, k.lgn, L_(blocks1), D, ctx->tw, s));
@@ -344,7 +341,7 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
     TLS_CHECK(launch_gather_b(2, L_(rows2), D, seed, s));
   }
   TLS_CHECK(launch_qr_b(2, k.qt, L_(tiles2), L_(rowtiles2), L_(trmm2), L_(fits), ldqmax, D, s));
-  TLS_CHECK(launch_triinv_b(2, k.pt, L_(fits), pmax, D, s));
+  TLS_CHECK(launch_triinv_b(k.pt, L_(fits), pmax, D, s));
   if (l.fits.n > 0) {
     hipLaunchKernelGGL(post_qr_b_kernel, dim3(l.fits.n), dim3(64), 0, s, I + l.fits.off, D,
                        o.warm_start || o.estimator == TLS_EST_SKETCH ? 1 : 0, mixed ? 1 : 0);

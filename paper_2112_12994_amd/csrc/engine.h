@@ -63,7 +63,7 @@ struct FitBufs {
   double* A;        // crows x ldq
   double* G;        // ldq^2 + 2 q^2
   double *R1, *R2, *R;
-  double *M, *Mt, *M0, *Mt0;
+  double *M, *Mt;
   double *Pi, *Om;
   void* Omhat;
   void* Vhat;
@@ -310,8 +310,6 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->R = a.take<double>(static_cast<size_t>(pl.q) * pl.q);
   b->M = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
   b->Mt = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
-  b->M0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
-  b->Mt0 = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
   b->Pi = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
   b->Om = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
   b->Omhat = a.take<char>(static_cast<size_t>(pl.k) * N * 2 * es);

@@ -53,8 +53,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       const int levels = o.sketch == TLS_SKETCH_RH ? rh_levels(pl.m, pl.c) : 1;
       for (int lev = levels - 1; lev >= 0; --lev) {
         TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 1, b.R, b.G, b.R1, b.R2, b.status + 2, s));
-        TLS_CHECK(launch_triinv(b.R, q, p, b.M0, b.Mt0, nullptr, b.status + 3, s));
-        TLS_CHECK(launch_jl_omega(b.M0, p, pl.k, o.jl_kind, b.Pi, b.Om, seed, fit, s));
+        TLS_CHECK(launch_jl_solve(b.R, q, p, pl.k, o.jl_kind, b.Pi, b.Om, seed, fit, s));
         TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.Om, p, p, pl.k, invB, b.Omhat, ctx->tw, nullptr,
                                     s));
         TLS_CHECK(launch_scores(prec, pl.lgn, b.Yhat, b.Omhat, pl.k, b.u, ctx->tw, pl.m, p, pl.L,
@@ -763,12 +762,14 @@ tls_status tls_op_triinv(tls_ctx* ctx, const double* d_R, int32_t q, int32_t p, 
   return TLS_OK;
 }
 
-tls_status tls_op_jl(tls_ctx* ctx, const double* d_M, int32_t p, int32_t k, int32_t kind,
-                     uint64_t seed, uint32_t fit, double* d_Pi, double* d_omega, void* stream) {
-  if (!ctx || !d_M || !d_omega || p < 1 || k < 1 || (kind != 0 && kind != 1)) return TLS_EINVAL;
+tls_status tls_op_jl(tls_ctx* ctx, const double* d_R, int32_t q, int32_t p, int32_t k,
+                     int32_t kind, uint64_t seed, uint32_t fit, double* d_Pi, double* d_omega,
+                     void* stream) {
+  if (!ctx || !d_R || !d_omega || p < 1 || q < p || k < 1 || (kind != 0 && kind != 1))
+    return TLS_EINVAL;
   if (p > P_MAX) return TLS_EUNSUPPORTED;
   hipSetDevice(ctx->device);
-  TLS_CHECK(launch_jl_omega(d_M, p, k, kind, d_Pi, d_omega, seed, fit, pick_stream(ctx, stream)));
+  TLS_CHECK(launch_jl_solve(d_R, q, p, k, kind, d_Pi, d_omega, seed, fit, pick_stream(ctx, stream)));
   return TLS_OK;
 }
 

@@ -71,8 +71,10 @@ hipError_t launch_sample(int prec, const void* scores, int64_t m, const double* 
 hipError_t launch_rh_mask(int prec, void* scores, int64_t m, int level, uint64_t seed,
                           uint32_t fit, hipStream_t st);
 size_t sample_work_doubles(int64_t m);
-hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, double* Om,
-                           uint64_t seed, uint32_t fit, hipStream_t st);
+// Pi (k x p JL map) and Omega = R[:p,:p]^{-1} Pi^T (p x k, column-major) for
+// upper-triangular R (row-major, leading dimension ldr >= p), p <= 1024.
+hipError_t launch_jl_solve(const double* R, int ldr, int p, int k, int kind, double* Pi,
+                           double* Om, uint64_t seed, uint32_t fit, hipStream_t st);
 
 // QR of the sketch and triangular helpers
 // rank_cols: leading columns whose breakdown or tiny pivot means rank
@@ -144,7 +146,7 @@ struct FitDesc {
   void* Yhat;
   void* Yhat64;
   void* u;
-  double *partial, *g, *A, *G, *R1, *R2, *R, *M, *Mt, *M0, *Mt0, *Pi, *Om;
+  double *partial, *g, *A, *G, *R1, *R2, *R, *M, *Mt, *Pi, *Om;
   void* Omhat;
   void* Vhat;
   void* Vhat32;
@@ -201,9 +203,9 @@ hipError_t launch_jl_b(const Item* items, int nitems, const FitDesc* D, int kind
 hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const Item* rowtiles,
                        int nrowtiles, const Item* rows, int nrows, const Item* fits, int nfits,
                        int ldqmax, const FitDesc* D, hipStream_t st);
-// stage 1: M0, Mt0 (status[3]); stage 2: M, Mt, phi0 (status[1]), |R_ii| range.
-hipError_t launch_triinv_b(int stage, int pt, const Item* fits, int nfits, int pmax,
-                           const FitDesc* D, hipStream_t st);
+// M, Mt, phi0 of the final factor (rank bits to status[1]), |R_ii| range.
+hipError_t launch_triinv_b(int pt, const Item* fits, int nfits, int pmax, const FitDesc* D,
+                           hipStream_t st);
 // One workgroup per item of `fits` (item.fit indexes D).  counts[0] += 1 for
 // each fit that finishes (LSQR) or is finished (refinement outer step);
 // counts[1] += 1 for each fit whose inner CG solve is finished; the LSQR step

@@ -1510,29 +1510,23 @@ __device__ __forceinline__ void diag_range(const FitDesc& d) {
 
 template <int QT>
 __global__ __launch_bounds__(256) void triinv_b_kernel(const Item* __restrict__ items,
-                                                       const FitDesc* __restrict__ D, int stage) {
+                                                       const FitDesc* __restrict__ D) {
   const FitDesc& d = D[items[blockIdx.x].fit];
-  double* M = stage == 1 ? d.M0 : d.M;
-  double* Mt = stage == 1 ? d.Mt0 : d.Mt;
-  triinv_reg_body<QT>(d.R, d.q, d.p, M, d.p, Mt);
+  triinv_reg_body<QT>(d.R, d.q, d.p, d.M, d.p, d.Mt);
   __syncthreads();
-  triinv_finish_body<256>(d.R, d.q, d.p, M, stage == 1 ? nullptr : d.phi0,
-                          stage == 1 ? d.status + 3 : d.status + 1);
-  if (stage == 2) diag_range(d);
+  triinv_finish_body<256>(d.R, d.q, d.p, d.M, d.phi0, d.status + 1);
+  diag_range(d);
 }
 
 // 128 < p <= 224: the 32 x 32 thread grid
 template <int QT>
 __global__ __launch_bounds__(1024) void triinv_b32_kernel(const Item* __restrict__ items,
-                                                          const FitDesc* __restrict__ D, int stage) {
+                                                          const FitDesc* __restrict__ D) {
   const FitDesc& d = D[items[blockIdx.x].fit];
-  double* M = stage == 1 ? d.M0 : d.M;
-  double* Mt = stage == 1 ? d.Mt0 : d.Mt;
-  triinv_reg32_body<QT>(d.R, d.q, d.p, M, d.p, Mt);
+  triinv_reg32_body<QT>(d.R, d.q, d.p, d.M, d.p, d.Mt);
   __syncthreads();
-  triinv_finish_body<1024>(d.R, d.q, d.p, M, stage == 1 ? nullptr : d.phi0,
-                           stage == 1 ? d.status + 3 : d.status + 1);
-  if (stage == 2) diag_range(d);
+  triinv_finish_body<1024>(d.R, d.q, d.p, d.M, d.phi0, d.status + 1);
+  diag_range(d);
 }
 
 // Blocked Cholesky and inverse of the fits of a launch with q (or p) above
@@ -1590,59 +1584,39 @@ void chol_blk_b(const Item* fits, int nfits, int ldqmax, int sweep, const FitDes
   }
 }
 
-__device__ __forceinline__ void inv_target(const FitDesc& d, int stage, double** M, double** Mt,
-                                           double** phi0, int** status) {
-  *M = stage == 1 ? d.M0 : d.M;
-  *Mt = stage == 1 ? d.Mt0 : d.Mt;
-  *phi0 = stage == 1 ? nullptr : d.phi0;
-  *status = stage == 1 ? d.status + 3 : d.status + 1;
-}
-
 __global__ __launch_bounds__(256) void inv_blk_diag_b_kernel(const Item* __restrict__ items,
                                                              const FitDesc* __restrict__ D,
-                                                             int stage, int per) {
+                                                             int per) {
   const FitDesc& d = D[items[blockIdx.x / per].fit];
   const int b = blockIdx.x % per;
   if (b >= (d.p + NBK - 1) / NBK) return;
-  double *M, *Mt, *phi0;
-  int* status;
-  inv_target(d, stage, &M, &Mt, &phi0, &status);
-  inv_blk_diag_body(d.R, d.q, d.p, M, Mt, b);
+  inv_blk_diag_body(d.R, d.q, d.p, d.M, d.Mt, b);
 }
 
 __global__ __launch_bounds__(256) void inv_blk_off_b_kernel(const Item* __restrict__ items,
                                                             const FitDesc* __restrict__ D,
-                                                            int stage, int dist, int per) {
+                                                            int dist, int per) {
   const FitDesc& d = D[items[blockIdx.x / per].fit];
   const int i = blockIdx.x % per;
   if (i + dist >= (d.p + NBK - 1) / NBK) return;
-  double *M, *Mt, *phi0;
-  int* status;
-  inv_target(d, stage, &M, &Mt, &phi0, &status);
-  inv_blk_off_body(d.R, d.q, d.p, M, Mt, dist, i);
+  inv_blk_off_body(d.R, d.q, d.p, d.M, d.Mt, dist, i);
 }
 
 __global__ __launch_bounds__(256) void inv_blk_finish_b_kernel(const Item* __restrict__ items,
                                                                const FitDesc* __restrict__ D,
-                                                               int stage, int per) {
+                                                               int per) {
   const FitDesc& d = D[items[blockIdx.x / per].fit];
-  double *M, *Mt, *phi0;
-  int* status;
-  inv_target(d, stage, &M, &Mt, &phi0, &status);
-  inv_blk_finish_body(d.R, d.q, d.p, M, Mt, phi0, status, stage == 2 ? d.dminmax : nullptr,
-                      blockIdx.x % per);
+  inv_blk_finish_body(d.R, d.q, d.p, d.M, d.Mt, d.phi0, d.status + 1, d.dminmax, blockIdx.x % per);
 }
 
-void inv_blk_b(int stage, const Item* fits, int nfits, int pmax, const FitDesc* D,
-               hipStream_t st) {
+void inv_blk_b(const Item* fits, int nfits, int pmax, const FitDesc* D, hipStream_t st) {
   const int nbp = (pmax + NBK - 1) / NBK;
-  hipLaunchKernelGGL(inv_blk_diag_b_kernel, dim3(nfits * nbp), dim3(256), 0, st, fits, D, stage, nbp);
+  hipLaunchKernelGGL(inv_blk_diag_b_kernel, dim3(nfits * nbp), dim3(256), 0, st, fits, D, nbp);
   for (int dist = 1; dist < nbp; ++dist)
     hipLaunchKernelGGL(inv_blk_off_b_kernel, dim3(nfits * (nbp - dist)), dim3(256), 0, st, fits, D,
-                       stage, dist, nbp - dist);
+                       dist, nbp - dist);
   const int per = nbp * nbp + nbp;
-  hipLaunchKernelGGL(inv_blk_finish_b_kernel, dim3(nfits * per), dim3(256), 0, st, fits, D, stage,
-                     per);
+  hipLaunchKernelGGL(inv_blk_finish_b_kernel, dim3(nfits * per), dim3(256), 0, st, fits, D, per);
 }
 
 template <int QT>
@@ -1675,17 +1649,16 @@ hipError_t qr_b_qt(int stage, const Item* tiles, int ntiles, const Item* rowtile
 }
 
 template <int QT>
-hipError_t triinv_b_qt(int stage, const Item* fits, int nfits, int pmax, const FitDesc* D,
-                       hipStream_t st) {
+hipError_t triinv_b_qt(const Item* fits, int nfits, int pmax, const FitDesc* D, hipStream_t st) {
   if constexpr (QT > 100) {
     const size_t shm = static_cast<size_t>(pmax) * 33 * sizeof(double);
     hipLaunchKernelGGL((triinv_b32_kernel<(QT > 100 ? QT - 100 : 1)>), dim3(nfits), dim3(1024), shm, st,
-                       fits, D, stage);
+                       fits, D);
   } else if constexpr (QT > 0) {
     const size_t shm = static_cast<size_t>(pmax) * (pmax + 1) * sizeof(double);
-    hipLaunchKernelGGL((triinv_b_kernel<QT>), dim3(nfits), dim3(256), shm, st, fits, D, stage);
+    hipLaunchKernelGGL((triinv_b_kernel<QT>), dim3(nfits), dim3(256), shm, st, fits, D);
   } else {
-    inv_blk_b(stage, fits, nfits, pmax, D, st);
+    inv_blk_b(fits, nfits, pmax, D, st);
   }
   return hipGetLastError();
 }
@@ -1715,22 +1688,22 @@ hipError_t launch_qr_b(int stage, int qt, const Item* tiles, int ntiles, const I
 }
 
 // pt = reg_tiles(p) of every fit of the launch.
-hipError_t launch_triinv_b(int stage, int pt, const Item* fits, int nfits, int pmax,
-                           const FitDesc* D, hipStream_t st) {
+hipError_t launch_triinv_b(int pt, const Item* fits, int nfits, int pmax, const FitDesc* D,
+                           hipStream_t st) {
   if (nfits < 1) return hipSuccess;
   switch (pt) {
-    case 0: return triinv_b_qt<0>(stage, fits, nfits, pmax, D, st);
-    case 1: return triinv_b_qt<1>(stage, fits, nfits, pmax, D, st);
-    case 2: return triinv_b_qt<2>(stage, fits, nfits, pmax, D, st);
-    case 3: return triinv_b_qt<3>(stage, fits, nfits, pmax, D, st);
-    case 4: return triinv_b_qt<4>(stage, fits, nfits, pmax, D, st);
-    case 5: return triinv_b_qt<5>(stage, fits, nfits, pmax, D, st);
-    case 6: return triinv_b_qt<6>(stage, fits, nfits, pmax, D, st);
-    case 7: return triinv_b_qt<7>(stage, fits, nfits, pmax, D, st);
-    case 8: return triinv_b_qt<8>(stage, fits, nfits, pmax, D, st);
-    case 105: return triinv_b_qt<105>(stage, fits, nfits, pmax, D, st);
-    case 106: return triinv_b_qt<106>(stage, fits, nfits, pmax, D, st);
-    case 107: return triinv_b_qt<107>(stage, fits, nfits, pmax, D, st);
+    case 0: return triinv_b_qt<0>(fits, nfits, pmax, D, st);
+    case 1: return triinv_b_qt<1>(fits, nfits, pmax, D, st);
+    case 2: return triinv_b_qt<2>(fits, nfits, pmax, D, st);
+    case 3: return triinv_b_qt<3>(fits, nfits, pmax, D, st);
+    case 4: return triinv_b_qt<4>(fits, nfits, pmax, D, st);
+    case 5: return triinv_b_qt<5>(fits, nfits, pmax, D, st);
+    case 6: return triinv_b_qt<6>(fits, nfits, pmax, D, st);
+    case 7: return triinv_b_qt<7>(fits, nfits, pmax, D, st);
+    case 8: return triinv_b_qt<8>(fits, nfits, pmax, D, st);
+    case 105: return triinv_b_qt<105>(fits, nfits, pmax, D, st);
+    case 106: return triinv_b_qt<106>(fits, nfits, pmax, D, st);
+    case 107: return triinv_b_qt<107>(fits, nfits, pmax, D, st);
     default: return hipErrorInvalidValue;
   }
 }

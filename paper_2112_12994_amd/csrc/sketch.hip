@@ -249,61 +249,127 @@ __global__ __launch_bounds__(256) void rh_mask_kernel(T* __restrict__ s, int64_t
   if (!(u < ldexp(1.0, -level))) s[r] = T(0);
 }
 
-// Pi (k x p) and Omega = M Pi^T (p x k, column-major).  kind 0: subsampled
-// randomized Hadamard map: Pi[q][j] = d_j (-1)^popcount(r_q & j) / sqrt(k)
-// with d_j = +-1 from the sign stream and r_q uniform in [0, P); kind 1:
-// Gaussian N(0, 1/k) entries (Box-Muller).  M is upper triangular, row-major (p x p).
-template <int NT>
-__device__ __forceinline__ void jl_omega_body(const double* __restrict__ M, int p, int k,
-                                                      int kind, double* __restrict__ Pi,
-                                                      double* __restrict__ Om, uint64_t seed,
-                                                      uint32_t fit, int q) {
-  extern __shared__ double prow[];
-  int P = 1;
-  while (P < p) P <<= 1;
-  const double invsk = 1.0 / sqrt(static_cast<double>(k));
-  uint32_t rq = 0;
+// Entry j of row q of the k x p JL map Pi.  kind 0: subsampled randomized
+// Hadamard map, Pi[q][j] = d_j (-1)^popcount(r_q & j) / sqrt(k) with
+// d_j = +-1 from the sign stream and r_q uniform in [0, P), P the power of
+// two >= p; kind 1: Gaussian N(0, 1/k) entries (Box-Muller).
+struct JlRow {
+  int kind;
+  uint32_t rq;
+  double invsk;
+};
+
+__device__ __forceinline__ JlRow jl_row(int p, int k, int kind, uint64_t seed, uint32_t fit,
+                                        int q) {
+  JlRow g{kind, 0u, 1.0 / sqrt(static_cast<double>(k))};
   if (kind == 0) {
+    int P = 1;
+    while (P < p) P <<= 1;
     const double ur = philox_u01(static_cast<uint64_t>(q), RNG_SRHT_ROWS, fit, seed);
     int64_t r = static_cast<int64_t>(floor(ur * static_cast<double>(P)));
     if (r > P - 1) r = P - 1;
-    rq = static_cast<uint32_t>(r);
+    g.rq = static_cast<uint32_t>(r);
   }
-  for (int j = threadIdx.x; j < p; j += NT) {
-    double val;
-    if (kind == 0) {
-      const double us = philox_u01(static_cast<uint64_t>(j), RNG_SRHT_SIGNS, fit, seed);
-      const double d = us < 0.5 ? 1.0 : -1.0;
-      const double h = (__popc(rq & static_cast<uint32_t>(j)) & 1) ? -1.0 : 1.0;
-      val = d * h * invsk;
-    } else {
-      const uint64_t e = static_cast<uint64_t>(q) * p + j;
-      const double u1 = philox_u01(2 * e, RNG_GAUSS, fit, seed);
-      const double u2 = philox_u01(2 * e + 1, RNG_GAUSS, fit, seed);
-      val = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2) * invsk;
+  return g;
+}
+
+__device__ __forceinline__ double jl_entry(const JlRow& g, int p, int q, int j, uint64_t seed,
+                                           uint32_t fit) {
+  if (g.kind == 0) {
+    const double us = philox_u01(static_cast<uint64_t>(j), RNG_SRHT_SIGNS, fit, seed);
+    const double d = us < 0.5 ? 1.0 : -1.0;
+    const double h = (__popc(g.rq & static_cast<uint32_t>(j)) & 1) ? -1.0 : 1.0;
+    return d * h * g.invsk;
+  }
+  const uint64_t e = static_cast<uint64_t>(q) * p + j;
+  const double u1 = philox_u01(2 * e, RNG_GAUSS, fit, seed);
+  const double u2 = philox_u01(2 * e + 1, RNG_GAUSS, fit, seed);
+  return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2) * g.invsk;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Row q of Pi and column q of Omega = R[:p,:p]^{-1} Pi^T (p x k,
+// column-major; R upper triangular, row-major with leading dimension ldr) by
+// back substitution, one wavefront per column: lane l holds b_j for
+// j = l + 64 t (t < T), step s takes x_s = b_s (1 / R_ss) from the lane
+// holding b_s (a register read with a uniform lane index) and updates the
+// rows above it with column s of R.  The column loads and the reciprocals
+// do not depend on the solution, so each block of U columns is prepared
+// while the previous block is solved; a step's dependent chain is a
+// multiply, the register read and an FMA.
+template <int T, int U>
+__device__ __forceinline__ void jl_solve_body(const double* __restrict__ R, int ldr, int p, int k,
+                                              int kind, double* __restrict__ Pi,
+                                              double* __restrict__ Om, uint64_t seed,
+                                              uint32_t fit, int q) {
+  const int lane = static_cast<int>(threadIdx.x);
+  const JlRow g = jl_row(p, k, kind, seed, fit, q);
+  double b[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int j = lane + 64 * t;
+    b[t] = j < p ? jl_entry(g, p, q, j, seed, fit) : 0.0;
+    if (Pi && j < p) Pi[static_cast<size_t>(q) * p + j] = b[t];
+  }
+  // column s of R above the diagonal (zero elsewhere) and R_ss
+  auto load = [&](int s0, double (&rc)[U][T], double (&dg)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = s0 - u;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int j = lane + 64 * t;
+        rc[u][t] = (s >= 0 && j < s) ? R[static_cast<size_t>(j) * ldr + s] : 0.0;
+      }
+      dg[u] = s >= 0 ? R[static_cast<size_t>(s) * ldr + s] : 1.0;
     }
-    prow[j] = val;
-    if (Pi) Pi[static_cast<size_t>(q) * p + j] = val;
+#pragma unroll
+    for (int u = 0; u < U; ++u) dg[u] = 1.0 / dg[u];
+  };
+  auto solve = [&](int s0, const double (&rc)[U][T], const double (&dg)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = s0 - u;
+      if (s < 0) break;
+      const int ts = s >> 6;
+      double bs = b[0];
+#pragma unroll
+      for (int t = 1; t < T; ++t)
+        if (t == ts) bs = b[t];
+      const double xs = readlane_f64(bs * dg[u], s & 63);
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        if (t == ts && lane == (s & 63)) b[t] = xs;
+        b[t] = fma(-rc[u][t], xs, b[t]);
+      }
+    }
+  };
+  double ra[U][T], rb[U][T], da[U], db[U];
+  load(p - 1, ra, da);
+  for (int s0 = p - 1; s0 >= 0; s0 -= 2 * U) {
+    load(s0 - U, rb, db);
+    solve(s0, ra, da);
+    load(s0 - 2 * U, ra, da);
+    solve(s0 - U, rb, db);
   }
-  __syncthreads();
-  // Om[:, q] = M prow: one wavefront per row, lanes over its columns (the
-  // row's result does not depend on which wavefront computes it)
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i = wid; i < p; i += NT / 64) {
-    const double* mi = M + static_cast<size_t>(i) * p;
-    double acc = 0.0;
-    for (int j = i + lane; j < p; j += 64) acc += mi[j] * prow[j];
-    acc = wave_sum(acc);
-    if (lane == 0) Om[static_cast<size_t>(q) * p + i] = acc;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int j = lane + 64 * t;
+    if (j < p) Om[static_cast<size_t>(q) * p + j] = b[t];
   }
 }
 
-template <int NT>
-__global__ __launch_bounds__(NT) void jl_omega_kernel(const double* __restrict__ M, int p, int k,
-                                                      int kind, double* __restrict__ Pi,
+template <int T, int U>
+__global__ __launch_bounds__(64) void jl_solve_kernel(const double* __restrict__ R, int ldr, int p,
+                                                      int k, int kind, double* __restrict__ Pi,
                                                       double* __restrict__ Om, uint64_t seed,
                                                       uint32_t fit) {
-  jl_omega_body<NT>(M, p, k, kind, Pi, Om, seed, fit, blockIdx.x);
+  jl_solve_body<T, U>(R, ldr, p, k, kind, Pi, Om, seed, fit, blockIdx.x);
 }
 
 }  // namespace
@@ -371,11 +437,23 @@ hipError_t launch_sample(int prec, const void* scores, int64_t m, const double* 
   return hipGetLastError();
 }
 
-hipError_t launch_jl_omega(const double* M, int p, int k, int kind, double* Pi, double* Om,
-                           uint64_t seed, uint32_t fit, hipStream_t st) {
-  if (p < 1 || k < 1 || p > 8192) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((jl_omega_kernel<1024>), dim3(k), dim3(1024), p * sizeof(double), st, M, p, k,
-                     kind, Pi, Om, seed, fit);
+hipError_t launch_jl_solve(const double* R, int ldr, int p, int k, int kind, double* Pi,
+                           double* Om, uint64_t seed, uint32_t fit, hipStream_t st) {
+  if (p < 1 || k < 1 || p > 1024 || ldr < p) return hipErrorInvalidValue;
+#define TLS_JL(T, U)                                                                             \
+  hipLaunchKernelGGL((jl_solve_kernel<T, U>), dim3(k), dim3(64), 0, st, R, ldr, p, k, kind, Pi, \
+                     Om, seed, fit)
+  if (p <= 64)
+    TLS_JL(1, 8);
+  else if (p <= 128)
+    TLS_JL(2, 8);
+  else if (p <= 256)
+    TLS_JL(4, 4);
+  else if (p <= 512)
+    TLS_JL(8, 4);
+  else
+    TLS_JL(16, 2);
+#undef TLS_JL
   return hipGetLastError();
 }
 
@@ -420,12 +498,15 @@ __global__ __launch_bounds__(64) void draw_b_kernel(const Item* __restrict__ ite
                d.scale, seed, d.fit, it.idx);
 }
 
-__global__ __launch_bounds__(256) void jl_b_kernel(const Item* __restrict__ items,
-                                                   const FitDesc* __restrict__ D, int kind,
-                                                   uint64_t seed) {
+// Omega of the stage-1 factor (in R after the stage-1 sweep), one
+// wavefront per (fit, JL column) item.
+template <int T, int U>
+__global__ __launch_bounds__(64) void jl_b_kernel(const Item* __restrict__ items,
+                                                  const FitDesc* __restrict__ D, int kind,
+                                                  uint64_t seed) {
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
-  jl_omega_body<256>(d.M0, d.p, d.k, kind, d.Pi, d.Om, seed, d.fit, it.idx);
+  jl_solve_body<T, U>(d.R, d.q, d.p, d.k, kind, d.Pi, d.Om, seed, d.fit, it.idx);
 }
 
 }  // namespace
@@ -461,8 +542,20 @@ hipError_t launch_sample_b(int prec, const Item* chunk_items, int nchunk_items,
 hipError_t launch_jl_b(const Item* items, int nitems, const FitDesc* D, int kind, int pmax,
                        uint64_t seed, hipStream_t st) {
   if (nitems < 1) return hipSuccess;
-  hipLaunchKernelGGL(jl_b_kernel, dim3(nitems), dim3(256), pmax * sizeof(double), st, items, D, kind,
-                     seed);
+  if (pmax > 1024) return hipErrorInvalidValue;
+#define TLS_JL_B(T, U)                                                                       \
+  hipLaunchKernelGGL((jl_b_kernel<T, U>), dim3(nitems), dim3(64), 0, st, items, D, kind, seed)
+  if (pmax <= 64)
+    TLS_JL_B(1, 8);
+  else if (pmax <= 128)
+    TLS_JL_B(2, 8);
+  else if (pmax <= 256)
+    TLS_JL_B(4, 4);
+  else if (pmax <= 512)
+    TLS_JL_B(8, 4);
+  else
+    TLS_JL_B(16, 2);
+#undef TLS_JL_B
   return hipGetLastError();
 }
 

@@ -332,17 +332,23 @@ def test_triinv(ctx, p):
 
 
 @pytest.mark.parametrize("kind", [0, 1])
-@pytest.mark.parametrize("p,k", [(5, 8), (100, 8), (37, 3)])
-def test_jl_map(ctx, kind, p, k):
+@pytest.mark.parametrize("p,k,extra", [(5, 8, 1), (100, 8, 1), (37, 3, 4), (64, 8, 0),
+                                       (200, 8, 1), (300, 5, 3), (700, 8, 1)])
+def test_jl_map(ctx, kind, p, k, extra):
+    """Pi from the Philox streams, and Omega = R[:p,:p]^{-1} Pi^T by back
+    substitution against a LAPACK triangular solve; R has q = p + extra
+    columns and NaN below its diagonal, which must not be read."""
     c = capi()
     torch, dev = torch_dev()
-    say("jl", kind, p, k)
-    rng = np.random.default_rng(15)
-    M = np.triu(rng.standard_normal((p, p))) + 3 * np.eye(p)
+    say("jl", kind, p, k, extra)
+    rng = np.random.default_rng(15 + p)
+    q = p + extra
+    R = np.triu(rng.standard_normal((q, q))) / np.sqrt(q) + 3 * np.eye(q)
+    R[np.tril_indices(q, -1)] = np.nan
     seed, fit = 77, 5
     dPi = torch.zeros(k * p, dtype=torch.float64, device=dev)
     dOm = torch.zeros(k * p, dtype=torch.float64, device=dev)
-    assert ctx.op_jl(to_dev(M.ravel()), p, k, kind, seed, fit, dPi, dOm) == c.TLS_OK
+    assert ctx.op_jl(to_dev(R.ravel()), q, p, k, kind, seed, fit, dPi, dOm) == c.TLS_OK
     Pi = to_np(dPi).reshape(k, p)
     P = 1 << max(0, math.ceil(math.log2(p)))
     if kind == 0:
@@ -352,5 +358,9 @@ def test_jl_map(ctx, kind, p, k):
     else:
         ref = oracle.philox_normal(k * p, c.RNG_GAUSS, fit, seed).reshape(k, p) / np.sqrt(k)
         assert np.allclose(Pi, ref, rtol=1e-13, atol=1e-15)
+    Ru = np.triu(np.nan_to_num(R[:p, :p]))
+    want = oracle.jl_omega(Ru, Pi)
     Om = to_np(dOm).reshape(k, p).T
-    assert np.allclose(Om, M @ Pi.T, rtol=1e-12, atol=1e-13 * np.abs(M @ Pi.T).max())
+    kap = oracle.kappa(Ru)
+    assert np.isfinite(Om).all()
+    assert np.abs(Om - want).max() <= 4 * p * 2.0 ** -53 * kap * np.abs(want).max()
