@@ -99,7 +99,9 @@ typedef struct tls_options {
   int32_t max_refine;  /* mixed precision: outer FP64 refinement steps for fits too
                           ill-conditioned for FP32 products alone (default 0: those fits
                           run FP64 LSQR; see tls_result.mixed_path) */
-  int32_t profile;     /* 1: time every Toeplitz pass with HIP events (tls_result.pass_ms) */
+  int32_t profile;     /* 1: time every Toeplitz pass with HIP events (tls_result.pass_ms);
+                          batched calls then run their launch classes one at a time, so
+                          each launch's time is not shared with another class's kernels */
   uint64_t seed;       /* random seed (default 0) */
   uint64_t request_id; /* selects the random streams of one fit (default 0) */
   int32_t no_graph;    /* batched calls: 1 launches every step directly; 0 (default) captures
@@ -141,9 +143,10 @@ typedef struct tls_result {
   int32_t pass_worked; /* profile = 1: how many of them did work */
   int32_t pass_kind;   /* which pass the three fields above cover: 0 the fused FP64 LSQR
                           pass, 1 the FP32 normal-equation pass of the mixed refinement,
-                          2 the fused LSQR pass with FP32 products (mixed, kappa_est <= 1e3).
-                          A mixed single fit whose FP64 LSQR finish ran reports whichever
-                          of the two took more device time; batched mixed fits report 2 */
+                          2 the fused LSQR pass with FP32 products (mixed_path 1).  A mixed
+                          single fit reports the pass of its path (with refinement and an
+                          FP64 finish, whichever took more device time); batched mixed
+                          calls time the launches of both product precisions and report 2 */
   int32_t mixed_path;  /* mixed precision: the path the fit took, chosen from
                           kappa_F = ||R||_F ||R^{-1}||_F of the sketch factor (>= kappa(R)):
                           1 LSQR with FP32 products (FP32 spectra, u and v's spectrum) and

@@ -184,6 +184,12 @@ ClassLists build_lists(std::vector<Item>& items, const std::vector<int>& desc,
   c.fits = add_items(items, desc, plans, [](const Plan&) { return 1; });
   c.fits1 = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? 1 : 0; });
   c.jl = add_items(items, desc, plans, [&](const Plan& q) { return sampled(q) ? q.k : 0; });
+  int pmax = 0;
+  for (const Plan* q : plans) pmax = std::max(pmax, q->p);
+  const int kc = jl_cols(pmax);  // as launch_jl_b picks for the class
+  c.jlg = add_items(items, desc, plans, [&](const Plan& q) {
+    return sampled(q) ? (q.k + kc - 1) / kc : 0;
+  });
   c.chunks = add_items(items, desc, plans, [&](const Plan& q) {
     return sampled(q) ? static_cast<int>((sample_work_doubles(q.m) - 1) / 2) : 0;
   });
@@ -334,7 +340,7 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
   TLS_CHECK(launch_gather_b(1, L_(rows1), D, seed, s));
   if (l.fits1.n > 0) {
     TLS_CHECK(launch_qr_b(1, k.qt, L_(tiles1), nullptr, 0, nullptr, 0, L_(fits1), ldqmax, D, s));
-    TLS_CHECK(launch_jl_b(L_(jl), D, o.jl_kind, pmax, seed, s));
+    TLS_CHECK(launch_jl_b(L_(jlg), D, o.jl_kind, pmax, seed, s));
     TLS_CHECK(launch_small_rfft_b(cprec, k.lgn, 0, L_(jl), D, ctx->tw, s));
     TLS_CHECK(launch_scores_b(cprec, k.lgn, L_(blocks1), D, ctx->tw, s));
     TLS_CHECK(launch_sample_b(cprec, L_(chunks), L_(draws), L_(fits1), D, seed, s));
@@ -562,9 +568,10 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     TLS_CHECK(batch_init(I + collect_off, nb, D, max_iter, max_refine, inner_max, 1e-5, s));
     TLS_CHECK(batch_zero_ints(counts, static_cast<int>(ncounts), s));
   }
-  // profile = 1: event pairs around every launch of the dominant pass (FP64:
-  // the fused LSQR pass; mixed: the FP32 normal-equation pass), one pool per
-  // class stream
+  // profile = 1: event pairs around every launch of the fused LSQR pass (in
+  // mixed batches both product precisions' launches), one pool per class
+  // stream; the classes then run one at a time, so that each launch's
+  // duration is its own and not shared with another class's kernels
   const bool graphs = !o.no_graph && !o.profile;
 
   // One class from setup to residual on stream cs; hc: 4 pinned ints.
@@ -783,10 +790,11 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     return done(residual_class(L_(rblocks), L_(fits), c.pmax, D, s));
   };
 
-  // The classes are independent: up to BATCH_STREAMS of them run at once,
-  // each on a stream of its own driven by a host thread; the caller's stream
-  // orders them after the uploads above and waits for all of them.
-  const int nw = std::min<int>(static_cast<int>(classes.size()), BATCH_STREAMS);
+  // The classes are independent: up to BATCH_STREAMS of them run at once
+  // (one while profiling), each on a stream of its own driven by a host
+  // thread; the caller's stream orders them after the uploads above and
+  // waits for all of them.
+  const int nw = std::min<int>(static_cast<int>(classes.size()), o.profile ? 1 : BATCH_STREAMS);
   std::vector<PassTimer> timers(BATCH_STREAMS);
   if (nw > 0) {
     TLS_CHECK(ensure_batch_streams(ctx));

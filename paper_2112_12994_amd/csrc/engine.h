@@ -539,9 +539,11 @@ ClassKey class_key(const Plan& pl);
 constexpr int BATCH_LDQ_MAX = 1024;
 
 // Work-item lists of one class (offsets into one device item table).
+// jl: one item per (fit, JL column); jlg: one per (fit, group of
+// jl_cols(pmax) columns solved by one wavefront), pmax over the lists' fits.
 struct ClassLists {
-  List blocks, groups, blocks1, rows1, rows2, tiles1, tiles2, rowtiles2, trmm2, fits, fits1, jl, chunks,
-      draws, cols, rblocks;
+  List blocks, groups, blocks1, rows1, rows2, tiles1, tiles2, rowtiles2, trmm2, fits, fits1, jl, jlg,
+      chunks, draws, cols, rblocks;
 };
 // Appends the lists of the fits with descriptor indices desc[i] and plans
 // plans[i] to `items`.

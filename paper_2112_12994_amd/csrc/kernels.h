@@ -73,6 +73,9 @@ hipError_t launch_rh_mask(int prec, void* scores, int64_t m, int level, uint64_t
 size_t sample_work_doubles(int64_t m);
 // Pi (k x p JL map) and Omega = R[:p,:p]^{-1} Pi^T (p x k, column-major) for
 // upper-triangular R (row-major, leading dimension ldr >= p), p <= 1024.
+// JL columns solved together by one wavefront at order p (fewer for long
+// columns, so that the right-hand sides stay in registers).
+constexpr int jl_cols(int p) { return p <= 256 ? 8 : (p <= 512 ? 4 : 2); }
 hipError_t launch_jl_solve(const double* R, int ldr, int p, int k, int kind, double* Pi,
                            double* Om, uint64_t seed, uint32_t fit, hipStream_t st);
 

@@ -170,7 +170,9 @@ __device__ __forceinline__ void draw_body(const T* __restrict__ s, int64_t m,
     const int step = (hi - lo + 64) / 64;
     const int k = lo + lane * step;
     const uint64_t le = __ballot(k <= hi && pre[k] <= target);
-    lo += (63 - __builtin_clzll(le)) * step;
+    // le has lane 0 unless the target is not a number (scores that are not
+    // finite): then lo stays, so every index stays inside the chunks
+    lo += (le ? 63 - __builtin_clzll(le) : 0) * step;
     hi = min(hi, lo + step - 1);
   }
   const int64_t base = static_cast<int64_t>(lo) * CHUNK;
@@ -293,30 +295,35 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Row q of Pi and column q of Omega = R[:p,:p]^{-1} Pi^T (p x k,
-// column-major; R upper triangular, row-major with leading dimension ldr) by
-// back substitution, one wavefront per column: lane l holds b_j for
-// j = l + 64 t (t < T), step s takes x_s = b_s (1 / R_ss) from the lane
+// Rows c0 .. c0 + KC - 1 (those below k) of Pi and the same columns of
+// Omega = R[:p,:p]^{-1} Pi^T (p x k, column-major; R upper triangular,
+// row-major with leading dimension ldr) by back substitution, one wavefront
+// for all of them: lane l holds b_j of every column for j = l + 64 t
+// (t < T), step s takes x_s = b_s (1 / R_ss) of each column from the lane
 // holding b_s (a register read with a uniform lane index) and updates the
-// rows above it with column s of R.  The column loads and the reciprocals
-// do not depend on the solution, so each block of U columns is prepared
-// while the previous block is solved; a step's dependent chain is a
-// multiply, the register read and an FMA.
-template <int T, int U>
+// rows above it with column s of R, loaded once for all the columns.  The
+// column loads and the reciprocals do not depend on the solution, so each
+// block of U columns is prepared while the previous block is solved.
+
+template <int T, int U, int KC>
 __device__ __forceinline__ void jl_solve_body(const double* __restrict__ R, int ldr, int p, int k,
                                               int kind, double* __restrict__ Pi,
                                               double* __restrict__ Om, uint64_t seed,
-                                              uint32_t fit, int q) {
+                                              uint32_t fit, int c0) {
   const int lane = static_cast<int>(threadIdx.x);
-  const JlRow g = jl_row(p, k, kind, seed, fit, q);
-  double b[T];
+  double b[T][KC];
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int j = lane + 64 * t;
-    b[t] = j < p ? jl_entry(g, p, q, j, seed, fit) : 0.0;
-    if (Pi && j < p) Pi[static_cast<size_t>(q) * p + j] = b[t];
+  for (int c = 0; c < KC; ++c) {
+    const int q = c0 + c;
+    const JlRow g = jl_row(p, k, kind, seed, fit, q < k ? q : 0);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int j = lane + 64 * t;
+      b[t][c] = (q < k && j < p) ? jl_entry(g, p, q, j, seed, fit) : 0.0;
+      if (Pi && q < k && j < p) Pi[static_cast<size_t>(q) * p + j] = b[t][c];
+    }
   }
-  // column s of R above the diagonal (zero elsewhere) and R_ss
+  // column s of R above the diagonal (zero elsewhere) and 1 / R_ss
   auto load = [&](int s0, double (&rc)[U][T], double (&dg)[U]) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -336,17 +343,23 @@ __device__ __forceinline__ void jl_solve_body(const double* __restrict__ R, int 
     for (int u = 0; u < U; ++u) {
       const int s = s0 - u;
       if (s < 0) break;
-      const int ts = s >> 6;
-      double bs = b[0];
+      const int ts = s >> 6, ls = s & 63;
+      double xs[KC];
 #pragma unroll
-      for (int t = 1; t < T; ++t)
-        if (t == ts) bs = b[t];
-      const double xs = readlane_f64(bs * dg[u], s & 63);
+      for (int c = 0; c < KC; ++c) {
+        double bs = b[0][c];
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        if (t == ts && lane == (s & 63)) b[t] = xs;
-        b[t] = fma(-rc[u][t], xs, b[t]);
+        for (int t = 1; t < T; ++t)
+          if (t == ts) bs = b[t][c];
+        xs[c] = readlane_f64(bs * dg[u], ls);
       }
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+          if (t == ts && lane == ls) b[t][c] = xs[c];
+          b[t][c] = fma(-rc[u][t], xs[c], b[t][c]);
+        }
     }
   };
   double ra[U][T], rb[U][T], da[U], db[U];
@@ -358,10 +371,23 @@ __device__ __forceinline__ void jl_solve_body(const double* __restrict__ R, int 
     solve(s0 - U, rb, db);
   }
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int j = lane + 64 * t;
-    if (j < p) Om[static_cast<size_t>(q) * p + j] = b[t];
+  for (int c = 0; c < KC; ++c) {
+    const int q = c0 + c;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int j = lane + 64 * t;
+      if (q < k && j < p) Om[static_cast<size_t>(q) * p + j] = b[t][c];
+    }
   }
+}
+
+// Columns per wavefront by rows per lane, as jl_cols of the order: batched
+// fits take one wavefront for several columns (the column loads of R shared
+// by all of them); a single fit, one wavefront per column (the k chains in
+// parallel on separate CUs).
+template <int T>
+constexpr int jl_kc() {
+  return T <= 4 ? 8 : (T <= 8 ? 4 : 2);
 }
 
 template <int T, int U>
@@ -369,7 +395,7 @@ __global__ __launch_bounds__(64) void jl_solve_kernel(const double* __restrict__
                                                       int k, int kind, double* __restrict__ Pi,
                                                       double* __restrict__ Om, uint64_t seed,
                                                       uint32_t fit) {
-  jl_solve_body<T, U>(R, ldr, p, k, kind, Pi, Om, seed, fit, blockIdx.x);
+  jl_solve_body<T, U, 1>(R, ldr, p, k, kind, Pi, Om, seed, fit, blockIdx.x);
 }
 
 }  // namespace
@@ -441,7 +467,8 @@ hipError_t launch_jl_solve(const double* R, int ldr, int p, int k, int kind, dou
                            double* Om, uint64_t seed, uint32_t fit, hipStream_t st) {
   if (p < 1 || k < 1 || p > 1024 || ldr < p) return hipErrorInvalidValue;
 #define TLS_JL(T, U)                                                                             \
-  hipLaunchKernelGGL((jl_solve_kernel<T, U>), dim3(k), dim3(64), 0, st, R, ldr, p, k, kind, Pi, \
+  hipLaunchKernelGGL((jl_solve_kernel<T, U>), dim3(k), dim3(64), 0, st, \
+                     R, ldr, p, k, kind, Pi, \
                      Om, seed, fit)
   if (p <= 64)
     TLS_JL(1, 8);
@@ -499,14 +526,15 @@ __global__ __launch_bounds__(64) void draw_b_kernel(const Item* __restrict__ ite
 }
 
 // Omega of the stage-1 factor (in R after the stage-1 sweep), one
-// wavefront per (fit, JL column) item.
+// wavefront per (fit, group of jl_cols(pmax) columns) item.
 template <int T, int U>
 __global__ __launch_bounds__(64) void jl_b_kernel(const Item* __restrict__ items,
                                                   const FitDesc* __restrict__ D, int kind,
                                                   uint64_t seed) {
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
-  jl_solve_body<T, U>(d.R, d.q, d.p, d.k, kind, d.Pi, d.Om, seed, d.fit, it.idx);
+  jl_solve_body<T, U, jl_kc<T>()>(d.R, d.q, d.p, d.k, kind, d.Pi, d.Om, seed, d.fit,
+                                  it.idx * jl_kc<T>());
 }
 
 }  // namespace
