@@ -223,11 +223,13 @@ def prof_summary(kind: str, dirs: list, out: str, cmd: str, title: str):
 
 
 def pass_groups(B: int, nblocks: int) -> int:
-    """Workgroups of the Toeplitz pass: blocks are taken 4 at a time up to
-    B = 1024, 2 at a time up to B = 4096, else singly (the library's
-    pass_nw)."""
+    """Workgroups of the Toeplitz pass: up to B = 1024 a 256-thread
+    workgroup takes 256 / (B / 16) blocks (B / 16 threads each, at least 8:
+    32 blocks at B = 128, 4 at B = 1024), 2 at a time up to B = 4096, else
+    singly (the library's pass_nw)."""
     lgn = B.bit_length() - 2
-    nw = 4 if lgn <= 9 else (2 if lgn <= 11 else 1)
+    nt = min(max((1 << lgn) // 8, 8), 256)
+    nw = 256 // nt if lgn <= 9 else (2 if lgn <= 11 else 1)
     return -(-nblocks // nw)
 
 

@@ -33,12 +33,12 @@ __device__ __forceinline__ int swz(int i) {
 }
 
 // Barrier of a group of NT threads that exchange data through LDS.  A
-// group of one wavefront needs none: its LDS operations are performed in
+// group within one wavefront needs none: its LDS operations are performed in
 // issue order, so the fences only keep the compiler from moving LDS
 // accesses across this point.
 template <int NT>
 __device__ __forceinline__ void group_sync() {
-  if constexpr (NT == 64) {
+  if constexpr (NT <= 64) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");

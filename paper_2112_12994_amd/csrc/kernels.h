@@ -23,17 +23,20 @@ struct Twiddles {
   const void* d32 = nullptr;  // cx<float>[BMAX]
 };
 
-// threads per workgroup used for a transform of complex length 2^lgn
-inline int fft_threads(int lgn) {
-  int n8 = (1 << lgn) / 8;
-  return n8 < 64 ? 64 : (n8 > 256 ? 256 : n8);
+// Threads per block transform of the Toeplitz pass at complex length 2^lgn:
+// eight points each (one radix-8 butterfly per stage), at most 256.
+constexpr int pass_nt(int lgn) {
+  return (1 << lgn) / 8 < 8 ? 8 : ((1 << lgn) / 8 > 256 ? 256 : (1 << lgn) / 8);
 }
 
 // Blocks per workgroup of the Toeplitz pass: that many blocks are
-// transformed side by side (each by fft_threads(lgn) threads) and their X^T
-// products share one inverse transform; the pass writes its partials per
-// group of pass_nw(lgn) consecutive blocks.
-constexpr int pass_nw(int lgn) { return lgn <= 9 ? 4 : (lgn <= 11 ? 2 : 1); }
+// transformed side by side (each by pass_nt(lgn) threads; short blocks fill
+// a 256-thread workgroup) and their X^T products share one inverse
+// transform; the pass writes its partials per group of pass_nw(lgn)
+// consecutive blocks.
+constexpr int pass_nw(int lgn) {
+  return lgn <= 9 ? 256 / pass_nt(lgn) : (lgn <= 11 ? 2 : 1);
+}
 inline int pass_groups(int lgn, int nblocks) {
   return (nblocks + pass_nw(lgn) - 1) / pass_nw(lgn);
 }

@@ -27,7 +27,7 @@ template <typename T, int LGN, int MODE>
 hipError_t toep_one(const void* Yhat, const void* Vhat, const void* w_in, void* u_out,
                     const void* u_in, double* partial, const double* coef, const int* flag,
                     const Twiddles& tw, int64_t m, int p, int L, int nblocks, hipStream_t st) {
-  constexpr int NT = nt_for(LGN);
+  constexpr int NT = pass_nt(LGN);
   constexpr int NW = pass_nw(LGN);
   const int ngroups = pass_groups(LGN, nblocks);
   hipLaunchKernelGGL((toep_pass_kernel<T, LGN, NT, NW, MODE>), dim3(ngroups), dim3(NT * NW), 0, st,
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(NT) void resid_b_kernel(const Item* __restrict__ it
 template <int LGN>
 hipError_t toep_b_sel(int prec, int variant, const Item* items, int nitems, const FitDesc* D,
                       const double* consts, const Twiddles& tw, hipStream_t st) {
-  constexpr int NT = nt_for(LGN);
+  constexpr int NT = pass_nt(LGN);
   switch (variant) {
     case BP_LSQR_FIRST:
       hipLaunchKernelGGL((toep_b_kernel<double, LGN, NT, BP_LSQR_FIRST>), dim3(nitems), dim3(NT * pass_nw(LGN)), 0,
