@@ -115,9 +115,30 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     // host waits for, so the device never idles on the host's convergence
     // check; iterations queued after convergence exit at once.  The first
     // check comes after CHUNK_ITERS iterations with half as many queued
-    // behind it, later chunks are two iterations long, so at most a few
-    // launches run past convergence.
+    // behind it.  Later chunks run to where the convergence test is
+    // expected to pass: the stopping ratio ||A^T r|| / (||A|| ||r||)
+    // falls about geometrically, so its rate between two checks predicts
+    // the iterations left; a chunk stops one short of that (the next check
+    // then sees the last ones queued) and takes 2 to 8 iterations.
     int launched = 0;
+    int prev_iter = -1;
+    double prev_ratio = 0.0;
+    auto next_chunk = [&](const LsqrState& st) -> int {
+      const double an = sqrt(st.anorm2);
+      const double ratio = an > 0.0 && st.rnorm > 0.0 ? st.arnorm / (an * st.rnorm) : 0.0;
+      int n = 2;
+      if (prev_iter >= 0 && st.iter > prev_iter && ratio > 0.0 && prev_ratio > ratio) {
+        const double rate = pow(ratio / prev_ratio, 1.0 / (st.iter - prev_iter));
+        if (ratio > st.tol && rate < 1.0) {
+          const double left = ceil(log(st.tol / ratio) / log(rate));
+          const int queued = launched - st.iter - 1;  // launched after this snapshot
+          n = static_cast<int>(std::min(8.0, std::max(2.0, left - queued - 1)));
+        }
+      }
+      prev_iter = st.iter;
+      prev_ratio = ratio;
+      return n;
+    };
     auto chunk = [&](int iters, int slot) -> tls_status {
       for (int it = 0; it < iters; ++it) {
         const tls_status ec = pass(b.u);
@@ -135,7 +156,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       const int slot = k & 1;
       TLS_CHECK(hipEventSynchronize(ctx->chunk_ev[slot]));
       if (ho->ring[slot].done || launched > max_iter + 2 * CHUNK_ITERS) break;
-      e = chunk(2, slot);
+      e = chunk(next_chunk(ho->ring[slot]), slot);
       if (e != TLS_OK) return e;
     }
     TLS_CHECK(hipMemcpyAsync(&ho->st, b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
