@@ -78,7 +78,7 @@ size_t sample_work_doubles(int64_t m);
 // upper-triangular R (row-major, leading dimension ldr >= p), p <= 1024.
 // JL columns solved together by one wavefront at order p (fewer for long
 // columns, so that the right-hand sides stay in registers).
-constexpr int jl_cols(int p) { return p <= 256 ? 8 : (p <= 512 ? 4 : 2); }
+constexpr int jl_cols(int p) { return p <= 128 ? 8 : (p <= 256 ? 4 : (p <= 512 ? 2 : 1)); }
 hipError_t launch_jl_solve(const double* R, int ldr, int p, int k, int kind, double* Pi,
                            double* Om, uint64_t seed, uint32_t fit, hipStream_t st);
 

@@ -387,7 +387,7 @@ __device__ __forceinline__ void jl_solve_body(const double* __restrict__ R, int 
 // parallel on separate CUs).
 template <int T>
 constexpr int jl_kc() {
-  return T <= 4 ? 8 : (T <= 8 ? 4 : 2);
+  return T <= 2 ? 8 : (T <= 4 ? 4 : (T <= 8 ? 2 : 1));
 }
 
 template <int T, int U>
