@@ -101,7 +101,7 @@ __global__ void done_flags_b_kernel(const Item* __restrict__ fits, int nfits,
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nfits) return;
   const FitDesc& d = D[fits[k].fit];
-  flags[k] = (which == 0 ? d.st->done : d.rst->done) ? 1 : 0;
+  flags[k] = (which == 0 ? d.st->done : (which == 1 ? d.rst->done : d.st->f32)) ? 1 : 0;
 }
 
 __global__ void collect_b_kernel(const Item* __restrict__ items, const FitDesc* __restrict__ D,
@@ -347,7 +347,8 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
   const bool mixed = o.precision == TLS_PREC_MIXED;
   const int cprec = mixed ? PREC_F32 : PREC_F64;
   const uint64_t seed = o.seed;
-  // spectra of the series blocks (mixed: FP32 for the products, FP64 for the residuals)
+  // spectra of the series blocks (mixed: FP32 for the products of the fits
+  // that take them, FP64 for the scores, the residuals and the others)
   TLS_CHECK(launch_spectra_b(cprec, k.lgn, L_(blocks), D, 0, ctx->tw, s));
   if (mixed) TLS_CHECK(launch_spectra_b(PREC_F64, k.lgn, L_(blocks), D, 1, ctx->tw, s));
   // sketch -> R
@@ -355,9 +356,10 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
   if (l.fits1.n > 0) {
     TLS_CHECK(launch_qr_b(1, k.qt, L_(tiles1), nullptr, 0, nullptr, 0, L_(fits1), ldqmax, D, s));
     TLS_CHECK(launch_jl_b(L_(jlg), D, o.jl_kind, pmax, seed, s));
-    TLS_CHECK(launch_small_rfft_b(cprec, k.lgn, 0, L_(jl), D, ctx->tw, s));
-    TLS_CHECK(launch_scores_b(cprec, k.lgn, L_(blocks1), D, ctx->tw, s));
-    TLS_CHECK(launch_sample_b(cprec, L_(chunks), L_(draws), L_(fits1), D, seed, s));
+    // the scores and the draw in FP64 in every precision
+    TLS_CHECK(launch_small_rfft_b(PREC_F64, k.lgn, 0, L_(jl), D, ctx->tw, s));
+    TLS_CHECK(launch_scores_b(PREC_F64, k.lgn, L_(blocks1), D, ctx->tw, s));
+    TLS_CHECK(launch_sample_b(PREC_F64, L_(chunks), L_(draws), L_(fits1), D, seed, s));
     TLS_CHECK(launch_gather_b(2, L_(rows2), D, seed, s));
   }
   TLS_CHECK(launch_qr_b(2, k.qt, L_(tiles2), L_(rowtiles2), L_(trmm2), L_(fits), ldqmax, D, s));
@@ -373,26 +375,33 @@ tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, co
 tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
                            int precs, const Item* groups, int ngroups, const Item* cols, int ncols,
                            const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
-                           PassTimer* tm, hipStream_t s) {
-  // precs bit 0: the fits with FP64 products; bit 1: those with FP32 products
-  // (FP32 spectra, u and v's spectrum in FP32).  Each launch skips the fits
-  // whose products have the other precision (LsqrState::f32).
+                           PassTimer* tm, hipStream_t s, const Item* groups32, int ngroups32,
+                           const Item* fits32, int nfits32) {
+  // FP32 products: FP32 spectra, u and v's spectrum in FP32 (LsqrState::f32)
   const bool p64 = (precs & 1) != 0, p32 = (precs & 2) != 0;
+  if (!groups32) {
+    groups32 = groups;
+    ngroups32 = ngroups;
+    fits32 = fits;
+    nfits32 = nfits;
+  }
   if (first && p64) TLS_CHECK(launch_small_rfft_b(PREC_F64, lgn, 1, fits, nfits, D, ctx->tw, s));
-  if (first && p32) TLS_CHECK(launch_small_rfft_b(PREC_F32, lgn, 1, fits, nfits, D, ctx->tw, s));
+  if (first && p32)
+    TLS_CHECK(launch_small_rfft_b(PREC_F32, lgn, 1, fits32, nfits32, D, ctx->tw, s));
   if (tm) TLS_CHECK(tm->begin(s));
-  if (p64)
+  if (p64 && ngroups > 0)
     TLS_CHECK(launch_toep_b(PREC_F64, lgn, first ? BP_LSQR_FIRST : BP_LSQR, groups, ngroups, D,
                             ctx->consts, ctx->tw, s));
-  if (p32)
-    TLS_CHECK(launch_toep_b(PREC_F32, lgn, BP_LSQR32, groups, ngroups, D, ctx->consts, ctx->tw, s));
+  if (p32 && ngroups32 > 0)
+    TLS_CHECK(launch_toep_b(PREC_F32, lgn, BP_LSQR32, groups32, ngroups32, D, ctx->consts, ctx->tw,
+                            s));
   if (tm) TLS_CHECK(tm->end(s));
   TLS_CHECK(launch_colsum_b(0, cols, ncols, D, s));
   if (p64)
     TLS_CHECK(launch_lsqr_step_b(PREC_F64, lgn, fits, nfits, pmax, mlds, D, counts, done_list,
                                  ctx->tw, s));
   if (p32)
-    TLS_CHECK(launch_lsqr_step_b(PREC_F32, lgn, fits, nfits, pmax, mlds, D, counts, done_list,
+    TLS_CHECK(launch_lsqr_step_b(PREC_F32, lgn, fits32, nfits32, pmax, mlds, D, counts, done_list,
                                  ctx->tw, s));
   return TLS_OK;
 }
@@ -618,10 +627,16 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     // rebuilt without them (in this class's region of the second item
     // buffer), so that the stragglers do not pay for launches over every
     // finished fit's blocks; the graphs are captured again.
+    // With split set (mixed batches), groups / fits hold the FP64-product
+    // fits and groups32 / fits32 the FP32-product ones (one list each per
+    // launch, none of whose workgroups then exits for the other precision);
+    // cols covers all of them.
     struct Lists {
       const Item *groups, *cols, *fits;
       int ngroups, ncols, nfits;
       std::vector<int> desc;  // descriptor index of each fit item, in list order
+      const Item *groups32 = nullptr, *fits32 = nullptr;
+      int ngroups32 = 0, nfits32 = 0;
     };
     auto full_lists = [&]() {
       Lists sl{I + l.groups.off, I + l.cols.off, I + l.fits.off, l.groups.n, l.cols.n, l.fits.n, {}};
@@ -629,25 +644,35 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       return sl;
     };
     std::vector<int> hflags;
+    std::vector<char> is32;  // per fit of the class (index j - c.first) when split
     // which: 0 = LSQR finished (st->done), 1 = refinement finished (rst->done)
     auto compact = [&](Lists& sl, int which) -> tls_status {
       int* dfl = dflags + c.first;
+      const int nlisted = static_cast<int>(sl.desc.size());
+      // the listed fits in desc order (the split lists hold them FP64 first)
       TLS_CHECK(launch_done_flags_b(sl.fits, sl.nfits, D, which, dfl, s));
-      hflags.resize(sl.nfits);
-      TLS_CHECK(hipMemcpyAsync(hflags.data(), dfl, sl.nfits * sizeof(int), hipMemcpyDeviceToHost, s));
+      if (sl.fits32 && sl.nfits32 > 0)
+        TLS_CHECK(launch_done_flags_b(sl.fits32, sl.nfits32, D, which, dfl + sl.nfits, s));
+      hflags.resize(nlisted);
+      TLS_CHECK(hipMemcpyAsync(hflags.data(), dfl, nlisted * sizeof(int), hipMemcpyDeviceToHost, s));
       TLS_CHECK(hipStreamSynchronize(s));
-      std::vector<Item> b2, c2, f2;
-      std::vector<int> keep;
-      for (int k = 0; k < sl.nfits; ++k) {
+      std::vector<Item> b2, c2, f2, b32, f32;
+      std::vector<int> keep, keep32;
+      for (int k = 0; k < nlisted; ++k) {
         if (hflags[k]) continue;
         const int j = sl.desc[k];
         const Plan& pl = plans[order[j]];
-        for (int t = 0; t < pl.ngroups; ++t) b2.push_back({j, t});
+        const bool to32 = !is32.empty() && is32[j - c.first];
+        for (int t = 0; t < pl.ngroups; ++t) (to32 ? b32 : b2).push_back({j, t});
         for (int t = 0; t <= pl.p; ++t) c2.push_back({j, t});
-        f2.push_back({j, 0});
-        keep.push_back(j);
+        (to32 ? f32 : f2).push_back({j, 0});
+        (to32 ? keep32 : keep).push_back(j);
       }
-      if (keep.empty()) return TLS_OK;
+      if (keep.empty() && keep32.empty()) return TLS_OK;
+      const int n64g = static_cast<int>(b2.size()), n64f = static_cast<int>(f2.size());
+      b2.insert(b2.end(), b32.begin(), b32.end());
+      f2.insert(f2.end(), f32.begin(), f32.end());
+      keep.insert(keep.end(), keep32.begin(), keep32.end());
       Item* base2 = items2;
       TLS_CHECK(hipMemcpyAsync(base2 + l.groups.off, b2.data(), b2.size() * sizeof(Item),
                                hipMemcpyHostToDevice, s));
@@ -657,9 +682,16 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
                                hipMemcpyHostToDevice, s));
       // the host vectors must outlive the copies
       TLS_CHECK(hipStreamSynchronize(s));
+      const bool split = !is32.empty();
       sl = Lists{base2 + l.groups.off, base2 + l.cols.off, base2 + l.fits.off,
-                 static_cast<int>(b2.size()), static_cast<int>(c2.size()),
-                 static_cast<int>(f2.size()), keep};
+                 split ? n64g : static_cast<int>(b2.size()), static_cast<int>(c2.size()),
+                 split ? n64f : static_cast<int>(f2.size()), keep};
+      if (split) {
+        sl.groups32 = base2 + l.groups.off + n64g;
+        sl.ngroups32 = static_cast<int>(b2.size()) - n64g;
+        sl.fits32 = base2 + l.fits.off + n64f;
+        sl.nfits32 = static_cast<int>(f2.size()) - n64f;
+      }
       drop_graphs();
       return TLS_OK;
     };
@@ -677,13 +709,26 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
     // launches: a graph when enabled (captured again when precs changes).
     auto lsqr_any = [&](PassTimer* t, int precs, int n32) -> tls_status {
       Lists sl = full_lists();
+      if (precs == 3) {
+        // the lists split by product precision before the first step
+        is32.assign(c.count, 0);
+        TLS_CHECK(launch_done_flags_b(sl.fits, sl.nfits, D, 2, dflags + c.first, s));
+        std::vector<int> f(sl.nfits);
+        TLS_CHECK(hipMemcpyAsync(f.data(), dflags + c.first, sl.nfits * sizeof(int),
+                                 hipMemcpyDeviceToHost, s));
+        TLS_CHECK(hipStreamSynchronize(s));
+        for (int k = 0; k < sl.nfits; ++k) is32[sl.desc[k] - c.first] = static_cast<char>(f[k]);
+        const tls_status ec = compact(sl, 0);
+        if (ec != TLS_OK) return ec;
+      }
       for (int launched = 0;; launched += B_CHUNK_ITERS) {
         auto chunk = [&, launched]() -> tls_status {
           for (int it = 0; it < B_CHUNK_ITERS; ++it) {
             const tls_status e = lsqr_step_class(ctx, c.key.lgn, c.pmax, c.key.mlds != 0,
                                                  launched == 0 && it == 0, precs,
                                                  SL_(groups),
-                                                 SL_(cols), SL_(fits), D, cnt, nullptr, t, s);
+                                                 SL_(cols), SL_(fits), D, cnt, nullptr, t, s,
+                                                 SL_(groups32), SL_(fits32));
             if (e != TLS_OK) return e;
           }
           return TLS_OK;
@@ -700,7 +745,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
             drop_graphs();
           }
         }
-        if (!t && worth_compacting(c.count - hc[0], sl.nfits)) {
+        if (!t && worth_compacting(c.count - hc[0], sl.nfits + sl.nfits32)) {
           const tls_status ec = compact(sl, 0);
           if (ec != TLS_OK) return ec;
         }
@@ -717,7 +762,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       hipLaunchKernelGGL(mixed_dispatch_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off,
                          D, 0, MIXED_TOL_F32, cnt, 0);
       if (hipError_t he = hipGetLastError()) return done(hip_status(he));
-      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off, D);
+      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.blocks.n), dim3(256), 0, s, I + l.blocks.off, D);
       if (hipError_t he = hipGetLastError()) return done(hip_status(he));
       if (hipError_t he = hipMemcpyAsync(hc, cnt, 4 * sizeof(int), hipMemcpyDeviceToHost, s))
         return done(hip_status(he));
@@ -740,7 +785,7 @@ tls_status run_batch(tls_ctx* ctx, int count, const double* const* host_series,
       if (hipError_t he = hipStreamSynchronize(s)) return done(hip_status(he));
       const int n_refine = hc[1];
       if (hc[0] < c.count) {
-        hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, s, I + l.fits.off, D);
+        hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.blocks.n), dim3(256), 0, s, I + l.blocks.off, D);
         if (hipError_t he = hipGetLastError()) return done(hip_status(he));
         const tls_status e = lsqr_any(tm, 2, c.count - hc[0]);
         if (e != TLS_OK) return done(e);

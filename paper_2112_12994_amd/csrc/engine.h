@@ -312,7 +312,7 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->Mt = a.take<double>(static_cast<size_t>(pl.p) * pl.p);
   b->Pi = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
   b->Om = a.take<double>(static_cast<size_t>(pl.k) * pl.p);
-  b->Omhat = a.take<char>(static_cast<size_t>(pl.k) * N * 2 * es);
+  b->Omhat = a.take<char>(static_cast<size_t>(pl.k) * N * 16);  // FP64 in every precision
   b->Vhat = a.take<char>(N * 16);
   b->v = a.take<double>(pl.p);
   b->w = a.take<double>(pl.p);
@@ -489,12 +489,16 @@ __global__ __launch_bounds__(256) void mixed_dispatch_b_kernel(const Item* fits,
   }
 }
 
-// u = float(b) (b = y[p:]) for the fits about to run FP32-product LSQR.
-__global__ __launch_bounds__(256) void to_f32_b_kernel(const Item* fits, const FitDesc* D) {
-  const FitDesc& d = D[fits[blockIdx.x].fit];
+// u = float(b) (b = y[p:]) for the fits about to run FP32-product LSQR, one
+// workgroup per (fit, FFT block) item: rows [idx L, (idx + 1) L).
+__global__ __launch_bounds__(256) void to_f32_b_kernel(const Item* blocks, const FitDesc* D) {
+  const Item it = blocks[blockIdx.x];
+  const FitDesc& d = D[it.fit];
   if (d.st->done || !d.st->f32) return;
   float* u = static_cast<float*>(d.u);
-  for (int64_t i = threadIdx.x; i < d.m; i += 256) u[i] = static_cast<float>(d.y[d.p + i]);
+  const int64_t r0 = static_cast<int64_t>(it.idx) * d.L;
+  const int64_t r1 = r0 + d.L < d.m ? r0 + d.L : d.m;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) u[i] = static_cast<float>(d.y[d.p + i]);
 }
 
 
@@ -577,12 +581,16 @@ struct PassTimer {
 // of one class.
 tls_status setup_class(tls_ctx* ctx, const ClassKey& k, int pmax, int ldqmax, const Item* I,
                        const ClassLists& l, FitDesc* D, const tls_options& o, hipStream_t s);
-// One FP64 LSQR step for the listed fits: the fused pass (first: from b and
+// One LSQR step for the listed fits: the fused pass (first: from b and
 // phi0, after the spectrum of phi0), the column sums and the p-side step.
+// precs bit 0: FP64 products, bit 1: FP32 products (each launch skips the
+// fits of the other precision).  groups32 / fits32 (optional): the FP32
+// launches' own lists, the FP64 ones then taking groups / fits alone.
 tls_status lsqr_step_class(tls_ctx* ctx, int lgn, int pmax, bool mlds, bool first,
                            int precs, const Item* groups, int ngroups, const Item* cols, int ncols,
                            const Item* fits, int nfits, FitDesc* D, int* counts, int* done_list,
-                           PassTimer* tm, hipStream_t s);
+                           PassTimer* tm, hipStream_t s, const Item* groups32 = nullptr,
+                           int ngroups32 = 0, const Item* fits32 = nullptr, int nfits32 = 0);
 // FP64 residual of phi (row-wise) for the listed fits.
 tls_status residual_class(const Item* rblocks, int nrblocks, const Item* fits, int nfits, int pmax,
                           FitDesc* D, hipStream_t s);

@@ -54,13 +54,14 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       for (int lev = levels - 1; lev >= 0; --lev) {
         TLS_CHECK(launch_qr(b.A, pl.crows, q, pl.ldq, p, 1, b.R, b.G, b.R1, b.R2, b.status + 2, s));
         TLS_CHECK(launch_jl_solve(b.R, q, p, pl.k, o.jl_kind, b.Pi, b.Om, seed, fit, s));
-        TLS_CHECK(launch_small_rfft(prec, pl.lgn, b.Om, p, p, pl.k, invB, b.Omhat, ctx->tw, nullptr,
-                                    s));
-        TLS_CHECK(launch_scores(prec, pl.lgn, b.Yhat, b.Omhat, pl.k, b.u, ctx->tw, pl.m, p, pl.L,
-                                pl.nblocks, s));
-        if (lev > 0) TLS_CHECK(launch_rh_mask(prec, b.u, pl.m, lev, seed, fit, s));
-        TLS_CHECK(launch_sample(prec, b.u, pl.m, nullptr, pl.c, b.idx, b.scale, b.swork, seed, fit,
-                                s, static_cast<uint64_t>(lev) * pl.c));
+        // scores and draws in FP64 in every precision (mixed: from the FP64 spectra)
+        TLS_CHECK(launch_small_rfft(PREC_F64, pl.lgn, b.Om, p, p, pl.k, invB, b.Omhat, ctx->tw,
+                                    nullptr, s));
+        TLS_CHECK(launch_scores(PREC_F64, pl.lgn, b.Yhat64, b.Omhat, pl.k, b.u, ctx->tw, pl.m, p,
+                                pl.L, pl.nblocks, s));
+        if (lev > 0) TLS_CHECK(launch_rh_mask(PREC_F64, b.u, pl.m, lev, seed, fit, s));
+        TLS_CHECK(launch_sample(PREC_F64, b.u, pl.m, nullptr, pl.c, b.idx, b.scale, b.swork, seed,
+                                fit, s, static_cast<uint64_t>(lev) * pl.c));
         TLS_CHECK(launch_gather(d_y, pl.m, p, 0, b.idx, b.scale, pl.c, pl.crows, pl.ldq, b.A,
                                 nullptr, nullptr, seed, fit, s));
       }

@@ -415,7 +415,7 @@ hipError_t tick(tls_server* S, std::vector<Request*>& admitted, std::vector<Requ
       // (mixed_path_of), else FP64; both LSQR variants then run over the lists
       hipLaunchKernelGGL(mixed_dispatch_b_kernel, dim3(l.fits.n), dim3(256), 0, ss,
                          I + l.fits.off, S->dD, 0, MIXED_TOL_F32, S->dCounts, 0);
-      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.fits.n), dim3(256), 0, ss, I + l.fits.off, S->dD);
+      hipLaunchKernelGGL(to_f32_b_kernel, dim3(l.blocks.n), dim3(256), 0, ss, I + l.blocks.off, S->dD);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }

@@ -385,7 +385,9 @@ __global__ __launch_bounds__(NT) void scores_b_kernel(const Item* __restrict__ i
                                                       const cx<T>* __restrict__ tab) {
   const Item it = items[blockIdx.x];
   const FitDesc& d = D[it.fit];
-  scores_body<T, LGN, NT>(static_cast<const cx<T>*>(d.Yhat), static_cast<const cx<T>*>(d.Omhat),
+  // FP64 scores from the FP64 spectra (Yhat64 is Yhat unless mixed)
+  scores_body<T, LGN, NT>(static_cast<const cx<T>*>(sizeof(T) == 8 ? d.Yhat64 : d.Yhat),
+                          static_cast<const cx<T>*>(d.Omhat),
                           d.k, static_cast<T*>(d.u), tab, d.m, d.p, d.L, it.idx);
 }
 
