@@ -56,7 +56,9 @@ typedef int32_t tls_status;
 const char* tls_status_string(tls_status s);
 
 #define TLS_PREC_F64 0    /* every step in FP64 */
-#define TLS_PREC_MIXED 1  /* FP32 FFT matvecs and sketch scores; FP64 QR, recurrences and residual */
+#define TLS_PREC_MIXED 1  /* FP32 FFT matvecs for the fits whose sketch factor allows them
+                             (tls_result.mixed_path); FP64 sketch scores, QR, recurrences and
+                             residual */
 
 #define TLS_SKETCH_LEVERAGE 0 /* uniform trials -> generalised leverage scores -> leverage sampling */
 #define TLS_SKETCH_UNIFORM 1  /* uniform trials only (Algorithm 1's sampling without the transform) */
