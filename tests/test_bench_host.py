@@ -52,6 +52,15 @@ def test_committed_profile_matches_sources():
     assert value > bench.fused_pass_bytes(1 << 22, 100, 1024, 4535, 8) * 0.5
 
 
+@pytest.mark.parametrize("workload", ["ar100", "ar500", "batch"])
+def test_committed_mfma_profile_matches_qr_sources(workload):
+    """The committed FP64-MFMA summaries were taken from the QR kernels as
+    they are now (else the bench line drops its qr_fp64_mfma field)."""
+    rec = bench.read_mfma_profile(workload)
+    assert rec is not None
+    assert rec["kernels"] and 0.0 < rec["util_over_mfma_kernels"] < 1.0
+
+
 def test_kernel_stats_summary(tmp_path):
     d = tmp_path / "run" / "node"
     d.mkdir(parents=True)
