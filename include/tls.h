@@ -304,8 +304,12 @@ tls_status tls_lsar_device(tls_ctx* ctx, const double* d_series, int64_t n, int3
  * O(c p + p^2) for the FP64 path) fits in the server's HBM budget and a slot is
  * free.  Each request gives the same result, bit for bit, as tls_fit_device
  * with the server's options and request_id, whatever else is in flight.
- * Submit, poll and wait are thread-safe; the context must outlive the server
- * (the server uses only its read-only tables, not its workspace or stream). */
+ * The worker spreads each tick's set-up, LSQR steps and finishing over four
+ * streams of its own (work units of different fits; one host
+ * synchronisation per tick) and hands finished results to their tickets as
+ * soon as they reach the host.  Submit, poll and wait are thread-safe; the
+ * context must outlive the server (the server uses only its read-only
+ * tables, not its workspace or stream). */
 typedef struct tls_server tls_server;
 typedef uint64_t tls_ticket;
 
