@@ -334,26 +334,26 @@ __global__ __launch_bounds__(NT * pass_nw(LGN)) void toep_b_kernel(const Item* _
   if constexpr (VARIANT == BP_LSQR_FIRST || VARIANT == BP_LSQR) {
     const T* w = VARIANT == BP_LSQR_FIRST ? reinterpret_cast<const T*>(d.y + d.p)
                                           : static_cast<const T*>(d.u);
-    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(static_cast<const cx<T>*>(d.Yhat64),
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED, false>(static_cast<const cx<T>*>(d.Yhat64),
                                            static_cast<const cx<T>*>(d.Vhat), opaque_ptr(w),
                                            opaque_ptr(static_cast<T*>(d.u)),
                                            opaque_ptr(static_cast<const T*>(nullptr)), d.partial,
                                            d.st->coef, &d.st->done, tab, d.m, d.p, d.L,
                                            d.nblocks, d.ngroups, it.idx);
   } else if constexpr (VARIANT == BP_LSQR32) {
-    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED, false>(
         static_cast<const cx<T>*>(d.Yhat), static_cast<const cx<T>*>(d.Vhat),
         opaque_ptr(static_cast<const T*>(d.u)), opaque_ptr(static_cast<T*>(d.u)),
         opaque_ptr(static_cast<const T*>(nullptr)), d.partial, d.st->coef, &d.st->done, tab, d.m,
         d.p, d.L, d.nblocks, d.ngroups, it.idx);
   } else if constexpr (VARIANT == BP_OUTER64) {
-    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED, false>(
         static_cast<const cx<T>*>(d.Yhat64), static_cast<const cx<T>*>(d.Vhat),
         opaque_ptr(reinterpret_cast<const T*>(d.y + d.p)), opaque_ptr(static_cast<T*>(nullptr)),
         opaque_ptr(static_cast<const T*>(nullptr)), d.partial, consts, &d.rst->done, tab, d.m,
         d.p, d.L, d.nblocks, d.ngroups, it.idx);
   } else {
-    toep_pass_body<T, LGN, NT, NW, MODE_FUSED>(
+    toep_pass_body<T, LGN, NT, NW, MODE_FUSED, false>(
         static_cast<const cx<T>*>(d.Yhat), static_cast<const cx<T>*>(d.Vhat32),
         opaque_ptr(static_cast<const T*>(nullptr)), opaque_ptr(static_cast<T*>(nullptr)),
         opaque_ptr(static_cast<const T*>(nullptr)), d.partial, consts + 2, &d.rst->inner_done,

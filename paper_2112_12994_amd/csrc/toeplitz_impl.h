@@ -13,6 +13,8 @@
 // (X[0], X[N]) (both real) and word k the bin X[k] for 0 < k < N.
 #pragma once
 
+#include <type_traits>
+
 #include "fft.h"
 #include "kernels.h"
 
@@ -54,6 +56,17 @@ struct PairLoads {
     yh = P[N / 2];
     if (tab) wh = twiddle<T, false>(tab, N / 2, LGN + 1);
   }
+  // the twiddles alone (bins kept from an earlier load)
+  __device__ __forceinline__ void load_tw(const cx<T>* __restrict__ tab) {
+    const int tid = opaque_tid<NT>();
+#pragma unroll
+    for (int ip = 0; ip < NP; ++ip) {
+      int k = tid + ip * NT;
+      if (!FULL) k = k < N / 2 ? k : 0;
+      w[ip] = twiddle<T, false>(tab, k, LGN + 1);
+    }
+    wh = twiddle<T, false>(tab, N / 2, LGN + 1);
+  }
   // the bins k and N-k (bin 0 pairs with bin N: both real, packed in word 0)
   __device__ __forceinline__ void get(int ip, int k, cx<T>& xk, cx<T>& xnk) const {
     xk = a[ip];
@@ -62,6 +75,29 @@ struct PairLoads {
       xk = {a[ip].x, T(0)};
       xnk = {a[ip].y, T(0)};
     }
+  }
+};
+
+// The bins of a PairLoads without its twiddles, kept between two uses.
+template <typename T, int LGN, int NT>
+struct PairBins {
+  static constexpr int NP = PairLoads<T, LGN, NT>::NP;
+  cx<T> a[NP], b[NP], yh;
+  __device__ __forceinline__ void take(const PairLoads<T, LGN, NT>& l) {
+#pragma unroll
+    for (int ip = 0; ip < NP; ++ip) {
+      a[ip] = l.a[ip];
+      b[ip] = l.b[ip];
+    }
+    yh = l.yh;
+  }
+  __device__ __forceinline__ void give(PairLoads<T, LGN, NT>& l) const {
+#pragma unroll
+    for (int ip = 0; ip < NP; ++ip) {
+      l.a[ip] = a[ip];
+      l.b[ip] = b[ip];
+    }
+    l.yh = yh;
   }
 };
 
@@ -166,7 +202,7 @@ __global__ __launch_bounds__(NT) void small_rfft_kernel(const double* __restrict
 // over blocks of conj(Y_b) E_b (the transform is linear and the same for
 // every block), so the NW product spectra are added in LDS in a fixed order
 // and one inverse transform per workgroup replaces one per block.
-template <typename T, int LGN, int NT, int NW, int MODE>
+template <typename T, int LGN, int NT, int NW, int MODE, bool KEEP_OK = true>
 __device__ __forceinline__ void toep_pass_body(
     const cx<T>* __restrict__ Yhat, const cx<T>* __restrict__ Vhat, const T* w_in, T* u_out,
     const T* __restrict__ u_in, double* __restrict__ partial, const double* __restrict__ coef,
@@ -189,12 +225,24 @@ __device__ __forceinline__ void toep_pass_body(
   const int64_t row0 = static_cast<int64_t>(blk) * L - (p - 1);  // row at tau = 0
 
   double nrm = 0.0;
+  // Y kept in registers between its two uses in the FP64 passes of 1024-
+  // and 4096-point blocks, where the pass's LDS already holds occupancy at
+  // four waves per SIMD and the kept bins fit under that register budget
+  // (126 and 125 VGPRs): at B = 1024 the second read had missed L2 (about
+  // the whole 37 MB of spectra per AR(100) pass came from HBM twice)
+  // (KEEP_OK false: the batched kernels, whose extra registers would cost
+  // a wave per SIMD)
+  constexpr bool KEEPY = KEEP_OK && sizeof(T) == 8 && (MODE & PM_MV) != 0 && (MODE & PM_RMV) != 0 &&
+                         ((LGN == 9 && NT == 64 && NW == 4) || (LGN == 11 && NT == 256 && NW == 2));
+  struct NoKeep {};
+  std::conditional_t<KEEPY, PairBins<T, LGN, NT>, NoKeep> ykeep;
   if constexpr ((MODE & PM_MV) != 0) {
     // spectrum of X v on this block: Y * V (V pre-scaled by 1/B), in the
     // half-length complex form, bit-reversed for the inverse transform.
     // Every operand is loaded before any is used (one memory round trip).
     PairLoads<T, LGN, NT> ly, lv;
     ly.load(Y, tab);
+    if constexpr (KEEPY) ykeep.take(ly);
     lv.load(Vhat, nullptr);
 #pragma unroll
     for (int ip = 0; ip < PairLoads<T, LGN, NT>::NP; ++ip) {
@@ -286,10 +334,15 @@ __device__ __forceinline__ void toep_pass_body(
   }
   if constexpr ((MODE & PM_RMV) != 0) {
     // this block's share of X^T e: correlation of the window with e, i.e.
-    // conj(E) * Y per bin pair (Y reloaded, a cache hit, rather than kept
-    // live across the transforms), left in the inverse transform's input form
+    // conj(E) * Y per bin pair (Y kept, or reloaded), left in the inverse
+    // transform's input form
     PairLoads<T, LGN, NT> ly;
-    ly.load(Y, tab);
+    if constexpr (KEEPY) {
+      ykeep.give(ly);
+      ly.load_tw(tab);
+    } else {
+      ly.load(Y, tab);
+    }
 #pragma unroll
     for (int ip = 0; ip < PairLoads<T, LGN, NT>::NP; ++ip) {
       const int k = tid + ip * NT;
