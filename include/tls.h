@@ -208,8 +208,10 @@ tls_status tls_fit_batch(tls_ctx* ctx, int32_t count, const double* const* serie
  * has finished).  coef_packed, coef_offset, out (count tls_result entries,
  * may be NULL) and per_fit_status (may be NULL) are host memory.  The fits
  * are grouped by FFT block length and order class and each group runs its
- * kernels as single launches over all of its fits; fit i gives the same
- * result, bit for bit, as tls_fit_device with request_id = opt.request_id + i.
+ * kernels as single launches over all of its fits (orders above 623, whose
+ * sketch TRSM exceeds the tiles' LDS, and the repeated-halving sketch run
+ * one fit at a time inside the call); fit i gives the same result, bit for
+ * bit, as tls_fit_device with request_id = opt.request_id + i.
  * The series must stay valid and unmodified until the call returns.
  * Returns TLS_OK when every fit is TLS_OK, else the first failing status. */
 tls_status tls_fit_batch_device(tls_ctx* ctx, int32_t count, const double* const* d_series,
@@ -337,7 +339,7 @@ tls_status tls_server_create(tls_ctx* ctx, size_t hbm_budget, int32_t max_slots,
 
 /* Queue a fit of the host series (copied before return) of length n, order p,
  * LSQR tolerance tol; request_id selects its random streams (Philox fit id).
- * Validation as tls_fit_ex: TLS_EINVAL, TLS_EUNSUPPORTED (p = 1024), TLS_ENOMEM
+ * Validation as tls_fit_ex: TLS_EINVAL, TLS_EUNSUPPORTED (p > 623), TLS_ENOMEM
  * (footprint above the whole budget).  *ticket identifies the request. */
 tls_status tls_submit(tls_server* server, const double* series, int64_t n, int32_t p, double tol,
                       uint64_t request_id, tls_ticket* ticket);

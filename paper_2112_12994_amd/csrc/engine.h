@@ -68,6 +68,7 @@ struct FitBufs {
   void* Omhat;
   void* Vhat;
   double *v, *w, *z, *phi0, *phi;
+  double* q;        // p: M v of the wide LSQR step
   double* phib;     // mixed: best refinement iterate
   int64_t* idx;
   double* scale;
@@ -319,6 +320,7 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->z = a.take<double>(pl.p);
   b->phi0 = a.take<double>(pl.p);
   b->phi = a.take<double>(pl.p);
+  b->q = a.take<double>(pl.p);
   b->phib = a.take<double>(pl.p);
   b->pack = a.take<double>(pl.p + 8);
   b->idx = a.take<int64_t>(pl.c);
@@ -539,8 +541,10 @@ struct ClassKey {
   }
 };
 ClassKey class_key(const Plan& pl);
-// The batched sketch kernels stage 16-row panels of width ldq in LDS.
-constexpr int BATCH_LDQ_MAX = 1024;
+// The batched sketch kernels stage 16-row panels of width ldq in LDS (the
+// tile TRSM's limit, orders up to 623); fits of larger order run one at a
+// time in batched calls and are not served.
+constexpr int BATCH_LDQ_MAX = TRSM_TILE_LDQ_MAX;
 
 // Work-item lists of one class (offsets into one device item table).
 // jl: one item per (fit, JL column); jlg: one per (fit, group of

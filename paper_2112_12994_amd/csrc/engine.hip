@@ -100,7 +100,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       }
       TLS_CHECK(launch_colsum(b.partial, pl.ngroups, p + 1, b.g, flag, s));
       TLS_CHECK(launch_lsqr_step(pp, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
-                                 b.phi, vh, ctx->tw, s));
+                                 b.phi, vh, b.q, ctx->tw, s));
       return TLS_OK;
     };
     TLS_CHECK(launch_small_rfft(pp, pl.lgn, b.phi0, p, p, 1, invB, vh, ctx->tw, nullptr, s));

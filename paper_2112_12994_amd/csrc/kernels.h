@@ -82,6 +82,11 @@ constexpr int jl_cols(int p) { return p <= 128 ? 8 : (p <= 256 ? 4 : (p <= 512 ?
 hipError_t launch_jl_solve(const double* R, int ldr, int p, int k, int kind, double* Pi,
                            double* Om, uint64_t seed, uint32_t fit, hipStream_t st);
 
+// Largest leading dimension (a multiple of 16) of the sketch whose TRSM runs
+// on LDS tiles; larger ones take the global-memory TRSM (single fits) or run
+// one fit at a time (batched calls).
+constexpr int TRSM_TILE_LDQ_MAX = 624;
+
 // QR of the sketch and triangular helpers
 // rank_cols: leading columns whose breakdown or tiny pivot means rank
 // deficiency (the sketch [S X | S b] passes p: b may lie in the range of X).
@@ -114,10 +119,12 @@ struct LsqrState {
   int iter, istop, done, max_iter, phase, best_iter;
   int f32;  // mixed precision: 1 when the fit's LSQR products are FP32
 };
+// q: p doubles of scratch for the wide step (p > 128 with M in global
+// memory: the products over many workgroups); NULL keeps one workgroup.
 hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const double* g,
                             const double* M, const double* Mt, double* v, double* w, double* z,
-                            const double* phi0, double* phi, void* Vhat, const Twiddles& tw,
-                            hipStream_t stream);
+                            const double* phi0, double* phi, void* Vhat, double* q,
+                            const Twiddles& tw, hipStream_t stream);
 // Mixed-precision refinement (FP64 outer residual, FP32 inner CG on the
 // preconditioned normal equations).
 struct RefineState {

@@ -83,17 +83,19 @@ __device__ __forceinline__ void stage_m(const double* __restrict__ M, int p, int
   }
 }
 
-// out[r] = sum_{c in [lo(r), hi(r))} Mrow[r][c] x[c] for the rows r of an
+// out[r] = sum_{c in [lo(r), hi(r))} Mrow[r][c] x(c) for the rows r of an
 // upper (lo(r) = r, hi = p) or lower (lo = 0, hi(r) = r + 1) triangular p x p
-// row-major matrix; 8 rows per wavefront, lanes over columns, 8 rows x 2
-// column chunks of loads in flight.  Results go to out[r] (lane 0 of the
-// owning wave) via the callback.
-template <int NT, bool UPPER, typename F>
-__device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, int p,
-                                              const double* __restrict__ x, F&& emit) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  constexpr int NW = NT / 64, RU = 8, CU = 2;
-  for (int r0 = wid * RU; r0 < p; r0 += NW * RU) {
+// row-major matrix.  Wavefront w0 of wstride takes the row groups
+// r0 = RU (w0 + wstride t), lanes the columns c = c0 + 64 k + lane, RU rows x
+// CU column chunks of loads in flight.  Each lane sums its columns in
+// increasing order and the lanes are combined by wave_sum, so a row's value
+// does not depend on which wavefront or workgroup computes it, nor on RU and
+// CU.  Results go to out[r] (lane 0 of the owning wave) via the callback.
+template <bool UPPER, int RU, int CU, typename X, typename F>
+__device__ __forceinline__ void tri_gemv_rows_at(const double* __restrict__ Mrow, int p, X&& xat,
+                                                 F&& emit, int w0, int wstride) {
+  const int lane = threadIdx.x & 63;
+  for (int r0 = w0 * RU; r0 < p; r0 += wstride * RU) {
     double acc[RU];
 #pragma unroll
     for (int u = 0; u < RU; ++u) acc[u] = 0.0;
@@ -112,7 +114,7 @@ __device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, i
 #pragma unroll
       for (int k = 0; k < CU; ++k) {
         const int c = c0 + 64 * k + lane;
-        const double xc = c < p ? x[c] : 0.0;
+        const double xc = c < p ? xat(c) : 0.0;
 #pragma unroll
         for (int u = 0; u < RU; ++u) acc[u] += mv[u][k] * xc;
       }
@@ -127,6 +129,16 @@ __device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, i
   }
 }
 
+// The same over the NT / 64 wavefronts of one workgroup, GEMV_RU rows x 2
+// column chunks in flight, x an array.
+constexpr int GEMV_RU = 8;
+template <int NT, bool UPPER, typename F>
+__device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, int p,
+                                              const double* __restrict__ x, F&& emit) {
+  tri_gemv_rows_at<UPPER, GEMV_RU, 2>(Mrow, p, [&](int c) { return x[c]; }, emit,
+                                      threadIdx.x >> 6, NT / 64);
+}
+
 // MLDS: M (p <= 128) is staged once into LDS (rows padded to an odd length)
 // and every product with M or M^T reads it there, PARTS = NT / 128 threads
 // per output (partial sums over every PARTS-th term, combined by a fixed
@@ -137,6 +149,162 @@ __device__ __forceinline__ double parts_sum_t(double x) {
   for (int off = 1; off < PARTS; off <<= 1) x += __shfl_xor(x, off, 64);
   return x;
 }
+
+// Scalars of one LSQR step, as stored back into LsqrState.
+struct StepOut {
+  double alpha, beta, rhobar, phibar, anorm2, bnorm, rnorm, arnorm, znorm, best_ratio;
+  int iter, istop, best_iter;
+  bool done;
+};
+
+// The recurrences of one step once alpha, beta and the normalised v~ (sv,
+// p values) are known: the plane rotation, z += (phi/rho) w and
+// w = v - (theta/rho) w (written to w and z), ||z|| and the stopping tests.
+// All NT threads of the workgroup take part (block sums).
+template <int NT>
+__device__ __forceinline__ StepOut lsqr_recur(int p, const LsqrState* __restrict__ st,
+                                              double alpha, double beta, bool init,
+                                              const double* __restrict__ sv,
+                                              double* __restrict__ w, double* __restrict__ z,
+                                              double* __restrict__ red) {
+  const int tid = threadIdx.x;
+  const double tol = st->tol;
+  const double alpha_prev = st->alpha;
+  StepOut o;
+  o.alpha = alpha;
+  o.beta = beta;
+  o.rhobar = st->rhobar;
+  o.phibar = st->phibar;
+  o.anorm2 = st->anorm2;
+  o.bnorm = st->bnorm;
+  o.znorm = st->znorm;
+  o.iter = st->iter;
+  o.istop = 0;
+  o.best_ratio = st->best_ratio;
+  o.best_iter = st->best_iter;
+  o.done = false;
+  if (init) {
+    o.bnorm = beta;
+    o.phibar = beta;
+    o.rhobar = alpha;
+    o.anorm2 = 0.0;
+    for (int j = tid; j < p; j += NT) {
+      w[j] = sv[j];
+      z[j] = 0.0;
+    }
+    o.rnorm = beta;
+    o.arnorm = alpha * beta;
+    o.znorm = 0.0;
+    o.best_ratio = INFINITY;
+    o.best_iter = 0;
+    if (o.arnorm == 0.0) {
+      o.done = true;
+      o.istop = 0;
+    }
+  } else if (!isfinite(alpha) || !isfinite(beta)) {
+    // numerical breakdown: keep the last finite iterate
+    o.done = true;
+    o.istop = 4;
+    o.iter += 1;
+    o.rnorm = st->rnorm;
+    o.arnorm = st->arnorm;
+  } else {
+    o.anorm2 += alpha_prev * alpha_prev + beta * beta;
+    const double rho = hypot(o.rhobar, beta);
+    const double c = o.rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    o.rhobar = -c * alpha;
+    const double phik = c * o.phibar;
+    o.phibar = sn * o.phibar;
+    const double t1 = phik / rho, t2 = -theta / rho;
+    double zsq = 0.0;
+    for (int j = tid; j < p; j += NT) {
+      const double wj = w[j];
+      const double zj = z[j] + t1 * wj;
+      z[j] = zj;
+      w[j] = sv[j] + t2 * wj;
+      zsq += zj * zj;
+    }
+    o.znorm = sqrt(block_sum<NT>(zsq, red));
+    o.rnorm = o.phibar;
+    o.arnorm = o.phibar * alpha * fabs(c);
+    const double anorm = sqrt(o.anorm2);
+    o.iter += 1;
+    const double ratio = o.arnorm / (anorm * o.rnorm);
+    if (ratio < 0.5 * o.best_ratio) {
+      o.best_ratio = ratio;
+      o.best_iter = o.iter;
+    }
+    if (o.arnorm <= tol * anorm * o.rnorm) {
+      o.done = true;
+      o.istop = 2;
+    } else if (o.rnorm <= tol * o.bnorm + tol * anorm * o.znorm) {
+      o.done = true;
+      o.istop = 1;
+    } else if (alpha == 0.0 || beta == 0.0) {
+      o.done = true;
+      o.istop = 3;
+    } else if (o.iter - o.best_iter >= LSQR_STALL) {
+      o.done = true;
+      o.istop = 5;
+    } else if (o.iter >= st->max_iter) {
+      o.done = true;
+      o.istop = 7;
+    }
+  }
+  return o;
+}
+
+__device__ __forceinline__ void lsqr_store(LsqrState* __restrict__ st, const StepOut& o) {
+  if (threadIdx.x == 0) {
+    st->alpha = o.alpha;
+    st->beta = o.beta;
+    st->rhobar = o.rhobar;
+    st->phibar = o.phibar;
+    st->anorm2 = o.anorm2;
+    st->bnorm = o.bnorm;
+    st->rnorm = o.rnorm;
+    st->arnorm = o.arnorm;
+    st->znorm = o.znorm;
+    st->best_ratio = o.best_ratio;
+    st->best_iter = o.best_iter;
+    st->iter = o.iter;
+    st->istop = o.istop;
+    st->phase = 1;
+    st->coef[0] = 1.0;
+    st->coef[1] = o.beta > 0.0 ? -o.alpha / o.beta : 0.0;
+    if (o.done) st->done = 1;
+  }
+}
+
+// Packed spectrum (scaled 1/B) of the real p-vector q into Vhat (TS words).
+template <int LGN, int NT, typename TS>
+__device__ void spectrum_of(const double* __restrict__ q, int p, cx<double>* s,
+                            cx<TS>* __restrict__ Vhat, const cx<double>* __restrict__ tab) {
+  constexpr int N = 1 << LGN;
+  for (int t = threadIdx.x; t < N; t += NT) {
+    const int i0 = 2 * t;
+    s[swz<double>(t)] = {i0 < p ? q[i0] : 0.0, i0 + 1 < p ? q[i0 + 1] : 0.0};
+  }
+  __syncthreads();
+  fft_dif<double, false, LGN, NT>(s, tab);
+  const double invB = 1.0 / static_cast<double>(2 * N);
+  for (int k = threadIdx.x; k <= N / 2; k += NT) {
+    const cx<double> wk = twiddle<double, false>(tab, k, LGN + 1);
+    cx<double> Xk, Xnk;
+    rfft_post(s[swz<double>(bitrev(k, LGN))], s[swz<double>(bitrev((N - k) & (N - 1), LGN))], wk,
+              Xk, Xnk);
+    Xk = cscale(Xk, invB);
+    Xnk = cscale(Xnk, invB);
+    if (k == 0) {
+      Vhat[0] = {static_cast<TS>(Xk.x), static_cast<TS>(Xnk.x)};
+    } else {
+      Vhat[k] = {static_cast<TS>(Xk.x), static_cast<TS>(Xk.y)};
+      if (2 * k != N) Vhat[N - k] = {static_cast<TS>(Xnk.x), static_cast<TS>(Xnk.y)};
+    }
+  }
+}
+
 template <int LGN, int NT, typename TS, bool MLDS>
 __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st,
                                                        const double* __restrict__ g,
@@ -170,7 +338,6 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
   }
   if (done_in) return;
   const bool init = st->phase == 0;
-  const double tol = st->tol;
 
   const double beta = sqrt(gp);
   const double invbeta = beta > 0.0 ? 1.0 / beta : 0.0;
@@ -193,6 +360,8 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
       hsq += h * h;
     }
   } else {
+    // ||v~||^2: lane 0 of each wavefront over its rows in order (the wide
+    // step's recurrence kernel repeats this order)
     tri_gemv_rows<NT, false>(Mt, p, sg, [&](int j, double acc) {
       const double h = init ? acc : acc - beta * v[j];
       sv[j] = h;
@@ -206,85 +375,10 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
     v[j] = sv[j];
   }
 
-  double alpha_prev = st->alpha;
-  double rhobar = st->rhobar, phibar = st->phibar, anorm2 = st->anorm2, bnorm = st->bnorm;
-  double rnorm, arnorm, znorm = st->znorm;
-  int iter = st->iter, istop = 0;
-  double best_ratio = st->best_ratio;
-  int best_iter = st->best_iter;
-  bool done = false;
-  if (init) {
-    bnorm = beta;
-    phibar = beta;
-    rhobar = alpha;
-    anorm2 = 0.0;
-    for (int j = tid; j < p; j += NT) {
-      w[j] = sv[j];
-      z[j] = 0.0;
-    }
-    rnorm = beta;
-    arnorm = alpha * beta;
-    znorm = 0.0;
-    best_ratio = INFINITY;
-    best_iter = 0;
-    if (arnorm == 0.0) {
-      done = true;
-      istop = 0;
-    }
-  } else if (!isfinite(alpha) || !isfinite(beta)) {
-    // numerical breakdown: keep the last finite iterate
-    done = true;
-    istop = 4;
-    iter += 1;
-    rnorm = st->rnorm;
-    arnorm = st->arnorm;
-  } else {
-    anorm2 += alpha_prev * alpha_prev + beta * beta;
-    const double rho = hypot(rhobar, beta);
-    const double c = rhobar / rho, sn = beta / rho;
-    const double theta = sn * alpha;
-    rhobar = -c * alpha;
-    const double phik = c * phibar;
-    phibar = sn * phibar;
-    const double t1 = phik / rho, t2 = -theta / rho;
-    double zsq = 0.0;
-    for (int j = tid; j < p; j += NT) {
-      const double wj = w[j];
-      const double zj = z[j] + t1 * wj;
-      z[j] = zj;
-      w[j] = sv[j] + t2 * wj;
-      zsq += zj * zj;
-    }
-    znorm = sqrt(block_sum<NT>(zsq, red));
-    rnorm = phibar;
-    arnorm = phibar * alpha * fabs(c);
-    const double anorm = sqrt(anorm2);
-    iter += 1;
-    const double ratio = arnorm / (anorm * rnorm);
-    if (ratio < 0.5 * best_ratio) {
-      best_ratio = ratio;
-      best_iter = iter;
-    }
-    if (arnorm <= tol * anorm * rnorm) {
-      done = true;
-      istop = 2;
-    } else if (rnorm <= tol * bnorm + tol * anorm * znorm) {
-      done = true;
-      istop = 1;
-    } else if (alpha == 0.0 || beta == 0.0) {
-      done = true;
-      istop = 3;
-    } else if (iter - best_iter >= LSQR_STALL) {
-      done = true;
-      istop = 5;
-    } else if (iter >= st->max_iter) {
-      done = true;
-      istop = 7;
-    }
-  }
+  const StepOut o = lsqr_recur<NT>(p, st, alpha, beta, init, sv, w, z, red);
   __syncthreads();
 
-  if (!done) {
+  if (!o.done) {
     // q = M v_new into sg, then its packed spectrum scaled by 1/B.
     if constexpr (MLDS) {
       const int i = tid / PARTS, part = tid % PARTS;
@@ -297,26 +391,7 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
       tri_gemv_rows<NT, true>(M, p, sv, [&](int i, double acc) { sg[i] = acc; });
     }
     __syncthreads();
-    for (int t = tid; t < N; t += NT) {
-      const int i0 = 2 * t;
-      s[swz<double>(t)] = {i0 < p ? sg[i0] : 0.0, i0 + 1 < p ? sg[i0 + 1] : 0.0};
-    }
-    __syncthreads();
-    fft_dif<double, false, LGN, NT>(s, tab);
-    const double invB = 1.0 / static_cast<double>(2 * N);
-    for (int k = tid; k <= N / 2; k += NT) {
-      const cx<double> wk = twiddle<double, false>(tab, k, LGN + 1);
-      cx<double> Xk, Xnk;
-      rfft_post(s[swz<double>(bitrev(k, LGN))], s[swz<double>(bitrev((N - k) & (N - 1), LGN))], wk, Xk, Xnk);
-      Xk = cscale(Xk, invB);
-      Xnk = cscale(Xnk, invB);
-      if (k == 0) {
-        Vhat[0] = {static_cast<TS>(Xk.x), static_cast<TS>(Xnk.x)};
-      } else {
-        Vhat[k] = {static_cast<TS>(Xk.x), static_cast<TS>(Xk.y)};
-        if (2 * k != N) Vhat[N - k] = {static_cast<TS>(Xnk.x), static_cast<TS>(Xnk.y)};
-      }
-    }
+    spectrum_of<LGN, NT, TS>(sg, p, s, Vhat, tab);
   } else {
     // phi = phi0 + M z
     __syncthreads();
@@ -330,25 +405,7 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
       tri_gemv_rows<NT, true>(M, p, z, [&](int i, double acc) { phi[i] = phi0[i] + acc; });
     }
   }
-  if (tid == 0) {
-    st->alpha = alpha;
-    st->beta = beta;
-    st->rhobar = rhobar;
-    st->phibar = phibar;
-    st->anorm2 = anorm2;
-    st->bnorm = bnorm;
-    st->rnorm = rnorm;
-    st->arnorm = arnorm;
-    st->znorm = znorm;
-    st->best_ratio = best_ratio;
-    st->best_iter = best_iter;
-    st->iter = iter;
-    st->istop = istop;
-    st->phase = 1;
-    st->coef[0] = 1.0;
-    st->coef[1] = beta > 0.0 ? -alpha / beta : 0.0;
-    if (done) st->done = 1;
-  }
+  lsqr_store(st, o);
 }
 
 template <int LGN, int NT, typename TS, bool MLDS>
@@ -366,57 +423,134 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
   lsqr_step_body<LGN, NT, TS, MLDS>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, tab);
 }
 
+// ---- wide step: M from global memory and p > WIDE_P_MIN -------------------
+// The two triangular products of a step spread over ceil(p / 64) workgroups
+// of 1024 threads (a wavefront per group of 4 rows, 8 column chunks of its
+// loads in flight), the recurrences and the spectrum on one workgroup each:
+// four launches in place of the one workgroup's chain of dependent memory
+// round trips (16 at p = 500).  They reproduce the one-workgroup step with M
+// in global memory bit for bit: each row of a product is summed by one
+// wavefront in the same lane order (tri_gemv_rows_at), and the recurrences
+// and the spectrum run the same code with the same thread count.
+constexpr int WIDE_NT = 1024, WIDE_RU = 4, WIDE_CU = 8, WIDE_P_MIN = 128;
+
+int wide_groups(int p) {
+  constexpr int rows = WIDE_RU * (WIDE_NT / 64);
+  return (p + rows - 1) / rows;
+}
+
+// v <- v~ = M^T (g / beta) - beta v (phase 0: without the v term), in place.
+__global__ __launch_bounds__(WIDE_NT) void wide_h_kernel(int p, const LsqrState* __restrict__ st,
+                                                         const double* __restrict__ g,
+                                                         const double* __restrict__ Mt,
+                                                         double* __restrict__ v) {
+  if (st->done) return;
+  const bool init = st->phase == 0;
+  const double beta = sqrt(g[p]);
+  const double invbeta = beta > 0.0 ? 1.0 / beta : 0.0;
+  constexpr int NW = WIDE_NT / 64;
+  tri_gemv_rows_at<false, WIDE_RU, WIDE_CU>(
+      Mt, p, [&](int c) { return g[c] * invbeta; },
+      [&](int j, double acc) { v[j] = init ? acc : acc - beta * v[j]; },
+      static_cast<int>(blockIdx.x) * NW + static_cast<int>(threadIdx.x >> 6),
+      static_cast<int>(gridDim.x) * NW);
+}
+
+// alpha = ||v~||, v = v~ / alpha, the recurrences and the stopping tests;
+// phi = phi0 + M z when the step ends the iteration.  One workgroup.
+__global__ __launch_bounds__(WIDE_NT) void wide_recur_kernel(int p, LsqrState* __restrict__ st,
+                                                             const double* __restrict__ g,
+                                                             const double* __restrict__ M,
+                                                             double* __restrict__ v,
+                                                             double* __restrict__ w,
+                                                             double* __restrict__ z,
+                                                             const double* __restrict__ phi0,
+                                                             double* __restrict__ phi) {
+  constexpr int NT = WIDE_NT;
+  extern __shared__ double sv[];
+  __shared__ double red[NT / 64];
+  if (st->done) return;
+  const bool init = st->phase == 0;
+  const double beta = sqrt(g[p]);
+  const int tid = threadIdx.x;
+  for (int j = tid; j < p; j += NT) sv[j] = v[j];
+  __syncthreads();
+  // ||v~||^2 in the one-workgroup step's order: lane 0 of wavefront w adds
+  // the squares of the rows it would have computed there (groups of GEMV_RU
+  // rows from GEMV_RU w, every NT / 64 groups), then the block sum
+  double hsq = 0.0;
+  if ((tid & 63) == 0) {
+    for (int r0 = (tid >> 6) * GEMV_RU; r0 < p; r0 += GEMV_RU * (NT / 64))
+      for (int u = 0; u < GEMV_RU; ++u)
+        if (r0 + u < p) hsq += sv[r0 + u] * sv[r0 + u];
+  }
+  const double alpha = sqrt(block_sum<NT>(hsq, red));
+  const double invalpha = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  for (int j = tid; j < p; j += NT) {
+    sv[j] *= invalpha;
+    v[j] = sv[j];
+  }
+  const StepOut o = lsqr_recur<NT>(p, st, alpha, beta, init, sv, w, z, red);
+  __syncthreads();
+  if (o.done)
+    tri_gemv_rows<NT, true>(M, p, z, [&](int i, double acc) { phi[i] = phi0[i] + acc; });
+  lsqr_store(st, o);
+}
+
+// q = M v for the next pass.
+__global__ __launch_bounds__(WIDE_NT) void wide_q_kernel(int p, const LsqrState* __restrict__ st,
+                                                         const double* __restrict__ M,
+                                                         const double* __restrict__ v,
+                                                         double* __restrict__ q) {
+  if (st->done) return;
+  constexpr int NW = WIDE_NT / 64;
+  tri_gemv_rows_at<true, WIDE_RU, WIDE_CU>(
+      M, p, [&](int c) { return v[c]; }, [&](int i, double acc) { q[i] = acc; },
+      static_cast<int>(blockIdx.x) * NW + static_cast<int>(threadIdx.x >> 6),
+      static_cast<int>(gridDim.x) * NW);
+}
+
+// The packed spectrum of q, scaled by 1/B, into Vhat.
+template <int LGN, typename TS>
+__global__ __launch_bounds__(WIDE_NT) void wide_spec_kernel(int p, const LsqrState* __restrict__ st,
+                                                            const double* __restrict__ q,
+                                                            cx<TS>* __restrict__ Vhat,
+                                                            const cx<double>* __restrict__ tab) {
+  __shared__ cx<double> s[1 << LGN];
+  if (st->done) return;
+  spectrum_of<LGN, WIDE_NT, TS>(q, p, s, Vhat, tab);
+}
+
 template <int LGN, typename TS>
 hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, const double* Mt,
                     double* v, double* w, double* z, const double* phi0, double* phi, void* Vhat,
-                    const Twiddles& tw, hipStream_t stream) {
+                    double* q, const Twiddles& tw, hipStream_t stream) {
   constexpr int NT = 512;  // M in LDS: 8 wavefronts
   const size_t small = 2 * static_cast<size_t>(p) * sizeof(double);
   const size_t with_m = small + static_cast<size_t>(p) * (p | 1) * sizeof(double);
+  const cx<double>* tab = static_cast<const cx<double>*>(tw.d64);
   if (lsqr_step_lds(LGN, p)) {
     hipLaunchKernelGGL((lsqr_step_kernel<LGN, NT, TS, true>), dim3(1), dim3(NT), with_m, stream, p,
-                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
-                       static_cast<const cx<double>*>(tw.d64));
+                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat), tab);
+  } else if (p > WIDE_P_MIN && q) {
+    const int groups = wide_groups(p);
+    hipLaunchKernelGGL(wide_h_kernel, dim3(groups), dim3(WIDE_NT), 0, stream, p, st, g, Mt, v);
+    hipLaunchKernelGGL(wide_recur_kernel, dim3(1), dim3(WIDE_NT), p * sizeof(double), stream, p,
+                       st, g, M, v, w, z, phi0, phi);
+    hipLaunchKernelGGL(wide_q_kernel, dim3(groups), dim3(WIDE_NT), 0, stream, p, st, M, v, q);
+    hipLaunchKernelGGL((wide_spec_kernel<LGN, TS>), dim3(1), dim3(WIDE_NT), 0, stream, p, st, q,
+                       static_cast<cx<TS>*>(Vhat), tab);
   } else {
     // M read from global memory: 16 wavefronts keep more of its rows in flight
     constexpr int NTG = 1024;
     hipLaunchKernelGGL((lsqr_step_kernel<LGN, NTG, TS, false>), dim3(1), dim3(NTG), small, stream, p,
-                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat),
-                       static_cast<const cx<double>*>(tw.d64));
+                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat), tab);
   }
   return hipGetLastError();
 }
 
 // ---- mixed-precision refinement p-side kernels ---------------------------
 // Both stage M into LDS when p <= 128 (padded rows), else read it from global.
-
-// Packed spectrum (scaled 1/B) of the real p-vector q into Vhat (TS words).
-template <int LGN, int NT, typename TS>
-__device__ void spectrum_of(const double* __restrict__ q, int p, cx<double>* s,
-                            cx<TS>* __restrict__ Vhat, const cx<double>* __restrict__ tab) {
-  constexpr int N = 1 << LGN;
-  for (int t = threadIdx.x; t < N; t += NT) {
-    const int i0 = 2 * t;
-    s[swz<double>(t)] = {i0 < p ? q[i0] : 0.0, i0 + 1 < p ? q[i0 + 1] : 0.0};
-  }
-  __syncthreads();
-  fft_dif<double, false, LGN, NT>(s, tab);
-  const double invB = 1.0 / static_cast<double>(2 * N);
-  for (int k = threadIdx.x; k <= N / 2; k += NT) {
-    const cx<double> wk = twiddle<double, false>(tab, k, LGN + 1);
-    cx<double> Xk, Xnk;
-    rfft_post(s[swz<double>(bitrev(k, LGN))], s[swz<double>(bitrev((N - k) & (N - 1), LGN))], wk,
-              Xk, Xnk);
-    Xk = cscale(Xk, invB);
-    Xnk = cscale(Xnk, invB);
-    if (k == 0) {
-      Vhat[0] = {static_cast<TS>(Xk.x), static_cast<TS>(Xnk.x)};
-    } else {
-      Vhat[k] = {static_cast<TS>(Xk.x), static_cast<TS>(Xk.y)};
-      if (2 * k != N) Vhat[N - k] = {static_cast<TS>(Xnk.x), static_cast<TS>(Xnk.y)};
-    }
-  }
-}
 
 // out = M^T x (M upper; out[j] = sum_{i <= j} M[i][j] x[i]) or M x.
 template <int NT, bool TRANS>
@@ -665,15 +799,15 @@ __global__ __launch_bounds__(256) void gemv_upper_kernel(const double* __restric
 
 hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const double* g,
                             const double* M, const double* Mt, double* v, double* w, double* z,
-                            const double* phi0, double* phi, void* Vhat, const Twiddles& tw,
-                            hipStream_t stream) {
+                            const double* phi0, double* phi, void* Vhat, double* q,
+                            const Twiddles& tw, hipStream_t stream) {
   const size_t shm = (2 * static_cast<size_t>(1 << lgn) + 2 * p) * sizeof(double);
   if (shm > 160 * 1024) return hipErrorInvalidValue;
 #define TLS_STEP_CASE(LG)                                                                       \
   case LG:                                                                                      \
     return prec == PREC_F64                                                                     \
-               ? step_one<LG, double>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, tw, stream)   \
-               : step_one<LG, float>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, tw, stream);
+               ? step_one<LG, double>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, q, tw, stream)   \
+               : step_one<LG, float>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, q, tw, stream);
   switch (lgn) {
     TLS_STEP_CASE(6)
     TLS_STEP_CASE(7)

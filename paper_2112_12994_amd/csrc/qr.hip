@@ -542,13 +542,19 @@ __global__ __launch_bounds__(64) void trsm_tile_kernel(double* __restrict__ A, i
   trsm_tile_body<RALL>(A, ldq, q, R, blockIdx.x);
 }
 
-// LDS of the tiled solve: 16 rows of A, then 16 rows of R or (ldq <= 128) all of R
-bool trsm_rall(int ldq) { return ldq <= 128; }
-size_t trsm_lds_bytes(int ldq) {
-  const size_t rrows = trsm_rall(ldq) ? static_cast<size_t>(ldq) : 16;
-  const size_t dinv = ldq <= TRSM_DINV_LDQ ? 16 * static_cast<size_t>(ldq) : 0;
-  return (16 * static_cast<size_t>(ldq + 1) + rrows * ldq + dinv) * sizeof(double);
+// LDS of the tiled solve: 16 rows of A (ldq + 1 padded), then 16 rows of R
+// or (ldq <= 128) all of R, and the inverted diagonal blocks for
+// ldq <= TRSM_DINV_LDQ; within 160 KiB up to ldq = TRSM_TILE_LDQ_MAX.
+constexpr bool trsm_rall(int ldq) { return ldq <= 128; }
+constexpr size_t trsm_lds_bytes(int ldq) {
+  return (16 * static_cast<size_t>(ldq + 1) +
+          (trsm_rall(ldq) ? static_cast<size_t>(ldq) : size_t{16}) * ldq +
+          (ldq <= TRSM_DINV_LDQ ? 16 * static_cast<size_t>(ldq) : 0)) *
+         sizeof(double);
 }
+static_assert(trsm_lds_bytes(TRSM_TILE_LDQ_MAX) <= 160 * 1024 &&
+                  trsm_lds_bytes(TRSM_TILE_LDQ_MAX + 16) > 160 * 1024,
+              "TRSM_TILE_LDQ_MAX is the largest ldq whose tile TRSM fits in LDS");
 
 // status |= 4 when min|R_ii| <= k u max|R_ii| over the first k = rank_cols
 // diagonal entries (numerical rank of the leading columns below k).
@@ -1344,8 +1350,11 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sw
   double* R3 = G + static_cast<size_t>(ldq) * ldq;
   double* T = R3 + static_cast<size_t>(q) * q;
   double* Rs[3] = {sweeps == 1 ? R : R1, R2, R3};
-  // the third sweep is gated on status bit 8 from the second Cholesky
-  const bool gate3 = sweeps == 3 && ldq <= 1024;
+  // the tile TRSM where its LDS fits (ldq <= TRSM_TILE_LDQ_MAX), else the
+  // global-memory one; the third sweep is gated on status bit 8 from the
+  // second Cholesky (tile path)
+  const bool tile = ldq <= TRSM_TILE_LDQ_MAX;
+  const bool gate3 = sweeps == 3 && tile;
   const size_t trsm_shm = trsm_lds_bytes(ldq);
   const bool rall = trsm_rall(ldq);
   for (int sweep = 0; sweep < sweeps; ++sweep) {
@@ -1357,7 +1366,7 @@ hipError_t launch_qr(double* A, int crows, int q, int ldq, int rank_cols, int sw
     chol_launch(G, ldq, q, crows, sweep == 0 ? 1 : 2, Rs[sweep], status, sweep == 0 ? 1 : 2,
                 rank_cols, gated ? status : nullptr, st);
     if (sweep == sweeps - 1) break;
-    if (ldq <= 1024) {
+    if (tile) {
       if (gate3 && sweep == 1) {
         if (rall)
           hipLaunchKernelGGL(trsm_tile_gated_kernel<true>, dim3(crows / 16), dim3(64), trsm_shm, st,

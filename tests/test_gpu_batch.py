@@ -81,6 +81,33 @@ def test_batch_orders_across_kernel_limits(ctx):
     _same_as_single(ctx, ys, ps, outs, 40, device=True)
 
 
+def test_batch_wide_step_orders_equal_single(ctx):
+    """Orders above 128 whose single fits take the wide LSQR step (the two
+    products over many workgroups, four launches) while the batched step runs
+    one workgroup per fit: both give the same bits, with FP64 products up to
+    the batched kernels' largest order (623; 700 and 1024 run one at a time
+    inside the call) and with FP32 products (mixed precision, path 1 on well
+    conditioned series of orders just above 128)."""
+    say("batch wide step orders")
+    rng = np.random.default_rng(23)
+    ps = [129, 623, 700, 1024]
+    ys = [synth.ar_series(int(n), p, rng, 0.3, 0.8)
+          for n, p in zip([20000, 30000, 30000, 40000], ps)]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=60)
+    _ok_or_stalled(s, outs)
+    _same_as_single(ctx, ys, ps, outs, 60, device=True)
+    # kappa_F >= q, so the FP32-product band (kappa_F <= 300) holds orders
+    # just above 128 on nearly white series
+    ps = [130, 140, 160]
+    ys = [synth.ar_series(int(n), p, rng, 0.05, 0.2) for n, p in zip([30000, 50000, 60000], ps)]
+    s, outs = ctx.fit_batch_device([to_dev(y) for y in ys], ps, 1e-10, request_id=70, precision=1)
+    assert s in (capi().TLS_OK, capi().TLS_ENOCONV)
+    paths = [o["mixed_path"] for o in outs]
+    say("   paths", paths)
+    assert 1 in paths
+    _same_as_single(ctx, ys, ps, outs, 70, device=True, precision=1)
+
+
 def test_batch_mixed_precision_equals_single(ctx):
     say("batch mixed")
     rng = np.random.default_rng(14)

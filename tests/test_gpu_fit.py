@@ -64,8 +64,12 @@ def test_ar3_config(ctx):
 
 @pytest.mark.parametrize("p,n,seed", [(1, 5000, 0), (2, 777, 1), (8, 20000, 2), (40, 65536, 3),
                                       (100, 65536, 0), (64, 262144, 4), (200, 100000, 5),
-                                      (300, 100000, 6), (500, 60000, 7)])
+                                      (300, 100000, 6), (500, 60000, 7), (623, 40000, 8),
+                                      (700, 40000, 9), (1024, 40000, 10)])
 def test_fit_f64_matches_oracle(ctx, p, n, seed):
+    """Orders across the kernels' limits: register-tile QR (q <= 224), the
+    tile TRSM up to p = 623 and the global-memory TRSM above, the wide LSQR
+    step above p = 128, the largest order 1024."""
     say("fit f64", p, n, seed)
     rng = np.random.default_rng(seed)
     y = synth.ar_series(n, p, rng, 0.3, 0.9)

@@ -116,6 +116,9 @@ def test_serve_rejections(ctx):
         with pytest.raises(c.TlsError) as e:
             srv.submit(bad, 5, 1e-10)
         assert e.value.status == c.TLS_EINVAL
+        with pytest.raises(c.TlsError) as e:
+            srv.submit(y, 624, 1e-10)  # above the batched kernels' largest order, 623
+        assert e.value.status == c.TLS_EUNSUPPORTED
         big = synth.ar_series(1 << 18, 5, rng, 0.3, 0.9)
         with pytest.raises(c.TlsError) as e:
             srv.submit(big, 5, 1e-10)  # footprint above the 4 MiB budget
