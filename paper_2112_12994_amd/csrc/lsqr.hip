@@ -129,13 +129,13 @@ __device__ __forceinline__ void tri_gemv_rows_at(const double* __restrict__ Mrow
   }
 }
 
-// The same over the NT / 64 wavefronts of one workgroup, GEMV_RU rows x 2
+// The same over the NT / 64 wavefronts of one workgroup, GEMV_RU rows x GEMV_CU
 // column chunks in flight, x an array.
-constexpr int GEMV_RU = 8;
+constexpr int GEMV_RU = 8, GEMV_CU = 2;
 template <int NT, bool UPPER, typename F>
 __device__ __forceinline__ void tri_gemv_rows(const double* __restrict__ Mrow, int p,
                                               const double* __restrict__ x, F&& emit) {
-  tri_gemv_rows_at<UPPER, GEMV_RU, 2>(Mrow, p, [&](int c) { return x[c]; }, emit,
+  tri_gemv_rows_at<UPPER, GEMV_RU, GEMV_CU>(Mrow, p, [&](int c) { return x[c]; }, emit,
                                       threadIdx.x >> 6, NT / 64);
 }
 
