@@ -424,23 +424,24 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
 }
 
 // ---- wide step: M from global memory and p > WIDE_P_MIN -------------------
-// The two triangular products of a step spread over ceil(p / 64) workgroups
-// of 1024 threads (a wavefront per group of 4 rows, 8 column chunks of its
-// loads in flight), the recurrences and the spectrum on one workgroup each:
+// The two triangular products of a step spread over ceil(p / 8) workgroups
+// of 256 threads (a wavefront per group of 2 rows, 8 column chunks of its
+// loads in flight: at p = 500 each CU streams 32 KB of M), the recurrences
+// and the spectrum on one workgroup of 1024 threads each:
 // four launches in place of the one workgroup's chain of dependent memory
 // round trips (16 at p = 500).  They reproduce the one-workgroup step with M
 // in global memory bit for bit: each row of a product is summed by one
 // wavefront in the same lane order (tri_gemv_rows_at), and the recurrences
 // and the spectrum run the same code with the same thread count.
-constexpr int WIDE_NT = 1024, WIDE_RU = 4, WIDE_CU = 8, WIDE_P_MIN = 128;
+constexpr int WIDE_NT = 1024, WIDE_GEMV_NT = 256, WIDE_RU = 2, WIDE_CU = 8, WIDE_P_MIN = 128;
 
 int wide_groups(int p) {
-  constexpr int rows = WIDE_RU * (WIDE_NT / 64);
+  constexpr int rows = WIDE_RU * (WIDE_GEMV_NT / 64);
   return (p + rows - 1) / rows;
 }
 
 // v <- v~ = M^T (g / beta) - beta v (phase 0: without the v term), in place.
-__global__ __launch_bounds__(WIDE_NT) void wide_h_kernel(int p, const LsqrState* __restrict__ st,
+__global__ __launch_bounds__(WIDE_GEMV_NT) void wide_h_kernel(int p, const LsqrState* __restrict__ st,
                                                          const double* __restrict__ g,
                                                          const double* __restrict__ Mt,
                                                          double* __restrict__ v) {
@@ -448,7 +449,7 @@ __global__ __launch_bounds__(WIDE_NT) void wide_h_kernel(int p, const LsqrState*
   const bool init = st->phase == 0;
   const double beta = sqrt(g[p]);
   const double invbeta = beta > 0.0 ? 1.0 / beta : 0.0;
-  constexpr int NW = WIDE_NT / 64;
+  constexpr int NW = WIDE_GEMV_NT / 64;
   tri_gemv_rows_at<false, WIDE_RU, WIDE_CU>(
       Mt, p, [&](int c) { return g[c] * invbeta; },
       [&](int j, double acc) { v[j] = init ? acc : acc - beta * v[j]; },
@@ -498,12 +499,12 @@ __global__ __launch_bounds__(WIDE_NT) void wide_recur_kernel(int p, LsqrState* _
 }
 
 // q = M v for the next pass.
-__global__ __launch_bounds__(WIDE_NT) void wide_q_kernel(int p, const LsqrState* __restrict__ st,
+__global__ __launch_bounds__(WIDE_GEMV_NT) void wide_q_kernel(int p, const LsqrState* __restrict__ st,
                                                          const double* __restrict__ M,
                                                          const double* __restrict__ v,
                                                          double* __restrict__ q) {
   if (st->done) return;
-  constexpr int NW = WIDE_NT / 64;
+  constexpr int NW = WIDE_GEMV_NT / 64;
   tri_gemv_rows_at<true, WIDE_RU, WIDE_CU>(
       M, p, [&](int c) { return v[c]; }, [&](int i, double acc) { q[i] = acc; },
       static_cast<int>(blockIdx.x) * NW + static_cast<int>(threadIdx.x >> 6),
@@ -534,10 +535,10 @@ hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, cons
                        st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat), tab);
   } else if (p > WIDE_P_MIN && q) {
     const int groups = wide_groups(p);
-    hipLaunchKernelGGL(wide_h_kernel, dim3(groups), dim3(WIDE_NT), 0, stream, p, st, g, Mt, v);
+    hipLaunchKernelGGL(wide_h_kernel, dim3(groups), dim3(WIDE_GEMV_NT), 0, stream, p, st, g, Mt, v);
     hipLaunchKernelGGL(wide_recur_kernel, dim3(1), dim3(WIDE_NT), p * sizeof(double), stream, p,
                        st, g, M, v, w, z, phi0, phi);
-    hipLaunchKernelGGL(wide_q_kernel, dim3(groups), dim3(WIDE_NT), 0, stream, p, st, M, v, q);
+    hipLaunchKernelGGL(wide_q_kernel, dim3(groups), dim3(WIDE_GEMV_NT), 0, stream, p, st, M, v, q);
     hipLaunchKernelGGL((wide_spec_kernel<LGN, TS>), dim3(1), dim3(WIDE_NT), 0, stream, p, st, q,
                        static_cast<cx<TS>*>(Vhat), tab);
   } else {
