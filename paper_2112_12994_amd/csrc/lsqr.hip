@@ -1,5 +1,7 @@
 // p-side step of R-preconditioned LSQR (Paige and Saunders, ACM TOMS 8(1),
-// 1982) on A = X M, M = R^{-1}, one workgroup per fit.
+// 1982) on A = X M, M = R^{-1}: one workgroup per fit, or for a single fit
+// of order above 128 with M in global memory the wide step (its products
+// over many workgroups, four launches, the same bits).
 //
 // The m-side work of step i (u~ = X (M v) - (alpha/beta) u~_prev, its norm,
 // and X^T u~) is done by the fused Toeplitz pass; the column sums arrive in
