@@ -81,7 +81,6 @@ struct FitBufs {
   void* Vhat32;     // mixed: FP32 spectrum of the CG direction
   RefineState* rst; // mixed: refinement state
   double *cw, *cres, *cd;  // mixed: CG vectors
-  double* pack;     // p + 7: phi, ||r||^2, |R_ii| range, status (one copy out)
 };
 
 namespace {
@@ -322,7 +321,6 @@ size_t carve(const Plan& pl, bool copy_y, FitBufs* b, char* base) {
   b->phi = a.take<double>(pl.p);
   b->q = a.take<double>(pl.p);
   b->phib = a.take<double>(pl.p);
-  b->pack = a.take<double>(pl.p + 8);
   b->idx = a.take<int64_t>(pl.c);
   b->scale = a.take<double>(pl.c);
   b->swork = a.take<double>(sample_work_doubles(pl.m));
@@ -363,8 +361,9 @@ __global__ void fill_refine_kernel(RefineState* st, double tol, int max_refine, 
   }
 }
 
-// The results of a fit in one buffer for a single device-to-host copy:
-// phi (p), ||r||^2, max and min |R_ii|, the four status words.
+// The results of a fit in one buffer of pinned host memory, written by this
+// kernel (no copy launch): phi (p), ||r||^2, max and min |R_ii|, the four
+// status words.
 __global__ void pack_results_kernel(const double* __restrict__ phi, int p,
                                     const double* __restrict__ rr,
                                     const double* __restrict__ dminmax,

@@ -87,7 +87,9 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
     void* vh = pp == PREC_F64 ? b.Vhat : b.Vhat32;
     size_t npass = 0;
     hipEvent_t ea = nullptr, eb = nullptr;
-    auto pass = [&](const void* w_in) -> tls_status {
+    // snap: NULL, or the host ring slot that receives the state after this
+    // step (written by the step kernel itself)
+    auto pass = [&](const void* w_in, LsqrState* snap) -> tls_status {
       if (timed) {
         TLS_CHECK(pass_events(ctx, npass, &ea, &eb));
         TLS_CHECK(hipEventRecord(ea, s));
@@ -100,7 +102,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       }
       TLS_CHECK(launch_colsum(b.partial, pl.ngroups, p + 1, b.g, flag, s));
       TLS_CHECK(launch_lsqr_step(pp, pl.lgn, p, b.st, b.g, b.M, b.Mt, b.v, b.w, b.z, b.phi0,
-                                 b.phi, vh, b.q, ctx->tw, s));
+                                 b.phi, vh, b.q, snap, ctx->tw, s));
       return TLS_OK;
     };
     TLS_CHECK(launch_small_rfft(pp, pl.lgn, b.phi0, p, p, 1, invB, vh, ctx->tw, nullptr, s));
@@ -110,7 +112,7 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
                          dim3(256), 0, s, d_y + p, static_cast<float*>(b.u), pl.m);
       TLS_CHECK(hipGetLastError());
     }
-    tls_status e = pass(pp == PREC_F64 ? static_cast<const void*>(d_y + p) : b.u);
+    tls_status e = pass(pp == PREC_F64 ? static_cast<const void*>(d_y + p) : b.u, nullptr);
     if (e != TLS_OK) return e;
     // Chunks of iterations with one chunk always queued behind the one the
     // host waits for, so the device never idles on the host's convergence
@@ -140,13 +142,16 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       prev_ratio = ratio;
       return n;
     };
+    // a chunk's last step writes the state into its ring slot in pinned
+    // host memory (no copy launch on the stream)
+    int last_slot = 0;
     auto chunk = [&](int iters, int slot) -> tls_status {
       for (int it = 0; it < iters; ++it) {
-        const tls_status ec = pass(b.u);
+        const tls_status ec = pass(b.u, it + 1 == iters ? &ho->ring[slot] : nullptr);
         if (ec != TLS_OK) return ec;
       }
       launched += iters;
-      TLS_CHECK(hipMemcpyAsync(&ho->ring[slot], b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+      last_slot = slot;
       TLS_CHECK(hipEventRecord(ctx->chunk_ev[slot], s));
       return TLS_OK;
     };
@@ -160,8 +165,9 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
       e = chunk(next_chunk(ho->ring[slot]), slot);
       if (e != TLS_OK) return e;
     }
-    TLS_CHECK(hipMemcpyAsync(&ho->st, b.st, sizeof(LsqrState), hipMemcpyDeviceToHost, s));
+    // the last chunk launched ends the iteration: its snapshot is the final state
     TLS_CHECK(hipStreamSynchronize(s));
+    ho->st = ho->ring[last_slot];
     if (timed) {
       // passes 0 .. iter did work; later launches in the last chunk exit at once
       double ms = 0.0;
@@ -297,10 +303,10 @@ tls_status run_fit(tls_ctx* ctx, const Plan& pl, const tls_options& o, const dou
   // FP64 residual of the returned coefficients, row by row.
   TLS_CHECK(launch_resid_direct(d_y, pl.m, p, b.phi, b.rpart, s));
   TLS_CHECK(launch_colsum(b.rpart, resid_direct_blocks(pl.m), 1, b.rr, nullptr, s));
+  // the results packed straight into pinned host memory (one kernel, no copy)
   hipLaunchKernelGGL(pack_results_kernel, dim3(1), dim3(256), 0, s, b.phi, p, b.rr, b.dminmax,
-                     b.status, b.pack);
+                     b.status, hphi);
   TLS_CHECK(hipGetLastError());
-  TLS_CHECK(hipMemcpyAsync(hphi, b.pack, (p + 7) * sizeof(double), hipMemcpyDeviceToHost, s));
   TLS_CHECK(hipStreamSynchronize(s));
 
   memcpy(coef, hphi, p * sizeof(double));

@@ -121,10 +121,12 @@ struct LsqrState {
 };
 // q: p doubles of scratch for the wide step (p > 128 with M in global
 // memory: the products over many workgroups); NULL keeps one workgroup.
+// snap: NULL, or host-mapped memory (pinned) that receives the state after
+// this step, also when the iteration had stopped before it.
 hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const double* g,
                             const double* M, const double* Mt, double* v, double* w, double* z,
                             const double* phi0, double* phi, void* Vhat, double* q,
-                            const Twiddles& tw, hipStream_t stream);
+                            LsqrState* snap, const Twiddles& tw, hipStream_t stream);
 // Mixed-precision refinement (FP64 outer residual, FP32 inner CG on the
 // preconditioned normal equations).
 struct RefineState {

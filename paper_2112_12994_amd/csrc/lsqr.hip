@@ -318,7 +318,8 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
                                                        const double* __restrict__ phi0,
                                                        double* __restrict__ phi,
                                                        cx<TS>* __restrict__ Vhat,
-                                                       const cx<double>* __restrict__ tab) {
+                                                       const cx<double>* __restrict__ tab,
+                                                       LsqrState* __restrict__ snap = nullptr) {
   constexpr int N = 1 << LGN;
   constexpr int PARTS = NT / 128 > 0 ? NT / 128 : 1;
   static_assert(!MLDS || PARTS * 128 == NT, "M in LDS: NT / 128 threads per output");
@@ -338,7 +339,10 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
   if constexpr (MLDS) {
     stage_m<NT>(M, p, ldm, sM);
   }
-  if (done_in) return;
+  if (done_in) {
+    if (snap && tid == 0) *snap = *st;
+    return;
+  }
   const bool init = st->phase == 0;
 
   const double beta = sqrt(gp);
@@ -408,6 +412,7 @@ __device__ __forceinline__ void lsqr_step_body(int p, LsqrState* __restrict__ st
     }
   }
   lsqr_store(st, o);
+  if (snap && tid == 0) *snap = *st;
 }
 
 template <int LGN, int NT, typename TS, bool MLDS>
@@ -421,8 +426,9 @@ __global__ __launch_bounds__(NT) void lsqr_step_kernel(int p, LsqrState* __restr
                                                        const double* __restrict__ phi0,
                                                        double* __restrict__ phi,
                                                        cx<TS>* __restrict__ Vhat,
-                                                       const cx<double>* __restrict__ tab) {
-  lsqr_step_body<LGN, NT, TS, MLDS>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, tab);
+                                                       const cx<double>* __restrict__ tab,
+                                                       LsqrState* __restrict__ snap) {
+  lsqr_step_body<LGN, NT, TS, MLDS>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, tab, snap);
 }
 
 // ---- wide step: M from global memory and p > WIDE_P_MIN -------------------
@@ -468,11 +474,15 @@ __global__ __launch_bounds__(WIDE_NT) void wide_recur_kernel(int p, LsqrState* _
                                                              double* __restrict__ w,
                                                              double* __restrict__ z,
                                                              const double* __restrict__ phi0,
-                                                             double* __restrict__ phi) {
+                                                             double* __restrict__ phi,
+                                                             LsqrState* __restrict__ snap) {
   constexpr int NT = WIDE_NT;
   extern __shared__ double sv[];
   __shared__ double red[NT / 64];
-  if (st->done) return;
+  if (st->done) {
+    if (snap && threadIdx.x == 0) *snap = *st;
+    return;
+  }
   const bool init = st->phase == 0;
   const double beta = sqrt(g[p]);
   const int tid = threadIdx.x;
@@ -498,6 +508,7 @@ __global__ __launch_bounds__(WIDE_NT) void wide_recur_kernel(int p, LsqrState* _
   if (o.done)
     tri_gemv_rows<NT, true>(M, p, z, [&](int i, double acc) { phi[i] = phi0[i] + acc; });
   lsqr_store(st, o);
+  if (snap && tid == 0) *snap = *st;
 }
 
 // q = M v for the next pass.
@@ -527,19 +538,19 @@ __global__ __launch_bounds__(WIDE_NT) void wide_spec_kernel(int p, const LsqrSta
 template <int LGN, typename TS>
 hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, const double* Mt,
                     double* v, double* w, double* z, const double* phi0, double* phi, void* Vhat,
-                    double* q, const Twiddles& tw, hipStream_t stream) {
+                    double* q, LsqrState* snap, const Twiddles& tw, hipStream_t stream) {
   constexpr int NT = 512;  // M in LDS: 8 wavefronts
   const size_t small = 2 * static_cast<size_t>(p) * sizeof(double);
   const size_t with_m = small + static_cast<size_t>(p) * (p | 1) * sizeof(double);
   const cx<double>* tab = static_cast<const cx<double>*>(tw.d64);
   if (lsqr_step_lds(LGN, p)) {
     hipLaunchKernelGGL((lsqr_step_kernel<LGN, NT, TS, true>), dim3(1), dim3(NT), with_m, stream, p,
-                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat), tab);
+                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat), tab, snap);
   } else if (p > WIDE_P_MIN && q) {
     const int groups = wide_groups(p);
     hipLaunchKernelGGL(wide_h_kernel, dim3(groups), dim3(WIDE_GEMV_NT), 0, stream, p, st, g, Mt, v);
     hipLaunchKernelGGL(wide_recur_kernel, dim3(1), dim3(WIDE_NT), p * sizeof(double), stream, p,
-                       st, g, M, v, w, z, phi0, phi);
+                       st, g, M, v, w, z, phi0, phi, snap);
     hipLaunchKernelGGL(wide_q_kernel, dim3(groups), dim3(WIDE_GEMV_NT), 0, stream, p, st, M, v, q);
     hipLaunchKernelGGL((wide_spec_kernel<LGN, TS>), dim3(1), dim3(WIDE_NT), 0, stream, p, st, q,
                        static_cast<cx<TS>*>(Vhat), tab);
@@ -547,7 +558,7 @@ hipError_t step_one(int p, LsqrState* st, const double* g, const double* M, cons
     // M read from global memory: 16 wavefronts keep more of its rows in flight
     constexpr int NTG = 1024;
     hipLaunchKernelGGL((lsqr_step_kernel<LGN, NTG, TS, false>), dim3(1), dim3(NTG), small, stream, p,
-                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat), tab);
+                       st, g, M, Mt, v, w, z, phi0, phi, static_cast<cx<TS>*>(Vhat), tab, snap);
   }
   return hipGetLastError();
 }
@@ -803,14 +814,14 @@ __global__ __launch_bounds__(256) void gemv_upper_kernel(const double* __restric
 hipError_t launch_lsqr_step(int prec, int lgn, int p, LsqrState* st, const double* g,
                             const double* M, const double* Mt, double* v, double* w, double* z,
                             const double* phi0, double* phi, void* Vhat, double* q,
-                            const Twiddles& tw, hipStream_t stream) {
+                            LsqrState* snap, const Twiddles& tw, hipStream_t stream) {
   const size_t shm = (2 * static_cast<size_t>(1 << lgn) + 2 * p) * sizeof(double);
   if (shm > 160 * 1024) return hipErrorInvalidValue;
 #define TLS_STEP_CASE(LG)                                                                       \
   case LG:                                                                                      \
     return prec == PREC_F64                                                                     \
-               ? step_one<LG, double>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, q, tw, stream)   \
-               : step_one<LG, float>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, q, tw, stream);
+               ? step_one<LG, double>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, q, snap, tw, stream)   \
+               : step_one<LG, float>(p, st, g, M, Mt, v, w, z, phi0, phi, Vhat, q, snap, tw, stream);
   switch (lgn) {
     TLS_STEP_CASE(6)
     TLS_STEP_CASE(7)
