@@ -107,6 +107,19 @@ def test_mixed_ar500_shape(ctx):
     _check_mixed(out, y, 500)
 
 
+def test_mixed_wide_step_fp32_products(ctx):
+    """Order 140 on a nearly white series: kappa_F of the sketch factor is
+    within the FP32-product band (kappa_F >= q), so the fit runs LSQR with
+    FP32 products through the wide step (its products over many workgroups)
+    and meets the FP32 products' bounds against the oracle."""
+    say("mixed wide step fp32")
+    rng = np.random.default_rng(29)
+    y = synth.ar_series(60000, 140, rng, 0.05, 0.2)
+    out = ctx.fit(y, 140, 1e-10, precision=MIXED)
+    assert out["mixed_path"] == 1
+    _check_mixed(out, y, 140)
+
+
 def test_mixed_equals_f64_fitted_values(ctx):
     """Mixed and FP64 paths agree on a moderately conditioned AR(100) series."""
     say("mixed vs f64")
